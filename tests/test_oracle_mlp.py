@@ -1,0 +1,109 @@
+"""Pins of the oracle network (paper section 2: g_NN_U maps the pair
+configuration to the energy) against closed forms and finite differences."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+from synth import sampling
+
+
+def _norm():
+    return mlp.Norm(in_shift=np.array([0.1, -0.2, 0.3, 0, 0, 0, 0.05]),
+                    in_scale=np.array([1 / 11.0] * 3 + [1.0] * 4),
+                    out_shift=-3.0, out_scale=7.5)
+
+
+def _inputs(n, seed=5):
+    return sampling.pair_batch(sampling.rng(seed), n, 4.2, 11.1)
+
+
+def test_silu_values():
+    # SiLU(z) = z * sigmoid(z): SiLU(0) = 0, slope 1/2 at 0, SiLU(1) = 1/(1+1/e)
+    z = np.array([0.0, 1.0, -1.0, 40.0, -40.0])
+    np.testing.assert_allclose(mlp.act(z), [0.0, 0.7310585786300049, -0.2689414213699951, 40.0,
+                                             -40.0 * np.exp(-40.0)], rtol=1e-12, atol=1e-300)
+    assert mlp.act_grad(np.array([0.0]))[0] == pytest.approx(0.5)
+
+
+def test_identity_activation_collapses_to_one_affine_map():
+    p = sampling.xavier_params(3)
+    layers = mlp.unpack(p)
+    rng = sampling.rng(9)
+    # non-zero biases so the folded bias is exercised
+    p = mlp.pack([(W, rng.normal(size=b.shape)) for W, b in layers])
+    layers = mlp.unpack(p)
+    M = np.eye(7)
+    c = np.zeros(7)
+    for W, b in layers:
+        c = W @ c + b
+        M = W @ M
+    nrm = _norm()
+    u = _inputs(64)
+    un = (u - nrm.in_shift) * nrm.in_scale
+    want = (un @ M.T + c)[:, 0] * nrm.out_scale + nrm.out_shift
+    np.testing.assert_allclose(mlp.forward(p, u, nrm, kind="identity"), want, rtol=1e-12)
+    # and the input gradient of an affine map is its matrix row
+    _, g = mlp.input_grad(p, u, nrm, kind="identity")
+    np.testing.assert_allclose(g, np.broadcast_to(M[0] * nrm.in_scale * nrm.out_scale, g.shape),
+                               rtol=1e-12)
+
+
+def test_input_gradient_central_differences_h1e4():
+    # the workload checks the network gradient by central differences, h = 1e-4
+    p = sampling.xavier_params(1003)
+    nrm = _norm()
+    u = _inputs(32)
+    E, g = mlp.input_grad(p, u, nrm)
+    h = 1e-4
+    for k in range(7):
+        up, um = u.copy(), u.copy()
+        up[:, k] += h
+        um[:, k] -= h
+        fd = (mlp.forward(p, up, nrm) - mlp.forward(p, um, nrm)) / (2 * h)
+        np.testing.assert_allclose(g[:, k], fd, rtol=1e-6, atol=1e-7 * np.abs(g).max())
+    np.testing.assert_allclose(E, mlp.forward(p, u, nrm), rtol=0, atol=0)
+
+
+def test_parameter_gradient_central_differences():
+    p = sampling.xavier_params(7)
+    rng = sampling.rng(8)
+    p = p + 0.05 * rng.normal(size=p.size)       # non-zero biases
+    nrm = _norm()
+    u = _inputs(16)
+    y = rng.normal(size=16) * 5
+    loss, g = mlp.loss_and_grad(p, u, y, nrm)
+    idx = np.concatenate([rng.choice(p.size, 60, replace=False),
+                          [0, 895, 896, 1023, p.size - 129, p.size - 1]])
+    h = 1e-6
+    for k in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[k] += h
+        pm[k] -= h
+        fd = (mlp.loss_and_grad(pp, u, y, nrm)[0] - mlp.loss_and_grad(pm, u, y, nrm)[0]) / (2 * h)
+        assert g[k] == pytest.approx(fd, rel=1e-5, abs=1e-9)
+
+
+def test_adam_first_step_closed_form():
+    # with m = v = 0 and t = 1 the bias-corrected step is -lr g / (|g| + eps)
+    rng = sampling.rng(2)
+    p = rng.normal(size=100)
+    g = rng.normal(size=100)
+    g[3] = 0.0
+    new, m, v = mlp.adam_step(p, np.zeros(100), np.zeros(100), 1, g, lr=1e-3)
+    np.testing.assert_allclose(new - p, -1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-18)
+    np.testing.assert_allclose(m, 0.1 * g)
+    np.testing.assert_allclose(v, 0.001 * g * g)
+
+
+def test_overfits_small_set():
+    p = sampling.xavier_params(11)
+    u = _inputs(16, seed=12)
+    y = sampling.rng(13).normal(size=16)
+    nrm = mlp.Norm(in_scale=np.array([1 / 11.0] * 3 + [1.0] * 4))
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    loss0 = mlp.loss_and_grad(p, u, y, nrm)[0]
+    for t in range(1, 1001):
+        loss, g = mlp.loss_and_grad(p, u, y, nrm)
+        p, m, v = mlp.adam_step(p, m, v, t, g, lr=1e-3)
+    assert loss < 1e-3 * loss0

@@ -1,0 +1,210 @@
+/*
+ * rigidnn.h -- C ABI of the MI355X (gfx950) rigid-body pair library.
+ *
+ * The library evaluates the energy, forces and torques of every neighbouring
+ * pair of composite-bead rigid bodies in two ways: the plain bead double sum
+ * (paper section 2, first equation), and a learned map from the pair
+ * configuration to the energy (paper section 2: the configuration of a pair
+ * is the position and orientation of body j in the frame of body i) whose
+ * gradient gives forces and torques (supplementary section 6).  It also
+ * builds the pair list, integrates rigid-body motion and trains the network.
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers owned by the caller unless the
+ *     comment says "host".  The library never frees them.
+ *   - Arrays of per-body or per-pair vectors are structure-of-arrays: a
+ *     "3 x n" FP64 array stores all x components, then all y, then all z.
+ *   - Quaternions are (w, x, y, z), Hamilton product, unit norm, and map the
+ *     body frame to the lab frame.  Bead templates are in the body frame with
+ *     the centre of mass at the origin and principal axes along x, y, z.
+ *   - A pair descriptor is 7 numbers (d_x, d_y, d_z, q_w, q_x, q_y, q_z):
+ *     d = R_i^T minimg(x_j - x_i) is body j's centre in body i's frame and
+ *     q = q_i^* q_j its orientation relative to body i (R(q) = R_i^T R_j).
+ *   - Per-pair force/torque outputs are 9 numbers (F_j, tau_i, tau_j) in
+ *     body i's frame: F_j is the force on body j (F_i = -F_j), tau_i and
+ *     tau_j are torques about each body's own centre.
+ *   - `stream` is a hipStream_t passed as void*.  Every call only enqueues
+ *     work on it and returns; nothing synchronises the host.  The library
+ *     allocates device memory only in rb_ctx_create.
+ *   - Return value: RB_OK or a negative RB_ERR_* code; rb_last_error() then
+ *     gives a message (thread local).  Conditions found on the device
+ *     (pair-list overflow, non-finite forces) are written to the caller's
+ *     int32 flag array, read when the caller chooses to synchronise.
+ */
+#ifndef RIGIDNN_H
+#define RIGIDNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RB_OK 0
+#define RB_ERR_INVALID_ARG (-1)
+#define RB_ERR_CAPACITY (-2)
+#define RB_ERR_HIP (-3)
+#define RB_ERR_UNSUPPORTED (-4)
+
+/* Device flag words (int32 array of RB_NFLAGS, caller owned, zero it once). */
+#define RB_FLAG_REBUILD 0    /* 1: the pair list must be rebuilt before use     */
+#define RB_FLAG_NPAIRS 1     /* pairs in the current list (<= capacity)         */
+#define RB_FLAG_OVERFLOW 2   /* pairs found by the last build when > capacity   */
+#define RB_FLAG_NREBUILDS 3  /* number of list builds done                      */
+#define RB_FLAG_NBEAD 4      /* pairs routed to the bead sum (|d| < d_min)      */
+#define RB_FLAG_NNN 5        /* pairs routed to the network                     */
+#define RB_FLAG_NONFINITE 6  /* a non-finite per-pair force or energy was seen   */
+#define RB_NFLAGS 8
+
+#define RB_PREC_BF16 0       /* 128x128 layers on BF16 MFMA, FP32 accumulate     */
+#define RB_PREC_FP32 1       /* every layer in FP32                              */
+
+#define RB_BUILD_ALWAYS 0
+#define RB_BUILD_IF_FLAGGED 1
+
+#define RB_MLP_NPARAMS 50689 /* 7 -> 128 -> 128 -> 128 -> 128 -> 1               */
+
+/* Fixed-point accumulator of per-body forces/torques and global sums:
+ * int64 array of RB_ACC_LEN(n) = 6 n + 10 words, layout F_x[n] F_y[n] F_z[n]
+ * tau_x[n] tau_y[n] tau_z[n] E W_xx W_xy W_xz W_yx ... W_zz, each word the
+ * value times 2^32.  Integer addition is associative, so the result does
+ * not depend on the order in which pairs are summed. */
+#define RB_ACC_SCALE 4294967296.0
+#define RB_ACC_LEN(n) (6 * (int64_t)(n) + 10)
+
+typedef struct rb_ctx rb_ctx;
+
+/* Context: bead templates and the bead potential (Lennard-Jones 12-6,
+ * energy-shifted at rc: u(r) - u(rc) for r < rc), and per-type mass and
+ * principal inertia for the integrator.  Host inputs: n_beads[n_types],
+ * beads[sum(n_beads) x 3] (xyz per bead, types concatenated), mass[n_types],
+ * inertia[n_types x 3].  At most 8 types, at most 256 beads per type.
+ * Allocates the device copies; rb_ctx_destroy frees them. */
+int rb_ctx_create(rb_ctx **out, int32_t n_types, const int32_t *n_beads, const float *beads,
+                  const double *mass, const double *inertia, float eps, float sigma, float rc);
+int rb_ctx_destroy(rb_ctx *ctx);
+const char *rb_last_error(void);
+
+/* ---- pair list: half list i < j of body pairs closer than r_list --------
+ * Paper abstract: only bead pairs "within a certain distance" are computed;
+ * a body pair can have a bead pair inside rc only when its centre distance
+ * is below 2 r_max + rc, so r_list = 2 r_max + rc + skin.  Cell list over a
+ * periodic orthorhombic box (host box[3]); requires box >= 2 r_list per axis.
+ * x: 3 x n FP64 positions (any periodic image).  Writes pair_i/pair_j
+ * (capacity max_pairs) sorted by i and, within i, in a fixed cell order, so
+ * the list is deterministic; flags[NPAIRS] = min(found, max_pairs) and
+ * flags[OVERFLOW] = found if found > max_pairs (else 0).  Copies x into
+ * x_ref (3 x n) for the skin test of rb_rigid_step.  With
+ * RB_BUILD_IF_FLAGGED the kernels do nothing unless flags[REBUILD] is set,
+ * which makes the call safe to capture in a graph; the call clears it.
+ * ws: scratch of rb_pairlist_workspace_bytes(n, box, r_list) bytes. */
+size_t rb_pairlist_workspace_bytes(int32_t n, const double *box, double r_list);
+int rb_pairlist_build(int32_t n, const double *x, const double *box, double r_list,
+                      int32_t *pair_i, int32_t *pair_j, int32_t max_pairs, double *x_ref,
+                      int32_t *flags, int mode, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- descriptors and routing ---------------------------------------------
+ * For the first flags[NPAIRS] pairs: desc (7 x max_pairs FP32) from FP64
+ * state, and routing of each pair to the network (|d| >= d_min) or to the
+ * bead sum (|d| < d_min, outside the network's training domain).  Routed
+ * pair indices go to idx_nn / idx_bead (capacity max_pairs each, order not
+ * specified) with counts in flags[NNN] / flags[NBEAD].  x: 3 x n, q: 4 x n. */
+int rb_pair_descriptors(int32_t n, const double *x, const double *q, const double *box,
+                        const int32_t *pair_i, const int32_t *pair_j, int32_t max_pairs,
+                        float d_min, float *desc, int32_t *idx_nn, int32_t *idx_bead,
+                        int32_t *flags, void *stream);
+
+/* ---- bead double sum (paper section 2, first equation) -------------------
+ * Per-pair form, for labelling and checks: body i of type type_i at the
+ * origin with identity orientation, body j of type type_j at desc's d with
+ * orientation q/|q|.  out: 11 x n_pairs FP32 = E, F_j[3], tau_i[3], tau_j[3]
+ * in body i's frame, and r_min, the smallest bead-bead distance. */
+int rb_bead_pair_eval(const rb_ctx *ctx, int64_t n_pairs, const float *desc, int32_t type_i,
+                      int32_t type_j, float *out, void *stream);
+
+/* Per-body form for dynamics: the pairs idx[0 .. *count_dev) of the list
+ * (idx == NULL: the pairs 0 .. *count_dev), count read on the device and
+ * capped at max_count.  Geometry from FP64 state (x 3 x n, q 4 x n, type n),
+ * bead sums in FP32.  Adds F, tau of both bodies, the pair energy and the
+ * molecular virial W_ab += d_a F_j,b (lab frame) into acc (RB_ACC_LEN(n)). */
+int rb_bead_pair_forces(const rb_ctx *ctx, int32_t n, const double *x, const double *q,
+                        const int32_t *type, const double *box, const int32_t *pair_i,
+                        const int32_t *pair_j, const int32_t *idx, const int32_t *count_dev,
+                        int32_t max_count, int64_t *acc, int32_t *flags, void *stream);
+
+/* ---- accumulator -----------------------------------------------------------
+ * rb_accum_zero clears acc with a fill kernel (graph safe).
+ * rb_accum_finalize converts acc into force[3 x n] and torque[3 x n] (FP32,
+ * lab frame) and energy_virial[10] (FP64: E then W row-major). */
+int rb_accum_zero(int32_t n, int64_t *acc, void *stream);
+int rb_accum_finalize(int32_t n, const int64_t *acc, float *force, float *torque,
+                      double *energy_virial, void *stream);
+
+/* ---- energy network (paper section 2, g_NN_U; supplementary section 6) ---
+ * params: RB_MLP_NPARAMS FP32, layer by layer W_l (out x in, row major) then
+ * b_l, dims 7 -> 128 -> 128 -> 128 -> 128 -> 1, SiLU on hidden layers.
+ * norm (host, 16 floats): in_shift[7], in_scale[7], out_shift, out_scale;
+ * the network sees u' = (u - in_shift) * in_scale and E = e' * out_scale +
+ * out_shift.  precision: RB_PREC_BF16 (first and last layer FP32, the three
+ * 128x128 layers BF16 MFMA with FP32 accumulation and BF16 activations) or
+ * RB_PREC_FP32.  desc: 7 x n_pairs FP32. */
+int rb_nn_pair_eval(const float *params, const float *norm, int precision, int64_t n_pairs,
+                    const float *desc, float *energy, void *stream);
+
+/* Input gradient by a hand-written reverse pass.  gE (n_pairs, NULL = all
+ * ones) seeds the reverse pass.  Outputs (each may be NULL): energy
+ * (n_pairs), dE_ddesc (7 x n_pairs, times gE), pair_ft (9 x n_pairs,
+ * F_j, tau_i, tau_j in body i's frame, times gE): F_j = -dE/dd,
+ * tau_j = -(w g_v - g_w v + v x g_v)/2 for q = (w, v) and g = dE/dq,
+ * tau_i = -tau_j - d x F_j. */
+int rb_nn_pair_grad(const float *params, const float *norm, int precision, int64_t n_pairs,
+                    const float *desc, const float *gE, float *energy, float *dE_ddesc,
+                    float *pair_ft, void *stream);
+
+/* Network forces for dynamics: pairs idx[0 .. *count_dev) (idx == NULL: all
+ * pairs up to *count_dev), desc from rb_pair_descriptors, q (4 x n FP64)
+ * for the rotation to the lab frame.  The energy is multiplied by a C1
+ * switch S(|d|) = 1 below sw_lo, smoothstep to 0 at sw_hi (sw_hi <= sw_lo
+ * disables it), and forces/torques come from the switched energy.  Adds
+ * into acc like rb_bead_pair_forces. */
+int rb_nn_pair_forces(const float *params, const float *norm, int precision, int32_t n,
+                      const double *q, const int32_t *pair_i, const int32_t *pair_j,
+                      const float *desc, int32_t desc_stride, const int32_t *idx,
+                      const int32_t *count_dev, int32_t max_count, float sw_lo, float sw_hi,
+                      int64_t *acc, int32_t *flags, void *stream);
+
+/* ---- rigid-body velocity Verlet (FP64) -------------------------------------
+ * State: x (3 x n), P (3 x n linear momentum), q (4 x n), L (3 x n angular
+ * momentum in the body frame).  phase 1: half kick with force/torque (lab
+ * frame, 3 x n FP32 each), drift, free rotation split as
+ * R3(dt/2) R2(dt/2) R1(dt) R2(dt/2) R3(dt/2) (NO_SQUISH, Miller et al.,
+ * J. Chem. Phys. 116, 8649, 2002), renormalise q; if x_ref != NULL and a
+ * body moved more than half_skin from x_ref, sets flags[REBUILD].  phase 2:
+ * second half kick; writes kinetic[2] = (translational, rotational) kinetic
+ * energy (FP64 deterministic reduction).  ws: rb_rigid_workspace_bytes(n). */
+size_t rb_rigid_workspace_bytes(int32_t n);
+int rb_rigid_step(const rb_ctx *ctx, int phase, int32_t n, double dt, double *x, double *P,
+                  double *q, double *L, const int32_t *type, const float *force,
+                  const float *torque, const double *x_ref, double half_skin, double *kinetic,
+                  int32_t *flags, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- training step (energy loss, Adam) ------------------------------------
+ * One step on the batch idx[0 .. batch) of a data set (desc 7 x n_data
+ * FP32, labels n_data FP32): forward with saved activations, loss
+ * mean((e' - y')^2) in normalised units, reverse pass, weight gradients,
+ * Adam (Kingma and Ba) on the FP32 master params with moments m, v and
+ * 1-based step number t.  loss (device, 1 float) receives the batch loss
+ * before the update; grad_out (RB_MLP_NPARAMS or NULL) the gradient.
+ * ws: rb_nn_train_workspace_bytes(batch). */
+size_t rb_nn_train_workspace_bytes(int32_t batch);
+int rb_nn_train_step(float *params, float *adam_m, float *adam_v, int32_t t, const float *norm,
+                     int precision, int32_t batch, const float *desc, int64_t n_data,
+                     const float *labels, const int32_t *idx, float lr, float beta1, float beta2,
+                     float eps, float *loss, float *grad_out, void *ws, size_t ws_bytes,
+                     void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RIGIDNN_H */

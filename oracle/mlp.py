@@ -34,6 +34,28 @@ class Norm:
         return np.concatenate([self.in_shift, self.in_scale, [self.out_shift, self.out_scale]])
 
 
+def round_bf16(x: np.ndarray) -> np.ndarray:
+    """Round FP32 values to the nearest BF16 value (ties to even), as FP64.
+
+    BF16 keeps the upper 16 bits of an FP32 number; rounding adds half of
+    the dropped part, with ties resolved toward an even kept part.
+    """
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    lsb = (u >> np.uint64(16)) & np.uint64(1)
+    u = (u + np.uint64(0x7FFF) + lsb) & np.uint64(0xFFFF0000)
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def bf16_network(params: np.ndarray, dims=DIMS) -> np.ndarray:
+    """The network the BF16 kernels implement: the three hidden-to-hidden
+    weight matrices rounded to BF16, every other parameter kept in FP32."""
+    layers = unpack(np.asarray(params, dtype=np.float32).astype(np.float64), dims)
+    out = []
+    for li, (W, b) in enumerate(layers):
+        out.append((round_bf16(W) if 0 < li < len(layers) - 1 else W, b))
+    return pack(out)
+
+
 def unpack(params: np.ndarray, dims=DIMS) -> list[tuple[np.ndarray, np.ndarray]]:
     params = np.asarray(params, dtype=np.float64)
     layers, o = [], 0

@@ -1,0 +1,96 @@
+// Pair descriptors and routing.
+//
+// Paper section 2: the configuration of a pair is fixed by the position and
+// the orientation of body j in the frame of body i.  Here that is
+// d = R_i^T minimg(x_j - x_i) and q = q_i^* q_j (R(q) = R_i^T R_j), computed
+// in FP64 from the state and stored in FP32 (7 x max_pairs, SoA).  Pairs with
+// |d| < d_min lie outside the network's training domain and are routed to
+// the bead sum; the rest go to the network.
+#include "rb_common.hpp"
+
+namespace rb {
+
+__global__ void k_route_reset(int32_t *flags) {
+    flags[RB_FLAG_NNN] = 0;
+    flags[RB_FLAG_NBEAD] = 0;
+}
+
+// Appends this lane's pair to one of two lists with one atomic per wave and
+// list (ballot + popcount of the lanes below).
+__device__ inline void wave_append(bool take, int value, int32_t *list, int32_t *counter) {
+    const unsigned long long m = __ballot(take);
+    if (m == 0) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    int base = 0;
+    const int leader = __ffsll((long long)m) - 1;
+    if (lane == leader) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, leader, kWave);
+    if (take) {
+        const unsigned long long below = m & ((1ull << lane) - 1ull);
+        list[base + __popcll(below)] = value;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_descriptors(int32_t n, const double *__restrict__ x,
+                                                     const double *__restrict__ q, double L0, double L1, double L2,
+                                                     const int32_t *__restrict__ pi, const int32_t *__restrict__ pj,
+                                                     int32_t maxp, float dmin2, float *__restrict__ desc,
+                                                     int32_t *__restrict__ idx_nn, int32_t *__restrict__ idx_bead,
+                                                     int32_t *__restrict__ flags) {
+    int count = flags[RB_FLAG_NPAIRS];
+    if (count > maxp) count = maxp;
+    const double Ls[3] = {L0, L1, L2};
+    for (int base = blockIdx.x * blockDim.x; base < count; base += gridDim.x * blockDim.x) {
+        const int p = base + threadIdx.x;
+        const bool live = p < count;
+        bool to_nn = false;
+        if (live) {
+            const int i = pi[p], j = pj[p];
+            double dl[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) dl[a] = min_image(x[a * n + j] - x[a * n + i], Ls[a], 1.0 / Ls[a]);
+            const double w = q[i], vx = q[n + i], vy = q[2 * n + i], vz = q[3 * n + i];
+            double R[9];
+            quat_to_rot<double>(w, vx, vy, vz, R);
+            double d[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) d[a] = R[a] * dl[0] + R[3 + a] * dl[1] + R[6 + a] * dl[2];
+            // q_i^* q_j
+            const double bw = q[j], bx = q[n + j], by = q[2 * n + j], bz = q[3 * n + j];
+            const double rw = w * bw + vx * bx + vy * by + vz * bz;
+            const double rx = w * bx - vx * bw - vy * bz + vz * by;
+            const double ry = w * by + vx * bz - vy * bw - vz * bx;
+            const double rz = w * bz - vx * by + vy * bx - vz * bw;
+            desc[p] = (float)d[0];
+            desc[maxp + p] = (float)d[1];
+            desc[2 * maxp + p] = (float)d[2];
+            desc[3 * maxp + p] = (float)rw;
+            desc[4 * maxp + p] = (float)rx;
+            desc[5 * maxp + p] = (float)ry;
+            desc[6 * maxp + p] = (float)rz;
+            to_nn = (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) >= (double)dmin2;
+        }
+        wave_append(live && to_nn, p, idx_nn, flags + RB_FLAG_NNN);
+        wave_append(live && !to_nn, p, idx_bead, flags + RB_FLAG_NBEAD);
+    }
+}
+
+}  // namespace rb
+
+using namespace rb;
+
+extern "C" int rb_pair_descriptors(int32_t n, const double *x, const double *q, const double *box,
+                                   const int32_t *pair_i, const int32_t *pair_j, int32_t max_pairs, float d_min,
+                                   float *desc, int32_t *idx_nn, int32_t *idx_bead, int32_t *flags, void *stream) {
+    RB_REQUIRE(x && q && box && pair_i && pair_j && desc && idx_nn && idx_bead && flags,
+               "rb_pair_descriptors: null argument");
+    RB_REQUIRE(n > 0 && max_pairs > 0, "rb_pair_descriptors: sizes must be > 0");
+    RB_REQUIRE(box[0] > 0 && box[1] > 0 && box[2] > 0, "rb_pair_descriptors: box must be > 0");
+    hipStream_t st = (hipStream_t)stream;
+    k_route_reset<<<1, 1, 0, st>>>(flags);
+    const float dm2 = d_min > 0 ? d_min * d_min : 0.f;
+    k_descriptors<<<grid_for(max_pairs, 256, 4096), 256, 0, st>>>(n, x, q, box[0], box[1], box[2], pair_i, pair_j,
+                                                                  max_pairs, dm2, desc, idx_nn, idx_bead, flags);
+    RB_LAUNCH_CHECK("rb_pair_descriptors");
+    return RB_OK;
+}

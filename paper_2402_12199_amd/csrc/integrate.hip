@@ -1,0 +1,203 @@
+// Rigid-body velocity Verlet in FP64 with the NO_SQUISH free-rotation
+// splitting (Miller, Eleftheriou, Pattnaik, Ndirango, Newns, Martyna,
+// J. Chem. Phys. 116, 8649 (2002)).  The paper itself only fixes the time
+// step (section 3, dt = 0.005 tau).
+//
+// The rotational state is kept as the body-frame angular momentum L.  The
+// NO_SQUISH sub-step about body axis k over a time h is the exact flow of
+// the k-th kinetic term L_k^2 / (2 I_k): the body turns by the angle
+// h L_k / I_k about its own axis k, i.e. q <- q (cos z, sin z e_k) with
+// z = h L_k / (2 I_k), and L turns by -2z about the same axis, which keeps
+// the lab-frame angular momentum fixed.  A kick adds the body-frame torque:
+// L <- L + (dt/2) R(q)^T tau.
+#include "rb_common.hpp"
+
+namespace rb {
+
+constexpr int kIntThreads = 256;
+
+struct Sub {
+    int k;
+    double h;
+};
+
+__device__ inline void free_sub(int k, double h, double I, double q[4], double L[3]) {
+    const double z = h * L[k] / (2.0 * I);
+    double s, c;
+    sincos(z, &s, &c);
+    // q <- q * (c, s e_k), written out per axis
+    const double w = q[0], x = q[1], y = q[2], zz = q[3];
+    if (k == 0) {
+        q[0] = c * w - s * x; q[1] = c * x + s * w; q[2] = c * y + s * zz; q[3] = c * zz - s * y;
+    } else if (k == 1) {
+        q[0] = c * w - s * y; q[1] = c * x - s * zz; q[2] = c * y + s * w; q[3] = c * zz + s * x;
+    } else {
+        q[0] = c * w - s * zz; q[1] = c * x + s * y; q[2] = c * y - s * x; q[3] = c * zz + s * w;
+    }
+    // L turns by -2z about axis k: (L_a, L_b) with (k, a, b) cyclic
+    const int a = (k + 1) % 3, b = (k + 2) % 3;
+    const double c2 = c * c - s * s, s2 = 2.0 * s * c;
+    const double La = L[a], Lb = L[b];
+    L[a] = c2 * La + s2 * Lb;
+    L[b] = -s2 * La + c2 * Lb;
+}
+
+__device__ inline void kick(double dt, double q[4], double P[3], double L[3], const float *force,
+                            const float *torque, int n, int i) {
+    double R[9];
+    quat_to_rot<double>(q[0], q[1], q[2], q[3], R);
+    const double t[3] = {torque[i], torque[n + i], torque[2 * n + i]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        P[a] += 0.5 * dt * (double)force[a * n + i];
+        L[a] += 0.5 * dt * (R[a] * t[0] + R[3 + a] * t[1] + R[6 + a] * t[2]);
+    }
+}
+
+__global__ __launch_bounds__(kIntThreads) void k_phase1(int32_t n, double dt, double *__restrict__ x,
+                                                        double *__restrict__ P, double *__restrict__ q,
+                                                        double *__restrict__ L, const int32_t *__restrict__ type,
+                                                        const double *__restrict__ mass,
+                                                        const double *__restrict__ inertia,
+                                                        const float *__restrict__ force,
+                                                        const float *__restrict__ torque,
+                                                        const double *__restrict__ x_ref, double half_skin2,
+                                                        int32_t *__restrict__ flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool moved = false;
+    if (i < n) {
+        const int t = type[i];
+        double qi[4] = {q[i], q[n + i], q[2 * n + i], q[3 * n + i]};
+        double Pi[3] = {P[i], P[n + i], P[2 * n + i]};
+        double Li[3] = {L[i], L[n + i], L[2 * n + i]};
+        kick(dt, qi, Pi, Li, force, torque, n, i);
+        const double im = 1.0 / mass[t];
+        double d2 = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double xn = x[a * n + i] + dt * Pi[a] * im;
+            x[a * n + i] = xn;
+            if (x_ref) {
+                const double dd = xn - x_ref[a * n + i];
+                d2 += dd * dd;
+            }
+        }
+        moved = x_ref && d2 > half_skin2;
+        const double I[3] = {inertia[3 * t], inertia[3 * t + 1], inertia[3 * t + 2]};
+        free_sub(2, 0.5 * dt, I[2], qi, Li);
+        free_sub(1, 0.5 * dt, I[1], qi, Li);
+        free_sub(0, dt, I[0], qi, Li);
+        free_sub(1, 0.5 * dt, I[1], qi, Li);
+        free_sub(2, 0.5 * dt, I[2], qi, Li);
+        const double inv = 1.0 / sqrt(qi[0] * qi[0] + qi[1] * qi[1] + qi[2] * qi[2] + qi[3] * qi[3]);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) q[a * n + i] = qi[a] * inv;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            P[a * n + i] = Pi[a];
+            L[a * n + i] = Li[a];
+        }
+    }
+    if (__any(moved) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(flags + RB_FLAG_REBUILD, 1);
+}
+
+// Second half kick; per-block FP64 kinetic partial sums, summed in block
+// order by the last block to finish, so the result is deterministic.
+__global__ __launch_bounds__(kIntThreads) void k_phase2(int32_t n, double dt, double *__restrict__ P,
+                                                        const double *__restrict__ q, double *__restrict__ L,
+                                                        const int32_t *__restrict__ type,
+                                                        const double *__restrict__ mass,
+                                                        const double *__restrict__ inertia,
+                                                        const float *__restrict__ force,
+                                                        const float *__restrict__ torque,
+                                                        double *__restrict__ partial, unsigned *__restrict__ ticket,
+                                                        double *__restrict__ kinetic) {
+    __shared__ double red[2][kIntThreads / kWave];
+    __shared__ bool last;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double kt = 0, kr = 0;
+    if (i < n) {
+        const int t = type[i];
+        double qi[4] = {q[i], q[n + i], q[2 * n + i], q[3 * n + i]};
+        double Pi[3] = {P[i], P[n + i], P[2 * n + i]};
+        double Li[3] = {L[i], L[n + i], L[2 * n + i]};
+        kick(dt, qi, Pi, Li, force, torque, n, i);
+        const double m = mass[t];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            P[a * n + i] = Pi[a];
+            L[a * n + i] = Li[a];
+            kt += Pi[a] * Pi[a] / (2.0 * m);
+            kr += Li[a] * Li[a] / (2.0 * inertia[3 * t + a]);
+        }
+    }
+    kt = wave_sum(kt);
+    kr = wave_sum(kr);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][w] = kt;
+        red[1][w] = kr;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0, b = 0;
+        for (int k = 0; k < kIntThreads / kWave; ++k) {
+            a += red[0][k];
+            b += red[1][k];
+        }
+        partial[2 * blockIdx.x] = a;
+        partial[2 * blockIdx.x + 1] = b;
+        __threadfence();
+        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        double a = 0, b = 0;
+        for (int k = 0; k < (int)gridDim.x; ++k) {
+            a += __hip_atomic_load(partial + 2 * k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            b += __hip_atomic_load(partial + 2 * k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        kinetic[0] = a;
+        kinetic[1] = b;
+        *ticket = 0u;
+    }
+}
+
+static size_t nblocks(int32_t n) { return (size_t)((n + kIntThreads - 1) / kIntThreads); }
+
+}  // namespace rb
+
+using namespace rb;
+
+extern "C" size_t rb_rigid_workspace_bytes(int32_t n) {
+    if (n <= 0) return 256;
+    return ((sizeof(double) * 2 * nblocks(n) + 255) & ~(size_t)255) + 256;
+}
+
+extern "C" int rb_rigid_step(const rb_ctx *ctx, int phase, int32_t n, double dt, double *x, double *P,
+                             double *q, double *L, const int32_t *type, const float *force,
+                             const float *torque, const double *x_ref, double half_skin, double *kinetic,
+                             int32_t *flags, void *ws, size_t ws_bytes, void *stream) {
+    RB_REQUIRE(ctx && P && q && L && type && force && torque, "rb_rigid_step: null argument");
+    RB_REQUIRE(phase == 1 || phase == 2, "rb_rigid_step: phase must be 1 or 2");
+    RB_REQUIRE(n > 0, "rb_rigid_step: n must be > 0");
+    hipStream_t st = (hipStream_t)stream;
+    const int grid = (int)nblocks(n);
+    if (phase == 1) {
+        RB_REQUIRE(x, "rb_rigid_step: x is null");
+        RB_REQUIRE(!x_ref || flags, "rb_rigid_step: the skin test needs flags");
+        k_phase1<<<grid, kIntThreads, 0, st>>>(n, dt, x, P, q, L, type, ctx->dev.mass, ctx->dev.inertia, force,
+                                               torque, x_ref, half_skin * half_skin, flags);
+    } else {
+        RB_REQUIRE(kinetic && ws, "rb_rigid_step: phase 2 needs kinetic and ws");
+        RB_REQUIRE(ws_bytes >= rb_rigid_workspace_bytes(n), "rb_rigid_step: workspace too small");
+        char *w = static_cast<char *>(ws);
+        double *partial = reinterpret_cast<double *>(w);
+        unsigned *ticket = reinterpret_cast<unsigned *>(w + rb_rigid_workspace_bytes(n) - 256);
+        k_phase2<<<grid, kIntThreads, 0, st>>>(n, dt, P, q, L, type, ctx->dev.mass, ctx->dev.inertia, force, torque,
+                                               partial, ticket, kinetic);
+    }
+    RB_LAUNCH_CHECK("rb_rigid_step");
+    return RB_OK;
+}

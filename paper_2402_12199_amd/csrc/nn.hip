@@ -1,0 +1,257 @@
+// Energy network: forward pass, hand-written reverse pass (input gradient),
+// and per-pair or per-body forces and torques from that gradient.
+//
+// BF16 path: layer 1 (7 -> 128) and layer 5 (128 -> 1) in FP32 on the VALU;
+// the three 128 x 128 layers on v_mfma_f32_16x16x32_bf16 with FP32
+// accumulation, weights staged once per block in LDS, activations rounded
+// to BF16 as MFMA operands.  SiLU derivatives of the forward pass are kept
+// in registers (BF16) for the reverse pass.  The reverse pass multiplies by
+// W^T: the forward reads a 16-byte row fragment of the LDS weights, the
+// reverse gathers eight 2-byte elements down a column of the same array.
+//
+// FP32 path: the same tiling on v_mfma_f32_16x16x4_f32, weights read from
+// global memory (they stay in the caches), activations and derivatives in
+// FP32.
+#include "nn_tile.hpp"
+
+namespace rb {
+
+enum NNMode { kEval = 0, kGrad = 1, kForces = 2 };
+
+struct NNArgs {
+    const float *params;
+    Norm nm;
+    int64_t P;              // rows (eval/grad) or max_count (forces)
+    const float *desc;
+    int64_t stride;         // row stride of desc
+    const float *gE;
+    float *energy;
+    float *dEdu;
+    float *ft;
+    // dynamics form
+    const int32_t *idx;
+    const int32_t *count_dev;
+    const double *q;
+    int32_t n;
+    const int32_t *pi;
+    const int32_t *pj;
+    float sw_lo, sw_hi;
+    int64_t *acc;
+    int32_t *flags;
+};
+
+// ------------------------------------------------------------------ kernels
+__device__ inline float smooth_switch(float r, float lo, float hi, float &dsdr) {
+    dsdr = 0.f;
+    if (!(hi > lo) || r <= lo) return 1.f;
+    if (r >= hi) return 0.f;
+    const float w = 1.f / (hi - lo), t = (r - lo) * w;
+    dsdr = -6.f * t * (1.f - t) * w;
+    return 1.f - t * t * (3.f - 2.f * t);
+}
+
+template <int MODE, bool BF16>
+__global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
+    constexpr int kWaves = NNCfg<BF16, MODE>::waves;
+    __shared__ typename NNLds<BF16>::T L;
+    if constexpr (BF16)
+        stage_bf16(L, a.params);
+    else
+        stage_small(L, a.params);
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, n = lane & 15;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int64_t count = a.P;
+    if (MODE == kForces) {
+        const int64_t c = *a.count_dev;
+        count = c < a.P ? c : a.P;
+    }
+    long long eacc[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) eacc[k] = 0;
+    bool bad = false;
+    const int64_t ntiles = (count + kTile - 1) / kTile;
+    for (int64_t t = (int64_t)blockIdx.x * kWaves + w; t < ntiles; t += (int64_t)gridDim.x * kWaves) {
+        // Keeps the compiler from hoisting the (tile-invariant) LDS weight
+        // reads out of the loop, which would pin ~600 registers.
+        __asm__ volatile("" ::: "memory");
+        const int64_t row = t * kTile + n;
+        const bool live = row < count;
+        int64_t pid = row;
+        if (MODE == kForces && live && a.idx) pid = a.idx[row];
+        float u[kIn];
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) u[k] = live ? a.desc[k * a.stride + pid] : (k == 3 ? 1.f : 0.f);
+        float seed = 1.f, dsdr = 0.f, S = 1.f, r = 0.f;
+        if (MODE == kGrad && a.gE) seed = live ? a.gE[pid] : 0.f;
+        if (MODE == kForces) {
+            r = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            S = smooth_switch(r, a.sw_lo, a.sw_hi, dsdr);
+            seed = S;
+        }
+        float gu[kIn];
+        float E;
+        if constexpr (BF16)
+            E = tile_bf16<MODE != kEval>(L, a.nm, u, seed, gu);
+        else
+            E = tile_fp32<MODE != kEval>(L, L, a.params, a.nm, u, seed, gu);
+        if (!live || g != 0) continue;
+        if (MODE == kEval) {
+            a.energy[pid] = E;
+        } else if (MODE == kGrad) {
+            if (a.energy) a.energy[pid] = E;
+            if (a.dEdu)
+#pragma unroll
+                for (int k = 0; k < kIn; ++k) a.dEdu[k * a.P + pid] = gu[k];
+            if (a.ft) {
+                float ft[9];
+                pair_ft_from_grad(u, gu, ft);
+#pragma unroll
+                for (int k = 0; k < 9; ++k) a.ft[k * a.P + pid] = ft[k];
+            }
+        } else {
+            // switched energy: E_s = S E, dE_s/dd = S g_d + E S'(r) d / r
+            if (dsdr != 0.f) {
+                const float c = E * dsdr / r;
+                gu[0] = fmaf(c, u[0], gu[0]);
+                gu[1] = fmaf(c, u[1], gu[1]);
+                gu[2] = fmaf(c, u[2], gu[2]);
+            }
+            const float Es = S * E;
+            float ft[9];
+            pair_ft_from_grad(u, gu, ft);
+            const int i = a.pi[pid], j = a.pj[pid];
+            double R[9];
+            quat_to_rot<double>(a.q[i], a.q[a.n + i], a.q[2 * a.n + i], a.q[3 * a.n + i], R);
+            double Fj[3], ti[3], tj[3], dl[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                Fj[c] = R[3 * c] * ft[0] + R[3 * c + 1] * ft[1] + R[3 * c + 2] * ft[2];
+                ti[c] = R[3 * c] * ft[3] + R[3 * c + 1] * ft[4] + R[3 * c + 2] * ft[5];
+                tj[c] = R[3 * c] * ft[6] + R[3 * c + 1] * ft[7] + R[3 * c + 2] * ft[8];
+                dl[c] = R[3 * c] * u[0] + R[3 * c + 1] * u[1] + R[3 * c + 2] * u[2];
+            }
+            if (!isfinite(Es) || !isfinite(ft[0]) || !isfinite(ft[3]) || !isfinite(ft[6])) bad = true;
+            const int64_t nn = a.n;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                acc_add(a.acc + c * nn + i, -Fj[c]);
+                acc_add(a.acc + c * nn + j, Fj[c]);
+                acc_add(a.acc + (3 + c) * nn + i, ti[c]);
+                acc_add(a.acc + (3 + c) * nn + j, tj[c]);
+            }
+            eacc[0] += to_fixed(Es);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) eacc[1 + 3 * c + b] += to_fixed(dl[c] * Fj[b]);
+        }
+    }
+    if (MODE == kForces) {
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            long long v = eacc[k];
+            v += __shfl_xor(v, 1, kWave);
+            v += __shfl_xor(v, 2, kWave);
+            v += __shfl_xor(v, 4, kWave);
+            v += __shfl_xor(v, 8, kWave);
+            if (lane == 0 && v) atomicAdd(reinterpret_cast<unsigned long long *>(a.acc + 6 * (int64_t)a.n + k),
+                                          (unsigned long long)v);
+        }
+        if (__any(bad) && lane == 0) atomicOr(a.flags + RB_FLAG_NONFINITE, 1);
+    }
+}
+
+// Compute units of the current device (one persistent block per CU: the
+// BF16 weight image fills most of a CU's LDS).
+static int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    return cus;
+}
+
+template <int MODE>
+static int launch(const NNArgs &a, int precision, int64_t rows, hipStream_t st) {
+    const int64_t tiles = (rows + kTile - 1) / kTile;
+    const int cus = device_cus();
+    if (precision == RB_PREC_BF16) {
+        constexpr int w = NNCfg<true, MODE>::waves;
+        k_nn<MODE, true><<<grid_for(tiles, w, cus), w * kWave, 0, st>>>(a);
+    } else {
+        constexpr int w = NNCfg<false, MODE>::waves;
+        k_nn<MODE, false><<<grid_for(tiles, w, cus), w * kWave, 0, st>>>(a);
+    }
+    return hip_check(hipGetLastError(), "network kernel launch");
+}
+
+}  // namespace rb
+
+using namespace rb;
+
+extern "C" int rb_nn_pair_eval(const float *params, const float *norm, int precision, int64_t n_pairs,
+                               const float *desc, float *energy, void *stream) {
+    RB_REQUIRE(params && norm, "rb_nn_pair_eval: null params/norm");
+    RB_REQUIRE(precision == RB_PREC_BF16 || precision == RB_PREC_FP32, "rb_nn_pair_eval: bad precision");
+    RB_REQUIRE(n_pairs >= 0, "rb_nn_pair_eval: n_pairs < 0");
+    if (n_pairs == 0) return RB_OK;
+    RB_REQUIRE(desc && energy, "rb_nn_pair_eval: null desc/energy");
+    NNArgs a = {};
+    a.params = params;
+    a.nm = norm_from_host(norm);
+    a.P = n_pairs;
+    a.desc = desc;
+    a.stride = n_pairs;
+    a.energy = energy;
+    return launch<kEval>(a, precision, n_pairs, (hipStream_t)stream);
+}
+
+extern "C" int rb_nn_pair_grad(const float *params, const float *norm, int precision, int64_t n_pairs,
+                               const float *desc, const float *gE, float *energy, float *dE_ddesc, float *pair_ft,
+                               void *stream) {
+    RB_REQUIRE(params && norm, "rb_nn_pair_grad: null params/norm");
+    RB_REQUIRE(precision == RB_PREC_BF16 || precision == RB_PREC_FP32, "rb_nn_pair_grad: bad precision");
+    RB_REQUIRE(n_pairs >= 0, "rb_nn_pair_grad: n_pairs < 0");
+    if (n_pairs == 0) return RB_OK;
+    RB_REQUIRE(desc, "rb_nn_pair_grad: null desc");
+    NNArgs a = {};
+    a.params = params;
+    a.nm = norm_from_host(norm);
+    a.P = n_pairs;
+    a.desc = desc;
+    a.stride = n_pairs;
+    a.gE = gE;
+    a.energy = energy;
+    a.dEdu = dE_ddesc;
+    a.ft = pair_ft;
+    return launch<kGrad>(a, precision, n_pairs, (hipStream_t)stream);
+}
+
+extern "C" int rb_nn_pair_forces(const float *params, const float *norm, int precision, int32_t n, const double *q,
+                                 const int32_t *pair_i, const int32_t *pair_j, const float *desc, int32_t desc_stride,
+                                 const int32_t *idx, const int32_t *count_dev, int32_t max_count, float sw_lo,
+                                 float sw_hi, int64_t *acc, int32_t *flags, void *stream) {
+    RB_REQUIRE(params && norm && q && pair_i && pair_j && desc && count_dev && acc && flags,
+               "rb_nn_pair_forces: null argument");
+    RB_REQUIRE(precision == RB_PREC_BF16 || precision == RB_PREC_FP32, "rb_nn_pair_forces: bad precision");
+    RB_REQUIRE(n > 0 && max_count >= 0 && desc_stride >= max_count, "rb_nn_pair_forces: bad sizes");
+    if (max_count == 0) return RB_OK;
+    NNArgs a = {};
+    a.params = params;
+    a.nm = norm_from_host(norm);
+    a.P = max_count;
+    a.desc = desc;
+    a.stride = desc_stride;
+    a.idx = idx;
+    a.count_dev = count_dev;
+    a.q = q;
+    a.n = n;
+    a.pi = pair_i;
+    a.pj = pair_j;
+    a.sw_lo = sw_lo;
+    a.sw_hi = sw_hi;
+    a.acc = acc;
+    a.flags = flags;
+    return launch<kForces>(a, precision, max_count, (hipStream_t)stream);
+}

@@ -1,0 +1,149 @@
+// Shared pieces of the energy-network kernels (inference, gradient, training).
+//
+// Network (paper section 2, g_NN_U, sized by the workload): u (7) ->
+// 128 -> 128 -> 128 -> 128 (SiLU) -> 1.  Parameter blob, layer by layer:
+// W_l (out x in, row major) then b_l.
+//
+// Register layout.  A wave processes a tile of 16 pairs.  The three
+// 128x128 layers run as 16x16 MFMA tiles with the pairs as the N
+// dimension: z^T (128 x 16) = W (128 x 128) h^T (128 x 16).  An MFMA result
+// fragment gives lane l the pair n = l % 16 and, for each of the eight
+// 16-row tiles mt, the four features 16 mt + 4 (l / 16) + r (r = 0..3).
+// The next layer consumes those values directly as its B operand: for the
+// K-block kb of 32 input features, lane group g = l / 16 supplies slots
+// k = 8 g + i, which hold the features 32 kb + perm32(8 g + i) with
+// perm32(s) = 16 ((s % 8) / 4) + 4 (s / 8) + (s % 4).  Reordering K is free
+// for a dot product, so the weights are staged with their input columns
+// permuted the same way and no activation ever moves between lanes.
+#pragma once
+
+#include "rb_common.hpp"
+
+namespace rb {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kH = 128;
+constexpr int kIn = 7;
+constexpr int kNnWaves = 8;
+constexpr int kNnThreads = kNnWaves * kWave;
+constexpr int kTile = 16;
+constexpr int kRow = kH + 8;   // padded LDS row of bf16 weights
+
+constexpr int OFF_W1 = 0, OFF_B1 = 896, OFF_W2 = 1024, OFF_B2 = 17408, OFF_W3 = 17536, OFF_B3 = 33920,
+              OFF_W4 = 34048, OFF_B4 = 50432, OFF_W5 = 50560, OFF_B5 = 50688, NPARAMS = 50689;
+static_assert(NPARAMS == RB_MLP_NPARAMS, "parameter count");
+
+__host__ __device__ constexpr int w_off(int layer) {  // layer 2..4
+    return layer == 2 ? OFF_W2 : (layer == 3 ? OFF_W3 : OFF_W4);
+}
+__host__ __device__ constexpr int b_off(int layer) {  // layer 1..4
+    return layer == 1 ? OFF_B1 : (layer == 2 ? OFF_B2 : (layer == 3 ? OFF_B3 : OFF_B4));
+}
+
+__host__ __device__ inline int perm32(int s) { return 16 * ((s & 7) >> 2) + 4 * (s >> 3) + (s & 3); }
+__host__ __device__ inline int perm32_inv(int f) { return 8 * ((f & 15) >> 2) + 4 * (f >> 4) + (f & 3); }
+
+struct Norm {
+    float shift[kIn], scale[kIn], oshift, oscale;
+};
+
+inline Norm norm_from_host(const float *h) {
+    Norm n;
+    for (int k = 0; k < kIn; ++k) {
+        n.shift[k] = h ? h[k] : 0.f;
+        n.scale[k] = h ? h[kIn + k] : 1.f;
+    }
+    n.oshift = h ? h[14] : 0.f;
+    n.oscale = h ? h[15] : 1.f;
+    return n;
+}
+
+// SiLU and its derivative: s = 1/(1+exp(-z)), h = z s, h' = s + h (1 - s).
+__device__ inline void silu(float z, float &h, float &dh) {
+    const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * z);
+    const float s = __builtin_amdgcn_rcpf(1.f + e);
+    h = z * s;
+    dh = fmaf(h, 1.f - s, s);
+}
+
+// LDS image of the weights used by the BF16 kernels.
+struct LdsBF16 {
+    __bf16 w[3][kH][kRow];   // W2..W4, columns permuted per 32-block
+    float w1[kH][8];          // W1 (7 columns, padded)
+    float b[4][kH];           // b1..b4
+    float w5[kH];
+    float b5;
+};
+
+__device__ inline void stage_bf16(LdsBF16 &L, const float *__restrict__ p) {
+    for (int idx = threadIdx.x; idx < 3 * kH * kH; idx += blockDim.x) {
+        const int l = idx / (kH * kH), o = (idx / kH) % kH, c = idx % kH;
+        const int in = 32 * (c >> 5) + perm32(c & 31);
+        L.w[l][o][c] = (__bf16)p[w_off(l + 2) + o * kH + in];
+    }
+    for (int idx = threadIdx.x; idx < kH * 8; idx += blockDim.x) {
+        const int o = idx >> 3, k = idx & 7;
+        L.w1[o][k] = k < kIn ? p[OFF_W1 + o * kIn + k] : 0.f;
+    }
+    for (int idx = threadIdx.x; idx < 4 * kH; idx += blockDim.x)
+        L.b[idx / kH][idx % kH] = p[b_off(idx / kH + 1) + idx % kH];
+    for (int idx = threadIdx.x; idx < kH; idx += blockDim.x) L.w5[idx] = p[OFF_W5 + idx];
+    if (threadIdx.x == 0) L.b5 = p[OFF_B5];
+}
+
+// Layer 1 in FP32 for this lane's 32 features (16 mt + 4 g + r).
+__device__ inline void layer1(const float (*w1)[8], const float *b1, const float un[kIn], int g, float hv[8][4],
+                              float dv[8][4]) {
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt) {
+        __asm__ volatile("" ::: "memory");   // one tile's weights in flight at a time
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int f = 16 * mt + 4 * g + r;
+            const float4 wa = *reinterpret_cast<const float4 *>(&w1[f][0]);
+            const float4 wb = *reinterpret_cast<const float4 *>(&w1[f][4]);
+            float z = b1[f];
+            z = fmaf(wa.x, un[0], z); z = fmaf(wa.y, un[1], z); z = fmaf(wa.z, un[2], z);
+            z = fmaf(wa.w, un[3], z); z = fmaf(wb.x, un[4], z); z = fmaf(wb.y, un[5], z);
+            z = fmaf(wb.z, un[6], z);
+            silu(z, hv[mt][r], dv[mt][r]);
+        }
+    }
+}
+
+__device__ inline bf16x8 pack8(const float a[4], const float b[4]) {
+    bf16x8 v;
+    v[0] = (__bf16)a[0]; v[1] = (__bf16)a[1]; v[2] = (__bf16)a[2]; v[3] = (__bf16)a[3];
+    v[4] = (__bf16)b[0]; v[5] = (__bf16)b[1]; v[6] = (__bf16)b[2]; v[7] = (__bf16)b[3];
+    return v;
+}
+
+// Sum over the four lane groups that share a pair.
+__device__ inline float group_sum(float v) {
+    v += __shfl_xor(v, 16, kWave);
+    v += __shfl_xor(v, 32, kWave);
+    return v;
+}
+
+// Forces and torques of a pair from g = dE/du (supplementary section 6
+// defines f = -dE/dx and tau = -dE/dtheta; with the quaternion descriptor
+// the rotation derivative has the closed form below), body i's frame:
+// F_j = -g_d, tau_j = -(w g_v - g_w v + v x g_v)/2, tau_i = -tau_j - d x F_j.
+__device__ inline void pair_ft_from_grad(const float u[kIn], const float gu[kIn], float ft[9]) {
+    const float w = u[3], vx = u[4], vy = u[5], vz = u[6];
+    const float gw = gu[3], gx = gu[4], gy = gu[5], gz = gu[6];
+    const float Fx = -gu[0], Fy = -gu[1], Fz = -gu[2];
+    const float tjx = -0.5f * (w * gx - gw * vx + (vy * gz - vz * gy));
+    const float tjy = -0.5f * (w * gy - gw * vy + (vz * gx - vx * gz));
+    const float tjz = -0.5f * (w * gz - gw * vz + (vx * gy - vy * gx));
+    const float dx = u[0], dy = u[1], dz = u[2];
+    ft[0] = Fx; ft[1] = Fy; ft[2] = Fz;
+    ft[3] = -tjx - (dy * Fz - dz * Fy);
+    ft[4] = -tjy - (dz * Fx - dx * Fz);
+    ft[5] = -tjz - (dx * Fy - dy * Fx);
+    ft[6] = tjx; ft[7] = tjy; ft[8] = tjz;
+}
+
+}  // namespace rb

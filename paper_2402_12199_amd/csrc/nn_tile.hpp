@@ -1,0 +1,329 @@
+// Per-tile forward / reverse passes of the energy network, shared by the
+// inference kernels and the training kernel.
+#pragma once
+
+#include "nn_common.hpp"
+
+namespace rb {
+
+// Optional output of the per-pair activations and reverse-pass deltas of a
+// tile (training): H rows h0 (7, normalised input), h1..h4 (128 each);
+// D rows delta1..delta4 (128 each, dX/dz_l) and delta5 (1, dX/de'); both
+// feature-major with row stride B, column = this lane's batch row.
+constexpr int kHRows = kIn + 4 * kH;
+constexpr int kDRows = 4 * kH + 1;
+struct Emit {
+    float *H = nullptr;
+    float *D = nullptr;
+    float *R = nullptr;     // residual e' - y' per batch row
+    int64_t B = 0;
+    int64_t b = 0;
+    bool live = false;
+    float y = 0.f;          // normalised label of this row
+    float k2 = 0.f;         // 2 / B: the loss gradient is k2 (e' - y')
+    __device__ float &h(int row) const { return H[row * B + b]; }
+    __device__ float &d(int row) const { return D[row * B + b]; }
+};
+
+// ------------------------------------------------------------------ BF16
+// Forward (and optionally reverse) pass of one 16-pair tile.  Returns E for
+// this lane's pair; gu receives dX/du when GRAD (X = seed * E).  Each 16-row
+// output tile is finished (bias, MFMA chain, SiLU, BF16 packing) before the
+// next one starts, which keeps the live register set small.
+template <bool GRAD, bool EMIT = false>
+__device__ inline float tile_bf16(const LdsBF16 &L, const Norm &nm, const float u[kIn], float seed,
+                                  float gu[kIn], const Emit &em = Emit{}) {
+    const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, n = lane & 15;
+    float un[kIn];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) un[k] = (u[k] - nm.shift[k]) * nm.scale[k];
+    if (EMIT && em.live && g == 0)
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) em.h(k) = un[k];
+    bf16x8 act[4];
+    bf16x8 sp[4][4];
+    {
+        float hv[8][4], dv[8][4];
+        layer1(L.w1, L.b[0], un, g, hv, dv);
+        if (EMIT && em.live)
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) em.h(kIn + 16 * mt + 4 * g + r) = hv[mt][r];
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+            act[kb] = pack8(hv[2 * kb], hv[2 * kb + 1]);
+            if (GRAD) sp[0][kb] = pack8(dv[2 * kb], dv[2 * kb + 1]);
+        }
+    }
+    float e = 0.f;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        bf16x8 nact[4];
+        float hlo[4], dlo[4];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            __asm__ volatile("" ::: "memory");
+            f32x4 c = *reinterpret_cast<const f32x4 *>(&L.b[l + 1][16 * mt + 4 * g]);
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&L.w[l][16 * mt + n][32 * kb + 8 * g]);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kb], c, 0, 0, 0);
+            }
+            float h[4], d[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) silu(c[r], h[r], d[r]);
+            if (EMIT && em.live)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) em.h(kIn + kH * (l + 1) + 16 * mt + 4 * g + r) = h[r];
+            if (l == 2) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) e = fmaf(L.w5[16 * mt + 4 * g + r], h[r], e);
+            }
+            if ((mt & 1) == 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) { hlo[r] = h[r]; dlo[r] = d[r]; }
+            } else {
+                if (l < 2) nact[mt >> 1] = pack8(hlo, h);
+                if (GRAD) sp[l + 1][mt >> 1] = pack8(dlo, d);
+            }
+        }
+        if (l < 2) {
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) act[kb] = nact[kb];
+        }
+    }
+    e = group_sum(e) + L.b5;
+    const float E = fmaf(e, nm.oscale, nm.oshift);
+    if (!GRAD) return E;
+    if (EMIT) {
+        seed = em.live ? em.k2 * (E - em.y) : 0.f;
+        if (em.live && g == 0) em.R[em.b] = E - em.y;
+    }
+
+    // reverse pass: delta_4 = seed * oscale * w5 (.) h4'
+    const float s0 = seed * nm.oscale;
+    bf16x8 dpk[4];
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        float a0[4], a1[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            a0[r] = s0 * L.w5[32 * kb + 4 * g + r] * (float)sp[3][kb][r];
+            a1[r] = s0 * L.w5[32 * kb + 16 + 4 * g + r] * (float)sp[3][kb][4 + r];
+            if (EMIT && em.live) {
+                em.d(3 * kH + 32 * kb + 4 * g + r) = a0[r];
+                em.d(3 * kH + 32 * kb + 16 + 4 * g + r) = a1[r];
+            }
+        }
+        dpk[kb] = pack8(a0, a1);
+    }
+    if (EMIT && em.live && g == 0) em.d(4 * kH) = s0;
+    float gk[kIn];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) gk[k] = 0.f;
+#pragma unroll
+    for (int l = 2; l >= 0; --l) {
+        bf16x8 ndpk[4];
+        float dlo[4];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            __asm__ volatile("" ::: "memory");
+            // input feature 16 mt + n lives in LDS column col
+            const int col = 32 * (mt >> 1) + 8 * (n >> 2) + 4 * (mt & 1) + (n & 3);
+            f32x4 c = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                bf16x8 a;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) a[i] = L.w[l][32 * kb + 16 * (i >> 2) + 4 * g + (i & 3)][col];
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, dpk[kb], c, 0, 0, 0);
+            }
+            float d[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) d[r] = c[r] * (float)sp[l][mt >> 1][4 * (mt & 1) + r];
+            if (EMIT && em.live)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) em.d(kH * l + 16 * mt + 4 * g + r) = d[r];
+            if (l > 0) {
+                if ((mt & 1) == 0) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) dlo[r] = d[r];
+                } else {
+                    ndpk[mt >> 1] = pack8(dlo, d);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int f = 16 * mt + 4 * g + r;
+#pragma unroll
+                    for (int k = 0; k < kIn; ++k) gk[k] = fmaf(L.w1[f][k], d[r], gk[k]);
+                }
+            }
+        }
+        if (l > 0) {
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) dpk[kb] = ndpk[kb];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) gu[k] = group_sum(gk[k]) * nm.scale[k];
+    return E;
+}
+
+// ------------------------------------------------------------------ FP32
+// Small LDS image for the FP32 path: W1, biases, w5, and per wave the SiLU
+// derivatives of the forward pass (4 layers x 32 values x 64 lanes).
+constexpr int kF32Waves = 4;
+struct LdsFP32 {
+    float w1[kH][8];
+    float b[4][kH];
+    float w5[kH];
+    float b5;
+    float sp[kF32Waves][4][32][kWave];
+};
+
+template <bool GRAD, bool EMIT = false>
+__device__ inline float tile_fp32(const LdsFP32 &Lc, LdsFP32 &L, const float *__restrict__ p, const Norm &nm,
+                                  const float u[kIn], float seed, float gu[kIn], const Emit &em = Emit{}) {
+    const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, n = lane & 15;
+    const int w = threadIdx.x >> 6;
+    float un[kIn];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) un[k] = (u[k] - nm.shift[k]) * nm.scale[k];
+    if (EMIT && em.live && g == 0)
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) em.h(k) = un[k];
+    float hv[8][4], dv[8][4];
+    layer1(Lc.w1, Lc.b[0], un, g, hv, dv);
+    if (EMIT && em.live)
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) em.h(kIn + 16 * mt + 4 * g + r) = hv[mt][r];
+    if (GRAD) {
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) L.sp[w][0][4 * mt + r][lane] = dv[mt][r];
+    }
+    for (int l = 0; l < 3; ++l) {
+        const float *W = p + w_off(l + 2);
+        f32x4 acc[8];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) acc[mt] = *reinterpret_cast<const f32x4 *>(&Lc.b[l + 1][16 * mt + 4 * g]);
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            __asm__ volatile("" ::: "memory");
+            const float *row = W + (16 * mt + n) * kH + 4 * g;
+#pragma unroll
+            for (int m2 = 0; m2 < 8; ++m2) {
+                const float4 a = *reinterpret_cast<const float4 *>(row + 16 * m2);
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, hv[m2][0], acc[mt], 0, 0, 0);
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, hv[m2][1], acc[mt], 0, 0, 0);
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, hv[m2][2], acc[mt], 0, 0, 0);
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, hv[m2][3], acc[mt], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                silu(acc[mt][r], hv[mt][r], dv[mt][r]);
+                if (GRAD) L.sp[w][l + 1][4 * mt + r][lane] = dv[mt][r];
+                if (EMIT && em.live) em.h(kIn + kH * (l + 1) + 16 * mt + 4 * g + r) = hv[mt][r];
+            }
+    }
+    float e = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) e = fmaf(Lc.w5[16 * mt + 4 * g + r], hv[mt][r], e);
+    e = group_sum(e) + Lc.b5;
+    const float E = fmaf(e, nm.oscale, nm.oshift);
+    if (!GRAD) return E;
+    if (EMIT) {
+        seed = em.live ? em.k2 * (E - em.y) : 0.f;
+        if (em.live && g == 0) em.R[em.b] = E - em.y;
+    }
+    const float s0 = seed * nm.oscale;
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            dv[mt][r] = s0 * Lc.w5[16 * mt + 4 * g + r] * L.sp[w][3][4 * mt + r][lane];
+            if (EMIT && em.live) em.d(3 * kH + 16 * mt + 4 * g + r) = dv[mt][r];
+        }
+    if (EMIT && em.live && g == 0) em.d(4 * kH) = s0;
+    for (int l = 2; l >= 0; --l) {
+        const float *W = p + w_off(l + 2);
+        f32x4 acc[8];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            __asm__ volatile("" ::: "memory");
+            const float *colp = W + 16 * mt + n;   // column (input feature) 16 mt + n
+#pragma unroll
+            for (int m2 = 0; m2 < 8; ++m2)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(colp[(16 * m2 + 4 * g + r) * kH], dv[m2][r],
+                                                                  acc[mt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                dv[mt][r] = acc[mt][r] * L.sp[w][l][4 * mt + r][lane];
+                if (EMIT && em.live) em.d(kH * l + 16 * mt + 4 * g + r) = dv[mt][r];
+            }
+    }
+    float gk[kIn];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) gk[k] = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int f = 16 * mt + 4 * g + r;
+#pragma unroll
+            for (int k = 0; k < kIn; ++k) gk[k] = fmaf(Lc.w1[f][k], dv[mt][r], gk[k]);
+        }
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) gu[k] = group_sum(gk[k]) * nm.scale[k];
+    return E;
+}
+
+// Stages W1, biases and w5 (the FP32 path reads W2..W4 from global memory).
+__device__ inline void stage_small(LdsFP32 &L, const float *__restrict__ p) {
+    for (int idx = threadIdx.x; idx < kH * 8; idx += blockDim.x) {
+        const int o = idx >> 3, k = idx & 7;
+        L.w1[o][k] = k < kIn ? p[OFF_W1 + o * kIn + k] : 0.f;
+    }
+    for (int idx = threadIdx.x; idx < 4 * kH; idx += blockDim.x)
+        L.b[idx / kH][idx % kH] = p[b_off(idx / kH + 1) + idx % kH];
+    for (int idx = threadIdx.x; idx < kH; idx += blockDim.x) L.w5[idx] = p[OFF_W5 + idx];
+    if (threadIdx.x == 0) L.b5 = p[OFF_B5];
+}
+
+// Waves per block: the BF16 forward fits two waves per SIMD (<= 256
+// registers); the BF16 reverse pass holds the SiLU derivatives of four layers
+// in registers and runs one wave per SIMD; the FP32 path keeps them in LDS.
+template <bool BF16, int MODE>
+struct NNCfg {
+    static constexpr int waves = BF16 ? (MODE == 0 ? kNnWaves : 4) : kF32Waves;
+};
+__host__ __device__ constexpr int nn_threads(bool bf16, int mode) {
+    return (bf16 ? (mode == 0 ? kNnWaves : 4) : kF32Waves) * kWave;
+}
+template <bool BF16>
+struct NNLds {
+    typedef LdsBF16 T;
+};
+template <>
+struct NNLds<false> {
+    typedef LdsFP32 T;
+};
+
+}  // namespace rb

@@ -1,0 +1,330 @@
+// Cell-list pair builder: half list (i < j) of body pairs whose minimum-image
+// centre distance is below r_list.
+//
+// Pipeline (each kernel returns at once when the list is only rebuilt on
+// request and the rebuild flag is clear, so the whole sequence can sit in a
+// captured graph):
+//   bin bodies into cells of edge >= r_list (count per cell)
+//   exclusive scan of cell counts -> cell starts
+//   scatter body ids into cell order, then sort each cell's ids, which makes
+//   the cell contents independent of atomic arrival order
+//   per body i: count neighbours j > i in the 27 surrounding cells
+//   exclusive scan of those counts -> per-body offsets, total -> flags
+//   per body i: write its pairs at its offset, in the same cell order
+// The resulting list is sorted by i and fully deterministic.
+#include "rb_common.hpp"
+
+namespace rb {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;  // 2048
+
+struct CellGrid {
+    int nc[3];
+    int ncell;
+    double L[3], inv[3], cinv[3];  // cinv: cells per unit length
+    double rl2;
+};
+
+__device__ inline bool skip(const int32_t *flags, int mode) {
+    return mode == RB_BUILD_IF_FLAGGED && flags[RB_FLAG_REBUILD] == 0;
+}
+
+__device__ inline int cell_coord(double x, double L, double cinv, int nc) {
+    double w = x - L * floor(x / L);  // wrap into [0, L)
+    int c = (int)(w * cinv);
+    return c >= nc ? nc - 1 : (c < 0 ? 0 : c);
+}
+
+__global__ void k_fill(int32_t *a, int m, int v, const int32_t *flags, int mode) {
+    if (skip(flags, mode)) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) a[i] = v;
+}
+
+__global__ void k_bin(int32_t n, const double *__restrict__ x, CellGrid g, int32_t *__restrict__ cell_of,
+                      int32_t *__restrict__ cnt, double *__restrict__ x_ref, const int32_t *flags, int mode) {
+    if (skip(flags, mode)) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double v = x[a * n + i];
+        if (x_ref) x_ref[a * n + i] = v;
+        c[a] = cell_coord(v, g.L[a], g.cinv[a], g.nc[a]);
+    }
+    int id = (c[0] * g.nc[1] + c[1]) * g.nc[2] + c[2];
+    cell_of[i] = id;
+    atomicAdd(cnt + id, 1);
+}
+
+// Block-local exclusive scan of kScanTile ints; block totals to tmp.
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const int32_t *__restrict__ in,
+                                                             int32_t *__restrict__ out, int m,
+                                                             int32_t *__restrict__ tmp,
+                                                             const int32_t *flags, int mode) {
+    if (skip(flags, mode)) return;
+    __shared__ int32_t wsum[kScanThreads / kWave];
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < m) ? in[base + k] : 0;
+        s += v[k];
+    }
+    // inclusive scan of thread sums within the wave
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+    int incl = s;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        int t = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += t;
+    }
+    if (lane == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    int woff = 0;
+    for (int k = 0; k < w; ++k) woff += wsum[k];
+    int run = woff + incl - s;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < m) out[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == kScanThreads - 1) tmp[blockIdx.x] = woff + incl;
+}
+
+// Scan of the (at most kScanTile) tile totals, in place, by one block; the
+// grand total goes to out[m], and optionally to the pair-count flags.
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(int32_t *__restrict__ tmp, int ntiles,
+                                                           int32_t *__restrict__ out, int m,
+                                                           int32_t *flags, int mode, int cap) {
+    if (skip(flags, mode)) return;
+    __shared__ int32_t wsum[kScanThreads / kWave];
+    const int base = threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < ntiles) ? tmp[base + k] : 0;
+        s += v[k];
+    }
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+    int incl = s;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        int t = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += t;
+    }
+    if (lane == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    int woff = 0;
+    for (int k = 0; k < w; ++k) woff += wsum[k];
+    int run = woff + incl - s;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < ntiles) tmp[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == kScanThreads - 1) {
+        const int total = woff + incl;
+        out[m] = total;
+        if (cap >= 0) {
+            flags[RB_FLAG_NPAIRS] = total < cap ? total : cap;
+            flags[RB_FLAG_OVERFLOW] = total > cap ? total : 0;
+        }
+    }
+}
+
+__global__ void k_scan_add(int32_t *__restrict__ out, int m, const int32_t *__restrict__ tmp,
+                           const int32_t *flags, int mode) {
+    if (skip(flags, mode)) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) out[i] += tmp[i / kScanTile];
+}
+
+__global__ void k_scatter(int32_t n, const int32_t *__restrict__ cell_of, const int32_t *__restrict__ start,
+                          int32_t *__restrict__ fill, int32_t *__restrict__ sorted, const int32_t *flags,
+                          int mode) {
+    if (skip(flags, mode)) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = cell_of[i];
+    int slot = atomicAdd(fill + c, 1);
+    sorted[start[c] + slot] = i;
+}
+
+// Insertion sort of each cell's ids (cells hold a handful of bodies).
+__global__ void k_sort_cells(int ncell, const int32_t *__restrict__ start, int32_t *__restrict__ sorted,
+                             const int32_t *flags, int mode) {
+    if (skip(flags, mode)) return;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    int b = start[c], e = start[c + 1];
+    for (int k = b + 1; k < e; ++k) {
+        int v = sorted[k], m = k - 1;
+        while (m >= b && sorted[m] > v) {
+            sorted[m + 1] = sorted[m];
+            --m;
+        }
+        sorted[m + 1] = v;
+    }
+}
+
+template <bool EMIT>
+__global__ void k_neigh(int32_t n, const double *__restrict__ x, CellGrid g, const int32_t *__restrict__ cell_of,
+                        const int32_t *__restrict__ start, const int32_t *__restrict__ sorted,
+                        int32_t *__restrict__ ncount, const int32_t *__restrict__ noff,
+                        int32_t *__restrict__ pi, int32_t *__restrict__ pj, int32_t cap,
+                        const int32_t *flags, int mode) {
+    if (skip(flags, mode)) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double xi = x[i], yi = x[n + i], zi = x[2 * n + i];
+    const int id = cell_of[i];
+    const int cz = id % g.nc[2], cy = (id / g.nc[2]) % g.nc[1], cx = id / (g.nc[2] * g.nc[1]);
+    int lo[3], hi[3];
+    const int cc[3] = {cx, cy, cz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = g.nc[a] >= 3 ? -1 : 0;
+        hi[a] = g.nc[a] >= 3 ? 1 : g.nc[a] - 1;
+    }
+    (void)cc;
+    int cnt = 0;
+    int out = EMIT ? noff[i] : 0;
+    for (int ox = lo[0]; ox <= hi[0]; ++ox) {
+        int nx = cx + ox;
+        nx += nx < 0 ? g.nc[0] : (nx >= g.nc[0] ? -g.nc[0] : 0);
+        for (int oy = lo[1]; oy <= hi[1]; ++oy) {
+            int ny = cy + oy;
+            ny += ny < 0 ? g.nc[1] : (ny >= g.nc[1] ? -g.nc[1] : 0);
+            for (int oz = lo[2]; oz <= hi[2]; ++oz) {
+                int nz = cz + oz;
+                nz += nz < 0 ? g.nc[2] : (nz >= g.nc[2] ? -g.nc[2] : 0);
+                const int c = (nx * g.nc[1] + ny) * g.nc[2] + nz;
+                for (int m = start[c], e = start[c + 1]; m < e; ++m) {
+                    const int j = sorted[m];
+                    if (j <= i) continue;
+                    const double dx = min_image(x[j] - xi, g.L[0], g.inv[0]);
+                    const double dy = min_image(x[n + j] - yi, g.L[1], g.inv[1]);
+                    const double dz = min_image(x[2 * n + j] - zi, g.L[2], g.inv[2]);
+                    if (dx * dx + dy * dy + dz * dz < g.rl2) {
+                        if (EMIT) {
+                            if (out < cap) {
+                                pi[out] = i;
+                                pj[out] = j;
+                            }
+                            ++out;
+                        } else {
+                            ++cnt;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (!EMIT) ncount[i] = cnt;
+}
+
+__global__ void k_finish(int32_t *flags, int mode) {
+    if (skip(flags, mode)) return;
+    flags[RB_FLAG_REBUILD] = 0;
+    flags[RB_FLAG_NREBUILDS] += 1;
+}
+
+struct PLLayout {
+    size_t cell_of, cnt, start, fill, sorted, ncount, noff, tmp, total;
+};
+
+static bool make_grid(int32_t n, const double *box, double r_list, CellGrid &g) {
+    if (!(r_list > 0)) return false;
+    int64_t ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (!(box[a] >= 2.0 * r_list)) return false;
+        int nc = (int)floor(box[a] / r_list);
+        if (nc > 1024) nc = 1024;
+        g.nc[a] = nc;
+        g.L[a] = box[a];
+        g.inv[a] = 1.0 / box[a];
+        g.cinv[a] = nc / box[a];
+        ncell *= nc;
+    }
+    if (ncell > (int64_t)kScanTile * kScanTile) return false;
+    g.ncell = (int)ncell;
+    g.rl2 = r_list * r_list;
+    (void)n;
+    return true;
+}
+
+static size_t al(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static PLLayout layout(int32_t n, int ncell) {
+    PLLayout L;
+    size_t o = 0;
+    L.cell_of = o; o += al(sizeof(int32_t) * n);
+    L.cnt = o; o += al(sizeof(int32_t) * ncell);
+    L.start = o; o += al(sizeof(int32_t) * (ncell + 1));
+    L.fill = o; o += al(sizeof(int32_t) * ncell);
+    L.sorted = o; o += al(sizeof(int32_t) * n);
+    L.ncount = o; o += al(sizeof(int32_t) * n);
+    L.noff = o; o += al(sizeof(int32_t) * (n + 1));
+    L.tmp = o; o += al(sizeof(int32_t) * kScanTile);
+    L.total = o;
+    return L;
+}
+
+// Exclusive scan of in[0..m) into out[0..m], total into out[m].
+static void scan(const int32_t *in, int32_t *out, int m, int32_t *tmp, int32_t *flags, int mode, int cap,
+                 hipStream_t st) {
+    const int ntiles = (m + kScanTile - 1) / kScanTile;
+    k_scan_tiles<<<ntiles > 0 ? ntiles : 1, kScanThreads, 0, st>>>(in, out, m, tmp, flags, mode);
+    k_scan_top<<<1, kScanThreads, 0, st>>>(tmp, ntiles, out, m, flags, mode, cap);
+    k_scan_add<<<(m + 255) / 256 > 0 ? (m + 255) / 256 : 1, 256, 0, st>>>(out, m, tmp, flags, mode);
+}
+
+}  // namespace rb
+
+using namespace rb;
+
+extern "C" size_t rb_pairlist_workspace_bytes(int32_t n, const double *box, double r_list) {
+    CellGrid g;
+    if (n < 0 || !box || !make_grid(n, box, r_list, g)) return 0;
+    return layout(n, g.ncell).total;
+}
+
+extern "C" int rb_pairlist_build(int32_t n, const double *x, const double *box, double r_list,
+                                 int32_t *pair_i, int32_t *pair_j, int32_t max_pairs, double *x_ref,
+                                 int32_t *flags, int mode, void *ws, size_t ws_bytes, void *stream) {
+    RB_REQUIRE(x && box && pair_i && pair_j && flags && ws, "rb_pairlist_build: null argument");
+    RB_REQUIRE(n > 0 && n <= (1 << 22), "rb_pairlist_build: n must be in 1..2^22");
+    RB_REQUIRE(max_pairs > 0, "rb_pairlist_build: max_pairs must be > 0");
+    RB_REQUIRE(mode == RB_BUILD_ALWAYS || mode == RB_BUILD_IF_FLAGGED, "rb_pairlist_build: bad mode");
+    CellGrid g;
+    RB_REQUIRE(make_grid(n, box, r_list, g),
+               "rb_pairlist_build: need box >= 2 r_list on every axis and at most 2048^2 cells");
+    PLLayout L = layout(n, g.ncell);
+    RB_REQUIRE(ws_bytes >= L.total, "rb_pairlist_build: workspace too small (%zu < %zu)", ws_bytes, L.total);
+    char *w = static_cast<char *>(ws);
+    int32_t *cell_of = (int32_t *)(w + L.cell_of), *cnt = (int32_t *)(w + L.cnt),
+            *start = (int32_t *)(w + L.start), *fill = (int32_t *)(w + L.fill),
+            *sorted = (int32_t *)(w + L.sorted), *ncount = (int32_t *)(w + L.ncount),
+            *noff = (int32_t *)(w + L.noff), *tmp = (int32_t *)(w + L.tmp);
+    hipStream_t st = (hipStream_t)stream;
+    const int gb = (n + 255) / 256, gc = (g.ncell + 255) / 256;
+    k_fill<<<gc, 256, 0, st>>>(cnt, g.ncell, 0, flags, mode);
+    k_fill<<<gc, 256, 0, st>>>(fill, g.ncell, 0, flags, mode);
+    k_bin<<<gb, 256, 0, st>>>(n, x, g, cell_of, cnt, x_ref, flags, mode);
+    scan(cnt, start, g.ncell, tmp, flags, mode, -1, st);
+    k_scatter<<<gb, 256, 0, st>>>(n, cell_of, start, fill, sorted, flags, mode);
+    k_sort_cells<<<gc, 256, 0, st>>>(g.ncell, start, sorted, flags, mode);
+    k_neigh<false><<<gb, 256, 0, st>>>(n, x, g, cell_of, start, sorted, ncount, nullptr, nullptr, nullptr, 0,
+                                       flags, mode);
+    scan(ncount, noff, n, tmp, flags, mode, max_pairs, st);
+    k_neigh<true><<<gb, 256, 0, st>>>(n, x, g, cell_of, start, sorted, nullptr, noff, pair_i, pair_j, max_pairs,
+                                      flags, mode);
+    k_finish<<<1, 1, 0, st>>>(flags, mode);
+    RB_LAUNCH_CHECK("rb_pairlist_build");
+    return RB_OK;
+}

@@ -1,0 +1,109 @@
+// Shared device helpers of the rigidnn HIP library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rigidnn.h"
+
+namespace rb {
+
+constexpr int kWave = 64;
+constexpr int kMaxTypes = 8;
+constexpr int kMaxBeads = 256;
+
+// Error string for rb_last_error (thread local), set by the entry points.
+void set_error(const char *fmt, ...);
+int hip_check(hipError_t e, const char *what);
+
+#define RB_REQUIRE(cond, ...)                  \
+    do {                                       \
+        if (!(cond)) {                         \
+            ::rb::set_error(__VA_ARGS__);      \
+            return RB_ERR_INVALID_ARG;         \
+        }                                      \
+    } while (0)
+
+#define RB_LAUNCH_CHECK(what)                                       \
+    do {                                                            \
+        int _rc = ::rb::hip_check(hipGetLastError(), what);         \
+        if (_rc != RB_OK) return _rc;                               \
+    } while (0)
+
+struct Templates {
+    const float4 *beads;       // all types concatenated, w unused
+    int n[kMaxTypes];
+    int off[kMaxTypes];
+    int n_types;
+};
+
+struct LJ {
+    float rc2, sig2, c4e, c24e, ushift;  // 4 eps, 24 eps, u(rc)
+};
+
+struct CtxDevice {
+    Templates t;
+    LJ lj;
+    const double *mass;      // [type]
+    const double *inertia;   // [type][3]
+};
+
+// ------------------------------------------------------------- fixed point
+__device__ inline long long to_fixed(double v) { return __double2ll_rn(v * RB_ACC_SCALE); }
+
+__device__ inline void acc_add(int64_t *a, double v) {
+    atomicAdd(reinterpret_cast<unsigned long long *>(a),
+              static_cast<unsigned long long>(to_fixed(v)));
+}
+
+// ------------------------------------------------------------- quaternions
+// Unit quaternion (w, x, y, z) -> rotation matrix, body to lab, row major.
+template <typename T>
+__device__ inline void quat_to_rot(T w, T x, T y, T z, T R[9]) {
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z); R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z); R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y); R[7] = 2 * (y * z + w * x); R[8] = 1 - 2 * (x * x + y * y);
+}
+
+__device__ inline double min_image(double d, double L, double invL) { return d - L * rint(d * invL); }
+
+// --------------------------------------------------------------- reductions
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+template <typename T>
+__device__ inline T wave_min(T v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Orders LDS writes of this wave before later LDS reads of other lanes of the
+// same wave.
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+inline int grid_for(int64_t work, int per_block, int cap) {
+    int64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return static_cast<int>(g);
+}
+
+}  // namespace rb
+
+struct rb_ctx {
+    rb::CtxDevice dev;
+    int n_types;
+    int n_beads[rb::kMaxTypes];
+    float rmax[rb::kMaxTypes];
+    void *alloc_beads;
+    void *alloc_mass;
+};

@@ -1,0 +1,142 @@
+"""Dynamics driver: composes the C-ABI entry points into one MD step.
+
+Bead path step (velocity Verlet):
+  rigid_step phase 1 (half kick, drift, free rotation, skin test)
+  pairlist_build (only when the skin test flagged a rebuild)
+  accum_zero -> bead_pair_forces over every listed pair -> accum_finalize
+  rigid_step phase 2 (second half kick, kinetic energy)
+Network path step: the same, except that after the pair list
+  pair_descriptors routes each pair to the network (|d| >= d_min) or to the
+  bead sum, and nn_pair_forces + bead_pair_forces share one accumulator.
+
+Every call only enqueues work on the current stream; nothing in `step`
+synchronises, so a step can be captured in a HIP graph.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import abi
+
+
+@dataclass
+class NNModel:
+    params: torch.Tensor           # RB_MLP_NPARAMS FP32 on the device
+    norm: np.ndarray               # 16 floats
+    precision: int = abi.RB_PREC_BF16
+    d_min: float = 0.0             # below: bead fallback
+    sw_lo: float = 0.0             # energy switch (sw_hi <= sw_lo: off)
+    sw_hi: float = 0.0
+
+
+class RigidSystem:
+    def __init__(self, templates, masses, inertias, types, x, q, P, L, box, r_list, skin,
+                 eps=1.0, sigma=1.0, rc=2.5, max_pairs=None, device="cuda"):
+        self.dev = torch.device(device)
+        self.ctx = abi.Ctx(templates, masses, inertias, eps, sigma, rc)
+        n = len(x)
+        self.n = n
+        self.box = np.broadcast_to(np.asarray(box, np.float64), (3,)).copy()
+        self.r_list = float(r_list)
+        self.half_skin = 0.5 * float(skin)
+
+        def dt64(a, rows):
+            return torch.tensor(np.ascontiguousarray(np.asarray(a, np.float64).T.reshape(rows, n)),
+                                device=self.dev)
+
+        self.x = dt64(x, 3)
+        self.q = dt64(q, 4)
+        self.P = dt64(P, 3)
+        self.L = dt64(L, 3)
+        self.types = torch.tensor(np.asarray(types, np.int32), device=self.dev)
+        self.x_ref = torch.zeros_like(self.x)
+        self.flags = torch.zeros(abi.RB_NFLAGS, dtype=torch.int32, device=self.dev)
+        if max_pairs is None:
+            vol = float(np.prod(self.box))
+            mean_nb = n * 4.0 / 3.0 * math.pi * self.r_list ** 3 / vol
+            max_pairs = int(n * (4.0 * mean_nb + 8.0) / 2.0) + 4096
+        self.max_pairs = int(max_pairs)
+        self.pair_i = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
+        self.pair_j = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
+        self.acc = torch.zeros(abi.acc_len(n), dtype=torch.int64, device=self.dev)
+        self.force = torch.zeros((3, n), dtype=torch.float32, device=self.dev)
+        self.torque = torch.zeros((3, n), dtype=torch.float32, device=self.dev)
+        self.ev = torch.zeros(10, dtype=torch.float64, device=self.dev)
+        self.kinetic = torch.zeros(2, dtype=torch.float64, device=self.dev)
+        self.ws_pl = torch.zeros(abi.rb_pairlist_workspace_bytes(n, self.box, self.r_list), dtype=torch.uint8,
+                                 device=self.dev)
+        self.ws_rig = torch.zeros(abi.rb_rigid_workspace_bytes(n), dtype=torch.uint8, device=self.dev)
+        self.nn: NNModel | None = None
+        self.desc = None
+
+    # ------------------------------------------------------------ pieces
+    def build_pairs(self, always=True):
+        abi.rb_pairlist_build(self.x, self.box, self.r_list, self.pair_i, self.pair_j, self.x_ref, self.flags,
+                              abi.RB_BUILD_ALWAYS if always else abi.RB_BUILD_IF_FLAGGED, self.ws_pl)
+
+    def set_nn(self, model: NNModel):
+        self.nn = model
+        self.desc = torch.zeros((7, self.max_pairs), dtype=torch.float32, device=self.dev)
+        self.idx_nn = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
+        self.idx_bead = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
+
+    def compute_forces(self, path="bead"):
+        abi.rb_accum_zero(self.n, self.acc)
+        if path == "bead":
+            abi.rb_bead_pair_forces(self.ctx, self.x, self.q, self.types, self.box, self.pair_i, self.pair_j,
+                                    None, self.flags[abi.RB_FLAG_NPAIRS:], self.max_pairs, self.acc, self.flags)
+        elif path == "nn":
+            m = self.nn
+            abi.rb_pair_descriptors(self.x, self.q, self.box, self.pair_i, self.pair_j, m.d_min, self.desc,
+                                    self.idx_nn, self.idx_bead, self.flags)
+            abi.rb_nn_pair_forces(m.params, m.norm, m.precision, self.q, self.pair_i, self.pair_j, self.desc,
+                                  self.idx_nn, self.flags[abi.RB_FLAG_NNN:], self.max_pairs, m.sw_lo, m.sw_hi,
+                                  self.acc, self.flags)
+            abi.rb_bead_pair_forces(self.ctx, self.x, self.q, self.types, self.box, self.pair_i, self.pair_j,
+                                    self.idx_bead, self.flags[abi.RB_FLAG_NBEAD:], self.max_pairs, self.acc,
+                                    self.flags)
+        else:
+            raise ValueError(path)
+        abi.rb_accum_finalize(self.n, self.acc, self.force, self.torque, self.ev)
+
+    def init_forces(self, path="bead"):
+        self.build_pairs(always=True)
+        self.compute_forces(path)
+
+    def step(self, dt, path="bead"):
+        abi.rb_rigid_step(self.ctx, 1, dt, self.x, self.P, self.q, self.L, self.types, self.force, self.torque,
+                          self.x_ref, self.half_skin, None, self.flags, None)
+        self.build_pairs(always=False)
+        self.compute_forces(path)
+        abi.rb_rigid_step(self.ctx, 2, dt, None, self.P, self.q, self.L, self.types, self.force, self.torque,
+                          None, 0.0, self.kinetic, None, self.ws_rig)
+
+    # ------------------------------------------------------------ readback
+    def flags_host(self) -> np.ndarray:
+        return self.flags.cpu().numpy()
+
+    def check_capacity(self):
+        f = self.flags_host()
+        if f[abi.RB_FLAG_OVERFLOW]:
+            raise RuntimeError(f"pair list overflow: {f[abi.RB_FLAG_OVERFLOW]} pairs > capacity {self.max_pairs}")
+        if f[abi.RB_FLAG_NONFINITE]:
+            raise RuntimeError("non-finite pair force or energy")
+        return f
+
+    def state_host(self) -> dict:
+        return dict(x=self.x.cpu().numpy().T.copy(), q=self.q.cpu().numpy().T.copy(),
+                    P=self.P.cpu().numpy().T.copy(), L=self.L.cpu().numpy().T.copy())
+
+    def energy(self) -> float:
+        return float(self.ev[0].item())
+
+    def kinetic_host(self) -> np.ndarray:
+        return self.kinetic.cpu().numpy()
+
+    def pairs_host(self) -> np.ndarray:
+        npairs = int(self.flags[abi.RB_FLAG_NPAIRS].item())
+        return np.stack([self.pair_i[:npairs].cpu().numpy(), self.pair_j[:npairs].cpu().numpy()], axis=1)

@@ -1,0 +1,98 @@
+"""Drivers of the network kernels: autograd wrapper, labelling with the bead
+sum, normalisation constants and the training loop.
+
+All arithmetic runs in the HIP kernels behind `abi`; this module only
+allocates device buffers, slices batches and loops.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import abi
+
+
+def make_norm(d_scale: float, e_shift: float = 0.0, e_scale: float = 1.0) -> np.ndarray:
+    """16 normalisation numbers: in_shift[7], in_scale[7], out_shift, out_scale.
+
+    The network sees (d / d_scale, q) and predicts (E - e_shift) / e_scale.
+    """
+    return np.concatenate([np.zeros(7), [1.0 / d_scale] * 3 + [1.0] * 4, [e_shift, e_scale]]).astype(np.float32)
+
+
+class NNPairEnergy(torch.autograd.Function):
+    """E = g_NN(desc) with a hand-written input gradient.
+
+    desc: (7, P) float32 CUDA tensor (structure of arrays).  Forward calls
+    rb_nn_pair_eval; backward calls rb_nn_pair_grad with the incoming
+    gradient as the reverse-pass seed.  The parameters are constants here
+    (training uses rb_nn_train_step).
+    """
+
+    @staticmethod
+    def forward(ctx, desc, params, norm, precision):
+        desc = desc.contiguous()
+        E = torch.empty(desc.shape[1], dtype=torch.float32, device=desc.device)
+        abi.rb_nn_pair_eval(params, norm, precision, desc, E)
+        ctx.save_for_backward(desc, params)
+        ctx.norm = norm
+        ctx.precision = precision
+        return E
+
+    @staticmethod
+    def backward(ctx, gE):
+        desc, params = ctx.saved_tensors
+        g = torch.empty_like(desc)
+        abi.rb_nn_pair_grad(params, ctx.norm, ctx.precision, desc, gE.contiguous().float(), None, g, None)
+        return g, None, None, None
+
+
+def nn_pair_energy(desc, params, norm, precision=abi.RB_PREC_BF16):
+    return NNPairEnergy.apply(desc, params, norm, precision)
+
+
+def label_pairs(ctx: abi.Ctx, desc: np.ndarray, type_i: int = 0, type_j: int = 0, chunk: int = 1 << 20,
+                device="cuda") -> np.ndarray:
+    """Bead-sum labels (P, 11) = E, F_j, tau_i, tau_j, r_min for desc (P, 7)."""
+    P = len(desc)
+    out = np.empty((P, 11), dtype=np.float32)
+    for s in range(0, P, chunk):
+        d = torch.tensor(np.ascontiguousarray(desc[s:s + chunk].T, dtype=np.float32), device=device)
+        o = torch.empty((11, d.shape[1]), dtype=torch.float32, device=device)
+        abi.rb_bead_pair_eval(ctx, d, type_i, type_j, o)
+        out[s:s + chunk] = o.cpu().numpy().T
+    return out
+
+
+class Trainer:
+    """Adam on the FP32 master parameters with the energy loss, on the GPU."""
+
+    def __init__(self, params: np.ndarray, norm: np.ndarray, precision=abi.RB_PREC_BF16, batch=8192, lr=1e-3,
+                 beta1=0.9, beta2=0.999, eps=1e-8, device="cuda"):
+        self.dev = torch.device(device)
+        self.params = torch.tensor(np.asarray(params, np.float32), device=self.dev)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.norm = np.asarray(norm, np.float32)
+        self.precision = precision
+        self.batch = batch
+        self.lr, self.beta1, self.beta2, self.eps = lr, beta1, beta2, eps
+        self.t = 0
+        self.ws = torch.zeros(abi.rb_nn_train_workspace_bytes(batch), dtype=torch.uint8, device=self.dev)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=self.dev)
+
+    def step(self, desc, labels, idx, grad_out=None):
+        self.t += 1
+        abi.rb_nn_train_step(self.params, self.m, self.v, self.t, self.norm, self.precision, idx.numel(), desc,
+                             labels, idx, self.lr, self.beta1, self.beta2, self.eps, self.loss, grad_out, self.ws)
+
+    def epoch(self, desc, labels, g: np.random.Generator):
+        """One pass over the data in a random order; returns the mean loss."""
+        n = labels.numel()
+        perm = torch.tensor(g.permutation(n).astype(np.int32), device=self.dev)
+        nb = n // self.batch
+        total = torch.zeros(1, dtype=torch.float64, device=self.dev)
+        for b in range(nb):
+            self.step(desc, labels, perm[b * self.batch:(b + 1) * self.batch])
+            total += self.loss
+        return float(total.item()) / max(nb, 1)

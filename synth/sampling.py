@@ -44,57 +44,65 @@ def place_bodies(g: np.random.Generator, n: int, body: BodyType, box: float,
 
     Each trial body gets a uniform position and a uniform orientation; it is
     rejected if any of its beads is closer than `min_bead_gap` to a bead of an
-    already placed body (minimum image).  Returns x (n,3) in [0, box) and
+    already placed body (minimum image).  Trials are drawn in chunks from g,
+    so the result depends only on the seed.  Returns x (n,3) in [0, box) and
     q (n,4).
     """
     reach = 2.0 * body.r_max + min_bead_gap
     nc = max(1, int(box // reach))
     cell_w = box / nc
-    cells: dict[tuple[int, int, int], list[int]] = {}
+    cells: dict[int, list[int]] = {}
+    offs = [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)]
     x = np.zeros((n, 3))
     q = np.zeros((n, 4))
     beads = np.zeros((n, body.n, 3))
     gap2 = min_bead_gap * min_bead_gap
     placed = 0
     tries = 0
+    chunk = 1024
     while placed < n:
-        tries += 1
-        if tries > max_tries * n:
-            raise RuntimeError(f"placement stalled at {placed}/{n} bodies")
-        xt = g.random(3) * box
-        qt = uniform_quaternions(g, 1)
-        bt = _rotate(qt, body.beads)[0]
-        c = tuple(int(v // cell_w) % nc for v in xt)
-        ok = True
-        seen = set()
-        for dx in (-1, 0, 1):
-            for dy in (-1, 0, 1):
-                for dz in (-1, 0, 1):
-                    cc = ((c[0] + dx) % nc, (c[1] + dy) % nc, (c[2] + dz) % nc)
-                    if cc in seen:
-                        continue
-                    seen.add(cc)
-                    for j in cells.get(cc, ()):
-                        d = x[j] - xt
-                        d -= box * np.round(d / box)
-                        if d @ d >= reach * reach:
-                            continue
-                        other = beads[j] + d
-                        diff = bt[:, None, :] - other[None, :, :]
-                        if np.min(np.einsum("abk,abk->ab", diff, diff)) < gap2:
+        xs = g.random((chunk, 3)) * box
+        qs = uniform_quaternions(g, chunk)
+        bs = _rotate(qs, body.beads)
+        for t in range(chunk):
+            if placed == n:
+                break
+            tries += 1
+            if tries > max_tries * n:
+                raise RuntimeError(f"placement stalled at {placed}/{n} bodies")
+            xt = xs[t]
+            c = (xt // cell_w).astype(int) % nc
+            cand = []
+            for o in offs:
+                key = (((c[0] + o[0]) % nc) * nc + (c[1] + o[1]) % nc) * nc + (c[2] + o[2]) % nc
+                lst = cells.get(key)
+                if lst:
+                    cand.extend(lst)
+            ok = True
+            if cand:
+                cand = np.unique(np.asarray(cand))
+                d = x[cand] - xt
+                d -= box * np.round(d / box)
+                near = np.einsum("ka,ka->k", d, d) < reach * reach
+                # only beads within r_max + gap of the other body's centre
+                # can be closer than gap to one of its beads
+                shell2 = (body.r_max + min_bead_gap) ** 2
+                bt = bs[t]
+                for j, dj in zip(cand[near], d[near]):
+                    other = beads[j] + dj
+                    o = other[np.einsum("ma,ma->m", other, other) < shell2]
+                    tt = bt[np.einsum("ma,ma->m", bt - dj, bt - dj) < shell2]
+                    if len(o) and len(tt):
+                        diff = tt[:, None, :] - o[None, :, :]
+                        if np.min(np.einsum("abc,abc->ab", diff, diff)) < gap2:
                             ok = False
                             break
-                    if not ok:
-                        break
-                if not ok:
-                    break
             if not ok:
-                break
-        if not ok:
-            continue
-        x[placed], q[placed], beads[placed] = xt, qt[0], bt
-        cells.setdefault(c, []).append(placed)
-        placed += 1
+                continue
+            x[placed], q[placed], beads[placed] = xt, qs[t], bs[t]
+            key = (c[0] * nc + c[1]) * nc + c[2]
+            cells.setdefault(key, []).append(placed)
+            placed += 1
     return x, q
 
 

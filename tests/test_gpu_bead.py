@@ -1,0 +1,216 @@
+"""GPU parity of the bead path (pair list, bead double sum, accumulation,
+integrator) against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from oracle import beads as obeads
+from synth import configs, sampling, state
+from tests.tolerances import assert_close
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def abi():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2402_12199_amd import abi as _abi
+    return _abi
+
+
+def _ctx(abi, bodies):
+    return abi.Ctx([b.beads for b in bodies], [b.mass for b in bodies], [b.inertia for b in bodies])
+
+
+def _t32(body):
+    """The template as the library holds it (FP32), for the oracle."""
+    return body.beads.astype(np.float32).astype(np.float64)
+
+
+def _pair_desc(body, n, seed, lo_factor=0.9):
+    d_min = 2 * body.r_in + 1.0
+    d_cut = 2 * body.r_max + 2.5
+    return sampling.pair_batch(sampling.rng(seed), n, lo_factor * d_min, d_cut)
+
+
+@pytest.mark.parametrize("shape,n", [("cube5", 300), ("cube6", 257), ("cyl134", 1001)])
+def test_bead_pair_eval_matches_oracle(abi, shape, n):
+    body = getattr(configs, shape)()
+    desc = _pair_desc(body, n, 17).astype(np.float32)
+    ctx = _ctx(abi, [body])
+    d_dev = torch.tensor(np.ascontiguousarray(desc.T), device="cuda")
+    out = torch.full((11, n), float("nan"), dtype=torch.float32, device="cuda")
+    abi.rb_bead_pair_eval(ctx, d_dev, 0, 0, out)
+    got = out.cpu().numpy().T.astype(np.float64)
+    ref = obeads.bead_pair_desc(_t32(body), _t32(body), desc.astype(np.float64))
+    np.testing.assert_allclose(got[:, 10], ref[:, 10], rtol=1e-5)
+    # Parity domain: no bead pair closer than 0.8 sigma (the labelling
+    # rejection).  Deeper overlaps put single LJ terms at 1e9..1e15, where
+    # FP32 bead coordinates (|r| up to ~12 sigma, ulp ~1e-6) limit the
+    # relative accuracy to about 12 * 1e-6 / r_min.
+    ok = ref[:, 10] >= 0.8
+    assert ok.sum() > 0.5 * n
+    assert_close(got[ok, 0], ref[ok, 0], 1e-5, "E")
+    for s, name in ((1, "F_j"), (4, "tau_i"), (7, "tau_j")):
+        assert_close(got[ok, s:s + 3], ref[ok, s:s + 3], 1e-4, name)
+    deep = ~ok
+    if deep.any():
+        rel = np.abs(got[deep, 0] - ref[deep, 0]) / np.abs(ref[deep, 0])
+        assert np.all(rel < 2e-5 / ref[deep, 10] ** 2)
+
+
+def test_bead_pair_eval_mixed_types_and_empty(abi):
+    c5, cy = configs.cube5(), configs.cyl134()
+    ctx = _ctx(abi, [c5, cy])
+    desc = sampling.pair_batch(sampling.rng(3), 130, 4.5, c5.r_max + cy.r_max + 2.5).astype(np.float32)
+    d_dev = torch.tensor(np.ascontiguousarray(desc.T), device="cuda")
+    out = torch.zeros((11, 130), dtype=torch.float32, device="cuda")
+    abi.rb_bead_pair_eval(ctx, d_dev, 0, 1, out)
+    ref = obeads.bead_pair_desc(_t32(c5), _t32(cy), desc.astype(np.float64))
+    got = out.cpu().numpy().T
+    ok = ref[:, 10] >= 0.8
+    assert_close(got[ok, 0], ref[ok, 0], 1e-5, "E")
+    assert_close(got[ok, 1:4], ref[ok, 1:4], 1e-4, "F_j")
+    assert_close(got[ok, 7:10], ref[ok, 7:10], 1e-4, "tau_j")
+    empty = torch.zeros((7, 0), dtype=torch.float32, device="cuda")
+    abi.rb_bead_pair_eval(ctx, empty, 0, 1, torch.zeros((11, 0), dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+
+
+def _system(abi, cfg, st=None):
+    from paper_2402_12199_amd.md import RigidSystem
+    st = st or state.initial_state(cfg)
+    b = cfg.body
+    return RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"],
+                       cfg.box, cfg.r_list, cfg.skin), st
+
+
+@pytest.mark.parametrize("cfgname", ["config1", "config2"])
+def test_pairlist_matches_bruteforce(abi, cfgname):
+    cfg = getattr(configs, cfgname)()
+    st = state.initial_state(cfg)
+    # positions in arbitrary periodic images
+    shift = sampling.rng(5).integers(-3, 4, size=st["x"].shape) * cfg.box
+    st = dict(st, x=st["x"] + shift)
+    sysm, _ = _system(abi, cfg, st)
+    sysm.build_pairs(always=True)
+    f = sysm.check_capacity()
+    got = sysm.pairs_host()
+    ref = obeads.pairs_within(st["x"], cfg.box, cfg.r_list)
+    assert f[abi.RB_FLAG_NPAIRS] == len(ref)
+    assert {tuple(p) for p in got} == {tuple(p) for p in ref}
+    assert np.all(got[:, 0] < got[:, 1])
+    assert np.all(np.diff(got[:, 0]) >= 0)          # sorted by i
+    assert f[abi.RB_FLAG_REBUILD] == 0 and f[abi.RB_FLAG_NREBUILDS] == 1
+
+
+def test_pairlist_overflow_reports_required_count(abi):
+    cfg = configs.config1()
+    st = state.initial_state(cfg)
+    from paper_2402_12199_amd.md import RigidSystem
+    b = cfg.body
+    ref = obeads.pairs_within(st["x"], cfg.box, cfg.r_list)
+    cap = max(1, len(ref) // 2)
+    sysm = RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"],
+                       cfg.box, cfg.r_list, cfg.skin, max_pairs=cap)
+    sysm.build_pairs(always=True)
+    f = sysm.flags_host()
+    assert f[abi.RB_FLAG_OVERFLOW] == len(ref)
+    assert f[abi.RB_FLAG_NPAIRS] == cap
+    with pytest.raises(RuntimeError):
+        sysm.check_capacity()
+
+
+@pytest.mark.parametrize("cfgname", ["config1", "config2"])
+def test_bead_forces_match_oracle(abi, cfgname):
+    cfg = getattr(configs, cfgname)()
+    sysm, st = _system(abi, cfg)
+    sysm.init_forces("bead")
+    sysm.check_capacity()
+    ref = obeads.bead_system(st["x"], st["q"], st["types"], [cfg.body.beads], cfg.box)
+    E = sysm.energy()
+    assert abs(E - ref["E"]) <= 1e-5 * abs(ref["E"])
+    assert_close(sysm.force.cpu().numpy().T, ref["F"], 1e-4, "force")
+    assert_close(sysm.torque.cpu().numpy().T, ref["tau"], 1e-4, "torque")
+    W = sysm.ev[1:].cpu().numpy().reshape(3, 3)
+    np.testing.assert_allclose(W, ref["virial"], rtol=1e-4, atol=1e-4 * np.abs(ref["virial"]).max())
+
+
+def test_bead_forces_bitwise_deterministic(abi):
+    cfg = configs.config1()
+    sysm, _ = _system(abi, cfg)
+    sysm.init_forces("bead")
+    a = sysm.acc.clone()
+    sysm.compute_forces("bead")
+    assert torch.equal(a, sysm.acc)
+
+
+def test_rigid_step_matches_oracle(abi):
+    cfg = configs.config1()
+    sysm, st = _system(abi, cfg)
+    g = sampling.rng(77)
+    n = cfg.n_bodies
+    F = (g.normal(size=(n, 3)) * 20).astype(np.float32)
+    T = (g.normal(size=(n, 3)) * 50).astype(np.float32)
+    sysm.force.copy_(torch.tensor(np.ascontiguousarray(F.T), device="cuda"))
+    sysm.torque.copy_(torch.tensor(np.ascontiguousarray(T.T), device="cuda"))
+    dt = 0.005
+    x, P, q, L = (np.ascontiguousarray(st[k].copy()) for k in ("x", "P", "q", "L"))
+    m, I = cfg.body.mass, cfg.body.inertia
+    for _ in range(3):
+        abi.rb_rigid_step(sysm.ctx, 1, dt, sysm.x, sysm.P, sysm.q, sysm.L, sysm.types, sysm.force, sysm.torque)
+        abi.rb_rigid_step(sysm.ctx, 2, dt, None, sysm.P, sysm.q, sysm.L, sysm.types, sysm.force, sysm.torque,
+                          None, 0.0, sysm.kinetic, None, sysm.ws_rig)
+        obeads.rigid_phase1(dt, x, P, q, L, m, I, F.astype(np.float64), T.astype(np.float64))
+        ke = obeads.rigid_phase2(dt, P, q, L, m, I, F.astype(np.float64), T.astype(np.float64))
+    got = sysm.state_host()
+    np.testing.assert_allclose(got["x"], x, rtol=1e-13, atol=1e-12)
+    np.testing.assert_allclose(got["P"], P, rtol=1e-12, atol=1e-11)
+    np.testing.assert_allclose(got["q"], q, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(got["L"], L, rtol=1e-12, atol=1e-10)
+    assert sysm.kinetic_host().sum() == pytest.approx(ke, rel=1e-12)
+
+
+def test_skin_test_flags_rebuild(abi):
+    cfg = configs.config1()
+    sysm, st = _system(abi, cfg)
+    sysm.build_pairs(always=True)
+    assert sysm.flags_host()[abi.RB_FLAG_REBUILD] == 0
+    zero = torch.zeros((3, cfg.n_bodies), dtype=torch.float32, device="cuda")
+    sysm.P.zero_()
+    sysm.P[0, 5] = cfg.body.mass * 0.6 / 0.005 * 1.0      # body 5 moves 0.6 > skin/2 in one step
+    abi.rb_rigid_step(sysm.ctx, 1, 0.005, sysm.x, sysm.P, sysm.q, sysm.L, sysm.types, zero, zero, sysm.x_ref,
+                      sysm.half_skin, None, sysm.flags, None)
+    assert sysm.flags_host()[abi.RB_FLAG_REBUILD] == 1
+    sysm.build_pairs(always=False)
+    f = sysm.flags_host()
+    assert f[abi.RB_FLAG_REBUILD] == 0 and f[abi.RB_FLAG_NREBUILDS] == 2
+
+
+def test_md_matches_oracle_first_steps_and_conserves_energy(abi):
+    cfg = configs.config1()
+    sysm, st = _system(abi, cfg)
+    sysm.init_forces("bead")
+    o = {k: np.ascontiguousarray(st[k].copy()) for k in ("x", "P", "q", "L")}
+    nst = 10
+    r = obeads.nve(o["x"], o["P"], o["q"], o["L"], st["types"], [cfg.body.beads], [cfg.body.mass],
+                   [cfg.body.inertia], cfg.box, nst, cfg.dt)
+    for _ in range(nst):
+        sysm.step(cfg.dt, "bead")
+    sysm.check_capacity()
+    got = sysm.state_host()
+    # FP32 forces against FP64 ones: the difference stays at the FP32 force
+    # error times dt^2-scale factors over ten steps
+    np.testing.assert_allclose(got["x"], o["x"], rtol=0, atol=1e-7 * cfg.box)
+    np.testing.assert_allclose(got["q"], o["q"], rtol=0, atol=1e-6)
+    e_gpu = sysm.energy() + sysm.kinetic_host().sum()
+    e_ref = r["pe"][-1] + r["ke"][-1]
+    assert e_gpu == pytest.approx(e_ref, rel=1e-5)
+    # longer run: energy drift
+    e0 = e_gpu
+    for _ in range(190):
+        sysm.step(cfg.dt, "bead")
+    sysm.check_capacity()
+    e1 = sysm.energy() + sysm.kinetic_host().sum()
+    assert abs(e1 - e0) < 1e-3 * sysm.kinetic_host().sum()

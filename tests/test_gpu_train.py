@@ -1,0 +1,100 @@
+"""GPU parity of the training step (hand-written reverse pass, weight
+gradients, Adam) against the FP64 oracle, and a short training run on
+bead-sum labels that must beat the untrained network."""
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+from synth import configs, sampling
+from tests.tolerances import assert_close
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+LAYER_SLICES = [(0, 896, "W1"), (896, 1024, "b1"), (1024, 17408, "W2"), (17408, 17536, "b2"),
+                (17536, 33920, "W3"), (33920, 34048, "b3"), (34048, 50432, "W4"), (50432, 50560, "b4"),
+                (50560, 50688, "W5"), (50688, 50689, "b5")]
+
+
+@pytest.fixture(scope="module")
+def abi():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2402_12199_amd import abi as _abi
+    return _abi
+
+
+def _net(params, prec):
+    return omlp.bf16_network(params) if prec == 0 else params.astype(np.float64)
+
+
+def _problem(n_data=700, seed=5):
+    g = sampling.rng(seed)
+    params = sampling.xavier_params(seed)
+    layers = omlp.unpack(params)
+    params = omlp.pack([(W, g.normal(size=b.shape) * 0.05) for W, b in layers]).astype(np.float32)
+    desc = sampling.pair_batch(g, n_data, 4.0, 11.138).astype(np.float32)
+    labels = (g.normal(size=n_data) * 3.0 + 1.0).astype(np.float32)
+    norm = omlp.Norm(in_scale=np.array([1 / 11.138] * 3 + [1.0] * 4), out_shift=0.5, out_scale=2.5)
+    return params, desc, labels, norm
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("batch", [64, 544])
+def test_gradient_and_adam_match_oracle(abi, prec, batch):
+    params, desc, labels, norm = _problem()
+    idx = sampling.rng(11).choice(len(labels), batch, replace=False).astype(np.int32)
+    dev = "cuda"
+    p = torch.tensor(params, device=dev)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    loss = torch.zeros(1, device=dev)
+    grad = torch.zeros_like(p)
+    ws = torch.zeros(abi.rb_nn_train_workspace_bytes(batch), dtype=torch.uint8, device=dev)
+    abi.rb_nn_train_step(p, m, v, 1, norm.as_array(), prec, batch, torch.tensor(np.ascontiguousarray(desc.T),
+                         device=dev), torch.tensor(labels, device=dev), torch.tensor(idx, device=dev),
+                         1e-3, 0.9, 0.999, 1e-8, loss, grad, ws)
+    lref, gref = omlp.loss_and_grad(_net(params, prec), desc[idx].astype(np.float64),
+                                    labels[idx].astype(np.float64), norm)
+    tol = 2e-2 if prec == 0 else 1e-4
+    assert loss.item() == pytest.approx(lref, rel=tol)
+    gg = grad.cpu().numpy()
+    for a, b, name in LAYER_SLICES:
+        assert_close(gg[a:b], gref[a:b], tol, f"grad {name}")
+    # Adam from the kernel's own gradient: FP32 arithmetic against FP64
+    pref, mref, vref = omlp.adam_step(params.astype(np.float64), 0.0, 0.0, 1, gg.astype(np.float64))
+    np.testing.assert_allclose(p.cpu().numpy(), pref, rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose(m.cpu().numpy(), mref, rtol=1e-6, atol=1e-12)
+
+
+def test_training_on_bead_labels_beats_untrained(abi):
+    # the learned part: fit bead-sum energies of cube-5 pairs, then compare
+    # the held-out error of the trained and the untrained network
+    from paper_2402_12199_amd import nn
+    body = configs.cube5()
+    ctx = abi.Ctx([body.beads], [body.mass], [body.inertia])
+    d_min, d_cut = 2 * body.r_in + 1.0, 2 * body.r_max + 2.5
+    g = sampling.rng(4)
+    raw = sampling.pair_batch(g, 1 << 15, d_min, d_cut)
+    lab = nn.label_pairs(ctx, raw)
+    keep = lab[:, 10] >= 0.8
+    raw, lab = raw[keep], lab[keep]
+    ntr = (len(raw) * 7 // 8) // 1024 * 1024
+    e = lab[:, 0].astype(np.float64)
+    norm = nn.make_norm(d_cut, float(e[:ntr].mean()), float(e[:ntr].std()))
+    tr = nn.Trainer(sampling.xavier_params(3), norm, precision=abi.RB_PREC_BF16, batch=1024, lr=1e-3)
+    desc_tr = torch.tensor(np.ascontiguousarray(raw[:ntr].T, dtype=np.float32), device="cuda")
+    y_tr = torch.tensor(lab[:ntr, 0], device="cuda")
+    test = torch.tensor(np.ascontiguousarray(raw[ntr:].T, dtype=np.float32), device="cuda")
+    E0 = torch.zeros(test.shape[1], device="cuda")
+    abi.rb_nn_pair_eval(tr.params, norm, abi.RB_PREC_BF16, test, E0)
+    first = tr.epoch(desc_tr, y_tr, g)
+    for _ in range(14):
+        last = tr.epoch(desc_tr, y_tr, g)
+    E1 = torch.zeros(test.shape[1], device="cuda")
+    abi.rb_nn_pair_eval(tr.params, norm, abi.RB_PREC_BF16, test, E1)
+    ref = lab[ntr:, 0]
+    rmse0 = float(np.sqrt(np.mean((E0.cpu().numpy() - ref) ** 2)))
+    rmse1 = float(np.sqrt(np.mean((E1.cpu().numpy() - ref) ** 2)))
+    assert last < 0.5 * first
+    assert rmse1 < 0.5 * rmse0, (rmse0, rmse1)

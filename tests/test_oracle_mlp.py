@@ -107,3 +107,15 @@ def test_overfits_small_set():
         loss, g = mlp.loss_and_grad(p, u, y, nrm)
         p, m, v = mlp.adam_step(p, m, v, t, g, lr=1e-3)
     assert loss < 1e-3 * loss0
+
+
+def test_bf16_rounding_known_values():
+    # 1 + 2^-8 is a tie between 1 and 1 + 2^-7: ties go to the even mantissa (1);
+    # 1 + 3 * 2^-8 is a tie between 1 + 2^-7 and 1 + 2^-6: rounds to 1 + 2^-6
+    x = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -8 + 2 ** -20, -3.0e-5, 65504.0], np.float32)
+    want = [1.0, 1.0, 1 + 2 ** -6, 1 + 2 ** -7, None, 65536.0]
+    got = mlp.round_bf16(x)
+    for g, w in zip(got, want):
+        if w is not None:
+            assert g == w
+    assert abs(got[4] / -3.0e-5 - 1) < 2 ** -8

@@ -1,0 +1,272 @@
+"""Benchmark of the rigid-body pair path on one MI355X.
+
+Workload of the headline number: 4096 cube shells of 152 beads (6x6x6
+surface lattice) at volume fraction 0.20, kT = 1, NVE velocity Verlet at
+dt = 0.005, cell-list pair list with skin 1.0.  A step is one MD step of the
+plain bead path: half kick + drift + free rotation, conditional list
+rebuild, the FP32 bead double sum over every listed pair with per-body
+accumulation, the second half kick.  value = rigid-pair F+tau evaluations
+per second over the timed steps.
+
+Also reported (same run): the network path on the same system (BF16 MLP
+with bead fallback below d_min), the network kernels on 2^20 random
+cylinder pairs (forward, forward + input gradient; BF16 and FP32), the
+per-kernel roofline of the bead kernel, and the FP64 oracle on the host as
+a CPU baseline.  Inputs are synthetic and seeded.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP32_VECTOR_PEAK = 78.6e12     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, packed FP32 math not used
+BF16_MFMA_PEAK = 2.5e15        # dense
+FP32_MFMA_PEAK = 157.3e12
+FLOP_PER_TEST = 8              # 3 sub + 1 mul + 2 fma
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_system(cfg, st, torch):
+    from paper_2402_12199_amd.md import RigidSystem
+    b = cfg.body
+    return RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"], cfg.box,
+                       cfg.r_list, cfg.skin)
+
+
+def run_md(sysm, steps, warmup, dt, path, torch, abi, time_kernel=True):
+    """Warm up, then time `steps` MD steps.  Returns timing and counters."""
+    for _ in range(warmup):
+        sysm.step(dt, path)
+    torch.cuda.synchronize()
+    sysm.check_capacity()
+    f0 = sysm.flags_host()
+    st = torch.cuda.current_stream()
+    ev = []
+    # kernel timing: events around the force call of every step, on the
+    # stream the kernels are launched on
+    orig = sysm.compute_forces
+
+    def timed_forces(p):
+        if time_kernel:
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(st)
+            orig(p)
+            b.record(st)
+            ev.append((a, b))
+        else:
+            orig(p)
+
+    sysm.compute_forces = timed_forces
+    e_start = torch.cuda.Event(enable_timing=True)
+    e_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e_start.record(st)
+    for _ in range(steps):
+        sysm.step(dt, path)
+    e_end.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sysm.compute_forces = orig
+    f1 = sysm.check_capacity()
+    gpu_ms = e_start.elapsed_time(e_end)
+    force_ms = [a.elapsed_time(b) for a, b in ev]
+    neval = (int(f1[abi.RB_FLAG_NEVAL]) - int(f0[abi.RB_FLAG_NEVAL])) % (1 << 32)
+    return dict(wall_s=wall, gpu_ms=gpu_ms, force_ms=force_ms, pairs_evaluated=neval,
+                rebuilds=int(f1[abi.RB_FLAG_NREBUILDS] - f0[abi.RB_FLAG_NREBUILDS]),
+                n_pairs=int(f1[abi.RB_FLAG_NPAIRS]), n_nn=int(f1[abi.RB_FLAG_NNN]),
+                n_bead=int(f1[abi.RB_FLAG_NBEAD]))
+
+
+def bead_kernel_time(sysm, reps, torch, abi):
+    """Average duration of the bead-sum kernel alone on the current list."""
+    st = torch.cuda.current_stream()
+    abi.rb_accum_zero(sysm.n, sysm.acc)
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        abi.rb_bead_pair_forces(sysm.ctx, sysm.x, sysm.q, sysm.types, sysm.box, sysm.pair_i, sysm.pair_j, None,
+                                sysm.flags[abi.RB_FLAG_NPAIRS:], sysm.max_pairs, sysm.acc, sysm.flags)
+        b.record(st)
+        times.append((a, b))
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in times]))
+
+
+def nn_kernels(torch, abi):
+    """Network kernels on 2^20 random cylinder pair configurations."""
+    from synth import configs, sampling
+    from paper_2402_12199_amd.nn import make_norm
+    cfg = configs.config3()
+    desc = sampling.pair_batch(sampling.rng(cfg.seed), cfg.n_pairs, cfg.d_lo, cfg.d_cut).astype(np.float32)
+    d = torch.tensor(np.ascontiguousarray(desc.T), device="cuda")
+    params = torch.tensor(sampling.xavier_params(cfg.seed).astype(np.float32), device="cuda")
+    norm = make_norm(cfg.d_cut)
+    P = cfg.n_pairs
+    E = torch.empty(P, dtype=torch.float32, device="cuda")
+    ft = torch.empty((9, P), dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+    out = {}
+    for prec, name in ((abi.RB_PREC_BF16, "bf16"), (abi.RB_PREC_FP32, "fp32")):
+        for kind in ("fwd", "fwd_grad"):
+            def call():
+                if kind == "fwd":
+                    abi.rb_nn_pair_eval(params, norm, prec, d, E)
+                else:
+                    abi.rb_nn_pair_grad(params, norm, prec, d, None, E, None, ft)
+            for _ in range(3):
+                call()
+            reps = 10
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(st)
+            for _ in range(reps):
+                call()
+            b.record(st)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            flop = (100352 if kind == "fwd" else 2 * 100352) * P
+            peak = BF16_MFMA_PEAK if prec == abi.RB_PREC_BF16 else FP32_MFMA_PEAK
+            out[f"{name}_{kind}"] = dict(ms=ms, pairs_per_s=P / (ms * 1e-3), tflops=flop / (ms * 1e-3) / 1e12,
+                                         mfma_frac=flop / (ms * 1e-3) / peak)
+    return out
+
+
+def cpu_baseline(cfg, st, target_s=12.0):
+    """The FP64 oracle (plain C, OpenMP over pairs) doing the same MD steps on
+    the host: full force evaluation + integration per step."""
+    from oracle import beads as ob
+    n = cfg.n_bodies
+    x = np.ascontiguousarray(st["x"].copy())
+    P = np.ascontiguousarray(st["P"].copy())
+    q = np.ascontiguousarray(st["q"].copy())
+    L = np.ascontiguousarray(st["L"].copy())
+    b = cfg.body
+    t0 = time.perf_counter()
+    r = ob.bead_system(x, q, st["types"], [b.beads], cfg.box)
+    t1 = time.perf_counter()
+    per_eval = t1 - t0
+    steps = max(1, int(target_s / max(per_eval, 1e-3)))
+    t0 = time.perf_counter()
+    ob.nve(x, P, q, L, st["types"], [b.beads], [b.mass], [b.inertia], cfg.box, steps, cfg.dt)
+    wall = time.perf_counter() - t0
+    pairs = r["n_pairs"] * (steps + 1)
+    return dict(value=pairs / wall, unit="rigid-pair F+tau evals/s", cores=ob.num_threads(), kind="oracle",
+                sample=f"{steps} NVE steps (+1 initial force evaluation) of the same 4096-cube system, "
+                       f"{r['n_pairs']} pairs per evaluation, FP64 C oracle, wall {wall:.1f} s",
+                md_steps_per_s=(steps + 1) / wall)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-nn", action="store_true", help="skip the network measurements")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the path is single-GPU; --gpus {args.gpus} is not supported)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2402_12199_amd import abi
+    from paper_2402_12199_amd.md import NNModel
+    from synth import configs, sampling, state
+
+    cfg = configs.config2()
+    log(f"[bench] generating {cfg.name}")
+    st = state.initial_state(cfg)
+    sysm = make_system(cfg, st, torch)
+    sysm.init_forces("bead")
+    torch.cuda.synchronize()
+    log(f"[bench] bead path: {args.warmup} warmup + {args.steps} timed steps")
+    bead = run_md(sysm, args.steps, args.warmup, cfg.dt, "bead", torch, abi)
+    kin = sysm.kinetic_host()
+    e_tot = sysm.energy() + float(kin.sum())
+    kern_ms = bead_kernel_time(sysm, 20, torch, abi)
+    npairs_now = int(sysm.flags_host()[abi.RB_FLAG_NPAIRS])
+    tests = npairs_now * cfg.body.n * cfg.body.n
+    achieved = tests * FLOP_PER_TEST / (kern_ms * 1e-3)
+    steps_per_s = args.steps / bead["wall_s"]
+    value = bead["pairs_evaluated"] / bead["wall_s"]
+
+    result = {
+        "metric": "rigid-pair F+tau evals/sec (bead sum FP32, MD step on 4096 cubes); MD steps/sec; "
+                  "NN(BF16) vs bead-sum(FP32), 1 GPU",
+        "value": value,
+        "unit": "rigid-pair F+tau evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * bead["wall_s"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded random placement, orientations, Maxwell-Boltzmann momenta)",
+        "config": {"workload": "cubes4096_phi0.20: 4096 cube shells (152 beads), LJ rc=2.5, NVE dt=0.005, "
+                               "kT=1, bead path",
+                   "n_bodies": cfg.n_bodies, "beads_per_body": cfg.body.n, "box": cfg.box,
+                   "pairs_per_step": npairs_now},
+        "md_steps_per_s": steps_per_s,
+        "bead_path": {"pairs_evaluated": bead["pairs_evaluated"], "rebuilds": bead["rebuilds"],
+                      "gpu_ms_per_step": bead["gpu_ms"] / args.steps,
+                      "force_call_ms_mean": float(np.mean(bead["force_ms"])),
+                      "total_energy_end": e_tot},
+        "roofline": {"kernel": "k_bead_md (rb_bead_pair_forces)", "bound": "alu", "achieved": achieved / 1e12,
+                     "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK,
+                     "traffic": None, "kernel_ms": kern_ms,
+                     "algorithmic_work": f"{npairs_now} pairs x {cfg.body.n}^2 bead tests x {FLOP_PER_TEST} FLOP"},
+    }
+
+    if not args.no_nn:
+        # network path on the same system: Xavier weights give the kernel
+        # cost (the cost does not depend on the weight values)
+        log("[bench] network path on the same system")
+        st2 = state.initial_state(cfg)
+        sysn = make_system(cfg, st2, torch)
+        from paper_2402_12199_amd.nn import make_norm
+        params = torch.tensor(sampling.xavier_params(1002).astype(np.float32), device="cuda")
+        sysn.set_nn(NNModel(params=params, norm=make_norm(cfg.d_cut), precision=abi.RB_PREC_BF16,
+                            d_min=cfg.d_min, sw_lo=cfg.d_cut - 1.0, sw_hi=cfg.d_cut))
+        sysn.init_forces("nn")
+        nnr = run_md(sysn, args.steps, args.warmup, cfg.dt, "nn", torch, abi)
+        result["nn_path"] = {
+            "pairs_per_s": nnr["pairs_evaluated"] / nnr["wall_s"],
+            "md_steps_per_s": args.steps / nnr["wall_s"],
+            "ms_per_step": 1e3 * nnr["wall_s"] / args.steps,
+            "force_call_ms_mean": float(np.mean(nnr["force_ms"])),
+            "pairs_nn": nnr["n_nn"], "pairs_bead_fallback": nnr["n_bead"],
+            "speedup_steps_vs_bead": (args.steps / nnr["wall_s"]) / steps_per_s,
+            "weights": "Xavier (timing only)",
+        }
+        log("[bench] network kernels on 2^20 pairs")
+        result["nn_kernels_2^20"] = nn_kernels(torch, abi)
+
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline")
+        result["cpu_baseline"] = cpu_baseline(cfg, st)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -55,6 +55,8 @@ extern "C" {
 #define RB_FLAG_NBEAD 4      /* pairs routed to the bead sum (|d| < d_min)      */
 #define RB_FLAG_NNN 5        /* pairs routed to the network                     */
 #define RB_FLAG_NONFINITE 6  /* a non-finite per-pair force or energy was seen   */
+#define RB_FLAG_NEVAL 7      /* running count of pairs evaluated by the per-body
+                                force calls (bead and network); wraps at 2^31  */
 #define RB_NFLAGS 8
 
 #define RB_PREC_BF16 0       /* 128x128 layers on BF16 MFMA, FP32 accumulate     */

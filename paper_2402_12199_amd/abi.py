@@ -16,7 +16,7 @@ import torch
 from ._lib import check, lib
 
 RB_FLAG_REBUILD, RB_FLAG_NPAIRS, RB_FLAG_OVERFLOW, RB_FLAG_NREBUILDS = 0, 1, 2, 3
-RB_FLAG_NBEAD, RB_FLAG_NNN, RB_FLAG_NONFINITE, RB_NFLAGS = 4, 5, 6, 8
+RB_FLAG_NBEAD, RB_FLAG_NNN, RB_FLAG_NONFINITE, RB_FLAG_NEVAL, RB_NFLAGS = 4, 5, 6, 7, 8
 RB_PREC_BF16, RB_PREC_FP32 = 0, 1
 RB_BUILD_ALWAYS, RB_BUILD_IF_FLAGGED = 0, 1
 RB_MLP_NPARAMS = 50689

@@ -174,6 +174,7 @@ __global__ __launch_bounds__(256) void k_bead_md(Templates T, LJ lj, int32_t n,
     float4 *sjlo = ldslo[w];
     int count = *count_dev;
     if (count > max_count) count = max_count;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(flags + RB_FLAG_NEVAL, count);
     long long eacc[10];
 #pragma unroll
     for (int a = 0; a < 10; ++a) eacc[a] = 0;

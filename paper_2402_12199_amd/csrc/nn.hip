@@ -65,6 +65,7 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
     if (MODE == kForces) {
         const int64_t c = *a.count_dev;
         count = c < a.P ? c : a.P;
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.flags + RB_FLAG_NEVAL, (int)count);
     }
     long long eacc[10];
 #pragma unroll

@@ -22,6 +22,7 @@
 namespace rb {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kH = 128;
@@ -118,6 +119,29 @@ __device__ inline bf16x8 pack8(const float a[4], const float b[4]) {
     v[0] = (__bf16)a[0]; v[1] = (__bf16)a[1]; v[2] = (__bf16)a[2]; v[3] = (__bf16)a[3];
     v[4] = (__bf16)b[0]; v[5] = (__bf16)b[1]; v[6] = (__bf16)b[2]; v[7] = (__bf16)b[3];
     return v;
+}
+
+// FP16 packing of the SiLU derivatives kept for the reverse pass (values in
+// [-0.1, 1.1]; FP16 keeps 11 significant bits against BF16's 8).
+__device__ inline f16x8 pack8h(const float a[4], const float b[4]) {
+    f16x8 v;
+    v[0] = (_Float16)a[0]; v[1] = (_Float16)a[1]; v[2] = (_Float16)a[2]; v[3] = (_Float16)a[3];
+    v[4] = (_Float16)b[0]; v[5] = (_Float16)b[1]; v[6] = (_Float16)b[2]; v[7] = (_Float16)b[3];
+    return v;
+}
+
+// Split of FP32 values into a BF16 head and the BF16 rounding of the
+// remainder: x ~ hi + lo to about 16 significant bits, so an MFMA product
+// with a BF16 operand can be carried as two BF16 MFMAs.
+__device__ inline void split8(const float a[4], const float b[4], bf16x8 &hi, bf16x8 &lo) {
+    hi = pack8(a, b);
+    float ra[4], rb[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        ra[r] = a[r] - (float)hi[r];
+        rb[r] = b[r] - (float)hi[4 + r];
+    }
+    lo = pack8(ra, rb);
 }
 
 // Sum over the four lane groups that share a pair.

@@ -41,7 +41,7 @@ __device__ inline float tile_bf16(const LdsBF16 &L, const Norm &nm, const float 
 #pragma unroll
         for (int k = 0; k < kIn; ++k) em.h(k) = un[k];
     bf16x8 act[4];
-    bf16x8 sp[4][4];
+    f16x8 sp[4][4];
     {
         float hv[8][4], dv[8][4];
         layer1(L.w1, L.b[0], un, g, hv, dv);
@@ -53,7 +53,7 @@ __device__ inline float tile_bf16(const LdsBF16 &L, const Norm &nm, const float 
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
             act[kb] = pack8(hv[2 * kb], hv[2 * kb + 1]);
-            if (GRAD) sp[0][kb] = pack8(dv[2 * kb], dv[2 * kb + 1]);
+            if (GRAD) sp[0][kb] = pack8h(dv[2 * kb], dv[2 * kb + 1]);
         }
     }
     float e = 0.f;
@@ -85,7 +85,7 @@ __device__ inline float tile_bf16(const LdsBF16 &L, const Norm &nm, const float 
                 for (int r = 0; r < 4; ++r) { hlo[r] = h[r]; dlo[r] = d[r]; }
             } else {
                 if (l < 2) nact[mt >> 1] = pack8(hlo, h);
-                if (GRAD) sp[l + 1][mt >> 1] = pack8(dlo, d);
+                if (GRAD) sp[l + 1][mt >> 1] = pack8h(dlo, d);
             }
         }
         if (l < 2) {
@@ -103,7 +103,7 @@ __device__ inline float tile_bf16(const LdsBF16 &L, const Norm &nm, const float 
 
     // reverse pass: delta_4 = seed * oscale * w5 (.) h4'
     const float s0 = seed * nm.oscale;
-    bf16x8 dpk[4];
+    bf16x8 dpk[4], dlk[4];   // delta as BF16 head + BF16 remainder
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) {
         float a0[4], a1[4];
@@ -116,7 +116,7 @@ __device__ inline float tile_bf16(const LdsBF16 &L, const Norm &nm, const float 
                 em.d(3 * kH + 32 * kb + 16 + 4 * g + r) = a1[r];
             }
         }
-        dpk[kb] = pack8(a0, a1);
+        split8(a0, a1, dpk[kb], dlk[kb]);
     }
     if (EMIT && em.live && g == 0) em.d(4 * kH) = s0;
     float gk[kIn];
@@ -124,7 +124,7 @@ __device__ inline float tile_bf16(const LdsBF16 &L, const Norm &nm, const float 
     for (int k = 0; k < kIn; ++k) gk[k] = 0.f;
 #pragma unroll
     for (int l = 2; l >= 0; --l) {
-        bf16x8 ndpk[4];
+        bf16x8 ndpk[4], ndlk[4];
         float dlo[4];
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt) {
@@ -138,6 +138,7 @@ __device__ inline float tile_bf16(const LdsBF16 &L, const Norm &nm, const float 
 #pragma unroll
                 for (int i = 0; i < 8; ++i) a[i] = L.w[l][32 * kb + 16 * (i >> 2) + 4 * g + (i & 3)][col];
                 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, dpk[kb], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, dlk[kb], c, 0, 0, 0);
             }
             float d[4];
 #pragma unroll
@@ -150,7 +151,7 @@ __device__ inline float tile_bf16(const LdsBF16 &L, const Norm &nm, const float 
 #pragma unroll
                     for (int r = 0; r < 4; ++r) dlo[r] = d[r];
                 } else {
-                    ndpk[mt >> 1] = pack8(dlo, d);
+                    split8(dlo, d, ndpk[mt >> 1], ndlk[mt >> 1]);
                 }
             } else {
 #pragma unroll
@@ -163,7 +164,10 @@ __device__ inline float tile_bf16(const LdsBF16 &L, const Norm &nm, const float 
         }
         if (l > 0) {
 #pragma unroll
-            for (int kb = 0; kb < 4; ++kb) dpk[kb] = ndpk[kb];
+            for (int kb = 0; kb < 4; ++kb) {
+                dpk[kb] = ndpk[kb];
+                dlk[kb] = ndlk[kb];
+            }
         }
     }
 #pragma unroll

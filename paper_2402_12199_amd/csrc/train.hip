@@ -89,14 +89,20 @@ __global__ __launch_bounds__(512) void k_train_wgrad(TrainArgs a) {
                 const float4 a0 = *reinterpret_cast<const float4 *>(ap);
                 const float4 a1 = *reinterpret_cast<const float4 *>(ap + 4);
                 const float av0[4] = {a0.x, a0.y, a0.z, a0.w}, av1[4] = {a1.x, a1.y, a1.z, a1.w};
-                const bf16x8 A = pack8(av0, av1);
+                bf16x8 Ahi, Alo;
+                split8(av0, av1, Ahi, Alo);
 #pragma unroll
                 for (int nt = 0; nt < 8; ++nt) {
                     const float *bp = Hl + (int64_t)(16 * nt + n) * B + k0 + 8 * g;
                     const float4 b0 = *reinterpret_cast<const float4 *>(bp);
                     const float4 b1 = *reinterpret_cast<const float4 *>(bp + 4);
                     const float bv0[4] = {b0.x, b0.y, b0.z, b0.w}, bv1[4] = {b1.x, b1.y, b1.z, b1.w};
-                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, pack8(bv0, bv1), acc[nt], 0, 0, 0);
+                    bf16x8 Bhi, Blo;
+                    split8(bv0, bv1, Bhi, Blo);
+                    // three BF16 passes: hi*hi + hi*lo + lo*hi (the lo*lo term is below FP32 rounding)
+                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ahi, Bhi, acc[nt], 0, 0, 0);
+                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ahi, Blo, acc[nt], 0, 0, 0);
+                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Alo, Bhi, acc[nt], 0, 0, 0);
                 }
             }
         } else {

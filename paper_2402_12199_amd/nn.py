@@ -12,12 +12,16 @@ import torch
 from . import abi
 
 
-def make_norm(d_scale: float, e_shift: float = 0.0, e_scale: float = 1.0) -> np.ndarray:
+def make_norm(d_cut: float, e_shift: float = 0.0, e_scale: float = 1.0, d_gain: float = 2.3,
+              q_gain: float = 2.0) -> np.ndarray:
     """16 normalisation numbers: in_shift[7], in_scale[7], out_shift, out_scale.
 
-    The network sees (d / d_scale, q) and predicts (E - e_shift) / e_scale.
+    The network sees (d_gain d / d_cut, q_gain q): with d uniform in direction
+    and |d| <= d_cut, and q uniform on S^3 (components of standard deviation
+    1/2), these gains give inputs of about unit spread.  It predicts
+    (E - e_shift) / e_scale.
     """
-    return np.concatenate([np.zeros(7), [1.0 / d_scale] * 3 + [1.0] * 4, [e_shift, e_scale]]).astype(np.float32)
+    return np.concatenate([np.zeros(7), [d_gain / d_cut] * 3 + [q_gain] * 4, [e_shift, e_scale]]).astype(np.float32)
 
 
 class NNPairEnergy(torch.autograd.Function):

@@ -8,8 +8,9 @@ rebuild, the FP32 bead double sum over every listed pair with per-body
 accumulation, the second half kick.  value = rigid-pair F+tau evaluations
 per second over the timed steps.
 
-Also reported (same run): the network path on the same system (BF16 MLP
-with bead fallback below d_min), the network kernels on 2^20 random
+Also reported (same run): a cube-6 surrogate trained on bead-labelled
+pairs (held-out errors), the network path on the same system with it (BF16
+MLP with bead fallback below d_min), the network kernels on 2^20 random
 cylinder pairs (forward, forward + input gradient; BF16 and FP32), the
 per-kernel roofline of the bead kernel, and the FP64 oracle on the host as
 a CPU baseline.  Inputs are synthetic and seeded.
@@ -47,56 +48,64 @@ def make_system(cfg, st, torch):
                        cfg.r_list, cfg.skin)
 
 
-def run_md(sysm, steps, warmup, dt, path, torch, abi, time_kernel=True):
-    """Warm up, then time `steps` MD steps.  Returns timing and counters."""
+GRAPH_STEPS = 10   # MD steps recorded per HIP graph
+
+
+def run_md(sysm, steps, warmup, dt, path, torch, abi):
+    """Warm up eagerly, record GRAPH_STEPS steps into a HIP graph, and time
+    `steps` steps as graph replays (steps is rounded up to a multiple of
+    GRAPH_STEPS).  Returns timing and device counters."""
     for _ in range(warmup):
         sysm.step(dt, path)
     torch.cuda.synchronize()
     sysm.check_capacity()
-    f0 = sysm.flags_host()
+    # fused stepping: each step is pair list (skipped unless flagged), forces
+    # into the accumulator, and one integrator launch that ends this step and
+    # starts the next
+    sysm.begin_fused(dt)
+    g = sysm.capture(dt, path, GRAPH_STEPS, fused=True)
+    g.replay()                      # one untimed replay
+    torch.cuda.synchronize()
+    f0 = sysm.check_capacity()
     st = torch.cuda.current_stream()
-    ev = []
-    # kernel timing: events around the force call of every step, on the
-    # stream the kernels are launched on
-    orig = sysm.compute_forces
-
-    def timed_forces(p):
-        if time_kernel:
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record(st)
-            orig(p)
-            b.record(st)
-            ev.append((a, b))
-        else:
-            orig(p)
-
-    sysm.compute_forces = timed_forces
+    reps = (steps + GRAPH_STEPS - 1) // GRAPH_STEPS
     e_start = torch.cuda.Event(enable_timing=True)
     e_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e_start.record(st)
-    for _ in range(steps):
-        sysm.step(dt, path)
+    for _ in range(reps):
+        g.replay()
     e_end.record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    sysm.compute_forces = orig
     f1 = sysm.check_capacity()
     gpu_ms = e_start.elapsed_time(e_end)
-    force_ms = [a.elapsed_time(b) for a, b in ev]
     neval = (int(f1[abi.RB_FLAG_NEVAL]) - int(f0[abi.RB_FLAG_NEVAL])) % (1 << 32)
-    return dict(wall_s=wall, gpu_ms=gpu_ms, force_ms=force_ms, pairs_evaluated=neval,
+    sysm.end_fused(dt, path)
+    # eager steps, timed separately (host launch overhead included)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(GRAPH_STEPS * 5):
+        sysm.step(dt, path)
+    torch.cuda.synchronize()
+    eager_ms = 1e3 * (time.perf_counter() - t1) / (GRAPH_STEPS * 5)
+    return dict(wall_s=wall, steps=reps * GRAPH_STEPS, gpu_ms=gpu_ms, pairs_evaluated=neval,
                 rebuilds=int(f1[abi.RB_FLAG_NREBUILDS] - f0[abi.RB_FLAG_NREBUILDS]),
                 n_pairs=int(f1[abi.RB_FLAG_NPAIRS]), n_nn=int(f1[abi.RB_FLAG_NNN]),
-                n_bead=int(f1[abi.RB_FLAG_NBEAD]))
+                n_bead=int(f1[abi.RB_FLAG_NBEAD]), eager_ms_per_step=eager_ms)
+
+
+def ntests(flags_np, abi):
+    return int(flags_np[abi.RB_FLAG_NTESTS:abi.RB_FLAG_NTESTS + 2].view(np.int64)[0])
 
 
 def bead_kernel_time(sysm, reps, torch, abi):
-    """Average duration of the bead-sum kernel alone on the current list."""
+    """Mean duration of the bead-sum kernel alone on the current list, and the
+    bead-bead distance tests it performs per launch (after culling)."""
     st = torch.cuda.current_stream()
     abi.rb_accum_zero(sysm.n, sysm.acc)
+    t0 = ntests(sysm.flags_host(), abi)
     times = []
     for _ in range(reps):
         a = torch.cuda.Event(enable_timing=True)
@@ -107,7 +116,9 @@ def bead_kernel_time(sysm, reps, torch, abi):
         b.record(st)
         times.append((a, b))
     torch.cuda.synchronize()
-    return float(np.mean([a.elapsed_time(b) for a, b in times]))
+    tests = (ntests(sysm.flags_host(), abi) - t0) / reps
+    abi.rb_accum_zero(sysm.n, sysm.acc)
+    return float(np.mean([a.elapsed_time(b) for a, b in times])), tests
 
 
 def nn_kernels(torch, abi):
@@ -181,6 +192,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-nn", action="store_true", help="skip the network measurements")
+    ap.add_argument("--nn-epochs", type=int, default=40, help="surrogate training epochs (2^20 pairs each)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the path is single-GPU; --gpus {args.gpus} is not supported)",
@@ -202,11 +214,12 @@ def main():
     bead = run_md(sysm, args.steps, args.warmup, cfg.dt, "bead", torch, abi)
     kin = sysm.kinetic_host()
     e_tot = sysm.energy() + float(kin.sum())
-    kern_ms = bead_kernel_time(sysm, 20, torch, abi)
+    kern_ms, tests_done = bead_kernel_time(sysm, 20, torch, abi)
     npairs_now = int(sysm.flags_host()[abi.RB_FLAG_NPAIRS])
-    tests = npairs_now * cfg.body.n * cfg.body.n
-    achieved = tests * FLOP_PER_TEST / (kern_ms * 1e-3)
-    steps_per_s = args.steps / bead["wall_s"]
+    tests_brute = npairs_now * cfg.body.n * cfg.body.n
+    achieved = tests_done * FLOP_PER_TEST / (kern_ms * 1e-3)
+    nsteps = bead["steps"]
+    steps_per_s = nsteps / bead["wall_s"]
     value = bead["pairs_evaluated"] / bead["wall_s"]
 
     result = {
@@ -215,9 +228,9 @@ def main():
         "value": value,
         "unit": "rigid-pair F+tau evals/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": nsteps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * bead["wall_s"] / args.steps,
+        "ms_per_step": 1e3 * bead["wall_s"] / nsteps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -229,35 +242,45 @@ def main():
                    "pairs_per_step": npairs_now},
         "md_steps_per_s": steps_per_s,
         "bead_path": {"pairs_evaluated": bead["pairs_evaluated"], "rebuilds": bead["rebuilds"],
-                      "gpu_ms_per_step": bead["gpu_ms"] / args.steps,
-                      "force_call_ms_mean": float(np.mean(bead["force_ms"])),
-                      "total_energy_end": e_tot},
+                      "gpu_ms_per_step": bead["gpu_ms"] / nsteps, "graph_steps": GRAPH_STEPS,
+                      "eager_ms_per_step": bead["eager_ms_per_step"], "total_energy_end": e_tot},
         "roofline": {"kernel": "k_bead_md (rb_bead_pair_forces)", "bound": "alu", "achieved": achieved / 1e12,
                      "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK,
                      "traffic": None, "kernel_ms": kern_ms,
-                     "algorithmic_work": f"{npairs_now} pairs x {cfg.body.n}^2 bead tests x {FLOP_PER_TEST} FLOP"},
+                     "algorithmic_work": f"{tests_done:.0f} bead-bead distance tests x {FLOP_PER_TEST} FLOP per "
+                                         f"launch (the tests that survive exact box culling; the brute-force "
+                                         f"double sum would do {npairs_now} pairs x {cfg.body.n}^2 = "
+                                         f"{tests_brute} tests)",
+                     "brute_force_equivalent_tflops": tests_brute * FLOP_PER_TEST / (kern_ms * 1e-3) / 1e12},
     }
 
     if not args.no_nn:
-        # network path on the same system: Xavier weights give the kernel
-        # cost (the cost does not depend on the weight values)
+        # network path on the same system, with a cube-6 surrogate trained
+        # here on bead-labelled pairs (its held-out errors are reported)
+        from paper_2402_12199_amd.surrogate import train_surrogate
+        log(f"[bench] training a {cfg.body.name} surrogate ({args.nn_epochs} epochs)")
+        sur = train_surrogate(cfg.body, 1 << 20, 1 << 16, args.nn_epochs, log=log)
         log("[bench] network path on the same system")
         st2 = state.initial_state(cfg)
         sysn = make_system(cfg, st2, torch)
-        from paper_2402_12199_amd.nn import make_norm
-        params = torch.tensor(sampling.xavier_params(1002).astype(np.float32), device="cuda")
-        sysn.set_nn(NNModel(params=params, norm=make_norm(cfg.d_cut), precision=abi.RB_PREC_BF16,
+        sysn.set_nn(NNModel(params=sur["params"], norm=sur["norm"], precision=abi.RB_PREC_BF16,
                             d_min=cfg.d_min, sw_lo=cfg.d_cut - 1.0, sw_hi=cfg.d_cut))
         sysn.init_forces("nn")
         nnr = run_md(sysn, args.steps, args.warmup, cfg.dt, "nn", torch, abi)
+        kin_n = sysn.kinetic_host()
         result["nn_path"] = {
             "pairs_per_s": nnr["pairs_evaluated"] / nnr["wall_s"],
-            "md_steps_per_s": args.steps / nnr["wall_s"],
-            "ms_per_step": 1e3 * nnr["wall_s"] / args.steps,
-            "force_call_ms_mean": float(np.mean(nnr["force_ms"])),
+            "md_steps_per_s": nnr["steps"] / nnr["wall_s"],
+            "ms_per_step": 1e3 * nnr["wall_s"] / nnr["steps"],
+            "eager_ms_per_step": nnr["eager_ms_per_step"],
             "pairs_nn": nnr["n_nn"], "pairs_bead_fallback": nnr["n_bead"],
-            "speedup_steps_vs_bead": (args.steps / nnr["wall_s"]) / steps_per_s,
-            "weights": "Xavier (timing only)",
+            "speedup_steps_vs_bead": (nnr["steps"] / nnr["wall_s"]) / steps_per_s,
+            "total_energy_end": sysn.energy() + float(kin_n.sum()),
+            "surrogate": {k: sur[k] for k in ("shape", "epochs", "steps", "batch", "n_train", "n_test",
+                                              "reject_rate", "label_s", "train_s", "samples_per_s", "d_min",
+                                              "d_cut")} | {"held_out": sur["trained"],
+                                                           "loss_first_last": [sur["loss_history"][0],
+                                                                               sur["loss_history"][-1]]},
         }
         log("[bench] network kernels on 2^20 pairs")
         result["nn_kernels_2^20"] = nn_kernels(torch, abi)

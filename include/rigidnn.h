@@ -47,7 +47,8 @@ extern "C" {
 #define RB_ERR_HIP (-3)
 #define RB_ERR_UNSUPPORTED (-4)
 
-/* Device flag words (int32 array of RB_NFLAGS, caller owned, zero it once). */
+/* Device flag words (int32 array of RB_NFLAGS, 8-byte aligned, caller owned,
+ * zero it once). */
 #define RB_FLAG_REBUILD 0    /* 1: the pair list must be rebuilt before use     */
 #define RB_FLAG_NPAIRS 1     /* pairs in the current list (<= capacity)         */
 #define RB_FLAG_OVERFLOW 2   /* pairs found by the last build when > capacity   */
@@ -57,7 +58,9 @@ extern "C" {
 #define RB_FLAG_NONFINITE 6  /* a non-finite per-pair force or energy was seen   */
 #define RB_FLAG_NEVAL 7      /* running count of pairs evaluated by the per-body
                                 force calls (bead and network); wraps at 2^31  */
-#define RB_NFLAGS 8
+#define RB_FLAG_NTESTS 8     /* flags[8..9] as one int64: running count of bead-
+                                bead distance tests performed after culling    */
+#define RB_NFLAGS 16
 
 #define RB_PREC_BF16 0       /* 128x128 layers on BF16 MFMA, FP32 accumulate     */
 #define RB_PREC_FP32 1       /* every layer in FP32                              */
@@ -68,12 +71,16 @@ extern "C" {
 #define RB_MLP_NPARAMS 50689 /* 7 -> 128 -> 128 -> 128 -> 128 -> 1               */
 
 /* Fixed-point accumulator of per-body forces/torques and global sums:
- * int64 array of RB_ACC_LEN(n) = 6 n + 10 words, layout F_x[n] F_y[n] F_z[n]
- * tau_x[n] tau_y[n] tau_z[n] E W_xx W_xy W_xz W_yx ... W_zz, each word the
- * value times 2^32.  Integer addition is associative, so the result does
- * not depend on the order in which pairs are summed. */
+ * int64 array of RB_ACC_LEN(n) = 6 n + 10 * RB_ACC_SLOTS words, layout
+ * F_x[n] F_y[n] F_z[n] tau_x[n] tau_y[n] tau_z[n], then for each of the 10
+ * global sums (E, W_xx, W_xy, W_xz, W_yx, ..., W_zz) RB_ACC_SLOTS partial
+ * words that different workgroups add into (spreading the atomics over many
+ * addresses); rb_accum_finalize adds the partials.  Every word is the value
+ * times 2^32; integer addition is associative, so the result does not
+ * depend on the order in which pairs are summed. */
 #define RB_ACC_SCALE 4294967296.0
-#define RB_ACC_LEN(n) (6 * (int64_t)(n) + 10)
+#define RB_ACC_SLOTS 64
+#define RB_ACC_LEN(n) (6 * (int64_t)(n) + 10 * RB_ACC_SLOTS)
 
 typedef struct rb_ctx rb_ctx;
 
@@ -108,22 +115,29 @@ int rb_pairlist_build(int32_t n, const double *x, const double *box, double r_li
 
 /* ---- descriptors and routing ---------------------------------------------
  * For the first flags[NPAIRS] pairs: desc (7 x max_pairs FP32) from FP64
- * state, and routing of each pair to the network (|d| >= d_min) or to the
- * bead sum (|d| < d_min, outside the network's training domain).  Routed
- * pair indices go to idx_nn / idx_bead (capacity max_pairs each, order not
- * specified) with counts in flags[NNN] / flags[NBEAD].  x: 3 x n, q: 4 x n. */
+ * state, and routing of each pair to the network (d_min <= |d| < d_max) or
+ * to the bead sum (|d| < d_min, outside the network's training domain);
+ * pairs at |d| >= d_max (where the switched network energy is zero; d_max
+ * <= 0: no limit) go to neither.  Routed pair indices go to idx_nn /
+ * idx_bead (capacity max_pairs each, order not specified) with counts in
+ * flags[NNN] / flags[NBEAD].  x: 3 x n, q: 4 x n. */
 int rb_pair_descriptors(int32_t n, const double *x, const double *q, const double *box,
                         const int32_t *pair_i, const int32_t *pair_j, int32_t max_pairs,
-                        float d_min, float *desc, int32_t *idx_nn, int32_t *idx_bead,
-                        int32_t *flags, void *stream);
+                        float d_min, float d_max, float *desc, int32_t *idx_nn,
+                        int32_t *idx_bead, int32_t *flags, void *stream);
 
 /* ---- bead double sum (paper section 2, first equation) -------------------
+ * Every bead pair closer than rc contributes; bead pairs are skipped only
+ * when a bead lies farther than rc from the other body's bead box, which
+ * cannot hold a partner within rc.
  * Per-pair form, for labelling and checks: body i of type type_i at the
  * origin with identity orientation, body j of type type_j at desc's d with
  * orientation q/|q|.  out: 11 x n_pairs FP32 = E, F_j[3], tau_i[3], tau_j[3]
- * in body i's frame, and r_min, the smallest bead-bead distance. */
+ * in body i's frame, and r_min = min(smallest bead-bead distance, rc).
+ * flags (may be NULL): adds the distance tests performed to
+ * flags[NTESTS]. */
 int rb_bead_pair_eval(const rb_ctx *ctx, int64_t n_pairs, const float *desc, int32_t type_i,
-                      int32_t type_j, float *out, void *stream);
+                      int32_t type_j, float *out, int32_t *flags, void *stream);
 
 /* Per-body form for dynamics: the pairs idx[0 .. *count_dev) of the list
  * (idx == NULL: the pairs 0 .. *count_dev), count read on the device and
@@ -136,16 +150,19 @@ int rb_bead_pair_forces(const rb_ctx *ctx, int32_t n, const double *x, const dou
                         int32_t max_count, int64_t *acc, int32_t *flags, void *stream);
 
 /* ---- accumulator -----------------------------------------------------------
- * rb_accum_zero clears acc with a fill kernel (graph safe).
+ * rb_accum_zero clears acc with a fill kernel (graph safe); needed once,
+ * before the first evaluation.
  * rb_accum_finalize converts acc into force[3 x n] and torque[3 x n] (FP32,
- * lab frame) and energy_virial[10] (FP64: E then W row-major). */
+ * lab frame) and energy_virial[10] (FP64: E then W row-major, may be NULL),
+ * and clears acc for the next evaluation. */
 int rb_accum_zero(int32_t n, int64_t *acc, void *stream);
-int rb_accum_finalize(int32_t n, const int64_t *acc, float *force, float *torque,
+int rb_accum_finalize(int32_t n, int64_t *acc, float *force, float *torque,
                       double *energy_virial, void *stream);
 
 /* ---- energy network (paper section 2, g_NN_U; supplementary section 6) ---
- * params: RB_MLP_NPARAMS FP32, layer by layer W_l (out x in, row major) then
- * b_l, dims 7 -> 128 -> 128 -> 128 -> 128 -> 1, SiLU on hidden layers.
+ * params: RB_MLP_NPARAMS FP32 (16-byte aligned), layer by layer W_l (out x
+ * in, row major) then b_l, dims 7 -> 128 -> 128 -> 128 -> 128 -> 1, SiLU on
+ * the hidden layers.
  * norm (host, 16 floats): in_shift[7], in_scale[7], out_shift, out_scale;
  * the network sees u' = (u - in_shift) * in_scale and E = e' * out_scale +
  * out_shift.  precision: RB_PREC_BF16 (first and last layer FP32, the three
@@ -184,12 +201,25 @@ int rb_nn_pair_forces(const float *params, const float *norm, int precision, int
  * J. Chem. Phys. 116, 8649, 2002), renormalise q; if x_ref != NULL and a
  * body moved more than half_skin from x_ref, sets flags[REBUILD].  phase 2:
  * second half kick; writes kinetic[2] = (translational, rotational) kinetic
- * energy (FP64 deterministic reduction).  ws: rb_rigid_workspace_bytes(n). */
+ * energy (FP64 deterministic reduction).  ws: rb_rigid_workspace_bytes(n),
+ * zero-filled before its first use. */
 size_t rb_rigid_workspace_bytes(int32_t n);
 int rb_rigid_step(const rb_ctx *ctx, int phase, int32_t n, double dt, double *x, double *P,
                   double *q, double *L, const int32_t *type, const float *force,
                   const float *torque, const double *x_ref, double half_skin, double *kinetic,
                   int32_t *flags, void *ws, size_t ws_bytes, void *stream);
+
+/* Step boundary in one launch, for loops that keep the forces in the
+ * accumulator: rb_accum_finalize (acc -> force, torque FP32, energy_virial
+ * FP64 (may be NULL), acc cleared) + phase 2 (kinetic energy at the full
+ * step) + phase 1 of the next step, with the same arithmetic in the same
+ * order.  A run of K steps is phase 1, then (pair list, forces into acc,
+ * rb_rigid_step_fused) K - 1 times, then pair list, forces, finalize,
+ * phase 2.  ws as for phase 2, zero-filled before its first use. */
+int rb_rigid_step_fused(const rb_ctx *ctx, int32_t n, double dt, double *x, double *P, double *q,
+                        double *L, const int32_t *type, int64_t *acc, float *force, float *torque,
+                        double *energy_virial, const double *x_ref, double half_skin,
+                        double *kinetic, int32_t *flags, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- training step (energy loss, Adam) ------------------------------------
  * One step on the batch idx[0 .. batch) of a data set (desc 7 x n_data

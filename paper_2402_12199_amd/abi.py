@@ -16,15 +16,18 @@ import torch
 from ._lib import check, lib
 
 RB_FLAG_REBUILD, RB_FLAG_NPAIRS, RB_FLAG_OVERFLOW, RB_FLAG_NREBUILDS = 0, 1, 2, 3
-RB_FLAG_NBEAD, RB_FLAG_NNN, RB_FLAG_NONFINITE, RB_FLAG_NEVAL, RB_NFLAGS = 4, 5, 6, 7, 8
+RB_FLAG_NBEAD, RB_FLAG_NNN, RB_FLAG_NONFINITE, RB_FLAG_NEVAL, RB_FLAG_NTESTS, RB_NFLAGS = 4, 5, 6, 7, 8, 16
 RB_PREC_BF16, RB_PREC_FP32 = 0, 1
 RB_BUILD_ALWAYS, RB_BUILD_IF_FLAGGED = 0, 1
 RB_MLP_NPARAMS = 50689
 RB_ACC_SCALE = 4294967296.0
 
 
+RB_ACC_SLOTS = 64
+
+
 def acc_len(n: int) -> int:
-    return 6 * n + 10
+    return 6 * n + 10 * RB_ACC_SLOTS
 
 
 def _stream():
@@ -107,14 +110,14 @@ def rb_pairlist_build(x, box, r_list, pair_i, pair_j, x_ref, flags, mode, ws):
           "rb_pairlist_build")
 
 
-def rb_pair_descriptors(x, q, box, pair_i, pair_j, d_min, desc, idx_nn, idx_bead, flags):
+def rb_pair_descriptors(x, q, box, pair_i, pair_j, d_min, desc, idx_nn, idx_bead, flags, d_max=0.0):
     n = x.shape[1]
     maxp = pair_i.numel()
     _, bp = _box(box)
     check(lib().rb_pair_descriptors(n, _ptr(x, torch.float64, (3, n), "x"),
                                     _ptr(q, torch.float64, (4, n), "q"), bp,
                                     _ptr(pair_i, torch.int32, name="pair_i"),
-                                    _ptr(pair_j, torch.int32, name="pair_j"), maxp, float(d_min),
+                                    _ptr(pair_j, torch.int32, name="pair_j"), maxp, float(d_min), float(d_max),
                                     _ptr(desc, torch.float32, (7, maxp), "desc"),
                                     _ptr(idx_nn, torch.int32, (maxp,), "idx_nn"),
                                     _ptr(idx_bead, torch.int32, (maxp,), "idx_bead"),
@@ -122,10 +125,11 @@ def rb_pair_descriptors(x, q, box, pair_i, pair_j, d_min, desc, idx_nn, idx_bead
           "rb_pair_descriptors")
 
 
-def rb_bead_pair_eval(ctx: Ctx, desc, type_i: int, type_j: int, out):
+def rb_bead_pair_eval(ctx: Ctx, desc, type_i: int, type_j: int, out, flags=None):
     P = desc.shape[1]
     check(lib().rb_bead_pair_eval(ctx.handle, P, _ptr(desc, torch.float32, (7, P), "desc"), type_i, type_j,
-                                  _ptr(out, torch.float32, (11, P), "out"), _stream()),
+                                  _ptr(out, torch.float32, (11, P), "out"),
+                                  _ptr(flags, torch.int32, (RB_NFLAGS,), "flags", optional=True), _stream()),
           "rb_bead_pair_eval")
 
 
@@ -212,6 +216,23 @@ def rb_rigid_step(ctx: Ctx, phase: int, dt: float, x, P, q, L, types, force, tor
                               _ptr(ws, torch.uint8, name="ws", optional=True), 0 if ws is None else ws.numel(),
                               _stream()),
           "rb_rigid_step")
+
+
+def rb_rigid_step_fused(ctx: Ctx, dt: float, x, P, q, L, types, acc, force, torque, energy_virial, x_ref,
+                        half_skin, kinetic, flags, ws):
+    n = P.shape[1]
+    check(lib().rb_rigid_step_fused(ctx.handle, n, float(dt), _ptr(x, torch.float64, (3, n), "x"),
+                                    _ptr(P, torch.float64, (3, n), "P"), _ptr(q, torch.float64, (4, n), "q"),
+                                    _ptr(L, torch.float64, (3, n), "L"), _ptr(types, torch.int32, (n,), "type"),
+                                    _ptr(acc, torch.int64, (acc_len(n),), "acc"),
+                                    _ptr(force, torch.float32, (3, n), "force"),
+                                    _ptr(torque, torch.float32, (3, n), "torque"),
+                                    _ptr(energy_virial, torch.float64, (10,), "energy_virial", optional=True),
+                                    _ptr(x_ref, torch.float64, (3, n), "x_ref", optional=True), float(half_skin),
+                                    _ptr(kinetic, torch.float64, (2,), "kinetic"),
+                                    _ptr(flags, torch.int32, (RB_NFLAGS,), "flags"),
+                                    _ptr(ws, torch.uint8, name="ws"), ws.numel(), _stream()),
+          "rb_rigid_step_fused")
 
 
 def rb_nn_train_workspace_bytes(batch: int) -> int:

@@ -3,105 +3,151 @@
 // N_i x N_j bead pairs), with the workloads' bead potential, Lennard-Jones
 // 12-6 shifted in energy at rc.
 //
-// Work mapping (gfx950, wave64): one wavefront per body pair.  The pair is
-// evaluated in body i's frame, where body i's beads are just its template.
-// Each lane keeps S = ceil(N_i / 64) of body i's beads in registers; body
-// j's beads are rotated into body i's frame (FP64, then rounded to FP32) and
-// staged in LDS, and every lane streams them with broadcast LDS reads, so
-// each LDS read feeds S distance tests.  Per-bead forces stay in registers;
-// F_i and tau_i are reduced across the wave with lane shuffles, and body j's
-// force and torque follow from pair identities (central bead forces):
-// F_j = -F_i and tau_j = d x F_i - tau_i.
+// Work mapping (gfx950, wave64): one wavefront per body pair, evaluated in
+// body i's frame, where body i's beads are its template.
+//  1. Body j's beads are rotated into body i's frame in FP64 and kept when
+//     they lie within rc of body i's bead box (the box that holds every bead
+//     centre of i); survivors go to LDS, compacted with a ballot, as an FP32
+//     value plus its FP32 rounding residual.
+//  2. Body i's beads are kept when they lie within rc of body j's bead box;
+//     survivors go to LDS.  A bead outside these boxes has no partner within
+//     rc, so the culling drops no interacting bead pair.
+//  3. The surviving ni x nj distance tests are spread over the 64 lanes:
+//     lanes form groups of P >= ni (a power of two) that each hold one of
+//     body i's beads, and the 64/P groups stride through body j's beads, so
+//     every LDS read is a broadcast to a group.  The tests are branch free:
+//     every lane evaluates the LJ term and keeps it when r < rc.
+//  4. Per-bead forces stay in registers; E, F_i and tau_i are reduced across
+//     the wave with lane shuffles, and body j's force and torque follow from
+//     pair identities (central bead forces): F_j = -F_i and
+//     tau_j = d x F_i - tau_i.
 #include "rb_common.hpp"
 
 namespace rb {
 
-constexpr int kBeadWaves = 4;      // waves per block
-constexpr float kFar = 1.0e4f;     // coordinate of padding beads: never inside rc
+constexpr int kBeadWaves = 4;        // waves per block
+constexpr float kCullMargin = 1.0e-3f;
 
-// Body j's beads, rotated and shifted into body i's frame, into this wave's
-// LDS slice: r_l = d + R b_l, computed in FP64 and split into an FP32 value
-// (sj) and its FP32 rounding residual (sjlo).
-__device__ inline void stage_j(const Templates &T, int tj, const double d[3], const double R[9],
-                               float4 *sj, float4 *sjlo, int lane) {
+struct WaveLds {
+    float4 j[kMaxBeads];     // body j's surviving beads (FP32), body i frame
+    float4 jlo[kMaxBeads];   // their FP32 rounding residuals
+    float4 i[kMaxBeads];     // body i's surviving beads, body i frame
+};
+
+__device__ inline float box_dist2(float x, float y, float z, float hx, float hy, float hz) {
+    const float ax = fmaxf(fabsf(x) - hx, 0.f), ay = fmaxf(fabsf(y) - hy, 0.f), az = fmaxf(fabsf(z) - hz, 0.f);
+    return fmaf(ax, ax, fmaf(ay, ay, az * az));
+}
+
+// Appends `v` (and `vlo`) for the lanes with keep set, in lane order, at
+// dst[count ...]; returns the new count (wave uniform).
+__device__ inline int wave_compact(bool keep, float4 v, float4 vlo, float4 *dst, float4 *dstlo, int count,
+                                   int lane) {
+    const unsigned long long m = __ballot(keep);
+    if (keep) {
+        const int pos = count + __popcll(m & ((1ull << lane) - 1ull));
+        dst[pos] = v;
+        if (dstlo) dstlo[pos] = vlo;
+    }
+    return count + __popcll(m);
+}
+
+// Stages the beads of body j (type tj, at d with rotation R relative to body
+// i) that can reach body i's box; r_l = d + R b_l is formed in FP64.
+__device__ inline int stage_j(const Templates &T, int ti, int tj, const double d[3], const double R[9],
+                              float cut2, WaveLds &L, int lane) {
     const int nj = T.n[tj];
     const float4 *bj = T.beads + T.off[tj];
-    for (int l = lane; l < nj; l += kWave) {
-        const float4 b = bj[l];
-        const double bx = b.x, by = b.y, bz = b.z;
-        const double x = d[0] + R[0] * bx + R[1] * by + R[2] * bz;
-        const double y = d[1] + R[3] * bx + R[4] * by + R[5] * bz;
-        const double z = d[2] + R[6] * bx + R[7] * by + R[8] * bz;
-        const float fx = (float)x, fy = (float)y, fz = (float)z;
-        sj[l] = make_float4(fx, fy, fz, 0.f);
-        sjlo[l] = make_float4((float)(x - fx), (float)(y - fy), (float)(z - fz), 0.f);
+    const float hx = T.hx[ti], hy = T.hy[ti], hz = T.hz[ti];
+    int count = 0;
+    for (int l0 = 0; l0 < nj; l0 += kWave) {
+        const int l = l0 + lane;
+        bool keep = false;
+        float4 hi = make_float4(0.f, 0.f, 0.f, 0.f), lo = hi;
+        if (l < nj) {
+            const float4 b = bj[l];
+            const double bx = b.x, by = b.y, bz = b.z;
+            const double x = d[0] + R[0] * bx + R[1] * by + R[2] * bz;
+            const double y = d[1] + R[3] * bx + R[4] * by + R[5] * bz;
+            const double z = d[2] + R[6] * bx + R[7] * by + R[8] * bz;
+            hi = make_float4((float)x, (float)y, (float)z, 0.f);
+            lo = make_float4((float)(x - hi.x), (float)(y - hi.y), (float)(z - hi.z), 0.f);
+            keep = box_dist2(hi.x, hi.y, hi.z, hx, hy, hz) < cut2;
+        }
+        count = wave_compact(keep, hi, lo, L.j, L.jlo, count, lane);
     }
+    return count;
 }
 
-template <int S>
-__device__ inline void load_i(const Templates &T, int ti, int lane, float (&bx)[S], float (&by)[S],
-                              float (&bz)[S]) {
+// Stages the beads of body i that can reach body j's box: a bead b of i sits
+// at R^T (b - d) in body j's frame (FP32 is ample for the test: the margin
+// is far above its rounding).
+__device__ inline int stage_i(const Templates &T, int ti, int tj, const double d[3], const double R[9],
+                              float cut2, WaveLds &L, int lane) {
     const int ni = T.n[ti];
-    const float4 *b = T.beads + T.off[ti];
+    const float4 *bi = T.beads + T.off[ti];
+    const float hx = T.hx[tj], hy = T.hy[tj], hz = T.hz[tj];
+    const float dx = (float)d[0], dy = (float)d[1], dz = (float)d[2];
+    float Rf[9];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-        const int k = lane + kWave * s;
+    for (int a = 0; a < 9; ++a) Rf[a] = (float)R[a];
+    int count = 0;
+    for (int k0 = 0; k0 < ni; k0 += kWave) {
+        const int k = k0 + lane;
+        bool keep = false;
+        float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
         if (k < ni) {
-            const float4 v = b[k];
-            bx[s] = v.x; by[s] = v.y; bz[s] = v.z;
-        } else {
-            bx[s] = kFar; by[s] = kFar; bz[s] = kFar;
+            b = bi[k];
+            const float ux = b.x - dx, uy = b.y - dy, uz = b.z - dz;
+            const float px = Rf[0] * ux + Rf[3] * uy + Rf[6] * uz;
+            const float py = Rf[1] * ux + Rf[4] * uy + Rf[7] * uz;
+            const float pz = Rf[2] * ux + Rf[5] * uy + Rf[8] * uz;
+            keep = box_dist2(px, py, pz, hx, hy, hz) < cut2;
         }
+        count = wave_compact(keep, b, b, L.i, nullptr, count, lane);
     }
+    return count;
 }
 
-// All N_i x N_j distance tests of one pair.  The screening distance uses
-// the FP32 positions; a bead pair that passes (r^2 < rc^2 + a margin far
-// above the FP32 rounding of r^2) is recomputed with the residuals of body
-// j's positions, so the cutoff test and the LJ terms see the positions to
-// about 1e-13 sigma.  Returns, reduced over the wave (valid in every lane):
-// r[0] = E, r[1..3] = F_i, r[4..6] = tau_i (about body i's centre, body i
-// frame), r[7] = min squared bead distance (only when TRACK_MIN).
-template <int S, bool TRACK_MIN>
-__device__ inline void pair_sum(const LJ &lj, int nj, const float (&bx)[S], const float (&by)[S],
-                                const float (&bz)[S], const float4 *sj, const float4 *sjlo, float r[8]) {
-    float fx[S], fy[S], fz[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) fx[s] = fy[s] = fz[s] = 0.f;
+// The ni x nj surviving tests.  Returns, reduced over the wave (valid in
+// every lane): r[0] = E, r[1..3] = F_i, r[4..6] = tau_i (body i frame, about
+// its centre), r[7] = min squared distance over the tests performed (only
+// when TRACK_MIN).
+template <bool TRACK_MIN>
+__device__ inline void pair_sum(const LJ &lj, int ni, int nj, const WaveLds &L, int lane, float r[8]) {
+    int P = 1;
+    while (P < ni && P < kWave) P <<= 1;
+    const int G = kWave / P, g = lane / P, kk = lane % P;
     float e = 0.f, r2min = 3.0e38f;
-    const float screen = lj.rc2 + 1.0e-3f;
-    for (int l = 0; l < nj; ++l) {
-        const float4 p = sj[l];
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            float dx = bx[s] - p.x, dy = by[s] - p.y, dz = bz[s] - p.z;
-            float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            if (TRACK_MIN) r2min = fminf(r2min, r2);
-            if (r2 < screen) {
-                const float4 lo = sjlo[l];
-                dx -= lo.x; dy -= lo.y; dz -= lo.z;
-                r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                if (r2 < lj.rc2) {
-                    const float ir2 = __builtin_amdgcn_rcpf(r2);
-                    const float s2 = lj.sig2 * ir2;
-                    const float s6 = s2 * s2 * s2;
-                    const float s12 = s6 * s6;
-                    e += fmaf(lj.c4e, s12 - s6, -lj.ushift);
-                    const float fr = lj.c24e * fmaf(2.f, s12, -s6) * ir2;
-                    fx[s] = fmaf(fr, dx, fx[s]);
-                    fy[s] = fmaf(fr, dy, fy[s]);
-                    fz[s] = fmaf(fr, dz, fz[s]);
-                }
-            }
-        }
-    }
     float F[3] = {0.f, 0.f, 0.f}, t[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        F[0] += fx[s]; F[1] += fy[s]; F[2] += fz[s];
-        t[0] += by[s] * fz[s] - bz[s] * fy[s];
-        t[1] += bz[s] * fx[s] - bx[s] * fz[s];
-        t[2] += bx[s] * fy[s] - by[s] * fx[s];
+    for (int kb = 0; kb < ni; kb += P) {
+        const int k = kb + kk;
+        const bool kv = k < ni;
+        const float4 b = kv ? L.i[k] : make_float4(1.0e4f, 1.0e4f, 1.0e4f, 0.f);
+        float fx = 0.f, fy = 0.f, fz = 0.f;
+        for (int l = g; l < nj; l += G) {
+            const float4 p = L.j[l];
+            const float4 lo = L.jlo[l];
+            const float dx = (b.x - p.x) - lo.x, dy = (b.y - p.y) - lo.y, dz = (b.z - p.z) - lo.z;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            if (TRACK_MIN) r2min = fminf(r2min, r2);
+            const bool in = r2 < lj.rc2;
+            const float ir2 = __builtin_amdgcn_rcpf(r2);
+            const float s2 = lj.sig2 * ir2;
+            const float s6 = s2 * s2 * s2;
+            const float s12 = s6 * s6;
+            const float ee = fmaf(lj.c4e, s12 - s6, -lj.ushift);
+            const float fr = lj.c24e * fmaf(2.f, s12, -s6) * ir2;
+            e += in ? ee : 0.f;
+            const float frm = in ? fr : 0.f;
+            fx = fmaf(frm, dx, fx);
+            fy = fmaf(frm, dy, fy);
+            fz = fmaf(frm, dz, fz);
+        }
+        F[0] += fx; F[1] += fy; F[2] += fz;
+        t[0] += b.y * fz - b.z * fy;
+        t[1] += b.z * fx - b.x * fz;
+        t[2] += b.x * fy - b.y * fx;
     }
     r[0] = wave_sum(e);
     r[1] = wave_sum(F[0]); r[2] = wave_sum(F[1]); r[3] = wave_sum(F[2]);
@@ -110,19 +156,17 @@ __device__ inline void pair_sum(const LJ &lj, int nj, const float (&bx)[S], cons
 }
 
 // Per-pair form: descriptors in, per-pair outputs in body i's frame out.
-template <int S>
+// r_min is exact when some bead pair is closer than rc; otherwise the value
+// reported is at least rc (culled bead pairs are all farther than rc).
 __global__ __launch_bounds__(256) void k_bead_desc(Templates T, LJ lj, int ti, int tj, int64_t P,
-                                                   const float *__restrict__ desc,
-                                                   float *__restrict__ out) {
-    __shared__ float4 lds[kBeadWaves][kMaxBeads];
-    __shared__ float4 ldslo[kBeadWaves][kMaxBeads];
+                                                   const float *__restrict__ desc, float *__restrict__ out,
+                                                   int32_t *__restrict__ flags) {
+    __shared__ WaveLds lds[kBeadWaves];
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    float4 *sj = lds[w];
-    float4 *sjlo = ldslo[w];
-    float bx[S], by[S], bz[S];
-    load_i<S>(T, ti, lane, bx, by, bz);
-    const int nj = T.n[tj];
+    WaveLds &L = lds[w];
+    const float cut2 = (sqrtf(lj.rc2) + kCullMargin) * (sqrtf(lj.rc2) + kCullMargin);
+    long long ntests = 0;
     const int64_t step = (int64_t)gridDim.x * kBeadWaves;
     for (int64_t p = (int64_t)blockIdx.x * kBeadWaves + w; p < P; p += step) {
         double d[3] = {desc[p], desc[P + p], desc[2 * P + p]};
@@ -130,10 +174,12 @@ __global__ __launch_bounds__(256) void k_bead_desc(Templates T, LJ lj, int ti, i
         const double inv = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
         double R[9];
         quat_to_rot<double>(qw * inv, qx * inv, qy * inv, qz * inv, R);
-        stage_j(T, tj, d, R, sj, sjlo, lane);
+        const int nj = stage_j(T, ti, tj, d, R, cut2, L, lane);
+        const int ni = nj ? stage_i(T, ti, tj, d, R, cut2, L, lane) : 0;
         wave_lds_sync();
         float r[8];
-        pair_sum<S, true>(lj, nj, bx, by, bz, sj, sjlo, r);
+        pair_sum<true>(lj, ni, nj, L, lane, r);
+        ntests += (long long)ni * nj;
         wave_lds_sync();
         if (lane == 0) {
             const float Fx = r[1], Fy = r[2], Fz = r[3];
@@ -144,8 +190,17 @@ __global__ __launch_bounds__(256) void k_bead_desc(Templates T, LJ lj, int ti, i
             out[7 * P + p] = (dy * Fz - dz * Fy) - r[4];
             out[8 * P + p] = (dz * Fx - dx * Fz) - r[5];
             out[9 * P + p] = (dx * Fy - dy * Fx) - r[6];
-            out[10 * P + p] = sqrtf(r[7]);
+            out[10 * P + p] = ni * nj ? fminf(sqrtf(r[7]), sqrtf(lj.rc2)) : sqrtf(lj.rc2);
         }
+    }
+    long long part[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, ntests};
+    __shared__ long long tred[kBeadWaves];
+    if (lane == 0) tred[w] = part[10];
+    __syncthreads();
+    if (flags && threadIdx.x == 0) {
+        long long t = 0;
+        for (int k = 0; k < kBeadWaves; ++k) t += tred[k];
+        if (t) atomicAdd(reinterpret_cast<unsigned long long *>(flags + RB_FLAG_NTESTS), (unsigned long long)t);
     }
 }
 
@@ -155,56 +210,60 @@ struct Box {
 
 // Per-body form for dynamics.  Geometry from FP64 state; the pair's outputs
 // are rotated to the lab frame and added to the fixed-point accumulator.
-template <int S>
-__global__ __launch_bounds__(256) void k_bead_md(Templates T, LJ lj, int32_t n,
-                                                 const double *__restrict__ x,
-                                                 const double *__restrict__ q,
-                                                 const int32_t *__restrict__ type, Box box,
-                                                 const int32_t *__restrict__ pi,
-                                                 const int32_t *__restrict__ pj,
-                                                 const int32_t *__restrict__ idx,
-                                                 const int32_t *__restrict__ count_dev,
-                                                 int32_t max_count, int64_t *__restrict__ acc,
-                                                 int32_t *__restrict__ flags) {
-    __shared__ float4 lds[kBeadWaves][kMaxBeads];
-    __shared__ float4 ldslo[kBeadWaves][kMaxBeads];
+__global__ __launch_bounds__(256) void k_bead_md(Templates T, LJ lj, int32_t n, const double *__restrict__ x,
+                                                 const double *__restrict__ q, const int32_t *__restrict__ type,
+                                                 Box box, const int32_t *__restrict__ pi,
+                                                 const int32_t *__restrict__ pj, const int32_t *__restrict__ idx,
+                                                 const int32_t *__restrict__ count_dev, int32_t max_count,
+                                                 int64_t *__restrict__ acc, int32_t *__restrict__ flags) {
+    __shared__ WaveLds lds[kBeadWaves];
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    float4 *sj = lds[w];
-    float4 *sjlo = ldslo[w];
+    WaveLds &L = lds[w];
+    const float cut2 = (sqrtf(lj.rc2) + kCullMargin) * (sqrtf(lj.rc2) + kCullMargin);
     int count = *count_dev;
     if (count > max_count) count = max_count;
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(flags + RB_FLAG_NEVAL, count);
     long long eacc[10];
 #pragma unroll
     for (int a = 0; a < 10; ++a) eacc[a] = 0;
+    long long ntests = 0;
     bool bad = false;
     const int step = gridDim.x * kBeadWaves;
     for (int p = blockIdx.x * kBeadWaves + w; p < count; p += step) {
         const int pid = idx ? idx[p] : p;
         const int i = pi[pid], j = pj[pid];
         const int ti = type[i], tj = type[j];
-        double dl[3], Ri[9], Rj[9], d[3], R[9];
+        double dl[3], d[3], R[9];
+        {
+            double Ri[9], qr[4];
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-            dl[a] = min_image(x[a * n + j] - x[a * n + i], box.L[a], box.inv[a]);
-        quat_to_rot<double>(q[i], q[n + i], q[2 * n + i], q[3 * n + i], Ri);
-        quat_to_rot<double>(q[j], q[n + j], q[2 * n + j], q[3 * n + j], Rj);
+            for (int a = 0; a < 3; ++a)
+                dl[a] = min_image(x[a * n + j] - x[a * n + i], box.L[a], box.inv[a]);
+            const double aw = q[i], ax = q[n + i], ay = q[2 * n + i], az = q[3 * n + i];
+            const double bw = q[j], bx = q[n + j], by = q[2 * n + j], bz = q[3 * n + j];
+            quat_to_rot<double>(aw, ax, ay, az, Ri);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            d[a] = Ri[a] * dl[0] + Ri[3 + a] * dl[1] + Ri[6 + a] * dl[2];
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-                R[3 * a + b] = Ri[a] * Rj[b] + Ri[3 + a] * Rj[3 + b] + Ri[6 + a] * Rj[6 + b];
+            for (int a = 0; a < 3; ++a) d[a] = Ri[a] * dl[0] + Ri[3 + a] * dl[1] + Ri[6 + a] * dl[2];
+            // relative orientation q_i^* q_j, so R = R_i^T R_j
+            qr[0] = aw * bw + ax * bx + ay * by + az * bz;
+            qr[1] = aw * bx - ax * bw - ay * bz + az * by;
+            qr[2] = aw * by + ax * bz - ay * bw - az * bx;
+            qr[3] = aw * bz - ax * by + ay * bx - az * bw;
+            quat_to_rot<double>(qr[0], qr[1], qr[2], qr[3], R);
         }
-        float bx[S], by[S], bz[S];
-        load_i<S>(T, ti, lane, bx, by, bz);
-        stage_j(T, tj, d, R, sj, sjlo, lane);
+        const int nj = stage_j(T, ti, tj, d, R, cut2, L, lane);
+        if (nj == 0) continue;   // no bead of j within rc of i's box: zero contribution
+        const int ni = stage_i(T, ti, tj, d, R, cut2, L, lane);
+        if (ni == 0) continue;
         wave_lds_sync();
         float r[8];
-        pair_sum<S, false>(lj, T.n[tj], bx, by, bz, sj, sjlo, r);
+        pair_sum<false>(lj, ni, nj, L, lane, r);
+        ntests += (long long)ni * nj;
         wave_lds_sync();
         if (lane == 0) {
+            double Ri[9];
+            quat_to_rot<double>(q[i], q[n + i], q[2 * n + i], q[3 * n + i], Ri);
             const double F[3] = {r[1], r[2], r[3]}, ti_[3] = {r[4], r[5], r[6]};
             const double tj_[3] = {d[1] * F[2] - d[2] * F[1] - ti_[0], d[2] * F[0] - d[0] * F[2] - ti_[1],
                                    d[0] * F[1] - d[1] * F[0] - ti_[2]};
@@ -230,37 +289,39 @@ __global__ __launch_bounds__(256) void k_bead_md(Templates T, LJ lj, int32_t n,
                 for (int b = 0; b < 3; ++b) eacc[1 + 3 * a + b] += to_fixed(-dl[a] * Fl[b]);
         }
     }
-    if (lane == 0) {
-        int64_t *g = acc + 6 * (int64_t)n;
+    long long part[11];
 #pragma unroll
-        for (int a = 0; a < 10; ++a)
-            if (eacc[a]) atomicAdd(reinterpret_cast<unsigned long long *>(g + a), (unsigned long long)eacc[a]);
-        if (bad) atomicOr(flags + RB_FLAG_NONFINITE, 1);
-    }
+    for (int a = 0; a < 10; ++a) part[a] = eacc[a];
+    part[10] = ntests;
+    block_flush_globals<kBeadWaves>(part, acc + 6 * (int64_t)n, flags);
+    if (lane == 0 && bad) atomicOr(flags + RB_FLAG_NONFINITE, 1);
 }
 
-static int slots_for(int nbeads) { return (nbeads + kWave - 1) / kWave; }
+static int device_cus_bead() {
+    static int cached = 0;
+    if (cached > 0) return cached;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    cached = cus;
+    return cus;
+}
 
 }  // namespace rb
 
 using namespace rb;
 
 extern "C" int rb_bead_pair_eval(const rb_ctx *ctx, int64_t n_pairs, const float *desc, int32_t type_i,
-                                 int32_t type_j, float *out, void *stream) {
+                                 int32_t type_j, float *out, int32_t *flags, void *stream) {
     RB_REQUIRE(ctx && (n_pairs == 0 || (desc && out)), "rb_bead_pair_eval: null argument");
     RB_REQUIRE(n_pairs >= 0, "rb_bead_pair_eval: n_pairs < 0");
     RB_REQUIRE(type_i >= 0 && type_i < ctx->n_types && type_j >= 0 && type_j < ctx->n_types,
                "rb_bead_pair_eval: bad type");
     if (n_pairs == 0) return RB_OK;
-    const int S = slots_for(ctx->n_beads[type_i]);
-    const int grid = grid_for(n_pairs, kBeadWaves, 65536);
-    hipStream_t st = (hipStream_t)stream;
-    switch (S) {
-        case 1: k_bead_desc<1><<<grid, 256, 0, st>>>(ctx->dev.t, ctx->dev.lj, type_i, type_j, n_pairs, desc, out); break;
-        case 2: k_bead_desc<2><<<grid, 256, 0, st>>>(ctx->dev.t, ctx->dev.lj, type_i, type_j, n_pairs, desc, out); break;
-        case 3: k_bead_desc<3><<<grid, 256, 0, st>>>(ctx->dev.t, ctx->dev.lj, type_i, type_j, n_pairs, desc, out); break;
-        default: k_bead_desc<4><<<grid, 256, 0, st>>>(ctx->dev.t, ctx->dev.lj, type_i, type_j, n_pairs, desc, out); break;
-    }
+    const int grid = grid_for(n_pairs, kBeadWaves, 3 * device_cus_bead());
+    k_bead_desc<<<grid, 256, 0, (hipStream_t)stream>>>(ctx->dev.t, ctx->dev.lj, type_i, type_j, n_pairs, desc, out,
+                                                      flags);
     RB_LAUNCH_CHECK("rb_bead_pair_eval");
     return RB_OK;
 }
@@ -273,27 +334,17 @@ extern "C" int rb_bead_pair_forces(const rb_ctx *ctx, int32_t n, const double *x
                "rb_bead_pair_forces: null argument");
     RB_REQUIRE(n >= 0 && max_count >= 0, "rb_bead_pair_forces: negative size");
     if (max_count == 0 || n == 0) return RB_OK;
-    int maxb = 0;
-    for (int t = 0; t < ctx->n_types; ++t) maxb = ctx->n_beads[t] > maxb ? ctx->n_beads[t] : maxb;
     Box b;
     for (int a = 0; a < 3; ++a) {
         RB_REQUIRE(box[a] > 0, "rb_bead_pair_forces: box must be > 0");
         b.L[a] = box[a];
         b.inv[a] = 1.0 / box[a];
     }
-    const int S = slots_for(maxb);
-    const int grid = grid_for(max_count, kBeadWaves, 8192);
-    hipStream_t st = (hipStream_t)stream;
-#define RB_MD_LAUNCH(SS)                                                                               \
-    k_bead_md<SS><<<grid, 256, 0, st>>>(ctx->dev.t, ctx->dev.lj, n, x, q, type, b, pair_i, pair_j, idx, \
-                                        count_dev, max_count, acc, flags)
-    switch (S) {
-        case 1: RB_MD_LAUNCH(1); break;
-        case 2: RB_MD_LAUNCH(2); break;
-        case 3: RB_MD_LAUNCH(3); break;
-        default: RB_MD_LAUNCH(4); break;
-    }
-#undef RB_MD_LAUNCH
+    // persistent grid: three 4-wave blocks fit a CU (LDS); waves stride over
+    // the pairs, and each block flushes its global sums once
+    const int grid = grid_for(max_count, kBeadWaves, 3 * device_cus_bead());
+    k_bead_md<<<grid, 256, 0, (hipStream_t)stream>>>(ctx->dev.t, ctx->dev.lj, n, x, q, type, b, pair_i, pair_j, idx,
+                                                    count_dev, max_count, acc, flags);
     RB_LAUNCH_CHECK("rb_bead_pair_forces");
     return RB_OK;
 }

@@ -30,7 +30,9 @@ __global__ void k_zero_i64(int64_t *a, int64_t n) {
         a[i] = 0;
 }
 
-__global__ void k_finalize(int32_t n, const int64_t *__restrict__ acc, float *__restrict__ force,
+// Converts the accumulator and clears it for the next evaluation (each word
+// is read and cleared by the same thread).
+__global__ void k_finalize(int32_t n, int64_t *__restrict__ acc, float *__restrict__ force,
                            float *__restrict__ torque, double *__restrict__ ev) {
     const double s = 1.0 / RB_ACC_SCALE;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -38,10 +40,19 @@ __global__ void k_finalize(int32_t n, const int64_t *__restrict__ acc, float *__
         for (int a = 0; a < 3; ++a) {
             force[a * n + i] = (float)((double)acc[a * (int64_t)n + i] * s);
             torque[a * n + i] = (float)((double)acc[(3 + a) * (int64_t)n + i] * s);
+            acc[a * (int64_t)n + i] = 0;
+            acc[(3 + a) * (int64_t)n + i] = 0;
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x < 10 && ev)
-        ev[threadIdx.x] = (double)acc[6 * (int64_t)n + threadIdx.x] * s;
+    if (blockIdx.x == 0 && threadIdx.x < 10) {
+        int64_t *g = acc + 6 * (int64_t)n + threadIdx.x * RB_ACC_SLOTS;
+        long long t = 0;
+        for (int k = 0; k < RB_ACC_SLOTS; ++k) {
+            t += g[k];
+            g[k] = 0;
+        }
+        if (ev) ev[threadIdx.x] = (double)t * s;
+    }
 }
 
 }  // namespace rb
@@ -72,13 +83,18 @@ extern "C" int rb_ctx_create(rb_ctx **out, int32_t n_types, const int32_t *n_bea
         c->dev.t.n[t] = n_beads[t];
         c->dev.t.off[t] = o;
         double r2max = 0;
+        float h[3] = {0.f, 0.f, 0.f};
         for (int k = 0; k < n_beads[t]; ++k, ++o) {
             hb[o] = make_float4(beads[3 * o], beads[3 * o + 1], beads[3 * o + 2], 0.f);
             double r2 = (double)beads[3 * o] * beads[3 * o] + (double)beads[3 * o + 1] * beads[3 * o + 1] +
                         (double)beads[3 * o + 2] * beads[3 * o + 2];
             if (r2 > r2max) r2max = r2;
+            for (int a = 0; a < 3; ++a) h[a] = fmaxf(h[a], fabsf(beads[3 * o + a]));
         }
         c->rmax[t] = (float)sqrt(r2max);
+        c->dev.t.hx[t] = h[0];
+        c->dev.t.hy[t] = h[1];
+        c->dev.t.hz[t] = h[2];
     }
     c->dev.t.n_types = n_types;
     int rc_ = RB_OK;
@@ -132,7 +148,7 @@ extern "C" int rb_accum_zero(int32_t n, int64_t *acc, void *stream) {
     return RB_OK;
 }
 
-extern "C" int rb_accum_finalize(int32_t n, const int64_t *acc, float *force, float *torque,
+extern "C" int rb_accum_finalize(int32_t n, int64_t *acc, float *force, float *torque,
                                  double *energy_virial, void *stream) {
     RB_REQUIRE(n >= 0 && acc && force && torque, "rb_accum_finalize: bad arguments");
     k_finalize<<<grid_for(n > 0 ? n : 1, 256, 4096), 256, 0, (hipStream_t)stream>>>(

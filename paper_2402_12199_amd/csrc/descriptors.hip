@@ -5,7 +5,8 @@
 // d = R_i^T minimg(x_j - x_i) and q = q_i^* q_j (R(q) = R_i^T R_j), computed
 // in FP64 from the state and stored in FP32 (7 x max_pairs, SoA).  Pairs with
 // |d| < d_min lie outside the network's training domain and are routed to
-// the bead sum; the rest go to the network.
+// the bead sum; pairs with d_min <= |d| < d_max go to the network; pairs
+// beyond d_max (zero switched network energy) go to neither.
 #include "rb_common.hpp"
 
 namespace rb {
@@ -34,7 +35,7 @@ __device__ inline void wave_append(bool take, int value, int32_t *list, int32_t 
 __global__ __launch_bounds__(256) void k_descriptors(int32_t n, const double *__restrict__ x,
                                                      const double *__restrict__ q, double L0, double L1, double L2,
                                                      const int32_t *__restrict__ pi, const int32_t *__restrict__ pj,
-                                                     int32_t maxp, float dmin2, float *__restrict__ desc,
+                                                     int32_t maxp, float dmin2, float dmax2, float *__restrict__ desc,
                                                      int32_t *__restrict__ idx_nn, int32_t *__restrict__ idx_bead,
                                                      int32_t *__restrict__ flags) {
     int count = flags[RB_FLAG_NPAIRS];
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(256) void k_descriptors(int32_t n, const double *__
     for (int base = blockIdx.x * blockDim.x; base < count; base += gridDim.x * blockDim.x) {
         const int p = base + threadIdx.x;
         const bool live = p < count;
-        bool to_nn = false;
+        bool to_nn = false, to_bead = false;
         if (live) {
             const int i = pi[p], j = pj[p];
             double dl[3];
@@ -68,10 +69,12 @@ __global__ __launch_bounds__(256) void k_descriptors(int32_t n, const double *__
             desc[4 * maxp + p] = (float)rx;
             desc[5 * maxp + p] = (float)ry;
             desc[6 * maxp + p] = (float)rz;
-            to_nn = (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) >= (double)dmin2;
+            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            to_nn = r2 >= (double)dmin2 && r2 < (double)dmax2;
+            to_bead = r2 < (double)dmin2;
         }
         wave_append(live && to_nn, p, idx_nn, flags + RB_FLAG_NNN);
-        wave_append(live && !to_nn, p, idx_bead, flags + RB_FLAG_NBEAD);
+        wave_append(live && to_bead, p, idx_bead, flags + RB_FLAG_NBEAD);
     }
 }
 
@@ -81,7 +84,8 @@ using namespace rb;
 
 extern "C" int rb_pair_descriptors(int32_t n, const double *x, const double *q, const double *box,
                                    const int32_t *pair_i, const int32_t *pair_j, int32_t max_pairs, float d_min,
-                                   float *desc, int32_t *idx_nn, int32_t *idx_bead, int32_t *flags, void *stream) {
+                                   float d_max, float *desc, int32_t *idx_nn, int32_t *idx_bead, int32_t *flags,
+                                   void *stream) {
     RB_REQUIRE(x && q && box && pair_i && pair_j && desc && idx_nn && idx_bead && flags,
                "rb_pair_descriptors: null argument");
     RB_REQUIRE(n > 0 && max_pairs > 0, "rb_pair_descriptors: sizes must be > 0");
@@ -89,8 +93,9 @@ extern "C" int rb_pair_descriptors(int32_t n, const double *x, const double *q, 
     hipStream_t st = (hipStream_t)stream;
     k_route_reset<<<1, 1, 0, st>>>(flags);
     const float dm2 = d_min > 0 ? d_min * d_min : 0.f;
+    const float dx2 = d_max > 0 ? d_max * d_max : 3.0e38f;
     k_descriptors<<<grid_for(max_pairs, 256, 4096), 256, 0, st>>>(n, x, q, box[0], box[1], box[2], pair_i, pair_j,
-                                                                  max_pairs, dm2, desc, idx_nn, idx_bead, flags);
+                                                                  max_pairs, dm2, dx2, desc, idx_nn, idx_bead, flags);
     RB_LAUNCH_CHECK("rb_pair_descriptors");
     return RB_OK;
 }

@@ -164,6 +164,119 @@ __global__ __launch_bounds__(kIntThreads) void k_phase2(int32_t n, double dt, do
     }
 }
 
+// Fused step boundary: the forces of step k come from the fixed-point
+// accumulator (converted to FP32 exactly as rb_accum_finalize does, stored,
+// and the accumulator cleared); then the second half kick of step k, the
+// kinetic energy at the full step, and the first half kick, drift and free
+// rotation of step k + 1.  Same arithmetic, in the same order, as
+// rb_accum_finalize + phase 2 + phase 1.
+__global__ __launch_bounds__(kIntThreads) void k_fused(int32_t n, double dt, double *__restrict__ x,
+                                                       double *__restrict__ P, double *__restrict__ q,
+                                                       double *__restrict__ L, const int32_t *__restrict__ type,
+                                                       const double *__restrict__ mass,
+                                                       const double *__restrict__ inertia, int64_t *__restrict__ acc,
+                                                       float *__restrict__ force, float *__restrict__ torque,
+                                                       double *__restrict__ ev, const double *__restrict__ x_ref,
+                                                       double half_skin2, int32_t *__restrict__ flags,
+                                                       double *__restrict__ partial, unsigned *__restrict__ ticket,
+                                                       double *__restrict__ kinetic) {
+    __shared__ double red[2][kIntThreads / kWave];
+    __shared__ bool last;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const double s = 1.0 / RB_ACC_SCALE;
+    double kt = 0, kr = 0;
+    bool moved = false;
+    if (i < n) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            force[a * n + i] = (float)((double)acc[a * (int64_t)n + i] * s);
+            torque[a * n + i] = (float)((double)acc[(3 + a) * (int64_t)n + i] * s);
+            acc[a * (int64_t)n + i] = 0;
+            acc[(3 + a) * (int64_t)n + i] = 0;
+        }
+        const int t = type[i];
+        double qi[4] = {q[i], q[n + i], q[2 * n + i], q[3 * n + i]};
+        double Pi[3] = {P[i], P[n + i], P[2 * n + i]};
+        double Li[3] = {L[i], L[n + i], L[2 * n + i]};
+        kick(dt, qi, Pi, Li, force, torque, n, i);
+        const double m = mass[t];
+        const double I[3] = {inertia[3 * t], inertia[3 * t + 1], inertia[3 * t + 2]};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            kt += Pi[a] * Pi[a] / (2.0 * m);
+            kr += Li[a] * Li[a] / (2.0 * I[a]);
+        }
+        // next step: half kick, drift, free rotation
+        kick(dt, qi, Pi, Li, force, torque, n, i);
+        const double im = 1.0 / m;
+        double d2 = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double xn = x[a * n + i] + dt * Pi[a] * im;
+            x[a * n + i] = xn;
+            if (x_ref) {
+                const double dd = xn - x_ref[a * n + i];
+                d2 += dd * dd;
+            }
+        }
+        moved = x_ref && d2 > half_skin2;
+        free_sub(2, 0.5 * dt, I[2], qi, Li);
+        free_sub(1, 0.5 * dt, I[1], qi, Li);
+        free_sub(0, dt, I[0], qi, Li);
+        free_sub(1, 0.5 * dt, I[1], qi, Li);
+        free_sub(2, 0.5 * dt, I[2], qi, Li);
+        const double inv = 1.0 / sqrt(qi[0] * qi[0] + qi[1] * qi[1] + qi[2] * qi[2] + qi[3] * qi[3]);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) q[a * n + i] = qi[a] * inv;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            P[a * n + i] = Pi[a];
+            L[a * n + i] = Li[a];
+        }
+    }
+    if (__any(moved) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(flags + RB_FLAG_REBUILD, 1);
+    if (blockIdx.x == 0 && threadIdx.x < 10) {
+        int64_t *g = acc + 6 * (int64_t)n + threadIdx.x * RB_ACC_SLOTS;
+        long long tsum = 0;
+        for (int k = 0; k < RB_ACC_SLOTS; ++k) {
+            tsum += g[k];
+            g[k] = 0;
+        }
+        if (ev) ev[threadIdx.x] = (double)tsum * s;
+    }
+    kt = wave_sum(kt);
+    kr = wave_sum(kr);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][w] = kt;
+        red[1][w] = kr;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0, b = 0;
+        for (int k = 0; k < kIntThreads / kWave; ++k) {
+            a += red[0][k];
+            b += red[1][k];
+        }
+        partial[2 * blockIdx.x] = a;
+        partial[2 * blockIdx.x + 1] = b;
+        __threadfence();
+        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        double a = 0, b = 0;
+        for (int k = 0; k < (int)gridDim.x; ++k) {
+            a += __hip_atomic_load(partial + 2 * k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            b += __hip_atomic_load(partial + 2 * k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        kinetic[0] = a;
+        kinetic[1] = b;
+        *ticket = 0u;
+    }
+}
+
 static size_t nblocks(int32_t n) { return (size_t)((n + kIntThreads - 1) / kIntThreads); }
 
 }  // namespace rb
@@ -199,5 +312,23 @@ extern "C" int rb_rigid_step(const rb_ctx *ctx, int phase, int32_t n, double dt,
                                                partial, ticket, kinetic);
     }
     RB_LAUNCH_CHECK("rb_rigid_step");
+    return RB_OK;
+}
+
+extern "C" int rb_rigid_step_fused(const rb_ctx *ctx, int32_t n, double dt, double *x, double *P, double *q,
+                                   double *L, const int32_t *type, int64_t *acc, float *force, float *torque,
+                                   double *energy_virial, const double *x_ref, double half_skin, double *kinetic,
+                                   int32_t *flags, void *ws, size_t ws_bytes, void *stream) {
+    RB_REQUIRE(ctx && x && P && q && L && type && acc && force && torque && kinetic && flags && ws,
+               "rb_rigid_step_fused: null argument");
+    RB_REQUIRE(n > 0, "rb_rigid_step_fused: n must be > 0");
+    RB_REQUIRE(ws_bytes >= rb_rigid_workspace_bytes(n), "rb_rigid_step_fused: workspace too small");
+    char *w = static_cast<char *>(ws);
+    double *partial = reinterpret_cast<double *>(w);
+    unsigned *ticket = reinterpret_cast<unsigned *>(w + rb_rigid_workspace_bytes(n) - 256);
+    k_fused<<<(int)nblocks(n), kIntThreads, 0, (hipStream_t)stream>>>(
+        n, dt, x, P, q, L, type, ctx->dev.mass, ctx->dev.inertia, acc, force, torque, energy_virial, x_ref,
+        half_skin * half_skin, flags, partial, ticket, kinetic);
+    RB_LAUNCH_CHECK("rb_rigid_step_fused");
     return RB_OK;
 }

@@ -149,6 +149,7 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
         }
     }
     if (MODE == kForces) {
+        long long part[11];
 #pragma unroll
         for (int k = 0; k < 10; ++k) {
             long long v = eacc[k];
@@ -156,9 +157,10 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
             v += __shfl_xor(v, 2, kWave);
             v += __shfl_xor(v, 4, kWave);
             v += __shfl_xor(v, 8, kWave);
-            if (lane == 0 && v) atomicAdd(reinterpret_cast<unsigned long long *>(a.acc + 6 * (int64_t)a.n + k),
-                                          (unsigned long long)v);
+            part[k] = v;
         }
+        part[10] = 0;
+        block_flush_globals<kWaves>(part, a.acc + 6 * (int64_t)a.n, nullptr);
         if (__any(bad) && lane == 0) atomicOr(a.flags + RB_FLAG_NONFINITE, 1);
     }
 }
@@ -166,10 +168,13 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
 // Compute units of the current device (one persistent block per CU: the
 // BF16 weight image fills most of a CU's LDS).
 static int device_cus() {
+    static int cached = 0;
+    if (cached > 0) return cached;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
         cus = 256;
+    cached = cus;
     return cus;
 }
 

@@ -69,6 +69,13 @@ __device__ inline void silu(float z, float &h, float &dh) {
     dh = fmaf(h, 1.f - s, s);
 }
 
+__device__ inline bf16x8 pack8(const float a[4], const float b[4]) {
+    bf16x8 v;
+    v[0] = (__bf16)a[0]; v[1] = (__bf16)a[1]; v[2] = (__bf16)a[2]; v[3] = (__bf16)a[3];
+    v[4] = (__bf16)b[0]; v[5] = (__bf16)b[1]; v[6] = (__bf16)b[2]; v[7] = (__bf16)b[3];
+    return v;
+}
+
 // LDS image of the weights used by the BF16 kernels.
 struct LdsBF16 {
     __bf16 w[3][kH][kRow];   // W2..W4, columns permuted per 32-block
@@ -79,10 +86,16 @@ struct LdsBF16 {
 };
 
 __device__ inline void stage_bf16(LdsBF16 &L, const float *__restrict__ p) {
-    for (int idx = threadIdx.x; idx < 3 * kH * kH; idx += blockDim.x) {
-        const int l = idx / (kH * kH), o = (idx / kH) % kH, c = idx % kH;
-        const int in = 32 * (c >> 5) + perm32(c & 31);
-        L.w[l][o][c] = (__bf16)p[w_off(l + 2) + o * kH + in];
+    // One 16-byte LDS store per work item: columns 32 cb + 8 g .. + 7 of row
+    // o hold the input features 32 cb + perm32(8 g + i), i.e. two runs of four
+    // consecutive features (32 cb + 4 g and 32 cb + 16 + 4 g).
+    for (int idx = threadIdx.x; idx < 3 * kH * 16; idx += blockDim.x) {
+        const int l = idx / (kH * 16), o = (idx / 16) % kH, u = idx % 16, cb = u >> 2, g = u & 3;
+        const float *row = p + w_off(l + 2) + o * kH + 32 * cb + 4 * g;
+        const float4 a = *reinterpret_cast<const float4 *>(row);
+        const float4 b = *reinterpret_cast<const float4 *>(row + 16);
+        const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+        *reinterpret_cast<bf16x8 *>(&L.w[l][o][32 * cb + 8 * g]) = pack8(av, bv);
     }
     for (int idx = threadIdx.x; idx < kH * 8; idx += blockDim.x) {
         const int o = idx >> 3, k = idx & 7;
@@ -114,12 +127,6 @@ __device__ inline void layer1(const float (*w1)[8], const float *b1, const float
     }
 }
 
-__device__ inline bf16x8 pack8(const float a[4], const float b[4]) {
-    bf16x8 v;
-    v[0] = (__bf16)a[0]; v[1] = (__bf16)a[1]; v[2] = (__bf16)a[2]; v[3] = (__bf16)a[3];
-    v[4] = (__bf16)b[0]; v[5] = (__bf16)b[1]; v[6] = (__bf16)b[2]; v[7] = (__bf16)b[3];
-    return v;
-}
 
 // FP16 packing of the SiLU derivatives kept for the reverse pass (values in
 // [-0.1, 1.1]; FP16 keeps 11 significant bits against BF16's 8).

@@ -234,6 +234,151 @@ __global__ void k_finish(int32_t *flags, int mode) {
     flags[RB_FLAG_NREBUILDS] += 1;
 }
 
+// ---------------------------------------------------------------- one block
+// For up to kSmallBodies bodies the whole rebuild runs in one workgroup with
+// barriers between the phases: a single launch per step, which returns at
+// once when no rebuild is flagged.
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallBodies = 65536;
+constexpr int kSmallCells = 262144;
+
+// Exclusive scan of in[0..m) into out[0..m) by one block; returns the total
+// (all threads).
+__device__ int block_scan(const int32_t *in, int32_t *out, int m) {
+    __shared__ int32_t wsum[kSmallThreads / kWave];
+    __shared__ int32_t carry_s;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    for (int base = 0; base < m; base += kSmallThreads) {
+        const int i = base + threadIdx.x;
+        const int v = i < m ? in[i] : 0;
+        int incl = v;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int t = __shfl_up(incl, o, kWave);
+            if (lane >= o) incl += t;
+        }
+        if (lane == kWave - 1) wsum[w] = incl;
+        __syncthreads();
+        int woff = 0, total = 0;
+        for (int k = 0; k < kSmallThreads / kWave; ++k) {
+            if (k < w) woff += wsum[k];
+            total += wsum[k];
+        }
+        const int carry = carry_s;
+        if (i < m) out[i] = carry + woff + incl - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry_s = carry + total;
+        __syncthreads();
+    }
+    return carry_s;
+}
+
+template <bool EMIT>
+__device__ inline int neigh_scan(int i, int32_t n, const double *__restrict__ x, const CellGrid &g,
+                                 const int32_t *__restrict__ cell_of, const int32_t *__restrict__ start,
+                                 const int32_t *__restrict__ sorted, int out, int32_t *__restrict__ pi,
+                                 int32_t *__restrict__ pj, int32_t cap) {
+    const double xi = x[i], yi = x[n + i], zi = x[2 * n + i];
+    const int id = cell_of[i];
+    const int cz = id % g.nc[2], cy = (id / g.nc[2]) % g.nc[1], cx = id / (g.nc[2] * g.nc[1]);
+    int lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = g.nc[a] >= 3 ? -1 : 0;
+        hi[a] = g.nc[a] >= 3 ? 1 : g.nc[a] - 1;
+    }
+    int cnt = 0;
+    for (int ox = lo[0]; ox <= hi[0]; ++ox) {
+        int nx = cx + ox;
+        nx += nx < 0 ? g.nc[0] : (nx >= g.nc[0] ? -g.nc[0] : 0);
+        for (int oy = lo[1]; oy <= hi[1]; ++oy) {
+            int ny = cy + oy;
+            ny += ny < 0 ? g.nc[1] : (ny >= g.nc[1] ? -g.nc[1] : 0);
+            for (int oz = lo[2]; oz <= hi[2]; ++oz) {
+                int nz = cz + oz;
+                nz += nz < 0 ? g.nc[2] : (nz >= g.nc[2] ? -g.nc[2] : 0);
+                const int c = (nx * g.nc[1] + ny) * g.nc[2] + nz;
+                for (int m = start[c], e = start[c + 1]; m < e; ++m) {
+                    const int j = sorted[m];
+                    if (j <= i) continue;
+                    const double dx = min_image(x[j] - xi, g.L[0], g.inv[0]);
+                    const double dy = min_image(x[n + j] - yi, g.L[1], g.inv[1]);
+                    const double dz = min_image(x[2 * n + j] - zi, g.L[2], g.inv[2]);
+                    if (dx * dx + dy * dy + dz * dz < g.rl2) {
+                        if (EMIT && out + cnt < cap) {
+                            pi[out + cnt] = i;
+                            pj[out + cnt] = j;
+                        }
+                        ++cnt;
+                    }
+                }
+            }
+        }
+    }
+    return cnt;
+}
+
+__global__ __launch_bounds__(kSmallThreads) void k_pairlist_small(
+    int32_t n, const double *__restrict__ x, CellGrid g, int32_t *__restrict__ cell_of, int32_t *__restrict__ cnt,
+    int32_t *__restrict__ start, int32_t *__restrict__ fill, int32_t *__restrict__ sorted,
+    int32_t *__restrict__ ncount, int32_t *__restrict__ noff, int32_t *__restrict__ pi, int32_t *__restrict__ pj,
+    int32_t cap, double *__restrict__ x_ref, int32_t *__restrict__ flags, int mode) {
+    if (skip(flags, mode)) return;
+    const int t = threadIdx.x, T = kSmallThreads;
+    for (int c = t; c < g.ncell; c += T) {
+        cnt[c] = 0;
+        fill[c] = 0;
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += T) {
+        int c[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double v = x[a * n + i];
+            if (x_ref) x_ref[a * n + i] = v;
+            c[a] = cell_coord(v, g.L[a], g.cinv[a], g.nc[a]);
+        }
+        const int id = (c[0] * g.nc[1] + c[1]) * g.nc[2] + c[2];
+        cell_of[i] = id;
+        atomicAdd(cnt + id, 1);
+    }
+    __syncthreads();
+    const int total_cells = block_scan(cnt, start, g.ncell);
+    if (t == 0) start[g.ncell] = total_cells;
+    __syncthreads();
+    for (int i = t; i < n; i += T) {
+        const int c = cell_of[i];
+        sorted[start[c] + atomicAdd(fill + c, 1)] = i;
+    }
+    __syncthreads();
+    for (int c = t; c < g.ncell; c += T) {
+        const int b = start[c], e = start[c + 1];
+        for (int k = b + 1; k < e; ++k) {
+            const int v = sorted[k];
+            int m = k - 1;
+            while (m >= b && sorted[m] > v) {
+                sorted[m + 1] = sorted[m];
+                --m;
+            }
+            sorted[m + 1] = v;
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += T) ncount[i] = neigh_scan<false>(i, n, x, g, cell_of, start, sorted, 0, pi, pj, cap);
+    __syncthreads();
+    const int total = block_scan(ncount, noff, n);
+    __syncthreads();
+    for (int i = t; i < n; i += T) (void)neigh_scan<true>(i, n, x, g, cell_of, start, sorted, noff[i], pi, pj, cap);
+    if (t == 0) {
+        flags[RB_FLAG_NPAIRS] = total < cap ? total : cap;
+        flags[RB_FLAG_OVERFLOW] = total > cap ? total : 0;
+        flags[RB_FLAG_REBUILD] = 0;
+        flags[RB_FLAG_NREBUILDS] += 1;
+    }
+}
+
 struct PLLayout {
     size_t cell_of, cnt, start, fill, sorted, ncount, noff, tmp, total;
 };
@@ -312,6 +457,12 @@ extern "C" int rb_pairlist_build(int32_t n, const double *x, const double *box, 
             *sorted = (int32_t *)(w + L.sorted), *ncount = (int32_t *)(w + L.ncount),
             *noff = (int32_t *)(w + L.noff), *tmp = (int32_t *)(w + L.tmp);
     hipStream_t st = (hipStream_t)stream;
+    if (n <= kSmallBodies && g.ncell <= kSmallCells) {
+        k_pairlist_small<<<1, kSmallThreads, 0, st>>>(n, x, g, cell_of, cnt, start, fill, sorted, ncount, noff, pair_i,
+                                                      pair_j, max_pairs, x_ref, flags, mode);
+        RB_LAUNCH_CHECK("rb_pairlist_build");
+        return RB_OK;
+    }
     const int gb = (n + 255) / 256, gc = (g.ncell + 255) / 256;
     k_fill<<<gc, 256, 0, st>>>(cnt, g.ncell, 0, flags, mode);
     k_fill<<<gc, 256, 0, st>>>(fill, g.ncell, 0, flags, mode);

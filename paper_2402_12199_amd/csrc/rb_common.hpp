@@ -34,6 +34,7 @@ struct Templates {
     const float4 *beads;       // all types concatenated, w unused
     int n[kMaxTypes];
     int off[kMaxTypes];
+    float hx[kMaxTypes], hy[kMaxTypes], hz[kMaxTypes];   // half extents of the bead-centre box
     int n_types;
 };
 
@@ -54,6 +55,33 @@ __device__ inline long long to_fixed(double v) { return __double2ll_rn(v * RB_AC
 __device__ inline void acc_add(int64_t *a, double v) {
     atomicAdd(reinterpret_cast<unsigned long long *>(a),
               static_cast<unsigned long long>(to_fixed(v)));
+}
+
+// Block-level sum of per-wave global partials (E, virial, tests: 11 int64)
+// followed by one atomic per quantity into this block's slot of the
+// accumulator, so few atomics hit the same address.  Every thread of the
+// block must call it; `part` is meaningful in each wave's lane 0.
+template <int NWAVES>
+__device__ inline void block_flush_globals(const long long part[11], int64_t *acc_globals, int32_t *flags) {
+    __shared__ long long red[NWAVES][11];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int a = 0; a < 11; ++a) red[w][a] = part[a];
+    __syncthreads();
+    if (threadIdx.x < 11) {
+        long long s = 0;
+#pragma unroll
+        for (int k = 0; k < NWAVES; ++k) s += red[k][threadIdx.x];
+        if (s) {
+            if (threadIdx.x < 10)
+                atomicAdd(reinterpret_cast<unsigned long long *>(acc_globals + threadIdx.x * RB_ACC_SLOTS +
+                                                                 blockIdx.x % RB_ACC_SLOTS),
+                          (unsigned long long)s);
+            else if (flags)
+                atomicAdd(reinterpret_cast<unsigned long long *>(flags + RB_FLAG_NTESTS), (unsigned long long)s);
+        }
+    }
 }
 
 // ------------------------------------------------------------- quaternions

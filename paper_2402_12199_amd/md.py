@@ -3,7 +3,8 @@
 Bead path step (velocity Verlet):
   rigid_step phase 1 (half kick, drift, free rotation, skin test)
   pairlist_build (only when the skin test flagged a rebuild)
-  accum_zero -> bead_pair_forces over every listed pair -> accum_finalize
+  bead_pair_forces over every listed pair -> accum_finalize (which also
+  clears the accumulator for the next step)
   rigid_step phase 2 (second half kick, kinetic energy)
 Network path step: the same, except that after the pair list
   pair_descriptors routes each pair to the network (|d| >= d_min) or to the
@@ -63,6 +64,7 @@ class RigidSystem:
         self.pair_i = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
         self.pair_j = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
         self.acc = torch.zeros(abi.acc_len(n), dtype=torch.int64, device=self.dev)
+        abi.rb_accum_zero(n, self.acc)
         self.force = torch.zeros((3, n), dtype=torch.float32, device=self.dev)
         self.torque = torch.zeros((3, n), dtype=torch.float32, device=self.dev)
         self.ev = torch.zeros(10, dtype=torch.float64, device=self.dev)
@@ -85,14 +87,16 @@ class RigidSystem:
         self.idx_bead = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
 
     def compute_forces(self, path="bead"):
-        abi.rb_accum_zero(self.n, self.acc)
+        # the accumulator is clear: zeroed at construction, cleared again by
+        # every rb_accum_finalize
         if path == "bead":
             abi.rb_bead_pair_forces(self.ctx, self.x, self.q, self.types, self.box, self.pair_i, self.pair_j,
                                     None, self.flags[abi.RB_FLAG_NPAIRS:], self.max_pairs, self.acc, self.flags)
         elif path == "nn":
             m = self.nn
             abi.rb_pair_descriptors(self.x, self.q, self.box, self.pair_i, self.pair_j, m.d_min, self.desc,
-                                    self.idx_nn, self.idx_bead, self.flags)
+                                    self.idx_nn, self.idx_bead, self.flags,
+                                    d_max=m.sw_hi if m.sw_hi > m.sw_lo else 0.0)
             abi.rb_nn_pair_forces(m.params, m.norm, m.precision, self.q, self.pair_i, self.pair_j, self.desc,
                                   self.idx_nn, self.flags[abi.RB_FLAG_NNN:], self.max_pairs, m.sw_lo, m.sw_hi,
                                   self.acc, self.flags)
@@ -114,6 +118,66 @@ class RigidSystem:
         self.compute_forces(path)
         abi.rb_rigid_step(self.ctx, 2, dt, None, self.P, self.q, self.L, self.types, self.force, self.torque,
                           None, 0.0, self.kinetic, None, self.ws_rig)
+
+    # ------------------------------------------------------------ fused loop
+    def _forces_to_acc(self, path):
+        if path == "bead":
+            abi.rb_bead_pair_forces(self.ctx, self.x, self.q, self.types, self.box, self.pair_i, self.pair_j,
+                                    None, self.flags[abi.RB_FLAG_NPAIRS:], self.max_pairs, self.acc, self.flags)
+        else:
+            m = self.nn
+            abi.rb_pair_descriptors(self.x, self.q, self.box, self.pair_i, self.pair_j, m.d_min, self.desc,
+                                    self.idx_nn, self.idx_bead, self.flags,
+                                    d_max=m.sw_hi if m.sw_hi > m.sw_lo else 0.0)
+            abi.rb_nn_pair_forces(m.params, m.norm, m.precision, self.q, self.pair_i, self.pair_j, self.desc,
+                                  self.idx_nn, self.flags[abi.RB_FLAG_NNN:], self.max_pairs, m.sw_lo, m.sw_hi,
+                                  self.acc, self.flags)
+            abi.rb_bead_pair_forces(self.ctx, self.x, self.q, self.types, self.box, self.pair_i, self.pair_j,
+                                    self.idx_bead, self.flags[abi.RB_FLAG_NBEAD:], self.max_pairs, self.acc,
+                                    self.flags)
+
+    def begin_fused(self, dt):
+        """Phase 1 of the first step of a fused run (forces must be current)."""
+        abi.rb_rigid_step(self.ctx, 1, dt, self.x, self.P, self.q, self.L, self.types, self.force, self.torque,
+                          self.x_ref, self.half_skin, None, self.flags, None)
+
+    def fused_step(self, dt, path="bead"):
+        """Pair list, forces into the accumulator, then one launch for the end
+        of this step and the start of the next (see rb_rigid_step_fused)."""
+        self.build_pairs(always=False)
+        self._forces_to_acc(path)
+        abi.rb_rigid_step_fused(self.ctx, dt, self.x, self.P, self.q, self.L, self.types, self.acc, self.force,
+                                self.torque, self.ev, self.x_ref, self.half_skin, self.kinetic, self.flags,
+                                self.ws_rig)
+
+    def end_fused(self, dt, path="bead"):
+        """Last step of a fused run: forces, finalize, phase 2."""
+        self.build_pairs(always=False)
+        self.compute_forces(path)
+        abi.rb_rigid_step(self.ctx, 2, dt, None, self.P, self.q, self.L, self.types, self.force, self.torque,
+                          None, 0.0, self.kinetic, None, self.ws_rig)
+
+    # ------------------------------------------------------------ graphs
+    def capture(self, dt, path="bead", steps=1, fused=False):
+        """Record `steps` MD steps into a HIP graph (torch.cuda.CUDAGraph).
+
+        Every step only enqueues kernels whose sizes are fixed at capture and
+        whose data-dependent extents (pair counts, rebuild flag) are read on
+        the device, so replaying the graph performs the same work as calling
+        `step` that many times.  Capturing does not execute the steps.
+        """
+        # one eager call first so lazily cached host values exist before capture
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            for _ in range(steps):
+                if fused:
+                    self.fused_step(dt, path)
+                else:
+                    self.step(dt, path)
+        torch.cuda.current_stream().wait_stream(side)
+        return g
 
     # ------------------------------------------------------------ readback
     def flags_host(self) -> np.ndarray:

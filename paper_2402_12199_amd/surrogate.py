@@ -1,0 +1,132 @@
+"""Surrogate pair energy: data from the bead path, training, held-out errors.
+
+Paper section 2: the network is trained on pair configurations whose
+energies, forces and torques come from the composite-bead method.  Here the
+configurations are synthetic (uniform direction, uniform distance in
+[d_lo, d_hi], uniform relative orientation), labelled on the GPU by the bead
+kernel (rb_bead_pair_eval), and configurations whose closest bead pair is
+below r_rej are rejected (deep overlaps, absent from dynamics at the
+workloads' temperature).  Training runs rb_nn_train_step (BF16 MFMA, FP32
+master weights, Adam) on the energy.  Errors are reported on a held-out set
+from another seed: energy, force and torque RMSE, and the fraction of
+force components outside a +-10 % band of the bead value (the paper's parity
+statistic, section 3).
+
+python -m paper_2402_12199_amd.surrogate --shape cyl134 --epochs 200
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import abi
+from .nn import Trainer, label_pairs, make_norm
+
+
+def make_dataset(ctx: abi.Ctx, n: int, seed: int, d_lo: float, d_hi: float, r_rej: float = 0.8,
+                 type_i: int = 0, type_j: int = 0):
+    """n accepted configurations (desc (n, 7) FP32, labels (n, 11) FP32) and
+    the rejection rate."""
+    from synth import sampling
+    g = sampling.rng(seed)
+    descs, labs = [], []
+    have = drawn = 0
+    while have < n:
+        m = int((n - have) * 1.5) + 1024
+        d = sampling.pair_batch(g, m, d_lo, d_hi).astype(np.float32)
+        lab = label_pairs(ctx, d, type_i, type_j)
+        keep = lab[:, 10] >= r_rej
+        drawn += m
+        descs.append(d[keep])
+        labs.append(lab[keep])
+        have += int(keep.sum())
+    desc = np.concatenate(descs)[:n]
+    lab = np.concatenate(labs)[:n]
+    return desc, lab, 1.0 - have / drawn
+
+
+def evaluate(params, norm, precision, desc: np.ndarray, lab: np.ndarray, chunk: int = 1 << 20) -> dict:
+    """Held-out errors of the network against bead labels (body i frame)."""
+    P = len(desc)
+    E = np.empty(P, np.float32)
+    ft = np.empty((P, 9), np.float32)
+    for s in range(0, P, chunk):
+        d = torch.tensor(np.ascontiguousarray(desc[s:s + chunk].T), device="cuda")
+        e = torch.empty(d.shape[1], device="cuda")
+        f = torch.empty((9, d.shape[1]), device="cuda")
+        abi.rb_nn_pair_grad(params, norm, precision, d, None, e, None, f)
+        E[s:s + chunk] = e.cpu().numpy()
+        ft[s:s + chunk] = f.cpu().numpy().T
+    ref_e, ref_ft = lab[:, 0].astype(np.float64), lab[:, 1:10].astype(np.float64)
+    rmse = lambda a, b: float(np.sqrt(np.mean((np.asarray(a, np.float64) - b) ** 2)))
+    fx, rfx = ft[:, 0].astype(np.float64), ref_ft[:, 0]
+    sig = np.abs(rfx) > 1e-3
+    outside = float(np.mean(np.abs(fx[sig] - rfx[sig]) > 0.1 * np.abs(rfx[sig]))) if sig.any() else float("nan")
+    return {
+        "n": int(P),
+        "rmse_E": rmse(E, ref_e), "std_E": float(ref_e.std()),
+        "rmse_F": rmse(ft[:, :3], ref_ft[:, :3]), "std_F": float(ref_ft[:, :3].std()),
+        "rmse_tau_i": rmse(ft[:, 3:6], ref_ft[:, 3:6]), "std_tau_i": float(ref_ft[:, 3:6].std()),
+        "rmse_tau_j": rmse(ft[:, 6:9], ref_ft[:, 6:9]), "std_tau_j": float(ref_ft[:, 6:9].std()),
+        "frac_fx_outside_10pct": outside,
+    }
+
+
+def train_surrogate(body, n_train: int, n_test: int, epochs: int, seed: int = 1004, test_seed: int = 2004,
+                    batch: int = 8192, lr: float = 1e-3, precision: int = abi.RB_PREC_BF16, r_rej: float = 0.8,
+                    rc: float = 2.5, sigma: float = 1.0, init_seed: int = 1003, log=None) -> dict:
+    """Label, train and evaluate a surrogate for pairs of one body type."""
+    from synth import sampling
+    t0 = time.perf_counter()
+    ctx = abi.Ctx([body.beads], [body.mass], [body.inertia])
+    d_min = 2.0 * body.r_in + sigma
+    d_cut = 2.0 * body.r_max + rc
+    desc, lab, rej = make_dataset(ctx, n_train, seed, d_min, d_cut, r_rej)
+    tdesc, tlab, _ = make_dataset(ctx, n_test, test_seed, d_min, d_cut, r_rej)
+    t_label = time.perf_counter() - t0
+    e = lab[:, 0].astype(np.float64)
+    norm = make_norm(d_cut, float(e.mean()), float(e.std()))
+    tr = Trainer(sampling.xavier_params(init_seed), norm, precision=precision, batch=batch, lr=lr)
+    d_dev = torch.tensor(np.ascontiguousarray(desc.T), device="cuda")
+    y_dev = torch.tensor(lab[:, 0].copy(), device="cuda")
+    g = sampling.rng(seed + 7)
+    before = evaluate(tr.params, norm, precision, tdesc, tlab)
+    hist = []
+    t1 = time.perf_counter()
+    for ep in range(epochs):
+        hist.append(tr.epoch(d_dev, y_dev, g))
+        if log and (ep % max(1, epochs // 10) == 0 or ep == epochs - 1):
+            log(f"[surrogate {body.name}] epoch {ep + 1}/{epochs} loss {hist[-1]:.4f}")
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    after = evaluate(tr.params, norm, precision, tdesc, tlab)
+    return dict(shape=body.name, params=tr.params, norm=norm, precision=precision, d_min=d_min, d_cut=d_cut,
+                epochs=epochs, steps=tr.t, batch=batch, n_train=n_train, n_test=n_test, reject_rate=rej,
+                label_s=t_label, train_s=t_train, samples_per_s=tr.t * batch / max(t_train, 1e-9),
+                loss_history=hist, untrained=before, trained=after)
+
+
+def main():
+    from synth import configs
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--shape", default="cyl134", choices=["cyl134", "cube6", "cube5"])
+    ap.add_argument("--epochs", type=int, default=200)
+    ap.add_argument("--n-train", type=int, default=1 << 21)
+    ap.add_argument("--n-test", type=int, default=1 << 16)
+    ap.add_argument("--out", default=None, help="write params/norm to this .npz")
+    a = ap.parse_args()
+    body = getattr(configs, a.shape)()
+    r = train_surrogate(body, a.n_train, a.n_test, a.epochs, log=lambda m: print(m, file=sys.stderr, flush=True))
+    if a.out:
+        np.savez(a.out, params=r["params"].cpu().numpy(), norm=r["norm"], d_min=r["d_min"], d_cut=r["d_cut"])
+    r = {k: v for k, v in r.items() if k not in ("params", "norm")}
+    print(json.dumps(r))
+
+
+if __name__ == "__main__":
+    main()

@@ -185,7 +185,7 @@ def test_md_forces_nn_plus_bead_fallback_match_oracle(abi, prec):
             F[j] += o["Fj"]
             T[i] += o["taui"]
             T[j] += o["tauj"]
-    assert f[abi.RB_FLAG_NNN] == nnm.sum()
+    assert f[abi.RB_FLAG_NNN] == (nnm & (r < sw_hi)).sum()
     etol, gtol = RTOL[prec]
     assert sysm.energy() == pytest.approx(E, rel=max(etol, 1e-5))
     assert_close(sysm.force.cpu().numpy().T, F, max(gtol, 1e-4), "force")

@@ -192,7 +192,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-nn", action="store_true", help="skip the network measurements")
-    ap.add_argument("--nn-epochs", type=int, default=40, help="surrogate training epochs (2^20 pairs each)")
+    ap.add_argument("--nn-steps", type=int, default=100,
+                    help="timed steps of the network path (its trajectory stays sound for a limited time)")
+    ap.add_argument("--nn-epochs", type=int, default=100, help="surrogate training epochs (2^20 pairs each)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the path is single-GPU; --gpus {args.gpus} is not supported)",
@@ -256,32 +258,63 @@ def main():
 
     if not args.no_nn:
         # network path on the same system, with a cube-6 surrogate trained
-        # here on bead-labelled pairs (its held-out errors are reported)
-        from paper_2402_12199_amd.surrogate import train_surrogate
+        # here on pairs visited by the bead dynamics from the same start,
+        # labelled by the bead kernel (its held-out errors are reported)
+        from paper_2402_12199_amd.surrogate import train_surrogate_md
         log(f"[bench] training a {cfg.body.name} surrogate ({args.nn_epochs} epochs)")
-        sur = train_surrogate(cfg.body, 1 << 20, 1 << 16, args.nn_epochs, log=log)
+        sur = train_surrogate_md(cfg, st, 1 << 20, 1 << 16, args.nn_epochs, log=log)
+        log(f"[bench] surrogate: label {sur['label_s']:.1f} s, train {sur['train_s']:.1f} s, "
+            f"held-out E rmse {sur['trained']['rmse_E']:.3f} (std {sur['trained']['std_E']:.3f})")
+        summary = {k: sur[k] for k in ("shape", "sampling", "epochs", "steps", "batch", "n_train", "n_test",
+                                       "label_s", "train_s", "samples_per_s", "d_min", "d_cut")}
+        summary["held_out"] = sur["trained"]
+        summary["loss_first_last"] = [sur["loss_history"][0], sur["loss_history"][-1]]
         log("[bench] network path on the same system")
         st2 = state.initial_state(cfg)
         sysn = make_system(cfg, st2, torch)
         sysn.set_nn(NNModel(params=sur["params"], norm=sur["norm"], precision=abi.RB_PREC_BF16,
                             d_min=cfg.d_min, sw_lo=cfg.d_cut - 1.0, sw_hi=cfg.d_cut))
         sysn.init_forces("nn")
-        nnr = run_md(sysn, args.steps, args.warmup, cfg.dt, "nn", torch, abi)
-        kin_n = sysn.kinetic_host()
-        result["nn_path"] = {
-            "pairs_per_s": nnr["pairs_evaluated"] / nnr["wall_s"],
-            "md_steps_per_s": nnr["steps"] / nnr["wall_s"],
-            "ms_per_step": 1e3 * nnr["wall_s"] / nnr["steps"],
-            "eager_ms_per_step": nnr["eager_ms_per_step"],
-            "pairs_nn": nnr["n_nn"], "pairs_bead_fallback": nnr["n_bead"],
-            "speedup_steps_vs_bead": (nnr["steps"] / nnr["wall_s"]) / steps_per_s,
-            "total_energy_end": sysn.energy() + float(kin_n.sum()),
-            "surrogate": {k: sur[k] for k in ("shape", "epochs", "steps", "batch", "n_train", "n_test",
-                                              "reject_rate", "label_s", "train_s", "samples_per_s", "d_min",
-                                              "d_cut")} | {"held_out": sur["trained"],
-                                                           "loss_first_last": [sur["loss_history"][0],
-                                                                               sur["loss_history"][-1]]},
-        }
+        ke0 = float((st2["P"] ** 2).sum() / (2 * cfg.body.mass) + (st2["L"] ** 2 / (2 * cfg.body.inertia)).sum())
+        e_nn0 = sysn.energy() + ke0
+        nn_steps = min(args.steps, args.nn_steps)
+        nn_warm = min(args.warmup, 20)
+        try:
+            nnr = run_md(sysn, nn_steps, nn_warm, cfg.dt, "nn", torch, abi)
+        except RuntimeError as e:       # a surrogate that lets bodies overlap
+            result["nn_path"] = {"error": str(e), "surrogate": summary}
+        else:
+            kin_n = sysn.kinetic_host()
+            e_end = sysn.energy() + float(kin_n.sum())
+            # how long the surrogate trajectory stays sound: continue eagerly
+            # to the bead run's length, checking the routing and the finite flag
+            done = nn_warm + nnr["steps"] + GRAPH_STEPS * 6
+            horizon, first_fallback = None, None
+            while done < args.warmup + args.steps:
+                for _ in range(50):
+                    sysn.step(cfg.dt, "nn")
+                done += 50
+                f = sysn.flags_host()
+                if first_fallback is None and f[abi.RB_FLAG_NBEAD] > 0:
+                    first_fallback = done
+                if f[abi.RB_FLAG_NONFINITE]:
+                    horizon = done
+                    break
+            result["nn_path"] = {
+                "pairs_per_s": nnr["pairs_evaluated"] / nnr["wall_s"],
+                "md_steps_per_s": nnr["steps"] / nnr["wall_s"],
+                "ms_per_step": 1e3 * nnr["wall_s"] / nnr["steps"],
+                "timed_steps": nnr["steps"], "warmup": nn_warm,
+                "eager_ms_per_step": nnr["eager_ms_per_step"],
+                "pairs_nn": nnr["n_nn"], "pairs_bead_fallback": nnr["n_bead"],
+                "speedup_steps_vs_bead": (nnr["steps"] / nnr["wall_s"]) / steps_per_s,
+                "speedup_pairs_vs_bead": (nnr["pairs_evaluated"] / nnr["wall_s"]) / value,
+                "total_energy_start_end_of_timed": [e_nn0, e_end],
+                "first_bead_fallback_step": first_fallback,
+                "nonfinite_at_step": horizon,
+                "steps_checked": done,
+                "surrogate": summary,
+            }
         log("[bench] network kernels on 2^20 pairs")
         result["nn_kernels_2^20"] = nn_kernels(torch, abi)
 

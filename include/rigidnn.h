@@ -96,13 +96,15 @@ int rb_ctx_destroy(rb_ctx *ctx);
 const char *rb_last_error(void);
 
 /* ---- pair list: half list i < j of body pairs closer than r_list --------
- * Paper abstract: only bead pairs "within a certain distance" are computed;
- * a body pair can have a bead pair inside rc only when its centre distance
- * is below 2 r_max + rc, so r_list = 2 r_max + rc + skin.  Cell list over a
- * periodic orthorhombic box (host box[3]); requires box >= 2 r_list per axis.
- * x: 3 x n FP64 positions (any periodic image).  Writes pair_i/pair_j
- * (capacity max_pairs) sorted by i and, within i, in a fixed cell order, so
- * the list is deterministic; flags[NPAIRS] = min(found, max_pairs) and
+ * Paper abstract: bead distances are computed only for bodies near each
+ * other; a body pair can have a bead pair inside rc only when its centre
+ * distance is below 2 r_max + rc, so r_list = 2 r_max + rc + skin.  Cell list
+ * over a periodic orthorhombic box (host box[3]); requires box >= 2 r_list
+ * per axis.  x: 3 x n FP64 positions (any periodic image).  Writes
+ * pair_i/pair_j (capacity max_pairs): the exact set of pairs; the pairs of
+ * one body i are contiguous and in a fixed cell order, the order of the
+ * bodies' runs is not specified for n <= 65536 (sorted by i above);
+ * flags[NPAIRS] = min(found, max_pairs) and
  * flags[OVERFLOW] = found if found > max_pairs (else 0).  Copies x into
  * x_ref (3 x n) for the skin test of rb_rigid_step.  With
  * RB_BUILD_IF_FLAGGED the kernels do nothing unless flags[REBUILD] is set,

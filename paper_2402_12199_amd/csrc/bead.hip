@@ -5,6 +5,9 @@
 //
 // Work mapping (gfx950, wave64): one wavefront per body pair, evaluated in
 // body i's frame, where body i's beads are its template.
+//  0. A separating-axis test between body j's bead box and body i's bead box
+//     grown by rc skips pairs that cannot have a bead pair within rc (most
+//     pairs of a list built with a skin) before any bead is touched.
 //  1. Body j's beads are rotated into body i's frame in FP64 and kept when
 //     they lie within rc of body i's bead box (the box that holds every bead
 //     centre of i); survivors go to LDS, compacted with a ballot, as an FP32
@@ -28,11 +31,63 @@ namespace rb {
 constexpr int kBeadWaves = 4;        // waves per block
 constexpr float kCullMargin = 1.0e-3f;
 
+// A wave's LDS: three arrays of `stride` float4 (stride >= the largest
+// template), carved from the block's dynamic LDS, so that the occupancy
+// follows the templates in use rather than the largest one allowed.
 struct WaveLds {
-    float4 j[kMaxBeads];     // body j's surviving beads (FP32), body i frame
-    float4 jlo[kMaxBeads];   // their FP32 rounding residuals
-    float4 i[kMaxBeads];     // body i's surviving beads, body i frame
+    float4 *j;     // body j's surviving beads (FP32), body i frame
+    float4 *jlo;   // their FP32 rounding residuals
+    float4 *i;     // body i's surviving beads, body i frame
 };
+
+__device__ inline WaveLds wave_lds(float4 *base, int w, int stride) {
+    float4 *p = base + (size_t)w * 3 * stride;
+    return WaveLds{p, p + stride, p + 2 * stride};
+}
+
+// Separating-axis test (15 axes) between box A, centred at the origin with
+// the axes of body i's frame and half extents a, and box B, centred at t with
+// axes the columns of R and half extents b.  Returns false when an axis
+// separates them.  FP32 with a small widening of the absolute rotation terms;
+// the caller grows A by rc plus a margin well above the rounding.
+__device__ inline bool boxes_overlap(const float a[3], const float b[3], const float t[3], const float R[9]) {
+    float AR[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) AR[k] = fabsf(R[k]) + 1.0e-6f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        if (fabsf(t[i]) > a[i] + b[0] * AR[3 * i] + b[1] * AR[3 * i + 1] + b[2] * AR[3 * i + 2]) return false;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const float tp = t[0] * R[j] + t[1] * R[3 + j] + t[2] * R[6 + j];
+        if (fabsf(tp) > a[0] * AR[j] + a[1] * AR[3 + j] + a[2] * AR[6 + j] + b[j]) return false;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            const float ra = a[i1] * AR[3 * i2 + j] + a[i2] * AR[3 * i1 + j];
+            const float rb = b[j1] * AR[3 * i + j2] + b[j2] * AR[3 * i + j1];
+            if (fabsf(t[i2] * R[3 * i1 + j] - t[i1] * R[3 * i2 + j]) > ra + rb) return false;
+        }
+    }
+    return true;
+}
+
+// Whether body j (type tj, at d with rotation R in body i's frame) can have
+// a bead within rc of a bead of body i (type ti).
+__device__ inline bool may_interact(const Templates &T, int ti, int tj, const double d[3], const double R[9],
+                                    float rc) {
+    const float a[3] = {T.hx[ti] + rc, T.hy[ti] + rc, T.hz[ti] + rc};
+    const float b[3] = {T.hx[tj], T.hy[tj], T.hz[tj]};
+    const float t[3] = {(float)d[0], (float)d[1], (float)d[2]};
+    float Rf[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rf[k] = (float)R[k];
+    return boxes_overlap(a, b, t, Rf);
+}
 
 __device__ inline float box_dist2(float x, float y, float z, float hx, float hy, float hz) {
     const float ax = fmaxf(fabsf(x) - hx, 0.f), ay = fmaxf(fabsf(y) - hy, 0.f), az = fmaxf(fabsf(z) - hz, 0.f);
@@ -160,12 +215,12 @@ __device__ inline void pair_sum(const LJ &lj, int ni, int nj, const WaveLds &L, 
 // reported is at least rc (culled bead pairs are all farther than rc).
 __global__ __launch_bounds__(256) void k_bead_desc(Templates T, LJ lj, int ti, int tj, int64_t P,
                                                    const float *__restrict__ desc, float *__restrict__ out,
-                                                   int32_t *__restrict__ flags) {
-    __shared__ WaveLds lds[kBeadWaves];
+                                                   int32_t *__restrict__ flags, int stride) {
+    extern __shared__ float4 bead_lds[];
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    WaveLds &L = lds[w];
-    const float cut2 = (sqrtf(lj.rc2) + kCullMargin) * (sqrtf(lj.rc2) + kCullMargin);
+    WaveLds L = wave_lds(bead_lds, w, stride);
+    const float rcm = sqrtf(lj.rc2) + kCullMargin, cut2 = rcm * rcm;
     long long ntests = 0;
     const int64_t step = (int64_t)gridDim.x * kBeadWaves;
     for (int64_t p = (int64_t)blockIdx.x * kBeadWaves + w; p < P; p += step) {
@@ -174,7 +229,7 @@ __global__ __launch_bounds__(256) void k_bead_desc(Templates T, LJ lj, int ti, i
         const double inv = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
         double R[9];
         quat_to_rot<double>(qw * inv, qx * inv, qy * inv, qz * inv, R);
-        const int nj = stage_j(T, ti, tj, d, R, cut2, L, lane);
+        const int nj = may_interact(T, ti, tj, d, R, rcm) ? stage_j(T, ti, tj, d, R, cut2, L, lane) : 0;
         const int ni = nj ? stage_i(T, ti, tj, d, R, cut2, L, lane) : 0;
         wave_lds_sync();
         float r[8];
@@ -215,12 +270,13 @@ __global__ __launch_bounds__(256) void k_bead_md(Templates T, LJ lj, int32_t n, 
                                                  Box box, const int32_t *__restrict__ pi,
                                                  const int32_t *__restrict__ pj, const int32_t *__restrict__ idx,
                                                  const int32_t *__restrict__ count_dev, int32_t max_count,
-                                                 int64_t *__restrict__ acc, int32_t *__restrict__ flags) {
-    __shared__ WaveLds lds[kBeadWaves];
+                                                 int64_t *__restrict__ acc, int32_t *__restrict__ flags,
+                                                 int stride) {
+    extern __shared__ float4 bead_lds[];
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    WaveLds &L = lds[w];
-    const float cut2 = (sqrtf(lj.rc2) + kCullMargin) * (sqrtf(lj.rc2) + kCullMargin);
+    WaveLds L = wave_lds(bead_lds, w, stride);
+    const float rcm = sqrtf(lj.rc2) + kCullMargin, cut2 = rcm * rcm;
     int count = *count_dev;
     if (count > max_count) count = max_count;
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(flags + RB_FLAG_NEVAL, count);
@@ -252,6 +308,7 @@ __global__ __launch_bounds__(256) void k_bead_md(Templates T, LJ lj, int32_t n, 
             qr[3] = aw * bz - ax * by + ay * bx - az * bw;
             quat_to_rot<double>(qr[0], qr[1], qr[2], qr[3], R);
         }
+        if (!may_interact(T, ti, tj, d, R, rcm)) continue;   // bead boxes farther apart than rc
         const int nj = stage_j(T, ti, tj, d, R, cut2, L, lane);
         if (nj == 0) continue;   // no bead of j within rc of i's box: zero contribution
         const int ni = stage_i(T, ti, tj, d, R, cut2, L, lane);
@@ -297,6 +354,23 @@ __global__ __launch_bounds__(256) void k_bead_md(Templates T, LJ lj, int32_t n, 
     if (lane == 0 && bad) atomicOr(flags + RB_FLAG_NONFINITE, 1);
 }
 
+// Dynamic LDS of a block (kBeadWaves waves, three arrays each) and the
+// number of such blocks a CU holds, cached per size.
+static size_t bead_lds_bytes(const rb_ctx *ctx, int &stride) {
+    stride = (ctx->max_beads + 3) & ~3;
+    return sizeof(float4) * 3 * (size_t)stride * kBeadWaves;
+}
+
+template <typename K>
+static int blocks_per_cu(K kernel, size_t lds, int *cache_lds, int *cache_nb) {
+    if (*cache_lds == (int)lds && *cache_nb > 0) return *cache_nb;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 256, lds) != hipSuccess || nb < 1) nb = 1;
+    *cache_lds = (int)lds;
+    *cache_nb = nb;
+    return nb;
+}
+
 static int device_cus_bead() {
     static int cached = 0;
     if (cached > 0) return cached;
@@ -319,9 +393,13 @@ extern "C" int rb_bead_pair_eval(const rb_ctx *ctx, int64_t n_pairs, const float
     RB_REQUIRE(type_i >= 0 && type_i < ctx->n_types && type_j >= 0 && type_j < ctx->n_types,
                "rb_bead_pair_eval: bad type");
     if (n_pairs == 0) return RB_OK;
-    const int grid = grid_for(n_pairs, kBeadWaves, 3 * device_cus_bead());
-    k_bead_desc<<<grid, 256, 0, (hipStream_t)stream>>>(ctx->dev.t, ctx->dev.lj, type_i, type_j, n_pairs, desc, out,
-                                                      flags);
+    int stride;
+    const size_t lds = bead_lds_bytes(ctx, stride);
+    static int c_lds = -1, c_nb = 0;
+    const int nb = blocks_per_cu(k_bead_desc, lds, &c_lds, &c_nb);
+    const int grid = grid_for(n_pairs, kBeadWaves, nb * device_cus_bead());
+    k_bead_desc<<<grid, 256, lds, (hipStream_t)stream>>>(ctx->dev.t, ctx->dev.lj, type_i, type_j, n_pairs, desc,
+                                                        out, flags, stride);
     RB_LAUNCH_CHECK("rb_bead_pair_eval");
     return RB_OK;
 }
@@ -340,11 +418,16 @@ extern "C" int rb_bead_pair_forces(const rb_ctx *ctx, int32_t n, const double *x
         b.L[a] = box[a];
         b.inv[a] = 1.0 / box[a];
     }
-    // persistent grid: three 4-wave blocks fit a CU (LDS); waves stride over
-    // the pairs, and each block flushes its global sums once
-    const int grid = grid_for(max_count, kBeadWaves, 3 * device_cus_bead());
-    k_bead_md<<<grid, 256, 0, (hipStream_t)stream>>>(ctx->dev.t, ctx->dev.lj, n, x, q, type, b, pair_i, pair_j, idx,
-                                                    count_dev, max_count, acc, flags);
+    // persistent grid: as many 4-wave blocks as a CU holds (LDS sized for
+    // the templates in use); waves stride over the pairs, and each block
+    // flushes its global sums once
+    int stride;
+    const size_t lds = bead_lds_bytes(ctx, stride);
+    static int c_lds = -1, c_nb = 0;
+    const int nb = blocks_per_cu(k_bead_md, lds, &c_lds, &c_nb);
+    const int grid = grid_for(max_count, kBeadWaves, nb * device_cus_bead());
+    k_bead_md<<<grid, 256, lds, (hipStream_t)stream>>>(ctx->dev.t, ctx->dev.lj, n, x, q, type, b, pair_i, pair_j,
+                                                      idx, count_dev, max_count, acc, flags, stride);
     RB_LAUNCH_CHECK("rb_bead_pair_forces");
     return RB_OK;
 }

@@ -44,15 +44,7 @@ __global__ void k_finalize(int32_t n, int64_t *__restrict__ acc, float *__restri
             acc[(3 + a) * (int64_t)n + i] = 0;
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x < 10) {
-        int64_t *g = acc + 6 * (int64_t)n + threadIdx.x * RB_ACC_SLOTS;
-        long long t = 0;
-        for (int k = 0; k < RB_ACC_SLOTS; ++k) {
-            t += g[k];
-            g[k] = 0;
-        }
-        if (ev) ev[threadIdx.x] = (double)t * s;
-    }
+    if (blockIdx.x == 0) finalize_globals(acc + 6 * (int64_t)n, ev);
 }
 
 }  // namespace rb
@@ -80,6 +72,7 @@ extern "C" int rb_ctx_create(rb_ctx **out, int32_t n_types, const int32_t *n_bea
     int o = 0;
     for (int t = 0; t < n_types; ++t) {
         c->n_beads[t] = n_beads[t];
+        if (n_beads[t] > c->max_beads) c->max_beads = n_beads[t];
         c->dev.t.n[t] = n_beads[t];
         c->dev.t.off[t] = o;
         double r2max = 0;

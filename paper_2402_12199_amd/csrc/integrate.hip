@@ -10,6 +10,12 @@
 // z = h L_k / (2 I_k), and L turns by -2z about the same axis, which keeps
 // the lab-frame angular momentum fixed.  A kick adds the body-frame torque:
 // L <- L + (dt/2) R(q)^T tau.
+
+// Multiply-add fusion only inside one source expression (also for the
+// helpers of the common header, hence before it): the fused step kernel
+// repeats the arithmetic of the two phase kernels and must round the same
+// way, which fusion across statements, chosen per kernel, would break.
+#pragma clang fp contract(on)
 #include "rb_common.hpp"
 
 namespace rb {
@@ -51,6 +57,51 @@ __device__ inline void kick(double dt, double q[4], double P[3], double L[3], co
     for (int a = 0; a < 3; ++a) {
         P[a] += 0.5 * dt * (double)force[a * n + i];
         L[a] += 0.5 * dt * (R[a] * t[0] + R[3 + a] * t[1] + R[6 + a] * t[2]);
+    }
+}
+
+// Grid-wide sums of (a, b) into out[0..1]: wave and block sums, one partial
+// pair per block, and the last block to finish adds the partials in a fixed
+// tree order (lane k takes blocks k, k + 64, ...), so the result depends only
+// on the grid size.
+__device__ inline void grid_sum2(double a, double b, double *__restrict__ partial, unsigned *__restrict__ ticket,
+                                 double *__restrict__ out) {
+    __shared__ double red[2][kIntThreads / kWave];
+    __shared__ bool last;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][w] = a;
+        red[1][w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = 0, sb = 0;
+        for (int k = 0; k < kIntThreads / kWave; ++k) {
+            sa += red[0][k];
+            sb += red[1][k];
+        }
+        partial[2 * blockIdx.x] = sa;
+        partial[2 * blockIdx.x + 1] = sb;
+        __threadfence();
+        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last && w == 0) {
+        __threadfence();
+        double sa = 0, sb = 0;
+        for (int k = lane; k < (int)gridDim.x; k += kWave) {
+            sa += __hip_atomic_load(partial + 2 * k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sb += __hip_atomic_load(partial + 2 * k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        sa = wave_sum(sa);
+        sb = wave_sum(sb);
+        if (lane == 0) {
+            out[0] = sa;
+            out[1] = sb;
+            *ticket = 0u;
+        }
     }
 }
 
@@ -112,8 +163,6 @@ __global__ __launch_bounds__(kIntThreads) void k_phase2(int32_t n, double dt, do
                                                         const float *__restrict__ torque,
                                                         double *__restrict__ partial, unsigned *__restrict__ ticket,
                                                         double *__restrict__ kinetic) {
-    __shared__ double red[2][kIntThreads / kWave];
-    __shared__ bool last;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double kt = 0, kr = 0;
     if (i < n) {
@@ -131,37 +180,7 @@ __global__ __launch_bounds__(kIntThreads) void k_phase2(int32_t n, double dt, do
             kr += Li[a] * Li[a] / (2.0 * inertia[3 * t + a]);
         }
     }
-    kt = wave_sum(kt);
-    kr = wave_sum(kr);
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
-    if (lane == 0) {
-        red[0][w] = kt;
-        red[1][w] = kr;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double a = 0, b = 0;
-        for (int k = 0; k < kIntThreads / kWave; ++k) {
-            a += red[0][k];
-            b += red[1][k];
-        }
-        partial[2 * blockIdx.x] = a;
-        partial[2 * blockIdx.x + 1] = b;
-        __threadfence();
-        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (last && threadIdx.x == 0) {
-        __threadfence();
-        double a = 0, b = 0;
-        for (int k = 0; k < (int)gridDim.x; ++k) {
-            a += __hip_atomic_load(partial + 2 * k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            b += __hip_atomic_load(partial + 2 * k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        kinetic[0] = a;
-        kinetic[1] = b;
-        *ticket = 0u;
-    }
+    grid_sum2(kt, kr, partial, ticket, kinetic);
 }
 
 // Fused step boundary: the forces of step k come from the fixed-point
@@ -180,8 +199,6 @@ __global__ __launch_bounds__(kIntThreads) void k_fused(int32_t n, double dt, dou
                                                        double half_skin2, int32_t *__restrict__ flags,
                                                        double *__restrict__ partial, unsigned *__restrict__ ticket,
                                                        double *__restrict__ kinetic) {
-    __shared__ double red[2][kIntThreads / kWave];
-    __shared__ bool last;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const double s = 1.0 / RB_ACC_SCALE;
     double kt = 0, kr = 0;
@@ -235,46 +252,8 @@ __global__ __launch_bounds__(kIntThreads) void k_fused(int32_t n, double dt, dou
         }
     }
     if (__any(moved) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(flags + RB_FLAG_REBUILD, 1);
-    if (blockIdx.x == 0 && threadIdx.x < 10) {
-        int64_t *g = acc + 6 * (int64_t)n + threadIdx.x * RB_ACC_SLOTS;
-        long long tsum = 0;
-        for (int k = 0; k < RB_ACC_SLOTS; ++k) {
-            tsum += g[k];
-            g[k] = 0;
-        }
-        if (ev) ev[threadIdx.x] = (double)tsum * s;
-    }
-    kt = wave_sum(kt);
-    kr = wave_sum(kr);
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
-    if (lane == 0) {
-        red[0][w] = kt;
-        red[1][w] = kr;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double a = 0, b = 0;
-        for (int k = 0; k < kIntThreads / kWave; ++k) {
-            a += red[0][k];
-            b += red[1][k];
-        }
-        partial[2 * blockIdx.x] = a;
-        partial[2 * blockIdx.x + 1] = b;
-        __threadfence();
-        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (last && threadIdx.x == 0) {
-        __threadfence();
-        double a = 0, b = 0;
-        for (int k = 0; k < (int)gridDim.x; ++k) {
-            a += __hip_atomic_load(partial + 2 * k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            b += __hip_atomic_load(partial + 2 * k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        kinetic[0] = a;
-        kinetic[1] = b;
-        *ticket = 0u;
-    }
+    if (blockIdx.x == 0) finalize_globals(acc + 6 * (int64_t)n, ev);
+    grid_sum2(kt, kr, partial, ticket, kinetic);
 }
 
 static size_t nblocks(int32_t n) { return (size_t)((n + kIntThreads - 1) / kIntThreads); }

@@ -50,12 +50,77 @@ __device__ inline float smooth_switch(float r, float lo, float hi, float &dsdr) 
     return 1.f - t * t * (3.f - 2.f * t);
 }
 
+// Forces of one pair for dynamics: switched energy, body-i-frame force and
+// torques, rotation to the lab frame, fixed-point accumulation on both
+// bodies; the energy and virial of the 16 rows of the wave's tile are summed
+// over the row lanes and added to the wave's LDS sums by lane 0.
+__device__ inline void forces_epilogue(const NNArgs &a, float gu[kIn], float E, int64_t pid, bool mine, int lane,
+                                       long long *wsum, bool &bad) {
+    long long ev[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) ev[k] = 0;
+    if (mine) {
+        // the descriptor and the switch are reloaded and recomputed here
+        // rather than kept in registers across the tile
+        float u[kIn];
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) u[k] = a.desc[k * a.stride + pid];
+        const float r = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        float dsdr;
+        const float S = smooth_switch(r, a.sw_lo, a.sw_hi, dsdr);
+        // switched energy: E_s = S E, dE_s/dd = S g_d + E S'(r) d / r
+        if (dsdr != 0.f) {
+            const float c = E * dsdr / r;
+            gu[0] = fmaf(c, u[0], gu[0]);
+            gu[1] = fmaf(c, u[1], gu[1]);
+            gu[2] = fmaf(c, u[2], gu[2]);
+        }
+        const float Es = S * E;
+        float ft[9];
+        pair_ft_from_grad(u, gu, ft);
+        const int i = a.pi[pid], j = a.pj[pid];
+        double R[9];
+        quat_to_rot<double>(a.q[i], a.q[a.n + i], a.q[2 * a.n + i], a.q[3 * a.n + i], R);
+        double Fj[3], ti[3], tj[3], dl[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Fj[c] = R[3 * c] * ft[0] + R[3 * c + 1] * ft[1] + R[3 * c + 2] * ft[2];
+            ti[c] = R[3 * c] * ft[3] + R[3 * c + 1] * ft[4] + R[3 * c + 2] * ft[5];
+            tj[c] = R[3 * c] * ft[6] + R[3 * c + 1] * ft[7] + R[3 * c + 2] * ft[8];
+            dl[c] = R[3 * c] * u[0] + R[3 * c + 1] * u[1] + R[3 * c + 2] * u[2];
+        }
+        if (!isfinite(Es) || !isfinite(ft[0]) || !isfinite(ft[3]) || !isfinite(ft[6])) bad = true;
+        const int64_t nn = a.n;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            acc_add(a.acc + c * nn + i, -Fj[c]);
+            acc_add(a.acc + c * nn + j, Fj[c]);
+            acc_add(a.acc + (3 + c) * nn + i, ti[c]);
+            acc_add(a.acc + (3 + c) * nn + j, tj[c]);
+        }
+        ev[0] = to_fixed(Es);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) ev[1 + 3 * c + b] = to_fixed(dl[c] * Fj[b]);
+    }
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        long long v = ev[k];
+        v += __shfl_xor(v, 1, kWave);
+        v += __shfl_xor(v, 2, kWave);
+        v += __shfl_xor(v, 4, kWave);
+        v += __shfl_xor(v, 8, kWave);
+        if (lane == 0) wsum[k] += v;
+    }
+}
+
 template <int MODE, bool BF16>
 __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
     constexpr int kWaves = NNCfg<BF16, MODE>::waves;
     __shared__ typename NNLds<BF16>::T L;
     if constexpr (BF16)
-        stage_bf16(L, a.params);
+        stage_bf16<nn_threads(true, MODE)>(L, a.params);
     else
         stage_small(L, a.params);
     __syncthreads();
@@ -67,9 +132,10 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
         count = c < a.P ? c : a.P;
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.flags + RB_FLAG_NEVAL, (int)count);
     }
-    long long eacc[10];
-#pragma unroll
-    for (int k = 0; k < 10; ++k) eacc[k] = 0;
+    // per-wave energy/virial sums live in LDS, not registers, so that they
+    // add nothing to the register pressure of the tile evaluation
+    __shared__ long long wacc[kWaves][10];
+    if (MODE == kForces && lane < 10) wacc[w][lane] = 0;
     bool bad = false;
     const int64_t ntiles = (count + kTile - 1) / kTile;
     for (int64_t t = (int64_t)blockIdx.x * kWaves + w; t < ntiles; t += (int64_t)gridDim.x * kWaves) {
@@ -83,12 +149,11 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
         float u[kIn];
 #pragma unroll
         for (int k = 0; k < kIn; ++k) u[k] = live ? a.desc[k * a.stride + pid] : (k == 3 ? 1.f : 0.f);
-        float seed = 1.f, dsdr = 0.f, S = 1.f, r = 0.f;
+        float seed = 1.f;
         if (MODE == kGrad && a.gE) seed = live ? a.gE[pid] : 0.f;
         if (MODE == kForces) {
-            r = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-            S = smooth_switch(r, a.sw_lo, a.sw_hi, dsdr);
-            seed = S;
+            float dsdr;
+            seed = smooth_switch(sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]), a.sw_lo, a.sw_hi, dsdr);
         }
         float gu[kIn];
         float E;
@@ -96,6 +161,12 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
             E = tile_bf16<MODE != kEval>(L, a.nm, u, seed, gu);
         else
             E = tile_fp32<MODE != kEval>(L, L, a.params, a.nm, u, seed, gu);
+        if (MODE == kForces) {
+            // every lane takes part in the shuffles below; the results of
+            // the lanes of groups 1..3 and of dead rows are discarded
+            forces_epilogue(a, gu, E, pid, live && g == 0, lane, wacc[w], bad);
+            continue;
+        }
         if (!live || g != 0) continue;
         if (MODE == kEval) {
             a.energy[pid] = E;
@@ -110,55 +181,12 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
 #pragma unroll
                 for (int k = 0; k < 9; ++k) a.ft[k * a.P + pid] = ft[k];
             }
-        } else {
-            // switched energy: E_s = S E, dE_s/dd = S g_d + E S'(r) d / r
-            if (dsdr != 0.f) {
-                const float c = E * dsdr / r;
-                gu[0] = fmaf(c, u[0], gu[0]);
-                gu[1] = fmaf(c, u[1], gu[1]);
-                gu[2] = fmaf(c, u[2], gu[2]);
-            }
-            const float Es = S * E;
-            float ft[9];
-            pair_ft_from_grad(u, gu, ft);
-            const int i = a.pi[pid], j = a.pj[pid];
-            double R[9];
-            quat_to_rot<double>(a.q[i], a.q[a.n + i], a.q[2 * a.n + i], a.q[3 * a.n + i], R);
-            double Fj[3], ti[3], tj[3], dl[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                Fj[c] = R[3 * c] * ft[0] + R[3 * c + 1] * ft[1] + R[3 * c + 2] * ft[2];
-                ti[c] = R[3 * c] * ft[3] + R[3 * c + 1] * ft[4] + R[3 * c + 2] * ft[5];
-                tj[c] = R[3 * c] * ft[6] + R[3 * c + 1] * ft[7] + R[3 * c + 2] * ft[8];
-                dl[c] = R[3 * c] * u[0] + R[3 * c + 1] * u[1] + R[3 * c + 2] * u[2];
-            }
-            if (!isfinite(Es) || !isfinite(ft[0]) || !isfinite(ft[3]) || !isfinite(ft[6])) bad = true;
-            const int64_t nn = a.n;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                acc_add(a.acc + c * nn + i, -Fj[c]);
-                acc_add(a.acc + c * nn + j, Fj[c]);
-                acc_add(a.acc + (3 + c) * nn + i, ti[c]);
-                acc_add(a.acc + (3 + c) * nn + j, tj[c]);
-            }
-            eacc[0] += to_fixed(Es);
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) eacc[1 + 3 * c + b] += to_fixed(dl[c] * Fj[b]);
         }
     }
     if (MODE == kForces) {
         long long part[11];
 #pragma unroll
-        for (int k = 0; k < 10; ++k) {
-            long long v = eacc[k];
-            v += __shfl_xor(v, 1, kWave);
-            v += __shfl_xor(v, 2, kWave);
-            v += __shfl_xor(v, 4, kWave);
-            v += __shfl_xor(v, 8, kWave);
-            part[k] = v;
-        }
+        for (int k = 0; k < 10; ++k) part[k] = wacc[w][k];
         part[10] = 0;
         block_flush_globals<kWaves>(part, a.acc + 6 * (int64_t)a.n, nullptr);
         if (__any(bad) && lane == 0) atomicOr(a.flags + RB_FLAG_NONFINITE, 1);

@@ -85,25 +85,51 @@ struct LdsBF16 {
     float b5;
 };
 
+// NT = threads of the block.  The loops have compile-time trip counts so
+// that a batch of global loads is in flight before the first LDS store (a
+// block that evaluates a single tile spends most of its time here).
+template <int NT>
 __device__ inline void stage_bf16(LdsBF16 &L, const float *__restrict__ p) {
     // One 16-byte LDS store per work item: columns 32 cb + 8 g .. + 7 of row
     // o hold the input features 32 cb + perm32(8 g + i), i.e. two runs of four
     // consecutive features (32 cb + 4 g and 32 cb + 16 + 4 g).
-    for (int idx = threadIdx.x; idx < 3 * kH * 16; idx += blockDim.x) {
-        const int l = idx / (kH * 16), o = (idx / 16) % kH, u = idx % 16, cb = u >> 2, g = u & 3;
-        const float *row = p + w_off(l + 2) + o * kH + 32 * cb + 4 * g;
-        const float4 a = *reinterpret_cast<const float4 *>(row);
-        const float4 b = *reinterpret_cast<const float4 *>(row + 16);
-        const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
-        *reinterpret_cast<bf16x8 *>(&L.w[l][o][32 * cb + 8 * g]) = pack8(av, bv);
+    constexpr int kItems = 3 * kH * 16;
+    static_assert(kItems % NT == 0, "block size must divide the weight items");
+    constexpr int kIter = kItems / NT;
+    constexpr int kBatch = kIter % 8 == 0 ? 8 : (kIter % 6 == 0 ? 6 : (kIter % 4 == 0 ? 4 : 1));
+#pragma unroll
+    for (int b0 = 0; b0 < kIter; b0 += kBatch) {
+        float4 va[kBatch], vb[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const int idx = threadIdx.x + (b0 + k) * NT;
+            const int l = idx / (kH * 16), o = (idx / 16) % kH, u = idx % 16, cb = u >> 2, g = u & 3;
+            const float *row = p + w_off(l + 2) + o * kH + 32 * cb + 4 * g;
+            va[k] = *reinterpret_cast<const float4 *>(row);
+            vb[k] = *reinterpret_cast<const float4 *>(row + 16);
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const int idx = threadIdx.x + (b0 + k) * NT;
+            const int l = idx / (kH * 16), o = (idx / 16) % kH, u = idx % 16, cb = u >> 2, g = u & 3;
+            const float av[4] = {va[k].x, va[k].y, va[k].z, va[k].w};
+            const float bv[4] = {vb[k].x, vb[k].y, vb[k].z, vb[k].w};
+            *reinterpret_cast<bf16x8 *>(&L.w[l][o][32 * cb + 8 * g]) = pack8(av, bv);
+        }
     }
-    for (int idx = threadIdx.x; idx < kH * 8; idx += blockDim.x) {
+    static_assert((kH * 8) % NT == 0 && (4 * kH) % NT == 0, "block size must divide the small tensors");
+#pragma unroll
+    for (int it = 0; it < kH * 8 / NT; ++it) {
+        const int idx = threadIdx.x + it * NT;
         const int o = idx >> 3, k = idx & 7;
         L.w1[o][k] = k < kIn ? p[OFF_W1 + o * kIn + k] : 0.f;
     }
-    for (int idx = threadIdx.x; idx < 4 * kH; idx += blockDim.x)
+#pragma unroll
+    for (int it = 0; it < 4 * kH / NT; ++it) {
+        const int idx = threadIdx.x + it * NT;
         L.b[idx / kH][idx % kH] = p[b_off(idx / kH + 1) + idx % kH];
-    for (int idx = threadIdx.x; idx < kH; idx += blockDim.x) L.w5[idx] = p[OFF_W5 + idx];
+    }
+    for (int idx = threadIdx.x; idx < kH; idx += NT) L.w5[idx] = p[OFF_W5 + idx];
     if (threadIdx.x == 0) L.b5 = p[OFF_B5];
 }
 

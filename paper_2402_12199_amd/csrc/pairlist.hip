@@ -1,9 +1,10 @@
 // Cell-list pair builder: half list (i < j) of body pairs whose minimum-image
 // centre distance is below r_list.
 //
-// Pipeline (each kernel returns at once when the list is only rebuilt on
-// request and the rebuild flag is clear, so the whole sequence can sit in a
-// captured graph):
+// Up to 65536 bodies: the two-launch pipeline below (k_pl_cells,
+// k_pl_pairs).  Beyond: the multi-kernel pipeline (each kernel returns at
+// once when the list is only rebuilt on request and the rebuild flag is
+// clear, so the whole sequence can sit in a captured graph):
 //   bin bodies into cells of edge >= r_list (count per cell)
 //   exclusive scan of cell counts -> cell starts
 //   scatter body ids into cell order, then sort each cell's ids, which makes
@@ -11,7 +12,9 @@
 //   per body i: count neighbours j > i in the 27 surrounding cells
 //   exclusive scan of those counts -> per-body offsets, total -> flags
 //   per body i: write its pairs at its offset, in the same cell order
-// The resulting list is sorted by i and fully deterministic.
+// The resulting list is sorted by i and fully deterministic.  Either way the
+// set of pairs is exact; the forces built from it do not depend on its order
+// (fixed-point accumulation).
 #include "rb_common.hpp"
 
 namespace rb {
@@ -234,11 +237,19 @@ __global__ void k_finish(int32_t *flags, int mode) {
     flags[RB_FLAG_NREBUILDS] += 1;
 }
 
-// ---------------------------------------------------------------- one block
-// For up to kSmallBodies bodies the whole rebuild runs in one workgroup with
-// barriers between the phases: a single launch per step, which returns at
-// once when no rebuild is flagged.
+// ----------------------------------------------------- two-launch pipeline
+// For up to kSmallBodies bodies a rebuild takes two launches, each of which
+// returns at once when no rebuild is flagged:
+//   k_pl_cells (one workgroup, barriers between phases): bin, scan the cell
+//     counts, scatter, sort each cell
+//   k_pl_pairs (many workgroups): half a wave per body, one lane per
+//     neighbour cell; the lanes count their pairs, the body reserves room
+//     for all of them with one atomic, and the lanes write them; the last
+//     workgroup to finish publishes the count and clears the rebuild flag.
+// The pairs of one body are contiguous and in cell order; the order of the
+// bodies' runs in the list follows the reservations and is not fixed.
 constexpr int kSmallThreads = 1024;
+constexpr int kPairThreads = 256;
 constexpr int kSmallBodies = 65536;
 constexpr int kSmallCells = 262144;
 
@@ -275,58 +286,16 @@ __device__ int block_scan(const int32_t *in, int32_t *out, int m) {
     return carry_s;
 }
 
-template <bool EMIT>
-__device__ inline int neigh_scan(int i, int32_t n, const double *__restrict__ x, const CellGrid &g,
-                                 const int32_t *__restrict__ cell_of, const int32_t *__restrict__ start,
-                                 const int32_t *__restrict__ sorted, int out, int32_t *__restrict__ pi,
-                                 int32_t *__restrict__ pj, int32_t cap) {
-    const double xi = x[i], yi = x[n + i], zi = x[2 * n + i];
-    const int id = cell_of[i];
-    const int cz = id % g.nc[2], cy = (id / g.nc[2]) % g.nc[1], cx = id / (g.nc[2] * g.nc[1]);
-    int lo[3], hi[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        lo[a] = g.nc[a] >= 3 ? -1 : 0;
-        hi[a] = g.nc[a] >= 3 ? 1 : g.nc[a] - 1;
-    }
-    int cnt = 0;
-    for (int ox = lo[0]; ox <= hi[0]; ++ox) {
-        int nx = cx + ox;
-        nx += nx < 0 ? g.nc[0] : (nx >= g.nc[0] ? -g.nc[0] : 0);
-        for (int oy = lo[1]; oy <= hi[1]; ++oy) {
-            int ny = cy + oy;
-            ny += ny < 0 ? g.nc[1] : (ny >= g.nc[1] ? -g.nc[1] : 0);
-            for (int oz = lo[2]; oz <= hi[2]; ++oz) {
-                int nz = cz + oz;
-                nz += nz < 0 ? g.nc[2] : (nz >= g.nc[2] ? -g.nc[2] : 0);
-                const int c = (nx * g.nc[1] + ny) * g.nc[2] + nz;
-                for (int m = start[c], e = start[c + 1]; m < e; ++m) {
-                    const int j = sorted[m];
-                    if (j <= i) continue;
-                    const double dx = min_image(x[j] - xi, g.L[0], g.inv[0]);
-                    const double dy = min_image(x[n + j] - yi, g.L[1], g.inv[1]);
-                    const double dz = min_image(x[2 * n + j] - zi, g.L[2], g.inv[2]);
-                    if (dx * dx + dy * dy + dz * dz < g.rl2) {
-                        if (EMIT && out + cnt < cap) {
-                            pi[out + cnt] = i;
-                            pj[out + cnt] = j;
-                        }
-                        ++cnt;
-                    }
-                }
-            }
-        }
-    }
-    return cnt;
-}
 
-__global__ __launch_bounds__(kSmallThreads) void k_pairlist_small(
-    int32_t n, const double *__restrict__ x, CellGrid g, int32_t *__restrict__ cell_of, int32_t *__restrict__ cnt,
-    int32_t *__restrict__ start, int32_t *__restrict__ fill, int32_t *__restrict__ sorted,
-    int32_t *__restrict__ ncount, int32_t *__restrict__ noff, int32_t *__restrict__ pi, int32_t *__restrict__ pj,
-    int32_t cap, double *__restrict__ x_ref, int32_t *__restrict__ flags, int mode) {
+__global__ __launch_bounds__(kSmallThreads) void k_pl_cells(int32_t n, const double *__restrict__ x, CellGrid g,
+                                                            int32_t *__restrict__ cell_of, int32_t *__restrict__ cnt,
+                                                            int32_t *__restrict__ start, int32_t *__restrict__ fill,
+                                                            int32_t *__restrict__ sorted, double *__restrict__ x_ref,
+                                                            int32_t *__restrict__ counter,
+                                                            const int32_t *__restrict__ flags, int mode) {
     if (skip(flags, mode)) return;
     const int t = threadIdx.x, T = kSmallThreads;
+    if (t < 2) counter[t] = 0;   // pair count and finishing ticket of k_pl_pairs
     for (int c = t; c < g.ncell; c += T) {
         cnt[c] = 0;
         fill[c] = 0;
@@ -365,22 +334,101 @@ __global__ __launch_bounds__(kSmallThreads) void k_pairlist_small(
             sorted[m + 1] = v;
         }
     }
+}
+
+// Pairs (i, j > i) of body i with the bodies of one neighbour cell c; writes
+// them from out on when EMIT (up to cap), returns their number.
+template <bool EMIT>
+__device__ inline int cell_pairs(int i, int c, double xi, double yi, double zi, int32_t n,
+                                 const double *__restrict__ x, const CellGrid &g, const int32_t *__restrict__ start,
+                                 const int32_t *__restrict__ sorted, int out, int32_t *__restrict__ pi,
+                                 int32_t *__restrict__ pj, int32_t cap) {
+    int cnt = 0;
+    for (int m = start[c], e = start[c + 1]; m < e; ++m) {
+        const int j = sorted[m];
+        if (j <= i) continue;
+        const double dx = min_image(x[j] - xi, g.L[0], g.inv[0]);
+        const double dy = min_image(x[n + j] - yi, g.L[1], g.inv[1]);
+        const double dz = min_image(x[2 * n + j] - zi, g.L[2], g.inv[2]);
+        if (dx * dx + dy * dy + dz * dz < g.rl2) {
+            if (EMIT && out + cnt < cap) {
+                pi[out + cnt] = i;
+                pj[out + cnt] = j;
+            }
+            ++cnt;
+        }
+    }
+    return cnt;
+}
+
+__global__ __launch_bounds__(kPairThreads) void k_pl_pairs(int32_t n, const double *__restrict__ x, CellGrid g,
+                                                           const int32_t *__restrict__ cell_of,
+                                                           const int32_t *__restrict__ start,
+                                                           const int32_t *__restrict__ sorted,
+                                                           int32_t *__restrict__ pi, int32_t *__restrict__ pj,
+                                                           int32_t cap, int32_t *__restrict__ counter,
+                                                           int32_t *__restrict__ flags, int mode) {
+    if (skip(flags, mode)) return;
+    __shared__ bool last;
+    const int lane = threadIdx.x & (kWave - 1), k = lane & 31;
+    const int i = (int)(((int64_t)blockIdx.x * (kPairThreads / kWave) + (threadIdx.x >> 6)) * 2 + (lane >> 5));
+    // neighbour cells per axis: all three offsets, or every cell when the
+    // axis has fewer than three
+    int lo[3], m[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = g.nc[a] >= 3 ? -1 : 0;
+        m[a] = g.nc[a] >= 3 ? 3 : g.nc[a];
+    }
+    const bool active = i < n && k < m[0] * m[1] * m[2];
+    double xi = 0, yi = 0, zi = 0;
+    int c = 0, cnt = 0;
+    if (active) {
+        xi = x[i];
+        yi = x[n + i];
+        zi = x[2 * n + i];
+        const int id = cell_of[i];
+        const int cz = id % g.nc[2], cy = (id / g.nc[2]) % g.nc[1], cx = id / (g.nc[2] * g.nc[1]);
+        int nx = cx + lo[0] + k / (m[1] * m[2]);
+        int ny = cy + lo[1] + (k / m[2]) % m[1];
+        int nz = cz + lo[2] + k % m[2];
+        nx += nx < 0 ? g.nc[0] : (nx >= g.nc[0] ? -g.nc[0] : 0);
+        ny += ny < 0 ? g.nc[1] : (ny >= g.nc[1] ? -g.nc[1] : 0);
+        nz += nz < 0 ? g.nc[2] : (nz >= g.nc[2] ? -g.nc[2] : 0);
+        c = (nx * g.nc[1] + ny) * g.nc[2] + nz;
+        cnt = cell_pairs<false>(i, c, xi, yi, zi, n, x, g, start, sorted, 0, pi, pj, cap);
+    }
+    // offsets of the lanes within the body's run (half-wave scan), one
+    // reservation per body
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) {
+        const int v = __shfl_up(incl, o, 32);
+        if (k >= o) incl += v;
+    }
+    const int total = __shfl(incl, 31, 32);
+    int base = 0;
+    if (k == 0 && total > 0) base = atomicAdd(counter, total);
+    base = __shfl(base, 0, 32);
+    if (active && cnt > 0) (void)cell_pairs<true>(i, c, xi, yi, zi, n, x, g, start, sorted, base + incl - cnt, pi, pj, cap);
     __syncthreads();
-    for (int i = t; i < n; i += T) ncount[i] = neigh_scan<false>(i, n, x, g, cell_of, start, sorted, 0, pi, pj, cap);
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(counter + 1, 1) == (int)gridDim.x - 1;
+    }
     __syncthreads();
-    const int total = block_scan(ncount, noff, n);
-    __syncthreads();
-    for (int i = t; i < n; i += T) (void)neigh_scan<true>(i, n, x, g, cell_of, start, sorted, noff[i], pi, pj, cap);
-    if (t == 0) {
-        flags[RB_FLAG_NPAIRS] = total < cap ? total : cap;
-        flags[RB_FLAG_OVERFLOW] = total > cap ? total : 0;
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        const int tot = __hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        flags[RB_FLAG_NPAIRS] = tot < cap ? tot : cap;
+        flags[RB_FLAG_OVERFLOW] = tot > cap ? tot : 0;
         flags[RB_FLAG_REBUILD] = 0;
         flags[RB_FLAG_NREBUILDS] += 1;
     }
 }
 
 struct PLLayout {
-    size_t cell_of, cnt, start, fill, sorted, ncount, noff, tmp, total;
+    size_t cell_of, cnt, start, fill, sorted, ncount, noff, tmp, counter, total;
 };
 
 static bool make_grid(int32_t n, const double *box, double r_list, CellGrid &g) {
@@ -416,6 +464,7 @@ static PLLayout layout(int32_t n, int ncell) {
     L.ncount = o; o += al(sizeof(int32_t) * n);
     L.noff = o; o += al(sizeof(int32_t) * (n + 1));
     L.tmp = o; o += al(sizeof(int32_t) * kScanTile);
+    L.counter = o; o += al(sizeof(int32_t) * 2);
     L.total = o;
     return L;
 }
@@ -458,8 +507,12 @@ extern "C" int rb_pairlist_build(int32_t n, const double *x, const double *box, 
             *noff = (int32_t *)(w + L.noff), *tmp = (int32_t *)(w + L.tmp);
     hipStream_t st = (hipStream_t)stream;
     if (n <= kSmallBodies && g.ncell <= kSmallCells) {
-        k_pairlist_small<<<1, kSmallThreads, 0, st>>>(n, x, g, cell_of, cnt, start, fill, sorted, ncount, noff, pair_i,
-                                                      pair_j, max_pairs, x_ref, flags, mode);
+        int32_t *counter = (int32_t *)(w + L.counter);
+        k_pl_cells<<<1, kSmallThreads, 0, st>>>(n, x, g, cell_of, cnt, start, fill, sorted, x_ref, counter, flags,
+                                                mode);
+        const int bodies_per_block = 2 * kPairThreads / kWave;
+        k_pl_pairs<<<(n + bodies_per_block - 1) / bodies_per_block, kPairThreads, 0, st>>>(
+            n, x, g, cell_of, start, sorted, pair_i, pair_j, max_pairs, counter, flags, mode);
         RB_LAUNCH_CHECK("rb_pairlist_build");
         return RB_OK;
     }

@@ -103,6 +103,22 @@ __device__ inline T wave_sum(T v) {
     return v;
 }
 
+// Sums and clears the RB_ACC_SLOTS slots of each of the 10 global fixed-point
+// sums (energy, virial), one lane per slot and one wave per sum; every wave of
+// the calling block takes part.  Integer sums: the order does not matter.
+__device__ inline void finalize_globals(int64_t *acc_globals, double *ev) {
+    static_assert(RB_ACC_SLOTS == kWave, "one lane per slot");
+    const int lane = threadIdx.x & (kWave - 1);
+    const int nw = (int)(blockDim.x / kWave);
+    for (int g = (int)(threadIdx.x / kWave); g < 10; g += nw) {
+        int64_t *p = acc_globals + g * RB_ACC_SLOTS + lane;
+        long long v = *p;
+        *p = 0;
+        v = wave_sum(v);
+        if (lane == 0 && ev) ev[g] = (double)v * (1.0 / RB_ACC_SCALE);
+    }
+}
+
 template <typename T>
 __device__ inline T wave_min(T v) {
 #pragma unroll
@@ -132,6 +148,7 @@ struct rb_ctx {
     int n_types;
     int n_beads[rb::kMaxTypes];
     float rmax[rb::kMaxTypes];
+    int max_beads;           // largest template
     void *alloc_beads;
     void *alloc_mass;
 };

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(nn_threads(BF16, 1)) void k_train_fb(TrainArgs a) {
     constexpr int kWaves = nn_threads(BF16, 1) / kWave;
     __shared__ typename NNLds<BF16>::T L;
     if constexpr (BF16)
-        stage_bf16(L, a.params);
+        stage_bf16<nn_threads(true, 1)>(L, a.params);
     else
         stage_small(L, a.params);
     __syncthreads();

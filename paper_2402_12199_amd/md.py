@@ -179,6 +179,19 @@ class RigidSystem:
         torch.cuda.current_stream().wait_stream(side)
         return g
 
+    def pair_configurations(self, d_min: float, d_max: float) -> torch.Tensor:
+        """Descriptors (7, m) of the listed pairs with d_min <= |d| < d_max
+        (training data drawn from the dynamics; uses the routing buffers)."""
+        if self.desc is None:
+            self.desc = torch.zeros((7, self.max_pairs), dtype=torch.float32, device=self.dev)
+            self.idx_nn = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
+            self.idx_bead = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
+        abi.rb_pair_descriptors(self.x, self.q, self.box, self.pair_i, self.pair_j, d_min, self.desc, self.idx_nn,
+                                self.idx_bead, self.flags, d_max=d_max)
+        m = int(self.flags[abi.RB_FLAG_NNN].item())
+        idx = torch.sort(self.idx_nn[:m].long()).values   # list order, independent of append order
+        return self.desc[:, idx]
+
     # ------------------------------------------------------------ readback
     def flags_host(self) -> np.ndarray:
         return self.flags.cpu().numpy()

@@ -1,10 +1,12 @@
 """Surrogate pair energy: data from the bead path, training, held-out errors.
 
 Paper section 2: the network is trained on pair configurations whose
-energies, forces and torques come from the composite-bead method.  Here the
-configurations are synthetic (uniform direction, uniform distance in
-[d_lo, d_hi], uniform relative orientation), labelled on the GPU by the bead
-kernel (rb_bead_pair_eval), and configurations whose closest bead pair is
+energies, forces and torques come from the composite-bead method.  Two
+sources of configurations: uniform draws (uniform direction, distance
+uniform in [d_lo, d_hi], uniform relative orientation), or the pairs that
+the bead-path dynamics of a workload visits (as in the paper, whose data
+come from composite-body simulations).  They are labelled on the GPU by the
+bead kernel (rb_bead_pair_eval); configurations whose closest bead pair is
 below r_rej are rejected (deep overlaps, absent from dynamics at the
 workloads' temperature).  Training runs rb_nn_train_step (BF16 MFMA, FP32
 master weights, Adam) on the energy.  Errors are reported on a held-out set
@@ -77,18 +79,19 @@ def evaluate(params, norm, precision, desc: np.ndarray, lab: np.ndarray, chunk: 
     }
 
 
-def train_surrogate(body, n_train: int, n_test: int, epochs: int, seed: int = 1004, test_seed: int = 2004,
-                    batch: int = 8192, lr: float = 1e-3, precision: int = abi.RB_PREC_BF16, r_rej: float = 0.8,
-                    rc: float = 2.5, sigma: float = 1.0, init_seed: int = 1003, log=None) -> dict:
-    """Label, train and evaluate a surrogate for pairs of one body type."""
+def label_set(ctx: abi.Ctx, desc: np.ndarray, r_rej: float = 0.8, type_i: int = 0, type_j: int = 0):
+    """Bead labels of given configurations, rejecting r_min < r_rej."""
+    lab = label_pairs(ctx, desc.astype(np.float32), type_i, type_j)
+    keep = lab[:, 10] >= r_rej
+    return desc[keep].astype(np.float32), lab[keep]
+
+
+def fit(desc: np.ndarray, lab: np.ndarray, tdesc: np.ndarray, tlab: np.ndarray, d_cut: float, epochs: int,
+        seed: int, batch: int = 8192, lr: float = 1e-3, precision: int = abi.RB_PREC_BF16, init_seed: int = 1003,
+        log=None, name: str = "") -> dict:
+    """Train a fresh network (Xavier init) on energies, return it with the
+    held-out errors before and after."""
     from synth import sampling
-    t0 = time.perf_counter()
-    ctx = abi.Ctx([body.beads], [body.mass], [body.inertia])
-    d_min = 2.0 * body.r_in + sigma
-    d_cut = 2.0 * body.r_max + rc
-    desc, lab, rej = make_dataset(ctx, n_train, seed, d_min, d_cut, r_rej)
-    tdesc, tlab, _ = make_dataset(ctx, n_test, test_seed, d_min, d_cut, r_rej)
-    t_label = time.perf_counter() - t0
     e = lab[:, 0].astype(np.float64)
     norm = make_norm(d_cut, float(e.mean()), float(e.std()))
     tr = Trainer(sampling.xavier_params(init_seed), norm, precision=precision, batch=batch, lr=lr)
@@ -97,18 +100,74 @@ def train_surrogate(body, n_train: int, n_test: int, epochs: int, seed: int = 10
     g = sampling.rng(seed + 7)
     before = evaluate(tr.params, norm, precision, tdesc, tlab)
     hist = []
+    torch.cuda.synchronize()
     t1 = time.perf_counter()
     for ep in range(epochs):
         hist.append(tr.epoch(d_dev, y_dev, g))
         if log and (ep % max(1, epochs // 10) == 0 or ep == epochs - 1):
-            log(f"[surrogate {body.name}] epoch {ep + 1}/{epochs} loss {hist[-1]:.4f}")
+            log(f"[surrogate {name}] epoch {ep + 1}/{epochs} loss {hist[-1]:.4f}")
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     after = evaluate(tr.params, norm, precision, tdesc, tlab)
-    return dict(shape=body.name, params=tr.params, norm=norm, precision=precision, d_min=d_min, d_cut=d_cut,
-                epochs=epochs, steps=tr.t, batch=batch, n_train=n_train, n_test=n_test, reject_rate=rej,
-                label_s=t_label, train_s=t_train, samples_per_s=tr.t * batch / max(t_train, 1e-9),
-                loss_history=hist, untrained=before, trained=after)
+    return dict(shape=name, params=tr.params, norm=norm, precision=precision, d_cut=d_cut, epochs=epochs,
+                steps=tr.t, batch=batch, n_train=int(len(desc)), n_test=int(len(tdesc)), train_s=t_train,
+                samples_per_s=tr.t * batch / max(t_train, 1e-9), loss_history=hist, untrained=before,
+                trained=after)
+
+
+def train_surrogate(body, n_train: int, n_test: int, epochs: int, seed: int = 1004, test_seed: int = 2004,
+                    r_rej: float = 0.8, rc: float = 2.5, sigma: float = 1.0, log=None, **kw) -> dict:
+    """Surrogate for pairs of one body type from uniformly drawn
+    configurations (distance uniform in [d_min, d_cut], orientation uniform)."""
+    t0 = time.perf_counter()
+    ctx = abi.Ctx([body.beads], [body.mass], [body.inertia])
+    d_min = 2.0 * body.r_in + sigma
+    d_cut = 2.0 * body.r_max + rc
+    desc, lab, rej = make_dataset(ctx, n_train, seed, d_min, d_cut, r_rej)
+    tdesc, tlab, _ = make_dataset(ctx, n_test, test_seed, d_min, d_cut, r_rej)
+    t_label = time.perf_counter() - t0
+    r = fit(desc, lab, tdesc, tlab, d_cut, epochs, seed, log=log, name=body.name, **kw)
+    r.update(sampling="uniform", d_min=d_min, reject_rate=rej, label_s=t_label)
+    return r
+
+
+def md_pair_samples(sysm, dt: float, n: int, every: int, d_min: float, d_max: float, path: str = "bead"):
+    """Pair configurations visited by the dynamics: every `every` steps, the
+    descriptors of all listed pairs with d_min <= |d| < d_max, until n are
+    collected (the system must have current forces)."""
+    out, have, steps = [], 0, 0
+    while have < n:
+        for _ in range(every):
+            sysm.step(dt, path)
+        steps += every
+        d = sysm.pair_configurations(d_min, d_max).cpu().numpy().T
+        out.append(d)
+        have += len(d)
+    sysm.check_capacity()
+    return np.concatenate(out)[:n], steps
+
+
+def train_surrogate_md(cfg, st, n_train: int, n_test: int, epochs: int, every: int = 10, seed: int = 1006,
+                       r_rej: float = 0.8, log=None, **kw) -> dict:
+    """Surrogate trained on configurations drawn from the bead-path dynamics
+    of a workload (paper section 2: training pairs come from composite-body
+    simulations).  The held-out set comes from the later part of the same
+    trajectory, after the training snapshots."""
+    from .md import RigidSystem
+    t0 = time.perf_counter()
+    b = cfg.body
+    sysm = RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"], cfg.box,
+                       cfg.r_list, cfg.skin)
+    sysm.init_forces("bead")
+    desc, s_train = md_pair_samples(sysm, cfg.dt, n_train, every, cfg.d_min, cfg.d_cut)
+    tdesc, s_test = md_pair_samples(sysm, cfg.dt, n_test, max(1, every // 2), cfg.d_min, cfg.d_cut)
+    desc, lab = label_set(sysm.ctx, desc, r_rej)
+    tdesc, tlab = label_set(sysm.ctx, tdesc, r_rej)
+    t_label = time.perf_counter() - t0
+    r = fit(desc, lab, tdesc, tlab, cfg.d_cut, epochs, seed, log=log, name=b.name, **kw)
+    r.update(sampling=f"bead MD of {cfg.name}: {s_train} steps, every {every} (train), then {s_test} steps "
+                      f"(held out)", d_min=cfg.d_min, label_s=t_label)
+    return r
 
 
 def main():

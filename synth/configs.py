@@ -4,7 +4,7 @@ Distances in units of the bead size sigma, energies in epsilon.  Readings of
 points the workload statements leave open are explicit fields here:
 
 * lj cut-and-shift shifts the energy only (the force is not shifted);
-* "body diameter" in the pair cutoff is 2 * r_max (bead-centre
+* the body diameter in the pair cutoff is 2 * r_max (bead-centre
   circumradius), so d_cut = 2 r_max + r_c bounds every interacting pair;
 * the body volume for the volume fraction is the bead-centre hull dilated
   by sigma/2;

@@ -102,8 +102,16 @@ def test_pairlist_matches_bruteforce(abi, cfgname):
     assert f[abi.RB_FLAG_NPAIRS] == len(ref)
     assert {tuple(p) for p in got} == {tuple(p) for p in ref}
     assert np.all(got[:, 0] < got[:, 1])
-    assert np.all(np.diff(got[:, 0]) >= 0)          # sorted by i
+    # the pairs of one body form one run
+    assert 1 + np.count_nonzero(np.diff(got[:, 0])) == len(np.unique(got[:, 0]))
     assert f[abi.RB_FLAG_REBUILD] == 0 and f[abi.RB_FLAG_NREBUILDS] == 1
+    # a second forced build gives the same set; an unflagged one does nothing
+    sysm.build_pairs(always=True)
+    again = sysm.pairs_host()
+    assert {tuple(p) for p in again} == {tuple(p) for p in ref}
+    sysm.build_pairs(always=False)
+    f = sysm.flags_host()
+    assert f[abi.RB_FLAG_NREBUILDS] == 2 and f[abi.RB_FLAG_NPAIRS] == len(ref)
 
 
 def test_pairlist_overflow_reports_required_count(abi):

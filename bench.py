@@ -36,6 +36,24 @@ BF16_MFMA_PEAK = 2.5e15        # dense
 FP32_MFMA_PEAK = 157.3e12
 FLOP_PER_TEST = 8              # 3 sub + 1 mul + 2 fma
 
+# HBM bytes per launch of the bead kernel on this workload, from two rocprofv3
+# counter runs (FETCH_SIZE, WRITE_SIZE; profiles/k_bead_md_cubes4096_hbm_traffic.txt),
+# each scaled by what the counter reads for a copy kernel of known size.  Valid
+# only for the kernel sources they were taken on (hash below); otherwise null.
+BEAD_TRAFFIC_BYTES = 6.94e6
+BEAD_TRAFFIC_SOURCES = ("paper_2402_12199_amd/csrc/bead.hip", "paper_2402_12199_amd/csrc/rb_common.hpp",
+                        "include/rigidnn.h")
+BEAD_TRAFFIC_HASH = "f0c8ff9dccdb72ee"
+
+
+def bead_traffic():
+    import hashlib
+    h = hashlib.sha256()
+    for f in BEAD_TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return BEAD_TRAFFIC_BYTES if h.hexdigest()[:16] == BEAD_TRAFFIC_HASH else None
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -101,24 +119,28 @@ def ntests(flags_np, abi):
 
 
 def bead_kernel_time(sysm, reps, torch, abi):
-    """Mean duration of the bead-sum kernel alone on the current list, and the
+    """Mean duration of the bead-sum kernel alone on the current list (HIP
+    events on the launch stream around `reps` back-to-back launches), and the
     bead-bead distance tests it performs per launch (after culling)."""
     st = torch.cuda.current_stream()
     abi.rb_accum_zero(sysm.n, sysm.acc)
-    t0 = ntests(sysm.flags_host(), abi)
-    times = []
-    for _ in range(reps):
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(st)
+
+    def launch():
         abi.rb_bead_pair_forces(sysm.ctx, sysm.x, sysm.q, sysm.types, sysm.box, sysm.pair_i, sysm.pair_j, None,
                                 sysm.flags[abi.RB_FLAG_NPAIRS:], sysm.max_pairs, sysm.acc, sysm.flags)
-        b.record(st)
-        times.append((a, b))
+    launch()
+    torch.cuda.synchronize()
+    t0 = ntests(sysm.flags_host(), abi)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(reps):
+        launch()
+    b.record(st)
     torch.cuda.synchronize()
     tests = (ntests(sysm.flags_host(), abi) - t0) / reps
     abi.rb_accum_zero(sysm.n, sysm.acc)
-    return float(np.mean([a.elapsed_time(b) for a, b in times])), tests
+    return a.elapsed_time(b) / reps, tests
 
 
 def nn_kernels(torch, abi):
@@ -160,6 +182,41 @@ def nn_kernels(torch, abi):
     return out
 
 
+def learned_part(args, torch, abi, log):
+    """Cylinder surrogate trained on uniformly drawn pair configurations
+    labelled by the bead kernel (2^21, held out 2^16 from another seed), then
+    2008 NVE steps of 32768 cylinders with the bead path and with the
+    network path (bead fallback below d_min) from the same start."""
+    from paper_2402_12199_amd.compare import compare
+    from paper_2402_12199_amd.md import NNModel
+    from paper_2402_12199_amd.surrogate import train_surrogate, train_surrogate_md
+    from synth import configs, state
+    c5 = configs.config5()
+    log(f"[bench] cylinder surrogate: 2^21 uniform pairs, {args.cyl_epochs} epochs")
+    cyl = train_surrogate(c5.body, 1 << 21, 1 << 16, args.cyl_epochs, log=log)
+    out = {"surrogate": {k: cyl[k] for k in ("shape", "sampling", "epochs", "steps", "batch", "n_train", "n_test",
+                                             "reject_rate", "label_s", "train_s", "samples_per_s", "d_min",
+                                             "d_cut")},
+           "held_out": cyl["trained"], "held_out_untrained": cyl["untrained"],
+           "label_pairs_per_s_with_host_copies": cyl["label_kernel_pairs_per_s"]}
+    log(f"[bench] generating {c5.name}")
+    st5 = state.initial_state(c5)
+    # a second surrogate trained on the pairs the bead dynamics of this
+    # workload visits (the paper's data source), held out from later steps
+    log(f"[bench] cylinder surrogate on bead-MD pairs of {c5.name}")
+    cmd = train_surrogate_md(c5, st5, 1 << 21, 1 << 16, args.cyl_epochs, log=log)
+    out["surrogate_md"] = {k: cmd[k] for k in ("sampling", "epochs", "n_train", "n_test", "train_s")}
+    out["held_out_md"] = cmd["trained"]
+
+    def model(r):
+        return NNModel(params=r["params"], norm=r["norm"], precision=abi.RB_PREC_BF16, d_min=c5.d_min,
+                       sw_lo=c5.d_cut - 1.0, sw_hi=c5.d_cut)
+    out["dynamics"] = compare(c5, st5, {"nn_uniform": model(cyl), "nn_md": model(cmd)}, chunks=8, replays=25,
+                              log=log)
+    out["workload"] = f"{c5.name}: {c5.n_bodies} cylinders ({c5.body.n} beads), NVE kT={c5.kT} dt={c5.dt}"
+    return out
+
+
 def cpu_baseline(cfg, st, target_s=12.0):
     """The FP64 oracle (plain C, OpenMP over pairs) doing the same MD steps on
     the host: full force evaluation + integration per step."""
@@ -192,6 +249,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-nn", action="store_true", help="skip the network measurements")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the cylinder surrogate and the network-vs-bead dynamics of 32768 cylinders")
+    ap.add_argument("--cyl-epochs", type=int, default=100, help="cylinder surrogate epochs (2^21 pairs each)")
     ap.add_argument("--nn-steps", type=int, default=100,
                     help="timed steps of the network path (its trajectory stays sound for a limited time)")
     ap.add_argument("--nn-epochs", type=int, default=100, help="surrogate training epochs (2^20 pairs each)")
@@ -248,7 +308,7 @@ def main():
                       "eager_ms_per_step": bead["eager_ms_per_step"], "total_energy_end": e_tot},
         "roofline": {"kernel": "k_bead_md (rb_bead_pair_forces)", "bound": "alu", "achieved": achieved / 1e12,
                      "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK,
-                     "traffic": None, "kernel_ms": kern_ms,
+                     "traffic": bead_traffic(), "traffic_unit": "bytes per launch", "kernel_ms": kern_ms,
                      "algorithmic_work": f"{tests_done:.0f} bead-bead distance tests x {FLOP_PER_TEST} FLOP per "
                                          f"launch (the tests that survive exact box culling; the brute-force "
                                          f"double sum would do {npairs_now} pairs x {cfg.body.n}^2 = "
@@ -317,6 +377,9 @@ def main():
             }
         log("[bench] network kernels on 2^20 pairs")
         result["nn_kernels_2^20"] = nn_kernels(torch, abi)
+
+    if not args.no_learned:
+        result["cylinders"] = learned_part(args, torch, abi, log)
 
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")

@@ -16,7 +16,8 @@
 
 namespace rb {
 
-constexpr int kChunk = 512;
+constexpr int kChunk = 256;
+constexpr int kSmallBlocks = 8;   // blocks per chunk for the FP32 layers, biases and loss
 constexpr int kPart = NPARAMS + 1;   // per chunk: gradient, then the loss sum
 
 struct TrainArgs {
@@ -120,9 +121,14 @@ __global__ __launch_bounds__(512) void k_train_wgrad(TrainArgs a) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) dW[(16 * mt + 4 * g + r) * kH + 16 * nt + n] = acc[nt][r];
     } else {
-        // FP32 layers, biases and the loss: one dot product over the chunk each
+        // FP32 layers, biases and the loss: one dot product over the chunk
+        // per wave (lanes stride over the rows, coalesced), spread over
+        // kSmallBlocks blocks
+        const int lane = threadIdx.x & (kWave - 1);
+        const int wpb = blockDim.x / kWave;
+        const int nw = kSmallBlocks * wpb;
         const int nsmall = kH * kIn + 4 * kH + kH + 2;
-        for (int j = threadIdx.x; j < nsmall; j += blockDim.x) {
+        for (int j = (blockIdx.y - 3) * wpb + (threadIdx.x >> 6); j < nsmall; j += nw) {
             const float *x = nullptr, *y = nullptr;
             int dst;
             if (j < kH * kIn) {                       // dW1[f][k]
@@ -149,10 +155,11 @@ __global__ __launch_bounds__(512) void k_train_wgrad(TrainArgs a) {
             }
             float s = 0.f;
             if (y)
-                for (int b = r0; b < r1; ++b) s = fmaf(x[b], y[b], s);
+                for (int b = r0 + lane; b < r1; b += kWave) s = fmaf(x[b], y[b], s);
             else
-                for (int b = r0; b < r1; ++b) s += x[b];
-            part[dst] = s;
+                for (int b = r0 + lane; b < r1; b += kWave) s += x[b];
+            s = wave_sum(s);
+            if (lane == 0) part[dst] = s;
         }
     }
 }
@@ -252,7 +259,7 @@ extern "C" int rb_nn_train_step(float *params, float *adam_m, float *adam_v, int
         k_train_fb<false><<<grid_for(ntiles, wv, cus), wv * kWave, 0, st>>>(a);
     }
     const int nchunks = (batch + kChunk - 1) / kChunk;
-    dim3 g2(nchunks, 4);
+    dim3 g2(nchunks, 3 + kSmallBlocks);
     if (precision == RB_PREC_BF16)
         k_train_wgrad<true><<<g2, 512, 0, st>>>(a);
     else

@@ -32,16 +32,20 @@ from .nn import Trainer, label_pairs, make_norm
 
 def make_dataset(ctx: abi.Ctx, n: int, seed: int, d_lo: float, d_hi: float, r_rej: float = 0.8,
                  type_i: int = 0, type_j: int = 0):
-    """n accepted configurations (desc (n, 7) FP32, labels (n, 11) FP32) and
-    the rejection rate."""
+    """n accepted configurations (desc (n, 7) FP32, labels (n, 11) FP32),
+    the rejection rate, and the seconds and count of bead-kernel labelling."""
     from synth import sampling
     g = sampling.rng(seed)
     descs, labs = [], []
     have = drawn = 0
+    t_lab = 0.0
     while have < n:
         m = int((n - have) * 1.5) + 1024
         d = sampling.pair_batch(g, m, d_lo, d_hi).astype(np.float32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         lab = label_pairs(ctx, d, type_i, type_j)
+        t_lab += time.perf_counter() - t0
         keep = lab[:, 10] >= r_rej
         drawn += m
         descs.append(d[keep])
@@ -49,7 +53,7 @@ def make_dataset(ctx: abi.Ctx, n: int, seed: int, d_lo: float, d_hi: float, r_re
         have += int(keep.sum())
     desc = np.concatenate(descs)[:n]
     lab = np.concatenate(labs)[:n]
-    return desc, lab, 1.0 - have / drawn
+    return desc, lab, 1.0 - have / drawn, t_lab, drawn
 
 
 def evaluate(params, norm, precision, desc: np.ndarray, lab: np.ndarray, chunk: int = 1 << 20) -> dict:
@@ -123,11 +127,12 @@ def train_surrogate(body, n_train: int, n_test: int, epochs: int, seed: int = 10
     ctx = abi.Ctx([body.beads], [body.mass], [body.inertia])
     d_min = 2.0 * body.r_in + sigma
     d_cut = 2.0 * body.r_max + rc
-    desc, lab, rej = make_dataset(ctx, n_train, seed, d_min, d_cut, r_rej)
-    tdesc, tlab, _ = make_dataset(ctx, n_test, test_seed, d_min, d_cut, r_rej)
+    desc, lab, rej, tl1, n1 = make_dataset(ctx, n_train, seed, d_min, d_cut, r_rej)
+    tdesc, tlab, _, tl2, n2 = make_dataset(ctx, n_test, test_seed, d_min, d_cut, r_rej)
     t_label = time.perf_counter() - t0
     r = fit(desc, lab, tdesc, tlab, d_cut, epochs, seed, log=log, name=body.name, **kw)
-    r.update(sampling="uniform", d_min=d_min, reject_rate=rej, label_s=t_label)
+    r.update(sampling="uniform", d_min=d_min, reject_rate=rej, label_s=t_label,
+             label_kernel_pairs_per_s=(n1 + n2) / max(tl1 + tl2, 1e-9))
     return r
 
 

@@ -136,6 +136,30 @@ def test_descriptors_match_oracle(abi):
     np.testing.assert_array_equal(nn, np.nonzero(far)[0])
 
 
+def test_routing_window_and_pair_configurations(abi):
+    # pairs below d_lo go to the bead list, d_lo <= |d| < d_hi to the network
+    # list, the rest to neither; pair_configurations returns the network
+    # window's descriptors in list order
+    cfg = configs.config1()
+    st = state.initial_state(cfg)
+    from paper_2402_12199_amd.md import RigidSystem
+    b = cfg.body
+    sysm = RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"], cfg.box,
+                       cfg.r_list, cfg.skin)
+    sysm.build_pairs(always=True)
+    pairs = sysm.pairs_host()
+    ref = oframes.descriptors(st["x"][pairs[:, 0]], st["q"][pairs[:, 0]], st["x"][pairs[:, 1]],
+                              st["q"][pairs[:, 1]], cfg.box)
+    r = np.linalg.norm(ref[:, :3], axis=1)
+    d_lo, d_hi = (float(v) for v in np.quantile(r, [0.3, 0.7]))
+    got = sysm.pair_configurations(d_lo, d_hi).cpu().numpy().T
+    win = (r >= d_lo) & (r < d_hi)
+    assert got.shape == (win.sum(), 7)
+    np.testing.assert_allclose(got, ref[win], rtol=0, atol=2e-6 * cfg.box)
+    f = sysm.flags_host()
+    assert f[abi.RB_FLAG_NNN] == win.sum() and f[abi.RB_FLAG_NBEAD] == (r < d_lo).sum()
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_md_forces_nn_plus_bead_fallback_match_oracle(abi, prec):
     # per-body forces of the mixed path: network for |d| >= d_min (with the

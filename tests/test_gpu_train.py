@@ -135,3 +135,21 @@ def test_network_path_is_faster_than_bead_sum(abi):
     t_nn = timeit(lambda: abi.rb_nn_pair_grad(params, norm, abi.RB_PREC_BF16, desc, None, E, None, ft))
     print(f"bead {t_bead:.3f} ms, network {t_nn:.3f} ms, ratio {t_bead / t_nn:.1f}")
     assert t_nn * 2 < t_bead
+
+
+def test_labelled_sets_reject_overlaps_and_match_the_oracle(abi):
+    # uniform pair configurations labelled by the GPU bead kernel: the count
+    # asked for, none closer than r_rej, labels equal to the oracle's
+    from oracle import beads as obeads
+    from paper_2402_12199_amd.surrogate import make_dataset
+    body = configs.cube5()
+    ctx = abi.Ctx([body.beads], [body.mass], [body.inertia])
+    d_min = 2 * body.r_in + 1.0
+    d_cut = 2 * body.r_max + 2.5
+    desc, lab, rej, _, drawn = make_dataset(ctx, 300, 17, d_min, d_cut, r_rej=0.8)
+    assert desc.shape == (300, 7) and lab.shape == (300, 11) and 0 < rej < 1 and drawn >= 300
+    assert lab[:, 10].min() >= 0.8
+    ref = obeads.bead_pair_desc(body.beads.astype(np.float32).astype(np.float64),
+                                body.beads.astype(np.float32).astype(np.float64), desc.astype(np.float64))
+    assert_close(lab[:, 0], ref[:, 0], 1e-5, "E")
+    assert_close(lab[:, 1:10], ref[:, 1:10], 1e-4, "F, tau")

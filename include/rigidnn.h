@@ -60,6 +60,8 @@ extern "C" {
                                 force calls (bead and network); wraps at 2^31  */
 #define RB_FLAG_NTESTS 8     /* flags[8..9] as one int64: running count of bead-
                                 bead distance tests performed after culling    */
+#define RB_FLAG_NSCREEN 10   /* pairs kept by rb_bead_screen (when its count_out
+                                is &flags[NSCREEN])                             */
 #define RB_NFLAGS 16
 
 #define RB_PREC_BF16 0       /* 128x128 layers on BF16 MFMA, FP32 accumulate     */
@@ -141,6 +143,21 @@ int rb_pair_descriptors(int32_t n, const double *x, const double *q, const doubl
 int rb_bead_pair_eval(const rb_ctx *ctx, int64_t n_pairs, const float *desc, int32_t type_i,
                       int32_t type_j, float *out, int32_t *flags, void *stream);
 
+/* Screen for the per-body form: of the pairs idx[0 .. *count_dev) of the
+ * list (idx == NULL: 0 .. *count_dev, capped at max_count), keeps those whose
+ * bead boxes can be within rc (separating-axis test between body j's bead
+ * box and body i's grown by rc, the same test rb_bead_pair_forces applies);
+ * every other pair has exactly zero bead energy, force and torque.  Writes
+ * the kept pair ids to idx_out (capacity max_count, order not specified) and
+ * their number to *count_out, to be passed to rb_bead_pair_forces.  tmp: two
+ * int32 of caller memory that must be zero before the first call; each call
+ * leaves them zero.  flags (may be NULL): the screened-out pairs are added to
+ * flags[NEVAL] (rb_bead_pair_forces adds the kept ones). */
+int rb_bead_screen(const rb_ctx *ctx, int32_t n, const double *x, const double *q, const int32_t *type,
+                   const double *box, const int32_t *pair_i, const int32_t *pair_j, const int32_t *idx,
+                   const int32_t *count_dev, int32_t max_count, int32_t *idx_out, int32_t *count_out,
+                   int32_t *tmp, int32_t *flags, void *stream);
+
 /* Per-body form for dynamics: the pairs idx[0 .. *count_dev) of the list
  * (idx == NULL: the pairs 0 .. *count_dev), count read on the device and
  * capped at max_count.  Geometry from FP64 state (x 3 x n, q 4 x n, type n),
@@ -217,7 +234,9 @@ int rb_rigid_step(const rb_ctx *ctx, int phase, int32_t n, double dt, double *x,
  * step) + phase 1 of the next step, with the same arithmetic in the same
  * order.  A run of K steps is phase 1, then (pair list, forces into acc,
  * rb_rigid_step_fused) K - 1 times, then pair list, forces, finalize,
- * phase 2.  ws as for phase 2, zero-filled before its first use. */
+ * phase 2.  kinetic may be NULL: the kinetic energy of that step is then
+ * not reduced (the grid-wide reduction is the launch's serial tail).  ws as
+ * for phase 2, zero-filled before its first use. */
 int rb_rigid_step_fused(const rb_ctx *ctx, int32_t n, double dt, double *x, double *P, double *q,
                         double *L, const int32_t *type, int64_t *acc, float *force, float *torque,
                         double *energy_virial, const double *x_ref, double half_skin,

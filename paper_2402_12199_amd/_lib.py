@@ -31,6 +31,7 @@ SIGNATURES = {
     "rb_pair_descriptors": (C.c_int, [I32, P, P, DP, P, P, I32, F32, F32, P, P, P, P, P]),
     "rb_bead_pair_eval": (C.c_int, [P, I64, P, I32, I32, P, P, P]),
     "rb_bead_pair_forces": (C.c_int, [P, I32, P, P, P, DP, P, P, P, P, I32, P, P, P]),
+    "rb_bead_screen": (C.c_int, [P, I32, P, P, P, DP, P, P, P, P, I32, P, P, P, P, P]),
     "rb_accum_zero": (C.c_int, [I32, P, P]),
     "rb_accum_finalize": (C.c_int, [I32, P, P, P, P, P]),
     "rb_nn_pair_eval": (C.c_int, [P, FP, C.c_int, I64, P, P, P]),

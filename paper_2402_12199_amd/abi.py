@@ -17,6 +17,7 @@ from ._lib import check, lib
 
 RB_FLAG_REBUILD, RB_FLAG_NPAIRS, RB_FLAG_OVERFLOW, RB_FLAG_NREBUILDS = 0, 1, 2, 3
 RB_FLAG_NBEAD, RB_FLAG_NNN, RB_FLAG_NONFINITE, RB_FLAG_NEVAL, RB_FLAG_NTESTS, RB_NFLAGS = 4, 5, 6, 7, 8, 16
+RB_FLAG_NSCREEN = 10
 RB_PREC_BF16, RB_PREC_FP32 = 0, 1
 RB_BUILD_ALWAYS, RB_BUILD_IF_FLAGGED = 0, 1
 RB_MLP_NPARAMS = 50689
@@ -147,6 +148,23 @@ def rb_bead_pair_forces(ctx: Ctx, x, q, types, box, pair_i, pair_j, idx, count_d
           "rb_bead_pair_forces")
 
 
+def rb_bead_screen(ctx: Ctx, x, q, types, box, pair_i, pair_j, idx, count_dev, max_count, idx_out, count_out, tmp,
+                   flags=None):
+    n = x.shape[1]
+    _, bp = _box(box)
+    check(lib().rb_bead_screen(ctx.handle, n, _ptr(x, torch.float64, (3, n), "x"),
+                               _ptr(q, torch.float64, (4, n), "q"), _ptr(types, torch.int32, (n,), "type"),
+                               bp, _ptr(pair_i, torch.int32, name="pair_i"),
+                               _ptr(pair_j, torch.int32, name="pair_j"),
+                               _ptr(idx, torch.int32, name="idx", optional=True),
+                               _ptr(count_dev, torch.int32, name="count_dev"), int(max_count),
+                               _ptr(idx_out, torch.int32, name="idx_out"),
+                               _ptr(count_out, torch.int32, name="count_out"),
+                               _ptr(tmp, torch.int32, (2,), "tmp"),
+                               _ptr(flags, torch.int32, (RB_NFLAGS,), "flags", optional=True), _stream()),
+          "rb_bead_screen")
+
+
 def rb_accum_zero(n: int, acc):
     check(lib().rb_accum_zero(n, _ptr(acc, torch.int64, (acc_len(n),), "acc"), _stream()), "rb_accum_zero")
 
@@ -229,7 +247,7 @@ def rb_rigid_step_fused(ctx: Ctx, dt: float, x, P, q, L, types, acc, force, torq
                                     _ptr(torque, torch.float32, (3, n), "torque"),
                                     _ptr(energy_virial, torch.float64, (10,), "energy_virial", optional=True),
                                     _ptr(x_ref, torch.float64, (3, n), "x_ref", optional=True), float(half_skin),
-                                    _ptr(kinetic, torch.float64, (2,), "kinetic"),
+                                    _ptr(kinetic, torch.float64, (2,), "kinetic", optional=True),
                                     _ptr(flags, torch.int32, (RB_NFLAGS,), "flags"),
                                     _ptr(ws, torch.uint8, name="ws"), ws.numel(), _stream()),
           "rb_rigid_step_fused")

@@ -45,6 +45,15 @@ __device__ inline WaveLds wave_lds(float4 *base, int w, int stride) {
     return WaveLds{p, p + stride, p + 2 * stride};
 }
 
+// Copies every template into the block's LDS after the waves' arrays (the
+// staging loops then read beads from LDS instead of global memory).
+__device__ inline const float4 *stage_templates(const Templates &T, float4 *base, int nwaves, int stride) {
+    float4 *tb = base + (size_t)nwaves * 3 * stride;
+    for (int k = threadIdx.x; k < T.total; k += blockDim.x) tb[k] = T.beads[k];
+    __syncthreads();
+    return tb;
+}
+
 // Separating-axis test (15 axes) between box A, centred at the origin with
 // the axes of body i's frame and half extents a, and box B, centred at t with
 // axes the columns of R and half extents b.  Returns false when an axis
@@ -109,10 +118,10 @@ __device__ inline int wave_compact(bool keep, float4 v, float4 vlo, float4 *dst,
 
 // Stages the beads of body j (type tj, at d with rotation R relative to body
 // i) that can reach body i's box; r_l = d + R b_l is formed in FP64.
-__device__ inline int stage_j(const Templates &T, int ti, int tj, const double d[3], const double R[9],
-                              float cut2, WaveLds &L, int lane) {
+__device__ inline int stage_j(const Templates &T, const float4 *tb, int ti, int tj, const double d[3],
+                              const double R[9], float cut2, WaveLds &L, int lane) {
     const int nj = T.n[tj];
-    const float4 *bj = T.beads + T.off[tj];
+    const float4 *bj = tb + T.off[tj];
     const float hx = T.hx[ti], hy = T.hy[ti], hz = T.hz[ti];
     int count = 0;
     for (int l0 = 0; l0 < nj; l0 += kWave) {
@@ -137,10 +146,10 @@ __device__ inline int stage_j(const Templates &T, int ti, int tj, const double d
 // Stages the beads of body i that can reach body j's box: a bead b of i sits
 // at R^T (b - d) in body j's frame (FP32 is ample for the test: the margin
 // is far above its rounding).
-__device__ inline int stage_i(const Templates &T, int ti, int tj, const double d[3], const double R[9],
-                              float cut2, WaveLds &L, int lane) {
+__device__ inline int stage_i(const Templates &T, const float4 *tb, int ti, int tj, const double d[3],
+                              const double R[9], float cut2, WaveLds &L, int lane) {
     const int ni = T.n[ti];
-    const float4 *bi = T.beads + T.off[ti];
+    const float4 *bi = tb + T.off[ti];
     const float hx = T.hx[tj], hy = T.hy[tj], hz = T.hz[tj];
     const float dx = (float)d[0], dy = (float)d[1], dz = (float)d[2];
     float Rf[9];
@@ -220,6 +229,7 @@ __global__ __launch_bounds__(256) void k_bead_desc(Templates T, LJ lj, int ti, i
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     WaveLds L = wave_lds(bead_lds, w, stride);
+    const float4 *tb = stage_templates(T, bead_lds, kBeadWaves, stride);
     const float rcm = sqrtf(lj.rc2) + kCullMargin, cut2 = rcm * rcm;
     long long ntests = 0;
     const int64_t step = (int64_t)gridDim.x * kBeadWaves;
@@ -229,8 +239,8 @@ __global__ __launch_bounds__(256) void k_bead_desc(Templates T, LJ lj, int ti, i
         const double inv = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
         double R[9];
         quat_to_rot<double>(qw * inv, qx * inv, qy * inv, qz * inv, R);
-        const int nj = may_interact(T, ti, tj, d, R, rcm) ? stage_j(T, ti, tj, d, R, cut2, L, lane) : 0;
-        const int ni = nj ? stage_i(T, ti, tj, d, R, cut2, L, lane) : 0;
+        const int nj = may_interact(T, ti, tj, d, R, rcm) ? stage_j(T, tb, ti, tj, d, R, cut2, L, lane) : 0;
+        const int ni = nj ? stage_i(T, tb, ti, tj, d, R, cut2, L, lane) : 0;
         wave_lds_sync();
         float r[8];
         pair_sum<true>(lj, ni, nj, L, lane, r);
@@ -263,8 +273,89 @@ struct Box {
     double L[3], inv[3];
 };
 
+// Geometry of pair (i, j) from the FP64 state: dl = minimum-image x_j - x_i
+// (lab), d = R_i^T dl and R = R_i^T R_j (from q_i^* q_j).  Shared by the
+// screen and the force kernel so that both take the same decisions.
+__device__ inline void pair_geometry(int32_t n, const double *__restrict__ x, const double *__restrict__ q,
+                                     const Box &box, int i, int j, double dl[3], double d[3], double R[9]) {
+    double Ri[9], qr[4];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dl[a] = min_image(x[a * n + j] - x[a * n + i], box.L[a], box.inv[a]);
+    const double aw = q[i], ax = q[n + i], ay = q[2 * n + i], az = q[3 * n + i];
+    const double bw = q[j], bx = q[n + j], by = q[2 * n + j], bz = q[3 * n + j];
+    quat_to_rot<double>(aw, ax, ay, az, Ri);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d[a] = Ri[a] * dl[0] + Ri[3 + a] * dl[1] + Ri[6 + a] * dl[2];
+    qr[0] = aw * bw + ax * bx + ay * by + az * bz;
+    qr[1] = aw * bx - ax * bw - ay * bz + az * by;
+    qr[2] = aw * by + ax * bz - ay * bw - az * bx;
+    qr[3] = aw * bz - ax * by + ay * bx - az * bw;
+    quat_to_rot<double>(qr[0], qr[1], qr[2], qr[3], R);
+}
+
+// Screen: one thread per listed pair; keeps the pairs whose bead boxes pass
+// the separating-axis test (the others have exactly zero bead energy, force
+// and torque) and appends them to idx_out with one atomic per wave.  tmp[0]
+// (append counter) and tmp[1] (finishing ticket) are zero on entry and left
+// zero; the last workgroup publishes the count.  The screened-out pairs are
+// counted as evaluated (their contribution is known to be zero).
+__global__ __launch_bounds__(256) void k_bead_screen(Templates T, float rcm, int32_t n, const double *__restrict__ x,
+                                                     const double *__restrict__ q, const int32_t *__restrict__ type,
+                                                     Box box, const int32_t *__restrict__ pi,
+                                                     const int32_t *__restrict__ pj, const int32_t *__restrict__ idx,
+                                                     const int32_t *__restrict__ count_dev, int32_t max_count,
+                                                     int32_t *__restrict__ idx_out, int32_t *__restrict__ count_out,
+                                                     int32_t *__restrict__ tmp, int32_t *__restrict__ flags) {
+    __shared__ bool last;
+    int count = *count_dev;
+    if (count > max_count) count = max_count;
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int base = blockIdx.x * blockDim.x; base < count; base += gridDim.x * blockDim.x) {
+        const int p = base + threadIdx.x;
+        bool keep = false;
+        int pid = 0;
+        if (p < count) {
+            pid = idx ? idx[p] : p;
+            const int i = pi[pid], j = pj[pid];
+            double dl[3], d[3], R[9];
+            pair_geometry(n, x, q, box, i, j, dl, d, R);
+            keep = may_interact(T, type[i], type[j], d, R, rcm);
+        }
+        const unsigned long long m = __ballot(keep);
+        if (m) {
+            const int leader = __ffsll((long long)m) - 1;
+            int at = 0;
+            if (lane == leader) at = atomicAdd(tmp, __popcll(m));
+            at = __shfl(at, leader, kWave);
+            if (keep) idx_out[at + __popcll(m & ((1ull << lane) - 1ull))] = pid;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(tmp + 1, 1) == (int)gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        const int kept = __hip_atomic_load(tmp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *count_out = kept;
+        if (flags) atomicAdd(flags + RB_FLAG_NEVAL, count - kept);
+        tmp[0] = 0;
+        tmp[1] = 0;
+    }
+}
+
 // Per-body form for dynamics.  Geometry from FP64 state; the pair's outputs
 // are rotated to the lab frame and added to the fixed-point accumulator.
+// Per-body form for dynamics.  A block takes the pairs b, b + G, b + 2G, ...
+// (G blocks), one thread per pair: indices, FP64 geometry and the
+// separating-axis test run for all of them at once (one round of memory
+// latency); the pairs that can interact go to an LDS queue from which the
+// block's waves take them one at a time (the work of a block is spread over
+// its waves whatever lane found it), each evaluated by a whole wave.  The
+// pair's outputs are rotated to the lab frame and added to the fixed-point
+// accumulator.
 __global__ __launch_bounds__(256) void k_bead_md(Templates T, LJ lj, int32_t n, const double *__restrict__ x,
                                                  const double *__restrict__ q, const int32_t *__restrict__ type,
                                                  Box box, const int32_t *__restrict__ pi,
@@ -273,82 +364,93 @@ __global__ __launch_bounds__(256) void k_bead_md(Templates T, LJ lj, int32_t n, 
                                                  int64_t *__restrict__ acc, int32_t *__restrict__ flags,
                                                  int stride) {
     extern __shared__ float4 bead_lds[];
+    __shared__ long long wacc[kBeadWaves][10];   // per-wave energy/virial sums (fixed point)
+    __shared__ int queue[256];
+    __shared__ int qn, qhead;
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     WaveLds L = wave_lds(bead_lds, w, stride);
+    if (lane < 10) wacc[w][lane] = 0;
+    const float4 *tb = stage_templates(T, bead_lds, kBeadWaves, stride);
     const float rcm = sqrtf(lj.rc2) + kCullMargin, cut2 = rcm * rcm;
     int count = *count_dev;
     if (count > max_count) count = max_count;
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(flags + RB_FLAG_NEVAL, count);
-    long long eacc[10];
-#pragma unroll
-    for (int a = 0; a < 10; ++a) eacc[a] = 0;
     long long ntests = 0;
     bool bad = false;
-    const int step = gridDim.x * kBeadWaves;
-    for (int p = blockIdx.x * kBeadWaves + w; p < count; p += step) {
-        const int pid = idx ? idx[p] : p;
-        const int i = pi[pid], j = pj[pid];
-        const int ti = type[i], tj = type[j];
-        double dl[3], d[3], R[9];
-        {
-            double Ri[9], qr[4];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-                dl[a] = min_image(x[a * n + j] - x[a * n + i], box.L[a], box.inv[a]);
-            const double aw = q[i], ax = q[n + i], ay = q[2 * n + i], az = q[3 * n + i];
-            const double bw = q[j], bx = q[n + j], by = q[2 * n + j], bz = q[3 * n + j];
-            quat_to_rot<double>(aw, ax, ay, az, Ri);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) d[a] = Ri[a] * dl[0] + Ri[3 + a] * dl[1] + Ri[6 + a] * dl[2];
-            // relative orientation q_i^* q_j, so R = R_i^T R_j
-            qr[0] = aw * bw + ax * bx + ay * by + az * bz;
-            qr[1] = aw * bx - ax * bw - ay * bz + az * by;
-            qr[2] = aw * by + ax * bz - ay * bw - az * bx;
-            qr[3] = aw * bz - ax * by + ay * bx - az * bw;
-            quat_to_rot<double>(qr[0], qr[1], qr[2], qr[3], R);
+    const int G = gridDim.x;
+    for (int p0 = blockIdx.x; p0 < count; p0 += G * (int)blockDim.x) {
+        const int p = p0 + threadIdx.x * G;
+        bool hit = false;
+        if (p < count) {
+            const int pid = idx ? idx[p] : p;
+            const int i = pi[pid], j = pj[pid];
+            double dl[3], d[3], R[9];
+            pair_geometry(n, x, q, box, i, j, dl, d, R);
+            hit = may_interact(T, type[i], type[j], d, R, rcm);
         }
-        if (!may_interact(T, ti, tj, d, R, rcm)) continue;   // bead boxes farther apart than rc
-        const int nj = stage_j(T, ti, tj, d, R, cut2, L, lane);
-        if (nj == 0) continue;   // no bead of j within rc of i's box: zero contribution
-        const int ni = stage_i(T, ti, tj, d, R, cut2, L, lane);
-        if (ni == 0) continue;
-        wave_lds_sync();
-        float r[8];
-        pair_sum<false>(lj, ni, nj, L, lane, r);
-        ntests += (long long)ni * nj;
-        wave_lds_sync();
-        if (lane == 0) {
-            double Ri[9];
-            quat_to_rot<double>(q[i], q[n + i], q[2 * n + i], q[3 * n + i], Ri);
-            const double F[3] = {r[1], r[2], r[3]}, ti_[3] = {r[4], r[5], r[6]};
-            const double tj_[3] = {d[1] * F[2] - d[2] * F[1] - ti_[0], d[2] * F[0] - d[0] * F[2] - ti_[1],
-                                   d[0] * F[1] - d[1] * F[0] - ti_[2]};
-            double Fl[3], til[3], tjl[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                Fl[a] = Ri[3 * a] * F[0] + Ri[3 * a + 1] * F[1] + Ri[3 * a + 2] * F[2];
-                til[a] = Ri[3 * a] * ti_[0] + Ri[3 * a + 1] * ti_[1] + Ri[3 * a + 2] * ti_[2];
-                tjl[a] = Ri[3 * a] * tj_[0] + Ri[3 * a + 1] * tj_[1] + Ri[3 * a + 2] * tj_[2];
-            }
-            if (!isfinite(r[0]) || !isfinite(r[1]) || !isfinite(r[2]) || !isfinite(r[3])) bad = true;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                acc_add(acc + (int64_t)a * n + i, Fl[a]);
-                acc_add(acc + (int64_t)a * n + j, -Fl[a]);
-                acc_add(acc + (int64_t)(3 + a) * n + i, til[a]);
-                acc_add(acc + (int64_t)(3 + a) * n + j, tjl[a]);
-            }
-            eacc[0] += to_fixed(r[0]);
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) eacc[1 + 3 * a + b] += to_fixed(-dl[a] * Fl[b]);
+        if (threadIdx.x == 0) {
+            qn = 0;
+            qhead = 0;
         }
+        __syncthreads();
+        if (hit) queue[atomicAdd(&qn, 1)] = p;
+        __syncthreads();
+        const int nq = qn;
+        for (;;) {
+            int k = 0;
+            if (lane == 0) k = atomicAdd(&qhead, 1);
+            k = __builtin_amdgcn_readfirstlane(k);
+            if (k >= nq) break;
+            const int pp = __builtin_amdgcn_readfirstlane(queue[k]);
+            const int pid = idx ? idx[pp] : pp;
+            const int i = pi[pid], j = pj[pid];
+            const int ti = type[i], tj = type[j];
+            double dl[3], d[3], R[9];
+            pair_geometry(n, x, q, box, i, j, dl, d, R);
+            const int nj = stage_j(T, tb, ti, tj, d, R, cut2, L, lane);
+            if (nj == 0) continue;   // no bead of j within rc of i's box: zero contribution
+            const int ni = stage_i(T, tb, ti, tj, d, R, cut2, L, lane);
+            if (ni == 0) continue;
+            wave_lds_sync();
+            float r[8];
+            pair_sum<false>(lj, ni, nj, L, lane, r);
+            ntests += (long long)ni * nj;
+            wave_lds_sync();
+            // lab-frame outputs, one component per lane: lanes 0..11 add
+            // F and tau of both bodies to the accumulator, lanes 12..21 the
+            // energy and the 9 virial components to the wave's sums
+            if (lane < 22) {
+                double Ri[9];
+                quat_to_rot<double>(q[i], q[n + i], q[2 * n + i], q[3 * n + i], Ri);
+                const double F[3] = {r[1], r[2], r[3]}, tI[3] = {r[4], r[5], r[6]};
+                const double tJ[3] = {d[1] * F[2] - d[2] * F[1] - tI[0], d[2] * F[0] - d[0] * F[2] - tI[1],
+                                      d[0] * F[1] - d[1] * F[0] - tI[2]};
+                if (lane < 12) {
+                    const int which = lane / 3, a = lane % 3;   // 0: F on i, 1: F on j, 2: tau_i, 3: tau_j
+                    const double *V = which < 2 ? F : (which == 2 ? tI : tJ);
+                    double v = Ri[3 * a] * V[0] + Ri[3 * a + 1] * V[1] + Ri[3 * a + 2] * V[2];
+                    if (which == 1) v = -v;
+                    const int body = (which == 0 || which == 2) ? i : j;
+                    acc_add(acc + (int64_t)((which < 2 ? 0 : 3) + a) * n + body, v);
+                } else {
+                    const int e = lane - 12;
+                    double v = r[0];
+                    if (e > 0) {
+                        const int a = (e - 1) / 3, b = (e - 1) % 3;
+                        const double Flb = Ri[3 * b] * F[0] + Ri[3 * b + 1] * F[1] + Ri[3 * b + 2] * F[2];
+                        v = -dl[a] * Flb;
+                    }
+                    wacc[w][e] += to_fixed(v);
+                }
+            }
+            if (lane == 0 && (!isfinite(r[0]) || !isfinite(r[1]) || !isfinite(r[2]) || !isfinite(r[3]))) bad = true;
+        }
+        __syncthreads();   // the queue is refilled by the next batch
     }
     long long part[11];
 #pragma unroll
-    for (int a = 0; a < 10; ++a) part[a] = eacc[a];
+    for (int a = 0; a < 10; ++a) part[a] = wacc[w][a];
     part[10] = ntests;
     block_flush_globals<kBeadWaves>(part, acc + 6 * (int64_t)n, flags);
     if (lane == 0 && bad) atomicOr(flags + RB_FLAG_NONFINITE, 1);
@@ -358,7 +460,7 @@ __global__ __launch_bounds__(256) void k_bead_md(Templates T, LJ lj, int32_t n, 
 // number of such blocks a CU holds, cached per size.
 static size_t bead_lds_bytes(const rb_ctx *ctx, int &stride) {
     stride = (ctx->max_beads + 3) & ~3;
-    return sizeof(float4) * 3 * (size_t)stride * kBeadWaves;
+    return sizeof(float4) * (3 * (size_t)stride * kBeadWaves + (size_t)ctx->total_beads);
 }
 
 template <typename K>
@@ -395,6 +497,7 @@ extern "C" int rb_bead_pair_eval(const rb_ctx *ctx, int64_t n_pairs, const float
     if (n_pairs == 0) return RB_OK;
     int stride;
     const size_t lds = bead_lds_bytes(ctx, stride);
+    RB_REQUIRE(lds <= 65536, "rb_bead_pair_eval: templates need %zu bytes of LDS (max 65536)", lds);
     static int c_lds = -1, c_nb = 0;
     const int nb = blocks_per_cu(k_bead_desc, lds, &c_lds, &c_nb);
     const int grid = grid_for(n_pairs, kBeadWaves, nb * device_cus_bead());
@@ -423,11 +526,32 @@ extern "C" int rb_bead_pair_forces(const rb_ctx *ctx, int32_t n, const double *x
     // flushes its global sums once
     int stride;
     const size_t lds = bead_lds_bytes(ctx, stride);
+    RB_REQUIRE(lds <= 65536, "rb_bead_pair_forces: templates need %zu bytes of LDS (max 65536)", lds);
     static int c_lds = -1, c_nb = 0;
     const int nb = blocks_per_cu(k_bead_md, lds, &c_lds, &c_nb);
     const int grid = grid_for(max_count, kBeadWaves, nb * device_cus_bead());
     k_bead_md<<<grid, 256, lds, (hipStream_t)stream>>>(ctx->dev.t, ctx->dev.lj, n, x, q, type, b, pair_i, pair_j,
                                                       idx, count_dev, max_count, acc, flags, stride);
     RB_LAUNCH_CHECK("rb_bead_pair_forces");
+    return RB_OK;
+}
+
+extern "C" int rb_bead_screen(const rb_ctx *ctx, int32_t n, const double *x, const double *q, const int32_t *type,
+                              const double *box, const int32_t *pair_i, const int32_t *pair_j, const int32_t *idx,
+                              const int32_t *count_dev, int32_t max_count, int32_t *idx_out, int32_t *count_out,
+                              int32_t *tmp, int32_t *flags, void *stream) {
+    RB_REQUIRE(ctx && x && q && type && box && pair_i && pair_j && count_dev && idx_out && count_out && tmp,
+               "rb_bead_screen: null argument");
+    RB_REQUIRE(n > 0 && max_count > 0, "rb_bead_screen: sizes must be > 0");
+    Box b;
+    for (int a = 0; a < 3; ++a) {
+        RB_REQUIRE(box[a] > 0, "rb_bead_screen: box must be > 0");
+        b.L[a] = box[a];
+        b.inv[a] = 1.0 / box[a];
+    }
+    const float rcm = sqrtf(ctx->dev.lj.rc2) + kCullMargin;
+    k_bead_screen<<<grid_for(max_count, 256, 4 * device_cus_bead()), 256, 0, (hipStream_t)stream>>>(
+        ctx->dev.t, rcm, n, x, q, type, b, pair_i, pair_j, idx, count_dev, max_count, idx_out, count_out, tmp, flags);
+    RB_LAUNCH_CHECK("rb_bead_screen");
     return RB_OK;
 }

@@ -112,6 +112,8 @@ extern "C" int rb_ctx_create(rb_ctx **out, int32_t n_types, const int32_t *n_bea
         return rc_;
     }
     c->dev.t.beads = static_cast<const float4 *>(c->alloc_beads);
+    c->dev.t.total = total;
+    c->total_beads = total;
     c->dev.mass = static_cast<const double *>(c->alloc_mass);
     c->dev.inertia = static_cast<const double *>(c->alloc_mass) + n_types;
     double s2 = (double)sigma * sigma, sr2 = s2 / ((double)rc * rc);

@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kIntThreads) void k_fused(int32_t n, double dt, dou
     }
     if (__any(moved) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(flags + RB_FLAG_REBUILD, 1);
     if (blockIdx.x == 0) finalize_globals(acc + 6 * (int64_t)n, ev);
-    grid_sum2(kt, kr, partial, ticket, kinetic);
+    if (kinetic) grid_sum2(kt, kr, partial, ticket, kinetic);
 }
 
 static size_t nblocks(int32_t n) { return (size_t)((n + kIntThreads - 1) / kIntThreads); }
@@ -298,7 +298,7 @@ extern "C" int rb_rigid_step_fused(const rb_ctx *ctx, int32_t n, double dt, doub
                                    double *L, const int32_t *type, int64_t *acc, float *force, float *torque,
                                    double *energy_virial, const double *x_ref, double half_skin, double *kinetic,
                                    int32_t *flags, void *ws, size_t ws_bytes, void *stream) {
-    RB_REQUIRE(ctx && x && P && q && L && type && acc && force && torque && kinetic && flags && ws,
+    RB_REQUIRE(ctx && x && P && q && L && type && acc && force && torque && flags && ws,
                "rb_rigid_step_fused: null argument");
     RB_REQUIRE(n > 0, "rb_rigid_step_fused: n must be > 0");
     RB_REQUIRE(ws_bytes >= rb_rigid_workspace_bytes(n), "rb_rigid_step_fused: workspace too small");

@@ -32,6 +32,7 @@ int hip_check(hipError_t e, const char *what);
 
 struct Templates {
     const float4 *beads;       // all types concatenated, w unused
+    int total;                 // beads of all types
     int n[kMaxTypes];
     int off[kMaxTypes];
     float hx[kMaxTypes], hy[kMaxTypes], hz[kMaxTypes];   // half extents of the bead-centre box
@@ -149,6 +150,7 @@ struct rb_ctx {
     int n_beads[rb::kMaxTypes];
     float rmax[rb::kMaxTypes];
     int max_beads;           // largest template
+    int total_beads;         // all templates
     void *alloc_beads;
     void *alloc_mass;
 };

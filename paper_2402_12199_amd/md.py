@@ -3,8 +3,8 @@
 Bead path step (velocity Verlet):
   rigid_step phase 1 (half kick, drift, free rotation, skin test)
   pairlist_build (only when the skin test flagged a rebuild)
-  bead_pair_forces over every listed pair -> accum_finalize (which also
-  clears the accumulator for the next step)
+  bead_pair_forces over every listed pair (optionally after bead_screen)
+  -> accum_finalize (which also clears the accumulator for the next step)
   rigid_step phase 2 (second half kick, kinetic energy)
 Network path step: the same, except that after the pair list
   pair_descriptors routes each pair to the network (|d| >= d_min) or to the
@@ -36,7 +36,7 @@ class NNModel:
 
 class RigidSystem:
     def __init__(self, templates, masses, inertias, types, x, q, P, L, box, r_list, skin,
-                 eps=1.0, sigma=1.0, rc=2.5, max_pairs=None, device="cuda"):
+                 eps=1.0, sigma=1.0, rc=2.5, max_pairs=None, device="cuda", screen=False):
         self.dev = torch.device(device)
         self.ctx = abi.Ctx(templates, masses, inertias, eps, sigma, rc)
         n = len(x)
@@ -74,6 +74,13 @@ class RigidSystem:
         self.ws_rig = torch.zeros(abi.rb_rigid_workspace_bytes(n), dtype=torch.uint8, device=self.dev)
         self.nn: NNModel | None = None
         self.desc = None
+        # optional bead-path screen (a separate pass over the list that keeps
+        # the pairs whose bead boxes can interact; the force kernel applies
+        # the same test itself, so the screen pays off only when most listed
+        # pairs are far apart)
+        self.screen = screen
+        self.idx_screen = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
+        self.tmp_screen = torch.zeros(2, dtype=torch.int32, device=self.dev)
 
     # ------------------------------------------------------------ pieces
     def build_pairs(self, always=True):
@@ -86,12 +93,24 @@ class RigidSystem:
         self.idx_nn = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
         self.idx_bead = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
 
+    def bead_forces(self):
+        """Bead sum over the whole list (or over the screened pairs)."""
+        if not self.screen:
+            abi.rb_bead_pair_forces(self.ctx, self.x, self.q, self.types, self.box, self.pair_i, self.pair_j,
+                                    None, self.flags[abi.RB_FLAG_NPAIRS:], self.max_pairs, self.acc, self.flags)
+            return
+        abi.rb_bead_screen(self.ctx, self.x, self.q, self.types, self.box, self.pair_i, self.pair_j, None,
+                           self.flags[abi.RB_FLAG_NPAIRS:], self.max_pairs, self.idx_screen,
+                           self.flags[abi.RB_FLAG_NSCREEN:], self.tmp_screen, self.flags)
+        abi.rb_bead_pair_forces(self.ctx, self.x, self.q, self.types, self.box, self.pair_i, self.pair_j,
+                                self.idx_screen, self.flags[abi.RB_FLAG_NSCREEN:], self.max_pairs, self.acc,
+                                self.flags)
+
     def compute_forces(self, path="bead"):
         # the accumulator is clear: zeroed at construction, cleared again by
         # every rb_accum_finalize
         if path == "bead":
-            abi.rb_bead_pair_forces(self.ctx, self.x, self.q, self.types, self.box, self.pair_i, self.pair_j,
-                                    None, self.flags[abi.RB_FLAG_NPAIRS:], self.max_pairs, self.acc, self.flags)
+            self.bead_forces()
         elif path == "nn":
             m = self.nn
             abi.rb_pair_descriptors(self.x, self.q, self.box, self.pair_i, self.pair_j, m.d_min, self.desc,
@@ -122,8 +141,7 @@ class RigidSystem:
     # ------------------------------------------------------------ fused loop
     def _forces_to_acc(self, path):
         if path == "bead":
-            abi.rb_bead_pair_forces(self.ctx, self.x, self.q, self.types, self.box, self.pair_i, self.pair_j,
-                                    None, self.flags[abi.RB_FLAG_NPAIRS:], self.max_pairs, self.acc, self.flags)
+            self.bead_forces()
         else:
             m = self.nn
             abi.rb_pair_descriptors(self.x, self.q, self.box, self.pair_i, self.pair_j, m.d_min, self.desc,
@@ -141,14 +159,16 @@ class RigidSystem:
         abi.rb_rigid_step(self.ctx, 1, dt, self.x, self.P, self.q, self.L, self.types, self.force, self.torque,
                           self.x_ref, self.half_skin, None, self.flags, None)
 
-    def fused_step(self, dt, path="bead"):
+    def fused_step(self, dt, path="bead", kinetic=False):
         """Pair list, forces into the accumulator, then one launch for the end
-        of this step and the start of the next (see rb_rigid_step_fused)."""
+        of this step and the start of the next (see rb_rigid_step_fused).
+        The kinetic energy is reduced only when asked for (end_fused always
+        does)."""
         self.build_pairs(always=False)
         self._forces_to_acc(path)
         abi.rb_rigid_step_fused(self.ctx, dt, self.x, self.P, self.q, self.L, self.types, self.acc, self.force,
-                                self.torque, self.ev, self.x_ref, self.half_skin, self.kinetic, self.flags,
-                                self.ws_rig)
+                                self.torque, self.ev, self.x_ref, self.half_skin,
+                                self.kinetic if kinetic else None, self.flags, self.ws_rig)
 
     def end_fused(self, dt, path="bead"):
         """Last step of a fused run: forces, finalize, phase 2."""

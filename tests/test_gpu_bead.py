@@ -157,6 +157,42 @@ def test_bead_forces_bitwise_deterministic(abi):
     assert not torch.any(sysm.acc)           # finalize leaves the accumulator clear
 
 
+@pytest.mark.parametrize("cfgname", ["config1", "config2"])
+def test_bead_screen_drops_only_zero_pairs(abi, cfgname):
+    # forces over the screened pairs equal, bit for bit, the forces over the
+    # whole list: the dropped pairs contribute exactly zero (fixed point)
+    cfg = getattr(configs, cfgname)()
+    sysm, st = _system(abi, cfg)
+    sysm.build_pairs(always=True)
+    npairs = int(sysm.flags_host()[abi.RB_FLAG_NPAIRS])
+    e0 = int(sysm.flags_host()[abi.RB_FLAG_NEVAL])
+    abi.rb_bead_pair_forces(sysm.ctx, sysm.x, sysm.q, sysm.types, sysm.box, sysm.pair_i, sysm.pair_j, None,
+                            sysm.flags[abi.RB_FLAG_NPAIRS:], sysm.max_pairs, sysm.acc, sysm.flags)
+    abi.rb_accum_finalize(sysm.n, sysm.acc, sysm.force, sysm.torque, sysm.ev)
+    full = [sysm.force.clone(), sysm.torque.clone(), sysm.ev.clone()]
+    e1 = int(sysm.flags_host()[abi.RB_FLAG_NEVAL])
+    sysm.screen = True
+    sysm.bead_forces()
+    abi.rb_accum_finalize(sysm.n, sysm.acc, sysm.force, sysm.torque, sysm.ev)
+    f = sysm.flags_host()
+    for a, b in zip(full, [sysm.force, sysm.torque, sysm.ev]):
+        assert torch.equal(a, b)
+    kept = int(f[abi.RB_FLAG_NSCREEN])
+    assert 0 < kept < npairs
+    assert e1 - e0 == npairs and int(f[abi.RB_FLAG_NEVAL]) - e1 == npairs   # every listed pair counted once
+    assert not torch.any(sysm.tmp_screen)                                  # scratch left zero
+    # kept pairs include every pair with a bead pair inside rc (oracle)
+    pairs = sysm.pairs_host()
+    kept_ids = np.sort(sysm.idx_screen[:kept].cpu().numpy())
+    assert len(np.unique(kept_ids)) == kept
+    if cfgname == "config1":
+        for p in np.setdiff1d(np.arange(npairs), kept_ids):
+            i, j = pairs[p]
+            r = obeads.bead_pair(cfg.body.beads, cfg.body.beads, st["x"][i], st["q"][i], st["x"][j], st["q"][j],
+                                 cfg.box)
+            assert r["E"] == 0.0
+
+
 def test_rigid_step_matches_oracle(abi):
     cfg = configs.config1()
     sysm, st = _system(abi, cfg)
@@ -309,7 +345,7 @@ def test_fused_step_loop_matches_plain_steps_bitwise(abi, path):
         plain.step(cfg.dt, path)
     fused.begin_fused(cfg.dt)
     for _ in range(K - 1):
-        fused.fused_step(cfg.dt, path)
+        fused.fused_step(cfg.dt, path, kinetic=(_ % 3 == 0))
     fused.end_fused(cfg.dt, path)
     graphed.begin_fused(cfg.dt)
     g = graphed.capture(cfg.dt, path, steps=10, fused=True)

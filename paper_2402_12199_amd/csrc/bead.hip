@@ -28,7 +28,8 @@
 
 namespace rb {
 
-constexpr int kBeadWaves = 4;        // waves per block
+constexpr int kBeadWaves = 4;        // waves per block (per-pair form)
+constexpr int kMdWaves = 8;          // waves per block (per-body form: one work queue per block)
 constexpr float kCullMargin = 1.0e-3f;
 
 // A wave's LDS: three arrays of `stride` float4 (stride >= the largest
@@ -276,13 +277,18 @@ struct Box {
 // Geometry of pair (i, j) from the FP64 state: dl = minimum-image x_j - x_i
 // (lab), d = R_i^T dl and R = R_i^T R_j (from q_i^* q_j).  Shared by the
 // screen and the force kernel so that both take the same decisions.
-__device__ inline void pair_geometry(int32_t n, const double *__restrict__ x, const double *__restrict__ q,
-                                     const Box &box, int i, int j, double dl[3], double d[3], double R[9]) {
-    double Ri[9], qr[4];
+__device__ inline void pair_frame(int32_t n, const double *__restrict__ x, const double *__restrict__ q,
+                                  const Box &box, int i, int j, double dl[3], double d[3], double qr[4],
+                                  double qa[4]) {
+    double Ri[9];
 #pragma unroll
     for (int a = 0; a < 3; ++a) dl[a] = min_image(x[a * n + j] - x[a * n + i], box.L[a], box.inv[a]);
     const double aw = q[i], ax = q[n + i], ay = q[2 * n + i], az = q[3 * n + i];
     const double bw = q[j], bx = q[n + j], by = q[2 * n + j], bz = q[3 * n + j];
+    qa[0] = aw;
+    qa[1] = ax;
+    qa[2] = ay;
+    qa[3] = az;
     quat_to_rot<double>(aw, ax, ay, az, Ri);
 #pragma unroll
     for (int a = 0; a < 3; ++a) d[a] = Ri[a] * dl[0] + Ri[3 + a] * dl[1] + Ri[6 + a] * dl[2];
@@ -290,6 +296,12 @@ __device__ inline void pair_geometry(int32_t n, const double *__restrict__ x, co
     qr[1] = aw * bx - ax * bw - ay * bz + az * by;
     qr[2] = aw * by + ax * bz - ay * bw - az * bx;
     qr[3] = aw * bz - ax * by + ay * bx - az * bw;
+}
+
+__device__ inline void pair_geometry(int32_t n, const double *__restrict__ x, const double *__restrict__ q,
+                                     const Box &box, int i, int j, double dl[3], double d[3], double R[9]) {
+    double qr[4], qa[4];
+    pair_frame(n, x, q, box, i, j, dl, d, qr, qa);
     quat_to_rot<double>(qr[0], qr[1], qr[2], qr[3], R);
 }
 
@@ -349,14 +361,21 @@ __global__ __launch_bounds__(256) void k_bead_screen(Templates T, float rcm, int
 // Per-body form for dynamics.  Geometry from FP64 state; the pair's outputs
 // are rotated to the lab frame and added to the fixed-point accumulator.
 // Per-body form for dynamics.  A block takes the pairs b, b + G, b + 2G, ...
-// (G blocks), one thread per pair: indices, FP64 geometry and the
-// separating-axis test run for all of them at once (one round of memory
-// latency); the pairs that can interact go to an LDS queue from which the
-// block's waves take them one at a time (the work of a block is spread over
-// its waves whatever lane found it), each evaluated by a whole wave.  The
-// pair's outputs are rotated to the lab frame and added to the fixed-point
-// accumulator.
-__global__ __launch_bounds__(256) void k_bead_md(Templates T, LJ lj, int32_t n, const double *__restrict__ x,
+// (G blocks) in rounds of 64, one lane of the first wave per pair: indices,
+// FP64 geometry and the separating-axis test run for the round at once (one
+// round of memory latency); the pairs that can interact go, with their
+// geometry, to an LDS queue from which the block's waves take them one at a
+// time, each evaluated by a whole wave.  The pair's outputs are rotated to
+// the lab frame and added to the fixed-point accumulator.
+constexpr int kRound = 64;
+
+struct PairQueue {
+    int i[kRound], j[kRound], ti[kRound], tj[kRound];
+    double dl[3][kRound], d[3][kRound], qr[4][kRound], qa[4][kRound];
+    int n, head;
+};
+
+__global__ __launch_bounds__(kMdWaves * kWave) void k_bead_md(Templates T, LJ lj, int32_t n, const double *__restrict__ x,
                                                  const double *__restrict__ q, const int32_t *__restrict__ type,
                                                  Box box, const int32_t *__restrict__ pi,
                                                  const int32_t *__restrict__ pj, const int32_t *__restrict__ idx,
@@ -364,14 +383,13 @@ __global__ __launch_bounds__(256) void k_bead_md(Templates T, LJ lj, int32_t n, 
                                                  int64_t *__restrict__ acc, int32_t *__restrict__ flags,
                                                  int stride) {
     extern __shared__ float4 bead_lds[];
-    __shared__ long long wacc[kBeadWaves][10];   // per-wave energy/virial sums (fixed point)
-    __shared__ int queue[256];
-    __shared__ int qn, qhead;
+    __shared__ long long wacc[kMdWaves][10];   // per-wave energy/virial sums (fixed point)
+    __shared__ PairQueue Q;
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     WaveLds L = wave_lds(bead_lds, w, stride);
     if (lane < 10) wacc[w][lane] = 0;
-    const float4 *tb = stage_templates(T, bead_lds, kBeadWaves, stride);
+    const float4 *tb = stage_templates(T, bead_lds, kMdWaves, stride);
     const float rcm = sqrtf(lj.rc2) + kCullMargin, cut2 = rcm * rcm;
     int count = *count_dev;
     if (count > max_count) count = max_count;
@@ -379,35 +397,61 @@ __global__ __launch_bounds__(256) void k_bead_md(Templates T, LJ lj, int32_t n, 
     long long ntests = 0;
     bool bad = false;
     const int G = gridDim.x;
-    for (int p0 = blockIdx.x; p0 < count; p0 += G * (int)blockDim.x) {
-        const int p = p0 + threadIdx.x * G;
-        bool hit = false;
-        if (p < count) {
-            const int pid = idx ? idx[p] : p;
-            const int i = pi[pid], j = pj[pid];
-            double dl[3], d[3], R[9];
-            pair_geometry(n, x, q, box, i, j, dl, d, R);
-            hit = may_interact(T, type[i], type[j], d, R, rcm);
-        }
-        if (threadIdx.x == 0) {
-            qn = 0;
-            qhead = 0;
+    for (int p0 = blockIdx.x; p0 < count; p0 += G * kRound) {
+        if (w == 0) {
+            const int p = p0 + lane * G;
+            bool hit = false;
+            int i = 0, j = 0, ti = 0, tj = 0;
+            double dl[3], d[3], qr[4], qa[4];
+            if (p < count) {
+                const int pid = idx ? idx[p] : p;
+                i = pi[pid];
+                j = pj[pid];
+                ti = type[i];
+                tj = type[j];
+                pair_frame(n, x, q, box, i, j, dl, d, qr, qa);
+                double R[9];
+                quat_to_rot<double>(qr[0], qr[1], qr[2], qr[3], R);
+                hit = may_interact(T, ti, tj, d, R, rcm);
+            }
+            const unsigned long long m = __ballot(hit);
+            if (hit) {
+                const int at = __popcll(m & ((1ull << lane) - 1ull));
+                Q.i[at] = i;
+                Q.j[at] = j;
+                Q.ti[at] = ti;
+                Q.tj[at] = tj;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    Q.dl[a][at] = dl[a];
+                    Q.d[a][at] = d[a];
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    Q.qr[a][at] = qr[a];
+                    Q.qa[a][at] = qa[a];
+                }
+            }
+            if (lane == 0) {
+                Q.n = __popcll(m);
+                Q.head = 0;
+            }
         }
         __syncthreads();
-        if (hit) queue[atomicAdd(&qn, 1)] = p;
-        __syncthreads();
-        const int nq = qn;
+        const int nq = Q.n;
         for (;;) {
             int k = 0;
-            if (lane == 0) k = atomicAdd(&qhead, 1);
+            if (lane == 0) k = atomicAdd(&Q.head, 1);
             k = __builtin_amdgcn_readfirstlane(k);
             if (k >= nq) break;
-            const int pp = __builtin_amdgcn_readfirstlane(queue[k]);
-            const int pid = idx ? idx[pp] : pp;
-            const int i = pi[pid], j = pj[pid];
-            const int ti = type[i], tj = type[j];
+            const int i = Q.i[k], j = Q.j[k], ti = Q.ti[k], tj = Q.tj[k];
             double dl[3], d[3], R[9];
-            pair_geometry(n, x, q, box, i, j, dl, d, R);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                dl[a] = Q.dl[a][k];
+                d[a] = Q.d[a][k];
+            }
+            quat_to_rot<double>(Q.qr[0][k], Q.qr[1][k], Q.qr[2][k], Q.qr[3][k], R);
             const int nj = stage_j(T, tb, ti, tj, d, R, cut2, L, lane);
             if (nj == 0) continue;   // no bead of j within rc of i's box: zero contribution
             const int ni = stage_i(T, tb, ti, tj, d, R, cut2, L, lane);
@@ -422,7 +466,7 @@ __global__ __launch_bounds__(256) void k_bead_md(Templates T, LJ lj, int32_t n, 
             // energy and the 9 virial components to the wave's sums
             if (lane < 22) {
                 double Ri[9];
-                quat_to_rot<double>(q[i], q[n + i], q[2 * n + i], q[3 * n + i], Ri);
+                quat_to_rot<double>(Q.qa[0][k], Q.qa[1][k], Q.qa[2][k], Q.qa[3][k], Ri);
                 const double F[3] = {r[1], r[2], r[3]}, tI[3] = {r[4], r[5], r[6]};
                 const double tJ[3] = {d[1] * F[2] - d[2] * F[1] - tI[0], d[2] * F[0] - d[0] * F[2] - tI[1],
                                       d[0] * F[1] - d[1] * F[0] - tI[2]};
@@ -446,31 +490,43 @@ __global__ __launch_bounds__(256) void k_bead_md(Templates T, LJ lj, int32_t n, 
             }
             if (lane == 0 && (!isfinite(r[0]) || !isfinite(r[1]) || !isfinite(r[2]) || !isfinite(r[3]))) bad = true;
         }
-        __syncthreads();   // the queue is refilled by the next batch
+        __syncthreads();   // the queue is refilled by the next round
     }
     long long part[11];
 #pragma unroll
     for (int a = 0; a < 10; ++a) part[a] = wacc[w][a];
     part[10] = ntests;
-    block_flush_globals<kBeadWaves>(part, acc + 6 * (int64_t)n, flags);
+    block_flush_globals<kMdWaves>(part, acc + 6 * (int64_t)n, flags);
     if (lane == 0 && bad) atomicOr(flags + RB_FLAG_NONFINITE, 1);
 }
 
 // Dynamic LDS of a block (kBeadWaves waves, three arrays each) and the
 // number of such blocks a CU holds, cached per size.
-static size_t bead_lds_bytes(const rb_ctx *ctx, int &stride) {
+static size_t bead_lds_bytes(const rb_ctx *ctx, int waves, int &stride) {
     stride = (ctx->max_beads + 3) & ~3;
-    return sizeof(float4) * (3 * (size_t)stride * kBeadWaves + (size_t)ctx->total_beads);
+    return sizeof(float4) * (3 * (size_t)stride * waves + (size_t)ctx->total_beads);
 }
 
 template <typename K>
-static int blocks_per_cu(K kernel, size_t lds, int *cache_lds, int *cache_nb) {
+static int blocks_per_cu(K kernel, int threads, size_t lds, int *cache_lds, int *cache_nb) {
     if (*cache_lds == (int)lds && *cache_nb > 0) return *cache_nb;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 256, lds) != hipSuccess || nb < 1) nb = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, lds) != hipSuccess || nb < 1) nb = 1;
     *cache_lds = (int)lds;
     *cache_nb = nb;
     return nb;
+}
+
+// Largest dynamic + static LDS a block may use on the current device.
+static size_t device_max_lds() {
+    static size_t cached = 0;
+    if (cached > 0) return cached;
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+        v = 65536;
+    cached = (size_t)v;
+    return cached;
 }
 
 static int device_cus_bead() {
@@ -496,10 +552,10 @@ extern "C" int rb_bead_pair_eval(const rb_ctx *ctx, int64_t n_pairs, const float
                "rb_bead_pair_eval: bad type");
     if (n_pairs == 0) return RB_OK;
     int stride;
-    const size_t lds = bead_lds_bytes(ctx, stride);
+    const size_t lds = bead_lds_bytes(ctx, kBeadWaves, stride);
     RB_REQUIRE(lds <= 65536, "rb_bead_pair_eval: templates need %zu bytes of LDS (max 65536)", lds);
     static int c_lds = -1, c_nb = 0;
-    const int nb = blocks_per_cu(k_bead_desc, lds, &c_lds, &c_nb);
+    const int nb = blocks_per_cu(k_bead_desc, 256, lds, &c_lds, &c_nb);
     const int grid = grid_for(n_pairs, kBeadWaves, nb * device_cus_bead());
     k_bead_desc<<<grid, 256, lds, (hipStream_t)stream>>>(ctx->dev.t, ctx->dev.lj, type_i, type_j, n_pairs, desc,
                                                         out, flags, stride);
@@ -525,12 +581,14 @@ extern "C" int rb_bead_pair_forces(const rb_ctx *ctx, int32_t n, const double *x
     // the templates in use); waves stride over the pairs, and each block
     // flushes its global sums once
     int stride;
-    const size_t lds = bead_lds_bytes(ctx, stride);
-    RB_REQUIRE(lds <= 65536, "rb_bead_pair_forces: templates need %zu bytes of LDS (max 65536)", lds);
+    const size_t lds = bead_lds_bytes(ctx, kMdWaves, stride);
+    RB_REQUIRE(lds + sizeof(PairQueue) + 1024 <= device_max_lds(),
+               "rb_bead_pair_forces: templates need %zu bytes of LDS per block (device max %zu)", lds,
+               device_max_lds());
     static int c_lds = -1, c_nb = 0;
-    const int nb = blocks_per_cu(k_bead_md, lds, &c_lds, &c_nb);
-    const int grid = grid_for(max_count, kBeadWaves, nb * device_cus_bead());
-    k_bead_md<<<grid, 256, lds, (hipStream_t)stream>>>(ctx->dev.t, ctx->dev.lj, n, x, q, type, b, pair_i, pair_j,
+    const int nb = blocks_per_cu(k_bead_md, kMdWaves * kWave, lds, &c_lds, &c_nb);
+    const int grid = grid_for(max_count, kMdWaves, nb * device_cus_bead());
+    k_bead_md<<<grid, kMdWaves * kWave, lds, (hipStream_t)stream>>>(ctx->dev.t, ctx->dev.lj, n, x, q, type, b, pair_i, pair_j,
                                                       idx, count_dev, max_count, acc, flags, stride);
     RB_LAUNCH_CHECK("rb_bead_pair_forces");
     return RB_OK;

@@ -54,8 +54,26 @@ __device__ inline float smooth_switch(float r, float lo, float hi, float &dsdr) 
 // torques, rotation to the lab frame, fixed-point accumulation on both
 // bodies; the energy and virial of the 16 rows of the wave's tile are summed
 // over the row lanes and added to the wave's LDS sums by lane 0.
-__device__ inline void forces_epilogue(const NNArgs &a, float gu[kIn], float E, int64_t pid, bool mine, int lane,
-                                       long long *wsum, bool &bad) {
+// Per-pair inputs of the forces epilogue, loaded before the tile is
+// evaluated so that their latency overlaps the network.
+struct EpiIn {
+    int i = 0, j = 0;
+    double q[4] = {1.0, 0.0, 0.0, 0.0};
+};
+
+__device__ inline EpiIn load_epi(const NNArgs &a, int64_t pid, bool live) {
+    EpiIn e;
+    if (live) {
+        e.i = a.pi[pid];
+        e.j = a.pj[pid];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) e.q[c] = a.q[c * a.n + e.i];
+    }
+    return e;
+}
+
+__device__ inline void forces_epilogue(const NNArgs &a, const EpiIn &in, float gu[kIn], float E, int64_t pid,
+                                       bool mine, int lane, long long *wsum, bool &bad) {
     long long ev[10];
 #pragma unroll
     for (int k = 0; k < 10; ++k) ev[k] = 0;
@@ -78,9 +96,9 @@ __device__ inline void forces_epilogue(const NNArgs &a, float gu[kIn], float E, 
         const float Es = S * E;
         float ft[9];
         pair_ft_from_grad(u, gu, ft);
-        const int i = a.pi[pid], j = a.pj[pid];
+        const int i = in.i, j = in.j;
         double R[9];
-        quat_to_rot<double>(a.q[i], a.q[a.n + i], a.q[2 * a.n + i], a.q[3 * a.n + i], R);
+        quat_to_rot<double>(in.q[0], in.q[1], in.q[2], in.q[3], R);
         double Fj[3], ti[3], tj[3], dl[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -119,6 +137,12 @@ template <int MODE, bool BF16>
 __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
     constexpr int kWaves = NNCfg<BF16, MODE>::waves;
     __shared__ typename NNLds<BF16>::T L;
+    if (MODE == kForces) {
+        // the grid is sized for the capacity; blocks without a tile leave
+        // before staging the weights
+        const int64_t c = *a.count_dev;
+        if ((int64_t)blockIdx.x * kWaves * kTile >= (c < a.P ? c : a.P)) return;
+    }
     if constexpr (BF16)
         stage_bf16<nn_threads(true, MODE)>(L, a.params);
     else
@@ -155,6 +179,8 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
             float dsdr;
             seed = smooth_switch(sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]), a.sw_lo, a.sw_hi, dsdr);
         }
+        EpiIn ein;
+        if (MODE == kForces) ein = load_epi(a, pid, live && g == 0);
         float gu[kIn];
         float E;
         if constexpr (BF16)
@@ -164,7 +190,7 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
         if (MODE == kForces) {
             // every lane takes part in the shuffles below; the results of
             // the lanes of groups 1..3 and of dead rows are discarded
-            forces_epilogue(a, gu, E, pid, live && g == 0, lane, wacc[w], bad);
+            forces_epilogue(a, ein, gu, E, pid, live && g == 0, lane, wacc[w], bad);
             continue;
         }
         if (!live || g != 0) continue;
@@ -193,6 +219,84 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
     }
 }
 
+// Four waves per tile (tile_bf16_wide), two tiles in flight per block; the
+// block walks the tiles in lockstep (a group past the end evaluates a dead
+// tile) so that every wave meets the same barriers.
+constexpr int kWideGroups = 3;
+constexpr int kWideThreads = kWideGroups * kWideGroup * kWave;
+
+template <int MODE>
+__global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
+    __shared__ LdsBF16 L;
+    __shared__ WideX X[kWideGroups];
+    __shared__ long long wacc[kWideGroups * kWideGroup][10];
+    int64_t count = a.P;
+    if (MODE == kForces) {
+        const int64_t c = *a.count_dev;
+        count = c < a.P ? c : a.P;
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.flags + RB_FLAG_NEVAL, (int)count);
+    }
+    const int64_t ntiles = (count + kTile - 1) / kTile;
+    // the grid is sized for the capacity; blocks without a tile leave before
+    // staging the weights
+    if ((int64_t)blockIdx.x * kWideGroups >= ntiles) return;
+    stage_bf16<kWideThreads>(L, a.params);
+    const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, n = lane & 15;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int grp = wave / kWideGroup, v = wave % kWideGroup;
+    if (MODE == kForces && lane < 10) wacc[wave][lane] = 0;
+    __syncthreads();
+    bool bad = false;
+    for (int64_t base = (int64_t)blockIdx.x * kWideGroups; base < ntiles;
+         base += (int64_t)gridDim.x * kWideGroups) {
+        const int64_t row = (base + grp) * kTile + n;
+        const bool live = row < count;
+        int64_t pid = row;
+        if (MODE == kForces && live && a.idx) pid = a.idx[row];
+        float u[kIn];
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) u[k] = live ? a.desc[k * a.stride + pid] : (k == 3 ? 1.f : 0.f);
+        float seed = 1.f;
+        if (MODE == kGrad && a.gE) seed = live ? a.gE[pid] : 0.f;
+        if (MODE == kForces) {
+            float dsdr;
+            seed = smooth_switch(sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]), a.sw_lo, a.sw_hi, dsdr);
+        }
+        EpiIn ein;
+        if (MODE == kForces) ein = load_epi(a, pid, live && g == 0 && v == 0);
+        float gu[kIn];
+        const float E = tile_bf16_wide<true>(L, X[grp], a.nm, u, seed, gu, v);
+        if (v != 0) continue;   // the group's results are the same in its four waves
+        if (MODE == kForces) {
+            forces_epilogue(a, ein, gu, E, pid, live && g == 0, lane, wacc[wave], bad);
+        } else if (live && g == 0) {
+            if (a.energy) a.energy[pid] = E;
+            if (a.dEdu)
+#pragma unroll
+                for (int k = 0; k < kIn; ++k) a.dEdu[k * a.P + pid] = gu[k];
+            if (a.ft) {
+                float ft[9];
+                pair_ft_from_grad(u, gu, ft);
+#pragma unroll
+                for (int k = 0; k < 9; ++k) a.ft[k * a.P + pid] = ft[k];
+            }
+        }
+    }
+    if (MODE == kForces) {
+        long long part[11];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) part[k] = wacc[wave][k];
+        part[10] = 0;
+        block_flush_globals<kWideGroups * kWideGroup>(part, a.acc + 6 * (int64_t)a.n, nullptr);
+        if (__any(bad) && lane == 0) atomicOr(a.flags + RB_FLAG_NONFINITE, 1);
+    }
+}
+
+// Batches up to this many tiles take the four-waves-per-tile form in BF16
+// (latency-bound sizes, such as the pair lists of dynamics); larger batches
+// the one-wave-per-tile form, which needs no barriers.
+constexpr int64_t kWideMaxTiles = 16384;
+
 // Compute units of the current device (one persistent block per CU: the
 // BF16 weight image fills most of a CU's LDS).
 static int device_cus() {
@@ -210,6 +314,12 @@ template <int MODE>
 static int launch(const NNArgs &a, int precision, int64_t rows, hipStream_t st) {
     const int64_t tiles = (rows + kTile - 1) / kTile;
     const int cus = device_cus();
+    if constexpr (MODE != kEval) {
+        if (precision == RB_PREC_BF16 && tiles <= kWideMaxTiles) {
+            k_nn_wide<MODE><<<grid_for(tiles, kWideGroups, cus), kWideThreads, 0, st>>>(a);
+            return hip_check(hipGetLastError(), "network kernel launch");
+        }
+    }
     if (precision == RB_PREC_BF16) {
         constexpr int w = NNCfg<true, MODE>::waves;
         k_nn<MODE, true><<<grid_for(tiles, w, cus), w * kWave, 0, st>>>(a);

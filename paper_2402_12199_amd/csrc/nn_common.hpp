@@ -117,17 +117,18 @@ __device__ inline void stage_bf16(LdsBF16 &L, const float *__restrict__ p) {
             *reinterpret_cast<bf16x8 *>(&L.w[l][o][32 * cb + 8 * g]) = pack8(av, bv);
         }
     }
-    static_assert((kH * 8) % NT == 0 && (4 * kH) % NT == 0, "block size must divide the small tensors");
 #pragma unroll
-    for (int it = 0; it < kH * 8 / NT; ++it) {
+    for (int it = 0; it < (kH * 8 + NT - 1) / NT; ++it) {
         const int idx = threadIdx.x + it * NT;
-        const int o = idx >> 3, k = idx & 7;
-        L.w1[o][k] = k < kIn ? p[OFF_W1 + o * kIn + k] : 0.f;
+        if (idx < kH * 8) {
+            const int o = idx >> 3, k = idx & 7;
+            L.w1[o][k] = k < kIn ? p[OFF_W1 + o * kIn + k] : 0.f;
+        }
     }
 #pragma unroll
-    for (int it = 0; it < 4 * kH / NT; ++it) {
+    for (int it = 0; it < (4 * kH + NT - 1) / NT; ++it) {
         const int idx = threadIdx.x + it * NT;
-        L.b[idx / kH][idx % kH] = p[b_off(idx / kH + 1) + idx % kH];
+        if (idx < 4 * kH) L.b[idx / kH][idx % kH] = p[b_off(idx / kH + 1) + idx % kH];
     }
     for (int idx = threadIdx.x; idx < kH; idx += NT) L.w5[idx] = p[OFF_W5 + idx];
     if (threadIdx.x == 0) L.b5 = p[OFF_B5];

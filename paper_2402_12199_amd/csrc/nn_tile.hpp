@@ -175,6 +175,174 @@ __device__ inline float tile_bf16(const LdsBF16 &L, const Norm &nm, const float 
     return E;
 }
 
+// ------------------------------------------------------------ BF16, wide
+// One 16-pair tile evaluated by a group of four waves.  Wave v of the group
+// owns the hidden features 32 v .. 32 v + 31 of every layer (output tiles
+// 2 v and 2 v + 1, i.e. the MFMA operand block kb = v of the next layer) and
+// the waves exchange their activation and delta blocks through LDS after
+// each layer; the energy and dX/du are summed over the four waves in a fixed
+// order.  Each wave does a quarter of the SiLU and MFMA work of a tile, so a
+// tile's latency is about a quarter of the single-wave form's, which is what
+// small batches (one tile per wave) are bound by.  Same arithmetic per
+// feature as tile_bf16 except the order of the final sums.
+constexpr int kWideGroup = 4;
+struct WideX {
+    bf16x8 a[kWideGroup][kWave];     // activation blocks
+    bf16x8 dh[kWideGroup][kWave];    // delta blocks, BF16 head
+    bf16x8 dl[kWideGroup][kWave];    // delta blocks, BF16 remainder
+    float red[kWideGroup][8][16];    // per-row partial sums (energy, dX/du)
+};
+
+__device__ inline void wide_sync() { __syncthreads(); }
+
+template <bool GRAD>
+__device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &nm, const float u[kIn], float seed,
+                                       float gu[kIn], int v) {
+    const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, n = lane & 15;
+    float un[kIn];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) un[k] = (u[k] - nm.shift[k]) * nm.scale[k];
+    bf16x8 act[4];
+    f16x8 spo[4];
+    {
+        float h[2][4], d[2][4];
+#pragma unroll
+        for (int mm = 0; mm < 2; ++mm)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int f = 32 * v + 16 * mm + 4 * g + r;
+                const float4 wa = *reinterpret_cast<const float4 *>(&L.w1[f][0]);
+                const float4 wb = *reinterpret_cast<const float4 *>(&L.w1[f][4]);
+                float z = L.b[0][f];
+                z = fmaf(wa.x, un[0], z); z = fmaf(wa.y, un[1], z); z = fmaf(wa.z, un[2], z);
+                z = fmaf(wa.w, un[3], z); z = fmaf(wb.x, un[4], z); z = fmaf(wb.y, un[5], z);
+                z = fmaf(wb.z, un[6], z);
+                silu(z, h[mm][r], d[mm][r]);
+            }
+        X.a[v][lane] = pack8(h[0], h[1]);
+        if (GRAD) spo[0] = pack8h(d[0], d[1]);
+    }
+    wide_sync();
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) act[kb] = X.a[kb][lane];
+    wide_sync();
+    float e = 0.f;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        float h[2][4], d[2][4];
+#pragma unroll
+        for (int mm = 0; mm < 2; ++mm) {
+            const int mt = 2 * v + mm;
+            f32x4 c = *reinterpret_cast<const f32x4 *>(&L.b[l + 1][16 * mt + 4 * g]);
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&L.w[l][16 * mt + n][32 * kb + 8 * g]);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kb], c, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) silu(c[r], h[mm][r], d[mm][r]);
+            if (l == 2) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) e = fmaf(L.w5[16 * mt + 4 * g + r], h[mm][r], e);
+            }
+        }
+        if (GRAD) spo[l + 1] = pack8h(d[0], d[1]);
+        if (l < 2) {
+            X.a[v][lane] = pack8(h[0], h[1]);
+            wide_sync();
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) act[kb] = X.a[kb][lane];
+            wide_sync();
+        }
+    }
+    e = group_sum(e);
+    if (g == 0) X.red[v][0][n] = e;
+    wide_sync();
+    e = ((X.red[0][0][n] + X.red[1][0][n]) + X.red[2][0][n]) + X.red[3][0][n] + L.b5;
+    wide_sync();
+    const float E = fmaf(e, nm.oscale, nm.oshift);
+    if (!GRAD) return E;
+
+    // reverse pass: this wave's block of delta_4 = seed * oscale * w5 (.) h4'
+    const float s0 = seed * nm.oscale;
+    bf16x8 dpk[4], dlk[4];
+    {
+        float a0[4], a1[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            a0[r] = s0 * L.w5[32 * v + 4 * g + r] * (float)spo[3][r];
+            a1[r] = s0 * L.w5[32 * v + 16 + 4 * g + r] * (float)spo[3][4 + r];
+        }
+        bf16x8 hi, lo;
+        split8(a0, a1, hi, lo);
+        X.dh[v][lane] = hi;
+        X.dl[v][lane] = lo;
+    }
+    wide_sync();
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        dpk[kb] = X.dh[kb][lane];
+        dlk[kb] = X.dl[kb][lane];
+    }
+    wide_sync();
+    float gk[kIn];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) gk[k] = 0.f;
+#pragma unroll
+    for (int l = 2; l >= 0; --l) {
+        float d[2][4];
+#pragma unroll
+        for (int mm = 0; mm < 2; ++mm) {
+            const int mt = 2 * v + mm;
+            // input feature 16 mt + n lives in LDS column col
+            const int col = 32 * (mt >> 1) + 8 * (n >> 2) + 4 * (mt & 1) + (n & 3);
+            f32x4 c = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                bf16x8 a;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) a[i] = L.w[l][32 * kb + 16 * (i >> 2) + 4 * g + (i & 3)][col];
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, dpk[kb], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, dlk[kb], c, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) d[mm][r] = c[r] * (float)spo[l][4 * mm + r];
+            if (l == 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int f = 16 * mt + 4 * g + r;
+#pragma unroll
+                    for (int k = 0; k < kIn; ++k) gk[k] = fmaf(L.w1[f][k], d[mm][r], gk[k]);
+                }
+            }
+        }
+        if (l > 0) {
+            bf16x8 hi, lo;
+            split8(d[0], d[1], hi, lo);
+            X.dh[v][lane] = hi;
+            X.dl[v][lane] = lo;
+            wide_sync();
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                dpk[kb] = X.dh[kb][lane];
+                dlk[kb] = X.dl[kb][lane];
+            }
+            wide_sync();
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) {
+        const float s = group_sum(gk[k]);
+        if (g == 0) X.red[v][1 + k][n] = s;
+    }
+    wide_sync();
+#pragma unroll
+    for (int k = 0; k < kIn; ++k)
+        gu[k] = (((X.red[0][1 + k][n] + X.red[1][1 + k][n]) + X.red[2][1 + k][n]) + X.red[3][1 + k][n]) * nm.scale[k];
+    wide_sync();
+    return E;
+}
+
 // ------------------------------------------------------------------ FP32
 // Small LDS image for the FP32 path: W1, biases, w5, and per wave the SiLU
 // derivatives of the forward pass (4 layers x 32 values x 64 lanes).

@@ -195,13 +195,16 @@ struct WideX {
 
 __device__ inline void wide_sync() { __syncthreads(); }
 
-template <bool GRAD>
+template <bool GRAD, bool EMIT = false>
 __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &nm, const float u[kIn], float seed,
-                                       float gu[kIn], int v) {
+                                       float gu[kIn], int v, const Emit &em = Emit{}) {
     const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, n = lane & 15;
     float un[kIn];
 #pragma unroll
     for (int k = 0; k < kIn; ++k) un[k] = (u[k] - nm.shift[k]) * nm.scale[k];
+    if (EMIT && em.live && g == 0 && v == 0)
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) em.h(k) = un[k];
     bf16x8 act[4];
     f16x8 spo[4];
     {
@@ -218,6 +221,7 @@ __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &n
                 z = fmaf(wa.w, un[3], z); z = fmaf(wb.x, un[4], z); z = fmaf(wb.y, un[5], z);
                 z = fmaf(wb.z, un[6], z);
                 silu(z, h[mm][r], d[mm][r]);
+                if (EMIT && em.live) em.h(kIn + f) = h[mm][r];
             }
         X.a[v][lane] = pack8(h[0], h[1]);
         if (GRAD) spo[0] = pack8h(d[0], d[1]);
@@ -241,6 +245,9 @@ __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &n
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) silu(c[r], h[mm][r], d[mm][r]);
+            if (EMIT && em.live)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) em.h(kIn + kH * (l + 1) + 16 * mt + 4 * g + r) = h[mm][r];
             if (l == 2) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) e = fmaf(L.w5[16 * mt + 4 * g + r], h[mm][r], e);
@@ -262,9 +269,14 @@ __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &n
     wide_sync();
     const float E = fmaf(e, nm.oscale, nm.oshift);
     if (!GRAD) return E;
+    if (EMIT) {
+        seed = em.live ? em.k2 * (E - em.y) : 0.f;
+        if (em.live && g == 0 && v == 0) em.R[em.b] = E - em.y;
+    }
 
     // reverse pass: this wave's block of delta_4 = seed * oscale * w5 (.) h4'
     const float s0 = seed * nm.oscale;
+    if (EMIT && em.live && g == 0 && v == 0) em.d(4 * kH) = s0;
     bf16x8 dpk[4], dlk[4];
     {
         float a0[4], a1[4];
@@ -272,6 +284,10 @@ __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &n
         for (int r = 0; r < 4; ++r) {
             a0[r] = s0 * L.w5[32 * v + 4 * g + r] * (float)spo[3][r];
             a1[r] = s0 * L.w5[32 * v + 16 + 4 * g + r] * (float)spo[3][4 + r];
+            if (EMIT && em.live) {
+                em.d(3 * kH + 32 * v + 4 * g + r) = a0[r];
+                em.d(3 * kH + 32 * v + 16 + 4 * g + r) = a1[r];
+            }
         }
         bf16x8 hi, lo;
         split8(a0, a1, hi, lo);
@@ -307,6 +323,9 @@ __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &n
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) d[mm][r] = c[r] * (float)spo[l][4 * mm + r];
+            if (EMIT && em.live)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) em.d(kH * l + 16 * mt + 4 * g + r) = d[mm][r];
             if (l == 0) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {

@@ -68,6 +68,40 @@ __global__ __launch_bounds__(nn_threads(BF16, 1)) void k_train_fb(TrainArgs a) {
     }
 }
 
+// BF16 forward + reverse with four waves per 16-row tile (tile_bf16_wide),
+// two tiles in flight per block, the block walking the tiles in lockstep.
+constexpr int kTrainGroups = 2;
+constexpr int kTrainWideThreads = kTrainGroups * kWideGroup * kWave;
+
+__global__ __launch_bounds__(kTrainWideThreads) void k_train_fb_wide(TrainArgs a) {
+    __shared__ LdsBF16 L;
+    __shared__ WideX X[kTrainGroups];
+    stage_bf16<kTrainWideThreads>(L, a.params);
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), n = lane & 15;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int grp = wave / kWideGroup, v = wave % kWideGroup;
+    const int ntiles = (a.B + kTile - 1) / kTile;
+    for (int base = blockIdx.x * kTrainGroups; base < ntiles; base += gridDim.x * kTrainGroups) {
+        const int b = (base + grp) * kTile + n;
+        Emit em;
+        em.H = a.H;
+        em.D = a.D;
+        em.R = a.R;
+        em.B = a.B;
+        em.b = b;
+        em.live = b < a.B;
+        em.k2 = 2.f / (float)a.B;
+        const int64_t pid = em.live ? a.idx[b] : 0;
+        float u[kIn];
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) u[k] = em.live ? a.desc[k * a.nd + pid] : (k == 3 ? 1.f : 0.f);
+        em.y = em.live ? (a.labels[pid] - a.oshift) / a.oscale : 0.f;
+        float gu[kIn];
+        (void)tile_bf16_wide<true, true>(L, X[grp], a.nm, u, 0.f, gu, v, em);
+    }
+}
+
 template <bool BF16>
 __global__ __launch_bounds__(512) void k_train_wgrad(TrainArgs a) {
     const int c = blockIdx.x;
@@ -252,8 +286,7 @@ extern "C" int rb_nn_train_step(float *params, float *adam_m, float *adam_v, int
     const int ntiles = (batch + kTile - 1) / kTile;
     const int cus = device_cus_train();
     if (precision == RB_PREC_BF16) {
-        constexpr int wv = nn_threads(true, 1) / kWave;
-        k_train_fb<true><<<grid_for(ntiles, wv, cus), wv * kWave, 0, st>>>(a);
+        k_train_fb_wide<<<grid_for(ntiles, kTrainGroups, cus), kTrainWideThreads, 0, st>>>(a);
     } else {
         constexpr int wv = nn_threads(false, 1) / kWave;
         k_train_fb<false><<<grid_for(ntiles, wv, cus), wv * kWave, 0, st>>>(a);

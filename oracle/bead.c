@@ -10,6 +10,9 @@
  *
  * Contents
  *   oracle_lj                 bead-bead Lennard-Jones 12-6, energy-shifted
+ *   oracle_hphc               bead-bead half-power half-cosine potential
+ *                             (paper section 3), selected for all the sums
+ *                             below by oracle_set_hphc (oracle_set_lj: back)
  *   oracle_bead_pair          double sum over the beads of two bodies
  *                             (paper section 2, first equation)
  *   oracle_bead_system        that double sum for every pair of bodies whose
@@ -29,6 +32,8 @@
 #ifdef _OPENMP
 #include <omp.h>
 #endif
+
+static const double kPi = 3.14159265358979323846;
 
 int oracle_num_threads(void) {
 #ifdef _OPENMP
@@ -90,6 +95,46 @@ double oracle_lj(double r2, double eps, double sigma, double rc, double *f_over_
     return 4.0 * eps * (s12 - s6) - 4.0 * eps * (sc12 - sc6);
 }
 
+/* Half-power half-cosine potential (paper section 3): a soft repulsion
+ * (b - r)^p - 2A for r <= b and a cosine well beyond.  The printed attractive
+ * branch, -A cos(c (r - b)), would jump from -2A to -A at r = b and end at +A
+ * at the end of the half period; it is read here as -A (1 + cos(c (r - b))),
+ * which joins the repulsive branch at r = b with zero slope and reaches zero
+ * with zero slope at r_c = b + pi / c, the cutoff.  Returns the energy and
+ * writes -(dU/dr)/r. */
+double oracle_hphc(double r2, double A, double b, double c, double p, double *f_over_r) {
+    const double rcut = b + kPi / c;
+    if (r2 >= rcut * rcut) { *f_over_r = 0.0; return 0.0; }
+    const double r = sqrt(r2);
+    if (r <= b) {
+        const double t = b - r;
+        *f_over_r = p * pow(t, p - 1.0) / r;
+        return pow(t, p) - 2.0 * A;
+    }
+    const double x = c * (r - b);
+    *f_over_r = -A * c * sin(x) / r;
+    return -A * (1.0 + cos(x));
+}
+
+/* Bead potential used by the sums: 0 = Lennard-Jones (eps, sigma, rc passed
+ * in), 1 = half-power half-cosine with the parameters set here. */
+static int g_pot = 0;
+static double g_hphc[4];
+
+void oracle_set_hphc(double A, double b, double c, double p) {
+    g_pot = 1;
+    g_hphc[0] = A; g_hphc[1] = b; g_hphc[2] = c; g_hphc[3] = p;
+}
+
+void oracle_set_lj(void) { g_pot = 0; }
+
+static double bead_cutoff(double rc) { return g_pot ? g_hphc[1] + kPi / g_hphc[2] : rc; }
+
+static double bead_u(double r2, double eps, double sigma, double rc, double *f_over_r) {
+    if (g_pot) return oracle_hphc(r2, g_hphc[0], g_hphc[1], g_hphc[2], g_hphc[3], f_over_r);
+    return oracle_lj(r2, eps, sigma, rc, f_over_r);
+}
+
 /* Energy, forces and torques between body i and body j: the sum of the bead
  * interaction over all N_i x N_j bead pairs (paper section 2).  Every bead
  * force is accumulated directly into both bodies; torques are about each
@@ -99,6 +144,7 @@ void oracle_bead_pair(int ni, const double *bi, int nj, const double *bj,
                       const double *xi, const double *qi, const double *xj, const double *qj,
                       const double *box, double eps, double sigma, double rc, double *out) {
     double Ri[3][3], Rj[3][3], dlab[3];
+    const double rcut = bead_cutoff(rc);
     qmat(qi, Ri); qmat(qj, Rj);
     for (int a = 0; a < 3; ++a) dlab[a] = xj[a] - xi[a];
     min_image(dlab, box);
@@ -117,8 +163,8 @@ void oracle_bead_pair(int ni, const double *bi, int nj, const double *bj,
                 r2 += v[a] * v[a];
             }
             if (r2 < rmin2) rmin2 = r2;
-            if (r2 >= rc * rc) continue;
-            E += oracle_lj(r2, eps, sigma, rc, &fr);
+            if (r2 >= rcut * rcut) continue;
+            E += bead_u(r2, eps, sigma, rc, &fr);
             for (int a = 0; a < 3; ++a) f[a] = fr * v[a];                /* force on bead k */
             for (int a = 0; a < 3; ++a) { Fi[a] += f[a]; Fj[a] -= f[a]; }
             cross(rk, f, t);
@@ -184,7 +230,7 @@ long oracle_bead_system(int n, const double *x, const double *q, const int *type
             double d[3];
             for (int a = 0; a < 3; ++a) d[a] = x[3 * j + a] - x[3 * i + a];
             min_image(d, box);
-            double c = rmax[type[i]] + rmax[type[j]] + rc;
+            double c = rmax[type[i]] + rmax[type[j]] + bead_cutoff(rc);
             if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] >= c * c) continue;
             if (np == cap) {
                 cap *= 2;

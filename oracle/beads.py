@@ -29,6 +29,12 @@ def lib():
         L.oracle_num_threads.restype = C.c_int
         L.oracle_lj.restype = C.c_double
         L.oracle_lj.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, _D]
+        L.oracle_hphc.restype = C.c_double
+        L.oracle_hphc.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, _D]
+        L.oracle_set_hphc.restype = None
+        L.oracle_set_hphc.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double]
+        L.oracle_set_lj.restype = None
+        L.oracle_set_lj.argtypes = []
         L.oracle_bead_pair.restype = None
         L.oracle_bead_pair.argtypes = [C.c_int, _D, C.c_int, _D, _D, _D, _D, _D, _D,
                                        C.c_double, C.c_double, C.c_double, _D]
@@ -70,6 +76,33 @@ def lj(r, eps=1.0, sigma=1.0, rc=2.5):
     fr = C.c_double()
     e = lib().oracle_lj(float(r) ** 2, eps, sigma, rc, C.byref(fr))
     return e, fr.value
+
+
+# Half-power half-cosine parameters of the paper (section 3), epsilon and sigma units.
+HPHC_PAPER = dict(A=0.00035, b=1.46375, c=3.3833, p=2.5)
+
+
+def hphc(r, A, b, c, p):
+    """Half-power half-cosine energy and -(du/dr)/r at distance r (scalar)."""
+    fr = C.c_double()
+    e = lib().oracle_hphc(float(r) ** 2, A, b, c, p, C.byref(fr))
+    return e, fr.value
+
+
+class use_hphc:
+    """Context in which every bead sum of the oracle uses the half-power
+    half-cosine potential (the Lennard-Jones arguments are then ignored)."""
+
+    def __init__(self, A, b, c, p):
+        self.args = (A, b, c, p)
+
+    def __enter__(self):
+        lib().oracle_set_hphc(*self.args)
+        return self
+
+    def __exit__(self, *exc):
+        lib().oracle_set_lj()
+        return False
 
 
 def bead_pair(bi, bj, xi, qi, xj, qj, box=None, eps=1.0, sigma=1.0, rc=2.5) -> dict:

@@ -95,6 +95,16 @@ typedef struct rb_ctx rb_ctx;
 int rb_ctx_create(rb_ctx **out, int32_t n_types, const int32_t *n_beads, const float *beads,
                   const double *mass, const double *inertia, float eps, float sigma, float rc);
 int rb_ctx_destroy(rb_ctx *ctx);
+
+/* Switches the context's bead potential to the half-power half-cosine form
+ * of the paper (section 3): U(r) = (b - r)^p - 2A for r <= b and
+ * -A (1 + cos(c (r - b))) for b < r < rc = b + pi / c, 0 beyond.  The printed
+ * attractive branch, -A cos(c (r - b)), would jump by A at r = b and end at
+ * +A; the form used joins both branches with zero slope and vanishes with
+ * zero slope at rc.  The paper's parameters: A = 0.00035, b = 1.46375,
+ * c = 3.3833, p = 2.5 (epsilon, sigma units).  Applies to every later bead
+ * sum with this context; the pair-list cutoff must use this rc. */
+int rb_ctx_set_hphc(rb_ctx *ctx, double A, double b, double c, double p);
 const char *rb_last_error(void);
 
 /* ---- pair list: half list i < j of body pairs closer than r_list --------

@@ -26,6 +26,7 @@ SIGNATURES = {
     "rb_last_error": (C.c_char_p, []),
     "rb_ctx_create": (C.c_int, [C.POINTER(P), I32, IP, FP, DP, DP, F32, F32, F32]),
     "rb_ctx_destroy": (C.c_int, [P]),
+    "rb_ctx_set_hphc": (C.c_int, [P, C.c_double, C.c_double, C.c_double, C.c_double]),
     "rb_pairlist_workspace_bytes": (SZ, [I32, DP, F64]),
     "rb_pairlist_build": (C.c_int, [I32, P, DP, F64, P, P, I32, P, P, C.c_int, P, SZ, P]),
     "rb_pair_descriptors": (C.c_int, [I32, P, P, DP, P, P, I32, F32, F32, P, P, P, P, P]),

@@ -9,6 +9,7 @@ memory and streams only.
 from __future__ import annotations
 
 import ctypes as C
+import math
 
 import numpy as np
 import torch
@@ -77,6 +78,11 @@ class Ctx:
               "rb_ctx_create")
         self.handle = h
         self.n_beads = nb
+
+    def set_hphc(self, A, b, c, p):
+        """Half-power half-cosine bead potential (rb_ctx_set_hphc)."""
+        check(lib().rb_ctx_set_hphc(self.handle, float(A), float(b), float(c), float(p)), "rb_ctx_set_hphc")
+        self.rc = float(b) + math.pi / float(c)
 
     def close(self):
         if self.handle:

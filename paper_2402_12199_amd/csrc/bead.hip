@@ -178,7 +178,33 @@ __device__ inline int stage_i(const Templates &T, const float4 *tb, int ti, int 
 // every lane): r[0] = E, r[1..3] = F_i, r[4..6] = tau_i (body i frame, about
 // its centre), r[7] = min squared distance over the tests performed (only
 // when TRACK_MIN).
-template <bool TRACK_MIN>
+// Energy and -(du/dr)/r of one bead pair at squared distance r2 < rc2.
+// Lennard-Jones: from 1/r^2.  Half-power half-cosine, with the attractive
+// branch read as -A (1 + cos(c (r - b))) (continuous with zero slope at b
+// and at rc = b + pi / c): (b - r)^p - 2A up to b, the cosine well beyond.
+template <int POT>
+__device__ inline void bead_pot(const LJ &lj, float r2, float &ee, float &fr) {
+    if constexpr (POT == kPotLJ) {
+        const float ir2 = __builtin_amdgcn_rcpf(r2);
+        const float s2 = lj.sig2 * ir2;
+        const float s6 = s2 * s2 * s2;
+        const float s12 = s6 * s6;
+        ee = fmaf(lj.c4e, s12 - s6, -lj.ushift);
+        fr = lj.c24e * fmaf(2.f, s12, -s6) * ir2;
+    } else {
+        const float r = sqrtf(r2);
+        const float ir = 1.f / r;
+        const float t = fmaxf(lj.b - r, 0.f);
+        const float tp1 = powf(t, lj.p - 1.f);
+        float sx, cx;
+        sincosf(lj.c * (r - lj.b), &sx, &cx);
+        const bool core = r <= lj.b;
+        ee = core ? fmaf(t, tp1, -2.f * lj.A) : -lj.A * (1.f + cx);
+        fr = (core ? lj.p * tp1 : -lj.A * lj.c * sx) * ir;
+    }
+}
+
+template <bool TRACK_MIN, int POT>
 __device__ inline void pair_sum(const LJ &lj, int ni, int nj, const WaveLds &L, int lane, float r[8]) {
     int P = 1;
     while (P < ni && P < kWave) P <<= 1;
@@ -197,12 +223,8 @@ __device__ inline void pair_sum(const LJ &lj, int ni, int nj, const WaveLds &L, 
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
             if (TRACK_MIN) r2min = fminf(r2min, r2);
             const bool in = r2 < lj.rc2;
-            const float ir2 = __builtin_amdgcn_rcpf(r2);
-            const float s2 = lj.sig2 * ir2;
-            const float s6 = s2 * s2 * s2;
-            const float s12 = s6 * s6;
-            const float ee = fmaf(lj.c4e, s12 - s6, -lj.ushift);
-            const float fr = lj.c24e * fmaf(2.f, s12, -s6) * ir2;
+            float ee, fr;
+            bead_pot<POT>(lj, r2, ee, fr);
             e += in ? ee : 0.f;
             const float frm = in ? fr : 0.f;
             fx = fmaf(frm, dx, fx);
@@ -223,6 +245,7 @@ __device__ inline void pair_sum(const LJ &lj, int ni, int nj, const WaveLds &L, 
 // Per-pair form: descriptors in, per-pair outputs in body i's frame out.
 // r_min is exact when some bead pair is closer than rc; otherwise the value
 // reported is at least rc (culled bead pairs are all farther than rc).
+template <int POT>
 __global__ __launch_bounds__(256) void k_bead_desc(Templates T, LJ lj, int ti, int tj, int64_t P,
                                                    const float *__restrict__ desc, float *__restrict__ out,
                                                    int32_t *__restrict__ flags, int stride) {
@@ -244,7 +267,7 @@ __global__ __launch_bounds__(256) void k_bead_desc(Templates T, LJ lj, int ti, i
         const int ni = nj ? stage_i(T, tb, ti, tj, d, R, cut2, L, lane) : 0;
         wave_lds_sync();
         float r[8];
-        pair_sum<true>(lj, ni, nj, L, lane, r);
+        pair_sum<true, POT>(lj, ni, nj, L, lane, r);
         ntests += (long long)ni * nj;
         wave_lds_sync();
         if (lane == 0) {
@@ -375,6 +398,7 @@ struct PairQueue {
     int n, head;
 };
 
+template <int POT>
 __global__ __launch_bounds__(kMdWaves * kWave) void k_bead_md(Templates T, LJ lj, int32_t n, const double *__restrict__ x,
                                                  const double *__restrict__ q, const int32_t *__restrict__ type,
                                                  Box box, const int32_t *__restrict__ pi,
@@ -458,7 +482,7 @@ __global__ __launch_bounds__(kMdWaves * kWave) void k_bead_md(Templates T, LJ lj
             if (ni == 0) continue;
             wave_lds_sync();
             float r[8];
-            pair_sum<false>(lj, ni, nj, L, lane, r);
+            pair_sum<false, POT>(lj, ni, nj, L, lane, r);
             ntests += (long long)ni * nj;
             wave_lds_sync();
             // lab-frame outputs, one component per lane: lanes 0..11 add
@@ -555,10 +579,14 @@ extern "C" int rb_bead_pair_eval(const rb_ctx *ctx, int64_t n_pairs, const float
     const size_t lds = bead_lds_bytes(ctx, kBeadWaves, stride);
     RB_REQUIRE(lds <= 65536, "rb_bead_pair_eval: templates need %zu bytes of LDS (max 65536)", lds);
     static int c_lds = -1, c_nb = 0;
-    const int nb = blocks_per_cu(k_bead_desc, 256, lds, &c_lds, &c_nb);
+    const int nb = blocks_per_cu(k_bead_desc<kPotLJ>, 256, lds, &c_lds, &c_nb);
     const int grid = grid_for(n_pairs, kBeadWaves, nb * device_cus_bead());
-    k_bead_desc<<<grid, 256, lds, (hipStream_t)stream>>>(ctx->dev.t, ctx->dev.lj, type_i, type_j, n_pairs, desc,
-                                                        out, flags, stride);
+    if (ctx->dev.lj.kind == kPotHPHC)
+        k_bead_desc<kPotHPHC><<<grid, 256, lds, (hipStream_t)stream>>>(ctx->dev.t, ctx->dev.lj, type_i, type_j,
+                                                                      n_pairs, desc, out, flags, stride);
+    else
+        k_bead_desc<kPotLJ><<<grid, 256, lds, (hipStream_t)stream>>>(ctx->dev.t, ctx->dev.lj, type_i, type_j,
+                                                                    n_pairs, desc, out, flags, stride);
     RB_LAUNCH_CHECK("rb_bead_pair_eval");
     return RB_OK;
 }
@@ -586,9 +614,10 @@ extern "C" int rb_bead_pair_forces(const rb_ctx *ctx, int32_t n, const double *x
                "rb_bead_pair_forces: templates need %zu bytes of LDS per block (device max %zu)", lds,
                device_max_lds());
     static int c_lds = -1, c_nb = 0;
-    const int nb = blocks_per_cu(k_bead_md, kMdWaves * kWave, lds, &c_lds, &c_nb);
+    const int nb = blocks_per_cu(k_bead_md<kPotLJ>, kMdWaves * kWave, lds, &c_lds, &c_nb);
     const int grid = grid_for(max_count, kMdWaves, nb * device_cus_bead());
-    k_bead_md<<<grid, kMdWaves * kWave, lds, (hipStream_t)stream>>>(ctx->dev.t, ctx->dev.lj, n, x, q, type, b, pair_i, pair_j,
+    auto kern = ctx->dev.lj.kind == kPotHPHC ? k_bead_md<kPotHPHC> : k_bead_md<kPotLJ>;
+    kern<<<grid, kMdWaves * kWave, lds, (hipStream_t)stream>>>(ctx->dev.t, ctx->dev.lj, n, x, q, type, b, pair_i, pair_j,
                                                       idx, count_dev, max_count, acc, flags, stride);
     RB_LAUNCH_CHECK("rb_bead_pair_forces");
     return RB_OK;

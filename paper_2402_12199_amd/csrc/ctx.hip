@@ -118,12 +118,26 @@ extern "C" int rb_ctx_create(rb_ctx **out, int32_t n_types, const int32_t *n_bea
     c->dev.inertia = static_cast<const double *>(c->alloc_mass) + n_types;
     double s2 = (double)sigma * sigma, sr2 = s2 / ((double)rc * rc);
     double sr6 = sr2 * sr2 * sr2;
+    c->dev.lj.kind = kPotLJ;
     c->dev.lj.rc2 = rc * rc;
     c->dev.lj.sig2 = (float)s2;
     c->dev.lj.c4e = 4.f * eps;
     c->dev.lj.c24e = 24.f * eps;
     c->dev.lj.ushift = (float)(4.0 * eps * (sr6 * sr6 - sr6));
     *out = c;
+    return RB_OK;
+}
+
+extern "C" int rb_ctx_set_hphc(rb_ctx *c, double A, double b, double cc, double p) {
+    RB_REQUIRE(c, "rb_ctx_set_hphc: null context");
+    RB_REQUIRE(A >= 0 && b > 0 && cc > 0 && p >= 1, "rb_ctx_set_hphc: need A >= 0, b > 0, c > 0, p >= 1");
+    const double rc = b + 3.14159265358979323846 / cc;
+    c->dev.lj.kind = kPotHPHC;
+    c->dev.lj.rc2 = (float)(rc * rc);
+    c->dev.lj.A = (float)A;
+    c->dev.lj.b = (float)b;
+    c->dev.lj.c = (float)cc;
+    c->dev.lj.p = (float)p;
     return RB_OK;
 }
 

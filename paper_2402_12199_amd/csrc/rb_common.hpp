@@ -39,8 +39,15 @@ struct Templates {
     int n_types;
 };
 
+// Bead-bead potential: kind 0 = Lennard-Jones 12-6 shifted in energy at rc
+// (the workloads'), kind 1 = half-power half-cosine (paper section 3).
+// rc2 is the squared cutoff either way.
+constexpr int kPotLJ = 0;
+constexpr int kPotHPHC = 1;
 struct LJ {
+    int kind;
     float rc2, sig2, c4e, c24e, ushift;  // 4 eps, 24 eps, u(rc)
+    float A, b, c, p;                     // half-power half-cosine
 };
 
 struct CtxDevice {

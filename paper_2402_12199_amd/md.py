@@ -36,9 +36,14 @@ class NNModel:
 
 class RigidSystem:
     def __init__(self, templates, masses, inertias, types, x, q, P, L, box, r_list, skin,
-                 eps=1.0, sigma=1.0, rc=2.5, max_pairs=None, device="cuda", screen=False):
+                 eps=1.0, sigma=1.0, rc=2.5, max_pairs=None, device="cuda", screen=False, hphc=None):
+        """hphc: dict(A, b, c, p) selects the half-power half-cosine bead
+        potential instead of Lennard-Jones (r_list must then cover its
+        cutoff b + pi / c)."""
         self.dev = torch.device(device)
         self.ctx = abi.Ctx(templates, masses, inertias, eps, sigma, rc)
+        if hphc is not None:
+            self.ctx.set_hphc(**hphc)
         n = len(x)
         self.n = n
         self.box = np.broadcast_to(np.asarray(box, np.float64), (3,)).copy()

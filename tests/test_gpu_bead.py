@@ -61,6 +61,49 @@ def test_bead_pair_eval_matches_oracle(abi, shape, n):
         assert np.all(rel < 2e-5 / ref[deep, 10] ** 2)
 
 
+@pytest.mark.parametrize("shape,n", [("cube5", 300), ("cyl134", 501)])
+def test_bead_pair_eval_hphc_matches_oracle(abi, shape, n):
+    # half-power half-cosine potential (soft core: every configuration,
+    # overlapping ones included, is in the parity domain)
+    body = getattr(configs, shape)()
+    P = obeads.HPHC_PAPER
+    rc = P["b"] + np.pi / P["c"]
+    desc = sampling.pair_batch(sampling.rng(23), n, 0.6 * (2 * body.r_in + 1.0),
+                               2 * body.r_max + rc).astype(np.float32)
+    ctx = _ctx(abi, [body])
+    ctx.set_hphc(**P)
+    d_dev = torch.tensor(np.ascontiguousarray(desc.T), device="cuda")
+    out = torch.full((11, n), float("nan"), dtype=torch.float32, device="cuda")
+    abi.rb_bead_pair_eval(ctx, d_dev, 0, 0, out)
+    got = out.cpu().numpy().T.astype(np.float64)
+    with obeads.use_hphc(**P):
+        ref = obeads.bead_pair_desc(_t32(body), _t32(body), desc.astype(np.float64))
+    np.testing.assert_allclose(got[:, 10], np.minimum(ref[:, 10], rc), rtol=1e-5)
+    assert ref[:, 10].min() > 1e-3 and (ref[:, 0] != 0).sum() > 0.5 * n
+    assert_close(got[:, 0], ref[:, 0], 1e-5, "E")
+    for s_, name in ((1, "F_j"), (4, "tau_i"), (7, "tau_j")):
+        assert_close(got[:, s_:s_ + 3], ref[:, s_:s_ + 3], 1e-4, name)
+
+
+def test_bead_forces_hphc_match_oracle(abi):
+    cfg = configs.config1()
+    st = state.initial_state(cfg)
+    from paper_2402_12199_amd.md import RigidSystem
+    P = obeads.HPHC_PAPER
+    rc = P["b"] + np.pi / P["c"]
+    b = cfg.body
+    sysm = RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"], cfg.box,
+                       2 * b.r_max + rc + cfg.skin, cfg.skin, hphc=P)
+    sysm.init_forces("bead")
+    sysm.check_capacity()
+    with obeads.use_hphc(**P):
+        ref = obeads.bead_system(st["x"], st["q"], st["types"], [_t32(b)], cfg.box)
+    assert ref["n_pairs"] > 0 and ref["E"] != 0
+    assert abs(sysm.energy() - ref["E"]) <= 1e-5 * abs(ref["E"])
+    assert_close(sysm.force.cpu().numpy().T, ref["F"], 1e-4, "force")
+    assert_close(sysm.torque.cpu().numpy().T, ref["tau"], 1e-4, "torque")
+
+
 def test_bead_pair_eval_mixed_types_and_empty(abi):
     c5, cy = configs.cube5(), configs.cyl134()
     ctx = _ctx(abi, [c5, cy])

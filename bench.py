@@ -12,8 +12,10 @@ Also reported (same run): a cube-6 surrogate trained on bead-labelled
 pairs (held-out errors), the network path on the same system with it (BF16
 MLP with bead fallback below d_min), the network kernels on 2^20 random
 cylinder pairs (forward, forward + input gradient; BF16 and FP32), the
-per-kernel roofline of the bead kernel, and the FP64 oracle on the host as
-a CPU baseline.  Inputs are synthetic and seeded.
+per-kernel roofline of the bead kernel, cylinder surrogates with the
+bead-vs-network dynamics of 32768 cylinders, the same comparison on cube
+shells with the paper's half-power half-cosine bead potential, and the FP64
+oracle on the host as a CPU baseline.  Inputs are synthetic and seeded.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -63,7 +65,7 @@ def make_system(cfg, st, torch):
     from paper_2402_12199_amd.md import RigidSystem
     b = cfg.body
     return RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"], cfg.box,
-                       cfg.r_list, cfg.skin)
+                       cfg.r_list, cfg.skin, hphc=cfg.hphc)
 
 
 GRAPH_STEPS = 10   # MD steps recorded per HIP graph
@@ -217,6 +219,31 @@ def learned_part(args, torch, abi, log):
     return out
 
 
+def hphc_part(args, torch, abi, log):
+    """The paper's half-power half-cosine bead potential on 4096 cube shells
+    (volume fraction 0.16, NVE kT=1): a surrogate trained on the pairs the
+    bead dynamics visits, then 2008 steps of the bead path and of the network
+    path from the same start, compared through g(r), P2, MSD and energy."""
+    from paper_2402_12199_amd.compare import compare
+    from paper_2402_12199_amd.md import NNModel
+    from paper_2402_12199_amd.surrogate import train_surrogate_md
+    from synth import configs, state
+    cfg = configs.config_hphc()
+    log(f"[bench] generating {cfg.name}")
+    st = state.initial_state(cfg)
+    log(f"[bench] {cfg.body.name} half-power half-cosine surrogate on bead-MD pairs, {args.hphc_epochs} epochs")
+    sur = train_surrogate_md(cfg, st, 1 << 20, 1 << 16, args.hphc_epochs, r_rej=0.0, log=log)
+    model = NNModel(params=sur["params"], norm=sur["norm"], precision=abi.RB_PREC_BF16, d_min=cfg.d_min,
+                    sw_lo=cfg.d_cut - 1.0, sw_hi=cfg.d_cut)
+    out = {"workload": f"{cfg.name}: {cfg.n_bodies} cube shells ({cfg.body.n} beads), half-power half-cosine "
+                       f"A={cfg.hphc['A']} b={cfg.hphc['b']} c={cfg.hphc['c']} p={cfg.hphc['p']}, "
+                       f"NVE kT={cfg.kT} dt={cfg.dt}",
+           "surrogate": {k: sur[k] for k in ("sampling", "epochs", "n_train", "n_test", "train_s", "samples_per_s")},
+           "held_out": sur["trained"], "held_out_untrained": sur["untrained"]}
+    out["dynamics"] = compare(cfg, st, {"nn_md": model}, chunks=8, replays=25, log=log)
+    return out
+
+
 def cpu_baseline(cfg, st, target_s=12.0):
     """The FP64 oracle (plain C, OpenMP over pairs) doing the same MD steps on
     the host: full force evaluation + integration per step."""
@@ -250,8 +277,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-nn", action="store_true", help="skip the network measurements")
     ap.add_argument("--no-learned", action="store_true",
-                    help="skip the cylinder surrogate and the network-vs-bead dynamics of 32768 cylinders")
+                    help="skip the cylinder and half-power half-cosine surrogates and their network-vs-bead "
+                         "dynamics")
     ap.add_argument("--cyl-epochs", type=int, default=100, help="cylinder surrogate epochs (2^21 pairs each)")
+    ap.add_argument("--hphc-epochs", type=int, default=300,
+                    help="half-power half-cosine cube surrogate epochs (2^20 pairs each)")
     ap.add_argument("--nn-steps", type=int, default=100,
                     help="timed steps of the network path (its trajectory stays sound for a limited time)")
     ap.add_argument("--nn-epochs", type=int, default=100, help="surrogate training epochs (2^20 pairs each)")
@@ -380,6 +410,7 @@ def main():
 
     if not args.no_learned:
         result["cylinders"] = learned_part(args, torch, abi, log)
+        result["hphc_cubes"] = hphc_part(args, torch, abi, log)
 
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")

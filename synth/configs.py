@@ -13,6 +13,7 @@ points the workload statements leave open are explicit fields here:
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass, field
 
 from .geometry import BodyType, box_length, make_cube, make_cylinder
@@ -36,6 +37,7 @@ class SystemConfig:
     rc: float = LJ_RC
     eps: float = LJ_EPS
     sigma: float = LJ_SIGMA
+    hphc: dict | None = None     # half-power half-cosine parameters (A, b, c, p) instead of LJ
 
     @property
     def box(self) -> float:
@@ -114,3 +116,16 @@ def config4(n_train: int = 1 << 21, n_test: int = 1 << 16) -> tuple[PairBatchCon
 def config5() -> SystemConfig:
     """32768 cylinders, volume fraction 0.15, NVE at kT=1."""
     return SystemConfig("cyl32768_phi0.15", cyl134(), 32768, 0.15, seed=1005, n_steps=2000)
+
+
+# Half-power half-cosine parameters of the paper (section 3), epsilon and sigma units.
+HPHC_PAPER = dict(A=0.00035, b=1.46375, c=3.3833, p=2.5)
+
+
+def config_hphc() -> SystemConfig:
+    """4096 cube shells of 152 beads with the paper's half-power half-cosine
+    bead potential (its parameters), volume fraction 0.16 (the paper's), NVE
+    at kT=1: the surrogate's dynamics against the bead path on a smooth pair
+    interaction."""
+    return SystemConfig("cubes4096_phi0.16_hphc", cube6(), 4096, 0.16, seed=1006, n_steps=2000,
+                        rc=HPHC_PAPER["b"] + math.pi / HPHC_PAPER["c"], hphc=dict(HPHC_PAPER))

@@ -153,3 +153,29 @@ def test_labelled_sets_reject_overlaps_and_match_the_oracle(abi):
                                 body.beads.astype(np.float32).astype(np.float64), desc.astype(np.float64))
     assert_close(lab[:, 0], ref[:, 0], 1e-5, "E")
     assert_close(lab[:, 1:10], ref[:, 1:10], 1e-4, "F, tau")
+
+
+def test_hphc_surrogate_dynamics_follow_the_bead_path(abi):
+    # With the paper's half-power half-cosine bead potential the pair energy
+    # is smooth enough for the surrogate to drive the dynamics: trained on
+    # the pairs the bead dynamics visits, its trajectory from the same start
+    # stays finite, conserves energy and diffuses like the bead trajectory.
+    import dataclasses
+    from paper_2402_12199_amd.compare import compare
+    from paper_2402_12199_amd.md import NNModel
+    from paper_2402_12199_amd.surrogate import train_surrogate_md
+    from synth import state
+    cfg = dataclasses.replace(configs.config_hphc(), name="cubes512_hphc", body=configs.cube5(), n_bodies=512,
+                              seed=77)
+    st = state.initial_state(cfg)
+    sur = train_surrogate_md(cfg, st, 1 << 17, 1 << 13, 60, r_rej=0.0, batch=2048)
+    h = sur["trained"]
+    assert h["rmse_E"] < 0.5 * h["std_E"] and h["rmse_F"] < h["std_F"]
+    model = NNModel(params=sur["params"], norm=sur["norm"], precision=abi.RB_PREC_BF16, d_min=cfg.d_min,
+                    sw_lo=cfg.d_cut - 1.0, sw_hi=cfg.d_cut)
+    out = compare(cfg, st, {"nn": model}, chunks=3, replays=10)
+    bead, nn = out["bead"], out["nn"]
+    assert bead["error"] is None and nn["error"] is None and nn["steps"] == bead["steps"] == 303
+    assert abs(nn["drift_per_body"]) < 5e-3 and abs(bead["drift_per_body"]) < 1e-5
+    assert 0.7 < nn["msd_ratio_vs_bead"] < 1.3
+    assert nn["rdf_l1_vs_bead"] < 0.2

@@ -292,9 +292,12 @@ __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
     }
 }
 
-// Batches up to this many tiles take the four-waves-per-tile form in BF16
-// (latency-bound sizes, such as the pair lists of dynamics); larger batches
-// the one-wave-per-tile form, which needs no barriers.
+// BF16 gradients of batches up to this many tiles take the
+// four-waves-per-tile form (latency-bound sizes); larger batches the
+// one-wave-per-tile form, which needs no barriers and is a few per cent
+// faster there.  Forces for dynamics always take the four-wave form: the
+// launch is sized for the list's capacity, while the pairs of a step are
+// usually far fewer.
 constexpr int64_t kWideMaxTiles = 16384;
 
 // Compute units of the current device (one persistent block per CU: the
@@ -315,7 +318,7 @@ static int launch(const NNArgs &a, int precision, int64_t rows, hipStream_t st) 
     const int64_t tiles = (rows + kTile - 1) / kTile;
     const int cus = device_cus();
     if constexpr (MODE != kEval) {
-        if (precision == RB_PREC_BF16 && tiles <= kWideMaxTiles) {
+        if (precision == RB_PREC_BF16 && (MODE == kForces || tiles <= kWideMaxTiles)) {
             k_nn_wide<MODE><<<grid_for(tiles, kWideGroups, cus), kWideThreads, 0, st>>>(a);
             return hip_check(hipGetLastError(), "network kernel launch");
         }

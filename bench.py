@@ -36,6 +36,7 @@ if ROOT not in sys.path:
 FP32_VECTOR_PEAK = 78.6e12     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, packed FP32 math not used
 BF16_MFMA_PEAK = 2.5e15        # dense
 FP32_MFMA_PEAK = 157.3e12
+HBM_PEAK = 8.0e12
 FLOP_PER_TEST = 8              # 3 sub + 1 mul + 2 fma
 
 # HBM bytes per launch of the bead kernel on this workload, from two rocprofv3
@@ -143,6 +144,111 @@ def bead_kernel_time(sysm, reps, torch, abi):
     tests = (ntests(sysm.flags_host(), abi) - t0) / reps
     abi.rb_accum_zero(sysm.n, sysm.acc)
     return a.elapsed_time(b) / reps, tests
+
+
+def time_launches(fn, reps, torch):
+    """Mean device duration of `fn` (one or more kernel launches on the
+    current stream): `reps` calls recorded once into a HIP graph, the graph
+    replayed between HIP events (so host launch overhead does not count)."""
+    fn()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        for _ in range(reps):
+            fn()
+    torch.cuda.current_stream().wait_stream(side)
+    g.replay()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    g.replay()
+    b.record(st)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def roof(ms, work, peak, unit, bound, what):
+    rate = work / (ms * 1e-3)
+    return {"ms": ms, "bound": bound, "achieved": rate / (1e9 if unit == "GB/s" else 1e12), "unit": unit,
+            "peak": peak / (1e9 if unit == "GB/s" else 1e12), "frac": rate / peak, "algorithmic_work": what}
+
+
+def kernel_table(sysm, cfg, torch, abi):
+    """Roofline of the hot-path kernels other than the bead sum, each timed
+    alone on the cube system's current state (after the timed run)."""
+    from paper_2402_12199_amd.nn import Trainer, make_norm
+    from synth import sampling
+    n, out = sysm.n, {}
+    f = sysm.flags_host()
+    npairs = int(f[abi.RB_FLAG_NPAIRS])
+    ms = time_launches(lambda: sysm.build_pairs(always=True), 10, torch)
+    out["pair_list_rebuild"] = roof(ms, 32.0 * n + 8.0 * npairs, HBM_PEAK, "GB/s", "hbm",
+                                    f"32 B per body + 8 B per listed pair ({n} bodies, {npairs} pairs)")
+    # the builder in its bandwidth regime: 2^22 point bodies at the same
+    # number density, uniform positions (multi-kernel path, list sorted by i)
+    from paper_2402_12199_amd.md import RigidSystem
+    nb = 1 << 22
+    boxb = float(sysm.box[0]) * (nb / n) ** (1.0 / 3.0)
+    gb = sampling.rng(31)
+    zero = np.zeros((nb, 3))
+    big = RigidSystem([np.zeros((1, 3))], [1.0], [[1.0, 1.0, 1.0]], np.zeros(nb, np.int32), gb.random((nb, 3)) * boxb,
+                      np.tile([1.0, 0, 0, 0], (nb, 1)), zero, zero, boxb, sysm.r_list, 0.0)
+    msb = time_launches(lambda: big.build_pairs(always=True), 5, torch)
+    npb = int(big.check_capacity()[abi.RB_FLAG_NPAIRS])
+    out["pair_list_rebuild_4M"] = roof(msb, 32.0 * nb + 8.0 * npb, HBM_PEAK, "GB/s", "hbm",
+                                       f"32 B per body + 8 B per listed pair ({nb} bodies at the cube system's "
+                                       f"number density, {npb} pairs)")
+    del big
+    torch.cuda.empty_cache()
+    ms = time_launches(lambda: abi.rb_accum_finalize(n, sysm.acc, sysm.force, sysm.torque, sysm.ev), 20, torch)
+    out["accum_finalize"] = roof(ms, 120.0 * n, HBM_PEAK, "GB/s", "hbm",
+                                 "120 B per body (6 int64 read and cleared, 6 FP32 written)")
+    st = {k: v.clone() for k, v in (("x", sysm.x), ("P", sysm.P), ("q", sysm.q), ("L", sysm.L))}
+    ms = time_launches(lambda: abi.rb_rigid_step_fused(sysm.ctx, cfg.dt, sysm.x, sysm.P, sysm.q, sysm.L, sysm.types,
+                                                       sysm.acc, sysm.force, sysm.torque, sysm.ev, sysm.x_ref,
+                                                       sysm.half_skin, None, sysm.flags, sysm.ws_rig), 20, torch)
+    for k, v in st.items():
+        getattr(sysm, k).copy_(v)
+    out["rigid_step_fused"] = roof(ms, 248.0 * n, HBM_PEAK, "GB/s", "hbm",
+                                   "248 B per body (FP64 state read and written, accumulator, forces)")
+    desc = sysm.pair_configurations(cfg.d_min, cfg.d_cut)      # allocates the routing buffers
+    ms = time_launches(lambda: abi.rb_pair_descriptors(sysm.x, sysm.q, sysm.box, sysm.pair_i, sysm.pair_j, cfg.d_min,
+                                                       sysm.desc, sysm.idx_nn, sysm.idx_bead, sysm.flags,
+                                                       d_max=cfg.d_cut), 20, torch)
+    out["pair_descriptors"] = roof(ms, 100.0 * npairs, HBM_PEAK, "GB/s", "hbm",
+                                   f"100 B per listed pair ({npairs}): two bodies' FP64 state, 7 FP32 out")
+    nnn = desc.shape[1]
+    params = torch.tensor(sampling.xavier_params(5).astype(np.float32), device="cuda")
+    norm = make_norm(cfg.d_cut)
+    ms = time_launches(lambda: abi.rb_nn_pair_forces(params, norm, abi.RB_PREC_BF16, sysm.q, sysm.pair_i, sysm.pair_j,
+                                                     sysm.desc, sysm.idx_nn, sysm.flags[abi.RB_FLAG_NNN:],
+                                                     sysm.max_pairs, cfg.d_cut - 1.0, cfg.d_cut, sysm.acc,
+                                                     sysm.flags), 20, torch)
+    abi.rb_accum_zero(n, sysm.acc)
+    out["nn_pair_forces_md"] = roof(ms, 2 * 100352.0 * nnn, BF16_MFMA_PEAK, "TFLOP/s", "mfma",
+                                    f"2 x 100352 FLOP per network pair ({nnn} pairs of the list)")
+    tr = Trainer(sampling.xavier_params(6), norm, batch=8192)
+    g = sampling.rng(9)
+    dd = torch.tensor(np.ascontiguousarray(sampling.pair_batch(g, 1 << 16, cfg.d_min, cfg.d_cut)
+                                           .astype(np.float32).T), device="cuda")
+    yy = torch.tensor(g.standard_normal(1 << 16).astype(np.float32), device="cuda")
+    idx = torch.arange(8192, dtype=torch.int32, device="cuda")
+    ms = time_launches(lambda: tr.step(dd, yy, idx), 20, torch)
+    out["nn_train_step_8192"] = roof(ms, 3.0e5 * 8192, BF16_MFMA_PEAK, "TFLOP/s", "mfma",
+                                     "3.0e5 FLOP per sample (forward, input-to-weight reverse pass, weight "
+                                     "gradients), batch 8192")
+    lab = torch.empty((11, 1 << 16), dtype=torch.float32, device="cuda")
+    t0 = ntests(sysm.flags_host(), abi)
+    ms = time_launches(lambda: abi.rb_bead_pair_eval(sysm.ctx, dd, 0, 0, lab, sysm.flags), 5, torch)
+    tests = (ntests(sysm.flags_host(), abi) - t0) / 11          # 1 eager call + 2 replays of 5
+    out["bead_pair_eval_labels"] = roof(ms, tests * FLOP_PER_TEST, FP32_VECTOR_PEAK, "TFLOP/s", "alu",
+                                        f"{tests:.0f} culled bead tests x {FLOP_PER_TEST} FLOP per launch "
+                                        f"(2^16 cube-6 configurations)")
+    return out
 
 
 def nn_kernels(torch, abi):
@@ -345,6 +451,9 @@ def main():
                                          f"{tests_brute} tests)",
                      "brute_force_equivalent_tflops": tests_brute * FLOP_PER_TEST / (kern_ms * 1e-3) / 1e12},
     }
+
+    log("[bench] per-kernel rooflines")
+    result["kernels"] = kernel_table(sysm, cfg, torch, abi)
 
     if not args.no_nn:
         # network path on the same system, with a cube-6 surrogate trained

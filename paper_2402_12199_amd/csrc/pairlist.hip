@@ -158,13 +158,11 @@ __global__ void k_scatter(int32_t n, const int32_t *__restrict__ cell_of, const 
     sorted[start[c] + slot] = i;
 }
 
-// Insertion sort of each cell's ids (cells hold a handful of bodies).
-__global__ void k_sort_cells(int ncell, const int32_t *__restrict__ start, int32_t *__restrict__ sorted,
-                             const int32_t *flags, int mode) {
-    if (skip(flags, mode)) return;
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell) return;
-    int b = start[c], e = start[c + 1];
+// Insertion sort of each cell's ids (cells hold a handful of bodies), then
+// the positions in the same cell order (xs, 3 x n FP64), so that the
+// neighbour scans read each cell's bodies as one contiguous run.
+__device__ inline void sort_cell_and_gather(int b, int e, int32_t n, const double *__restrict__ x,
+                                            int32_t *__restrict__ sorted, double *__restrict__ xs) {
     for (int k = b + 1; k < e; ++k) {
         int v = sorted[k], m = k - 1;
         while (m >= b && sorted[m] > v) {
@@ -173,18 +171,34 @@ __global__ void k_sort_cells(int ncell, const int32_t *__restrict__ start, int32
         }
         sorted[m + 1] = v;
     }
+    for (int k = b; k < e; ++k) {
+        const int j = sorted[k];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) xs[a * n + k] = x[a * n + j];
+    }
 }
 
+__global__ void k_sort_cells(int ncell, int32_t n, const double *__restrict__ x, const int32_t *__restrict__ start,
+                             int32_t *__restrict__ sorted, double *__restrict__ xs, const int32_t *flags, int mode) {
+    if (skip(flags, mode)) return;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    sort_cell_and_gather(start[c], start[c + 1], n, x, sorted, xs);
+}
+
+// Thread t takes the t-th body in cell order, so that neighbouring threads
+// scan the same neighbour cells; counts and offsets stay indexed by body.
 template <bool EMIT>
-__global__ void k_neigh(int32_t n, const double *__restrict__ x, CellGrid g, const int32_t *__restrict__ cell_of,
+__global__ void k_neigh(int32_t n, const double *__restrict__ xs, CellGrid g, const int32_t *__restrict__ cell_of,
                         const int32_t *__restrict__ start, const int32_t *__restrict__ sorted,
                         int32_t *__restrict__ ncount, const int32_t *__restrict__ noff,
                         int32_t *__restrict__ pi, int32_t *__restrict__ pj, int32_t cap,
                         const int32_t *flags, int mode) {
     if (skip(flags, mode)) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double xi = x[i], yi = x[n + i], zi = x[2 * n + i];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int i = sorted[t];
+    const double xi = xs[t], yi = xs[n + t], zi = xs[2 * n + t];
     const int id = cell_of[i];
     const int cz = id % g.nc[2], cy = (id / g.nc[2]) % g.nc[1], cx = id / (g.nc[2] * g.nc[1]);
     int lo[3], hi[3];
@@ -210,9 +224,9 @@ __global__ void k_neigh(int32_t n, const double *__restrict__ x, CellGrid g, con
                 for (int m = start[c], e = start[c + 1]; m < e; ++m) {
                     const int j = sorted[m];
                     if (j <= i) continue;
-                    const double dx = min_image(x[j] - xi, g.L[0], g.inv[0]);
-                    const double dy = min_image(x[n + j] - yi, g.L[1], g.inv[1]);
-                    const double dz = min_image(x[2 * n + j] - zi, g.L[2], g.inv[2]);
+                    const double dx = min_image(xs[m] - xi, g.L[0], g.inv[0]);
+                    const double dy = min_image(xs[n + m] - yi, g.L[1], g.inv[1]);
+                    const double dz = min_image(xs[2 * n + m] - zi, g.L[2], g.inv[2]);
                     if (dx * dx + dy * dy + dz * dz < g.rl2) {
                         if (EMIT) {
                             if (out < cap) {
@@ -290,8 +304,8 @@ __device__ int block_scan(const int32_t *in, int32_t *out, int m) {
 __global__ __launch_bounds__(kSmallThreads) void k_pl_cells(int32_t n, const double *__restrict__ x, CellGrid g,
                                                             int32_t *__restrict__ cell_of, int32_t *__restrict__ cnt,
                                                             int32_t *__restrict__ start, int32_t *__restrict__ fill,
-                                                            int32_t *__restrict__ sorted, double *__restrict__ x_ref,
-                                                            int32_t *__restrict__ counter,
+                                                            int32_t *__restrict__ sorted, double *__restrict__ xs,
+                                                            double *__restrict__ x_ref, int32_t *__restrict__ counter,
                                                             const int32_t *__restrict__ flags, int mode) {
     if (skip(flags, mode)) return;
     const int t = threadIdx.x, T = kSmallThreads;
@@ -322,34 +336,23 @@ __global__ __launch_bounds__(kSmallThreads) void k_pl_cells(int32_t n, const dou
         sorted[start[c] + atomicAdd(fill + c, 1)] = i;
     }
     __syncthreads();
-    for (int c = t; c < g.ncell; c += T) {
-        const int b = start[c], e = start[c + 1];
-        for (int k = b + 1; k < e; ++k) {
-            const int v = sorted[k];
-            int m = k - 1;
-            while (m >= b && sorted[m] > v) {
-                sorted[m + 1] = sorted[m];
-                --m;
-            }
-            sorted[m + 1] = v;
-        }
-    }
+    for (int c = t; c < g.ncell; c += T) sort_cell_and_gather(start[c], start[c + 1], n, x, sorted, xs);
 }
 
 // Pairs (i, j > i) of body i with the bodies of one neighbour cell c; writes
 // them from out on when EMIT (up to cap), returns their number.
 template <bool EMIT>
 __device__ inline int cell_pairs(int i, int c, double xi, double yi, double zi, int32_t n,
-                                 const double *__restrict__ x, const CellGrid &g, const int32_t *__restrict__ start,
+                                 const double *__restrict__ xs, const CellGrid &g, const int32_t *__restrict__ start,
                                  const int32_t *__restrict__ sorted, int out, int32_t *__restrict__ pi,
                                  int32_t *__restrict__ pj, int32_t cap) {
     int cnt = 0;
     for (int m = start[c], e = start[c + 1]; m < e; ++m) {
         const int j = sorted[m];
         if (j <= i) continue;
-        const double dx = min_image(x[j] - xi, g.L[0], g.inv[0]);
-        const double dy = min_image(x[n + j] - yi, g.L[1], g.inv[1]);
-        const double dz = min_image(x[2 * n + j] - zi, g.L[2], g.inv[2]);
+        const double dx = min_image(xs[m] - xi, g.L[0], g.inv[0]);
+        const double dy = min_image(xs[n + m] - yi, g.L[1], g.inv[1]);
+        const double dz = min_image(xs[2 * n + m] - zi, g.L[2], g.inv[2]);
         if (dx * dx + dy * dy + dz * dz < g.rl2) {
             if (EMIT && out + cnt < cap) {
                 pi[out + cnt] = i;
@@ -361,7 +364,7 @@ __device__ inline int cell_pairs(int i, int c, double xi, double yi, double zi, 
     return cnt;
 }
 
-__global__ __launch_bounds__(kPairThreads) void k_pl_pairs(int32_t n, const double *__restrict__ x, CellGrid g,
+__global__ __launch_bounds__(kPairThreads) void k_pl_pairs(int32_t n, const double *__restrict__ xs, CellGrid g,
                                                            const int32_t *__restrict__ cell_of,
                                                            const int32_t *__restrict__ start,
                                                            const int32_t *__restrict__ sorted,
@@ -371,7 +374,9 @@ __global__ __launch_bounds__(kPairThreads) void k_pl_pairs(int32_t n, const doub
     if (skip(flags, mode)) return;
     __shared__ bool last;
     const int lane = threadIdx.x & (kWave - 1), k = lane & 31;
-    const int i = (int)(((int64_t)blockIdx.x * (kPairThreads / kWave) + (threadIdx.x >> 6)) * 2 + (lane >> 5));
+    // half-wave t takes the t-th body in cell order (neighbouring half-waves
+    // scan the same cells)
+    const int t = (int)(((int64_t)blockIdx.x * (kPairThreads / kWave) + (threadIdx.x >> 6)) * 2 + (lane >> 5));
     // neighbour cells per axis: all three offsets, or every cell when the
     // axis has fewer than three
     int lo[3], m[3];
@@ -380,13 +385,14 @@ __global__ __launch_bounds__(kPairThreads) void k_pl_pairs(int32_t n, const doub
         lo[a] = g.nc[a] >= 3 ? -1 : 0;
         m[a] = g.nc[a] >= 3 ? 3 : g.nc[a];
     }
-    const bool active = i < n && k < m[0] * m[1] * m[2];
+    const bool active = t < n && k < m[0] * m[1] * m[2];
     double xi = 0, yi = 0, zi = 0;
-    int c = 0, cnt = 0;
+    int i = 0, c = 0, cnt = 0;
     if (active) {
-        xi = x[i];
-        yi = x[n + i];
-        zi = x[2 * n + i];
+        i = sorted[t];
+        xi = xs[t];
+        yi = xs[n + t];
+        zi = xs[2 * n + t];
         const int id = cell_of[i];
         const int cz = id % g.nc[2], cy = (id / g.nc[2]) % g.nc[1], cx = id / (g.nc[2] * g.nc[1]);
         int nx = cx + lo[0] + k / (m[1] * m[2]);
@@ -396,7 +402,7 @@ __global__ __launch_bounds__(kPairThreads) void k_pl_pairs(int32_t n, const doub
         ny += ny < 0 ? g.nc[1] : (ny >= g.nc[1] ? -g.nc[1] : 0);
         nz += nz < 0 ? g.nc[2] : (nz >= g.nc[2] ? -g.nc[2] : 0);
         c = (nx * g.nc[1] + ny) * g.nc[2] + nz;
-        cnt = cell_pairs<false>(i, c, xi, yi, zi, n, x, g, start, sorted, 0, pi, pj, cap);
+        cnt = cell_pairs<false>(i, c, xi, yi, zi, n, xs, g, start, sorted, 0, pi, pj, cap);
     }
     // offsets of the lanes within the body's run (half-wave scan), one
     // reservation per body
@@ -410,7 +416,8 @@ __global__ __launch_bounds__(kPairThreads) void k_pl_pairs(int32_t n, const doub
     int base = 0;
     if (k == 0 && total > 0) base = atomicAdd(counter, total);
     base = __shfl(base, 0, 32);
-    if (active && cnt > 0) (void)cell_pairs<true>(i, c, xi, yi, zi, n, x, g, start, sorted, base + incl - cnt, pi, pj, cap);
+    if (active && cnt > 0)
+        (void)cell_pairs<true>(i, c, xi, yi, zi, n, xs, g, start, sorted, base + incl - cnt, pi, pj, cap);
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
@@ -428,7 +435,7 @@ __global__ __launch_bounds__(kPairThreads) void k_pl_pairs(int32_t n, const doub
 }
 
 struct PLLayout {
-    size_t cell_of, cnt, start, fill, sorted, ncount, noff, tmp, counter, total;
+    size_t cell_of, cnt, start, fill, sorted, ncount, noff, tmp, counter, xs, total;
 };
 
 static bool make_grid(int32_t n, const double *box, double r_list, CellGrid &g) {
@@ -465,6 +472,7 @@ static PLLayout layout(int32_t n, int ncell) {
     L.noff = o; o += al(sizeof(int32_t) * (n + 1));
     L.tmp = o; o += al(sizeof(int32_t) * kScanTile);
     L.counter = o; o += al(sizeof(int32_t) * 2);
+    L.xs = o; o += al(sizeof(double) * 3 * (size_t)n);
     L.total = o;
     return L;
 }
@@ -505,14 +513,15 @@ extern "C" int rb_pairlist_build(int32_t n, const double *x, const double *box, 
             *start = (int32_t *)(w + L.start), *fill = (int32_t *)(w + L.fill),
             *sorted = (int32_t *)(w + L.sorted), *ncount = (int32_t *)(w + L.ncount),
             *noff = (int32_t *)(w + L.noff), *tmp = (int32_t *)(w + L.tmp);
+    double *xs = (double *)(w + L.xs);
     hipStream_t st = (hipStream_t)stream;
     if (n <= kSmallBodies && g.ncell <= kSmallCells) {
         int32_t *counter = (int32_t *)(w + L.counter);
-        k_pl_cells<<<1, kSmallThreads, 0, st>>>(n, x, g, cell_of, cnt, start, fill, sorted, x_ref, counter, flags,
-                                                mode);
+        k_pl_cells<<<1, kSmallThreads, 0, st>>>(n, x, g, cell_of, cnt, start, fill, sorted, xs, x_ref, counter,
+                                                flags, mode);
         const int bodies_per_block = 2 * kPairThreads / kWave;
         k_pl_pairs<<<(n + bodies_per_block - 1) / bodies_per_block, kPairThreads, 0, st>>>(
-            n, x, g, cell_of, start, sorted, pair_i, pair_j, max_pairs, counter, flags, mode);
+            n, xs, g, cell_of, start, sorted, pair_i, pair_j, max_pairs, counter, flags, mode);
         RB_LAUNCH_CHECK("rb_pairlist_build");
         return RB_OK;
     }
@@ -522,11 +531,11 @@ extern "C" int rb_pairlist_build(int32_t n, const double *x, const double *box, 
     k_bin<<<gb, 256, 0, st>>>(n, x, g, cell_of, cnt, x_ref, flags, mode);
     scan(cnt, start, g.ncell, tmp, flags, mode, -1, st);
     k_scatter<<<gb, 256, 0, st>>>(n, cell_of, start, fill, sorted, flags, mode);
-    k_sort_cells<<<gc, 256, 0, st>>>(g.ncell, start, sorted, flags, mode);
-    k_neigh<false><<<gb, 256, 0, st>>>(n, x, g, cell_of, start, sorted, ncount, nullptr, nullptr, nullptr, 0,
+    k_sort_cells<<<gc, 256, 0, st>>>(g.ncell, n, x, start, sorted, xs, flags, mode);
+    k_neigh<false><<<gb, 256, 0, st>>>(n, xs, g, cell_of, start, sorted, ncount, nullptr, nullptr, nullptr, 0,
                                        flags, mode);
     scan(ncount, noff, n, tmp, flags, mode, max_pairs, st);
-    k_neigh<true><<<gb, 256, 0, st>>>(n, x, g, cell_of, start, sorted, nullptr, noff, pair_i, pair_j, max_pairs,
+    k_neigh<true><<<gb, 256, 0, st>>>(n, xs, g, cell_of, start, sorted, nullptr, noff, pair_i, pair_j, max_pairs,
                                       flags, mode);
     k_finish<<<1, 1, 0, st>>>(flags, mode);
     RB_LAUNCH_CHECK("rb_pairlist_build");

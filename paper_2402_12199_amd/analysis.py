@@ -50,6 +50,15 @@ def msd(x0: np.ndarray, x: np.ndarray) -> float:
     return float((d * d).sum(axis=1).mean())
 
 
+def msr(q0: np.ndarray, q: np.ndarray) -> float:
+    """Mean-squared rotation (supplementary section 5): the mean over bodies
+    of the orientational distance 1 - <q0, q>^2 between each body's starting
+    and current unit quaternions (0 for the same orientation, q and -q
+    included; 1 for orientations a half turn apart)."""
+    dot = (np.asarray(q0, np.float64) * np.asarray(q, np.float64)).sum(axis=1)
+    return float((1.0 - dot * dot).mean())
+
+
 def rdf_distance(r: np.ndarray, g1: np.ndarray, g2: np.ndarray) -> float:
     """Integrated absolute difference of two g(r) on the same bins, divided by
     the integral of the first."""

@@ -32,7 +32,7 @@ def run_dynamics(cfg, st, path: str, nn: NNModel | None = None, chunks: int = 8,
     sysm.init_forces(path)
     ke0 = float((st["P"] ** 2).sum() / (2 * b.mass) + (st["L"] ** 2 / (2 * b.inertia)).sum())
     e0 = sysm.energy() + ke0
-    x0 = st["x"].copy()
+    x0, q0 = st["x"].copy(), st["q"].copy()
     stream = torch.cuda.current_stream()
     snaps, energies, times, steps_done, graph = [], [e0], [], 0, None
     f_prev = sysm.flags_host()
@@ -68,13 +68,13 @@ def run_dynamics(cfg, st, path: str, nn: NNModel | None = None, chunks: int = 8,
     gpu_s = 1e-3 * float(np.sum(times))
     return dict(path=path, steps=steps_done, timed_steps=timed_steps, timed_gpu_s=gpu_s,
                 steps_per_s=timed_steps / gpu_s if gpu_s > 0 else None,
-                pair_evals_per_step=n_eval / max(steps_done, 1), energies=energies, x0=x0, snaps=snaps,
+                pair_evals_per_step=n_eval / max(steps_done, 1), energies=energies, x0=x0, q0=q0, snaps=snaps,
                 rebuilds=int(f[abi.RB_FLAG_NREBUILDS]), fallback_max=fallback_max, error=error)
 
 
 def observables(cfg, run: dict, rdf_bins: int = 80) -> dict:
-    """g(r) of the last snapshot, P2 of the body z axis, MSD per snapshot,
-    energy drift per body."""
+    """g(r) of the last snapshot, P2 of the body z axis, MSD and MSR per
+    snapshot, energy drift per body."""
     if not run["snaps"]:
         return {}
     steps, x, q = run["snaps"][-1]
@@ -82,6 +82,7 @@ def observables(cfg, run: dict, rdf_bins: int = 80) -> dict:
     e = np.asarray(run["energies"])
     return dict(step=steps, r=r, g=g, p2=analysis.p2(q, axis=2),
                 msd=[(s, analysis.msd(run["x0"], xs)) for s, xs, _ in run["snaps"]],
+                msr=[(s, analysis.msr(run["q0"], qs)) for s, _, qs in run["snaps"]],
                 drift_per_body=float((e[-1] - e[0]) / cfg.n_bodies),
                 max_dev_per_body=float(np.abs(e - e[0]).max() / cfg.n_bodies))
 
@@ -99,7 +100,8 @@ def compare(cfg, st, models: dict, chunks: int = 8, replays: int = 25, log=None)
         out[p] = {k: r[k] for k in ("path", "steps", "timed_steps", "steps_per_s", "pair_evals_per_step", "rebuilds",
                                     "fallback_max", "error")}
         if o:
-            out[p].update(p2=o["p2"], msd_last=o["msd"][-1][1], drift_per_body=o["drift_per_body"],
+            out[p].update(p2=o["p2"], msd_last=o["msd"][-1][1], msr_last=o["msr"][-1][1],
+                          drift_per_body=o["drift_per_body"],
                           max_dev_per_body=o["max_dev_per_body"],
                           rdf_peak=[float(o["r"][np.argmax(o["g"])]), float(o["g"].max())])
         if p == "bead" or not o or not obs["bead"]:
@@ -108,6 +110,8 @@ def compare(cfg, st, models: dict, chunks: int = 8, replays: int = 25, log=None)
             out[p]["rdf_l1_vs_bead"] = analysis.rdf_distance(obs["bead"]["r"], obs["bead"]["g"], o["g"])
             mb = obs["bead"]["msd"][-1][1]
             out[p]["msd_ratio_vs_bead"] = o["msd"][-1][1] / mb if mb > 0 else None
+            rb = obs["bead"]["msr"][-1][1]
+            out[p]["msr_ratio_vs_bead"] = o["msr"][-1][1] / rb if rb > 0 else None
         if out["bead"]["steps_per_s"] and out[p]["steps_per_s"]:
             out[p]["speedup_steps_vs_bead"] = out[p]["steps_per_s"] / out["bead"]["steps_per_s"]
     return out

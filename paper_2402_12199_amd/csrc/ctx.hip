@@ -31,11 +31,16 @@ __global__ void k_zero_i64(int64_t *a, int64_t n) {
 }
 
 // Converts the accumulator and clears it for the next evaluation (each word
-// is read and cleared by the same thread).
-__global__ void k_finalize(int32_t n, int64_t *__restrict__ acc, float *__restrict__ force,
+// is read and cleared by the same thread).  The first nb blocks take the
+// bodies, one extra block the global sums.
+__global__ void k_finalize(int32_t n, int nb, int64_t *__restrict__ acc, float *__restrict__ force,
                            float *__restrict__ torque, double *__restrict__ ev) {
     const double s = 1.0 / RB_ACC_SCALE;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    if ((int)blockIdx.x == nb) {
+        finalize_globals(acc + 6 * (int64_t)n, ev);
+        return;
+    }
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += nb * blockDim.x) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             force[a * n + i] = (float)((double)acc[a * (int64_t)n + i] * s);
@@ -44,7 +49,6 @@ __global__ void k_finalize(int32_t n, int64_t *__restrict__ acc, float *__restri
             acc[(3 + a) * (int64_t)n + i] = 0;
         }
     }
-    if (blockIdx.x == 0) finalize_globals(acc + 6 * (int64_t)n, ev);
 }
 
 }  // namespace rb
@@ -160,8 +164,8 @@ extern "C" int rb_accum_zero(int32_t n, int64_t *acc, void *stream) {
 extern "C" int rb_accum_finalize(int32_t n, int64_t *acc, float *force, float *torque,
                                  double *energy_virial, void *stream) {
     RB_REQUIRE(n >= 0 && acc && force && torque, "rb_accum_finalize: bad arguments");
-    k_finalize<<<grid_for(n > 0 ? n : 1, 256, 4096), 256, 0, (hipStream_t)stream>>>(
-        n, acc, force, torque, energy_virial);
+    const int nb = grid_for(n > 0 ? n : 1, 256, 4096);
+    k_finalize<<<nb + 1, 256, 0, (hipStream_t)stream>>>(n, nb, acc, force, torque, energy_virial);
     RB_LAUNCH_CHECK("rb_accum_finalize");
     return RB_OK;
 }

@@ -252,7 +252,7 @@ __global__ __launch_bounds__(kIntThreads) void k_fused(int32_t n, double dt, dou
         }
     }
     if (__any(moved) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(flags + RB_FLAG_REBUILD, 1);
-    if (blockIdx.x == 0) finalize_globals(acc + 6 * (int64_t)n, ev);
+    if (blockIdx.x == gridDim.x - 1) finalize_globals(acc + 6 * (int64_t)n, ev);
     if (kinetic) grid_sum2(kt, kr, partial, ticket, kinetic);
 }
 
@@ -264,7 +264,7 @@ using namespace rb;
 
 extern "C" size_t rb_rigid_workspace_bytes(int32_t n) {
     if (n <= 0) return 256;
-    return ((sizeof(double) * 2 * nblocks(n) + 255) & ~(size_t)255) + 256;
+    return ((sizeof(double) * 2 * (nblocks(n) + 1) + 255) & ~(size_t)255) + 256;
 }
 
 extern "C" int rb_rigid_step(const rb_ctx *ctx, int phase, int32_t n, double dt, double *x, double *P,
@@ -305,7 +305,8 @@ extern "C" int rb_rigid_step_fused(const rb_ctx *ctx, int32_t n, double dt, doub
     char *w = static_cast<char *>(ws);
     double *partial = reinterpret_cast<double *>(w);
     unsigned *ticket = reinterpret_cast<unsigned *>(w + rb_rigid_workspace_bytes(n) - 256);
-    k_fused<<<(int)nblocks(n), kIntThreads, 0, (hipStream_t)stream>>>(
+    // one block more than the bodies need: it adds up the global sums
+    k_fused<<<(int)nblocks(n) + 1, kIntThreads, 0, (hipStream_t)stream>>>(
         n, dt, x, P, q, L, type, ctx->dev.mass, ctx->dev.inertia, acc, force, torque, energy_virial, x_ref,
         half_skin * half_skin, flags, partial, ticket, kinetic);
     RB_LAUNCH_CHECK("rb_rigid_step_fused");

@@ -113,17 +113,29 @@ __device__ inline T wave_sum(T v) {
 
 // Sums and clears the RB_ACC_SLOTS slots of each of the 10 global fixed-point
 // sums (energy, virial), one lane per slot and one wave per sum; every wave of
-// the calling block takes part.  Integer sums: the order does not matter.
+// the calling block takes part, with all of a wave's loads issued before its
+// sums.  Integer sums: the order does not matter.
 __device__ inline void finalize_globals(int64_t *acc_globals, double *ev) {
     static_assert(RB_ACC_SLOTS == kWave, "one lane per slot");
+    constexpr int kSums = 10, kPerWave = 3;   // blocks of at least four waves: one round
     const int lane = threadIdx.x & (kWave - 1);
-    const int nw = (int)(blockDim.x / kWave);
-    for (int g = (int)(threadIdx.x / kWave); g < 10; g += nw) {
-        int64_t *p = acc_globals + g * RB_ACC_SLOTS + lane;
-        long long v = *p;
-        *p = 0;
-        v = wave_sum(v);
-        if (lane == 0 && ev) ev[g] = (double)v * (1.0 / RB_ACC_SCALE);
+    const int w = (int)(threadIdx.x / kWave), nw = (int)(blockDim.x / kWave);
+    for (int g0 = w; g0 < kSums; g0 += kPerWave * nw) {
+        long long v[kPerWave];
+#pragma unroll
+        for (int r = 0; r < kPerWave; ++r) {
+            const int g = g0 + r * nw;
+            v[r] = g < kSums ? acc_globals[g * RB_ACC_SLOTS + lane] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < kPerWave; ++r) {
+            const int g = g0 + r * nw;
+            if (g < kSums) {
+                acc_globals[g * RB_ACC_SLOTS + lane] = 0;
+                const long long s = wave_sum(v[r]);
+                if (lane == 0 && ev) ev[g] = (double)s * (1.0 / RB_ACC_SCALE);
+            }
+        }
     }
 }
 

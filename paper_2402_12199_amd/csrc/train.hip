@@ -5,11 +5,14 @@
 //   k_train_fb     per 16-row tile: forward with the activations h_l and
 //                  reverse pass with the deltas dX/dz_l written to the
 //                  workspace (feature-major), residuals for the loss
-//   k_train_wgrad  per 512-row chunk of the batch: partial weight gradients.
-//                  dW_l = sum_b delta_l h_{l-1}^T for the three 128x128
-//                  layers as MFMA GEMMs over the batch (BF16 operands in the
-//                  BF16 mode, FP32 otherwise), the FP32 layers (W1, W5) and
-//                  the biases as plain sums, and the chunk's loss
+//   k_train_wgrad  per 256-row chunk of the batch: partial weight gradients
+//                  dW_l = sum_b delta_l h_{l-1}^T and db_l = sum_b delta_l.
+//                  BF16 mode: one block per layer, each an MFMA GEMM over the
+//                  chunk with BF16 hi/lo operands staged once in LDS for all
+//                  eight waves (the 128 x 7 input layer and the 1 x 128
+//                  output layer padded to 16-row tiles), the loss beside the
+//                  output layer.  FP32 mode: FP32 MFMA from global memory for
+//                  the 128x128 layers, plain sums for the rest
 //   k_adam         sums the chunk partials in a fixed order (deterministic)
 //                  and applies the Adam update
 #include "nn_tile.hpp"
@@ -17,7 +20,6 @@
 namespace rb {
 
 constexpr int kChunk = 256;
-constexpr int kSmallBlocks = 8;   // blocks per chunk for the FP32 layers, biases and loss
 constexpr int kPart = NPARAMS + 1;   // per chunk: gradient, then the loss sum
 
 struct TrainArgs {
@@ -102,99 +104,255 @@ __global__ __launch_bounds__(kTrainWideThreads) void k_train_fb_wide(TrainArgs a
     }
 }
 
+// FP32 mode, edge block of a chunk: dW1 (128 x 7), db1, dW5, db5 and the loss sum, one
+// dot product over the chunk per output (lanes stride over the rows), with
+// the chunk's 7 input rows and the output delta staged in LDS.
+__device__ void wgrad_edge(const TrainArgs &a, int r0, int nr, float *part, float (*E)[kChunk]) {
+    const int64_t B = a.B;
+    for (int i = threadIdx.x; i < 8 * nr; i += blockDim.x) {
+        const int row = i / nr, col = i - row * nr;
+        E[row][col] = (row < kIn ? a.H + (int64_t)row * B : a.D + (int64_t)(4 * kH) * B)[r0 + col];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    constexpr int kPer = kChunk / kWave;
+    for (int f = w; f < kH; f += nw) {
+        // dW1[f][:], db1[f]
+        const float *d1 = a.D + (int64_t)f * B + r0;
+        float dv[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) dv[q] = lane + kWave * q < nr ? d1[lane + kWave * q] : 0.f;
+        float s[kIn + 1];
+#pragma unroll
+        for (int k = 0; k <= kIn; ++k) s[k] = 0.f;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int b = lane + kWave * q;
+            if (b < nr) {
+#pragma unroll
+                for (int k = 0; k < kIn; ++k) s[k] = fmaf(dv[q], E[k][b], s[k]);
+            }
+            s[kIn] += dv[q];
+        }
+#pragma unroll
+        for (int k = 0; k <= kIn; ++k) s[k] = wave_sum(s[k]);
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < kIn; ++k) part[OFF_W1 + f * kIn + k] = s[k];
+            part[OFF_B1 + f] = s[kIn];
+        }
+        // dW5[f] = sum_b delta_5 h_4[f]
+        const float *h4 = a.H + (int64_t)(kIn + 3 * kH + f) * B + r0;
+        float t = 0.f;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int b = lane + kWave * q;
+            if (b < nr) t = fmaf(E[kIn][b], h4[b], t);
+        }
+        t = wave_sum(t);
+        if (lane == 0) part[OFF_W5 + f] = t;
+    }
+    if (w == 0) {
+        float s5 = 0.f, l = 0.f;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int b = lane + kWave * q;
+            if (b < nr) {
+                s5 += E[kIn][b];
+                const float r = a.R[r0 + b];
+                l = fmaf(r, r, l);
+            }
+        }
+        s5 = wave_sum(s5);
+        l = wave_sum(l);
+        if (lane == 0) {
+            part[OFF_B5] = s5;
+            part[NPARAMS] = l;
+        }
+    }
+}
+
+// BF16 mode: dW (ma x nb, row stride ldw) = sum over the chunk's rows b of
+// A[:, b] B[:, b]^T for feature-major A (ma <= 128 rows) and B (nb <= 128
+// rows), and optionally db = sum_b A[:, b].  Per 32-row step every thread
+// loads eight consecutive batch entries of one feature row of A and of B:
+// exactly the MFMA operand fragment of one lane of one 16-row tile, so it is
+// split into BF16 hi/lo once and stored in LDS in fragment order (rows past
+// ma or nb as zeros; double-buffered, one barrier per step; the next step's
+// global loads are in flight during the MFMAs).  Wave w computes the 4 x 2
+// output tiles rows 64 (w / 4) .., columns 32 (w % 4) .., skipping tiles
+// outside ma x nb.
+__device__ void wgrad_gemm_bf16(const float *Ar, int ma, const float *Br, int nb, int64_t B, int r0, int r1,
+                                float *dW, int ldw, float *db, bf16x8 *S) {
+    const int t = threadIdx.x, f = t >> 2, p = t & 3;
+    const bool va = f < ma, vb = f < nb;
+    const float *arow = Ar + (int64_t)(va ? f : 0) * B + 8 * p;
+    const float *brow = Br + (int64_t)(vb ? f : 0) * B + 8 * p;
+    // fragment slot of this thread's data: tile f / 16, lane 16 p + f % 16
+    const int slot = (f >> 4) * kWave + 16 * p + (f & 15);
+    constexpr int kOp = 8 * kWave;   // one operand half (hi or lo) of 8 tiles
+    constexpr int kBuf = 4 * kOp;    // A hi, A lo, B hi, B lo
+    const int lane = t & (kWave - 1), w = t >> 6, g = lane >> 4, n = lane & 15;
+    const int mt0 = 4 * (w >> 2), nt0 = 2 * (w & 3);
+    const int mtn = min(4, (ma + 15) / 16 - mt0), ntn = min(2, (nb + 15) / 16 - nt0);   // tiles of this wave
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const float4 z4 = {0.f, 0.f, 0.f, 0.f};
+    float4 a0 = z4, a1 = z4, b0 = z4, b1 = z4;
+    if (va) {
+        a0 = *reinterpret_cast<const float4 *>(arow + r0);
+        a1 = *reinterpret_cast<const float4 *>(arow + r0 + 4);
+    }
+    if (vb) {
+        b0 = *reinterpret_cast<const float4 *>(brow + r0);
+        b1 = *reinterpret_cast<const float4 *>(brow + r0 + 4);
+    }
+    float dsum = 0.f;
+    for (int k0 = r0, buf = 0; k0 < r1; k0 += 32, buf ^= 1) {
+        bf16x8 *Sb = S + buf * kBuf;
+        {
+            const float av0[4] = {a0.x, a0.y, a0.z, a0.w}, av1[4] = {a1.x, a1.y, a1.z, a1.w};
+            const float bv0[4] = {b0.x, b0.y, b0.z, b0.w}, bv1[4] = {b1.x, b1.y, b1.z, b1.w};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dsum += av0[r];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dsum += av1[r];
+            bf16x8 hi, lo;
+            split8(av0, av1, hi, lo);
+            Sb[slot] = hi;
+            Sb[kOp + slot] = lo;
+            split8(bv0, bv1, hi, lo);
+            Sb[2 * kOp + slot] = hi;
+            Sb[3 * kOp + slot] = lo;
+        }
+        __syncthreads();
+        if (k0 + 32 < r1) {
+            if (va) {
+                a0 = *reinterpret_cast<const float4 *>(arow + k0 + 32);
+                a1 = *reinterpret_cast<const float4 *>(arow + k0 + 36);
+            }
+            if (vb) {
+                b0 = *reinterpret_cast<const float4 *>(brow + k0 + 32);
+                b1 = *reinterpret_cast<const float4 *>(brow + k0 + 36);
+            }
+        }
+        if (mtn > 0 && ntn > 0) {
+            bf16x8 Bh[2], Bl[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                Bh[j] = Sb[2 * kOp + (nt0 + j) * kWave + lane];
+                Bl[j] = Sb[3 * kOp + (nt0 + j) * kWave + lane];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (i >= mtn) break;
+                const bf16x8 Ah = Sb[(mt0 + i) * kWave + lane], Al = Sb[kOp + (mt0 + i) * kWave + lane];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    if (j >= ntn) break;
+                    // three BF16 passes: hi*hi + hi*lo + lo*hi (lo*lo is below FP32 rounding)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bl[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bh[j], acc[i][j], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * (mt0 + i) + 4 * g + r, col = 16 * (nt0 + j) + n;
+                if (i < mtn && j < ntn && row < ma && col < nb) dW[row * ldw + col] = acc[i][j][r];
+            }
+    if (db) {
+        // the four threads of row f are adjacent lanes
+        dsum += __shfl_xor(dsum, 1, kWave);
+        dsum += __shfl_xor(dsum, 2, kWave);
+        if (p == 0 && va) db[f] = dsum;
+    }
+}
+
+// BF16 mode, block y of a chunk: 0..2 the 128x128 layers 2..4 (dW_l, db_l);
+// 3 the input layer (dW1 = delta_1 u^T, db1); 4 the output layer
+// (dW5 = delta_5 h_4^T, db5) and the chunk's loss
+__device__ void wgrad_block_bf16(const TrainArgs &a, int y, int r0, int r1, float *part, bf16x8 *S) {
+    const int64_t B = a.B;
+    if (y < 3) {
+        const int layer = y + 2;
+        wgrad_gemm_bf16(a.D + (int64_t)kH * (layer - 1) * B, kH, a.H + (int64_t)(kIn + kH * (layer - 2)) * B, kH, B,
+                        r0, r1, part + w_off(layer), kH, part + b_off(layer), S);
+    } else if (y == 3) {
+        wgrad_gemm_bf16(a.D, kH, a.H, kIn, B, r0, r1, part + OFF_W1, kIn, part + OFF_B1, S);
+    } else {
+        if (threadIdx.x < kWave) {
+            const int lane = threadIdx.x;
+            float rv[kChunk / kWave], l = 0.f;
+#pragma unroll
+            for (int q = 0; q < kChunk / kWave; ++q) {
+                const int b = r0 + lane + kWave * q;
+                rv[q] = b < r1 ? a.R[b] : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < kChunk / kWave; ++q) l = fmaf(rv[q], rv[q], l);
+            l = wave_sum(l);
+            if (lane == 0) part[NPARAMS] = l;
+        }
+        wgrad_gemm_bf16(a.D + (int64_t)(4 * kH) * B, 1, a.H + (int64_t)(kIn + 3 * kH) * B, kH, B, r0, r1,
+                        part + OFF_W5, kH, part + OFF_B5, S);
+    }
+}
+
+// FP32 mode, one 128x128 layer over one chunk: FP32 MFMA straight from
+// global memory, wave w owns the 16-row tile w of dW_l and of db_l.
+__device__ void wgrad_layer_fp32(const TrainArgs &a, int layer, int r0, int r1, float *part) {
+    const int64_t B = a.B;
+    const float *Dl = a.D + (int64_t)kH * (layer - 1) * B;
+    const float *Hl = a.H + (int64_t)(kIn + kH * (layer - 2)) * B;
+    const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, n = lane & 15;
+    const int mt = threadIdx.x >> 6;
+    f32x4 acc[8];
+#pragma unroll
+    for (int nt = 0; nt < 8; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float dsum = 0.f;
+    for (int k0 = r0; k0 < r1; k0 += 4) {
+        const float A = Dl[(int64_t)(16 * mt + n) * B + k0 + g];
+        dsum += A;
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt)
+            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A, Hl[(int64_t)(16 * nt + n) * B + k0 + g], acc[nt], 0, 0,
+                                                          0);
+    }
+    float *dW = part + w_off(layer);
+#pragma unroll
+    for (int nt = 0; nt < 8; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dW[(16 * mt + 4 * g + r) * kH + 16 * nt + n] = acc[nt][r];
+    dsum = group_sum(dsum);
+    if (g == 0) part[b_off(layer) + 16 * mt + n] = dsum;
+}
+
+// grid (chunks, 5) in BF16 mode (blocks as in wgrad_block_bf16), (chunks, 4)
+// in FP32 mode: blockIdx.y 0..2 = layers 2..4, 3 = edge block
 template <bool BF16>
 __global__ __launch_bounds__(512) void k_train_wgrad(TrainArgs a) {
+    __shared__ __align__(16) bf16x8 S[2 * 4 * 8 * kWave];   // 64 KiB
     const int c = blockIdx.x;
     const int r0 = c * kChunk;
     const int r1 = min(a.B, r0 + kChunk);
-    const int64_t B = a.B;
     float *part = a.part + (int64_t)c * kPart;
-    if (blockIdx.y < 3) {
-        const int layer = blockIdx.y + 2;
-        const float *Dl = a.D + (int64_t)kH * (layer - 1) * B;
-        const float *Hl = a.H + (int64_t)(kIn + kH * (layer - 2)) * B;
-        const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, n = lane & 15;
-        const int mt = threadIdx.x >> 6;   // 8 waves: one 16-row tile of dW each
-        f32x4 acc[8];
-#pragma unroll
-        for (int nt = 0; nt < 8; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        if constexpr (BF16) {
-            for (int k0 = r0; k0 < r1; k0 += 32) {
-                const float *ap = Dl + (int64_t)(16 * mt + n) * B + k0 + 8 * g;
-                const float4 a0 = *reinterpret_cast<const float4 *>(ap);
-                const float4 a1 = *reinterpret_cast<const float4 *>(ap + 4);
-                const float av0[4] = {a0.x, a0.y, a0.z, a0.w}, av1[4] = {a1.x, a1.y, a1.z, a1.w};
-                bf16x8 Ahi, Alo;
-                split8(av0, av1, Ahi, Alo);
-#pragma unroll
-                for (int nt = 0; nt < 8; ++nt) {
-                    const float *bp = Hl + (int64_t)(16 * nt + n) * B + k0 + 8 * g;
-                    const float4 b0 = *reinterpret_cast<const float4 *>(bp);
-                    const float4 b1 = *reinterpret_cast<const float4 *>(bp + 4);
-                    const float bv0[4] = {b0.x, b0.y, b0.z, b0.w}, bv1[4] = {b1.x, b1.y, b1.z, b1.w};
-                    bf16x8 Bhi, Blo;
-                    split8(bv0, bv1, Bhi, Blo);
-                    // three BF16 passes: hi*hi + hi*lo + lo*hi (the lo*lo term is below FP32 rounding)
-                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ahi, Bhi, acc[nt], 0, 0, 0);
-                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ahi, Blo, acc[nt], 0, 0, 0);
-                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Alo, Bhi, acc[nt], 0, 0, 0);
-                }
-            }
-        } else {
-            for (int k0 = r0; k0 < r1; k0 += 4) {
-                const float A = Dl[(int64_t)(16 * mt + n) * B + k0 + g];
-#pragma unroll
-                for (int nt = 0; nt < 8; ++nt)
-                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A, Hl[(int64_t)(16 * nt + n) * B + k0 + g], acc[nt],
-                                                                  0, 0, 0);
-            }
-        }
-        float *dW = part + w_off(layer);
-#pragma unroll
-        for (int nt = 0; nt < 8; ++nt)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) dW[(16 * mt + 4 * g + r) * kH + 16 * nt + n] = acc[nt][r];
+    if constexpr (BF16) {
+        wgrad_block_bf16(a, blockIdx.y, r0, r1, part, S);
+    } else if (blockIdx.y == 3) {
+        static_assert(sizeof(S) >= sizeof(float) * 8 * kChunk, "edge staging fits the operand buffer");
+        wgrad_edge(a, r0, r1 - r0, part, reinterpret_cast<float (*)[kChunk]>(S));
     } else {
-        // FP32 layers, biases and the loss: one dot product over the chunk
-        // per wave (lanes stride over the rows, coalesced), spread over
-        // kSmallBlocks blocks
-        const int lane = threadIdx.x & (kWave - 1);
-        const int wpb = blockDim.x / kWave;
-        const int nw = kSmallBlocks * wpb;
-        const int nsmall = kH * kIn + 4 * kH + kH + 2;
-        for (int j = (blockIdx.y - 3) * wpb + (threadIdx.x >> 6); j < nsmall; j += nw) {
-            const float *x = nullptr, *y = nullptr;
-            int dst;
-            if (j < kH * kIn) {                       // dW1[f][k]
-                const int f = j / kIn, k = j % kIn;
-                x = a.D + (int64_t)f * B;
-                y = a.H + (int64_t)k * B;
-                dst = OFF_W1 + j;
-            } else if (j < kH * kIn + 4 * kH) {       // db_l
-                const int jj = j - kH * kIn, l = jj / kH + 1, f = jj % kH;
-                x = a.D + (int64_t)(kH * (l - 1) + f) * B;
-                dst = b_off(l) + f;
-            } else if (j < kH * kIn + 5 * kH) {       // dW5[f]
-                const int f = j - kH * kIn - 4 * kH;
-                x = a.D + (int64_t)(4 * kH) * B;
-                y = a.H + (int64_t)(kIn + 3 * kH + f) * B;
-                dst = OFF_W5 + f;
-            } else if (j == kH * kIn + 5 * kH) {      // db5
-                x = a.D + (int64_t)(4 * kH) * B;
-                dst = OFF_B5;
-            } else {                                  // loss: sum of squared residuals
-                x = a.R;
-                y = a.R;
-                dst = NPARAMS;
-            }
-            float s = 0.f;
-            if (y)
-                for (int b = r0 + lane; b < r1; b += kWave) s = fmaf(x[b], y[b], s);
-            else
-                for (int b = r0 + lane; b < r1; b += kWave) s += x[b];
-            s = wave_sum(s);
-            if (lane == 0) part[dst] = s;
-        }
+        wgrad_layer_fp32(a, blockIdx.y + 2, r0, r1, part);
     }
 }
 
@@ -208,8 +366,17 @@ __global__ void k_adam(float *__restrict__ p, float *__restrict__ m, float *__re
         loss[0] = s * invB;
     }
     if (i >= NPARAMS) return;
+    // chunk partials summed in chunk order; eight loads in flight at a time
     float g = 0.f;
-    for (int c = 0; c < nchunks; ++c) g += part[(int64_t)c * kPart + i];
+    int c = 0;
+    for (; c + 8 <= nchunks; c += 8) {
+        float v8[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v8[k] = part[(int64_t)(c + k) * kPart + i];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) g += v8[k];
+    }
+    for (; c < nchunks; ++c) g += part[(int64_t)c * kPart + i];
     if (grad_out) grad_out[i] = g;
     const float mi = fmaf(b1, m[i], (1.f - b1) * g);
     const float vi = fmaf(b2, v[i], (1.f - b2) * g * g);
@@ -292,11 +459,10 @@ extern "C" int rb_nn_train_step(float *params, float *adam_m, float *adam_v, int
         k_train_fb<false><<<grid_for(ntiles, wv, cus), wv * kWave, 0, st>>>(a);
     }
     const int nchunks = (batch + kChunk - 1) / kChunk;
-    dim3 g2(nchunks, 3 + kSmallBlocks);
     if (precision == RB_PREC_BF16)
-        k_train_wgrad<true><<<g2, 512, 0, st>>>(a);
+        k_train_wgrad<true><<<dim3(nchunks, 5), 512, 0, st>>>(a);
     else
-        k_train_wgrad<false><<<g2, 512, 0, st>>>(a);
+        k_train_wgrad<false><<<dim3(nchunks, 4), 512, 0, st>>>(a);
     const double c1 = 1.0 / (1.0 - pow((double)beta1, (double)t));
     const double c2 = 1.0 / (1.0 - pow((double)beta2, (double)t));
     k_adam<<<(NPARAMS + 255) / 256, 256, 0, st>>>(params, adam_m, adam_v, a.part, nchunks, lr, beta1, beta2, eps,

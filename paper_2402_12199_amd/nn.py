@@ -85,18 +85,24 @@ class Trainer:
         self.ws = torch.zeros(abi.rb_nn_train_workspace_bytes(batch), dtype=torch.uint8, device=self.dev)
         self.loss = torch.zeros(1, dtype=torch.float32, device=self.dev)
 
-    def step(self, desc, labels, idx, grad_out=None):
+    def step(self, desc, labels, idx, grad_out=None, loss=None):
+        """One Adam step on the batch idx; the batch loss goes to `loss` (a
+        one-element device tensor, default self.loss)."""
         self.t += 1
         abi.rb_nn_train_step(self.params, self.m, self.v, self.t, self.norm, self.precision, idx.numel(), desc,
-                             labels, idx, self.lr, self.beta1, self.beta2, self.eps, self.loss, grad_out, self.ws)
+                             labels, idx, self.lr, self.beta1, self.beta2, self.eps,
+                             self.loss if loss is None else loss, grad_out, self.ws)
 
     def epoch(self, desc, labels, g: np.random.Generator):
-        """One pass over the data in a random order; returns the mean loss."""
+        """One pass over the data in a random order; returns the mean loss.
+        Each step writes its loss into its own slot, so the loop launches
+        nothing but the training step."""
         n = labels.numel()
         perm = torch.tensor(g.permutation(n).astype(np.int32), device=self.dev)
         nb = n // self.batch
-        total = torch.zeros(1, dtype=torch.float64, device=self.dev)
+        losses = torch.zeros(max(nb, 1), dtype=torch.float32, device=self.dev)
         for b in range(nb):
-            self.step(desc, labels, perm[b * self.batch:(b + 1) * self.batch])
-            total += self.loss
-        return float(total.item()) / max(nb, 1)
+            self.step(desc, labels, perm[b * self.batch:(b + 1) * self.batch], loss=losses[b:b + 1])
+        if nb:
+            self.loss.copy_(losses[nb - 1:nb])
+        return float(losses[:nb].double().sum().item()) / max(nb, 1)

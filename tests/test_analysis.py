@@ -61,3 +61,23 @@ def test_msd_and_rdf_distance():
     g1 = np.ones(50)
     assert analysis.rdf_distance(r, g1, g1) == 0.0
     assert abs(analysis.rdf_distance(r, g1, 2 * g1) - 1.0) < 1e-12
+
+
+def test_msr_closed_forms():
+    g = np.random.default_rng(5)
+    n = 20000
+    q0 = g.normal(size=(n, 4))
+    q0 /= np.linalg.norm(q0, axis=1, keepdims=True)
+    assert abs(analysis.msr(q0, q0)) < 1e-14
+    assert abs(analysis.msr(q0, -q0)) < 1e-14            # q and -q are the same orientation
+    # a turn by theta about any body axis: distance sin^2(theta / 2)
+    theta = 0.7
+    axis = g.normal(size=(n, 3))
+    axis /= np.linalg.norm(axis, axis=1, keepdims=True)
+    r = Rotation.from_quat(q0[:, [1, 2, 3, 0]]) * Rotation.from_rotvec(theta * axis)
+    q1 = r.as_quat()[:, [3, 0, 1, 2]]
+    assert abs(analysis.msr(q0, q1) - np.sin(theta / 2) ** 2) < 1e-12
+    # independent uniform orientations: <q0, q>^2 averages 1/4 on S^3, so 3/4
+    q2 = g.normal(size=(n, 4))
+    q2 /= np.linalg.norm(q2, axis=1, keepdims=True)
+    assert abs(analysis.msr(q0, q2) - 0.75) < 0.01

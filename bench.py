@@ -66,7 +66,7 @@ def make_system(cfg, st, torch):
     from paper_2402_12199_amd.md import RigidSystem
     b = cfg.body
     return RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"], cfg.box,
-                       cfg.r_list, cfg.skin, hphc=cfg.hphc)
+                       cfg.r_list, cfg.skin, hphc=cfg.hphc, margin=cfg.bead_margin)
 
 
 GRAPH_STEPS = 10   # MD steps recorded per HIP graph

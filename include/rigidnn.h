@@ -61,7 +61,12 @@ extern "C" {
 #define RB_FLAG_NTESTS 8     /* flags[8..9] as one int64: running count of bead-
                                 bead distance tests performed after culling    */
 #define RB_FLAG_NSCREEN 10   /* pairs kept by rb_bead_screen (when its count_out
-                                is &flags[NSCREEN])                             */
+                                is &flags[NSCREEN]), or in the screened list of
+                                rb_bead_pair_forces_screened                    */
+#define RB_FLAG_RESCREEN 11  /* 1: the screened list must be rebuilt before use;
+                                set by every pair-list build and by the
+                                integrator's margin test                        */
+#define RB_FLAG_NRESCREENS 12 /* number of screened-list builds done           */
 #define RB_NFLAGS 16
 
 #define RB_PREC_BF16 0       /* 128x128 layers on BF16 MFMA, FP32 accumulate     */
@@ -178,6 +183,31 @@ int rb_bead_pair_forces(const rb_ctx *ctx, int32_t n, const double *x, const dou
                         const int32_t *pair_j, const int32_t *idx, const int32_t *count_dev,
                         int32_t max_count, int64_t *acc, int32_t *flags, void *stream);
 
+/* Two-level form of rb_bead_pair_forces for dynamics over the whole list
+ * (pairs 0 .. *count_dev, capped at max_count): the same sums, the same
+ * accumulator outputs and the same flags[NEVAL] count (every listed pair),
+ * but a launch visits only the listed pairs of a screened list unless
+ * flags[RESCREEN] is set.  A launch with flags[RESCREEN] set evaluates the
+ * whole list and rebuilds the screened list: screen_list (capacity
+ * max_count) receives the pairs whose bead boxes come within rc + margin
+ * (separating-axis test, as in rb_bead_screen with rc widened by margin),
+ * flags[NSCREEN] their number; x, q are copied to x_sref (3 x n) and q_sref
+ * (4 x n); flags[RESCREEN] is cleared and flags[NRESCREENS] incremented.
+ * A listed pair outside the screened list has no bead pair within rc while
+ * every body's beads have moved by at most margin / 2 since then, which
+ * rb_rigid_step and rb_rigid_step_fused test (given x_sref, q_sref and
+ * half_margin = margin / 2) and report by setting flags[RESCREEN]; every
+ * pair-list build sets it too.  Set flags[RESCREEN] before the first call.
+ * tmp: four int32 of caller memory, zero before the first call (entries 0..2
+ * are left zero, entry 3 holds state between calls).  Forces, torques,
+ * energy and virial equal those of rb_bead_pair_forces on the same list bit
+ * for bit (same per-pair arithmetic, fixed-point sums). */
+int rb_bead_pair_forces_screened(const rb_ctx *ctx, int32_t n, const double *x, const double *q,
+                                 const int32_t *type, const double *box, const int32_t *pair_i,
+                                 const int32_t *pair_j, const int32_t *count_dev, int32_t max_count,
+                                 double margin, int32_t *screen_list, double *x_sref, double *q_sref,
+                                 int32_t *tmp, int64_t *acc, int32_t *flags, void *stream);
+
 /* ---- accumulator -----------------------------------------------------------
  * rb_accum_zero clears acc with a fill kernel (graph safe); needed once,
  * before the first evaluation.
@@ -228,15 +258,21 @@ int rb_nn_pair_forces(const float *params, const float *norm, int precision, int
  * frame, 3 x n FP32 each), drift, free rotation split as
  * R3(dt/2) R2(dt/2) R1(dt) R2(dt/2) R3(dt/2) (NO_SQUISH, Miller et al.,
  * J. Chem. Phys. 116, 8649, 2002), renormalise q; if x_ref != NULL and a
- * body moved more than half_skin from x_ref, sets flags[REBUILD].  phase 2:
+ * body moved more than half_skin from x_ref, sets flags[REBUILD]; if x_sref
+ * != NULL (then q_sref too) and some bead of a body may have moved more than
+ * half_margin since the state (x_sref, q_sref), i.e.
+ * |x - x_sref| + 2 rho |vec(q_sref^* q)| > half_margin with rho the type's
+ * largest bead radius, sets flags[RESCREEN] (the screened list of
+ * rb_bead_pair_forces_screened).  phase 2:
  * second half kick; writes kinetic[2] = (translational, rotational) kinetic
  * energy (FP64 deterministic reduction).  ws: rb_rigid_workspace_bytes(n),
  * zero-filled before its first use. */
 size_t rb_rigid_workspace_bytes(int32_t n);
 int rb_rigid_step(const rb_ctx *ctx, int phase, int32_t n, double dt, double *x, double *P,
                   double *q, double *L, const int32_t *type, const float *force,
-                  const float *torque, const double *x_ref, double half_skin, double *kinetic,
-                  int32_t *flags, void *ws, size_t ws_bytes, void *stream);
+                  const float *torque, const double *x_ref, double half_skin, const double *x_sref,
+                  const double *q_sref, double half_margin, double *kinetic, int32_t *flags, void *ws,
+                  size_t ws_bytes, void *stream);
 
 /* Step boundary in one launch, for loops that keep the forces in the
  * accumulator: rb_accum_finalize (acc -> force, torque FP32, energy_virial
@@ -250,6 +286,7 @@ int rb_rigid_step(const rb_ctx *ctx, int phase, int32_t n, double dt, double *x,
 int rb_rigid_step_fused(const rb_ctx *ctx, int32_t n, double dt, double *x, double *P, double *q,
                         double *L, const int32_t *type, int64_t *acc, float *force, float *torque,
                         double *energy_virial, const double *x_ref, double half_skin,
+                        const double *x_sref, const double *q_sref, double half_margin,
                         double *kinetic, int32_t *flags, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- training step (energy loss, Adam) ------------------------------------

@@ -32,6 +32,7 @@ SIGNATURES = {
     "rb_pair_descriptors": (C.c_int, [I32, P, P, DP, P, P, I32, F32, F32, P, P, P, P, P]),
     "rb_bead_pair_eval": (C.c_int, [P, I64, P, I32, I32, P, P, P]),
     "rb_bead_pair_forces": (C.c_int, [P, I32, P, P, P, DP, P, P, P, P, I32, P, P, P]),
+    "rb_bead_pair_forces_screened": (C.c_int, [P, I32, P, P, P, DP, P, P, P, I32, F64, P, P, P, P, P, P, P]),
     "rb_bead_screen": (C.c_int, [P, I32, P, P, P, DP, P, P, P, P, I32, P, P, P, P, P]),
     "rb_accum_zero": (C.c_int, [I32, P, P]),
     "rb_accum_finalize": (C.c_int, [I32, P, P, P, P, P]),
@@ -40,8 +41,9 @@ SIGNATURES = {
     "rb_nn_pair_forces": (C.c_int, [P, FP, C.c_int, I32, P, P, P, P, I32, P, P, I32, F32, F32, P, P,
                                     P]),
     "rb_rigid_workspace_bytes": (SZ, [I32]),
-    "rb_rigid_step": (C.c_int, [P, C.c_int, I32, F64, P, P, P, P, P, P, P, P, F64, P, P, P, SZ, P]),
-    "rb_rigid_step_fused": (C.c_int, [P, I32, F64, P, P, P, P, P, P, P, P, P, P, F64, P, P, P, SZ, P]),
+    "rb_rigid_step": (C.c_int, [P, C.c_int, I32, F64, P, P, P, P, P, P, P, P, F64, P, P, F64, P, P, P, SZ, P]),
+    "rb_rigid_step_fused": (C.c_int, [P, I32, F64, P, P, P, P, P, P, P, P, P, P, F64, P, P, F64, P, P, P, SZ,
+                                      P]),
     "rb_nn_train_workspace_bytes": (SZ, [I32]),
     "rb_nn_train_step": (C.c_int, [P, P, P, I32, FP, C.c_int, I32, P, I64, P, P, F32, F32, F32, F32,
                                    P, P, P, SZ, P]),

@@ -18,7 +18,7 @@ from ._lib import check, lib
 
 RB_FLAG_REBUILD, RB_FLAG_NPAIRS, RB_FLAG_OVERFLOW, RB_FLAG_NREBUILDS = 0, 1, 2, 3
 RB_FLAG_NBEAD, RB_FLAG_NNN, RB_FLAG_NONFINITE, RB_FLAG_NEVAL, RB_FLAG_NTESTS, RB_NFLAGS = 4, 5, 6, 7, 8, 16
-RB_FLAG_NSCREEN = 10
+RB_FLAG_NSCREEN, RB_FLAG_RESCREEN, RB_FLAG_NRESCREENS = 10, 11, 12
 RB_PREC_BF16, RB_PREC_FP32 = 0, 1
 RB_BUILD_ALWAYS, RB_BUILD_IF_FLAGGED = 0, 1
 RB_MLP_NPARAMS = 50689
@@ -154,6 +154,27 @@ def rb_bead_pair_forces(ctx: Ctx, x, q, types, box, pair_i, pair_j, idx, count_d
           "rb_bead_pair_forces")
 
 
+def rb_bead_pair_forces_screened(ctx: Ctx, x, q, types, box, pair_i, pair_j, count_dev, max_count, margin,
+                                 screen_list, x_sref, q_sref, tmp, acc, flags):
+    n = x.shape[1]
+    _, bp = _box(box)
+    if screen_list.numel() < max_count:
+        raise ValueError("screen_list must hold max_count entries")
+    check(lib().rb_bead_pair_forces_screened(ctx.handle, n, _ptr(x, torch.float64, (3, n), "x"),
+                                             _ptr(q, torch.float64, (4, n), "q"),
+                                             _ptr(types, torch.int32, (n,), "type"), bp,
+                                             _ptr(pair_i, torch.int32, name="pair_i"),
+                                             _ptr(pair_j, torch.int32, name="pair_j"),
+                                             _ptr(count_dev, torch.int32, name="count_dev"), int(max_count),
+                                             float(margin), _ptr(screen_list, torch.int32, name="screen_list"),
+                                             _ptr(x_sref, torch.float64, (3, n), "x_sref"),
+                                             _ptr(q_sref, torch.float64, (4, n), "q_sref"),
+                                             _ptr(tmp, torch.int32, (4,), "tmp"),
+                                             _ptr(acc, torch.int64, (acc_len(n),), "acc"),
+                                             _ptr(flags, torch.int32, (RB_NFLAGS,), "flags"), _stream()),
+          "rb_bead_pair_forces_screened")
+
+
 def rb_bead_screen(ctx: Ctx, x, q, types, box, pair_i, pair_j, idx, count_dev, max_count, idx_out, count_out, tmp,
                    flags=None):
     n = x.shape[1]
@@ -226,7 +247,7 @@ def rb_rigid_workspace_bytes(n: int) -> int:
 
 
 def rb_rigid_step(ctx: Ctx, phase: int, dt: float, x, P, q, L, types, force, torque, x_ref=None,
-                  half_skin=0.0, kinetic=None, flags=None, ws=None):
+                  half_skin=0.0, kinetic=None, flags=None, ws=None, x_sref=None, q_sref=None, half_margin=0.0):
     n = P.shape[1]
     check(lib().rb_rigid_step(ctx.handle, phase, n, float(dt),
                               _ptr(x, torch.float64, (3, n), "x", optional=True),
@@ -235,6 +256,8 @@ def rb_rigid_step(ctx: Ctx, phase: int, dt: float, x, P, q, L, types, force, tor
                               _ptr(force, torch.float32, (3, n), "force"),
                               _ptr(torque, torch.float32, (3, n), "torque"),
                               _ptr(x_ref, torch.float64, (3, n), "x_ref", optional=True), float(half_skin),
+                              _ptr(x_sref, torch.float64, (3, n), "x_sref", optional=True),
+                              _ptr(q_sref, torch.float64, (4, n), "q_sref", optional=True), float(half_margin),
                               _ptr(kinetic, torch.float64, (2,), "kinetic", optional=True),
                               _ptr(flags, torch.int32, (RB_NFLAGS,), "flags", optional=True),
                               _ptr(ws, torch.uint8, name="ws", optional=True), 0 if ws is None else ws.numel(),
@@ -243,7 +266,7 @@ def rb_rigid_step(ctx: Ctx, phase: int, dt: float, x, P, q, L, types, force, tor
 
 
 def rb_rigid_step_fused(ctx: Ctx, dt: float, x, P, q, L, types, acc, force, torque, energy_virial, x_ref,
-                        half_skin, kinetic, flags, ws):
+                        half_skin, kinetic, flags, ws, x_sref=None, q_sref=None, half_margin=0.0):
     n = P.shape[1]
     check(lib().rb_rigid_step_fused(ctx.handle, n, float(dt), _ptr(x, torch.float64, (3, n), "x"),
                                     _ptr(P, torch.float64, (3, n), "P"), _ptr(q, torch.float64, (4, n), "q"),
@@ -253,6 +276,8 @@ def rb_rigid_step_fused(ctx: Ctx, dt: float, x, P, q, L, types, acc, force, torq
                                     _ptr(torque, torch.float32, (3, n), "torque"),
                                     _ptr(energy_virial, torch.float64, (10,), "energy_virial", optional=True),
                                     _ptr(x_ref, torch.float64, (3, n), "x_ref", optional=True), float(half_skin),
+                                    _ptr(x_sref, torch.float64, (3, n), "x_sref", optional=True),
+                                    _ptr(q_sref, torch.float64, (4, n), "q_sref", optional=True), float(half_margin),
                                     _ptr(kinetic, torch.float64, (2,), "kinetic", optional=True),
                                     _ptr(flags, torch.int32, (RB_NFLAGS,), "flags"),
                                     _ptr(ws, torch.uint8, name="ws"), ws.numel(), _stream()),

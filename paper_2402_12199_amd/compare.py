@@ -26,7 +26,7 @@ def run_dynamics(cfg, st, path: str, nn: NNModel | None = None, chunks: int = 8,
     force or energy turns non-finite."""
     b = cfg.body
     sysm = RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"], cfg.box,
-                       cfg.r_list, cfg.skin, hphc=cfg.hphc)
+                       cfg.r_list, cfg.skin, hphc=cfg.hphc, margin=cfg.bead_margin if path == "bead" else None)
     if nn is not None:
         sysm.set_nn(nn)
     sysm.init_forces(path)

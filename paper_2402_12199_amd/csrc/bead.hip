@@ -174,6 +174,81 @@ __device__ inline int stage_i(const Templates &T, const float4 *tb, int ti, int 
     return count;
 }
 
+// Both stagings in one pass (independent work in flight together): body
+// j's beads as stage_j keeps them, body i's as stage_i does.  Outputs the
+// counts of both.
+__device__ inline void stage_pair(const Templates &T, const float4 *tb, int ti, int tj, const double d[3],
+                                  const double R[9], float cut2, WaveLds &L, int lane, int &ni_out, int &nj_out) {
+    const int nj = T.n[tj], ni = T.n[ti];
+    const float4 *bj = tb + T.off[tj];
+    const float4 *bi = tb + T.off[ti];
+    const float hxi = T.hx[ti], hyi = T.hy[ti], hzi = T.hz[ti];
+    const float hxj = T.hx[tj], hyj = T.hy[tj], hzj = T.hz[tj];
+    const float dx = (float)d[0], dy = (float)d[1], dz = (float)d[2];
+    float Rf[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) Rf[a] = (float)R[a];
+    int cj = 0, ci = 0;
+    const int nm = nj > ni ? nj : ni;
+    for (int l0 = 0; l0 < nm; l0 += kWave) {
+        const int l = l0 + lane;
+        bool kj = false, ki = false;
+        float4 hi = make_float4(0.f, 0.f, 0.f, 0.f), lo = hi, b = hi;
+        if (l < nj) {
+            const float4 c = bj[l];
+            const double bx = c.x, by = c.y, bz = c.z;
+            const double x = d[0] + R[0] * bx + R[1] * by + R[2] * bz;
+            const double y = d[1] + R[3] * bx + R[4] * by + R[5] * bz;
+            const double z = d[2] + R[6] * bx + R[7] * by + R[8] * bz;
+            hi = make_float4((float)x, (float)y, (float)z, 0.f);
+            lo = make_float4((float)(x - hi.x), (float)(y - hi.y), (float)(z - hi.z), 0.f);
+            kj = box_dist2(hi.x, hi.y, hi.z, hxi, hyi, hzi) < cut2;
+        }
+        if (l < ni) {
+            b = bi[l];
+            const float ux = b.x - dx, uy = b.y - dy, uz = b.z - dz;
+            const float px = Rf[0] * ux + Rf[3] * uy + Rf[6] * uz;
+            const float py = Rf[1] * ux + Rf[4] * uy + Rf[7] * uz;
+            const float pz = Rf[2] * ux + Rf[5] * uy + Rf[8] * uz;
+            ki = box_dist2(px, py, pz, hxj, hyj, hzj) < cut2;
+        }
+        cj = wave_compact(kj, hi, lo, L.j, L.jlo, cj, lane);
+        ci = wave_compact(ki, b, b, L.i, nullptr, ci, lane);
+    }
+    ni_out = ci;
+    nj_out = cj;
+}
+
+// Sums over the wave of eight per-lane values with ten lane exchanges
+// instead of 8 x 6: three halving exchanges leave value v summed over eight
+// lanes in lanes 8v .. 8v + 7, three more finish it there; every lane
+// receives the eight sums.  Fixed order: the result does not depend on
+// timing.
+__device__ inline void wave_sum8(const float v[8], int lane, float out[8]) {
+    const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0, b3 = (lane & 8) != 0;
+    float a[4], c[2];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const float send = b5 ? v[r] : v[4 + r], keep = b5 ? v[4 + r] : v[r];
+        a[r] = keep + __shfl_xor(send, 32, kWave);
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const float send = b4 ? a[r] : a[2 + r], keep = b4 ? a[2 + r] : a[r];
+        c[r] = keep + __shfl_xor(send, 16, kWave);
+    }
+    float e;
+    {
+        const float send = b3 ? c[0] : c[1], keep = b3 ? c[1] : c[0];
+        e = keep + __shfl_xor(send, 8, kWave);
+    }
+    e += __shfl_xor(e, 4, kWave);
+    e += __shfl_xor(e, 2, kWave);
+    e += __shfl_xor(e, 1, kWave);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) out[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(e), 8 * k));
+}
+
 // The ni x nj surviving tests.  Returns, reduced over the wave (valid in
 // every lane): r[0] = E, r[1..3] = F_i, r[4..6] = tau_i (body i frame, about
 // its centre), r[7] = min squared distance over the tests performed (only
@@ -236,9 +311,8 @@ __device__ inline void pair_sum(const LJ &lj, int ni, int nj, const WaveLds &L, 
         t[1] += b.z * fx - b.x * fz;
         t[2] += b.x * fy - b.y * fx;
     }
-    r[0] = wave_sum(e);
-    r[1] = wave_sum(F[0]); r[2] = wave_sum(F[1]); r[3] = wave_sum(F[2]);
-    r[4] = wave_sum(t[0]); r[5] = wave_sum(t[1]); r[6] = wave_sum(t[2]);
+    const float v8[8] = {e, F[0], F[1], F[2], t[0], t[1], t[2], 0.f};
+    wave_sum8(v8, lane, r);
     r[7] = TRACK_MIN ? wave_min(r2min) : 0.f;
 }
 
@@ -302,8 +376,7 @@ struct Box {
 // screen and the force kernel so that both take the same decisions.
 __device__ inline void pair_frame(int32_t n, const double *__restrict__ x, const double *__restrict__ q,
                                   const Box &box, int i, int j, double dl[3], double d[3], double qr[4],
-                                  double qa[4]) {
-    double Ri[9];
+                                  double qa[4], double Ri[9]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) dl[a] = min_image(x[a * n + j] - x[a * n + i], box.L[a], box.inv[a]);
     const double aw = q[i], ax = q[n + i], ay = q[2 * n + i], az = q[3 * n + i];
@@ -323,8 +396,8 @@ __device__ inline void pair_frame(int32_t n, const double *__restrict__ x, const
 
 __device__ inline void pair_geometry(int32_t n, const double *__restrict__ x, const double *__restrict__ q,
                                      const Box &box, int i, int j, double dl[3], double d[3], double R[9]) {
-    double qr[4], qa[4];
-    pair_frame(n, x, q, box, i, j, dl, d, qr, qa);
+    double qr[4], qa[4], Ri[9];
+    pair_frame(n, x, q, box, i, j, dl, d, qr, qa, Ri);
     quat_to_rot<double>(qr[0], qr[1], qr[2], qr[3], R);
 }
 
@@ -381,8 +454,6 @@ __global__ __launch_bounds__(256) void k_bead_screen(Templates T, float rcm, int
     }
 }
 
-// Per-body form for dynamics.  Geometry from FP64 state; the pair's outputs
-// are rotated to the lab frame and added to the fixed-point accumulator.
 // Per-body form for dynamics.  A block takes the pairs b, b + G, b + 2G, ...
 // (G blocks) in rounds of 64, one lane of the first wave per pair: indices,
 // FP64 geometry and the separating-axis test run for the round at once (one
@@ -390,6 +461,21 @@ __global__ __launch_bounds__(256) void k_bead_screen(Templates T, float rcm, int
 // geometry, to an LDS queue from which the block's waves take them one at a
 // time, each evaluated by a whole wave.  The pair's outputs are rotated to
 // the lab frame and added to the fixed-point accumulator.
+//
+// Two-level form (SCREENED): the list of body pairs (built with a skin on
+// the centre distance) is screened once more with the separating-axis test
+// widened by a margin m; a listed pair outside that screened list has no
+// bead pair within rc for as long as no body has moved by more than m / 2
+// (a bead moves by at most |dx| + 2 rho sin(theta / 2) for a body
+// displacement dx and rotation theta, rho the body's largest bead radius),
+// which the integrator watches, raising the rescreen flag.  A launch with
+// the flag set runs the form above over the whole list and rebuilds the
+// screened list (pairs that pass the plain test first, those that pass only
+// the widened one from the end of the array) and the reference state; a
+// launch with the flag clear runs the same rounds over the screened list
+// only, whose pairs that passed the plain test are dealt out evenly over
+// the blocks.  This pays where the list spans several rounds per block
+// (large systems); with one round per block the two forms cost the same.
 constexpr int kRound = 64;
 
 struct PairQueue {
@@ -398,14 +484,89 @@ struct PairQueue {
     int n, head;
 };
 
+struct ScreenArgs {
+    int32_t *list;          // screened pair indices (capacity max_count)
+    double *x_ref, *q_ref;  // state at the last screening (3 x n, 4 x n)
+    int32_t *tmp;           // [0], [1]: append counters, [2]: ticket (zero between launches), [3]: pairs of the list that passed the plain test
+    float rcm_wide;         // rc + cull margin + screening margin
+};
+
+// One body pair, whole wave: staging, culling, the bead sum and the
+// lab-frame outputs, one component per lane: lanes 0..11 add F and tau of
+// both bodies to the accumulator, lanes 12..21 the energy and the 9 virial
+// components to the wave's sums.
 template <int POT>
-__global__ __launch_bounds__(kMdWaves * kWave) void k_bead_md(Templates T, LJ lj, int32_t n, const double *__restrict__ x,
+__device__ inline void md_pair(const Templates &T, const LJ &lj, const float4 *tb, WaveLds &L, int lane, float cut2,
+                               int32_t n, int i, int j, int ti, int tj, const double dl[3], const double d[3],
+                               const double R[9], const double Ri[9], int64_t *__restrict__ acc, long long *wacc,
+                               long long &ntests, bool &bad) {
+    int ni, nj;
+    stage_pair(T, tb, ti, tj, d, R, cut2, L, lane, ni, nj);
+    if (ni == 0 || nj == 0) return;   // no bead pair within rc: zero contribution
+    wave_lds_sync();
+    float r[8];
+    pair_sum<false, POT>(lj, ni, nj, L, lane, r);
+    ntests += (long long)ni * nj;
+    wave_lds_sync();
+    if (lane < 22) {
+        // per-lane choices by selects, not by indexing (a lane-dependent
+        // index into a register array would put the array in scratch memory)
+        auto sel3 = [](int k, double x0, double x1, double x2) { return k == 0 ? x0 : (k == 1 ? x1 : x2); };
+        const double F[3] = {r[1], r[2], r[3]}, tI[3] = {r[4], r[5], r[6]};
+        const double tJ[3] = {d[1] * F[2] - d[2] * F[1] - tI[0], d[2] * F[0] - d[0] * F[2] - tI[1],
+                              d[0] * F[1] - d[1] * F[0] - tI[2]};
+        if (lane < 12) {
+            const int which = lane / 3, a = lane % 3;   // 0: F on i, 1: F on j, 2: tau_i, 3: tau_j
+            const double R0 = sel3(a, Ri[0], Ri[3], Ri[6]), R1 = sel3(a, Ri[1], Ri[4], Ri[7]),
+                         R2 = sel3(a, Ri[2], Ri[5], Ri[8]);
+            const double V0 = which < 2 ? F[0] : (which == 2 ? tI[0] : tJ[0]);
+            const double V1 = which < 2 ? F[1] : (which == 2 ? tI[1] : tJ[1]);
+            const double V2 = which < 2 ? F[2] : (which == 2 ? tI[2] : tJ[2]);
+            double v = R0 * V0 + R1 * V1 + R2 * V2;
+            if (which == 1) v = -v;
+            const int body = (which == 0 || which == 2) ? i : j;
+            acc_add(acc + (int64_t)((which < 2 ? 0 : 3) + a) * n + body, v);
+        } else {
+            const int e = lane - 12;
+            double v = r[0];
+            if (e > 0) {
+                const int a = (e - 1) / 3, b = (e - 1) % 3;
+                const double Flb = sel3(b, Ri[0], Ri[3], Ri[6]) * F[0] + sel3(b, Ri[1], Ri[4], Ri[7]) * F[1] +
+                                   sel3(b, Ri[2], Ri[5], Ri[8]) * F[2];
+                v = -sel3(a, dl[0], dl[1], dl[2]) * Flb;
+            }
+            wacc[e] += to_fixed(v);
+        }
+    }
+    if (lane == 0 && (!isfinite(r[0]) || !isfinite(r[1]) || !isfinite(r[2]) || !isfinite(r[3]))) bad = true;
+}
+
+// Wave-aggregated append of the lanes with `keep` at list[base + rank]
+// (forward) or list[end - 1 - (base + rank)] (backward), base from counter.
+__device__ inline void list_append(bool keep, int value, int32_t *counter, int32_t *list, int end, bool backward,
+                                   int lane) {
+    const unsigned long long m = __ballot(keep);
+    if (!m) return;
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, leader, kWave);
+    if (keep) {
+        const int at = base + __popcll(m & ((1ull << lane) - 1ull));
+        list[backward ? end - 1 - at : at] = value;
+    }
+}
+
+// at least four waves per SIMD (two 8-wave blocks per CU, which the LDS
+// allows for templates of up to ~150 beads)
+template <int POT, bool SCREENED>
+__global__ __launch_bounds__(kMdWaves * kWave) __attribute__((amdgpu_waves_per_eu(4))) void k_bead_md(Templates T, LJ lj, int32_t n, const double *__restrict__ x,
                                                  const double *__restrict__ q, const int32_t *__restrict__ type,
                                                  Box box, const int32_t *__restrict__ pi,
                                                  const int32_t *__restrict__ pj, const int32_t *__restrict__ idx,
                                                  const int32_t *__restrict__ count_dev, int32_t max_count,
                                                  int64_t *__restrict__ acc, int32_t *__restrict__ flags,
-                                                 int stride) {
+                                                 int stride, ScreenArgs S) {
     extern __shared__ float4 bead_lds[];
     __shared__ long long wacc[kMdWaves][10];   // per-wave energy/virial sums (fixed point)
     __shared__ PairQueue Q;
@@ -421,100 +582,93 @@ __global__ __launch_bounds__(kMdWaves * kWave) void k_bead_md(Templates T, LJ lj
     long long ntests = 0;
     bool bad = false;
     const int G = gridDim.x;
-    for (int p0 = blockIdx.x; p0 < count; p0 += G * kRound) {
-        if (w == 0) {
-            const int p = p0 + lane * G;
-            bool hit = false;
-            int i = 0, j = 0, ti = 0, tj = 0;
-            double dl[3], d[3], qr[4], qa[4];
-            if (p < count) {
-                const int pid = idx ? idx[p] : p;
-                i = pi[pid];
-                j = pj[pid];
-                ti = type[i];
-                tj = type[j];
-                pair_frame(n, x, q, box, i, j, dl, d, qr, qa);
-                double R[9];
-                quat_to_rot<double>(qr[0], qr[1], qr[2], qr[3], R);
-                hit = may_interact(T, ti, tj, d, R, rcm);
+    const bool full = !SCREENED || flags[RB_FLAG_RESCREEN] != 0;
+    // pairs of this launch: the whole list, or the screened pairs (those that
+    // passed the plain test at the screening first, spread evenly over the
+    // blocks by the interleaved assignment)
+    int npass = count, core = 0;
+    if (SCREENED && !full) {
+        npass = flags[RB_FLAG_NSCREEN];
+        if (npass > count) npass = count;
+        core = min(S.tmp[3], npass);
+    }
+    {
+        if (SCREENED && full) {
+            for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < n; b += G * blockDim.x) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) S.x_ref[a * n + b] = x[a * n + b];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) S.q_ref[a * n + b] = q[a * n + b];
             }
-            const unsigned long long m = __ballot(hit);
-            if (hit) {
-                const int at = __popcll(m & ((1ull << lane) - 1ull));
-                Q.i[at] = i;
-                Q.j[at] = j;
-                Q.ti[at] = ti;
-                Q.tj[at] = tj;
+        }
+        for (int p0 = blockIdx.x; p0 < npass; p0 += G * kRound) {
+            if (w == 0) {
+                const int p = p0 + lane * G;
+                bool hit = false, wide = false;
+                int pid = 0, i = 0, j = 0, ti = 0, tj = 0;
+                double dl[3], d[3], qr[4], qa[4];
+                if (p < npass) {
+                    if (SCREENED && !full)
+                        pid = p < core ? S.list[p] : S.list[max_count - 1 - (p - core)];
+                    else
+                        pid = idx ? idx[p] : p;
+                    i = pi[pid];
+                    j = pj[pid];
+                    ti = type[i];
+                    tj = type[j];
+                    double R[9], Ri[9];
+                    pair_frame(n, x, q, box, i, j, dl, d, qr, qa, Ri);
+                    quat_to_rot<double>(qr[0], qr[1], qr[2], qr[3], R);
+                    hit = may_interact(T, ti, tj, d, R, rcm);
+                    if (SCREENED && full) wide = hit || may_interact(T, ti, tj, d, R, S.rcm_wide);
+                }
+                if (SCREENED && full) {
+                    list_append(hit, pid, S.tmp, S.list, max_count, false, lane);
+                    list_append(wide && !hit, pid, S.tmp + 1, S.list, max_count, true, lane);
+                }
+                const unsigned long long m = __ballot(hit);
+                if (hit) {
+                    const int at = __popcll(m & ((1ull << lane) - 1ull));
+                    Q.i[at] = i;
+                    Q.j[at] = j;
+                    Q.ti[at] = ti;
+                    Q.tj[at] = tj;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        Q.dl[a][at] = dl[a];
+                        Q.d[a][at] = d[a];
+                    }
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        Q.qr[a][at] = qr[a];
+                        Q.qa[a][at] = qa[a];
+                    }
+                }
+                if (lane == 0) {
+                    Q.n = __popcll(m);
+                    Q.head = 0;
+                }
+            }
+            __syncthreads();
+            const int nq = Q.n;
+            for (;;) {
+                int k = 0;
+                if (lane == 0) k = atomicAdd(&Q.head, 1);
+                k = __builtin_amdgcn_readfirstlane(k);
+                if (k >= nq) break;
+                double dl[3], d[3], R[9], Ri[9];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    Q.dl[a][at] = dl[a];
-                    Q.d[a][at] = d[a];
+                    dl[a] = Q.dl[a][k];
+                    d[a] = Q.d[a][k];
                 }
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    Q.qr[a][at] = qr[a];
-                    Q.qa[a][at] = qa[a];
-                }
-            }
-            if (lane == 0) {
-                Q.n = __popcll(m);
-                Q.head = 0;
-            }
-        }
-        __syncthreads();
-        const int nq = Q.n;
-        for (;;) {
-            int k = 0;
-            if (lane == 0) k = atomicAdd(&Q.head, 1);
-            k = __builtin_amdgcn_readfirstlane(k);
-            if (k >= nq) break;
-            const int i = Q.i[k], j = Q.j[k], ti = Q.ti[k], tj = Q.tj[k];
-            double dl[3], d[3], R[9];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                dl[a] = Q.dl[a][k];
-                d[a] = Q.d[a][k];
-            }
-            quat_to_rot<double>(Q.qr[0][k], Q.qr[1][k], Q.qr[2][k], Q.qr[3][k], R);
-            const int nj = stage_j(T, tb, ti, tj, d, R, cut2, L, lane);
-            if (nj == 0) continue;   // no bead of j within rc of i's box: zero contribution
-            const int ni = stage_i(T, tb, ti, tj, d, R, cut2, L, lane);
-            if (ni == 0) continue;
-            wave_lds_sync();
-            float r[8];
-            pair_sum<false, POT>(lj, ni, nj, L, lane, r);
-            ntests += (long long)ni * nj;
-            wave_lds_sync();
-            // lab-frame outputs, one component per lane: lanes 0..11 add
-            // F and tau of both bodies to the accumulator, lanes 12..21 the
-            // energy and the 9 virial components to the wave's sums
-            if (lane < 22) {
-                double Ri[9];
+                quat_to_rot<double>(Q.qr[0][k], Q.qr[1][k], Q.qr[2][k], Q.qr[3][k], R);
                 quat_to_rot<double>(Q.qa[0][k], Q.qa[1][k], Q.qa[2][k], Q.qa[3][k], Ri);
-                const double F[3] = {r[1], r[2], r[3]}, tI[3] = {r[4], r[5], r[6]};
-                const double tJ[3] = {d[1] * F[2] - d[2] * F[1] - tI[0], d[2] * F[0] - d[0] * F[2] - tI[1],
-                                      d[0] * F[1] - d[1] * F[0] - tI[2]};
-                if (lane < 12) {
-                    const int which = lane / 3, a = lane % 3;   // 0: F on i, 1: F on j, 2: tau_i, 3: tau_j
-                    const double *V = which < 2 ? F : (which == 2 ? tI : tJ);
-                    double v = Ri[3 * a] * V[0] + Ri[3 * a + 1] * V[1] + Ri[3 * a + 2] * V[2];
-                    if (which == 1) v = -v;
-                    const int body = (which == 0 || which == 2) ? i : j;
-                    acc_add(acc + (int64_t)((which < 2 ? 0 : 3) + a) * n + body, v);
-                } else {
-                    const int e = lane - 12;
-                    double v = r[0];
-                    if (e > 0) {
-                        const int a = (e - 1) / 3, b = (e - 1) % 3;
-                        const double Flb = Ri[3 * b] * F[0] + Ri[3 * b + 1] * F[1] + Ri[3 * b + 2] * F[2];
-                        v = -dl[a] * Flb;
-                    }
-                    wacc[w][e] += to_fixed(v);
-                }
+                md_pair<POT>(T, lj, tb, L, lane, cut2, n, Q.i[k], Q.j[k], Q.ti[k], Q.tj[k], dl, d, R, Ri, acc, wacc[w],
+                             ntests, bad);
             }
-            if (lane == 0 && (!isfinite(r[0]) || !isfinite(r[1]) || !isfinite(r[2]) || !isfinite(r[3]))) bad = true;
+            __syncthreads();   // the queue is refilled by the next round
         }
-        __syncthreads();   // the queue is refilled by the next round
     }
     long long part[11];
 #pragma unroll
@@ -522,6 +676,28 @@ __global__ __launch_bounds__(kMdWaves * kWave) void k_bead_md(Templates T, LJ lj
     part[10] = ntests;
     block_flush_globals<kMdWaves>(part, acc + 6 * (int64_t)n, flags);
     if (lane == 0 && bad) atomicOr(flags + RB_FLAG_NONFINITE, 1);
+    if (SCREENED && full) {
+        // the last block to finish publishes the screened list
+        __shared__ bool last;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            last = atomicAdd(S.tmp + 2, 1) == G - 1;
+        }
+        __syncthreads();
+        if (last && threadIdx.x == 0) {
+            __threadfence();
+            const int c = __hip_atomic_load(S.tmp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int m = __hip_atomic_load(S.tmp + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            flags[RB_FLAG_NSCREEN] = c + m;
+            S.tmp[3] = c;
+            S.tmp[0] = 0;
+            S.tmp[1] = 0;
+            S.tmp[2] = 0;
+            flags[RB_FLAG_RESCREEN] = 0;
+            flags[RB_FLAG_NRESCREENS] += 1;
+        }
+    }
 }
 
 // Dynamic LDS of a block (kBeadWaves waves, three arrays each) and the
@@ -591,6 +767,35 @@ extern "C" int rb_bead_pair_eval(const rb_ctx *ctx, int64_t n_pairs, const float
     return RB_OK;
 }
 
+// Launch of the per-body form: a persistent grid of 8-wave blocks, as many
+// as a CU holds (LDS sized for the templates in use); each block flushes its
+// global sums once.
+template <bool SCREENED>
+static int launch_bead_md(const rb_ctx *ctx, int32_t n, const double *x, const double *q, const int32_t *type,
+                          const double *box, const int32_t *pair_i, const int32_t *pair_j, const int32_t *idx,
+                          const int32_t *count_dev, int32_t max_count, int64_t *acc, int32_t *flags,
+                          const ScreenArgs &S, void *stream, const char *who) {
+    Box b;
+    for (int a = 0; a < 3; ++a) {
+        RB_REQUIRE(box[a] > 0, "%s: box must be > 0", who);
+        b.L[a] = box[a];
+        b.inv[a] = 1.0 / box[a];
+    }
+    int stride;
+    const size_t lds = bead_lds_bytes(ctx, kMdWaves, stride);
+    RB_REQUIRE(lds + sizeof(PairQueue) + 1024 <= device_max_lds(),
+               "%s: templates need %zu bytes of LDS per block (device max %zu)", who, lds, device_max_lds());
+    const bool hphc = ctx->dev.lj.kind == kPotHPHC;
+    auto kern = hphc ? k_bead_md<kPotHPHC, SCREENED> : k_bead_md<kPotLJ, SCREENED>;
+    static int c_lds[2] = {-1, -1}, c_nb[2] = {0, 0};
+    const int nb = blocks_per_cu(kern, kMdWaves * kWave, lds, &c_lds[hphc], &c_nb[hphc]);
+    const int grid = grid_for(max_count, kMdWaves, nb * device_cus_bead());
+    kern<<<grid, kMdWaves * kWave, lds, (hipStream_t)stream>>>(ctx->dev.t, ctx->dev.lj, n, x, q, type, b, pair_i,
+                                                              pair_j, idx, count_dev, max_count, acc, flags, stride,
+                                                              S);
+    return RB_OK;
+}
+
 extern "C" int rb_bead_pair_forces(const rb_ctx *ctx, int32_t n, const double *x, const double *q,
                                    const int32_t *type, const double *box, const int32_t *pair_i,
                                    const int32_t *pair_j, const int32_t *idx, const int32_t *count_dev,
@@ -599,27 +804,34 @@ extern "C" int rb_bead_pair_forces(const rb_ctx *ctx, int32_t n, const double *x
                "rb_bead_pair_forces: null argument");
     RB_REQUIRE(n >= 0 && max_count >= 0, "rb_bead_pair_forces: negative size");
     if (max_count == 0 || n == 0) return RB_OK;
-    Box b;
-    for (int a = 0; a < 3; ++a) {
-        RB_REQUIRE(box[a] > 0, "rb_bead_pair_forces: box must be > 0");
-        b.L[a] = box[a];
-        b.inv[a] = 1.0 / box[a];
-    }
-    // persistent grid: as many 4-wave blocks as a CU holds (LDS sized for
-    // the templates in use); waves stride over the pairs, and each block
-    // flushes its global sums once
-    int stride;
-    const size_t lds = bead_lds_bytes(ctx, kMdWaves, stride);
-    RB_REQUIRE(lds + sizeof(PairQueue) + 1024 <= device_max_lds(),
-               "rb_bead_pair_forces: templates need %zu bytes of LDS per block (device max %zu)", lds,
-               device_max_lds());
-    static int c_lds = -1, c_nb = 0;
-    const int nb = blocks_per_cu(k_bead_md<kPotLJ>, kMdWaves * kWave, lds, &c_lds, &c_nb);
-    const int grid = grid_for(max_count, kMdWaves, nb * device_cus_bead());
-    auto kern = ctx->dev.lj.kind == kPotHPHC ? k_bead_md<kPotHPHC> : k_bead_md<kPotLJ>;
-    kern<<<grid, kMdWaves * kWave, lds, (hipStream_t)stream>>>(ctx->dev.t, ctx->dev.lj, n, x, q, type, b, pair_i, pair_j,
-                                                      idx, count_dev, max_count, acc, flags, stride);
+    const int rc = launch_bead_md<false>(ctx, n, x, q, type, box, pair_i, pair_j, idx, count_dev, max_count, acc,
+                                         flags, ScreenArgs{}, stream, "rb_bead_pair_forces");
+    if (rc != RB_OK) return rc;
     RB_LAUNCH_CHECK("rb_bead_pair_forces");
+    return RB_OK;
+}
+
+extern "C" int rb_bead_pair_forces_screened(const rb_ctx *ctx, int32_t n, const double *x, const double *q,
+                                            const int32_t *type, const double *box, const int32_t *pair_i,
+                                            const int32_t *pair_j, const int32_t *count_dev, int32_t max_count,
+                                            double margin, int32_t *screen_list, double *x_sref, double *q_sref,
+                                            int32_t *tmp, int64_t *acc, int32_t *flags, void *stream) {
+    RB_REQUIRE(ctx && x && q && type && box && pair_i && pair_j && count_dev && screen_list && x_sref && q_sref &&
+                   tmp && acc && flags,
+               "rb_bead_pair_forces_screened: null argument");
+    RB_REQUIRE(n >= 0 && max_count >= 0, "rb_bead_pair_forces_screened: negative size");
+    RB_REQUIRE(margin >= 0 && margin < 1e6, "rb_bead_pair_forces_screened: margin must be in [0, 1e6)");
+    if (max_count == 0 || n == 0) return RB_OK;
+    ScreenArgs S;
+    S.list = screen_list;
+    S.x_ref = x_sref;
+    S.q_ref = q_sref;
+    S.tmp = tmp;
+    S.rcm_wide = (float)(sqrt((double)ctx->dev.lj.rc2) + kCullMargin + margin);
+    const int rc = launch_bead_md<true>(ctx, n, x, q, type, box, pair_i, pair_j, nullptr, count_dev, max_count, acc,
+                                        flags, S, stream, "rb_bead_pair_forces_screened");
+    if (rc != RB_OK) return rc;
+    RB_LAUNCH_CHECK("rb_bead_pair_forces_screened");
     return RB_OK;
 }
 

@@ -60,6 +60,54 @@ __device__ inline void kick(double dt, double q[4], double P[3], double L[3], co
     }
 }
 
+// Displacement watch of the lists built from an earlier state.  Pair list:
+// raise the rebuild flag when a centre has moved by more than half the skin
+// since the build (x_ref).  Screened list of the two-level bead sum: raise
+// the rescreen flag when some bead of a body may have moved by more than
+// half the screening margin since the screening (x_sref, q_sref): a bead at
+// radius rho moves by at most |dx| + 2 rho |vec(q_ref^* q)| = |dx| +
+// 2 rho sin(theta / 2) under a displacement dx and a rotation by theta.
+struct Watch {
+    const double *x_ref;
+    double half_skin2;
+    const double *x_sref, *q_sref;
+    double half_margin;
+    double rho[kMaxTypes];   // largest bead radius per type, rounded up
+};
+
+__device__ inline void watch(const Watch &wt, int32_t n, int i, int t, const double xn[3], const double qn[4],
+                             bool &rebuild, bool &rescreen) {
+    if (wt.x_ref) {
+        double d2 = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double dd = xn[a] - wt.x_ref[a * n + i];
+            d2 += dd * dd;
+        }
+        rebuild = d2 > wt.half_skin2;
+    }
+    if (wt.x_sref) {
+        double d2 = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double dd = xn[a] - wt.x_sref[a * n + i];
+            d2 += dd * dd;
+        }
+        const double sw = wt.q_sref[i], sx = wt.q_sref[n + i], sy = wt.q_sref[2 * n + i], sz = wt.q_sref[3 * n + i];
+        // vector part of q_ref^* q = sw v - w s - s x v
+        const double vx = sw * qn[1] - qn[0] * sx - (sy * qn[3] - sz * qn[2]);
+        const double vy = sw * qn[2] - qn[0] * sy - (sz * qn[1] - sx * qn[3]);
+        const double vz = sw * qn[3] - qn[0] * sz - (sx * qn[2] - sy * qn[1]);
+        rescreen = sqrt(d2) + 2.0 * wt.rho[t] * sqrt(vx * vx + vy * vy + vz * vz) > wt.half_margin;
+    }
+}
+
+__device__ inline void raise_flags(bool rebuild, bool rescreen, int32_t *flags) {
+    const bool lead = (threadIdx.x & (kWave - 1)) == 0;
+    if (__any(rebuild) && lead) atomicOr(flags + RB_FLAG_REBUILD, 1);
+    if (__any(rescreen) && lead) atomicOr(flags + RB_FLAG_RESCREEN, 1);
+}
+
 // Grid-wide sums of (a, b) into out[0..1]: wave and block sums, one partial
 // pair per block, and the last block to finish adds the partials in a fixed
 // tree order (lane k takes blocks k, k + 64, ...), so the result depends only
@@ -111,11 +159,10 @@ __global__ __launch_bounds__(kIntThreads) void k_phase1(int32_t n, double dt, do
                                                         const double *__restrict__ mass,
                                                         const double *__restrict__ inertia,
                                                         const float *__restrict__ force,
-                                                        const float *__restrict__ torque,
-                                                        const double *__restrict__ x_ref, double half_skin2,
+                                                        const float *__restrict__ torque, Watch wt,
                                                         int32_t *__restrict__ flags) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    bool moved = false;
+    bool rebuild = false, rescreen = false;
     if (i < n) {
         const int t = type[i];
         double qi[4] = {q[i], q[n + i], q[2 * n + i], q[3 * n + i]};
@@ -123,17 +170,12 @@ __global__ __launch_bounds__(kIntThreads) void k_phase1(int32_t n, double dt, do
         double Li[3] = {L[i], L[n + i], L[2 * n + i]};
         kick(dt, qi, Pi, Li, force, torque, n, i);
         const double im = 1.0 / mass[t];
-        double d2 = 0;
+        double xn[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const double xn = x[a * n + i] + dt * Pi[a] * im;
-            x[a * n + i] = xn;
-            if (x_ref) {
-                const double dd = xn - x_ref[a * n + i];
-                d2 += dd * dd;
-            }
+            xn[a] = x[a * n + i] + dt * Pi[a] * im;
+            x[a * n + i] = xn[a];
         }
-        moved = x_ref && d2 > half_skin2;
         const double I[3] = {inertia[3 * t], inertia[3 * t + 1], inertia[3 * t + 2]};
         free_sub(2, 0.5 * dt, I[2], qi, Li);
         free_sub(1, 0.5 * dt, I[1], qi, Li);
@@ -142,14 +184,18 @@ __global__ __launch_bounds__(kIntThreads) void k_phase1(int32_t n, double dt, do
         free_sub(2, 0.5 * dt, I[2], qi, Li);
         const double inv = 1.0 / sqrt(qi[0] * qi[0] + qi[1] * qi[1] + qi[2] * qi[2] + qi[3] * qi[3]);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) q[a * n + i] = qi[a] * inv;
+        for (int a = 0; a < 4; ++a) {
+            qi[a] *= inv;
+            q[a * n + i] = qi[a];
+        }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             P[a * n + i] = Pi[a];
             L[a * n + i] = Li[a];
         }
+        watch(wt, n, i, t, xn, qi, rebuild, rescreen);
     }
-    if (__any(moved) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(flags + RB_FLAG_REBUILD, 1);
+    raise_flags(rebuild, rescreen, flags);
 }
 
 // Second half kick; per-block FP64 kinetic partial sums, summed in block
@@ -195,14 +241,13 @@ __global__ __launch_bounds__(kIntThreads) void k_fused(int32_t n, double dt, dou
                                                        const double *__restrict__ mass,
                                                        const double *__restrict__ inertia, int64_t *__restrict__ acc,
                                                        float *__restrict__ force, float *__restrict__ torque,
-                                                       double *__restrict__ ev, const double *__restrict__ x_ref,
-                                                       double half_skin2, int32_t *__restrict__ flags,
+                                                       double *__restrict__ ev, Watch wt, int32_t *__restrict__ flags,
                                                        double *__restrict__ partial, unsigned *__restrict__ ticket,
                                                        double *__restrict__ kinetic) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const double s = 1.0 / RB_ACC_SCALE;
     double kt = 0, kr = 0;
-    bool moved = false;
+    bool rebuild = false, rescreen = false;
     if (i < n) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -226,17 +271,12 @@ __global__ __launch_bounds__(kIntThreads) void k_fused(int32_t n, double dt, dou
         // next step: half kick, drift, free rotation
         kick(dt, qi, Pi, Li, force, torque, n, i);
         const double im = 1.0 / m;
-        double d2 = 0;
+        double xn[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const double xn = x[a * n + i] + dt * Pi[a] * im;
-            x[a * n + i] = xn;
-            if (x_ref) {
-                const double dd = xn - x_ref[a * n + i];
-                d2 += dd * dd;
-            }
+            xn[a] = x[a * n + i] + dt * Pi[a] * im;
+            x[a * n + i] = xn[a];
         }
-        moved = x_ref && d2 > half_skin2;
         free_sub(2, 0.5 * dt, I[2], qi, Li);
         free_sub(1, 0.5 * dt, I[1], qi, Li);
         free_sub(0, dt, I[0], qi, Li);
@@ -244,14 +284,18 @@ __global__ __launch_bounds__(kIntThreads) void k_fused(int32_t n, double dt, dou
         free_sub(2, 0.5 * dt, I[2], qi, Li);
         const double inv = 1.0 / sqrt(qi[0] * qi[0] + qi[1] * qi[1] + qi[2] * qi[2] + qi[3] * qi[3]);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) q[a * n + i] = qi[a] * inv;
+        for (int a = 0; a < 4; ++a) {
+            qi[a] *= inv;
+            q[a * n + i] = qi[a];
+        }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             P[a * n + i] = Pi[a];
             L[a * n + i] = Li[a];
         }
+        watch(wt, n, i, t, xn, qi, rebuild, rescreen);
     }
-    if (__any(moved) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(flags + RB_FLAG_REBUILD, 1);
+    raise_flags(rebuild, rescreen, flags);
     if (blockIdx.x == gridDim.x - 1) finalize_globals(acc + 6 * (int64_t)n, ev);
     if (kinetic) grid_sum2(kt, kr, partial, ticket, kinetic);
 }
@@ -267,10 +311,23 @@ extern "C" size_t rb_rigid_workspace_bytes(int32_t n) {
     return ((sizeof(double) * 2 * (nblocks(n) + 1) + 255) & ~(size_t)255) + 256;
 }
 
+static Watch make_watch(const rb_ctx *ctx, const double *x_ref, double half_skin, const double *x_sref,
+                        const double *q_sref, double half_margin) {
+    Watch wt;
+    wt.x_ref = x_ref;
+    wt.half_skin2 = half_skin * half_skin;
+    wt.x_sref = x_sref;
+    wt.q_sref = q_sref;
+    wt.half_margin = half_margin;
+    for (int t = 0; t < kMaxTypes; ++t) wt.rho[t] = t < ctx->n_types ? (double)ctx->rmax[t] * (1.0 + 1e-6) : 0.0;
+    return wt;
+}
+
 extern "C" int rb_rigid_step(const rb_ctx *ctx, int phase, int32_t n, double dt, double *x, double *P,
                              double *q, double *L, const int32_t *type, const float *force,
-                             const float *torque, const double *x_ref, double half_skin, double *kinetic,
-                             int32_t *flags, void *ws, size_t ws_bytes, void *stream) {
+                             const float *torque, const double *x_ref, double half_skin, const double *x_sref,
+                             const double *q_sref, double half_margin, double *kinetic, int32_t *flags, void *ws,
+                             size_t ws_bytes, void *stream) {
     RB_REQUIRE(ctx && P && q && L && type && force && torque, "rb_rigid_step: null argument");
     RB_REQUIRE(phase == 1 || phase == 2, "rb_rigid_step: phase must be 1 or 2");
     RB_REQUIRE(n > 0, "rb_rigid_step: n must be > 0");
@@ -278,9 +335,11 @@ extern "C" int rb_rigid_step(const rb_ctx *ctx, int phase, int32_t n, double dt,
     const int grid = (int)nblocks(n);
     if (phase == 1) {
         RB_REQUIRE(x, "rb_rigid_step: x is null");
-        RB_REQUIRE(!x_ref || flags, "rb_rigid_step: the skin test needs flags");
+        RB_REQUIRE((!x_ref && !x_sref) || flags, "rb_rigid_step: the displacement tests need flags");
+        RB_REQUIRE(!x_sref || q_sref, "rb_rigid_step: x_sref needs q_sref");
         k_phase1<<<grid, kIntThreads, 0, st>>>(n, dt, x, P, q, L, type, ctx->dev.mass, ctx->dev.inertia, force,
-                                               torque, x_ref, half_skin * half_skin, flags);
+                                               torque, make_watch(ctx, x_ref, half_skin, x_sref, q_sref, half_margin),
+                                               flags);
     } else {
         RB_REQUIRE(kinetic && ws, "rb_rigid_step: phase 2 needs kinetic and ws");
         RB_REQUIRE(ws_bytes >= rb_rigid_workspace_bytes(n), "rb_rigid_step: workspace too small");
@@ -296,19 +355,21 @@ extern "C" int rb_rigid_step(const rb_ctx *ctx, int phase, int32_t n, double dt,
 
 extern "C" int rb_rigid_step_fused(const rb_ctx *ctx, int32_t n, double dt, double *x, double *P, double *q,
                                    double *L, const int32_t *type, int64_t *acc, float *force, float *torque,
-                                   double *energy_virial, const double *x_ref, double half_skin, double *kinetic,
+                                   double *energy_virial, const double *x_ref, double half_skin,
+                                   const double *x_sref, const double *q_sref, double half_margin, double *kinetic,
                                    int32_t *flags, void *ws, size_t ws_bytes, void *stream) {
     RB_REQUIRE(ctx && x && P && q && L && type && acc && force && torque && flags && ws,
                "rb_rigid_step_fused: null argument");
     RB_REQUIRE(n > 0, "rb_rigid_step_fused: n must be > 0");
     RB_REQUIRE(ws_bytes >= rb_rigid_workspace_bytes(n), "rb_rigid_step_fused: workspace too small");
+    RB_REQUIRE(!x_sref || q_sref, "rb_rigid_step_fused: x_sref needs q_sref");
     char *w = static_cast<char *>(ws);
     double *partial = reinterpret_cast<double *>(w);
     unsigned *ticket = reinterpret_cast<unsigned *>(w + rb_rigid_workspace_bytes(n) - 256);
     // one block more than the bodies need: it adds up the global sums
     k_fused<<<(int)nblocks(n) + 1, kIntThreads, 0, (hipStream_t)stream>>>(
-        n, dt, x, P, q, L, type, ctx->dev.mass, ctx->dev.inertia, acc, force, torque, energy_virial, x_ref,
-        half_skin * half_skin, flags, partial, ticket, kinetic);
+        n, dt, x, P, q, L, type, ctx->dev.mass, ctx->dev.inertia, acc, force, torque, energy_virial,
+        make_watch(ctx, x_ref, half_skin, x_sref, q_sref, half_margin), flags, partial, ticket, kinetic);
     RB_LAUNCH_CHECK("rb_rigid_step_fused");
     return RB_OK;
 }

@@ -249,6 +249,7 @@ __global__ void k_finish(int32_t *flags, int mode) {
     if (skip(flags, mode)) return;
     flags[RB_FLAG_REBUILD] = 0;
     flags[RB_FLAG_NREBUILDS] += 1;
+    flags[RB_FLAG_RESCREEN] = 1;   // a screened list drawn from the old list is stale
 }
 
 // ----------------------------------------------------- two-launch pipeline
@@ -431,6 +432,7 @@ __global__ __launch_bounds__(kPairThreads) void k_pl_pairs(int32_t n, const doub
         flags[RB_FLAG_OVERFLOW] = tot > cap ? tot : 0;
         flags[RB_FLAG_REBUILD] = 0;
         flags[RB_FLAG_NREBUILDS] += 1;
+        flags[RB_FLAG_RESCREEN] = 1;   // a screened list drawn from the old list is stale
     }
 }
 

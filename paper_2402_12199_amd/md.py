@@ -1,9 +1,11 @@
 """Dynamics driver: composes the C-ABI entry points into one MD step.
 
 Bead path step (velocity Verlet):
-  rigid_step phase 1 (half kick, drift, free rotation, skin test)
+  rigid_step phase 1 (half kick, drift, free rotation, skin and margin tests)
   pairlist_build (only when the skin test flagged a rebuild)
-  bead_pair_forces over every listed pair (optionally after bead_screen)
+  bead_pair_forces over every listed pair (optionally after bead_screen), or
+  bead_pair_forces_screened (two-level list: the listed pairs whose bead
+  boxes came within rc + margin at the last screening)
   -> accum_finalize (which also clears the accumulator for the next step)
   rigid_step phase 2 (second half kick, kinetic energy)
 Network path step: the same, except that after the pair list
@@ -36,10 +38,15 @@ class NNModel:
 
 class RigidSystem:
     def __init__(self, templates, masses, inertias, types, x, q, P, L, box, r_list, skin,
-                 eps=1.0, sigma=1.0, rc=2.5, max_pairs=None, device="cuda", screen=False, hphc=None):
+                 eps=1.0, sigma=1.0, rc=2.5, max_pairs=None, device="cuda", screen=False, hphc=None,
+                 margin=None):
         """hphc: dict(A, b, c, p) selects the half-power half-cosine bead
         potential instead of Lennard-Jones (r_list must then cover its
-        cutoff b + pi / c)."""
+        cutoff b + pi / c).  margin: bead path over a two-level list whose
+        screened pairs are rebuilt when a body's beads may have moved by
+        margin / 2 (rb_bead_pair_forces_screened)."""
+        if screen and margin is not None:
+            raise ValueError("screen and margin are exclusive")
         self.dev = torch.device(device)
         self.ctx = abi.Ctx(templates, masses, inertias, eps, sigma, rc)
         if hphc is not None:
@@ -86,6 +93,16 @@ class RigidSystem:
         self.screen = screen
         self.idx_screen = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
         self.tmp_screen = torch.zeros(2, dtype=torch.int32, device=self.dev)
+        # two-level list
+        self.margin = None if margin is None else float(margin)
+        self.x_sref = self.q_sref = None
+        if self.margin is not None:
+            self.screen_list = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
+            self.x_sref = torch.zeros_like(self.x)
+            self.q_sref = torch.zeros_like(self.q)
+            self.tmp_two = torch.zeros(4, dtype=torch.int32, device=self.dev)
+            self.flags[abi.RB_FLAG_RESCREEN] = 1
+        self.half_margin = 0.0 if margin is None else 0.5 * float(margin)
 
     # ------------------------------------------------------------ pieces
     def build_pairs(self, always=True):
@@ -100,6 +117,12 @@ class RigidSystem:
 
     def bead_forces(self):
         """Bead sum over the whole list (or over the screened pairs)."""
+        if self.margin is not None:
+            abi.rb_bead_pair_forces_screened(self.ctx, self.x, self.q, self.types, self.box, self.pair_i,
+                                             self.pair_j, self.flags[abi.RB_FLAG_NPAIRS:], self.max_pairs,
+                                             self.margin, self.screen_list, self.x_sref, self.q_sref, self.tmp_two,
+                                             self.acc, self.flags)
+            return
         if not self.screen:
             abi.rb_bead_pair_forces(self.ctx, self.x, self.q, self.types, self.box, self.pair_i, self.pair_j,
                                     None, self.flags[abi.RB_FLAG_NPAIRS:], self.max_pairs, self.acc, self.flags)
@@ -137,7 +160,8 @@ class RigidSystem:
 
     def step(self, dt, path="bead"):
         abi.rb_rigid_step(self.ctx, 1, dt, self.x, self.P, self.q, self.L, self.types, self.force, self.torque,
-                          self.x_ref, self.half_skin, None, self.flags, None)
+                          self.x_ref, self.half_skin, None, self.flags, None, self.x_sref, self.q_sref,
+                          self.half_margin)
         self.build_pairs(always=False)
         self.compute_forces(path)
         abi.rb_rigid_step(self.ctx, 2, dt, None, self.P, self.q, self.L, self.types, self.force, self.torque,
@@ -162,7 +186,8 @@ class RigidSystem:
     def begin_fused(self, dt):
         """Phase 1 of the first step of a fused run (forces must be current)."""
         abi.rb_rigid_step(self.ctx, 1, dt, self.x, self.P, self.q, self.L, self.types, self.force, self.torque,
-                          self.x_ref, self.half_skin, None, self.flags, None)
+                          self.x_ref, self.half_skin, None, self.flags, None, self.x_sref, self.q_sref,
+                          self.half_margin)
 
     def fused_step(self, dt, path="bead", kinetic=False):
         """Pair list, forces into the accumulator, then one launch for the end
@@ -173,7 +198,8 @@ class RigidSystem:
         self._forces_to_acc(path)
         abi.rb_rigid_step_fused(self.ctx, dt, self.x, self.P, self.q, self.L, self.types, self.acc, self.force,
                                 self.torque, self.ev, self.x_ref, self.half_skin,
-                                self.kinetic if kinetic else None, self.flags, self.ws_rig)
+                                self.kinetic if kinetic else None, self.flags, self.ws_rig, self.x_sref, self.q_sref,
+                                self.half_margin)
 
     def end_fused(self, dt, path="bead"):
         """Last step of a fused run: forces, finalize, phase 2."""

@@ -162,7 +162,7 @@ def train_surrogate_md(cfg, st, n_train: int, n_test: int, epochs: int, every: i
     t0 = time.perf_counter()
     b = cfg.body
     sysm = RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"], cfg.box,
-                       cfg.r_list, cfg.skin, hphc=cfg.hphc)
+                       cfg.r_list, cfg.skin, hphc=cfg.hphc, margin=cfg.bead_margin)
     sysm.init_forces("bead")
     desc, s_train = md_pair_samples(sysm, cfg.dt, n_train, every, cfg.d_min, cfg.d_cut)
     tdesc, s_test = md_pair_samples(sysm, cfg.dt, n_test, max(1, every // 2), cfg.d_min, cfg.d_cut)

@@ -38,6 +38,7 @@ class SystemConfig:
     eps: float = LJ_EPS
     sigma: float = LJ_SIGMA
     hphc: dict | None = None     # half-power half-cosine parameters (A, b, c, p) instead of LJ
+    bead_margin: float | None = None   # two-level list margin for the bead path (None: one level)
 
     @property
     def box(self) -> float:
@@ -115,7 +116,7 @@ def config4(n_train: int = 1 << 21, n_test: int = 1 << 16) -> tuple[PairBatchCon
 
 def config5() -> SystemConfig:
     """32768 cylinders, volume fraction 0.15, NVE at kT=1."""
-    return SystemConfig("cyl32768_phi0.15", cyl134(), 32768, 0.15, seed=1005, n_steps=2000)
+    return SystemConfig("cyl32768_phi0.15", cyl134(), 32768, 0.15, seed=1005, n_steps=2000, bead_margin=0.4)
 
 
 # Half-power half-cosine parameters of the paper (section 3), epsilon and sigma units.

@@ -400,3 +400,38 @@ def test_fused_step_loop_matches_plain_steps_bitwise(abi, path):
     for other in (fused, graphed):
         for name in ("x", "q", "P", "L", "force", "torque", "ev", "kinetic"):
             assert torch.equal(getattr(plain, name), getattr(other, name)), name
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("margin", [0.02, 0.4])
+def test_two_level_list_matches_full_list_bitwise(abi, margin):
+    # the bead path over the screened list (rebuilt on the integrator's margin
+    # test and after every pair-list build) reproduces the bead path over the
+    # whole list exactly, through graph replays of fused steps
+    from paper_2402_12199_amd.md import RigidSystem
+    cfg = configs.config2()
+    st = state.initial_state(cfg)
+    b = cfg.body
+    systems = []
+    for m in (None, margin):
+        sysm = RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"],
+                           cfg.box, cfg.r_list, cfg.skin, margin=m)
+        sysm.init_forces("bead")
+        systems.append(sysm)
+    plain, two = systems
+    assert torch.equal(plain.force, two.force) and torch.equal(plain.ev, two.ev)
+    for sysm in systems:
+        sysm.begin_fused(cfg.dt)
+        g = sysm.capture(cfg.dt, "bead", steps=10, fused=True)
+        for _ in range(30):
+            g.replay()
+        sysm.end_fused(cfg.dt, "bead")
+    torch.cuda.synchronize()
+    for name in ("x", "q", "P", "L", "force", "torque", "ev", "kinetic"):
+        assert torch.equal(getattr(plain, name), getattr(two, name)), name
+    fp, f2 = plain.flags_host(), two.flags_host()
+    assert fp[abi.RB_FLAG_NEVAL] == f2[abi.RB_FLAG_NEVAL]
+    assert (fp[abi.RB_FLAG_NTESTS:abi.RB_FLAG_NTESTS + 2] == f2[abi.RB_FLAG_NTESTS:abi.RB_FLAG_NTESTS + 2]).all()
+    assert f2[abi.RB_FLAG_NRESCREENS] >= (10 if margin < 0.1 else 1)
+    assert 0 < f2[abi.RB_FLAG_NSCREEN] <= f2[abi.RB_FLAG_NPAIRS]
+    assert f2[abi.RB_FLAG_RESCREEN] in (0, 1)

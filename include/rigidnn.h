@@ -266,13 +266,24 @@ int rb_nn_pair_forces(const float *params, const float *norm, int precision, int
  * rb_bead_pair_forces_screened).  phase 2:
  * second half kick; writes kinetic[2] = (translational, rotational) kinetic
  * energy (FP64 deterministic reduction).  ws: rb_rigid_workspace_bytes(n),
- * zero-filled before its first use. */
+ * zero-filled before its first use.
+ * Constant temperature (paper section 3, Nose-Hoover): nh != NULL is a
+ * device array of 5 doubles, (xi, eta, s, Q, g kT), with xi = eta = 0,
+ * s = 1 and the thermostat mass Q and g kT (g degrees of freedom, e.g.
+ * 6 n - 3) set by the caller.  Phase 2 then follows the half kick with the
+ * thermostat flow for dt on every momentum, as two halves U(dt/2), each
+ * xi += (h/2)(2K - g kT)/Q, momenta *= exp(-xi h), eta += xi h,
+ * xi += (h/2)(2K' - g kT)/Q (h = dt/2, K' the scaled kinetic energy),
+ * written back to nh with the accumulated momentum factor s, which the next
+ * phase 1 (given the same nh) applies to P and L before its half kick.
+ * kinetic[] holds the energies before the thermostat.  Conserved:
+ * K + U + Q xi^2 / 2 + g kT eta.  nh == NULL: constant energy. */
 size_t rb_rigid_workspace_bytes(int32_t n);
 int rb_rigid_step(const rb_ctx *ctx, int phase, int32_t n, double dt, double *x, double *P,
                   double *q, double *L, const int32_t *type, const float *force,
                   const float *torque, const double *x_ref, double half_skin, const double *x_sref,
-                  const double *q_sref, double half_margin, double *kinetic, int32_t *flags, void *ws,
-                  size_t ws_bytes, void *stream);
+                  const double *q_sref, double half_margin, double *kinetic, double *nh, int32_t *flags,
+                  void *ws, size_t ws_bytes, void *stream);
 
 /* Step boundary in one launch, for loops that keep the forces in the
  * accumulator: rb_accum_finalize (acc -> force, torque FP32, energy_virial

@@ -14,5 +14,6 @@ Modules
           written in those descriptors
   mlp     the energy network: forward pass, input gradient, parameter
           gradient of the training loss, Adam
+  thermostat  Nose-Hoover constant-temperature steps around the integrator
 """
-from . import beads, frames, mlp  # noqa: F401
+from . import beads, frames, mlp, thermostat  # noqa: F401

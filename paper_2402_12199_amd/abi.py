@@ -247,7 +247,8 @@ def rb_rigid_workspace_bytes(n: int) -> int:
 
 
 def rb_rigid_step(ctx: Ctx, phase: int, dt: float, x, P, q, L, types, force, torque, x_ref=None,
-                  half_skin=0.0, kinetic=None, flags=None, ws=None, x_sref=None, q_sref=None, half_margin=0.0):
+                  half_skin=0.0, kinetic=None, flags=None, ws=None, x_sref=None, q_sref=None, half_margin=0.0,
+                  nh=None):
     n = P.shape[1]
     check(lib().rb_rigid_step(ctx.handle, phase, n, float(dt),
                               _ptr(x, torch.float64, (3, n), "x", optional=True),
@@ -259,6 +260,7 @@ def rb_rigid_step(ctx: Ctx, phase: int, dt: float, x, P, q, L, types, force, tor
                               _ptr(x_sref, torch.float64, (3, n), "x_sref", optional=True),
                               _ptr(q_sref, torch.float64, (4, n), "q_sref", optional=True), float(half_margin),
                               _ptr(kinetic, torch.float64, (2,), "kinetic", optional=True),
+                              _ptr(nh, torch.float64, (5,), "nh", optional=True),
                               _ptr(flags, torch.int32, (RB_NFLAGS,), "flags", optional=True),
                               _ptr(ws, torch.uint8, name="ws", optional=True), 0 if ws is None else ws.numel(),
                               _stream()),

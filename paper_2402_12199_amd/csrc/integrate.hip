@@ -10,6 +10,19 @@
 // z = h L_k / (2 I_k), and L turns by -2z about the same axis, which keeps
 // the lab-frame angular momentum fixed.  A kick adds the body-frame torque:
 // L <- L + (dt/2) R(q)^T tau.
+//
+// Constant temperature (the paper's ensemble, section 3: Nose-Hoover): one
+// thermostat variable xi with mass Q acts on every momentum, translational
+// and angular, through the flow dP/dt = -xi P, dL/dt = -xi L,
+// dxi/dt = (2K - g kT) / Q, deta/dt = xi (g degrees of freedom, K the total
+// kinetic energy).  Split as U_T(dt/2) U_T(dt/2) after each velocity-Verlet
+// step (the end-of-step half and the next step's opening half), each half
+// U_T(h): xi += (h/2) G(K); P, L *= exp(-xi h); eta += xi h;
+// xi += (h/2) G(K') with G(K) = (2K - g kT) / Q and K' = exp(-2 xi h) K.
+// Only the total kinetic energy enters, so the last block of the phase-2
+// reduction does the whole update and leaves the momentum scale factor, which
+// the next phase 1 applies before its half kick.  The conserved quantity is
+// K + U + Q xi^2 / 2 + g kT eta.
 
 // Multiply-add fusion only inside one source expression (also for the
 // helpers of the common header, hence before it): the fused step kernel
@@ -112,7 +125,7 @@ __device__ inline void raise_flags(bool rebuild, bool rescreen, int32_t *flags) 
 // pair per block, and the last block to finish adds the partials in a fixed
 // tree order (lane k takes blocks k, k + 64, ...), so the result depends only
 // on the grid size.
-__device__ inline void grid_sum2(double a, double b, double *__restrict__ partial, unsigned *__restrict__ ticket,
+__device__ inline bool grid_sum2(double a, double b, double *__restrict__ partial, unsigned *__restrict__ ticket,
                                  double *__restrict__ out) {
     __shared__ double red[2][kIntThreads / kWave];
     __shared__ bool last;
@@ -149,8 +162,30 @@ __device__ inline void grid_sum2(double a, double b, double *__restrict__ partia
             out[0] = sa;
             out[1] = sb;
             *ticket = 0u;
+            return true;
         }
     }
+    return false;
+}
+
+// Nose-Hoover state (caller-owned device doubles): xi, eta, the momentum
+// scale for the next phase 1, Q, g kT.
+constexpr int kNhXi = 0, kNhEta = 1, kNhScale = 2, kNhQ = 3, kNhGkT = 4;
+
+__device__ inline void nh_update(double *nh, double K, double dt) {
+    double xi = nh[kNhXi], eta = nh[kNhEta], scale = 1.0;
+    const double Q = nh[kNhQ], gkT = nh[kNhGkT], h = 0.5 * dt;
+    for (int half = 0; half < 2; ++half) {
+        xi += 0.5 * h * (2.0 * K - gkT) / Q;
+        const double s = exp(-xi * h);
+        eta += xi * h;
+        K *= s * s;
+        scale *= s;
+        xi += 0.5 * h * (2.0 * K - gkT) / Q;
+    }
+    nh[kNhXi] = xi;
+    nh[kNhEta] = eta;
+    nh[kNhScale] = scale;
 }
 
 __global__ __launch_bounds__(kIntThreads) void k_phase1(int32_t n, double dt, double *__restrict__ x,
@@ -160,7 +195,7 @@ __global__ __launch_bounds__(kIntThreads) void k_phase1(int32_t n, double dt, do
                                                         const double *__restrict__ inertia,
                                                         const float *__restrict__ force,
                                                         const float *__restrict__ torque, Watch wt,
-                                                        int32_t *__restrict__ flags) {
+                                                        int32_t *__restrict__ flags, const double *__restrict__ nh) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     bool rebuild = false, rescreen = false;
     if (i < n) {
@@ -168,6 +203,14 @@ __global__ __launch_bounds__(kIntThreads) void k_phase1(int32_t n, double dt, do
         double qi[4] = {q[i], q[n + i], q[2 * n + i], q[3 * n + i]};
         double Pi[3] = {P[i], P[n + i], P[2 * n + i]};
         double Li[3] = {L[i], L[n + i], L[2 * n + i]};
+        if (nh) {
+            const double s = nh[kNhScale];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                Pi[a] *= s;
+                Li[a] *= s;
+            }
+        }
         kick(dt, qi, Pi, Li, force, torque, n, i);
         const double im = 1.0 / mass[t];
         double xn[3];
@@ -208,7 +251,7 @@ __global__ __launch_bounds__(kIntThreads) void k_phase2(int32_t n, double dt, do
                                                         const float *__restrict__ force,
                                                         const float *__restrict__ torque,
                                                         double *__restrict__ partial, unsigned *__restrict__ ticket,
-                                                        double *__restrict__ kinetic) {
+                                                        double *__restrict__ kinetic, double *__restrict__ nh) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double kt = 0, kr = 0;
     if (i < n) {
@@ -226,7 +269,7 @@ __global__ __launch_bounds__(kIntThreads) void k_phase2(int32_t n, double dt, do
             kr += Li[a] * Li[a] / (2.0 * inertia[3 * t + a]);
         }
     }
-    grid_sum2(kt, kr, partial, ticket, kinetic);
+    if (grid_sum2(kt, kr, partial, ticket, kinetic) && nh) nh_update(nh, kinetic[0] + kinetic[1], dt);
 }
 
 // Fused step boundary: the forces of step k come from the fixed-point
@@ -326,8 +369,8 @@ static Watch make_watch(const rb_ctx *ctx, const double *x_ref, double half_skin
 extern "C" int rb_rigid_step(const rb_ctx *ctx, int phase, int32_t n, double dt, double *x, double *P,
                              double *q, double *L, const int32_t *type, const float *force,
                              const float *torque, const double *x_ref, double half_skin, const double *x_sref,
-                             const double *q_sref, double half_margin, double *kinetic, int32_t *flags, void *ws,
-                             size_t ws_bytes, void *stream) {
+                             const double *q_sref, double half_margin, double *kinetic, double *nh,
+                             int32_t *flags, void *ws, size_t ws_bytes, void *stream) {
     RB_REQUIRE(ctx && P && q && L && type && force && torque, "rb_rigid_step: null argument");
     RB_REQUIRE(phase == 1 || phase == 2, "rb_rigid_step: phase must be 1 or 2");
     RB_REQUIRE(n > 0, "rb_rigid_step: n must be > 0");
@@ -339,7 +382,7 @@ extern "C" int rb_rigid_step(const rb_ctx *ctx, int phase, int32_t n, double dt,
         RB_REQUIRE(!x_sref || q_sref, "rb_rigid_step: x_sref needs q_sref");
         k_phase1<<<grid, kIntThreads, 0, st>>>(n, dt, x, P, q, L, type, ctx->dev.mass, ctx->dev.inertia, force,
                                                torque, make_watch(ctx, x_ref, half_skin, x_sref, q_sref, half_margin),
-                                               flags);
+                                               flags, nh);
     } else {
         RB_REQUIRE(kinetic && ws, "rb_rigid_step: phase 2 needs kinetic and ws");
         RB_REQUIRE(ws_bytes >= rb_rigid_workspace_bytes(n), "rb_rigid_step: workspace too small");
@@ -347,7 +390,7 @@ extern "C" int rb_rigid_step(const rb_ctx *ctx, int phase, int32_t n, double dt,
         double *partial = reinterpret_cast<double *>(w);
         unsigned *ticket = reinterpret_cast<unsigned *>(w + rb_rigid_workspace_bytes(n) - 256);
         k_phase2<<<grid, kIntThreads, 0, st>>>(n, dt, P, q, L, type, ctx->dev.mass, ctx->dev.inertia, force, torque,
-                                               partial, ticket, kinetic);
+                                               partial, ticket, kinetic, nh);
     }
     RB_LAUNCH_CHECK("rb_rigid_step");
     return RB_OK;

@@ -39,12 +39,14 @@ class NNModel:
 class RigidSystem:
     def __init__(self, templates, masses, inertias, types, x, q, P, L, box, r_list, skin,
                  eps=1.0, sigma=1.0, rc=2.5, max_pairs=None, device="cuda", screen=False, hphc=None,
-                 margin=None):
+                 margin=None, nvt=None):
         """hphc: dict(A, b, c, p) selects the half-power half-cosine bead
         potential instead of Lennard-Jones (r_list must then cover its
         cutoff b + pi / c).  margin: bead path over a two-level list whose
         screened pairs are rebuilt when a body's beads may have moved by
-        margin / 2 (rb_bead_pair_forces_screened)."""
+        margin / 2 (rb_bead_pair_forces_screened).  nvt: dict(kT, tau) runs
+        the plain steps at constant temperature (Nose-Hoover, g = 6 n - 3,
+        Q = g kT tau^2)."""
         if screen and margin is not None:
             raise ValueError("screen and margin are exclusive")
         self.dev = torch.device(device)
@@ -103,6 +105,12 @@ class RigidSystem:
             self.tmp_two = torch.zeros(4, dtype=torch.int32, device=self.dev)
             self.flags[abi.RB_FLAG_RESCREEN] = 1
         self.half_margin = 0.0 if margin is None else 0.5 * float(margin)
+        # Nose-Hoover state (xi, eta, s, Q, g kT)
+        self.nh = None
+        if nvt is not None:
+            g = 6.0 * n - 3.0
+            kT, tau = float(nvt["kT"]), float(nvt["tau"])
+            self.nh = torch.tensor([0.0, 0.0, 1.0, g * kT * tau * tau, g * kT], dtype=torch.float64, device=self.dev)
 
     # ------------------------------------------------------------ pieces
     def build_pairs(self, always=True):
@@ -161,11 +169,21 @@ class RigidSystem:
     def step(self, dt, path="bead"):
         abi.rb_rigid_step(self.ctx, 1, dt, self.x, self.P, self.q, self.L, self.types, self.force, self.torque,
                           self.x_ref, self.half_skin, None, self.flags, None, self.x_sref, self.q_sref,
-                          self.half_margin)
+                          self.half_margin, nh=self.nh)
         self.build_pairs(always=False)
         self.compute_forces(path)
         abi.rb_rigid_step(self.ctx, 2, dt, None, self.P, self.q, self.L, self.types, self.force, self.torque,
-                          None, 0.0, self.kinetic, None, self.ws_rig)
+                          None, 0.0, self.kinetic, None, self.ws_rig, nh=self.nh)
+
+    def extended_energy(self) -> float:
+        """After a step: K + U + Q xi^2 / 2 + g kT eta with K the kinetic
+        energy of the thermostat-scaled momenta (conserved by the
+        thermostatted dynamics); K + U without a thermostat."""
+        K = float(self.kinetic.sum().item())
+        if self.nh is None:
+            return self.energy() + K
+        xi, eta, s, Q, gkT = self.nh.cpu().numpy()
+        return self.energy() + s * s * K + 0.5 * Q * xi * xi + gkT * eta
 
     # ------------------------------------------------------------ fused loop
     def _forces_to_acc(self, path):
@@ -185,6 +203,8 @@ class RigidSystem:
 
     def begin_fused(self, dt):
         """Phase 1 of the first step of a fused run (forces must be current)."""
+        if self.nh is not None:
+            raise ValueError("the fused step is constant-energy only; thermostatted runs use step()")
         abi.rb_rigid_step(self.ctx, 1, dt, self.x, self.P, self.q, self.L, self.types, self.force, self.torque,
                           self.x_ref, self.half_skin, None, self.flags, None, self.x_sref, self.q_sref,
                           self.half_margin)
@@ -194,6 +214,8 @@ class RigidSystem:
         of this step and the start of the next (see rb_rigid_step_fused).
         The kinetic energy is reduced only when asked for (end_fused always
         does)."""
+        if self.nh is not None:
+            raise ValueError("the fused step is constant-energy only; thermostatted runs use step()")
         self.build_pairs(always=False)
         self._forces_to_acc(path)
         abi.rb_rigid_step_fused(self.ctx, dt, self.x, self.P, self.q, self.L, self.types, self.acc, self.force,

@@ -435,3 +435,44 @@ def test_two_level_list_matches_full_list_bitwise(abi, margin):
     assert f2[abi.RB_FLAG_NRESCREENS] >= (10 if margin < 0.1 else 1)
     assert 0 < f2[abi.RB_FLAG_NSCREEN] <= f2[abi.RB_FLAG_NPAIRS]
     assert f2[abi.RB_FLAG_RESCREEN] in (0, 1)
+
+
+def test_nvt_matches_oracle_and_conserves_extended_energy(abi):
+    # Nose-Hoover steps (phase kernels with the thermostat state) against the
+    # FP64 oracle of the same scheme, then the conserved quantity over a
+    # longer run, eagerly and as graph replays
+    from oracle import thermostat
+    from paper_2402_12199_amd.md import RigidSystem
+    cfg = configs.config1()
+    st = state.initial_state(cfg)
+    b = cfg.body
+    kT, tau = 1.5, 0.2
+    sysm = RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"], cfg.box,
+                       cfg.r_list, cfg.skin, nvt=dict(kT=kT, tau=tau))
+    sysm.init_forces("bead")
+    g = 6.0 * cfg.n_bodies - 3.0
+    o = {k: np.ascontiguousarray(st[k].copy()) for k in ("x", "P", "q", "L")}
+    nst = 10
+    r = thermostat.nvt(o["x"], o["P"], o["q"], o["L"], st["types"], [b.beads], [b.mass], [b.inertia], cfg.box, nst,
+                       cfg.dt, Q=g * kT * tau * tau, gkT=g * kT)
+    for _ in range(nst):
+        sysm.step(cfg.dt, "bead")
+    sysm.check_capacity()
+    got = sysm.state_host()
+    np.testing.assert_allclose(got["x"], o["x"], rtol=0, atol=1e-7 * cfg.box)
+    np.testing.assert_allclose(got["q"], o["q"], rtol=0, atol=1e-6)
+    xi, eta, s, Q, gkT = sysm.nh.cpu().numpy()
+    assert Q == pytest.approx(g * kT * tau * tau, rel=1e-15) and gkT == pytest.approx(g * kT, rel=1e-15)
+    assert xi == pytest.approx(r["xi"][-1], rel=1e-6) and eta == pytest.approx(r["eta"][-1], rel=1e-6)
+    assert s == pytest.approx(r["scale"][-1], rel=1e-9)
+    assert sysm.extended_energy() == pytest.approx(r["conserved"][-1], rel=1e-5)
+    h0 = sysm.extended_energy()
+    g10 = sysm.capture(cfg.dt, "bead", steps=10, fused=False)
+    for _ in range(15):
+        g10.replay()
+    torch.cuda.synchronize()
+    sysm.check_capacity()
+    assert abs(sysm.extended_energy() - h0) < 1e-3 * sysm.kinetic_host().sum()
+    assert abs(sysm.nh[0].item()) > 0.05          # the thermostat is active
+    with pytest.raises(ValueError):
+        sysm.begin_fused(cfg.dt)

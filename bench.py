@@ -329,7 +329,8 @@ def hphc_part(args, torch, abi, log):
     """The paper's half-power half-cosine bead potential on 4096 cube shells
     (volume fraction 0.16, NVE kT=1): a surrogate trained on the pairs the
     bead dynamics visits, then 2008 steps of the bead path and of the network
-    path from the same start, compared through g(r), P2, MSD and energy."""
+    path from the same start, compared through g(r), P2, MSD, MSR and energy;
+    the same again at constant temperature (Nose-Hoover)."""
     from paper_2402_12199_amd.compare import compare
     from paper_2402_12199_amd.md import NNModel
     from paper_2402_12199_amd.surrogate import train_surrogate_md
@@ -347,6 +348,11 @@ def hphc_part(args, torch, abi, log):
            "surrogate": {k: sur[k] for k in ("sampling", "epochs", "n_train", "n_test", "train_s", "samples_per_s")},
            "held_out": sur["trained"], "held_out_untrained": sur["untrained"]}
     out["dynamics"] = compare(cfg, st, {"nn_md": model}, chunks=8, replays=25, log=log)
+    # the paper's ensemble: Nose-Hoover NVT at the same temperature
+    nvt = dict(kT=cfg.kT, tau=0.5)
+    out["dynamics_nvt"] = compare(cfg, st, {"nn_md": model}, chunks=8, replays=25, log=log, nvt=nvt)
+    out["dynamics_nvt"]["thermostat"] = dict(nvt, scheme="Nose-Hoover, one thermostat on all momenta, "
+                                                       "g = 6 n - 3, Q = g kT tau^2")
     return out
 
 

@@ -21,12 +21,14 @@ GRAPH_STEPS = 10
 
 
 def run_dynamics(cfg, st, path: str, nn: NNModel | None = None, chunks: int = 8, replays: int = 25,
-                 log=None) -> dict:
-    """chunks x (replays x GRAPH_STEPS + 1) steps of NVE; stops early when a
-    force or energy turns non-finite."""
+                 log=None, nvt: dict | None = None) -> dict:
+    """chunks x (replays x GRAPH_STEPS + 1) steps of NVE (or of Nose-Hoover
+    NVT with nvt = dict(kT, tau), through graphs of plain steps); stops early
+    when a force or energy turns non-finite."""
     b = cfg.body
     sysm = RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"], cfg.box,
-                       cfg.r_list, cfg.skin, hphc=cfg.hphc, margin=cfg.bead_margin if path == "bead" else None)
+                       cfg.r_list, cfg.skin, hphc=cfg.hphc, margin=cfg.bead_margin if path == "bead" else None,
+                       nvt=nvt)
     if nn is not None:
         sysm.set_nn(nn)
     sysm.init_forces(path)
@@ -39,16 +41,20 @@ def run_dynamics(cfg, st, path: str, nn: NNModel | None = None, chunks: int = 8,
     eval0 = int(f_prev[abi.RB_FLAG_NEVAL])
     timed_steps, fallback_max, error = 0, 0, None
     for c in range(chunks):
-        sysm.begin_fused(cfg.dt)
+        if nvt is None:
+            sysm.begin_fused(cfg.dt)
         if graph is None:
-            graph = sysm.capture(cfg.dt, path, GRAPH_STEPS, fused=True)
+            graph = sysm.capture(cfg.dt, path, GRAPH_STEPS, fused=nvt is None)
         a = torch.cuda.Event(enable_timing=True)
         e = torch.cuda.Event(enable_timing=True)
         a.record(stream)
         for _ in range(replays):
             graph.replay()
         e.record(stream)
-        sysm.end_fused(cfg.dt, path)
+        if nvt is None:
+            sysm.end_fused(cfg.dt, path)
+        else:
+            sysm.step(cfg.dt, path)
         torch.cuda.synchronize()
         times.append(a.elapsed_time(e))
         timed_steps += replays * GRAPH_STEPS
@@ -60,13 +66,16 @@ def run_dynamics(cfg, st, path: str, nn: NNModel | None = None, chunks: int = 8,
             break
         s = sysm.state_host()
         snaps.append((steps_done, s["x"], s["q"]))
-        energies.append(sysm.energy() + float(sysm.kinetic_host().sum()))
+        energies.append(sysm.extended_energy())
         if log:
             log(f"[{path}] step {steps_done}: E_total {energies[-1]:.3f}")
     f = sysm.flags_host()
     n_eval = (int(f[abi.RB_FLAG_NEVAL]) - eval0) % (1 << 32)
     gpu_s = 1e-3 * float(np.sum(times))
-    return dict(path=path, steps=steps_done, timed_steps=timed_steps, timed_gpu_s=gpu_s,
+    temperature = None
+    if nvt is not None:
+        temperature = 2.0 * float(sysm.kinetic_host().sum()) / (6.0 * sysm.n - 3.0)
+    return dict(path=path, temperature_last=temperature, steps=steps_done, timed_steps=timed_steps, timed_gpu_s=gpu_s,
                 steps_per_s=timed_steps / gpu_s if gpu_s > 0 else None,
                 pair_evals_per_step=n_eval / max(steps_done, 1), energies=energies, x0=x0, q0=q0, snaps=snaps,
                 rebuilds=int(f[abi.RB_FLAG_NREBUILDS]), fallback_max=fallback_max, error=error)
@@ -87,18 +96,18 @@ def observables(cfg, run: dict, rdf_bins: int = 80) -> dict:
                 max_dev_per_body=float(np.abs(e - e[0]).max() / cfg.n_bodies))
 
 
-def compare(cfg, st, models: dict, chunks: int = 8, replays: int = 25, log=None) -> dict:
+def compare(cfg, st, models: dict, chunks: int = 8, replays: int = 25, log=None, nvt: dict | None = None) -> dict:
     """Bead path and one network path per model (name -> NNModel), all from
     the same start; summary for a report."""
     out = {}
-    runs = {"bead": run_dynamics(cfg, st, "bead", None, chunks, replays, log)}
+    runs = {"bead": run_dynamics(cfg, st, "bead", None, chunks, replays, log, nvt)}
     for name, nn in models.items():
-        runs[name] = run_dynamics(cfg, st, "nn", nn, chunks, replays, log)
+        runs[name] = run_dynamics(cfg, st, "nn", nn, chunks, replays, log, nvt)
     obs = {p: observables(cfg, runs[p]) for p in runs}
     for p in runs:
         r, o = runs[p], obs[p]
         out[p] = {k: r[k] for k in ("path", "steps", "timed_steps", "steps_per_s", "pair_evals_per_step", "rebuilds",
-                                    "fallback_max", "error")}
+                                    "fallback_max", "error", "temperature_last")}
         if o:
             out[p].update(p2=o["p2"], msd_last=o["msd"][-1][1], msr_last=o["msr"][-1][1],
                           drift_per_body=o["drift_per_body"],

@@ -179,3 +179,13 @@ def test_hphc_surrogate_dynamics_follow_the_bead_path(abi):
     assert abs(nn["drift_per_body"]) < 5e-3 and abs(bead["drift_per_body"]) < 1e-5
     assert 0.7 < nn["msd_ratio_vs_bead"] < 1.3
     assert nn["rdf_l1_vs_bead"] < 0.2
+    assert 0.5 < nn["msr_ratio_vs_bead"] < 2.0
+    # the same at constant temperature (Nose-Hoover): both paths stay near
+    # the target and the network path still moves like the bead path
+    out = compare(cfg, st, {"nn": model}, chunks=3, replays=10, nvt=dict(kT=cfg.kT, tau=0.5))
+    bead, nn = out["bead"], out["nn"]
+    assert bead["error"] is None and nn["error"] is None and nn["steps"] == bead["steps"] == 303
+    for r in (bead, nn):
+        assert 0.6 * cfg.kT < r["temperature_last"] < 1.4 * cfg.kT
+    assert abs(bead["drift_per_body"]) < 1e-4 and abs(nn["drift_per_body"]) < 5e-3
+    assert 0.7 < nn["msd_ratio_vs_bead"] < 1.3

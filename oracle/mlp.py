@@ -19,6 +19,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+from . import frames
+
 DIMS = (7, 128, 128, 128, 128, 1)
 
 
@@ -156,3 +158,71 @@ def adam_step(params, m, v, t, g, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     mhat = m / (1.0 - beta1 ** t)
     vhat = v / (1.0 - beta2 ** t)
     return params - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def act_grad2(z, kind="silu"):
+    """Second derivative of the activation."""
+    if kind == "identity":
+        return np.zeros_like(z)
+    s = _sigmoid(z)
+    return s * (1.0 - s) * (2.0 + z * (1.0 - 2.0 * s))
+
+
+def fm_loss_and_grad(params, u, y, ft, lam_f, lam_t, norm: Norm | None = None, kind="silu", dims=DIMS):
+    """Energy loss plus force/torque matching, and the exact parameter
+    gradient.
+
+    loss = mean((e' - y')^2) + lam_f mean |F_j - F_j*|^2 + lam_t mean
+    |tau_j - tau_j*|^2, with F_j, tau_j from the network's input gradient
+    (frames.forces_from_grad) and ft = (F_j*, tau_j*) (P, 6) the labels, in
+    physical units.
+    Returns (energy term, force/torque term, gradient).
+
+    The force/torque term depends on the parameters through g = dE/du; its
+    gradient is sum_b v_b . dg_b/dtheta with v_b = dL/dg_b, i.e. the
+    parameter gradient of the directional derivative of E along v_b.  That
+    derivative is carried forward (tangents z_l', a_l' of every layer) and
+    then differentiated in reverse through both the tangent and the primal
+    chains (second derivative of the activation where they meet).
+    """
+    norm = norm or Norm()
+    u = np.asarray(u, np.float64)
+    P = len(u)
+    e_loss, g_e = loss_and_grad(params, u, y, norm, kind, dims)
+    e, acts, zs, layers, norm = _forward(params, u, norm, kind, dims)
+    gn, _ = _backward(np.ones_like(e), acts, zs, layers, kind)
+    g = gn * norm.in_scale * norm.out_scale                     # dE/du, physical
+    fr = frames.forces_from_grad(u, g)
+    F, tau = fr[:, :3], fr[:, 6:9]
+    dF, dT = F - ft[:, :3], tau - ft[:, 3:6]
+    fm_loss = float(lam_f * np.mean((dF * dF).sum(1)) + lam_t * np.mean((dT * dT).sum(1)))
+    wF, wT = 2.0 * lam_f * dF / P, 2.0 * lam_t * dT / P
+    # v = dL/dg through F_j = -g_d, tau_j = -(w g_v - g_w v + v x g_v) / 2
+    wq, vq = u[:, 3:4], u[:, 4:7]
+    v = np.zeros_like(u)
+    v[:, :3] = -wF
+    v[:, 3] = 0.5 * (wT * vq).sum(1)
+    v[:, 4:7] = -0.5 * (wq * wT + np.cross(wT, vq))
+    # v . g = out_scale * (v * in_scale) . g_n: tangent along vt in normalised
+    # input units, then scaled by out_scale
+    vt = v * norm.in_scale
+    adot, zdot = [vt], [None]          # tangents a_l', z_l' (layer 0: the input)
+    for li, (W, _) in enumerate(layers[:-1]):
+        zdot.append(adot[-1] @ W.T)
+        adot.append(act_grad(zs[li], kind) * zdot[-1])
+    grads = [None] * len(layers)
+    W5, _ = layers[-1]
+    grads[-1] = (norm.out_scale * adot[-1].sum(0)[None, :], np.zeros(1))
+    abar = np.broadcast_to(W5, (P, W5.shape[1])) * norm.out_scale   # adjoint of a_4'
+    pbar = np.zeros_like(abar)                                      # adjoint of a_4 (primal)
+    for li in range(len(layers) - 2, -1, -1):
+        W, _ = layers[li]
+        z = zs[li]
+        zdbar = abar * act_grad(z, kind)                            # adjoint of z_l'
+        zbar = abar * zdot[li + 1] * act_grad2(z, kind) + pbar * act_grad(z, kind)
+        dW = zdbar.T @ adot[li] + zbar.T @ acts[li]
+        db = zbar.sum(0)
+        grads[li] = (dW, db)
+        abar = zdbar @ W
+        pbar = zbar @ W
+    return e_loss, fm_loss, g_e + pack(grads)

@@ -3,7 +3,7 @@ configuration to the energy) against closed forms and finite differences."""
 import numpy as np
 import pytest
 
-from oracle import mlp
+from oracle import frames, mlp
 from synth import sampling
 
 
@@ -119,3 +119,52 @@ def test_bf16_rounding_known_values():
         if w is not None:
             assert g == w
     assert abs(got[4] / -3.0e-5 - 1) < 2 ** -8
+
+
+def _fm_case(seed, P=10):
+    rng = np.random.default_rng(seed)
+    p = sampling.xavier_params(seed)
+    u = sampling.pair_batch(rng, P, 4.0, 11.0)
+    y = rng.normal(size=P)
+    ft = rng.normal(size=(P, 6))
+    norm = mlp.Norm(in_shift=rng.normal(size=7) * 0.1, in_scale=rng.uniform(0.2, 0.5, size=7), out_shift=0.2,
+                    out_scale=1.7)
+    return p, u, y, ft, norm, rng
+
+
+def test_force_matching_gradient_central_differences():
+    # the exact (forward-over-reverse) parameter gradient of energy + force
+    # + torque matching against central differences of the loss, on
+    # parameters of every layer
+    p, u, y, ft, norm, rng = _fm_case(11)
+    lam_f, lam_t = 0.7, 1.3
+    _, _, grad = mlp.fm_loss_and_grad(p, u, y, ft, lam_f, lam_t, norm)
+
+    def loss(pp):
+        a, b, _ = mlp.fm_loss_and_grad(pp, u, y, ft, lam_f, lam_t, norm)
+        return a + b
+
+    bounds = np.cumsum([0] + [fo * fi + fo for fi, fo in zip(mlp.DIMS[:-1], mlp.DIMS[1:])])
+    idx = [int(rng.integers(lo, hi)) for lo, hi in zip(bounds[:-1], bounds[1:]) for _ in range(3)]
+    idx += [int(bounds[-1] - 1), 0]
+    h = 1e-5
+    for k in idx:
+        e = np.zeros_like(p)
+        e[k] = h
+        fd = (loss(p + e) - loss(p - e)) / (2 * h)
+        assert abs(grad[k] - fd) <= 1e-5 * max(abs(fd), 1e-3), (k, grad[k], fd)
+
+
+def test_force_matching_reduces_to_energy_loss_and_matches_its_forces():
+    p, u, y, ft, norm, _ = _fm_case(12)
+    e_loss, fm0, g0 = mlp.fm_loss_and_grad(p, u, y, ft, 0.0, 0.0, norm)
+    ref_loss, ref_grad = mlp.loss_and_grad(p, u, y, norm)
+    assert fm0 == 0.0 and e_loss == ref_loss
+    np.testing.assert_array_equal(g0, ref_grad)
+    # labels equal to the network's own forces and torques: zero matching
+    # loss and no gradient beyond the energy term's
+    _, g = mlp.input_grad(p, u, norm)
+    own = frames.forces_from_grad(u, g)
+    _, fm, g1 = mlp.fm_loss_and_grad(p, u, y, np.concatenate([own[:, :3], own[:, 6:9]], 1), 2.0, 3.0, norm)
+    assert fm < 1e-25
+    np.testing.assert_allclose(g1, ref_grad, rtol=0, atol=1e-12)

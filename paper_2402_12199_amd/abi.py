@@ -286,6 +286,28 @@ def rb_rigid_step_fused(ctx: Ctx, dt: float, x, P, q, L, types, acc, force, torq
           "rb_rigid_step_fused")
 
 
+def rb_nn_train_step_fm(params, adam_m, adam_v, t: int, norm, precision: int, batch: int, desc, labels, ft_labels,
+                        idx, lam_f, lam_t, fd_step, lr, beta1, beta2, eps, loss, grad_out=None, ws=None):
+    nd = desc.shape[1]
+    _, npn = _norm(norm)
+    check(lib().rb_nn_train_step_fm(_ptr(params, torch.float32, (RB_MLP_NPARAMS,), "params"),
+                                    _ptr(adam_m, torch.float32, (RB_MLP_NPARAMS,), "adam_m"),
+                                    _ptr(adam_v, torch.float32, (RB_MLP_NPARAMS,), "adam_v"), int(t), npn,
+                                    precision, int(batch), _ptr(desc, torch.float32, (7, nd), "desc"), nd,
+                                    _ptr(labels, torch.float32, (nd,), "labels"),
+                                    _ptr(ft_labels, torch.float32, (6, nd), "ft_labels"),
+                                    _ptr(idx, torch.int32, name="idx"), float(lam_f), float(lam_t), float(fd_step),
+                                    float(lr), float(beta1), float(beta2), float(eps),
+                                    _ptr(loss, torch.float32, (2,), "loss"),
+                                    _ptr(grad_out, torch.float32, (RB_MLP_NPARAMS,), "grad_out", optional=True),
+                                    _ptr(ws, torch.uint8, name="ws"), ws.numel(), _stream()),
+          "rb_nn_train_step_fm")
+
+
+def rb_nn_train_fm_workspace_bytes(batch: int) -> int:
+    return int(lib().rb_nn_train_fm_workspace_bytes(batch))
+
+
 def rb_nn_train_workspace_bytes(batch: int) -> int:
     return int(lib().rb_nn_train_workspace_bytes(batch))
 

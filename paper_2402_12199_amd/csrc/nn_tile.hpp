@@ -21,6 +21,8 @@ struct Emit {
     bool live = false;
     float y = 0.f;          // normalised label of this row
     float k2 = 0.f;         // 2 / B: the loss gradient is k2 (e' - y')
+    bool fixed = false;     // row with a given output adjoint (no energy loss term)
+    float adj = 0.f;        // that adjoint
     __device__ float &h(int row) const { return H[row * B + b]; }
     __device__ float &d(int row) const { return D[row * B + b]; }
 };
@@ -97,8 +99,8 @@ __device__ inline float tile_bf16(const LdsBF16 &L, const Norm &nm, const float 
     const float E = fmaf(e, nm.oscale, nm.oshift);
     if (!GRAD) return E;
     if (EMIT) {
-        seed = em.live ? em.k2 * (E - em.y) : 0.f;
-        if (em.live && g == 0) em.R[em.b] = E - em.y;
+        seed = em.live ? (em.fixed ? em.adj : em.k2 * (E - em.y)) : 0.f;
+        if (em.live && g == 0) em.R[em.b] = em.fixed ? 0.f : E - em.y;
     }
 
     // reverse pass: delta_4 = seed * oscale * w5 (.) h4'
@@ -270,8 +272,8 @@ __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &n
     const float E = fmaf(e, nm.oscale, nm.oshift);
     if (!GRAD) return E;
     if (EMIT) {
-        seed = em.live ? em.k2 * (E - em.y) : 0.f;
-        if (em.live && g == 0 && v == 0) em.R[em.b] = E - em.y;
+        seed = em.live ? (em.fixed ? em.adj : em.k2 * (E - em.y)) : 0.f;
+        if (em.live && g == 0 && v == 0) em.R[em.b] = em.fixed ? 0.f : E - em.y;
     }
 
     // reverse pass: this wave's block of delta_4 = seed * oscale * w5 (.) h4'
@@ -434,8 +436,8 @@ __device__ inline float tile_fp32(const LdsFP32 &Lc, LdsFP32 &L, const float *__
     const float E = fmaf(e, nm.oscale, nm.oshift);
     if (!GRAD) return E;
     if (EMIT) {
-        seed = em.live ? em.k2 * (E - em.y) : 0.f;
-        if (em.live && g == 0) em.R[em.b] = E - em.y;
+        seed = em.live ? (em.fixed ? em.adj : em.k2 * (E - em.y)) : 0.f;
+        if (em.live && g == 0) em.R[em.b] = em.fixed ? 0.f : E - em.y;
     }
     const float s0 = seed * nm.oscale;
 #pragma unroll

@@ -26,13 +26,42 @@ struct TrainArgs {
     const float *params;
     Norm nm;          // input normalisation; output mapped to identity
     float oshift, oscale;
-    int32_t B;
+    int32_t B;        // rows of the step
+    int32_t B1;       // rows 0 .. B1: energy rows (descriptors through idx, labels)
+    float k2;         // 2 / B1
     const float *desc;
     int64_t nd;
     const float *labels;
     const int32_t *idx;
+    const float *desc2;   // rows B1 .. B: descriptors (7 x (B - B1))
+    const float *adj2;    // and their output adjoints
     float *H, *D, *R, *part;
 };
+
+// Row b of a step: an energy row (descriptor through idx, energy loss) or,
+// past B1, a row with a given output adjoint; rows past B are padding.
+__device__ inline void load_row(const TrainArgs &a, int b, Emit &em, float u[kIn]) {
+    em.H = a.H;
+    em.D = a.D;
+    em.R = a.R;
+    em.B = a.B;
+    em.b = b;
+    em.live = b < a.B;
+    em.k2 = a.k2;
+    em.fixed = em.live && b >= a.B1;
+    if (em.fixed) {
+        const int64_t m = a.B - a.B1, r = b - a.B1;
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) u[k] = a.desc2[k * m + r];
+        em.adj = a.adj2[r];
+        em.y = 0.f;
+    } else {
+        const int64_t pid = em.live ? a.idx[b] : 0;
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) u[k] = em.live ? a.desc[k * a.nd + pid] : (k == 3 ? 1.f : 0.f);
+        em.y = em.live ? (a.labels[pid] - a.oshift) / a.oscale : 0.f;
+    }
+}
 
 template <bool BF16>
 __global__ __launch_bounds__(nn_threads(BF16, 1)) void k_train_fb(TrainArgs a) {
@@ -50,18 +79,8 @@ __global__ __launch_bounds__(nn_threads(BF16, 1)) void k_train_fb(TrainArgs a) {
         __asm__ volatile("" ::: "memory");
         const int b = t * kTile + n;
         Emit em;
-        em.H = a.H;
-        em.D = a.D;
-        em.R = a.R;
-        em.B = a.B;
-        em.b = b;
-        em.live = b < a.B;
-        em.k2 = 2.f / (float)a.B;
-        const int64_t pid = em.live ? a.idx[b] : 0;
         float u[kIn];
-#pragma unroll
-        for (int k = 0; k < kIn; ++k) u[k] = em.live ? a.desc[k * a.nd + pid] : (k == 3 ? 1.f : 0.f);
-        em.y = em.live ? (a.labels[pid] - a.oshift) / a.oscale : 0.f;
+        load_row(a, b, em, u);
         float gu[kIn];
         if constexpr (BF16)
             (void)tile_bf16<true, true>(L, a.nm, u, 0.f, gu, em);
@@ -87,18 +106,8 @@ __global__ __launch_bounds__(kTrainWideThreads) void k_train_fb_wide(TrainArgs a
     for (int base = blockIdx.x * kTrainGroups; base < ntiles; base += gridDim.x * kTrainGroups) {
         const int b = (base + grp) * kTile + n;
         Emit em;
-        em.H = a.H;
-        em.D = a.D;
-        em.R = a.R;
-        em.B = a.B;
-        em.b = b;
-        em.live = b < a.B;
-        em.k2 = 2.f / (float)a.B;
-        const int64_t pid = em.live ? a.idx[b] : 0;
         float u[kIn];
-#pragma unroll
-        for (int k = 0; k < kIn; ++k) u[k] = em.live ? a.desc[k * a.nd + pid] : (k == 3 ? 1.f : 0.f);
-        em.y = em.live ? (a.labels[pid] - a.oshift) / a.oscale : 0.f;
+        load_row(a, b, em, u);
         float gu[kIn];
         (void)tile_bf16_wide<true, true>(L, X[grp], a.nm, u, 0.f, gu, v, em);
     }
@@ -358,12 +367,18 @@ __global__ __launch_bounds__(512) void k_train_wgrad(TrainArgs a) {
 
 __global__ void k_adam(float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
                        const float *__restrict__ part, int nchunks, float lr, float b1, float b2, float eps, float c1,
-                       float c2, float invB, float *__restrict__ loss, float *__restrict__ grad_out) {
+                       float c2, float invB, float *__restrict__ loss, float *__restrict__ grad_out,
+                       const float *__restrict__ fmpart, int nfm) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) {
         float s = 0.f;
         for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * kPart + NPARAMS];
         loss[0] = s * invB;
+        if (fmpart) {
+            float f = 0.f;
+            for (int c = 0; c < nfm; ++c) f += fmpart[c];
+            loss[1] = f;
+        }
     }
     if (i >= NPARAMS) return;
     // chunk partials summed in chunk order; eight loads in flight at a time
@@ -383,6 +398,98 @@ __global__ void k_adam(float *__restrict__ p, float *__restrict__ m, float *__re
     m[i] = mi;
     v[i] = vi;
     p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+// ------------------------------------------------ force/torque matching
+// The loss adds lam_f mean |F_j - F_j*|^2 + lam_t mean |tau_j - tau_j*|^2,
+// where F_j = -g_d and tau_j = -(w g_v - g_w v + v x g_v) / 2 come from the
+// network's input gradient g = dE/du (pair descriptors u = (d, q), q =
+// (w, v)).  Its parameter gradient is sum_b v_b . dg_b/dtheta with
+// v_b = dL/dg_b (linear in the errors), i.e. the parameter gradient of the
+// directional derivative of E along v_b.  That directional derivative is
+// taken as a central difference, (E(u + eps vh) - E(u - eps vh)) / (2 eps)
+// along vh = v / |v|: two extra rows per sample whose output adjoints are
+// +-|v| oscale / (2 eps), which the ordinary reverse pass and weight-
+// gradient GEMMs then handle like any other row.  The difference is exact
+// to O(eps^2) in the third derivatives of E.
+
+constexpr int kFmThreads = 256;
+
+__global__ void k_fm_gather(int32_t B1, const float *__restrict__ desc, int64_t nd, const int32_t *__restrict__ idx,
+                            float *__restrict__ descb) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B1) return;
+    const int64_t pid = idx[b];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) descb[(int64_t)k * B1 + b] = desc[k * nd + pid];
+}
+
+// Per sample: the force and torque errors, the loss term, v = dL/dg and the
+// two difference rows with their adjoints; per-block loss partials.
+__global__ __launch_bounds__(kFmThreads) void k_fm_rows(int32_t B1, const float *__restrict__ descb,
+                                                        const float *__restrict__ gb,
+                                                        const float *__restrict__ ft_labels, int64_t nd,
+                                                        const int32_t *__restrict__ idx, float lam_f, float lam_t,
+                                                        float step, float oscale, float *__restrict__ desc2,
+                                                        float *__restrict__ adj2, float *__restrict__ fmpart) {
+    __shared__ float red[kFmThreads / kWave];
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    float lsum = 0.f;
+    if (b < B1) {
+        float u[kIn], g[kIn];
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) {
+            u[k] = descb[(int64_t)k * B1 + b];
+            g[k] = gb[(int64_t)k * B1 + b];
+        }
+        const float w = u[3], vx = u[4], vy = u[5], vz = u[6];
+        const float gw = g[3], gx = g[4], gy = g[5], gz = g[6];
+        const float F[3] = {-g[0], -g[1], -g[2]};
+        const float T[3] = {-0.5f * (w * gx - gw * vx + (vy * gz - vz * gy)),
+                            -0.5f * (w * gy - gw * vy + (vz * gx - vx * gz)),
+                            -0.5f * (w * gz - gw * vz + (vx * gy - vy * gx))};
+        const int64_t pid = idx[b];
+        float dF[3], dT[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            dF[a] = F[a] - ft_labels[a * nd + pid];
+            dT[a] = T[a] - ft_labels[(3 + a) * nd + pid];
+            lsum += lam_f * dF[a] * dF[a] + lam_t * dT[a] * dT[a];
+        }
+        lsum /= (float)B1;
+        const float cf = 2.f * lam_f / (float)B1, ct = 2.f * lam_t / (float)B1;
+        const float wF[3] = {cf * dF[0], cf * dF[1], cf * dF[2]}, wT[3] = {ct * dT[0], ct * dT[1], ct * dT[2]};
+        // v = dL/dg: F_j = -g_d; tau_j as above (w_T x v_q from the cross product)
+        float v[kIn];
+        v[0] = -wF[0];
+        v[1] = -wF[1];
+        v[2] = -wF[2];
+        v[3] = 0.5f * (wT[0] * vx + wT[1] * vy + wT[2] * vz);
+        v[4] = -0.5f * (w * wT[0] + (wT[1] * vz - wT[2] * vy));
+        v[5] = -0.5f * (w * wT[1] + (wT[2] * vx - wT[0] * vz));
+        v[6] = -0.5f * (w * wT[2] + (wT[0] * vy - wT[1] * vx));
+        float nv2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) nv2 += v[k] * v[k];
+        const float nv = sqrtf(nv2), inv = nv > 0.f ? 1.f / nv : 0.f;
+        const int64_t m = 2 * (int64_t)B1;
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) {
+            desc2[k * m + b] = u[k] + step * v[k] * inv;
+            desc2[k * m + B1 + b] = u[k] - step * v[k] * inv;
+        }
+        const float s = oscale * nv / (2.f * step);
+        adj2[b] = s;
+        adj2[B1 + b] = -s;
+    }
+    lsum = wave_sum(lsum);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = lsum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.f;
+        for (int k = 0; k < kFmThreads / kWave; ++k) t += red[k];
+        fmpart[blockIdx.x] = t;
+    }
 }
 
 struct TrainLayout {
@@ -411,6 +518,78 @@ static int device_cus_train() {
     return cus;
 }
 
+// Forward/reverse, weight gradients and Adam over the rows of `a` (energy
+// rows first); fmpart (nfm partials) adds the matching loss to loss[1].
+static void train_launch(TrainArgs &a, int precision, float *params, float *adam_m, float *adam_v, int32_t t,
+                         float lr, float beta1, float beta2, float eps, float *loss, float *grad_out,
+                         const float *fmpart, int nfm, hipStream_t st) {
+    const int ntiles = (a.B + kTile - 1) / kTile;
+    const int cus = device_cus_train();
+    if (precision == RB_PREC_BF16) {
+        k_train_fb_wide<<<grid_for(ntiles, kTrainGroups, cus), kTrainWideThreads, 0, st>>>(a);
+    } else {
+        constexpr int wv = nn_threads(false, 1) / kWave;
+        k_train_fb<false><<<grid_for(ntiles, wv, cus), wv * kWave, 0, st>>>(a);
+    }
+    const int nchunks = (a.B + kChunk - 1) / kChunk;
+    if (precision == RB_PREC_BF16)
+        k_train_wgrad<true><<<dim3(nchunks, 5), 512, 0, st>>>(a);
+    else
+        k_train_wgrad<false><<<dim3(nchunks, 4), 512, 0, st>>>(a);
+    const double c1 = 1.0 / (1.0 - pow((double)beta1, (double)t));
+    const double c2 = 1.0 / (1.0 - pow((double)beta2, (double)t));
+    k_adam<<<(NPARAMS + 255) / 256, 256, 0, st>>>(params, adam_m, adam_v, a.part, nchunks, lr, beta1, beta2, eps,
+                                                   (float)c1, (float)c2, 1.f / (float)a.B1, loss, grad_out, fmpart,
+                                                   nfm);
+}
+
+static TrainArgs train_args(float *params, const float *norm, const float *desc, int64_t n_data,
+                            const float *labels, const int32_t *idx, int32_t rows, int32_t batch, char *w,
+                            const TrainLayout &Lw) {
+    TrainArgs a;
+    a.params = params;
+    a.nm = norm_from_host(norm);
+    a.oshift = a.nm.oshift;
+    a.oscale = a.nm.oscale;
+    a.nm.oshift = 0.f;
+    a.nm.oscale = 1.f;
+    a.B = rows;
+    a.B1 = batch;
+    a.k2 = 2.f / (float)batch;
+    a.desc = desc;
+    a.nd = n_data;
+    a.labels = labels;
+    a.idx = idx;
+    a.desc2 = nullptr;
+    a.adj2 = nullptr;
+    a.H = reinterpret_cast<float *>(w + Lw.H);
+    a.D = reinterpret_cast<float *>(w + Lw.D);
+    a.R = reinterpret_cast<float *>(w + Lw.R);
+    a.part = reinterpret_cast<float *>(w + Lw.part);
+    return a;
+}
+
+// Workspace of the matching step: the training rows (3 per sample), then the
+// gathered descriptors, their input gradients, the difference rows, their
+// adjoints and the loss partials.
+struct FmLayout {
+    TrainLayout tr;
+    size_t descb, gb, desc2, adj2, fmpart, total;
+};
+
+static FmLayout fm_layout(int32_t batch) {
+    FmLayout f;
+    f.tr = train_layout(3 * batch);
+    size_t o = f.tr.total;
+    f.descb = o; o += al(sizeof(float) * (size_t)kIn * batch);
+    f.gb = o; o += al(sizeof(float) * (size_t)kIn * batch);
+    f.desc2 = o; o += al(sizeof(float) * (size_t)kIn * 2 * batch);
+    f.adj2 = o; o += al(sizeof(float) * (size_t)2 * batch);
+    f.fmpart = o; o += al(sizeof(float) * (size_t)((batch + kFmThreads - 1) / kFmThreads));
+    f.total = o;
+    return f;
+}
+
 }  // namespace rb
 
 using namespace rb;
@@ -418,6 +597,11 @@ using namespace rb;
 extern "C" size_t rb_nn_train_workspace_bytes(int32_t batch) {
     if (batch <= 0 || batch % 32 != 0 || batch > (1 << 20)) return 0;
     return train_layout(batch).total;
+}
+
+extern "C" size_t rb_nn_train_fm_workspace_bytes(int32_t batch) {
+    if (batch <= 0 || batch % 32 != 0 || batch > (1 << 18)) return 0;
+    return fm_layout(batch).total;
 }
 
 extern "C" int rb_nn_train_step(float *params, float *adam_m, float *adam_v, int32_t t, const float *norm,
@@ -432,41 +616,42 @@ extern "C" int rb_nn_train_step(float *params, float *adam_m, float *adam_v, int
     RB_REQUIRE(n_data > 0 && t >= 1, "rb_nn_train_step: n_data > 0 and t >= 1 required");
     const TrainLayout Lw = train_layout(batch);
     RB_REQUIRE(ws_bytes >= Lw.total, "rb_nn_train_step: workspace too small (%zu < %zu)", ws_bytes, Lw.total);
-    char *w = static_cast<char *>(ws);
-    TrainArgs a;
-    a.params = params;
-    a.nm = norm_from_host(norm);
-    a.oshift = a.nm.oshift;
-    a.oscale = a.nm.oscale;
-    a.nm.oshift = 0.f;
-    a.nm.oscale = 1.f;
-    a.B = batch;
-    a.desc = desc;
-    a.nd = n_data;
-    a.labels = labels;
-    a.idx = idx;
-    a.H = reinterpret_cast<float *>(w + Lw.H);
-    a.D = reinterpret_cast<float *>(w + Lw.D);
-    a.R = reinterpret_cast<float *>(w + Lw.R);
-    a.part = reinterpret_cast<float *>(w + Lw.part);
-    hipStream_t st = (hipStream_t)stream;
-    const int ntiles = (batch + kTile - 1) / kTile;
-    const int cus = device_cus_train();
-    if (precision == RB_PREC_BF16) {
-        k_train_fb_wide<<<grid_for(ntiles, kTrainGroups, cus), kTrainWideThreads, 0, st>>>(a);
-    } else {
-        constexpr int wv = nn_threads(false, 1) / kWave;
-        k_train_fb<false><<<grid_for(ntiles, wv, cus), wv * kWave, 0, st>>>(a);
-    }
-    const int nchunks = (batch + kChunk - 1) / kChunk;
-    if (precision == RB_PREC_BF16)
-        k_train_wgrad<true><<<dim3(nchunks, 5), 512, 0, st>>>(a);
-    else
-        k_train_wgrad<false><<<dim3(nchunks, 4), 512, 0, st>>>(a);
-    const double c1 = 1.0 / (1.0 - pow((double)beta1, (double)t));
-    const double c2 = 1.0 / (1.0 - pow((double)beta2, (double)t));
-    k_adam<<<(NPARAMS + 255) / 256, 256, 0, st>>>(params, adam_m, adam_v, a.part, nchunks, lr, beta1, beta2, eps,
-                                                   (float)c1, (float)c2, 1.f / (float)batch, loss, grad_out);
+    TrainArgs a = train_args(params, norm, desc, n_data, labels, idx, batch, batch, static_cast<char *>(ws), Lw);
+    train_launch(a, precision, params, adam_m, adam_v, t, lr, beta1, beta2, eps, loss, grad_out, nullptr, 0,
+                 (hipStream_t)stream);
     RB_LAUNCH_CHECK("rb_nn_train_step");
+    return RB_OK;
+}
+
+extern "C" int rb_nn_train_step_fm(float *params, float *adam_m, float *adam_v, int32_t t, const float *norm,
+                                   int precision, int32_t batch, const float *desc, int64_t n_data,
+                                   const float *labels, const float *ft_labels, const int32_t *idx, float lam_f,
+                                   float lam_t, float fd_step, float lr, float beta1, float beta2, float eps,
+                                   float *loss, float *grad_out, void *ws, size_t ws_bytes, void *stream) {
+    RB_REQUIRE(params && adam_m && adam_v && norm && desc && labels && ft_labels && idx && loss && ws,
+               "rb_nn_train_step_fm: null argument");
+    RB_REQUIRE(precision == RB_PREC_BF16 || precision == RB_PREC_FP32, "rb_nn_train_step_fm: bad precision");
+    RB_REQUIRE(batch > 0 && batch % 32 == 0 && batch <= (1 << 18),
+               "rb_nn_train_step_fm: batch must be a positive multiple of 32, at most 2^18");
+    RB_REQUIRE(n_data > 0 && t >= 1, "rb_nn_train_step_fm: n_data > 0 and t >= 1 required");
+    RB_REQUIRE(lam_f >= 0.f && lam_t >= 0.f && fd_step > 0.f, "rb_nn_train_step_fm: lam >= 0 and fd_step > 0");
+    const FmLayout F = fm_layout(batch);
+    RB_REQUIRE(ws_bytes >= F.total, "rb_nn_train_step_fm: workspace too small (%zu < %zu)", ws_bytes, F.total);
+    char *w = static_cast<char *>(ws);
+    hipStream_t st = (hipStream_t)stream;
+    float *descb = reinterpret_cast<float *>(w + F.descb), *gb = reinterpret_cast<float *>(w + F.gb);
+    float *desc2 = reinterpret_cast<float *>(w + F.desc2), *adj2 = reinterpret_cast<float *>(w + F.adj2);
+    float *fmpart = reinterpret_cast<float *>(w + F.fmpart);
+    const int nblk = (batch + kFmThreads - 1) / kFmThreads;
+    k_fm_gather<<<nblk, kFmThreads, 0, st>>>(batch, desc, n_data, idx, descb);
+    const int rc = rb_nn_pair_grad(params, norm, precision, batch, descb, nullptr, nullptr, gb, nullptr, stream);
+    if (rc != RB_OK) return rc;
+    k_fm_rows<<<nblk, kFmThreads, 0, st>>>(batch, descb, gb, ft_labels, n_data, idx, lam_f, lam_t, fd_step, norm[15],
+                                           desc2, adj2, fmpart);
+    TrainArgs a = train_args(params, norm, desc, n_data, labels, idx, 3 * batch, batch, w, F.tr);
+    a.desc2 = desc2;
+    a.adj2 = adj2;
+    train_launch(a, precision, params, adam_m, adam_v, t, lr, beta1, beta2, eps, loss, grad_out, fmpart, nblk, st);
+    RB_LAUNCH_CHECK("rb_nn_train_step_fm");
     return RB_OK;
 }

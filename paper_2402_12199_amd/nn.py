@@ -72,7 +72,9 @@ class Trainer:
     """Adam on the FP32 master parameters with the energy loss, on the GPU."""
 
     def __init__(self, params: np.ndarray, norm: np.ndarray, precision=abi.RB_PREC_BF16, batch=8192, lr=1e-3,
-                 beta1=0.9, beta2=0.999, eps=1e-8, device="cuda"):
+                 beta1=0.9, beta2=0.999, eps=1e-8, device="cuda", fm: dict | None = None):
+        """fm: dict(lam_f, lam_t, fd_step) adds force and torque matching
+        (rb_nn_train_step_fm); the data then need (6, n) F_j, tau_j labels."""
         self.dev = torch.device(device)
         self.params = torch.tensor(np.asarray(params, np.float32), device=self.dev)
         self.m = torch.zeros_like(self.params)
@@ -82,27 +84,38 @@ class Trainer:
         self.batch = batch
         self.lr, self.beta1, self.beta2, self.eps = lr, beta1, beta2, eps
         self.t = 0
-        self.ws = torch.zeros(abi.rb_nn_train_workspace_bytes(batch), dtype=torch.uint8, device=self.dev)
-        self.loss = torch.zeros(1, dtype=torch.float32, device=self.dev)
+        self.fm = fm
+        nws = abi.rb_nn_train_fm_workspace_bytes(batch) if fm else abi.rb_nn_train_workspace_bytes(batch)
+        self.ws = torch.zeros(nws, dtype=torch.uint8, device=self.dev)
+        self.loss = torch.zeros(2, dtype=torch.float32, device=self.dev)   # energy, matching
 
-    def step(self, desc, labels, idx, grad_out=None, loss=None):
-        """One Adam step on the batch idx; the batch loss goes to `loss` (a
-        one-element device tensor, default self.loss)."""
+    def step(self, desc, labels, idx, grad_out=None, loss=None, ft=None):
+        """One Adam step on the batch idx; the batch losses go to `loss` (a
+        two-element device tensor, default self.loss: energy, matching)."""
         self.t += 1
-        abi.rb_nn_train_step(self.params, self.m, self.v, self.t, self.norm, self.precision, idx.numel(), desc,
-                             labels, idx, self.lr, self.beta1, self.beta2, self.eps,
-                             self.loss if loss is None else loss, grad_out, self.ws)
+        loss = self.loss if loss is None else loss
+        if self.fm is None:
+            abi.rb_nn_train_step(self.params, self.m, self.v, self.t, self.norm, self.precision, idx.numel(), desc,
+                                 labels, idx, self.lr, self.beta1, self.beta2, self.eps, loss[:1], grad_out, self.ws)
+        else:
+            abi.rb_nn_train_step_fm(self.params, self.m, self.v, self.t, self.norm, self.precision, idx.numel(),
+                                    desc, labels, ft, idx, self.fm["lam_f"], self.fm["lam_t"],
+                                    self.fm.get("fd_step", 0.1), self.lr, self.beta1, self.beta2, self.eps, loss,
+                                    grad_out, self.ws)
 
-    def epoch(self, desc, labels, g: np.random.Generator):
-        """One pass over the data in a random order; returns the mean loss.
-        Each step writes its loss into its own slot, so the loop launches
-        nothing but the training step."""
+    def epoch(self, desc, labels, g: np.random.Generator, ft=None):
+        """One pass over the data in a random order; returns the mean energy
+        loss (the mean matching loss is left in self.fm_loss).  Each step
+        writes its losses into its own slots, so the loop launches nothing
+        but the training step."""
         n = labels.numel()
         perm = torch.tensor(g.permutation(n).astype(np.int32), device=self.dev)
         nb = n // self.batch
-        losses = torch.zeros(max(nb, 1), dtype=torch.float32, device=self.dev)
+        losses = torch.zeros((max(nb, 1), 2), dtype=torch.float32, device=self.dev)
         for b in range(nb):
-            self.step(desc, labels, perm[b * self.batch:(b + 1) * self.batch], loss=losses[b:b + 1])
+            self.step(desc, labels, perm[b * self.batch:(b + 1) * self.batch], loss=losses[b], ft=ft)
         if nb:
-            self.loss.copy_(losses[nb - 1:nb])
-        return float(losses[:nb].double().sum().item()) / max(nb, 1)
+            self.loss.copy_(losses[nb - 1])
+        mean = (losses[:nb].double().sum(0) / max(nb, 1)).cpu().numpy()
+        self.fm_loss = float(mean[1])
+        return float(mean[0])

@@ -92,28 +92,39 @@ def label_set(ctx: abi.Ctx, desc: np.ndarray, r_rej: float = 0.8, type_i: int = 
 
 def fit(desc: np.ndarray, lab: np.ndarray, tdesc: np.ndarray, tlab: np.ndarray, d_cut: float, epochs: int,
         seed: int, batch: int = 8192, lr: float = 1e-3, precision: int = abi.RB_PREC_BF16, init_seed: int = 1003,
-        log=None, name: str = "") -> dict:
-    """Train a fresh network (Xavier init) on energies, return it with the
-    held-out errors before and after."""
+        log=None, name: str = "", fm: dict | None = None) -> dict:
+    """Train a fresh network (Xavier init) on energies (and, with fm =
+    dict(lam_f, lam_t[, fd_step]) or dict(weight[, fd_step]), on the bead
+    forces and torques too; `weight` sets lam_f, lam_t to weight over the
+    mean squared label), return it with the held-out errors before and
+    after."""
     from synth import sampling
     e = lab[:, 0].astype(np.float64)
     norm = make_norm(d_cut, float(e.mean()), float(e.std()))
-    tr = Trainer(sampling.xavier_params(init_seed), norm, precision=precision, batch=batch, lr=lr)
     d_dev = torch.tensor(np.ascontiguousarray(desc.T), device="cuda")
     y_dev = torch.tensor(lab[:, 0].copy(), device="cuda")
+    ft_dev = None
+    if fm is not None:   # F_j and tau_j columns of the bead labels
+        ft = lab[:, [1, 2, 3, 7, 8, 9]].astype(np.float64)
+        if "weight" in fm:   # weights from the label spread: each term ~ weight x (relative error)^2
+            fm = dict(fm, lam_f=fm["weight"] / max(float((ft[:, :3] ** 2).sum(1).mean()), 1e-30),
+                      lam_t=fm["weight"] / max(float((ft[:, 3:] ** 2).sum(1).mean()), 1e-30))
+        ft_dev = torch.tensor(np.ascontiguousarray(ft.T.astype(np.float32)), device="cuda")
+    tr = Trainer(sampling.xavier_params(init_seed), norm, precision=precision, batch=batch, lr=lr, fm=fm)
     g = sampling.rng(seed + 7)
     before = evaluate(tr.params, norm, precision, tdesc, tlab)
     hist = []
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for ep in range(epochs):
-        hist.append(tr.epoch(d_dev, y_dev, g))
+        hist.append(tr.epoch(d_dev, y_dev, g, ft_dev))
         if log and (ep % max(1, epochs // 10) == 0 or ep == epochs - 1):
-            log(f"[surrogate {name}] epoch {ep + 1}/{epochs} loss {hist[-1]:.4f}")
+            log(f"[surrogate {name}] epoch {ep + 1}/{epochs} loss {hist[-1]:.4f}" +
+                (f" matching {tr.fm_loss:.4f}" if fm is not None else ""))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     after = evaluate(tr.params, norm, precision, tdesc, tlab)
-    return dict(shape=name, params=tr.params, norm=norm, precision=precision, d_cut=d_cut, epochs=epochs,
+    return dict(shape=name, params=tr.params, norm=norm, precision=precision, d_cut=d_cut, epochs=epochs, fm=fm,
                 steps=tr.t, batch=batch, n_train=int(len(desc)), n_test=int(len(tdesc)), train_s=t_train,
                 samples_per_s=tr.t * batch / max(t_train, 1e-9), loss_history=hist, untrained=before,
                 trained=after)

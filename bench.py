@@ -342,15 +342,25 @@ def hphc_part(args, torch, abi, log):
     sur = train_surrogate_md(cfg, st, 1 << 20, 1 << 16, args.hphc_epochs, r_rej=0.0, log=log)
     model = NNModel(params=sur["params"], norm=sur["norm"], precision=abi.RB_PREC_BF16, d_min=cfg.d_min,
                     sw_lo=cfg.d_cut - 1.0, sw_hi=cfg.d_cut)
+    # the same data with force and torque matching (weights 10 / mean squared label)
+    log(f"[bench] {cfg.body.name} surrogate with force and torque matching, {args.hphc_epochs} epochs")
+    fm = dict(weight=10.0, fd_step=0.1)
+    surf = train_surrogate_md(cfg, st, 1 << 20, 1 << 16, args.hphc_epochs, r_rej=0.0, log=log, fm=fm)
+    model_fm = NNModel(params=surf["params"], norm=surf["norm"], precision=abi.RB_PREC_BF16, d_min=cfg.d_min,
+                       sw_lo=cfg.d_cut - 1.0, sw_hi=cfg.d_cut)
     out = {"workload": f"{cfg.name}: {cfg.n_bodies} cube shells ({cfg.body.n} beads), half-power half-cosine "
                        f"A={cfg.hphc['A']} b={cfg.hphc['b']} c={cfg.hphc['c']} p={cfg.hphc['p']}, "
                        f"NVE kT={cfg.kT} dt={cfg.dt}",
            "surrogate": {k: sur[k] for k in ("sampling", "epochs", "n_train", "n_test", "train_s", "samples_per_s")},
-           "held_out": sur["trained"], "held_out_untrained": sur["untrained"]}
-    out["dynamics"] = compare(cfg, st, {"nn_md": model}, chunks=8, replays=25, log=log)
+           "held_out": sur["trained"], "held_out_untrained": sur["untrained"],
+           "force_matching": {"weights": fm, "lam_f": surf["fm"]["lam_f"], "lam_t": surf["fm"]["lam_t"],
+                              "train_s": surf["train_s"], "samples_per_s": surf["samples_per_s"],
+                              "held_out": surf["trained"]}}
+    models = {"nn_md": model, "nn_md_fm": model_fm}
+    out["dynamics"] = compare(cfg, st, models, chunks=8, replays=25, log=log)
     # the paper's ensemble: Nose-Hoover NVT at the same temperature
     nvt = dict(kT=cfg.kT, tau=0.5)
-    out["dynamics_nvt"] = compare(cfg, st, {"nn_md": model}, chunks=8, replays=25, log=log, nvt=nvt)
+    out["dynamics_nvt"] = compare(cfg, st, models, chunks=8, replays=25, log=log, nvt=nvt)
     out["dynamics_nvt"]["thermostat"] = dict(nvt, scheme="Nose-Hoover, one thermostat on all momenta, "
                                                        "g = 6 n - 3, Q = g kT tau^2")
     return out

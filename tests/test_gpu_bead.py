@@ -236,9 +236,14 @@ def test_bead_screen_drops_only_zero_pairs(abi, cfgname):
             assert r["E"] == 0.0
 
 
-def test_rigid_step_matches_oracle(abi):
+@pytest.mark.parametrize("spin", [1.0, 300.0])
+def test_rigid_step_matches_oracle(abi, spin):
+    # spin scales the angular momenta: at 300 every sub-step angle is past
+    # the range where the integrator takes sin and cos from their series
     cfg = configs.config1()
-    sysm, st = _system(abi, cfg)
+    _, st = _system(abi, cfg)
+    st = dict(st, L=st["L"] * spin)
+    sysm, _ = _system(abi, cfg, st)
     g = sampling.rng(77)
     n = cfg.n_bodies
     F = (g.normal(size=(n, 3)) * 20).astype(np.float32)

@@ -15,5 +15,7 @@ Modules
   mlp     the energy network: forward pass, input gradient, parameter
           gradient of the training loss, Adam
   thermostat  Nose-Hoover constant-temperature steps around the integrator
+  symmetry    the symmetry-reduced descriptor of a cube pair, its inverse
+              and its Jacobian
 """
-from . import beads, frames, mlp, thermostat  # noqa: F401
+from . import beads, frames, mlp, symmetry, thermostat  # noqa: F401

@@ -252,6 +252,45 @@ int rb_nn_pair_forces(const float *params, const float *norm, int precision, int
                       const int32_t *count_dev, int32_t max_count, float sw_lo, float sw_hi,
                       int64_t *acc, int32_t *flags, void *stream);
 
+/* ---- symmetry-reduced descriptor of cube pairs -----------------------------
+ * Paper, supplementary section 1: a pair of identical cubes reduced to six
+ * numbers s = (p_x, p_y, p_z, alpha_1, alpha_2, alpha_3).  Body 1's axes are
+ * relabelled and their signs chosen (signed permutation g, reflections
+ * included) so that p = g d has p_x >= p_y >= p_z >= 0; with
+ * M = g R(q) g^T, w is body 2's face normal with the largest x component,
+ * alpha_1 = acos(w_x), alpha_2 = atan2(w_z, w_y); alpha_3 in [0, pi/2) is
+ * the turn of body 2 about w: the angle in the y-z plane of Q v, Q the
+ * smallest rotation taking w to (1, 0, 0) and v another face normal, modulo
+ * pi/2.  Ties go to the lower axis index.  For the pairs k = 0 .. count
+ * (count = *count_dev capped at max_count, or n_pairs when count_dev is
+ * NULL), pair pid = idx[k] (or k) of desc (7 x stride: d, q): sym (7 x
+ * max_count, or 7 x n_pairs without count_dev) receives s in rows 0..5 and 0
+ * in row 6 (the network's seventh input), jac (42 x the same) the Jacobian
+ * ds_r/du_m at row r * 7 + m (u = (d, q), q as four free components).  The
+ * descriptor is discontinuous where the choices switch (ties, alpha_2 at
+ * +-pi, alpha_3 at 0 and pi/2); the Jacobian is that of the branch taken. */
+int rb_cube_sym_descriptors(int64_t n_pairs, const float *desc, int64_t stride, const int32_t *idx,
+                            const int32_t *count_dev, int64_t max_count, float *sym, float *jac,
+                            void *stream);
+
+/* rb_nn_pair_grad with the network taking the symmetry-reduced descriptor:
+ * the network reads sym (7 x n_pairs), dE_ddesc receives dE/du =
+ * J^T dE/ds (7 x n_pairs, with respect to desc's (d, q)), and pair_ft the
+ * forces and torques from it as in rb_nn_pair_grad (desc: 7 x n_pairs). */
+int rb_nn_pair_grad_sym(const float *params, const float *norm, int precision, int64_t n_pairs,
+                        const float *desc, const float *sym, const float *jac, const float *gE,
+                        float *energy, float *dE_ddesc, float *pair_ft, void *stream);
+
+/* rb_nn_pair_forces with the symmetry-reduced descriptor: sym and jac (row
+ * stride max_count) hold the descriptor and Jacobian of launch row k, i.e.
+ * of pair idx[k], as rb_cube_sym_descriptors writes them from the same idx
+ * and count. */
+int rb_nn_pair_forces_sym(const float *params, const float *norm, int precision, int32_t n,
+                          const double *q, const int32_t *pair_i, const int32_t *pair_j,
+                          const float *desc, int32_t desc_stride, const float *sym, const float *jac,
+                          const int32_t *idx, const int32_t *count_dev, int32_t max_count, float sw_lo,
+                          float sw_hi, int64_t *acc, int32_t *flags, void *stream);
+
 /* ---- rigid-body velocity Verlet (FP64) -------------------------------------
  * State: x (3 x n), P (3 x n linear momentum), q (4 x n), L (3 x n angular
  * momentum in the body frame).  phase 1: half kick with force/torque (lab

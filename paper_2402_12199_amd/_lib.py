@@ -40,6 +40,10 @@ SIGNATURES = {
     "rb_nn_pair_grad": (C.c_int, [P, FP, C.c_int, I64, P, P, P, P, P, P]),
     "rb_nn_pair_forces": (C.c_int, [P, FP, C.c_int, I32, P, P, P, P, I32, P, P, I32, F32, F32, P, P,
                                     P]),
+    "rb_cube_sym_descriptors": (C.c_int, [I64, P, I64, P, P, I64, P, P, P]),
+    "rb_nn_pair_grad_sym": (C.c_int, [P, FP, C.c_int, I64, P, P, P, P, P, P, P, P]),
+    "rb_nn_pair_forces_sym": (C.c_int, [P, FP, C.c_int, I32, P, P, P, P, I32, P, P, P, P, I32, F32, F32, P, P,
+                                        P]),
     "rb_rigid_workspace_bytes": (SZ, [I32]),
     "rb_rigid_step": (C.c_int, [P, C.c_int, I32, F64, P, P, P, P, P, P, P, P, F64, P, P, F64, P, P, P, P, SZ,
                                 P]),

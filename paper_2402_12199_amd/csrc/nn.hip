@@ -38,7 +38,34 @@ struct NNArgs {
     float sw_lo, sw_hi;
     int64_t *acc;
     int32_t *flags;
+    // symmetry-reduced inputs (cube pairs): the network sees sym (7 x P, row
+    // k of the launch), and dE/du = J^T dE/ds with jac (42 x P, r * 7 + m);
+    // desc then holds the pairs' (d, q) for the forces.  Null: plain (d, q).
+    const float *sym;
+    const float *jac;
 };
+
+// The network's input of launch row `row` (pair pid).
+__device__ inline void net_input(const NNArgs &a, int64_t row, int64_t pid, bool live, float u[kIn]) {
+#pragma unroll
+    for (int k = 0; k < kIn; ++k)
+        u[k] = !live ? (k == 3 ? 1.f : 0.f) : (a.sym ? a.sym[k * a.P + row] : a.desc[k * a.stride + pid]);
+}
+
+// dE/ds -> dE/du through the descriptor's Jacobian (symmetry-reduced form).
+__device__ inline void sym_chain(const NNArgs &a, int64_t row, float gu[kIn]) {
+    if (!a.jac) return;
+    float gs[6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) gs[r] = gu[r];
+#pragma unroll
+    for (int m = 0; m < kIn; ++m) {
+        float v = 0.f;
+#pragma unroll
+        for (int r = 0; r < 6; ++r) v = fmaf(a.jac[(r * kIn + m) * a.P + row], gs[r], v);
+        gu[m] = v;
+    }
+}
 
 // ------------------------------------------------------------------ kernels
 __device__ inline float smooth_switch(float r, float lo, float hi, float &dsdr) {
@@ -171,8 +198,7 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
         int64_t pid = row;
         if (MODE == kForces && live && a.idx) pid = a.idx[row];
         float u[kIn];
-#pragma unroll
-        for (int k = 0; k < kIn; ++k) u[k] = live ? a.desc[k * a.stride + pid] : (k == 3 ? 1.f : 0.f);
+        net_input(a, row, pid, live, u);
         float seed = 1.f;
         if (MODE == kGrad && a.gE) seed = live ? a.gE[pid] : 0.f;
         if (MODE == kForces) {
@@ -187,6 +213,7 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
             E = tile_bf16<MODE != kEval>(L, a.nm, u, seed, gu);
         else
             E = tile_fp32<MODE != kEval>(L, L, a.params, a.nm, u, seed, gu);
+        if (MODE != kEval && live && g == 0) sym_chain(a, row, gu);
         if (MODE == kForces) {
             // every lane takes part in the shuffles below; the results of
             // the lanes of groups 1..3 and of dead rows are discarded
@@ -202,8 +229,14 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
 #pragma unroll
                 for (int k = 0; k < kIn; ++k) a.dEdu[k * a.P + pid] = gu[k];
             if (a.ft) {
-                float ft[9];
-                pair_ft_from_grad(u, gu, ft);
+                float ft[9], ud[kIn];
+                if (a.sym)
+#pragma unroll
+                    for (int k = 0; k < kIn; ++k) ud[k] = a.desc[k * a.stride + pid];
+                else
+#pragma unroll
+                    for (int k = 0; k < kIn; ++k) ud[k] = u[k];
+                pair_ft_from_grad(ud, gu, ft);
 #pragma unroll
                 for (int k = 0; k < 9; ++k) a.ft[k * a.P + pid] = ft[k];
             }
@@ -254,8 +287,7 @@ __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
         int64_t pid = row;
         if (MODE == kForces && live && a.idx) pid = a.idx[row];
         float u[kIn];
-#pragma unroll
-        for (int k = 0; k < kIn; ++k) u[k] = live ? a.desc[k * a.stride + pid] : (k == 3 ? 1.f : 0.f);
+        net_input(a, row, pid, live, u);
         float seed = 1.f;
         if (MODE == kGrad && a.gE) seed = live ? a.gE[pid] : 0.f;
         if (MODE == kForces) {
@@ -267,6 +299,7 @@ __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
         float gu[kIn];
         const float E = tile_bf16_wide<true>(L, X[grp], a.nm, u, seed, gu, v);
         if (v != 0) continue;   // the group's results are the same in its four waves
+        if (live && g == 0) sym_chain(a, row, gu);
         if (MODE == kForces) {
             forces_epilogue(a, ein, gu, E, pid, live && g == 0, lane, wacc[wave], bad);
         } else if (live && g == 0) {
@@ -275,8 +308,14 @@ __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
 #pragma unroll
                 for (int k = 0; k < kIn; ++k) a.dEdu[k * a.P + pid] = gu[k];
             if (a.ft) {
-                float ft[9];
-                pair_ft_from_grad(u, gu, ft);
+                float ft[9], ud[kIn];
+                if (a.sym)
+#pragma unroll
+                    for (int k = 0; k < kIn; ++k) ud[k] = a.desc[k * a.stride + pid];
+                else
+#pragma unroll
+                    for (int k = 0; k < kIn; ++k) ud[k] = u[k];
+                pair_ft_from_grad(ud, gu, ft);
 #pragma unroll
                 for (int k = 0; k < 9; ++k) a.ft[k * a.P + pid] = ft[k];
             }
@@ -400,5 +439,59 @@ extern "C" int rb_nn_pair_forces(const float *params, const float *norm, int pre
     a.sw_hi = sw_hi;
     a.acc = acc;
     a.flags = flags;
+    return launch<kForces>(a, precision, max_count, (hipStream_t)stream);
+}
+
+extern "C" int rb_nn_pair_grad_sym(const float *params, const float *norm, int precision, int64_t n_pairs,
+                                   const float *desc, const float *sym, const float *jac, const float *gE,
+                                   float *energy, float *dE_ddesc, float *pair_ft, void *stream) {
+    RB_REQUIRE(params && norm, "rb_nn_pair_grad_sym: null params/norm");
+    RB_REQUIRE(precision == RB_PREC_BF16 || precision == RB_PREC_FP32, "rb_nn_pair_grad_sym: bad precision");
+    RB_REQUIRE(n_pairs >= 0, "rb_nn_pair_grad_sym: n_pairs < 0");
+    if (n_pairs == 0) return RB_OK;
+    RB_REQUIRE(desc && sym && jac, "rb_nn_pair_grad_sym: null desc/sym/jac");
+    NNArgs a = {};
+    a.params = params;
+    a.nm = norm_from_host(norm);
+    a.P = n_pairs;
+    a.desc = desc;
+    a.stride = n_pairs;
+    a.gE = gE;
+    a.energy = energy;
+    a.dEdu = dE_ddesc;
+    a.ft = pair_ft;
+    a.sym = sym;
+    a.jac = jac;
+    return launch<kGrad>(a, precision, n_pairs, (hipStream_t)stream);
+}
+
+extern "C" int rb_nn_pair_forces_sym(const float *params, const float *norm, int precision, int32_t n,
+                                     const double *q, const int32_t *pair_i, const int32_t *pair_j,
+                                     const float *desc, int32_t desc_stride, const float *sym, const float *jac,
+                                     const int32_t *idx, const int32_t *count_dev, int32_t max_count, float sw_lo,
+                                     float sw_hi, int64_t *acc, int32_t *flags, void *stream) {
+    RB_REQUIRE(params && norm && q && pair_i && pair_j && desc && sym && jac && count_dev && acc && flags,
+               "rb_nn_pair_forces_sym: null argument");
+    RB_REQUIRE(precision == RB_PREC_BF16 || precision == RB_PREC_FP32, "rb_nn_pair_forces_sym: bad precision");
+    RB_REQUIRE(n > 0 && max_count >= 0 && desc_stride >= max_count, "rb_nn_pair_forces_sym: bad sizes");
+    if (max_count == 0) return RB_OK;
+    NNArgs a = {};
+    a.params = params;
+    a.nm = norm_from_host(norm);
+    a.P = max_count;
+    a.desc = desc;
+    a.stride = desc_stride;
+    a.idx = idx;
+    a.count_dev = count_dev;
+    a.q = q;
+    a.n = n;
+    a.pi = pair_i;
+    a.pj = pair_j;
+    a.sw_lo = sw_lo;
+    a.sw_hi = sw_hi;
+    a.acc = acc;
+    a.flags = flags;
+    a.sym = sym;
+    a.jac = jac;
     return launch<kForces>(a, precision, max_count, (hipStream_t)stream);
 }

@@ -34,6 +34,7 @@ class NNModel:
     d_min: float = 0.0             # below: bead fallback
     sw_lo: float = 0.0             # energy switch (sw_hi <= sw_lo: off)
     sw_hi: float = 0.0
+    sym: bool = False              # network takes the symmetry-reduced cube-pair descriptor
 
 
 class RigidSystem:
@@ -122,6 +123,29 @@ class RigidSystem:
         self.desc = torch.zeros((7, self.max_pairs), dtype=torch.float32, device=self.dev)
         self.idx_nn = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
         self.idx_bead = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
+        if model.sym:
+            self.sym = torch.zeros((7, self.max_pairs), dtype=torch.float32, device=self.dev)
+            self.jac = torch.zeros((42, self.max_pairs), dtype=torch.float32, device=self.dev)
+
+    def nn_forces(self):
+        """Descriptors, routing, network forces of the routed pairs and the
+        bead sum of the fallback pairs, all into the accumulator."""
+        m = self.nn
+        abi.rb_pair_descriptors(self.x, self.q, self.box, self.pair_i, self.pair_j, m.d_min, self.desc,
+                                self.idx_nn, self.idx_bead, self.flags,
+                                d_max=m.sw_hi if m.sw_hi > m.sw_lo else 0.0)
+        if m.sym:
+            abi.rb_cube_sym_descriptors(self.desc, self.sym, self.jac, self.idx_nn, self.flags[abi.RB_FLAG_NNN:],
+                                        self.max_pairs)
+            abi.rb_nn_pair_forces_sym(m.params, m.norm, m.precision, self.q, self.pair_i, self.pair_j, self.desc,
+                                      self.sym, self.jac, self.idx_nn, self.flags[abi.RB_FLAG_NNN:], self.max_pairs,
+                                      m.sw_lo, m.sw_hi, self.acc, self.flags)
+        else:
+            abi.rb_nn_pair_forces(m.params, m.norm, m.precision, self.q, self.pair_i, self.pair_j, self.desc,
+                                  self.idx_nn, self.flags[abi.RB_FLAG_NNN:], self.max_pairs, m.sw_lo, m.sw_hi,
+                                  self.acc, self.flags)
+        abi.rb_bead_pair_forces(self.ctx, self.x, self.q, self.types, self.box, self.pair_i, self.pair_j,
+                                self.idx_bead, self.flags[abi.RB_FLAG_NBEAD:], self.max_pairs, self.acc, self.flags)
 
     def bead_forces(self):
         """Bead sum over the whole list (or over the screened pairs)."""
@@ -148,16 +172,7 @@ class RigidSystem:
         if path == "bead":
             self.bead_forces()
         elif path == "nn":
-            m = self.nn
-            abi.rb_pair_descriptors(self.x, self.q, self.box, self.pair_i, self.pair_j, m.d_min, self.desc,
-                                    self.idx_nn, self.idx_bead, self.flags,
-                                    d_max=m.sw_hi if m.sw_hi > m.sw_lo else 0.0)
-            abi.rb_nn_pair_forces(m.params, m.norm, m.precision, self.q, self.pair_i, self.pair_j, self.desc,
-                                  self.idx_nn, self.flags[abi.RB_FLAG_NNN:], self.max_pairs, m.sw_lo, m.sw_hi,
-                                  self.acc, self.flags)
-            abi.rb_bead_pair_forces(self.ctx, self.x, self.q, self.types, self.box, self.pair_i, self.pair_j,
-                                    self.idx_bead, self.flags[abi.RB_FLAG_NBEAD:], self.max_pairs, self.acc,
-                                    self.flags)
+            self.nn_forces()
         else:
             raise ValueError(path)
         abi.rb_accum_finalize(self.n, self.acc, self.force, self.torque, self.ev)
@@ -190,16 +205,7 @@ class RigidSystem:
         if path == "bead":
             self.bead_forces()
         else:
-            m = self.nn
-            abi.rb_pair_descriptors(self.x, self.q, self.box, self.pair_i, self.pair_j, m.d_min, self.desc,
-                                    self.idx_nn, self.idx_bead, self.flags,
-                                    d_max=m.sw_hi if m.sw_hi > m.sw_lo else 0.0)
-            abi.rb_nn_pair_forces(m.params, m.norm, m.precision, self.q, self.pair_i, self.pair_j, self.desc,
-                                  self.idx_nn, self.flags[abi.RB_FLAG_NNN:], self.max_pairs, m.sw_lo, m.sw_hi,
-                                  self.acc, self.flags)
-            abi.rb_bead_pair_forces(self.ctx, self.x, self.q, self.types, self.box, self.pair_i, self.pair_j,
-                                    self.idx_bead, self.flags[abi.RB_FLAG_NBEAD:], self.max_pairs, self.acc,
-                                    self.flags)
+            self.nn_forces()
 
     def begin_fused(self, dt):
         """Phase 1 of the first step of a fused run (forces must be current)."""

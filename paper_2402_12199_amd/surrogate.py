@@ -27,7 +27,7 @@ import numpy as np
 import torch
 
 from . import abi
-from .nn import Trainer, label_pairs, make_norm
+from .nn import Trainer, label_pairs, make_norm, make_norm_sym, sym_descriptors
 
 
 def make_dataset(ctx: abi.Ctx, n: int, seed: int, d_lo: float, d_hi: float, r_rej: float = 0.8,
@@ -56,8 +56,10 @@ def make_dataset(ctx: abi.Ctx, n: int, seed: int, d_lo: float, d_hi: float, r_re
     return desc, lab, 1.0 - have / drawn, t_lab, drawn
 
 
-def evaluate(params, norm, precision, desc: np.ndarray, lab: np.ndarray, chunk: int = 1 << 20) -> dict:
-    """Held-out errors of the network against bead labels (body i frame)."""
+def evaluate(params, norm, precision, desc: np.ndarray, lab: np.ndarray, chunk: int = 1 << 18,
+             sym: bool = False) -> dict:
+    """Held-out errors of the network against bead labels (body i frame);
+    sym: the network takes the symmetry-reduced cube-pair descriptor."""
     P = len(desc)
     E = np.empty(P, np.float32)
     ft = np.empty((P, 9), np.float32)
@@ -65,7 +67,11 @@ def evaluate(params, norm, precision, desc: np.ndarray, lab: np.ndarray, chunk: 
         d = torch.tensor(np.ascontiguousarray(desc[s:s + chunk].T), device="cuda")
         e = torch.empty(d.shape[1], device="cuda")
         f = torch.empty((9, d.shape[1]), device="cuda")
-        abi.rb_nn_pair_grad(params, norm, precision, d, None, e, None, f)
+        if sym:
+            sy, jc = sym_descriptors(d)
+            abi.rb_nn_pair_grad_sym(params, norm, precision, d, sy, jc, None, e, None, f)
+        else:
+            abi.rb_nn_pair_grad(params, norm, precision, d, None, e, None, f)
         E[s:s + chunk] = e.cpu().numpy()
         ft[s:s + chunk] = f.cpu().numpy().T
     ref_e, ref_ft = lab[:, 0].astype(np.float64), lab[:, 1:10].astype(np.float64)
@@ -92,16 +98,21 @@ def label_set(ctx: abi.Ctx, desc: np.ndarray, r_rej: float = 0.8, type_i: int = 
 
 def fit(desc: np.ndarray, lab: np.ndarray, tdesc: np.ndarray, tlab: np.ndarray, d_cut: float, epochs: int,
         seed: int, batch: int = 8192, lr: float = 1e-3, precision: int = abi.RB_PREC_BF16, init_seed: int = 1003,
-        log=None, name: str = "", fm: dict | None = None) -> dict:
+        log=None, name: str = "", fm: dict | None = None, sym: bool = False) -> dict:
     """Train a fresh network (Xavier init) on energies (and, with fm =
     dict(lam_f, lam_t[, fd_step]) or dict(weight[, fd_step]), on the bead
     forces and torques too; `weight` sets lam_f, lam_t to weight over the
     mean squared label), return it with the held-out errors before and
-    after."""
+    after.  sym: train on the symmetry-reduced cube-pair descriptor
+    (supplementary section 1; energy loss only)."""
     from synth import sampling
+    if sym and fm is not None:
+        raise ValueError("force matching takes the (d, q) descriptor")
     e = lab[:, 0].astype(np.float64)
-    norm = make_norm(d_cut, float(e.mean()), float(e.std()))
+    norm = (make_norm_sym if sym else make_norm)(d_cut, float(e.mean()), float(e.std()))
     d_dev = torch.tensor(np.ascontiguousarray(desc.T), device="cuda")
+    if sym:
+        d_dev = sym_descriptors(d_dev, with_jac=False)[0]
     y_dev = torch.tensor(lab[:, 0].copy(), device="cuda")
     ft_dev = None
     if fm is not None:   # F_j and tau_j columns of the bead labels
@@ -112,7 +123,7 @@ def fit(desc: np.ndarray, lab: np.ndarray, tdesc: np.ndarray, tlab: np.ndarray, 
         ft_dev = torch.tensor(np.ascontiguousarray(ft.T.astype(np.float32)), device="cuda")
     tr = Trainer(sampling.xavier_params(init_seed), norm, precision=precision, batch=batch, lr=lr, fm=fm)
     g = sampling.rng(seed + 7)
-    before = evaluate(tr.params, norm, precision, tdesc, tlab)
+    before = evaluate(tr.params, norm, precision, tdesc, tlab, sym=sym)
     hist = []
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -123,8 +134,8 @@ def fit(desc: np.ndarray, lab: np.ndarray, tdesc: np.ndarray, tlab: np.ndarray, 
                 (f" matching {tr.fm_loss:.4f}" if fm is not None else ""))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
-    after = evaluate(tr.params, norm, precision, tdesc, tlab)
-    return dict(shape=name, params=tr.params, norm=norm, precision=precision, d_cut=d_cut, epochs=epochs, fm=fm,
+    after = evaluate(tr.params, norm, precision, tdesc, tlab, sym=sym)
+    return dict(shape=name, params=tr.params, norm=norm, precision=precision, d_cut=d_cut, epochs=epochs, fm=fm, sym=sym,
                 steps=tr.t, batch=batch, n_train=int(len(desc)), n_test=int(len(tdesc)), train_s=t_train,
                 samples_per_s=tr.t * batch / max(t_train, 1e-9), loss_history=hist, untrained=before,
                 trained=after)

@@ -261,14 +261,18 @@ int rb_nn_pair_forces(const float *params, const float *norm, int precision, int
  * alpha_1 = acos(w_x), alpha_2 = atan2(w_z, w_y); alpha_3 in [0, pi/2) is
  * the turn of body 2 about w: the angle in the y-z plane of Q v, Q the
  * smallest rotation taking w to (1, 0, 0) and v another face normal, modulo
- * pi/2.  Ties go to the lower axis index.  For the pairs k = 0 .. count
- * (count = *count_dev capped at max_count, or n_pairs when count_dev is
- * NULL), pair pid = idx[k] (or k) of desc (7 x stride: d, q): sym (7 x
- * max_count, or 7 x n_pairs without count_dev) receives s in rows 0..5 and 0
- * in row 6 (the network's seventh input), jac (42 x the same) the Jacobian
- * ds_r/du_m at row r * 7 + m (u = (d, q), q as four free components).  The
- * descriptor is discontinuous where the choices switch (ties, alpha_2 at
- * +-pi, alpha_3 at 0 and pi/2); the Jacobian is that of the branch taken. */
+ * pi/2.  Ties go to the lower axis index.  The network's seven inputs are
+ * s = (p_x, p_y, p_z, w_y, w_z, cos 4 alpha_3, sin 4 alpha_3): the same
+ * numbers through smooth functions (w_y = sin a1 cos a2, w_z = sin a1 sin a2),
+ * free of the angles' polar singularity at w = (1, 0, 0) and of alpha_3's
+ * cut.  For the pairs k = 0 .. count (count = *count_dev capped at
+ * max_count, or n_pairs when count_dev is NULL), pair pid = idx[k] (or k) of
+ * desc (7 x stride: d, q): sym (7 x max_count, or 7 x n_pairs without
+ * count_dev) receives s, jac (49 x the same) the Jacobian ds_r/du_m at row
+ * r * 7 + m (u = (d, q), q as four free components; R(q) taken as the
+ * homogeneous form v -> q v q^*).  s still switches where the choices do
+ * (ties in the sort or in the choice of w); the Jacobian is that of the
+ * branch taken. */
 int rb_cube_sym_descriptors(int64_t n_pairs, const float *desc, int64_t stride, const int32_t *idx,
                             const int32_t *count_dev, int64_t max_count, float *sym, float *jac,
                             void *stream);

@@ -21,8 +21,13 @@ energy unchanged.  The descriptor picks one representative:
 
 Readings (the supplement is silent on them): ties in the sort and in the
 choice of w go to the lower axis index; alpha_2 in (-pi, pi], alpha_3 in
-[0, pi/2).  The descriptor is s = (p_x, p_y, p_z, alpha_1, alpha_2,
-alpha_3).
+[0, pi/2).  The network takes the angles through smooth functions of them,
+s = (p_x, p_y, p_z, sin a1 cos a2, sin a1 sin a2, cos 4 a3, sin 4 a3) =
+(p, w_y, w_z, cos 4 a3, sin 4 a3): the same information (w_x >= 1/sqrt 3 is
+fixed by w_y, w_z; alpha_3 is taken modulo pi/2) without the polar
+singularity of (alpha_1, alpha_2) at w = (1, 0, 0), where the chain rule of
+the angles divides by sin alpha_1, and without the cut of alpha_3 between 0
+and pi/2.  cube_angles gives the paper's six numbers.
 """
 from __future__ import annotations
 
@@ -40,12 +45,12 @@ def rotation_matrices(q: np.ndarray) -> np.ndarray:
     return np.stack(cols, axis=-1)
 
 
-def cube_descriptor(desc: np.ndarray) -> np.ndarray:
-    """s (P, 6) from pair descriptors desc (P, 7) = (d, q), d body 2's centre
-    in body 1's frame and q its orientation relative to body 1."""
+def _canonical(desc: np.ndarray):
+    """Per pair: p (3), the face normal w (3) and the turn beta about it
+    (not yet reduced modulo pi/2)."""
     desc = np.asarray(desc, np.float64)
     d, R = desc[:, :3], rotation_matrices(desc[:, 3:7])
-    out = np.empty((len(desc), 6))
+    out = np.empty((len(desc), 7))
     for n in range(len(desc)):
         a = np.abs(d[n])
         order = sorted(range(3), key=lambda k: (-a[k], k))          # largest first, ties by index
@@ -59,18 +64,43 @@ def cube_descriptor(desc: np.ndarray) -> np.ndarray:
         v = M[:, (k + 1) % 3]
         c = v[0] / (1.0 + w[0])                                     # Q v = v - (w + e_x) v_x / (1 + w_x)
         beta = np.arctan2(v[2] - w[2] * c, v[1] - w[1] * c)
-        out[n] = (p[0], p[1], p[2], np.arccos(np.clip(w[0], -1.0, 1.0)), np.arctan2(w[2], w[1]),
-                  beta - HALF_PI * np.floor(beta / HALF_PI))
+        out[n] = (p[0], p[1], p[2], w[0], w[1], w[2], beta)
     return out
 
 
-def cube_configuration(s: np.ndarray) -> np.ndarray:
-    """A pair configuration (P, 7) = (d, q) with descriptor s: body 2 at p
-    with w = (cos a1, sin a1 cos a2, sin a1 sin a2) and the turn a3 about it."""
-    from scipy.spatial.transform import Rotation
+def cube_angles(desc: np.ndarray) -> np.ndarray:
+    """The paper's six numbers (p_x, p_y, p_z, alpha_1, alpha_2, alpha_3)
+    (P, 6) from pair descriptors desc (P, 7) = (d, q), d body 2's centre in
+    body 1's frame and q its orientation relative to body 1."""
+    c = _canonical(desc)
+    beta = c[:, 6]
+    return np.stack([c[:, 0], c[:, 1], c[:, 2], np.arccos(np.clip(c[:, 3], -1.0, 1.0)), np.arctan2(c[:, 5], c[:, 4]),
+                     beta - HALF_PI * np.floor(beta / HALF_PI)], axis=1)
+
+
+def cube_descriptor(desc: np.ndarray) -> np.ndarray:
+    """The network's input s (P, 7) = (p, w_y, w_z, cos 4 a3, sin 4 a3) =
+    (p, sin a1 cos a2, sin a1 sin a2, cos 4 a3, sin 4 a3) from pair
+    descriptors desc (P, 7) = (d, q)."""
+    c = _canonical(desc)
+    return np.stack([c[:, 0], c[:, 1], c[:, 2], c[:, 4], c[:, 5], np.cos(4 * c[:, 6]), np.sin(4 * c[:, 6])], axis=1)
+
+
+def angles_of(s: np.ndarray) -> np.ndarray:
+    """The six angles' form of descriptors s (P, 7)."""
     s = np.asarray(s, np.float64)
+    a3 = 0.25 * np.arctan2(s[:, 6], s[:, 5])
+    return np.stack([s[:, 0], s[:, 1], s[:, 2], np.arcsin(np.clip(np.hypot(s[:, 3], s[:, 4]), 0.0, 1.0)),
+                     np.arctan2(s[:, 4], s[:, 3]), a3 - HALF_PI * np.floor(a3 / HALF_PI)], axis=1)
+
+
+def cube_configuration(s: np.ndarray) -> np.ndarray:
+    """A pair configuration (P, 7) = (d, q) with descriptor s (P, 7): body 2
+    at p with w = (cos a1, sin a1 cos a2, sin a1 sin a2) and the turn a3
+    about it."""
+    from scipy.spatial.transform import Rotation
     out = np.empty((len(s), 7))
-    for n, (px, py, pz, a1, a2, a3) in enumerate(s):
+    for n, (px, py, pz, a1, a2, a3) in enumerate(angles_of(s)):
         w = np.array([np.cos(a1), np.sin(a1) * np.cos(a2), np.sin(a1) * np.sin(a2)])
         axis = np.cross(w, [1.0, 0.0, 0.0])
         nrm = np.linalg.norm(axis)
@@ -83,16 +113,12 @@ def cube_configuration(s: np.ndarray) -> np.ndarray:
 
 
 def cube_descriptor_jacobian(desc: np.ndarray, h: float = 1e-6) -> np.ndarray:
-    """d s / d (d, q) (P, 6, 7) by central differences of cube_descriptor
-    (q treated as four free components; alpha_3 unwrapped across its cut)."""
+    """d s / d (d, q) (P, 7, 7) by central differences of cube_descriptor
+    (q treated as four free components)."""
     desc = np.asarray(desc, np.float64)
-    J = np.empty((len(desc), 6, 7))
+    J = np.empty((len(desc), 7, 7))
     for k in range(7):
         e = np.zeros(7)
         e[k] = h
-        sp, sm = cube_descriptor(desc + e), cube_descriptor(desc - e)
-        diff = sp - sm
-        diff[:, 5] -= HALF_PI * np.round(diff[:, 5] / HALF_PI)
-        diff[:, 4] -= 2 * np.pi * np.round(diff[:, 4] / (2 * np.pi))
-        J[:, :, k] = diff / (2 * h)
+        J[:, :, k] = (cube_descriptor(desc + e) - cube_descriptor(desc - e)) / (2 * h)
     return J

@@ -248,13 +248,13 @@ def rb_cube_sym_descriptors(desc, sym, jac, idx=None, count_dev=None, max_count=
     max_count)."""
     stride = desc.shape[1]
     m = int(max_count if count_dev is not None else stride)
-    if sym.shape != (7, m) or jac.shape != (42, m):
-        raise ValueError(f"sym must be (7, {m}) and jac (42, {m})")
+    if sym.shape != (7, m) or jac.shape != (49, m):
+        raise ValueError(f"sym must be (7, {m}) and jac (49, {m})")
     check(lib().rb_cube_sym_descriptors(stride if count_dev is None else 0, _ptr(desc, torch.float32, name="desc"),
                                         stride, _ptr(idx, torch.int32, name="idx", optional=True),
                                         _ptr(count_dev, torch.int32, name="count_dev", optional=True), m,
                                         _ptr(sym, torch.float32, (7, m), "sym"),
-                                        _ptr(jac, torch.float32, (42, m), "jac"), _stream()),
+                                        _ptr(jac, torch.float32, (49, m), "jac"), _stream()),
           "rb_cube_sym_descriptors")
 
 
@@ -264,7 +264,7 @@ def rb_nn_pair_grad_sym(params, norm, precision: int, desc, sym, jac, gE=None, e
     _, npn = _norm(norm)
     check(lib().rb_nn_pair_grad_sym(_ptr(params, torch.float32, (RB_MLP_NPARAMS,), "params"), npn, precision, P,
                                     _ptr(desc, torch.float32, (7, P), "desc"), _ptr(sym, torch.float32, (7, P), "sym"),
-                                    _ptr(jac, torch.float32, (42, P), "jac"),
+                                    _ptr(jac, torch.float32, (49, P), "jac"),
                                     _ptr(gE, torch.float32, (P,), "gE", optional=True),
                                     _ptr(energy, torch.float32, (P,), "energy", optional=True),
                                     _ptr(dE_ddesc, torch.float32, (7, P), "dE_ddesc", optional=True),
@@ -282,7 +282,7 @@ def rb_nn_pair_forces_sym(params, norm, precision, q, pair_i, pair_j, desc, sym,
                                       _ptr(pair_i, torch.int32, name="pair_i"),
                                       _ptr(pair_j, torch.int32, name="pair_j"),
                                       _ptr(desc, torch.float32, name="desc"), desc.shape[1],
-                                      _ptr(sym, torch.float32, (7, m), "sym"), _ptr(jac, torch.float32, (42, m), "jac"),
+                                      _ptr(sym, torch.float32, (7, m), "sym"), _ptr(jac, torch.float32, (49, m), "jac"),
                                       _ptr(idx, torch.int32, name="idx", optional=True),
                                       _ptr(count_dev, torch.int32, name="count_dev"), m,
                                       float(sw_lo), float(sw_hi), _ptr(acc, torch.int64, (acc_len(n),), "acc"),

@@ -39,7 +39,7 @@ struct NNArgs {
     int64_t *acc;
     int32_t *flags;
     // symmetry-reduced inputs (cube pairs): the network sees sym (7 x P, row
-    // k of the launch), and dE/du = J^T dE/ds with jac (42 x P, r * 7 + m);
+    // k of the launch), and dE/du = J^T dE/ds with jac (49 x P, r * 7 + m);
     // desc then holds the pairs' (d, q) for the forces.  Null: plain (d, q).
     const float *sym;
     const float *jac;
@@ -55,14 +55,14 @@ __device__ inline void net_input(const NNArgs &a, int64_t row, int64_t pid, bool
 // dE/ds -> dE/du through the descriptor's Jacobian (symmetry-reduced form).
 __device__ inline void sym_chain(const NNArgs &a, int64_t row, float gu[kIn]) {
     if (!a.jac) return;
-    float gs[6];
+    float gs[kIn];
 #pragma unroll
-    for (int r = 0; r < 6; ++r) gs[r] = gu[r];
+    for (int r = 0; r < kIn; ++r) gs[r] = gu[r];
 #pragma unroll
     for (int m = 0; m < kIn; ++m) {
         float v = 0.f;
 #pragma unroll
-        for (int r = 0; r < 6; ++r) v = fmaf(a.jac[(r * kIn + m) * a.P + row], gs[r], v);
+        for (int r = 0; r < kIn; ++r) v = fmaf(a.jac[(r * kIn + m) * a.P + row], gs[r], v);
         gu[m] = v;
     }
 }

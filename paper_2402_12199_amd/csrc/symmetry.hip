@@ -9,7 +9,11 @@
 // atan2(w_z, w_y), and alpha_3 is the angle, modulo pi/2, of Q v in the y-z
 // plane, Q the smallest rotation taking w to (1, 0, 0) and v a second face
 // normal (Q v = v - (w + e_x) v_x / (1 + w_x) for v perpendicular to w).
-// Ties in the sort and in the choice of w go to the lower index.
+// Ties in the sort and in the choice of w go to the lower index.  The
+// network takes s = (p_x, p_y, p_z, w_y, w_z, cos 4 alpha_3, sin 4 alpha_3),
+// smooth functions of the six numbers (w_y = sin a1 cos a2, w_z =
+// sin a1 sin a2) without the polar singularity of (alpha_1, alpha_2) at
+// w = (1, 0, 0) and without the cut of alpha_3 between 0 and pi/2.
 //
 // One thread per pair, FP64.  p is a signed permutation of d, so its rows of
 // the Jacobian are those of g; the angles depend on d only through the
@@ -76,15 +80,6 @@ __device__ inline Dual operator/(const Dual &a, const Dual &b) {
     for (int k = 0; k < kND; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * ib;
     return r;
 }
-__device__ inline Dual dacos(const Dual &a) {
-    const double x = fmin(fmax(a.v, -1.0), 1.0);
-    Dual r;
-    r.v = acos(x);
-    const double f = -1.0 / sqrt(fmax(1.0 - x * x, 1e-300));
-#pragma unroll
-    for (int k = 0; k < kND; ++k) r.d[k] = f * a.d[k];
-    return r;
-}
 __device__ inline Dual datan2(const Dual &y, const Dual &x) {
     Dual r;
     r.v = atan2(y.v, x.v);
@@ -104,7 +99,7 @@ __device__ inline Dual dsel(int k, const Dual &a, const Dual &b, const Dual &c) 
     return r;
 }
 
-__device__ void cube_sym(const double u[7], double s[6], double J[6][7]) {
+__device__ void cube_sym(const double u[7], double s[7], double J[7][7]) {
     Dual q[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) q[k] = dvar(u[3 + k], k);
@@ -168,31 +163,35 @@ __device__ void cube_sym(const double u[7], double s[6], double J[6][7]) {
         wv[r] = sk * dsel(k, M[r][0], M[r][1], M[r][2]);
         vv[r] = dsel(k1, M[r][0], M[r][1], M[r][2]);
     }
-    const Dual al1 = dacos(wv[0]);
-    const Dual al2 = datan2(wv[2], wv[1]);
     const Dual c = vv[0] / (one + wv[0]);
     const Dual beta = datan2(vv[2] - wv[2] * c, vv[1] - wv[1] * c);
-    const double half_pi = 1.5707963267948966;
+    const double c4 = cos(4.0 * beta.v), s4 = sin(4.0 * beta.v);
     s[0] = p[0];
     s[1] = p[1];
     s[2] = p[2];
-    s[3] = al1.v;
-    s[4] = al2.v;
-    s[5] = beta.v - half_pi * floor(beta.v / half_pi);
+    s[3] = wv[1].v;
+    s[4] = wv[2].v;
+    s[5] = c4;
+    s[6] = s4;
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int m = 0; m < 7; ++m) J[r][m] = m < 3 ? g[r][m] : 0.0;
 #pragma unroll
-    for (int m = 0; m < 3; ++m) J[3][m] = J[4][m] = J[5][m] = 0.0;
+    for (int r = 3; r < 7; ++r)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) J[r][m] = 0.0;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        J[3][3 + m] = al1.d[m];
-        J[4][3 + m] = al2.d[m];
-        J[5][3 + m] = beta.d[m];
+        J[3][3 + m] = wv[1].d[m];
+        J[4][3 + m] = wv[2].d[m];
+        J[5][3 + m] = -4.0 * s4 * beta.d[m];
+        J[6][3 + m] = 4.0 * c4 * beta.d[m];
     }
 }
 
+// k-th listed pair (pid = idx[k], or k): s to the 7 rows of sym, J to jac
+// (49 rows, r * 7 + m), both with row stride max_count.
 __global__ __launch_bounds__(256) void k_cube_sym(const float *__restrict__ desc, int64_t stride, const int32_t *__restrict__ idx,
                            const int32_t *__restrict__ count_dev, int64_t n_pairs, int64_t max_count,
                            float *__restrict__ sym, float *__restrict__ jac) {
@@ -207,13 +206,12 @@ __global__ __launch_bounds__(256) void k_cube_sym(const float *__restrict__ desc
         double u[7];
 #pragma unroll
         for (int m = 0; m < 7; ++m) u[m] = desc[m * stride + pid];
-        double s[6], J[6][7];
+        double s[7], J[7][7];
         cube_sym(u, s, J);
 #pragma unroll
-        for (int r = 0; r < 6; ++r) sym[r * max_count + k] = (float)s[r];
-        sym[6 * max_count + k] = 0.f;
+        for (int r = 0; r < 7; ++r) sym[r * max_count + k] = (float)s[r];
 #pragma unroll
-        for (int r = 0; r < 6; ++r)
+        for (int r = 0; r < 7; ++r)
 #pragma unroll
             for (int m = 0; m < 7; ++m) jac[(r * 7 + m) * max_count + k] = (float)J[r][m];
     }

@@ -125,7 +125,7 @@ class RigidSystem:
         self.idx_bead = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
         if model.sym:
             self.sym = torch.zeros((7, self.max_pairs), dtype=torch.float32, device=self.dev)
-            self.jac = torch.zeros((42, self.max_pairs), dtype=torch.float32, device=self.dev)
+            self.jac = torch.zeros((49, self.max_pairs), dtype=torch.float32, device=self.dev)
 
     def nn_forces(self):
         """Descriptors, routing, network forces of the routed pairs and the

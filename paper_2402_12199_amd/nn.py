@@ -26,30 +26,29 @@ def make_norm(d_cut: float, e_shift: float = 0.0, e_scale: float = 1.0, d_gain: 
 
 def make_norm_sym(d_cut: float, e_shift: float = 0.0, e_scale: float = 1.0, d_gain: float = 2.3) -> np.ndarray:
     """Normalisation of the symmetry-reduced cube-pair descriptor
-    (p_x, p_y, p_z, alpha_1, alpha_2, alpha_3, 0): the centre coordinates as
-    in make_norm, alpha_1 in [0, 0.96] centred, alpha_2 in (-pi, pi] and
-    alpha_3 in [0, pi/2) scaled to about unit spread; the seventh input is
-    unused."""
-    shift = [0.0, 0.0, 0.0, 0.5, 0.0, 0.25 * np.pi, 0.0]
-    scale = [d_gain / d_cut] * 3 + [3.0, 0.6, 2.0, 0.0]
+    (p_x, p_y, p_z, w_y, w_z, cos 4 a3, sin 4 a3): the centre coordinates as
+    in make_norm, w_y, w_z (|w_y|, |w_z| <= 0.82) and the unit circle of
+    4 a3 at about unit spread."""
+    shift = [0.0] * 7
+    scale = [d_gain / d_cut] * 3 + [2.0, 2.0, 1.0, 1.0]
     return np.concatenate([shift, scale, [e_shift, e_scale]]).astype(np.float32)
 
 
 def sym_descriptors(desc: torch.Tensor, chunk: int = 1 << 18, with_jac: bool = True):
-    """(sym (7, P), jac (42, P) or None) of pair descriptors desc (7, P) on
+    """(sym (7, P), jac (49, P) or None) of pair descriptors desc (7, P) on
     the device (rb_cube_sym_descriptors), in chunks when the Jacobian is
     dropped."""
     P = desc.shape[1]
     sym = torch.empty((7, P), dtype=torch.float32, device=desc.device)
     if with_jac:
-        jac = torch.empty((42, P), dtype=torch.float32, device=desc.device)
+        jac = torch.empty((49, P), dtype=torch.float32, device=desc.device)
         abi.rb_cube_sym_descriptors(desc, sym, jac)
         return sym, jac
     for s0 in range(0, P, chunk):
         d = desc[:, s0:s0 + chunk].contiguous()
         m = d.shape[1]
         sy = torch.empty((7, m), dtype=torch.float32, device=desc.device)
-        jc = torch.empty((42, m), dtype=torch.float32, device=desc.device)
+        jc = torch.empty((49, m), dtype=torch.float32, device=desc.device)
         abi.rb_cube_sym_descriptors(d, sy, jc)
         sym[:, s0:s0 + m] = sy
     return sym, None

@@ -22,17 +22,13 @@ def abi():
     return _abi
 
 
-def _away_from_cuts(desc, s, margin=2e-3):
+def _away_from_cuts(desc, margin=2e-3):
     """Rows whose descriptor does not sit near a switch of its choices (sort
-    ties, face-normal ties, the alpha_2 and alpha_3 cuts), where FP32 input
-    rounding could take the other branch, nor near alpha_1 = 0, where
-    alpha_2's derivatives grow like 1 / sin(alpha_1)."""
+    ties, face-normal ties), where FP32 input rounding could take the other
+    branch."""
     a = np.sort(np.abs(desc[:, :3]), axis=1)
     R = osym.rotation_matrices(desc[:, 3:7])
     ok = (a[:, 2] - a[:, 1] > margin) & (a[:, 1] - a[:, 0] > margin)
-    ok &= np.pi - np.abs(s[:, 4]) > margin
-    ok &= (s[:, 5] > margin) & (np.pi / 2 - s[:, 5] > margin)
-    ok &= s[:, 3] > 10 * margin   # alpha_2 is singular where w meets the x axis
     for n in np.nonzero(ok)[0]:
         g = np.zeros((3, 3))
         for r, k in enumerate(sorted(range(3), key=lambda k: (-abs(desc[n, k]), k))):
@@ -47,25 +43,24 @@ def test_descriptor_and_jacobian_match_oracle(abi):
     desc = sampling.pair_batch(sampling.rng(31), P, 6.0, 11.2).astype(np.float32)
     d = torch.tensor(np.ascontiguousarray(desc.T), device="cuda")
     sym = torch.full((7, P), float("nan"), device="cuda")
-    jac = torch.full((42, P), float("nan"), device="cuda")
+    jac = torch.full((49, P), float("nan"), device="cuda")
     abi.rb_cube_sym_descriptors(d, sym, jac)
     got_s = sym.cpu().numpy().T
-    got_j = jac.cpu().numpy().T.reshape(P, 6, 7)
+    got_j = jac.cpu().numpy().T.reshape(P, 7, 7)
     u = desc.astype(np.float64)
     ref_s = osym.cube_descriptor(u)
-    ok = _away_from_cuts(u, ref_s)
+    ok = _away_from_cuts(u)
     assert ok.sum() > 0.8 * P
-    assert np.all(got_s[:, 6] == 0.0)
-    err = np.abs(got_s[ok, :6] - ref_s[ok]) / np.abs(ref_s).max(axis=0)
+    err = np.abs(got_s[ok] - ref_s[ok]) / np.abs(ref_s).max(axis=0)
     assert err.max() < 2e-5, (err.max(axis=0), np.argmax(err, axis=0))
     ref_j = osym.cube_descriptor_jacobian(u[ok])
-    assert_close(got_j[ok].reshape(-1, 42), ref_j.reshape(-1, 42), 1e-4, "jacobian")
+    assert_close(got_j[ok].reshape(-1, 49), ref_j.reshape(-1, 49), 1e-4, "jacobian")
     # compacted form: pairs idx[0 .. count) into rows 0 .. count
     idx = np.sort(sampling.rng(32).choice(P, 700, replace=False)).astype(np.int32)
     m = 1024
     cnt = torch.tensor([len(idx)], dtype=torch.int32, device="cuda")
     sym2 = torch.zeros((7, m), device="cuda")
-    jac2 = torch.zeros((42, m), device="cuda")
+    jac2 = torch.zeros((49, m), device="cuda")
     abi.rb_cube_sym_descriptors(d, sym2, jac2, torch.tensor(idx, device="cuda"), cnt, m)
     assert torch.equal(sym2[:, :len(idx)], sym[:, idx]) and torch.equal(jac2[:, :len(idx)], jac[:, idx])
     assert torch.all(sym2[:, len(idx):] == 0)
@@ -76,14 +71,13 @@ def test_network_gradient_through_the_descriptor_matches_oracle(abi, prec):
     P = 1500
     desc = sampling.pair_batch(sampling.rng(33), P, 6.0, 11.2).astype(np.float32)
     u = desc.astype(np.float64)
-    ref_s = osym.cube_descriptor(u)
-    ok = _away_from_cuts(u, ref_s)
+    ok = _away_from_cuts(u)
     params = sampling.xavier_params(34)
     from paper_2402_12199_amd.nn import make_norm_sym
     norm = make_norm_sym(11.2)
     d = torch.tensor(np.ascontiguousarray(desc.T), device="cuda")
     sym = torch.empty((7, P), device="cuda")
-    jac = torch.empty((42, P), device="cuda")
+    jac = torch.empty((49, P), device="cuda")
     abi.rb_cube_sym_descriptors(d, sym, jac)
     e = torch.empty(P, device="cuda")
     g = torch.empty((7, P), device="cuda")
@@ -93,9 +87,8 @@ def test_network_gradient_through_the_descriptor_matches_oracle(abi, prec):
     net = omlp.bf16_network(params) if prec == 0 else params.astype(np.float32).astype(np.float64)
     on = omlp.Norm(in_shift=norm[:7].astype(np.float64), in_scale=norm[7:14].astype(np.float64),
                    out_shift=float(norm[14]), out_scale=float(norm[15]))
-    s7 = np.concatenate([ref_s[ok], np.zeros((ok.sum(), 1))], axis=1)
-    E_ref, gs = omlp.input_grad(net, s7, on)
-    gu = np.einsum("pk,pkm->pm", gs[:, :6], osym.cube_descriptor_jacobian(u[ok]))
+    E_ref, gs = omlp.input_grad(net, osym.cube_descriptor(u[ok]), on)
+    gu = np.einsum("pk,pkm->pm", gs, osym.cube_descriptor_jacobian(u[ok]))
     ft_ref = oframes.forces_from_grad(u[ok], gu)
     tol = 2e-2 if prec == 0 else 1e-4
     assert_close(e.cpu().numpy()[ok], E_ref, tol, "E")
@@ -125,9 +118,8 @@ def test_system_forces_through_the_descriptor_match_oracle(abi):
                             box=cfg.box)
     on = omlp.Norm(in_shift=norm[:7].astype(np.float64), in_scale=norm[7:14].astype(np.float64),
                    out_shift=float(norm[14]), out_scale=float(norm[15]))
-    s7 = np.concatenate([osym.cube_descriptor(u), np.zeros((len(u), 1))], axis=1)
-    E, gs = omlp.input_grad(omlp.bf16_network(params), s7, on)
-    gu = np.einsum("pk,pkm->pm", gs[:, :6], osym.cube_descriptor_jacobian(u))
+    E, gs = omlp.input_grad(omlp.bf16_network(params), osym.cube_descriptor(u), on)
+    gu = np.einsum("pk,pkm->pm", gs, osym.cube_descriptor_jacobian(u))
     lab = oframes.to_lab(st["q"][pairs[:, 0]], oframes.forces_from_grad(u, gu))
     F = np.zeros((cfg.n_bodies, 3))
     T = np.zeros((cfg.n_bodies, 3))

@@ -33,7 +33,7 @@ def _pairs(n, seed):
 
 
 def test_ranges():
-    s = symmetry.cube_descriptor(_pairs(400, 1))
+    s = symmetry.cube_angles(_pairs(400, 1))
     assert np.all(s[:, 0] >= s[:, 1]) and np.all(s[:, 1] >= s[:, 2]) and np.all(s[:, 2] >= 0)
     assert np.all(s[:, 3] >= 0) and np.all(s[:, 3] <= np.arccos(1 / np.sqrt(3)) + 1e-12)
     assert np.all(s[:, 4] > -np.pi) and np.all(s[:, 4] <= np.pi)
@@ -45,7 +45,7 @@ def test_invariant_under_the_cube_symmetries():
     # included) and turning body 2 by any of its 24 self-rotations leave the
     # descriptor unchanged
     desc = _pairs(30, 2)
-    s = symmetry.cube_descriptor(desc)
+    s = symmetry.cube_angles(desc)
     G = _signed_perms()
     H = [g for g in G if np.linalg.det(g) > 0]
     assert len(G) == 48 and len(H) == 24
@@ -54,7 +54,7 @@ def test_invariant_under_the_cube_symmetries():
     for g in G:
         h = H[rng.integers(len(H))]
         moved = np.array([np.concatenate([g @ d, _quat(g @ Rn @ g.T @ h)]) for d, Rn in zip(desc[:, :3], R)])
-        np.testing.assert_allclose(symmetry.cube_descriptor(moved), s, atol=1e-10)
+        np.testing.assert_allclose(symmetry.cube_angles(moved), s, atol=1e-10)
 
 
 def test_bead_energy_is_a_function_of_the_descriptor():
@@ -78,7 +78,7 @@ def test_chain_rule_forces_of_an_energy_in_the_descriptor(seed):
     # E = net(s(d, q)): F_j, tau_j from g_u = J^T g_s and the closed form
     # against central differences of the whole chain in the lab frame
     p = sampling.xavier_params(60 + seed)
-    nrm = mlp.Norm(in_scale=np.array([0.2, 0.2, 0.2, 2.0, 0.6, 1.2, 0.0]))
+    nrm = mlp.Norm(in_scale=np.array([0.2, 0.2, 0.2, 2.0, 2.0, 1.0, 1.0]))
     g = sampling.rng(70 + seed)
     qi, qj = sampling.uniform_quaternions(g, 2)
     xi = np.zeros(3)
@@ -86,13 +86,11 @@ def test_chain_rule_forces_of_an_energy_in_the_descriptor(seed):
 
     def E(xj_, qj_):
         u = frames.descriptors(xi, qi, xj_, qj_)[None, :]
-        s = np.concatenate([symmetry.cube_descriptor(u), np.zeros((1, 1))], axis=1)
-        return mlp.forward(p, s, nrm)[0]
+        return mlp.forward(p, symmetry.cube_descriptor(u), nrm)[0]
 
     u = frames.descriptors(xi, qi, xj, qj)[None, :]
-    s = np.concatenate([symmetry.cube_descriptor(u), np.zeros((1, 1))], axis=1)
-    _, gs = mlp.input_grad(p, s, nrm)
-    gu = np.einsum("pk,pkm->pm", gs[:, :6], symmetry.cube_descriptor_jacobian(u))
+    _, gs = mlp.input_grad(p, symmetry.cube_descriptor(u), nrm)
+    gu = np.einsum("pk,pkm->pm", gs, symmetry.cube_descriptor_jacobian(u))
     lab = frames.to_lab(qi[None, :], frames.forces_from_grad(u, gu))[0]
     h = 1e-5
     sc = max(np.abs(lab).max(), 1e-3)
@@ -103,3 +101,20 @@ def test_chain_rule_forces_of_an_energy_in_the_descriptor(seed):
         fd_t = -(E(xj, frames.qmul(frames.qexp(e), qj)) - E(xj, frames.qmul(frames.qexp(-e), qj))) / (2 * h)
         assert lab[a] == pytest.approx(fd_F, abs=1e-6 * sc)
         assert lab[6 + a] == pytest.approx(fd_t, abs=1e-6 * sc)
+
+
+def test_smooth_form_carries_the_angles():
+    # the network's seven numbers give the paper's six back, and stay smooth
+    # where the angles are not: w on the x axis (alpha_2 undefined) and
+    # alpha_3 at its cut
+    desc = _pairs(300, 6)
+    a = symmetry.cube_angles(desc)
+    np.testing.assert_allclose(symmetry.angles_of(symmetry.cube_descriptor(desc)), a, atol=1e-12)
+    s = symmetry.cube_descriptor(symmetry.cube_configuration(np.array([[8.0, 2.0, 1.0, 0.0, 0.0, 1.0, 0.0]])))
+    np.testing.assert_allclose(s, [[8.0, 2.0, 1.0, 0.0, 0.0, 1.0, 0.0]], atol=1e-12)
+    eps = 1e-7
+    lo = symmetry.cube_descriptor(symmetry.cube_configuration(
+        np.array([[8.0, 2.0, 1.0, 0.1, 0.2, np.cos(4 * eps), np.sin(4 * eps)]])))
+    hi = symmetry.cube_descriptor(symmetry.cube_configuration(
+        np.array([[8.0, 2.0, 1.0, 0.1, 0.2, np.cos(-4 * eps), np.sin(-4 * eps)]])))
+    assert np.abs(lo - hi).max() < 1e-5

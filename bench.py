@@ -355,7 +355,14 @@ def hphc_part(args, torch, abi, log):
            "force_matching": {"weights": fm, "lam_f": surf["fm"]["lam_f"], "lam_t": surf["fm"]["lam_t"],
                               "train_s": surf["train_s"], "samples_per_s": surf["samples_per_s"],
                               "held_out": surf["trained"]}}
-    models = {"nn_md": model, "nn_md_fm": model_fm}
+    # the paper's symmetry-reduced cube-pair descriptor (supplementary section 1)
+    log(f"[bench] {cfg.body.name} surrogate on the symmetry-reduced descriptor, {args.hphc_epochs} epochs")
+    surs = train_surrogate_md(cfg, st, 1 << 20, 1 << 16, args.hphc_epochs, r_rej=0.0, log=log, sym=True)
+    model_sym = NNModel(params=surs["params"], norm=surs["norm"], precision=abi.RB_PREC_BF16, d_min=cfg.d_min,
+                        sw_lo=cfg.d_cut - 1.0, sw_hi=cfg.d_cut, sym=True)
+    out["symmetry_reduced"] = {"descriptor": "(p_x, p_y, p_z, w_y, w_z, cos 4 a3, sin 4 a3)", "train_s": surs["train_s"],
+                               "held_out": surs["trained"]}
+    models = {"nn_md": model, "nn_md_fm": model_fm, "nn_md_sym": model_sym}
     out["dynamics"] = compare(cfg, st, models, chunks=8, replays=25, log=log)
     # the paper's ensemble: Nose-Hoover NVT at the same temperature
     nvt = dict(kT=cfg.kT, tau=0.5)

@@ -258,11 +258,150 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
 constexpr int kWideGroups = 3;
 constexpr int kWideThreads = kWideGroups * kWideGroup * kWave;
 
+// Inputs of one lane's row of a tile: the network input, the backward seed
+// (the switch for dynamics, dL/dE for gradients) and, for the lanes that
+// run the forces epilogue, that epilogue's per-pair inputs.
+struct TileIn {
+    int64_t row, pid;
+    bool live;
+    float u[kIn];
+    float seed;
+    EpiIn ein;
+};
+
+template <int MODE>
+__device__ inline TileIn tile_in(const NNArgs &a, int64_t row, int64_t count, bool epi) {
+    TileIn t;
+    t.row = row;
+    t.live = row < count;
+    t.pid = row;
+    if (MODE == kForces && t.live && a.idx) t.pid = a.idx[row];
+    net_input(a, row, t.pid, t.live, t.u);
+    t.seed = 1.f;
+    if (MODE == kGrad && a.gE) t.seed = t.live ? a.gE[t.pid] : 0.f;
+    if (MODE == kForces) {
+        float dsdr;
+        t.seed = smooth_switch(sqrtf(t.u[0] * t.u[0] + t.u[1] * t.u[1] + t.u[2] * t.u[2]), a.sw_lo, a.sw_hi, dsdr);
+        t.ein = load_epi(a, t.pid, t.live && epi);
+    }
+    return t;
+}
+
+// Per-pair outputs of the gradient mode: energy, dE/du and the pair's
+// body-frame force and torques.
+__device__ inline void store_grad(const NNArgs &a, const TileIn &t, const float gu[kIn], float E) {
+    const int64_t pid = t.pid;
+    if (a.energy) a.energy[pid] = E;
+    if (a.dEdu)
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) a.dEdu[k * a.P + pid] = gu[k];
+    if (a.ft) {
+        float ft[9], ud[kIn];
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) ud[k] = a.sym ? a.desc[k * a.stride + pid] : t.u[k];
+        pair_ft_from_grad(ud, gu, ft);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) a.ft[k * a.P + pid] = ft[k];
+    }
+}
+
+// Per-pair inputs of a group's forces epilogue, held in LDS across the tile
+// (16 pairs): the pair's bodies, body i's orientation and the pair's (d, q).
+struct EpiLds {
+    double q[4][kTile];
+    float d[kIn][kTile];
+    int i[kTile], j[kTile];
+};
+
+// u: the network input, which is the pair's (d, q) unless the network sees
+// the symmetry-reduced form (then (d, q) is read here).
+__device__ inline void put_epi(const NNArgs &a, EpiLds &e, const EpiIn &in, const float u[kIn], int64_t pid,
+                               bool live, int n) {
+    e.i[n] = in.i;
+    e.j[n] = in.j;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) e.q[c][n] = in.q[c];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) e.d[k][n] = a.sym && live ? a.desc[k * a.stride + pid] : u[k];
+}
+
+// Forces epilogue of the four-wave form: the group's 16 pairs are shared
+// out over its waves by quantity, so each lane converts and adds three
+// values.  Lanes g = 0 of wave v add, to the lab-frame accumulators, the
+// force on j (v = 0), the force on i (v = 1), the torque on i (v = 2) or the
+// torque on j (v = 3); in wave 0 lane group g adds the energy (g = 0) or
+// row g - 1 of the pair virial d (x) F_j, summed over the 16 pairs into the
+// wave's LDS sums.  Same values as forces_epilogue (fixed-point sums are
+// exact and order-free).
+__device__ inline void forces_epilogue_wide(const NNArgs &a, const EpiLds &e, const float gu_in[kIn], float E,
+                                            bool live, int v, int g, int n, long long *wsum, bool &bad) {
+    long long ev[3] = {0, 0, 0};
+    if (live && (g == 0 || v == 0)) {
+        float u[kIn], gu[kIn];
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) {
+            u[k] = e.d[k][n];
+            gu[k] = gu_in[k];
+        }
+        const float r = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        float dsdr;
+        const float S = smooth_switch(r, a.sw_lo, a.sw_hi, dsdr);
+        if (dsdr != 0.f) {
+            const float c = E * dsdr / r;
+            gu[0] = fmaf(c, u[0], gu[0]);
+            gu[1] = fmaf(c, u[1], gu[1]);
+            gu[2] = fmaf(c, u[2], gu[2]);
+        }
+        const float Es = S * E;
+        float ft[9];
+        pair_ft_from_grad(u, gu, ft);
+        // this wave's body-frame vector (v is uniform over the wave)
+        const float f0 = v < 2 ? ft[0] : (v == 2 ? ft[3] : ft[6]);
+        const float f1 = v < 2 ? ft[1] : (v == 2 ? ft[4] : ft[7]);
+        const float f2 = v < 2 ? ft[2] : (v == 2 ? ft[5] : ft[8]);
+        double R[9];
+        quat_to_rot<double>(e.q[0][n], e.q[1][n], e.q[2][n], e.q[3][n], R);
+        double V[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) V[c] = R[3 * c] * f0 + R[3 * c + 1] * f1 + R[3 * c + 2] * f2;
+        if (g == 0) {
+            const int64_t nn = a.n;
+            const int64_t body = (v == 1 || v == 2) ? e.i[n] : e.j[n];
+            const int64_t row0 = v < 2 ? 0 : 3;
+            const double sgn = v == 1 ? -1.0 : 1.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc_add(a.acc + (row0 + c) * nn + body, sgn * V[c]);
+            if (!isfinite(f0) || (v == 0 && !isfinite(Es))) bad = true;
+            if (v == 0) ev[0] = to_fixed(Es);
+        } else {
+            // virial row c = g - 1: (R d)_c * F_j
+            const int c = g - 1;
+            const double r0 = c == 0 ? R[0] : (c == 1 ? R[3] : R[6]);
+            const double r1 = c == 0 ? R[1] : (c == 1 ? R[4] : R[7]);
+            const double r2 = c == 0 ? R[2] : (c == 1 ? R[5] : R[8]);
+            const double dl = r0 * u[0] + r1 * u[1] + r2 * u[2];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) ev[b] = to_fixed(dl * V[b]);
+        }
+    }
+    if (v != 0) return;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        long long s = ev[b];
+        s += __shfl_xor(s, 1, kWave);
+        s += __shfl_xor(s, 2, kWave);
+        s += __shfl_xor(s, 4, kWave);
+        s += __shfl_xor(s, 8, kWave);
+        if (n == 0 && (g > 0 || b == 0)) wsum[g == 0 ? 0 : 1 + 3 * (g - 1) + b] += s;
+    }
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
     __shared__ LdsBF16 L;
     __shared__ WideX X[kWideGroups];
     __shared__ long long wacc[kWideGroups * kWideGroup][10];
+    __shared__ EpiLds EL[MODE == kForces ? kWideGroups : 1];
     int64_t count = a.P;
     if (MODE == kForces) {
         const int64_t c = *a.count_dev;
@@ -273,53 +412,44 @@ __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
     // the grid is sized for the capacity; blocks without a tile leave before
     // staging the weights
     if ((int64_t)blockIdx.x * kWideGroups >= ntiles) return;
-    stage_bf16<kWideThreads>(L, a.params);
     const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, n = lane & 15;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int grp = wave / kWideGroup, v = wave % kWideGroup;
+    // the first tile's inputs are requested before the weights are staged,
+    // so that their latency overlaps the staging
+    int64_t base = (int64_t)blockIdx.x * kWideGroups;
+    TileIn t = tile_in<MODE>(a, (base + grp) * kTile + n, count, g == 0 && v == 0);
+    stage_bf16<kWideThreads>(L, a.params);
     if (MODE == kForces && lane < 10) wacc[wave][lane] = 0;
-    __syncthreads();
     bool bad = false;
-    for (int64_t base = (int64_t)blockIdx.x * kWideGroups; base < ntiles;
-         base += (int64_t)gridDim.x * kWideGroups) {
-        const int64_t row = (base + grp) * kTile + n;
-        const bool live = row < count;
-        int64_t pid = row;
-        if (MODE == kForces && live && a.idx) pid = a.idx[row];
-        float u[kIn];
-        net_input(a, row, pid, live, u);
-        float seed = 1.f;
-        if (MODE == kGrad && a.gE) seed = live ? a.gE[pid] : 0.f;
-        if (MODE == kForces) {
-            float dsdr;
-            seed = smooth_switch(sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]), a.sw_lo, a.sw_hi, dsdr);
-        }
-        EpiIn ein;
-        if (MODE == kForces) ein = load_epi(a, pid, live && g == 0 && v == 0);
+    for (;;) {
+        if (MODE == kForces && v == 0 && g == 0) put_epi(a, EL[grp], t.ein, t.u, t.pid, t.live, n);
+        __syncthreads();
         float gu[kIn];
-        const float E = tile_bf16_wide<true>(L, X[grp], a.nm, u, seed, gu, v);
-        if (v != 0) continue;   // the group's results are the same in its four waves
-        if (live && g == 0) sym_chain(a, row, gu);
+        const float E = tile_bf16_wide<true>(L, X[grp], a.nm, t.u, t.seed, gu, v);
+        // the group's results are the same in its four waves
         if (MODE == kForces) {
-            forces_epilogue(a, ein, gu, E, pid, live && g == 0, lane, wacc[wave], bad);
-        } else if (live && g == 0) {
-            if (a.energy) a.energy[pid] = E;
-            if (a.dEdu)
+            if (a.jac) {
+                // dE/du = J^T dE/ds once per pair, shared through LDS
+                if (v == 0 && g == 0 && t.live) {
+                    sym_chain(a, t.row, gu);
 #pragma unroll
-                for (int k = 0; k < kIn; ++k) a.dEdu[k * a.P + pid] = gu[k];
-            if (a.ft) {
-                float ft[9], ud[kIn];
-                if (a.sym)
+                    for (int k = 0; k < kIn; ++k) X[grp].red[0][1 + k][n] = gu[k];
+                }
+                __syncthreads();
 #pragma unroll
-                    for (int k = 0; k < kIn; ++k) ud[k] = a.desc[k * a.stride + pid];
-                else
-#pragma unroll
-                    for (int k = 0; k < kIn; ++k) ud[k] = u[k];
-                pair_ft_from_grad(ud, gu, ft);
-#pragma unroll
-                for (int k = 0; k < 9; ++k) a.ft[k * a.P + pid] = ft[k];
+                for (int k = 0; k < kIn; ++k) gu[k] = X[grp].red[0][1 + k][n];
             }
+            forces_epilogue_wide(a, EL[grp], gu, E, t.live, v, g, n, wacc[wave], bad);
+        } else if (v == 0 && t.live && g == 0) {
+            sym_chain(a, t.row, gu);
+            store_grad(a, t, gu, E);
         }
+        base += (int64_t)gridDim.x * kWideGroups;
+        if (base >= ntiles) break;
+        t = tile_in<MODE>(a, (base + grp) * kTile + n, count, g == 0 && v == 0);
+        // the previous tile's epilogue has read its inputs from LDS
+        __syncthreads();
     }
     if (MODE == kForces) {
         long long part[11];

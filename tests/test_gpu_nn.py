@@ -161,11 +161,14 @@ def test_routing_window_and_pair_configurations(abi):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_md_forces_nn_plus_bead_fallback_match_oracle(abi, prec):
+@pytest.mark.parametrize("cfgname", ["config1", "config2"])
+def test_md_forces_nn_plus_bead_fallback_match_oracle(abi, prec, cfgname):
     # per-body forces of the mixed path: network for |d| >= d_min (with the
-    # energy switch), bead sum below, against the oracle doing the same
+    # energy switch), bead sum below, against the oracle doing the same; the
+    # 4096-cube system is the launch the benchmark times (about 9.5k network
+    # pairs, 600 tiles)
     from paper_2402_12199_amd.md import NNModel, RigidSystem
-    cfg = configs.config1()
+    cfg = getattr(configs, cfgname)()
     st = state.initial_state(cfg)
     b = cfg.body
     params, norm, _ = _setup(1)
@@ -195,14 +198,14 @@ def test_md_forces_nn_plus_bead_fallback_match_oracle(abi, prec):
     g = g * S[:, None]
     g[:, :3] += (Ep * dS / r)[:, None] * u[:, :3]
     ft = oframes.to_lab(q[pairs[:, 0]], oframes.forces_from_grad(u, g))
+    pi, pj = pairs[nnm, 0], pairs[nnm, 1]
+    E += np.sum(S[nnm] * Ep[nnm])
+    np.add.at(F, pi, -ft[nnm, :3])
+    np.add.at(F, pj, ft[nnm, :3])
+    np.add.at(T, pi, ft[nnm, 3:6])
+    np.add.at(T, pj, ft[nnm, 6:])
     for k, (i, j) in enumerate(pairs):
-        if nnm[k]:
-            E += S[k] * Ep[k]
-            F[i] -= ft[k, :3]
-            F[j] += ft[k, :3]
-            T[i] += ft[k, 3:6]
-            T[j] += ft[k, 6:]
-        else:
+        if not nnm[k]:
             o = obeads.bead_pair(b.beads, b.beads, x[i], q[i], x[j], q[j], box=cfg.box)
             E += o["E"]
             F[i] += o["Fi"]
@@ -214,3 +217,64 @@ def test_md_forces_nn_plus_bead_fallback_match_oracle(abi, prec):
     assert sysm.energy() == pytest.approx(E, rel=max(etol, 1e-5))
     assert_close(sysm.force.cpu().numpy().T, F, max(gtol, 1e-4), "force")
     assert_close(sysm.torque.cpu().numpy().T, T, max(gtol, 1e-4), "torque")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("count", [0, 1, 17, 48, 49, 130])
+def test_nn_pair_forces_ragged_counts_match_oracle(abi, prec, count):
+    # the dynamics forces kernel at tile- and block-ragged list lengths (16
+    # pairs per tile, three tiles per block in BF16), through an index list,
+    # with the count read on the device and clipped at the capacity (120)
+    g = sampling.rng(2024)
+    n, P, cap = 40, 160, 120
+    params, norm, _ = _setup(1, seed=11)
+    q = g.normal(size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    pi = g.integers(0, n, P).astype(np.int32)
+    pj = ((pi + 1 + g.integers(0, n - 1, P)) % n).astype(np.int32)
+    desc = sampling.pair_batch(g, P, 4.2, 11.138).astype(np.float32)
+    idx = g.permutation(P)[:cap].astype(np.int32)
+    sw_lo, sw_hi = 10.0, 11.138
+    acc = torch.zeros(abi.acc_len(n), dtype=torch.int64, device="cuda")
+    flags = torch.zeros(abi.RB_NFLAGS, dtype=torch.int32, device="cuda")
+    cnt = torch.tensor([count], dtype=torch.int32, device="cuda")
+    abi.rb_nn_pair_forces(_dev(params), norm.as_array(), prec, _dev(q.T), _dev(pi), _dev(pj), _dev(desc.T),
+                          _dev(idx), cnt, cap, sw_lo, sw_hi, acc, flags)
+    force = torch.zeros((3, n), dtype=torch.float32, device="cuda")
+    torque = torch.zeros((3, n), dtype=torch.float32, device="cuda")
+    ev = torch.zeros(10, dtype=torch.float64, device="cuda")
+    abi.rb_accum_finalize(n, acc, force, torque, ev)
+    m = min(count, cap)
+    assert int(flags[abi.RB_FLAG_NEVAL].item()) == m
+    rows = idx[:m]
+    u = desc[rows].astype(np.float64)
+    F = np.zeros((n, 3))
+    T = np.zeros((n, 3))
+    W = np.zeros((3, 3))
+    E = 0.0
+    if m:
+        r = np.linalg.norm(u[:, :3], axis=1)
+        Ep, gr = omlp.input_grad(_net(params, prec), u, norm)
+        t = np.clip((r - sw_lo) / (sw_hi - sw_lo), 0, 1)
+        S = 1 - t * t * (3 - 2 * t)
+        dS = np.where((r > sw_lo) & (r < sw_hi), -6 * t * (1 - t) / (sw_hi - sw_lo), 0.0)
+        gr = gr * S[:, None]
+        gr[:, :3] += (Ep * dS / r)[:, None] * u[:, :3]
+        qi = q[pi[rows]]
+        ft = oframes.to_lab(qi, oframes.forces_from_grad(u, gr))
+        np.add.at(F, pi[rows], -ft[:, :3])
+        np.add.at(F, pj[rows], ft[:, :3])
+        np.add.at(T, pi[rows], ft[:, 3:6])
+        np.add.at(T, pj[rows], ft[:, 6:])
+        E = float(np.sum(S * Ep))
+        dl = oframes.qrotate(qi, u[:, :3])
+        W = dl.T @ ft[:, :3]
+    etol, gtol = RTOL[prec]
+    got_ev = ev.cpu().numpy()
+    if m == 0:
+        assert not acc.any() and not force.any() and not torque.any() and not got_ev.any()
+        return
+    assert got_ev[0] == pytest.approx(E, rel=max(etol, 1e-5))
+    assert_close(force.cpu().numpy().T, F, max(gtol, 1e-4), "force")
+    assert_close(torque.cpu().numpy().T, T, max(gtol, 1e-4), "torque")
+    assert_close(got_ev[1:].reshape(3, 3), W, max(gtol, 1e-4), "virial")

@@ -365,33 +365,44 @@ __global__ __launch_bounds__(512) void k_train_wgrad(TrainArgs a) {
     }
 }
 
+// Sum of n partials base[c * stride], c = 0 .. n - 1, added in order c = 0,
+// 1, ...; the loads are issued 32 (then 4) at a time so that at most a few
+// memory round trips are paid.
+__device__ inline float ordered_sum(const float *__restrict__ base, int n, int64_t stride) {
+    float s = 0.f;
+    int c = 0;
+    for (; c + 32 <= n; c += 32) {
+        float v[32];
+#pragma unroll
+        for (int k = 0; k < 32; ++k) v[k] = base[(int64_t)(c + k) * stride];
+#pragma unroll
+        for (int k = 0; k < 32; ++k) s += v[k];
+    }
+    for (; c + 4 <= n; c += 4) {
+        float v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = base[(int64_t)(c + k) * stride];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s += v[k];
+    }
+    for (; c < n; ++c) s += base[(int64_t)c * stride];
+    return s;
+}
+
 __global__ void k_adam(float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
                        const float *__restrict__ part, int nchunks, float lr, float b1, float b2, float eps, float c1,
                        float c2, float invB, float *__restrict__ loss, float *__restrict__ grad_out,
                        const float *__restrict__ fmpart, int nfm) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
-        float s = 0.f;
-        for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * kPart + NPARAMS];
-        loss[0] = s * invB;
-        if (fmpart) {
-            float f = 0.f;
-            for (int c = 0; c < nfm; ++c) f += fmpart[c];
-            loss[1] = f;
-        }
+    // the losses are summed by one thread of the last block (the one with
+    // the fewest parameters)
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1) {
+        loss[0] = ordered_sum(part + NPARAMS, nchunks, kPart) * invB;
+        if (fmpart) loss[1] = ordered_sum(fmpart, nfm, 1);
     }
     if (i >= NPARAMS) return;
-    // chunk partials summed in chunk order; eight loads in flight at a time
-    float g = 0.f;
-    int c = 0;
-    for (; c + 8 <= nchunks; c += 8) {
-        float v8[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) v8[k] = part[(int64_t)(c + k) * kPart + i];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) g += v8[k];
-    }
-    for (; c < nchunks; ++c) g += part[(int64_t)c * kPart + i];
+    // chunk partials summed in chunk order
+    const float g = ordered_sum(part + i, nchunks, kPart);
     if (grad_out) grad_out[i] = g;
     const float mi = fmaf(b1, m[i], (1.f - b1) * g);
     const float vi = fmaf(b2, v[i], (1.f - b2) * g * g);

@@ -417,6 +417,14 @@ __global__ __launch_bounds__(256) void k_bead_screen(Templates T, float rcm, int
     __shared__ bool last;
     int count = *count_dev;
     if (count > max_count) count = max_count;
+    // the grid is sized for the capacity: only the blocks that own pairs take
+    // part (and take a finishing ticket)
+    const int nb = min((int)gridDim.x, (count + (int)blockDim.x - 1) / (int)blockDim.x);
+    if (count == 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *count_out = 0;
+        return;
+    }
+    if ((int)blockIdx.x >= nb) return;
     const int lane = threadIdx.x & (kWave - 1);
     for (int base = blockIdx.x * blockDim.x; base < count; base += gridDim.x * blockDim.x) {
         const int p = base + threadIdx.x;
@@ -441,7 +449,7 @@ __global__ __launch_bounds__(256) void k_bead_screen(Templates T, float rcm, int
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
-        last = atomicAdd(tmp + 1, 1) == (int)gridDim.x - 1;
+        last = atomicAdd(tmp + 1, 1) == nb - 1;
     }
     __syncthreads();
     if (last && threadIdx.x == 0) {

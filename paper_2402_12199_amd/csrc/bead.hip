@@ -467,8 +467,11 @@ __global__ __launch_bounds__(256) void k_bead_screen(Templates T, float rcm, int
 // FP64 geometry and the separating-axis test run for the round at once (one
 // round of memory latency); the pairs that can interact go, with their
 // geometry, to an LDS queue from which the block's waves take them one at a
-// time, each evaluated by a whole wave.  The pair's outputs are rotated to
-// the lab frame and added to the fixed-point accumulator.
+// time, each evaluated by a whole wave.  Two queues alternate, so that the
+// first wave screens the next round while the block drains the current one
+// (and the first round while the other waves copy the templates).  The
+// pair's outputs are rotated to the lab frame and added to the fixed-point
+// accumulator.
 //
 // Two-level form (SCREENED): the list of body pairs (built with a skin on
 // the centre distance) is screened once more with the separating-axis test
@@ -577,12 +580,18 @@ __global__ __launch_bounds__(kMdWaves * kWave) __attribute__((amdgpu_waves_per_e
                                                  int stride, ScreenArgs S) {
     extern __shared__ float4 bead_lds[];
     __shared__ long long wacc[kMdWaves][10];   // per-wave energy/virial sums (fixed point)
-    __shared__ PairQueue Q;
+    __shared__ PairQueue Qs[2];                // this round's queue and the next round's
+    static_assert(kMdWaves > 1, "wave 0 screens while the others copy the templates");
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     WaveLds L = wave_lds(bead_lds, w, stride);
     if (lane < 10) wacc[w][lane] = 0;
-    const float4 *tb = stage_templates(T, bead_lds, kMdWaves, stride);
+    // the templates are copied by waves 1.. while wave 0 screens the first
+    // round; one barrier publishes both
+    float4 *tbw = bead_lds + (size_t)kMdWaves * 3 * stride;
+    if (w != 0)
+        for (int k = threadIdx.x - kWave; k < T.total; k += blockDim.x - kWave) tbw[k] = T.beads[k];
+    const float4 *tb = tbw;
     const float rcm = sqrtf(lj.rc2) + kCullMargin, cut2 = rcm * rcm;
     int count = *count_dev;
     if (count > max_count) count = max_count;
@@ -600,64 +609,75 @@ __global__ __launch_bounds__(kMdWaves * kWave) __attribute__((amdgpu_waves_per_e
         if (npass > count) npass = count;
         core = min(S.tmp[3], npass);
     }
-    {
+    if (SCREENED && full) {
+        for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < n; b += G * blockDim.x) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) S.x_ref[a * n + b] = x[a * n + b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) S.q_ref[a * n + b] = q[a * n + b];
+        }
+    }
+    // Screening of the round starting at p0 into Q (wave 0 only): one lane
+    // per pair, the pairs that can interact go to the queue with their
+    // geometry.
+    auto screen = [&](int p0, PairQueue &Q) {
+        const int p = p0 + lane * G;
+        bool hit = false, wide = false;
+        int pid = 0, i = 0, j = 0, ti = 0, tj = 0;
+        double dl[3], d[3], qr[4], qa[4];
+        if (p < npass) {
+            if (SCREENED && !full)
+                pid = p < core ? S.list[p] : S.list[max_count - 1 - (p - core)];
+            else
+                pid = idx ? idx[p] : p;
+            i = pi[pid];
+            j = pj[pid];
+            ti = type[i];
+            tj = type[j];
+            double R[9], Ri[9];
+            pair_frame(n, x, q, box, i, j, dl, d, qr, qa, Ri);
+            quat_to_rot<double>(qr[0], qr[1], qr[2], qr[3], R);
+            hit = may_interact(T, ti, tj, d, R, rcm);
+            if (SCREENED && full) wide = hit || may_interact(T, ti, tj, d, R, S.rcm_wide);
+        }
         if (SCREENED && full) {
-            for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < n; b += G * blockDim.x) {
+            list_append(hit, pid, S.tmp, S.list, max_count, false, lane);
+            list_append(wide && !hit, pid, S.tmp + 1, S.list, max_count, true, lane);
+        }
+        const unsigned long long m = __ballot(hit);
+        if (hit) {
+            const int at = __popcll(m & ((1ull << lane) - 1ull));
+            Q.i[at] = i;
+            Q.j[at] = j;
+            Q.ti[at] = ti;
+            Q.tj[at] = tj;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) S.x_ref[a * n + b] = x[a * n + b];
+            for (int a = 0; a < 3; ++a) {
+                Q.dl[a][at] = dl[a];
+                Q.d[a][at] = d[a];
+            }
 #pragma unroll
-                for (int a = 0; a < 4; ++a) S.q_ref[a * n + b] = q[a * n + b];
+            for (int a = 0; a < 4; ++a) {
+                Q.qr[a][at] = qr[a];
+                Q.qa[a][at] = qa[a];
             }
         }
-        for (int p0 = blockIdx.x; p0 < npass; p0 += G * kRound) {
-            if (w == 0) {
-                const int p = p0 + lane * G;
-                bool hit = false, wide = false;
-                int pid = 0, i = 0, j = 0, ti = 0, tj = 0;
-                double dl[3], d[3], qr[4], qa[4];
-                if (p < npass) {
-                    if (SCREENED && !full)
-                        pid = p < core ? S.list[p] : S.list[max_count - 1 - (p - core)];
-                    else
-                        pid = idx ? idx[p] : p;
-                    i = pi[pid];
-                    j = pj[pid];
-                    ti = type[i];
-                    tj = type[j];
-                    double R[9], Ri[9];
-                    pair_frame(n, x, q, box, i, j, dl, d, qr, qa, Ri);
-                    quat_to_rot<double>(qr[0], qr[1], qr[2], qr[3], R);
-                    hit = may_interact(T, ti, tj, d, R, rcm);
-                    if (SCREENED && full) wide = hit || may_interact(T, ti, tj, d, R, S.rcm_wide);
-                }
-                if (SCREENED && full) {
-                    list_append(hit, pid, S.tmp, S.list, max_count, false, lane);
-                    list_append(wide && !hit, pid, S.tmp + 1, S.list, max_count, true, lane);
-                }
-                const unsigned long long m = __ballot(hit);
-                if (hit) {
-                    const int at = __popcll(m & ((1ull << lane) - 1ull));
-                    Q.i[at] = i;
-                    Q.j[at] = j;
-                    Q.ti[at] = ti;
-                    Q.tj[at] = tj;
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        Q.dl[a][at] = dl[a];
-                        Q.d[a][at] = d[a];
-                    }
-#pragma unroll
-                    for (int a = 0; a < 4; ++a) {
-                        Q.qr[a][at] = qr[a];
-                        Q.qa[a][at] = qa[a];
-                    }
-                }
-                if (lane == 0) {
-                    Q.n = __popcll(m);
-                    Q.head = 0;
-                }
-            }
-            __syncthreads();
+        if (lane == 0) {
+            Q.n = __popcll(m);
+            Q.head = 0;
+        }
+    };
+    // Rounds: wave 0 screens round r + 1 into the other queue while the
+    // block drains round r (wave 0 joins when done); the barrier at the end
+    // of a round orders the drained queue's reuse after every read of it.
+    int p0 = blockIdx.x;
+    if (w == 0 && p0 < npass) screen(p0, Qs[0]);
+    __syncthreads();
+    for (int r = 0; p0 < npass; p0 += G * kRound, ++r) {
+        PairQueue &Q = Qs[r & 1];
+        const int pn = p0 + G * kRound;
+        if (w == 0 && pn < npass) screen(pn, Qs[(r + 1) & 1]);
+        {
             const int nq = Q.n;
             for (;;) {
                 int k = 0;
@@ -675,8 +695,8 @@ __global__ __launch_bounds__(kMdWaves * kWave) __attribute__((amdgpu_waves_per_e
                 md_pair<POT>(T, lj, tb, L, lane, cut2, n, Q.i[k], Q.j[k], Q.ti[k], Q.tj[k], dl, d, R, Ri, acc, wacc[w],
                              ntests, bad);
             }
-            __syncthreads();   // the queue is refilled by the next round
         }
+        __syncthreads();
     }
     long long part[11];
 #pragma unroll
@@ -791,7 +811,7 @@ static int launch_bead_md(const rb_ctx *ctx, int32_t n, const double *x, const d
     }
     int stride;
     const size_t lds = bead_lds_bytes(ctx, kMdWaves, stride);
-    RB_REQUIRE(lds + sizeof(PairQueue) + 1024 <= device_max_lds(),
+    RB_REQUIRE(lds + 2 * sizeof(PairQueue) + 1024 <= device_max_lds(),
                "%s: templates need %zu bytes of LDS per block (device max %zu)", who, lds, device_max_lds());
     const bool hphc = ctx->dev.lj.kind == kPotHPHC;
     auto kern = hphc ? k_bead_md<kPotHPHC, SCREENED> : k_bead_md<kPotLJ, SCREENED>;

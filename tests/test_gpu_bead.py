@@ -236,6 +236,33 @@ def test_bead_screen_drops_only_zero_pairs(abi, cfgname):
             assert r["E"] == 0.0
 
 
+def test_bead_screen_empty_and_short_lists(abi):
+    # an empty list publishes a zero count without touching the scratch; a
+    # list shorter than one workgroup is screened by a single workgroup
+    cfg = configs.config1()
+    sysm, _ = _system(abi, cfg)
+    sysm.build_pairs(always=True)
+    zero = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = torch.full((1,), 77, dtype=torch.int32, device="cuda")
+    e0 = int(sysm.flags_host()[abi.RB_FLAG_NEVAL])
+    abi.rb_bead_screen(sysm.ctx, sysm.x, sysm.q, sysm.types, sysm.box, sysm.pair_i, sysm.pair_j, None, zero,
+                       sysm.max_pairs, sysm.idx_screen, out, sysm.tmp_screen, sysm.flags)
+    torch.cuda.synchronize()
+    assert int(out.item()) == 0 and not torch.any(sysm.tmp_screen)
+    assert int(sysm.flags_host()[abi.RB_FLAG_NEVAL]) == e0
+    for m in (1, 5, 63):
+        cnt = torch.tensor([m], dtype=torch.int32, device="cuda")
+        abi.rb_bead_screen(sysm.ctx, sysm.x, sysm.q, sysm.types, sysm.box, sysm.pair_i, sysm.pair_j, None, cnt,
+                           sysm.max_pairs, sysm.idx_screen, out, sysm.tmp_screen, sysm.flags)
+        kept = int(out.item())
+        ids = np.sort(sysm.idx_screen[:kept].cpu().numpy())
+        assert 0 <= kept <= m and len(np.unique(ids)) == kept and (ids < m).all()
+        assert not torch.any(sysm.tmp_screen)
+        e1 = int(sysm.flags_host()[abi.RB_FLAG_NEVAL])
+        assert e1 - e0 == m - kept   # the dropped pairs; the force kernel counts the kept ones
+        e0 = e1
+
+
 @pytest.mark.parametrize("spin", [1.0, 300.0])
 def test_rigid_step_matches_oracle(abi, spin):
     # spin scales the angular momenta: at 300 every sub-step angle is past

@@ -429,6 +429,10 @@ def main():
     st = state.initial_state(cfg)
     sysm = make_system(cfg, st, torch)
     sysm.init_forces("bead")
+    # one eager step first: its integrator pass yields the kinetic energy, so
+    # the total energy is known at the start of the measured trajectory
+    sysm.step(cfg.dt, "bead")
+    e_start = sysm.energy() + float(sysm.kinetic_host().sum())
     torch.cuda.synchronize()
     log(f"[bench] bead path: {args.warmup} warmup + {args.steps} timed steps")
     bead = run_md(sysm, args.steps, args.warmup, cfg.dt, "bead", torch, abi)
@@ -463,7 +467,12 @@ def main():
         "md_steps_per_s": steps_per_s,
         "bead_path": {"pairs_evaluated": bead["pairs_evaluated"], "rebuilds": bead["rebuilds"],
                       "gpu_ms_per_step": bead["gpu_ms"] / nsteps, "graph_steps": GRAPH_STEPS,
-                      "eager_ms_per_step": bead["eager_ms_per_step"], "total_energy_end": e_tot},
+                      "eager_ms_per_step": bead["eager_ms_per_step"],
+                      "total_energy_start": e_start, "total_energy_end": e_tot,
+                      "energy_drift_per_body": (e_tot - e_start) / sysm.n,
+                      # the first eager step, the warm-up, one untimed graph replay, the
+                      # timed steps and the eager steps timed after them
+                      "drift_over_steps": 1 + args.warmup + GRAPH_STEPS + nsteps + 5 * GRAPH_STEPS},
         "roofline": {"kernel": "k_bead_md (rb_bead_pair_forces)", "bound": "alu", "achieved": achieved / 1e12,
                      "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK,
                      "traffic": bead_traffic(), "traffic_unit": "bytes per launch", "kernel_ms": kern_ms,

@@ -291,6 +291,7 @@ __device__ inline void pair_sum(const LJ &lj, int ni, int nj, const WaveLds &L, 
         const bool kv = k < ni;
         const float4 b = kv ? L.i[k] : make_float4(1.0e4f, 1.0e4f, 1.0e4f, 0.f);
         float fx = 0.f, fy = 0.f, fz = 0.f;
+#pragma unroll 2
         for (int l = g; l < nj; l += G) {
             const float4 p = L.j[l];
             const float4 lo = L.jlo[l];

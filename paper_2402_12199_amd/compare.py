@@ -39,7 +39,7 @@ def run_dynamics(cfg, st, path: str, nn: NNModel | None = None, chunks: int = 8,
     snaps, energies, times, steps_done, graph = [], [e0], [], 0, None
     f_prev = sysm.flags_host()
     eval0 = int(f_prev[abi.RB_FLAG_NEVAL])
-    timed_steps, fallback_max, error = 0, 0, None
+    timed_steps, fallback_max, error, first = 0, 0, None, None
     for c in range(chunks):
         if nvt is None:
             sysm.begin_fused(cfg.dt)
@@ -61,6 +61,12 @@ def run_dynamics(cfg, st, path: str, nn: NNModel | None = None, chunks: int = 8,
         steps_done += replays * GRAPH_STEPS + 1
         f = sysm.flags_host()
         fallback_max = max(fallback_max, int(f[abi.RB_FLAG_NBEAD])) if path == "nn" else 0
+        if c == 0:
+            # the first chunk alone: the path's speed before a learned
+            # trajectory can drift into rebuild-heavy or unphysical states
+            first = dict(steps=replays * GRAPH_STEPS, steps_per_s=replays * GRAPH_STEPS / (1e-3 * times[0]),
+                         rebuilds=int(f[abi.RB_FLAG_NREBUILDS] - f_prev[abi.RB_FLAG_NREBUILDS]),
+                         fallback=fallback_max, finite=not (f[abi.RB_FLAG_OVERFLOW] or f[abi.RB_FLAG_NONFINITE]))
         if f[abi.RB_FLAG_OVERFLOW] or f[abi.RB_FLAG_NONFINITE]:
             error = "pair list overflow" if f[abi.RB_FLAG_OVERFLOW] else "non-finite force or energy"
             break
@@ -78,7 +84,7 @@ def run_dynamics(cfg, st, path: str, nn: NNModel | None = None, chunks: int = 8,
     return dict(path=path, temperature_last=temperature, steps=steps_done, timed_steps=timed_steps, timed_gpu_s=gpu_s,
                 steps_per_s=timed_steps / gpu_s if gpu_s > 0 else None,
                 pair_evals_per_step=n_eval / max(steps_done, 1), energies=energies, x0=x0, q0=q0, snaps=snaps,
-                rebuilds=int(f[abi.RB_FLAG_NREBUILDS]), fallback_max=fallback_max, error=error)
+                rebuilds=int(f[abi.RB_FLAG_NREBUILDS]), fallback_max=fallback_max, error=error, first_chunk=first)
 
 
 def observables(cfg, run: dict, rdf_bins: int = 80) -> dict:
@@ -107,7 +113,7 @@ def compare(cfg, st, models: dict, chunks: int = 8, replays: int = 25, log=None,
     for p in runs:
         r, o = runs[p], obs[p]
         out[p] = {k: r[k] for k in ("path", "steps", "timed_steps", "steps_per_s", "pair_evals_per_step", "rebuilds",
-                                    "fallback_max", "error", "temperature_last")}
+                                    "fallback_max", "error", "temperature_last", "first_chunk")}
         if o:
             out[p].update(p2=o["p2"], msd_last=o["msd"][-1][1], msr_last=o["msr"][-1][1],
                           drift_per_body=o["drift_per_body"],
@@ -123,4 +129,7 @@ def compare(cfg, st, models: dict, chunks: int = 8, replays: int = 25, log=None,
             out[p]["msr_ratio_vs_bead"] = o["msr"][-1][1] / rb if rb > 0 else None
         if out["bead"]["steps_per_s"] and out[p]["steps_per_s"]:
             out[p]["speedup_steps_vs_bead"] = out[p]["steps_per_s"] / out["bead"]["steps_per_s"]
+        fb, fp = out["bead"].get("first_chunk"), out[p].get("first_chunk")
+        if fb and fp:
+            out[p]["first_chunk_speedup_vs_bead"] = fp["steps_per_s"] / fb["steps_per_s"]
     return out

@@ -155,6 +155,24 @@ __device__ inline void layer1(const float (*w1)[8], const float *b1, const float
 }
 
 
+// Layer 1 on the FP32 matrix cores (v_mfma_f32_16x16x4_f32, the 7 inputs
+// padded to 8 in two k-steps): pre-activations of rows 16 mt + 4 g + r
+// (r = 0..3) for the tile's pair n.  A = W1 rows 16 mt .. + 15 (lane: row n,
+// column 4 s + g), B = the normalised inputs (lane: input 4 s + g of pair
+// n; l1_inputs picks them), C starts from the bias.  The padding column of
+// W1 in LDS is zero.
+__device__ inline void l1_inputs(const float un[kIn], int g, float &x0, float &x1) {
+    x0 = g == 0 ? un[0] : (g == 1 ? un[1] : (g == 2 ? un[2] : un[3]));
+    x1 = g == 0 ? un[4] : (g == 1 ? un[5] : (g == 2 ? un[6] : 0.f));
+}
+
+__device__ inline f32x4 layer1_rows(const float (*w1)[8], const float *b1, float x0, float x1, int n, int g, int mt) {
+    f32x4 c = *reinterpret_cast<const f32x4 *>(&b1[16 * mt + 4 * g]);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(w1[16 * mt + n][g], x0, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(w1[16 * mt + n][4 + g], x1, c, 0, 0, 0);
+    return c;
+}
+
 // FP16 packing of the SiLU derivatives kept for the reverse pass (values in
 // [-0.1, 1.1]; FP16 keeps 11 significant bits against BF16's 8).
 __device__ inline f16x8 pack8h(const float a[4], const float b[4]) {

@@ -46,7 +46,14 @@ __device__ inline float tile_bf16(const LdsBF16 &L, const Norm &nm, const float 
     f16x8 sp[4][4];
     {
         float hv[8][4], dv[8][4];
-        layer1(L.w1, L.b[0], un, g, hv, dv);
+        float x0, x1;
+        l1_inputs(un, g, x0, x1);
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            const f32x4 z = layer1_rows(L.w1, L.b[0], x0, x1, n, g, mt);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) silu(z[r], hv[mt][r], dv[mt][r]);
+        }
         if (EMIT && em.live)
 #pragma unroll
             for (int mt = 0; mt < 8; ++mt)
@@ -211,20 +218,17 @@ __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &n
     f16x8 spo[4];
     {
         float h[2][4], d[2][4];
+        float x0, x1;
+        l1_inputs(un, g, x0, x1);
 #pragma unroll
-        for (int mm = 0; mm < 2; ++mm)
+        for (int mm = 0; mm < 2; ++mm) {
+            const f32x4 z = layer1_rows(L.w1, L.b[0], x0, x1, n, g, 2 * v + mm);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int f = 32 * v + 16 * mm + 4 * g + r;
-                const float4 wa = *reinterpret_cast<const float4 *>(&L.w1[f][0]);
-                const float4 wb = *reinterpret_cast<const float4 *>(&L.w1[f][4]);
-                float z = L.b[0][f];
-                z = fmaf(wa.x, un[0], z); z = fmaf(wa.y, un[1], z); z = fmaf(wa.z, un[2], z);
-                z = fmaf(wa.w, un[3], z); z = fmaf(wb.x, un[4], z); z = fmaf(wb.y, un[5], z);
-                z = fmaf(wb.z, un[6], z);
-                silu(z, h[mm][r], d[mm][r]);
-                if (EMIT && em.live) em.h(kIn + f) = h[mm][r];
+                silu(z[r], h[mm][r], d[mm][r]);
+                if (EMIT && em.live) em.h(kIn + 32 * v + 16 * mm + 4 * g + r) = h[mm][r];
             }
+        }
         X.a[v][lane] = pack8(h[0], h[1]);
         if (GRAD) spo[0] = pack8h(d[0], d[1]);
     }

@@ -77,7 +77,7 @@ __device__ inline bf16x8 pack8(const float a[4], const float b[4]) {
 }
 
 // LDS image of the weights used by the BF16 kernels.
-struct LdsBF16 {
+struct alignas(16) LdsBF16 {
     __bf16 w[3][kH][kRow];   // W2..W4, columns permuted per 32-block
     float w1[kH][8];          // W1 (7 columns, padded)
     float b[4][kH];           // b1..b4

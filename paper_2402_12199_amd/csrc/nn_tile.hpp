@@ -372,7 +372,7 @@ __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &n
 // Small LDS image for the FP32 path: W1, biases, w5, and per wave the SiLU
 // derivatives of the forward pass (4 layers x 32 values x 64 lanes).
 constexpr int kF32Waves = 4;
-struct LdsFP32 {
+struct alignas(16) LdsFP32 {
     float w1[kH][8];
     float b[4][kH];
     float w5[kH];

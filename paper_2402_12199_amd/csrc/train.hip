@@ -191,8 +191,9 @@ __device__ void wgrad_edge(const TrainArgs &a, int r0, int nr, float *part, floa
 // global loads are in flight during the MFMAs).  Wave w computes the 4 x 2
 // output tiles rows 64 (w / 4) .., columns 32 (w % 4) .., skipping tiles
 // outside ma x nb.
-__device__ void wgrad_gemm_bf16(const float *Ar, int ma, const float *Br, int nb, int64_t B, int r0, int r1,
-                                float *dW, int ldw, float *db, bf16x8 *S) {
+__device__ __attribute__((always_inline)) inline void wgrad_gemm_bf16(const float *Ar, int ma, const float *Br, int nb,
+                                                                    int64_t B, int r0, int r1,
+                                                                    float *dW, int ldw, float *db, bf16x8 *S) {
     const int t = threadIdx.x, f = t >> 2, p = t & 3;
     const bool va = f < ma, vb = f < nb;
     const float *arow = Ar + (int64_t)(va ? f : 0) * B + 8 * p;

@@ -1,11 +1,12 @@
 // Energy network: forward pass, hand-written reverse pass (input gradient),
 // and per-pair or per-body forces and torques from that gradient.
 //
-// BF16 path: layer 1 (7 -> 128) and layer 5 (128 -> 1) in FP32 on the VALU;
-// the three 128 x 128 layers on v_mfma_f32_16x16x32_bf16 with FP32
-// accumulation, weights staged once per block in LDS, activations rounded
-// to BF16 as MFMA operands.  SiLU derivatives of the forward pass are kept
-// in registers (BF16) for the reverse pass.  The reverse pass multiplies by
+// BF16 path: layer 1 (7 -> 128) in FP32 on v_mfma_f32_16x16x4_f32, layer 5
+// (128 -> 1) in FP32 on the VALU; the three 128 x 128 layers on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation, weights staged once per
+// block in a 16-byte aligned LDS image, activations rounded to BF16 as MFMA
+// operands.  SiLU derivatives of the forward pass are kept in registers
+// (FP16) for the reverse pass.  The reverse pass multiplies by
 // W^T: the forward reads a 16-byte row fragment of the LDS weights, the
 // reverse gathers eight 2-byte elements down a column of the same array.
 //

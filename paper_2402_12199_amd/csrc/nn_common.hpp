@@ -76,7 +76,8 @@ __device__ inline bf16x8 pack8(const float a[4], const float b[4]) {
     return v;
 }
 
-// LDS image of the weights used by the BF16 kernels.
+// LDS image of the weights used by the BF16 kernels, 16-byte aligned so that
+// 16-byte weight fragments and bias vectors load as single ds_read_b128.
 struct alignas(16) LdsBF16 {
     __bf16 w[3][kH][kRow];   // W2..W4, columns permuted per 32-block
     float w1[kH][8];          // W1 (7 columns, padded)
@@ -134,7 +135,8 @@ __device__ inline void stage_bf16(LdsBF16 &L, const float *__restrict__ p) {
     if (threadIdx.x == 0) L.b5 = p[OFF_B5];
 }
 
-// Layer 1 in FP32 for this lane's 32 features (16 mt + 4 g + r).
+// Layer 1 in FP32 on the VALU for this lane's 32 features (16 mt + 4 g + r)
+// (FP32 path).
 __device__ inline void layer1(const float (*w1)[8], const float *b1, const float un[kIn], int g, float hv[8][4],
                               float dv[8][4]) {
 #pragma unroll

@@ -38,6 +38,14 @@ __global__ __launch_bounds__(256) void k_descriptors(int32_t n, const double *__
                                                      int32_t maxp, float dmin2, float dmax2, float *__restrict__ desc,
                                                      int32_t *__restrict__ idx_nn, int32_t *__restrict__ idx_bead,
                                                      int32_t *__restrict__ flags) {
+    // the first round's pair indices are requested together with the count
+    // (any slot below the capacity may be read; only live ones are used)
+    const int p0 = blockIdx.x * blockDim.x + threadIdx.x;
+    int i0 = 0, j0 = 0;
+    if (p0 < maxp) {
+        i0 = pi[p0];
+        j0 = pj[p0];
+    }
     int count = flags[RB_FLAG_NPAIRS];
     if (count > maxp) count = maxp;
     const double Ls[3] = {L0, L1, L2};
@@ -46,7 +54,7 @@ __global__ __launch_bounds__(256) void k_descriptors(int32_t n, const double *__
         const bool live = p < count;
         bool to_nn = false, to_bead = false;
         if (live) {
-            const int i = pi[p], j = pj[p];
+            const int i = p == p0 ? i0 : pi[p], j = p == p0 ? j0 : pj[p];
             double dl[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) dl[a] = min_image(x[a * n + j] - x[a * n + i], Ls[a], 1.0 / Ls[a]);

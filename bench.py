@@ -203,7 +203,8 @@ def kernel_table(sysm, cfg, torch, abi):
                                        f"number density, {npb} pairs)")
     del big
     torch.cuda.empty_cache()
-    ms = time_launches(lambda: abi.rb_accum_finalize(n, sysm.acc, sysm.force, sysm.torque, sysm.ev), 20, torch)
+    ms = time_launches(lambda: abi.rb_accum_finalize(n, sysm.acc, sysm.force, sysm.torque, sysm.ev, sysm.flags), 20,
+                       torch)
     out["accum_finalize"] = roof(ms, 120.0 * n, HBM_PEAK, "GB/s", "hbm",
                                  "120 B per body (6 int64 read and cleared, 6 FP32 written)")
     st = {k: v.clone() for k, v in (("x", sysm.x), ("P", sysm.P), ("q", sysm.q), ("L", sysm.L))}

@@ -46,6 +46,8 @@ extern "C" {
 #define RB_ERR_CAPACITY (-2)
 #define RB_ERR_HIP (-3)
 #define RB_ERR_UNSUPPORTED (-4)
+#define RB_ERR_NONFINITE (-5)   /* rb_flags_check: the device reported non-finite
+                                   or overflowing forces, energies or orientations */
 
 /* Device flag words (int32 array of RB_NFLAGS, 8-byte aligned, caller owned,
  * zero it once). */
@@ -67,6 +69,15 @@ extern "C" {
                                 set by every pair-list build and by the
                                 integrator's margin test                        */
 #define RB_FLAG_NRESCREENS 12 /* number of screened-list builds done           */
+#define RB_FLAG_FIXOVF 13    /* 1: a term added to the fixed-point accumulator
+                                reached 2^28 in magnitude or was not finite, or
+                                a per-body or global total reached 2^30 (the
+                                accumulator holds totals below 2^31): forces,
+                                torques, energy or virial may be invalid       */
+#define RB_FLAG_QDRIFT 14    /* running count of body updates whose quaternion
+                                norm had drifted from 1 by more than 1e-10
+                                (|q|^2 - 1) before the integrator's
+                                renormalisation; also counts non-finite q      */
 #define RB_NFLAGS 16
 
 #define RB_PREC_BF16 0       /* 128x128 layers on BF16 MFMA, FP32 accumulate     */
@@ -111,6 +122,15 @@ int rb_ctx_destroy(rb_ctx *ctx);
  * sum with this context; the pair-list cutoff must use this rc. */
 int rb_ctx_set_hphc(rb_ctx *ctx, double A, double b, double c, double p);
 const char *rb_last_error(void);
+
+/* Host check of a flag array the caller has copied to host memory
+ * (flags_host, RB_NFLAGS int32): RB_ERR_CAPACITY when the last pair-list
+ * build overflowed its capacity, RB_ERR_NONFINITE when a non-finite pair
+ * force or energy (RB_FLAG_NONFINITE), a fixed-point accumulator overflow
+ * (RB_FLAG_FIXOVF) or a quaternion norm drift (RB_FLAG_QDRIFT) was
+ * reported, RB_OK otherwise; rb_last_error() names the condition.  Touches
+ * no device state. */
+int rb_flags_check(const int32_t *flags_host);
 
 /* ---- pair list: half list i < j of body pairs closer than r_list --------
  * Paper abstract: bead distances are computed only for bodies near each
@@ -213,10 +233,11 @@ int rb_bead_pair_forces_screened(const rb_ctx *ctx, int32_t n, const double *x, 
  * before the first evaluation.
  * rb_accum_finalize converts acc into force[3 x n] and torque[3 x n] (FP32,
  * lab frame) and energy_virial[10] (FP64: E then W row-major, may be NULL),
- * and clears acc for the next evaluation. */
+ * and clears acc for the next evaluation.  flags (may be NULL): a total of
+ * 2^30 or more in magnitude sets flags[RB_FLAG_FIXOVF]. */
 int rb_accum_zero(int32_t n, int64_t *acc, void *stream);
 int rb_accum_finalize(int32_t n, int64_t *acc, float *force, float *torque,
-                      double *energy_virial, void *stream);
+                      double *energy_virial, int32_t *flags, void *stream);
 
 /* ---- energy network (paper section 2, g_NN_U; supplementary section 6) ---
  * params: RB_MLP_NPARAMS FP32 (16-byte aligned), layer by layer W_l (out x
@@ -306,7 +327,9 @@ int rb_nn_pair_forces_sym(const float *params, const float *norm, int precision,
  * half_margin since the state (x_sref, q_sref), i.e.
  * |x - x_sref| + 2 rho |vec(q_sref^* q)| > half_margin with rho the type's
  * largest bead radius, sets flags[RESCREEN] (the screened list of
- * rb_bead_pair_forces_screened).  phase 2:
+ * rb_bead_pair_forces_screened); each body whose |q|^2 had drifted from 1
+ * by more than 1e-10 before the renormalisation adds 1 to flags[QDRIFT]
+ * (flags may be NULL only when x_ref and x_sref are).  phase 2:
  * second half kick; writes kinetic[2] = (translational, rotational) kinetic
  * energy (FP64 deterministic reduction).  ws: rb_rigid_workspace_bytes(n),
  * zero-filled before its first use.
@@ -334,7 +357,9 @@ int rb_rigid_step(const rb_ctx *ctx, int phase, int32_t n, double dt, double *x,
  * step) + phase 1 of the next step, with the same arithmetic in the same
  * order.  A run of K steps is phase 1, then (pair list, forces into acc,
  * rb_rigid_step_fused) K - 1 times, then pair list, forces, finalize,
- * phase 2.  kinetic may be NULL: the kinetic energy of that step is then
+ * phase 2.  The accumulator and quaternion checks of rb_accum_finalize and
+ * phase 1 set flags[FIXOVF] and flags[QDRIFT] here too.
+ * kinetic may be NULL: the kinetic energy of that step is then
  * not reduced (the grid-wide reduction is the launch's serial tail).  ws as
  * for phase 2, zero-filled before its first use. */
 int rb_rigid_step_fused(const rb_ctx *ctx, int32_t n, double dt, double *x, double *P, double *q,
@@ -344,6 +369,13 @@ int rb_rigid_step_fused(const rb_ctx *ctx, int32_t n, double dt, double *x, doub
                         double *kinetic, int32_t *flags, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- training step (energy loss, Adam) ------------------------------------
+ * Paper section 2: the network g_NN_U is fitted by regression to pair
+ * energies that the bead method computes for sampled pair configurations
+ * (the same section: training data come from composite-body simulations;
+ * supplementary section 1: fully connected feed-forward networks trained on
+ * such samples); section 3 and supplementary section 6 then take forces and
+ * torques from this energy network's gradient.  The optimiser is Adam
+ * (Kingma and Ba, ICLR 2015); the paper does not name one.
  * One step on the batch idx[0 .. batch) of a data set (desc 7 x n_data
  * FP32, labels n_data FP32): forward with saved activations, loss
  * mean((e' - y')^2) in normalised units, reverse pass, weight gradients,

@@ -35,7 +35,8 @@ SIGNATURES = {
     "rb_bead_pair_forces_screened": (C.c_int, [P, I32, P, P, P, DP, P, P, P, I32, F64, P, P, P, P, P, P, P]),
     "rb_bead_screen": (C.c_int, [P, I32, P, P, P, DP, P, P, P, P, I32, P, P, P, P, P]),
     "rb_accum_zero": (C.c_int, [I32, P, P]),
-    "rb_accum_finalize": (C.c_int, [I32, P, P, P, P, P]),
+    "rb_accum_finalize": (C.c_int, [I32, P, P, P, P, P, P]),
+    "rb_flags_check": (C.c_int, [IP]),
     "rb_nn_pair_eval": (C.c_int, [P, FP, C.c_int, I64, P, P, P]),
     "rb_nn_pair_grad": (C.c_int, [P, FP, C.c_int, I64, P, P, P, P, P, P]),
     "rb_nn_pair_forces": (C.c_int, [P, FP, C.c_int, I32, P, P, P, P, I32, P, P, I32, F32, F32, P, P,

@@ -19,6 +19,8 @@ from ._lib import check, lib
 RB_FLAG_REBUILD, RB_FLAG_NPAIRS, RB_FLAG_OVERFLOW, RB_FLAG_NREBUILDS = 0, 1, 2, 3
 RB_FLAG_NBEAD, RB_FLAG_NNN, RB_FLAG_NONFINITE, RB_FLAG_NEVAL, RB_FLAG_NTESTS, RB_NFLAGS = 4, 5, 6, 7, 8, 16
 RB_FLAG_NSCREEN, RB_FLAG_RESCREEN, RB_FLAG_NRESCREENS = 10, 11, 12
+RB_FLAG_FIXOVF, RB_FLAG_QDRIFT = 13, 14
+RB_OK, RB_ERR_CAPACITY, RB_ERR_NONFINITE = 0, -2, -5
 RB_PREC_BF16, RB_PREC_FP32 = 0, 1
 RB_BUILD_ALWAYS, RB_BUILD_IF_FLAGGED = 0, 1
 RB_MLP_NPARAMS = 50689
@@ -196,13 +198,22 @@ def rb_accum_zero(n: int, acc):
     check(lib().rb_accum_zero(n, _ptr(acc, torch.int64, (acc_len(n),), "acc"), _stream()), "rb_accum_zero")
 
 
-def rb_accum_finalize(n: int, acc, force, torque, energy_virial=None):
+def rb_accum_finalize(n: int, acc, force, torque, energy_virial=None, flags=None):
     check(lib().rb_accum_finalize(n, _ptr(acc, torch.int64, (acc_len(n),), "acc"),
                                   _ptr(force, torch.float32, (3, n), "force"),
                                   _ptr(torque, torch.float32, (3, n), "torque"),
                                   _ptr(energy_virial, torch.float64, (10,), "energy_virial", optional=True),
+                                  _ptr(flags, torch.int32, (RB_NFLAGS,), "flags", optional=True),
                                   _stream()),
           "rb_accum_finalize")
+
+
+def rb_flags_check(flags_host) -> tuple[int, str]:
+    """Status of a host copy of the flag array (RB_OK, RB_ERR_CAPACITY or
+    RB_ERR_NONFINITE) and the library's message for it."""
+    f = np.ascontiguousarray(np.asarray(flags_host, dtype=np.int32).reshape(RB_NFLAGS))
+    rc = lib().rb_flags_check(f.ctypes.data_as(C.POINTER(C.c_int32)))
+    return int(rc), (lib().rb_last_error().decode(errors="replace") if rc else "")
 
 
 def rb_nn_pair_eval(params, norm, precision: int, desc, energy):

@@ -66,9 +66,10 @@ def run_dynamics(cfg, st, path: str, nn: NNModel | None = None, chunks: int = 8,
             # trajectory can drift into rebuild-heavy or unphysical states
             first = dict(steps=replays * GRAPH_STEPS, steps_per_s=replays * GRAPH_STEPS / (1e-3 * times[0]),
                          rebuilds=int(f[abi.RB_FLAG_NREBUILDS] - f_prev[abi.RB_FLAG_NREBUILDS]),
-                         fallback=fallback_max, finite=not (f[abi.RB_FLAG_OVERFLOW] or f[abi.RB_FLAG_NONFINITE]))
-        if f[abi.RB_FLAG_OVERFLOW] or f[abi.RB_FLAG_NONFINITE]:
-            error = "pair list overflow" if f[abi.RB_FLAG_OVERFLOW] else "non-finite force or energy"
+                         fallback=fallback_max, finite=abi.rb_flags_check(f)[0] == abi.RB_OK)
+        rc, msg = abi.rb_flags_check(f)
+        if rc != abi.RB_OK:
+            error = msg
             break
         s = sysm.state_host()
         snaps.append((steps_done, s["x"], s["q"]))

@@ -511,7 +511,7 @@ template <int POT>
 __device__ inline void md_pair(const Templates &T, const LJ &lj, const float4 *tb, WaveLds &L, int lane, float cut2,
                                int32_t n, int i, int j, int ti, int tj, const double dl[3], const double d[3],
                                const double R[9], const double Ri[9], int64_t *__restrict__ acc, long long *wacc,
-                               long long &ntests, bool &bad) {
+                               long long &ntests, bool &bad, bool &ovf) {
     int ni, nj;
     stage_pair(T, tb, ti, tj, d, R, cut2, L, lane, ni, nj);
     if (ni == 0 || nj == 0) return;   // no bead pair within rc: zero contribution
@@ -537,7 +537,7 @@ __device__ inline void md_pair(const Templates &T, const LJ &lj, const float4 *t
             double v = R0 * V0 + R1 * V1 + R2 * V2;
             if (which == 1) v = -v;
             const int body = (which == 0 || which == 2) ? i : j;
-            acc_add(acc + (int64_t)((which < 2 ? 0 : 3) + a) * n + body, v);
+            acc_add(acc + (int64_t)((which < 2 ? 0 : 3) + a) * n + body, v, ovf);
         } else {
             const int e = lane - 12;
             double v = r[0];
@@ -547,6 +547,7 @@ __device__ inline void md_pair(const Templates &T, const LJ &lj, const float4 *t
                                    sel3(b, Ri[2], Ri[5], Ri[8]) * F[2];
                 v = -sel3(a, dl[0], dl[1], dl[2]) * Flb;
             }
+            ovf |= !fix_ok(v);
             wacc[e] += to_fixed(v);
         }
     }
@@ -598,7 +599,7 @@ __global__ __launch_bounds__(kMdWaves * kWave) __attribute__((amdgpu_waves_per_e
     if (count > max_count) count = max_count;
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(flags + RB_FLAG_NEVAL, count);
     long long ntests = 0;
-    bool bad = false;
+    bool bad = false, ovf = false;
     const int G = gridDim.x;
     const bool full = !SCREENED || flags[RB_FLAG_RESCREEN] != 0;
     // pairs of this launch: the whole list, or the screened pairs (those that
@@ -694,7 +695,7 @@ __global__ __launch_bounds__(kMdWaves * kWave) __attribute__((amdgpu_waves_per_e
                 quat_to_rot<double>(Q.qr[0][k], Q.qr[1][k], Q.qr[2][k], Q.qr[3][k], R);
                 quat_to_rot<double>(Q.qa[0][k], Q.qa[1][k], Q.qa[2][k], Q.qa[3][k], Ri);
                 md_pair<POT>(T, lj, tb, L, lane, cut2, n, Q.i[k], Q.j[k], Q.ti[k], Q.tj[k], dl, d, R, Ri, acc, wacc[w],
-                             ntests, bad);
+                             ntests, bad, ovf);
             }
         }
         __syncthreads();
@@ -705,6 +706,7 @@ __global__ __launch_bounds__(kMdWaves * kWave) __attribute__((amdgpu_waves_per_e
     part[10] = ntests;
     block_flush_globals<kMdWaves>(part, acc + 6 * (int64_t)n, flags);
     if (lane == 0 && bad) atomicOr(flags + RB_FLAG_NONFINITE, 1);
+    report_fixovf(ovf, flags);
     if (SCREENED && full) {
         // the last block to finish publishes the screened list
         __shared__ bool last;

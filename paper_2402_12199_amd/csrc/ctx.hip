@@ -34,21 +34,26 @@ __global__ void k_zero_i64(int64_t *a, int64_t n) {
 // is read and cleared by the same thread).  The first nb blocks take the
 // bodies, one extra block the global sums.
 __global__ void k_finalize(int32_t n, int nb, int64_t *__restrict__ acc, float *__restrict__ force,
-                           float *__restrict__ torque, double *__restrict__ ev) {
+                           float *__restrict__ torque, double *__restrict__ ev, int32_t *__restrict__ flags) {
     const double s = 1.0 / RB_ACC_SCALE;
+    bool ovf = false;
     if ((int)blockIdx.x == nb) {
-        finalize_globals(acc + 6 * (int64_t)n, ev);
+        finalize_globals(acc + 6 * (int64_t)n, ev, ovf);
+        report_fixovf(ovf, flags);
         return;
     }
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += nb * blockDim.x) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            force[a * n + i] = (float)((double)acc[a * (int64_t)n + i] * s);
-            torque[a * n + i] = (float)((double)acc[(3 + a) * (int64_t)n + i] * s);
+            const long long f = acc[a * (int64_t)n + i], t = acc[(3 + a) * (int64_t)n + i];
+            ovf |= !fix_word_ok(f) || !fix_word_ok(t);
+            force[a * n + i] = (float)((double)f * s);
+            torque[a * n + i] = (float)((double)t * s);
             acc[a * (int64_t)n + i] = 0;
             acc[(3 + a) * (int64_t)n + i] = 0;
         }
     }
+    report_fixovf(ovf, flags);
 }
 
 }  // namespace rb
@@ -56,6 +61,27 @@ __global__ void k_finalize(int32_t n, int nb, int64_t *__restrict__ acc, float *
 using namespace rb;
 
 extern "C" const char *rb_last_error(void) { return g_err; }
+
+extern "C" int rb_flags_check(const int32_t *f) {
+    RB_REQUIRE(f, "rb_flags_check: null flags");
+    if (f[RB_FLAG_OVERFLOW] > 0) {
+        set_error("pair list overflow: %d pairs found", f[RB_FLAG_OVERFLOW]);
+        return RB_ERR_CAPACITY;
+    }
+    if (f[RB_FLAG_NONFINITE]) {
+        set_error("non-finite pair force or energy");
+        return RB_ERR_NONFINITE;
+    }
+    if (f[RB_FLAG_FIXOVF]) {
+        set_error("fixed-point accumulator overflow (a term of 2^28 or a total of 2^30 in magnitude)");
+        return RB_ERR_NONFINITE;
+    }
+    if (f[RB_FLAG_QDRIFT]) {
+        set_error("quaternion norm drift beyond 1e-10 in %d body updates", f[RB_FLAG_QDRIFT]);
+        return RB_ERR_NONFINITE;
+    }
+    return RB_OK;
+}
 
 extern "C" int rb_ctx_create(rb_ctx **out, int32_t n_types, const int32_t *n_beads,
                              const float *beads, const double *mass, const double *inertia,
@@ -162,10 +188,10 @@ extern "C" int rb_accum_zero(int32_t n, int64_t *acc, void *stream) {
 }
 
 extern "C" int rb_accum_finalize(int32_t n, int64_t *acc, float *force, float *torque,
-                                 double *energy_virial, void *stream) {
+                                 double *energy_virial, int32_t *flags, void *stream) {
     RB_REQUIRE(n >= 0 && acc && force && torque, "rb_accum_finalize: bad arguments");
     const int nb = grid_for(n > 0 ? n : 1, 256, 4096);
-    k_finalize<<<nb + 1, 256, 0, (hipStream_t)stream>>>(n, nb, acc, force, torque, energy_virial);
+    k_finalize<<<nb + 1, 256, 0, (hipStream_t)stream>>>(n, nb, acc, force, torque, energy_virial, flags);
     RB_LAUNCH_CHECK("rb_accum_finalize");
     return RB_OK;
 }

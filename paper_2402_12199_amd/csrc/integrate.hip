@@ -135,6 +135,22 @@ __device__ inline void raise_flags(bool rebuild, bool rescreen, int32_t *flags) 
     if (__any(rescreen) && lead) atomicOr(flags + RB_FLAG_RESCREEN, 1);
 }
 
+// Renormalises q in place; returns true when |q|^2 had drifted from 1 by
+// more than 1e-10 (or was not finite) before the renormalisation.
+__device__ inline bool renormalise(double qi[4]) {
+    const double n2 = qi[0] * qi[0] + qi[1] * qi[1] + qi[2] * qi[2] + qi[3] * qi[3];
+    const double inv = 1.0 / sqrt(n2);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) qi[a] *= inv;
+    return !(fabs(n2 - 1.0) <= 1.0e-10);
+}
+
+// Adds the number of drifted quaternions of the wave to flags[QDRIFT].
+__device__ inline void count_drift(bool drift, int32_t *flags) {
+    const unsigned long long m = __ballot(drift);
+    if (m && (threadIdx.x & (kWave - 1)) == 0 && flags) atomicAdd(flags + RB_FLAG_QDRIFT, (int)__popcll(m));
+}
+
 // Grid-wide sums of (a, b) into out[0..1]: wave and block sums, one partial
 // pair per block, and the last block to finish adds the partials in a fixed
 // tree order (lane k takes blocks k, k + 64, ...), so the result depends only
@@ -211,7 +227,7 @@ __global__ __launch_bounds__(kIntThreads) void k_phase1(int32_t n, double dt, do
                                                         const float *__restrict__ torque, Watch wt,
                                                         int32_t *__restrict__ flags, const double *__restrict__ nh) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    bool rebuild = false, rescreen = false;
+    bool rebuild = false, rescreen = false, drift = false;
     if (i < n) {
         const int t = type[i];
         double qi[4] = {q[i], q[n + i], q[2 * n + i], q[3 * n + i]};
@@ -239,12 +255,9 @@ __global__ __launch_bounds__(kIntThreads) void k_phase1(int32_t n, double dt, do
         free_sub(0, dt, I[0], qi, Li);
         free_sub(1, 0.5 * dt, I[1], qi, Li);
         free_sub(2, 0.5 * dt, I[2], qi, Li);
-        const double inv = 1.0 / sqrt(qi[0] * qi[0] + qi[1] * qi[1] + qi[2] * qi[2] + qi[3] * qi[3]);
+        drift = renormalise(qi);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            qi[a] *= inv;
-            q[a * n + i] = qi[a];
-        }
+        for (int a = 0; a < 4; ++a) q[a * n + i] = qi[a];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             P[a * n + i] = Pi[a];
@@ -253,6 +266,7 @@ __global__ __launch_bounds__(kIntThreads) void k_phase1(int32_t n, double dt, do
         watch(wt, n, i, t, xn, qi, rebuild, rescreen);
     }
     raise_flags(rebuild, rescreen, flags);
+    count_drift(drift, flags);
 }
 
 // Second half kick; per-block FP64 kinetic partial sums, summed in block
@@ -304,12 +318,14 @@ __global__ __launch_bounds__(kIntThreads) void k_fused(int32_t n, double dt, dou
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const double s = 1.0 / RB_ACC_SCALE;
     double kt = 0, kr = 0;
-    bool rebuild = false, rescreen = false;
+    bool rebuild = false, rescreen = false, drift = false, ovf = false;
     if (i < n) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            force[a * n + i] = (float)((double)acc[a * (int64_t)n + i] * s);
-            torque[a * n + i] = (float)((double)acc[(3 + a) * (int64_t)n + i] * s);
+            const long long fw = acc[a * (int64_t)n + i], tw = acc[(3 + a) * (int64_t)n + i];
+            ovf |= !fix_word_ok(fw) || !fix_word_ok(tw);
+            force[a * n + i] = (float)((double)fw * s);
+            torque[a * n + i] = (float)((double)tw * s);
             acc[a * (int64_t)n + i] = 0;
             acc[(3 + a) * (int64_t)n + i] = 0;
         }
@@ -339,12 +355,9 @@ __global__ __launch_bounds__(kIntThreads) void k_fused(int32_t n, double dt, dou
         free_sub(0, dt, I[0], qi, Li);
         free_sub(1, 0.5 * dt, I[1], qi, Li);
         free_sub(2, 0.5 * dt, I[2], qi, Li);
-        const double inv = 1.0 / sqrt(qi[0] * qi[0] + qi[1] * qi[1] + qi[2] * qi[2] + qi[3] * qi[3]);
+        drift = renormalise(qi);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            qi[a] *= inv;
-            q[a * n + i] = qi[a];
-        }
+        for (int a = 0; a < 4; ++a) q[a * n + i] = qi[a];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             P[a * n + i] = Pi[a];
@@ -353,7 +366,9 @@ __global__ __launch_bounds__(kIntThreads) void k_fused(int32_t n, double dt, dou
         watch(wt, n, i, t, xn, qi, rebuild, rescreen);
     }
     raise_flags(rebuild, rescreen, flags);
-    if (blockIdx.x == gridDim.x - 1) finalize_globals(acc + 6 * (int64_t)n, ev);
+    count_drift(drift, flags);
+    if (blockIdx.x == gridDim.x - 1) finalize_globals(acc + 6 * (int64_t)n, ev, ovf);
+    report_fixovf(ovf, flags);
     if (kinetic) grid_sum2(kt, kr, partial, ticket, kinetic);
 }
 

@@ -101,7 +101,7 @@ __device__ inline EpiIn load_epi(const NNArgs &a, int64_t pid, bool live) {
 }
 
 __device__ inline void forces_epilogue(const NNArgs &a, const EpiIn &in, float gu[kIn], float E, int64_t pid,
-                                       bool mine, int lane, long long *wsum, bool &bad) {
+                                       bool mine, int lane, long long *wsum, bool &bad, bool &ovf) {
     long long ev[10];
 #pragma unroll
     for (int k = 0; k < 10; ++k) ev[k] = 0;
@@ -139,16 +139,20 @@ __device__ inline void forces_epilogue(const NNArgs &a, const EpiIn &in, float g
         const int64_t nn = a.n;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            acc_add(a.acc + c * nn + i, -Fj[c]);
-            acc_add(a.acc + c * nn + j, Fj[c]);
-            acc_add(a.acc + (3 + c) * nn + i, ti[c]);
-            acc_add(a.acc + (3 + c) * nn + j, tj[c]);
+            acc_add(a.acc + c * nn + i, -Fj[c], ovf);
+            acc_add(a.acc + c * nn + j, Fj[c], ovf);
+            acc_add(a.acc + (3 + c) * nn + i, ti[c], ovf);
+            acc_add(a.acc + (3 + c) * nn + j, tj[c], ovf);
         }
+        ovf |= !fix_ok(Es);
         ev[0] = to_fixed(Es);
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
-            for (int b = 0; b < 3; ++b) ev[1 + 3 * c + b] = to_fixed(dl[c] * Fj[b]);
+            for (int b = 0; b < 3; ++b) {
+                ovf |= !fix_ok(dl[c] * Fj[b]);
+                ev[1 + 3 * c + b] = to_fixed(dl[c] * Fj[b]);
+            }
     }
 #pragma unroll
     for (int k = 0; k < 10; ++k) {
@@ -188,7 +192,7 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
     // add nothing to the register pressure of the tile evaluation
     __shared__ long long wacc[kWaves][10];
     if (MODE == kForces && lane < 10) wacc[w][lane] = 0;
-    bool bad = false;
+    bool bad = false, ovf = false;
     const int64_t ntiles = (count + kTile - 1) / kTile;
     for (int64_t t = (int64_t)blockIdx.x * kWaves + w; t < ntiles; t += (int64_t)gridDim.x * kWaves) {
         // Keeps the compiler from hoisting the (tile-invariant) LDS weight
@@ -218,7 +222,7 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
         if (MODE == kForces) {
             // every lane takes part in the shuffles below; the results of
             // the lanes of groups 1..3 and of dead rows are discarded
-            forces_epilogue(a, ein, gu, E, pid, live && g == 0, lane, wacc[w], bad);
+            forces_epilogue(a, ein, gu, E, pid, live && g == 0, lane, wacc[w], bad, ovf);
             continue;
         }
         if (!live || g != 0) continue;
@@ -250,6 +254,7 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
         part[10] = 0;
         block_flush_globals<kWaves>(part, a.acc + 6 * (int64_t)a.n, nullptr);
         if (__any(bad) && lane == 0) atomicOr(a.flags + RB_FLAG_NONFINITE, 1);
+        report_fixovf(ovf, a.flags);
     }
 }
 
@@ -335,7 +340,7 @@ __device__ inline void put_epi(const NNArgs &a, EpiLds &e, const EpiIn &in, cons
 // wave's LDS sums.  Same values as forces_epilogue (fixed-point sums are
 // exact and order-free).
 __device__ inline void forces_epilogue_wide(const NNArgs &a, const EpiLds &e, const float gu_in[kIn], float E,
-                                            bool live, int v, int g, int n, long long *wsum, bool &bad) {
+                                            bool live, int v, int g, int n, long long *wsum, bool &bad, bool &ovf) {
     long long ev[3] = {0, 0, 0};
     if (live && (g == 0 || v == 0)) {
         float u[kIn], gu[kIn];
@@ -371,9 +376,12 @@ __device__ inline void forces_epilogue_wide(const NNArgs &a, const EpiLds &e, co
             const int64_t row0 = v < 2 ? 0 : 3;
             const double sgn = v == 1 ? -1.0 : 1.0;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) acc_add(a.acc + (row0 + c) * nn + body, sgn * V[c]);
+            for (int c = 0; c < 3; ++c) acc_add(a.acc + (row0 + c) * nn + body, sgn * V[c], ovf);
             if (!isfinite(f0) || (v == 0 && !isfinite(Es))) bad = true;
-            if (v == 0) ev[0] = to_fixed(Es);
+            if (v == 0) {
+                ovf |= !fix_ok(Es);
+                ev[0] = to_fixed(Es);
+            }
         } else {
             // virial row c = g - 1: (R d)_c * F_j
             const int c = g - 1;
@@ -382,7 +390,10 @@ __device__ inline void forces_epilogue_wide(const NNArgs &a, const EpiLds &e, co
             const double r2 = c == 0 ? R[2] : (c == 1 ? R[5] : R[8]);
             const double dl = r0 * u[0] + r1 * u[1] + r2 * u[2];
 #pragma unroll
-            for (int b = 0; b < 3; ++b) ev[b] = to_fixed(dl * V[b]);
+            for (int b = 0; b < 3; ++b) {
+                ovf |= !fix_ok(dl * V[b]);
+                ev[b] = to_fixed(dl * V[b]);
+            }
         }
     }
     if (v != 0) return;
@@ -422,7 +433,7 @@ __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
     TileIn t = tile_in<MODE>(a, (base + grp) * kTile + n, count, g == 0 && v == 0);
     stage_bf16<kWideThreads>(L, a.params);
     if (MODE == kForces && lane < 10) wacc[wave][lane] = 0;
-    bool bad = false;
+    bool bad = false, ovf = false;
     for (;;) {
         if (MODE == kForces && v == 0 && g == 0) put_epi(a, EL[grp], t.ein, t.u, t.pid, t.live, n);
         __syncthreads();
@@ -441,7 +452,7 @@ __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
 #pragma unroll
                 for (int k = 0; k < kIn; ++k) gu[k] = X[grp].red[0][1 + k][n];
             }
-            forces_epilogue_wide(a, EL[grp], gu, E, t.live, v, g, n, wacc[wave], bad);
+            forces_epilogue_wide(a, EL[grp], gu, E, t.live, v, g, n, wacc[wave], bad, ovf);
         } else if (v == 0 && t.live && g == 0) {
             sym_chain(a, t.row, gu);
             store_grad(a, t, gu, E);
@@ -459,6 +470,7 @@ __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
         part[10] = 0;
         block_flush_globals<kWideGroups * kWideGroup>(part, a.acc + 6 * (int64_t)a.n, nullptr);
         if (__any(bad) && lane == 0) atomicOr(a.flags + RB_FLAG_NONFINITE, 1);
+        report_fixovf(ovf, a.flags);
     }
 }
 

@@ -58,11 +58,30 @@ struct CtxDevice {
 };
 
 // ------------------------------------------------------------- fixed point
+// A word holds value * 2^32 in an int64, so totals must stay below 2^31 in
+// magnitude.  A single term of 2^28 or more (or a non-finite one) is reported
+// through `ovf` (and then flags[RB_FLAG_FIXOVF]): with fewer than eight such
+// terms per word no total can wrap unnoticed, and finalize reports totals of
+// 2^30 or more.
+constexpr double kFixTermLimit = 268435456.0;                 // 2^28
+constexpr long long kFixWordLimit = 4611686018427387904LL;    // 2^62 = 2^30 * 2^32
+
 __device__ inline long long to_fixed(double v) { return __double2ll_rn(v * RB_ACC_SCALE); }
 
-__device__ inline void acc_add(int64_t *a, double v) {
+// false for |v| >= 2^28 and for NaN
+__device__ inline bool fix_ok(double v) { return fabs(v) < kFixTermLimit; }
+
+__device__ inline bool fix_word_ok(long long w) { return w < kFixWordLimit && w > -kFixWordLimit; }
+
+__device__ inline void acc_add(int64_t *a, double v, bool &ovf) {
+    ovf |= !fix_ok(v);
     atomicAdd(reinterpret_cast<unsigned long long *>(a),
               static_cast<unsigned long long>(to_fixed(v)));
+}
+
+// One atomic per wave that saw an accumulator overflow (every lane calls it).
+__device__ inline void report_fixovf(bool ovf, int32_t *flags) {
+    if (__any(ovf) && (threadIdx.x & 63) == 0 && flags) atomicOr(flags + RB_FLAG_FIXOVF, 1);
 }
 
 // Block-level sum of per-wave global partials (E, virial, tests: 11 int64)
@@ -115,7 +134,7 @@ __device__ inline T wave_sum(T v) {
 // sums (energy, virial), one lane per slot and one wave per sum; every wave of
 // the calling block takes part, with all of a wave's loads issued before its
 // sums.  Integer sums: the order does not matter.
-__device__ inline void finalize_globals(int64_t *acc_globals, double *ev) {
+__device__ inline void finalize_globals(int64_t *acc_globals, double *ev, bool &ovf) {
     static_assert(RB_ACC_SLOTS == kWave, "one lane per slot");
     constexpr int kSums = 10, kPerWave = 3;   // blocks of at least four waves: one round
     const int lane = threadIdx.x & (kWave - 1);
@@ -133,6 +152,7 @@ __device__ inline void finalize_globals(int64_t *acc_globals, double *ev) {
             if (g < kSums) {
                 acc_globals[g * RB_ACC_SLOTS + lane] = 0;
                 const long long s = wave_sum(v[r]);
+                ovf |= !fix_word_ok(v[r]) || !fix_word_ok(s);
                 if (lane == 0 && ev) ev[g] = (double)s * (1.0 / RB_ACC_SCALE);
             }
         }

@@ -175,7 +175,7 @@ class RigidSystem:
             self.nn_forces()
         else:
             raise ValueError(path)
-        abi.rb_accum_finalize(self.n, self.acc, self.force, self.torque, self.ev)
+        abi.rb_accum_finalize(self.n, self.acc, self.force, self.torque, self.ev, self.flags)
 
     def init_forces(self, path="bead"):
         self.build_pairs(always=True)
@@ -276,11 +276,13 @@ class RigidSystem:
         return self.flags.cpu().numpy()
 
     def check_capacity(self):
+        """Raises on any condition the device reported (pair-list overflow,
+        non-finite forces, fixed-point overflow, quaternion drift), through
+        rb_flags_check; returns the host copy of the flags."""
         f = self.flags_host()
-        if f[abi.RB_FLAG_OVERFLOW]:
-            raise RuntimeError(f"pair list overflow: {f[abi.RB_FLAG_OVERFLOW]} pairs > capacity {self.max_pairs}")
-        if f[abi.RB_FLAG_NONFINITE]:
-            raise RuntimeError("non-finite pair force or energy")
+        rc, msg = abi.rb_flags_check(f)
+        if rc != abi.RB_OK:
+            raise RuntimeError(f"{msg} (capacity {self.max_pairs})" if rc == abi.RB_ERR_CAPACITY else msg)
         return f
 
     def state_host(self) -> dict:

@@ -5,6 +5,8 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -46,3 +48,23 @@ def test_host_side_argument_errors():
     assert L.rb_pairlist_workspace_bytes(100, box, 6.0) == 0
     assert L.rb_pairlist_workspace_bytes(100, box, 4.0) > 0
     assert L.rb_rigid_workspace_bytes(1000) >= 16 * 4
+
+
+def test_flags_check_reports_device_conditions():
+    # rb_flags_check is a host function over a host copy of the flag array:
+    # each device-reported condition maps to its status code and message
+    from paper_2402_12199_amd import abi
+    f = np.zeros(abi.RB_NFLAGS, np.int32)
+    f[abi.RB_FLAG_NPAIRS] = 123
+    f[abi.RB_FLAG_NEVAL] = 99
+    assert abi.rb_flags_check(f) == (abi.RB_OK, "")
+    cases = [(abi.RB_FLAG_OVERFLOW, 5000, abi.RB_ERR_CAPACITY, "overflow"),
+             (abi.RB_FLAG_NONFINITE, 1, abi.RB_ERR_NONFINITE, "non-finite"),
+             (abi.RB_FLAG_FIXOVF, 1, abi.RB_ERR_NONFINITE, "fixed-point"),
+             (abi.RB_FLAG_QDRIFT, 3, abi.RB_ERR_NONFINITE, "quaternion")]
+    for k, v, rc, word in cases:
+        g = f.copy()
+        g[k] = v
+        got, msg = abi.rb_flags_check(g)
+        assert got == rc and word in msg, (k, got, msg)
+    assert abi.RB_ERR_NONFINITE == -5

@@ -370,10 +370,10 @@ def test_graph_replays_match_eager_steps_bitwise(abi, path):
     assert eager.flags_host()[abi.RB_FLAG_NEVAL] == graphed.flags_host()[abi.RB_FLAG_NEVAL]
 
 
-def test_pairlist_multi_kernel_path_matches_kdtree(abi):
+def test_pairlist_multi_kernel_path_matches_oracle(abi):
     # above 65536 bodies the list is built by the multi-kernel pipeline;
-    # reference: scipy's periodic k-d tree (a library neighbour search)
-    from scipy.spatial import cKDTree
+    # reference: the oracle's brute-force minimum-image search over all
+    # n (n - 1) / 2 pairs
     from paper_2402_12199_amd.md import RigidSystem
     n = 70001
     box = 300.0
@@ -388,8 +388,7 @@ def test_pairlist_multi_kernel_path_matches_kdtree(abi):
     sysm.build_pairs(always=True)
     f = sysm.check_capacity()
     got = sysm.pairs_host()
-    ref = cKDTree(x, boxsize=box).query_pairs(r, output_type="ndarray")
-    ref = np.sort(ref, axis=1)
+    ref = np.sort(obeads.pairs_within(x, box, r), axis=1)
     assert f[abi.RB_FLAG_NPAIRS] == len(ref)
     key = lambda a: a[:, 0].astype(np.int64) * n + a[:, 1]
     np.testing.assert_array_equal(np.sort(key(got)), np.sort(key(ref)))
@@ -508,3 +507,41 @@ def test_nvt_matches_oracle_and_conserves_extended_energy(abi):
     assert abs(sysm.nh[0].item()) > 0.05          # the thermostat is active
     with pytest.raises(ValueError):
         sysm.begin_fused(cfg.dt)
+
+
+def test_fixed_point_overflow_and_quaternion_drift_are_flagged(abi):
+    # Two single-bead bodies 0.05 sigma apart: the Lennard-Jones force, about
+    # 4e18, is finite in FP32 and FP64 but far beyond what the fixed-point
+    # accumulator holds (totals below 2^31); the kernels must report it in
+    # flags[FIXOVF] (and rb_flags_check turn it into RB_ERR_NONFINITE) instead
+    # of wrapping silently.  A body given a quaternion of norm 1.1 is counted
+    # in flags[QDRIFT] by the integrator's renormalisation.
+    from paper_2402_12199_amd.md import RigidSystem
+    one = np.zeros((1, 3))
+    x = np.array([[10.0, 10.0, 10.0], [10.05, 10.0, 10.0], [30.0, 30.0, 30.0]])
+    q = np.array([[1.0, 0, 0, 0], [1.0, 0, 0, 0], [1.1, 0, 0, 0]])
+    zero = np.zeros((3, 3))
+    sysm = RigidSystem([one], [1.0], [[1.0, 1.0, 1.0]], np.zeros(3, np.int32), x, q, zero, zero, 50.0, 3.0, 0.5)
+    sysm.init_forces("bead")
+    f = sysm.flags_host()
+    assert f[abi.RB_FLAG_NONFINITE] == 0          # finite, but too large
+    assert f[abi.RB_FLAG_FIXOVF] == 1
+    assert f[abi.RB_FLAG_QDRIFT] == 0
+    rc, msg = abi.rb_flags_check(f)
+    assert rc == abi.RB_ERR_NONFINITE and "fixed-point" in msg
+    with pytest.raises(RuntimeError, match="fixed-point"):
+        sysm.check_capacity()
+    # a sane pair (1.2 sigma) raises nothing; the non-unit quaternion is
+    # counted once per phase-1 update
+    x[1, 0] = 11.2
+    sane = RigidSystem([one], [1.0], [[1.0, 1.0, 1.0]], np.zeros(3, np.int32), x, q, zero, zero, 50.0, 3.0, 0.5)
+    sane.init_forces("bead")
+    assert sane.flags_host()[abi.RB_FLAG_FIXOVF] == 0
+    sane.step(0.001)
+    f = sane.flags_host()
+    assert f[abi.RB_FLAG_QDRIFT] == 1 and f[abi.RB_FLAG_FIXOVF] == 0
+    assert abs(np.linalg.norm(sane.state_host()["q"][2]) - 1.0) < 1e-14
+    sane.step(0.001)
+    assert sane.flags_host()[abi.RB_FLAG_QDRIFT] == 1    # renormalised: no new drift
+    rc, msg = abi.rb_flags_check(sane.flags_host())
+    assert rc == abi.RB_ERR_NONFINITE and "quaternion" in msg

@@ -78,6 +78,22 @@ def test_grad_and_pair_forces_match_oracle(abi, prec):
         assert_close(got[:, s:s + 3], ftr[:, s:s + 3], gtol, name)
 
 
+def test_bf16_mode_against_unrounded_master_weights(abi):
+    # The BF16 kernels hold W2..W4 in BF16; the trainer's FP32 master weights
+    # are what dynamics and training mean by "the network".  Energy and input
+    # gradient of the BF16 mode against the FP64 network on those unrounded
+    # weights, at the same 2e-2 bound (weight rounding and BF16 activations
+    # together).
+    n = 4099
+    params, norm, desc = _setup(n, seed=13)
+    E = torch.zeros(n, dtype=torch.float32, device="cuda")
+    g = torch.zeros((7, n), dtype=torch.float32, device="cuda")
+    abi.rb_nn_pair_grad(_dev(params), norm.as_array(), 0, _dev(desc.T), None, E, g, None)
+    Er, gr = omlp.input_grad(params.astype(np.float64), desc.astype(np.float64), norm)
+    assert_close(E.cpu().numpy(), Er, 2e-2, "E vs FP32 master weights")
+    assert_close(g.cpu().numpy().T, gr, 2e-2, "dE/du vs FP32 master weights")
+
+
 def test_config3_full_batch_sampled_rows(abi):
     # 2^20 rows in the launch configuration of the benchmark; every output is
     # compared on a random sample of rows the oracle evaluates one by one

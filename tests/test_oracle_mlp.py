@@ -168,3 +168,37 @@ def test_force_matching_reduces_to_energy_loss_and_matches_its_forces():
     _, fm, g1 = mlp.fm_loss_and_grad(p, u, y, np.concatenate([own[:, :3], own[:, 6:9]], 1), 2.0, 3.0, norm)
     assert fm < 1e-25
     np.testing.assert_allclose(g1, ref_grad, rtol=0, atol=1e-12)
+
+
+def test_bf16_network_rounds_exactly_the_hidden_to_hidden_weights():
+    # A hand-built net of widths 7 -> 4 -> 4 -> 4 -> 4 -> 1 in which every
+    # parameter is 1 + 3 * 2^-10 or, in a second pass, 1 + 5 * 2^-9.  BF16
+    # keeps 7 fraction bits, so the BF16 neighbours are 1 and 1 + 2^-7: the
+    # first value (3 * 2^-10 below the midpoint 2^-8) rounds to 1, the second
+    # (5 * 2^-9 above it) to 1 + 2^-7.  Only W2, W3 and W4 may change, each
+    # element to that hand-computed value; W1, W5 and every bias must come
+    # back unchanged.
+    dims = (7, 4, 4, 4, 4, 1)
+    n = sum(fi * fo + fo for fi, fo in zip(dims[:-1], dims[1:]))
+    for val, rounded in ((1 + 3 * 2 ** -10, 1.0), (1 + 5 * 2 ** -9, 1 + 2 ** -7)):
+        p = np.full(n, val, np.float32)
+        assert float(p[0]) == val                      # exact in FP32
+        out = mlp.unpack(mlp.bf16_network(p, dims), dims)
+        assert len(out) == 5
+        for li, (W, b) in enumerate(out):
+            want_W = rounded if li in (1, 2, 3) else val
+            np.testing.assert_array_equal(W, np.full(W.shape, want_W), err_msg=f"W{li + 1}")
+            np.testing.assert_array_equal(b, np.full(b.shape, val), err_msg=f"b{li + 1}")
+    # the full-size network: the same rule on the Xavier parameters, compared
+    # with the element-wise rounding of each block
+    p = sampling.xavier_params(3).astype(np.float32)
+    p = p + np.float32(1e-3) * np.arange(p.size, dtype=np.float32) / p.size   # non-zero biases
+    got = mlp.unpack(mlp.bf16_network(p))
+    ref = mlp.unpack(p.astype(np.float64))
+    for li, ((Wg, bg), (Wr, br)) in enumerate(zip(got, ref)):
+        if li in (1, 2, 3):
+            assert np.any(Wg != Wr)
+            np.testing.assert_array_equal(Wg, mlp.round_bf16(Wr.astype(np.float32)))
+        else:
+            np.testing.assert_array_equal(Wg, Wr)
+        np.testing.assert_array_equal(bg, br)

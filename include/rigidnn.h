@@ -154,16 +154,28 @@ int rb_pairlist_build(int32_t n, const double *x, const double *box, double r_li
 
 /* ---- descriptors and routing ---------------------------------------------
  * For the first flags[NPAIRS] pairs: desc (7 x max_pairs FP32) from FP64
- * state, and routing of each pair to the network (d_min <= |d| < d_max) or
- * to the bead sum (|d| < d_min, outside the network's training domain);
- * pairs at |d| >= d_max (where the switched network energy is zero; d_max
- * <= 0: no limit) go to neither.  Routed pair indices go to idx_nn /
+ * state, and routing of each pair (paper section 2: the network replaces the
+ * bead sum inside its training domain; the bead sum stays the reference
+ * everywhere).  Without shells (ctx == NULL, type == NULL): pairs with
+ * d_min <= |d| < d_max go to the network, pairs with |d| < d_min to the
+ * bead sum, pairs at |d| >= d_max (where the switched network energy is
+ * zero; d_max <= 0: no limit) to neither.  With shells (ctx and the bodies'
+ * types, n int32): a lower bound G on the pair's closest bead-centre
+ * distance is formed from two convex shells of each type's bead centres --
+ * the bead-centre box (15-axis separating-axis gaps) and a capsule along the
+ * longest body axis (segment distance minus radii), G the larger bound --
+ * and, among the pairs with |d| < d_max, those with |d| < d_min or
+ * G < gap_min (possibly closer than the training data's closest bead
+ * distance) go to the bead sum, those with G >= gap_max (gap_max > 0; no
+ * bead pair within gap_max, so zero bead energy when gap_max >= rc) to
+ * neither, the rest to the network.  Routed pair indices go to idx_nn /
  * idx_bead (capacity max_pairs each, order not specified) with counts in
  * flags[NNN] / flags[NBEAD].  x: 3 x n, q: 4 x n. */
 int rb_pair_descriptors(int32_t n, const double *x, const double *q, const double *box,
                         const int32_t *pair_i, const int32_t *pair_j, int32_t max_pairs,
                         float d_min, float d_max, float *desc, int32_t *idx_nn,
-                        int32_t *idx_bead, int32_t *flags, void *stream);
+                        int32_t *idx_bead, int32_t *flags, const rb_ctx *ctx,
+                        const int32_t *type, float gap_min, float gap_max, void *stream);
 
 /* ---- bead double sum (paper section 2, first equation) -------------------
  * Every bead pair closer than rc contributes; bead pairs are skipped only
@@ -305,6 +317,33 @@ int rb_cube_sym_descriptors(int64_t n_pairs, const float *desc, int64_t stride, 
 int rb_nn_pair_grad_sym(const float *params, const float *norm, int precision, int64_t n_pairs,
                         const float *desc, const float *sym, const float *jac, const float *gE,
                         float *energy, float *dE_ddesc, float *pair_ft, void *stream);
+
+/* ---- four-number descriptor of cylinder pairs -----------------------------
+ * Paper section 2 (a cylinder pair depends on four numbers thanks to the
+ * cylindrical symmetry) and supplementary section 2: in body 1's frame with
+ * z along its axis (oriented so that p_z >= 0) and x chosen so that p_y = 0,
+ * body 2's centre is (p_r, 0, p_z) and its axis a unit vector a at spherical
+ * angles (theta, phi).  The network's seven inputs are the smooth functions
+ * s = (p_r^2, p_z^2, a_z^2, (p_r a_x)^2, p_r a_x a_z p_z, 0, 0), which are
+ * also unchanged when body 2 is turned end over end and under the mirror
+ * y -> -y of that frame; in the pair descriptor (d, q) they are polynomials
+ * of d and the axis A = q e_z q^* (body z axis = cylinder axis).  Layout and
+ * arguments as rb_cube_sym_descriptors; jac is the Jacobian of those
+ * polynomials (q as four free components, homogeneous form). */
+int rb_cyl_sym_descriptors(int64_t n_pairs, const float *desc, int64_t stride, const int32_t *idx,
+                           const int32_t *count_dev, int64_t max_count, float *sym, float *jac,
+                           void *stream);
+
+/* rb_nn_pair_forces for cylinder pairs: the network sees the four-number form
+ * of each pair's (d, q) (as rb_cyl_sym_descriptors defines it), computed
+ * with its Jacobian inside the kernel; forces and torques from dE/du =
+ * J^T dE/ds and the closed form of rb_nn_pair_grad.  The torque of each
+ * cylinder about its own axis is zero.  Arguments as rb_nn_pair_forces. */
+int rb_nn_pair_forces_cyl(const float *params, const float *norm, int precision, int32_t n,
+                          const double *q, const int32_t *pair_i, const int32_t *pair_j,
+                          const float *desc, int32_t desc_stride, const int32_t *idx,
+                          const int32_t *count_dev, int32_t max_count, float sw_lo, float sw_hi,
+                          int64_t *acc, int32_t *flags, void *stream);
 
 /* rb_nn_pair_forces with the symmetry-reduced descriptor: sym and jac (row
  * stride max_count) hold the descriptor and Jacobian of launch row k, i.e.

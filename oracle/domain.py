@@ -1,0 +1,120 @@
+"""ORACLE (test infrastructure only): a lower bound on the closest bead-bead
+distance of a body pair, from two convex shells around each body's bead
+centres, and the routing it implies.
+
+The learned pair energy is fitted on configurations whose closest bead pair
+is at least r_rej apart (deeper overlaps are absent from dynamics at the
+workloads' temperatures and are rejected from the training data).  A pair
+may be handed to the network only when it provably lies in that domain;
+every other pair goes to the bead sum, which is exact everywhere (paper
+section 2: the bead path is the reference the network approximates).
+
+Shells, in the body frame (centre of mass at the origin):
+* the bead-centre box: |x| <= h_x, |y| <= h_y, |z| <= h_z (largest
+  coordinate magnitudes);
+* a capsule along the body axis k with the largest h_k: the points within
+  R of the segment from -H e_k to +H e_k, with R the largest distance of a
+  bead from that axis and H the smallest half-length that keeps every bead
+  inside.
+
+For convex sets, the gap between the projections onto any unit axis is a
+lower bound on their distance (separating-axis theorem); for the boxes the
+15 candidate axes of two boxes are tried (each box's face normals and the
+cross products of their edges).  The capsule distance is the distance of the
+two segments minus both radii.  gap = max(box gap, capsule gap) bounds the
+closest bead-centre distance from below.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import frames
+
+
+def shells(beads: np.ndarray):
+    """Box half extents h (3), capsule axis k, radius R and half-length H."""
+    b = np.asarray(beads, np.float64)
+    h = np.abs(b).max(axis=0)
+    k = int(np.argmax(h))
+    perp = np.sqrt(np.sum(np.delete(b, k, axis=1) ** 2, axis=1))
+    R = float(perp.max())
+    H = float(max(0.0, np.max(np.abs(b[:, k]) - np.sqrt(np.maximum(R * R - perp * perp, 0.0)))))
+    return h, k, R, H
+
+
+def _corners(h: np.ndarray) -> np.ndarray:
+    s = np.array([[sx, sy, sz] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)], np.float64)
+    return s * h
+
+
+def box_gap(ha: np.ndarray, hb: np.ndarray, d: np.ndarray, R: np.ndarray) -> np.ndarray:
+    """Largest projected gap between box A (origin, frame axes, half extents
+    ha) and box B (centre d, axes the columns of R, half extents hb) over
+    the 15 separating-axis candidates, each box projected through its 8
+    corners; d (P, 3), R (P, 3, 3) -> (P,).  Negative when no candidate axis
+    separates them."""
+    d = np.atleast_2d(np.asarray(d, np.float64))
+    R = np.asarray(R, np.float64).reshape(-1, 3, 3)
+    P = len(d)
+    ca = _corners(np.asarray(ha, np.float64))                          # (8, 3)
+    cb = d[:, None, :] + np.einsum("ck,pjk->pcj", _corners(np.asarray(hb, np.float64)), R)   # (P, 8, 3)
+    E = np.broadcast_to(np.eye(3), (P, 3, 3))
+    axes = [E[:, i] for i in range(3)] + [R[:, :, j] for j in range(3)]
+    axes += [np.cross(E[:, i], R[:, :, j]) for i in range(3) for j in range(3)]
+    best = np.full(P, -np.inf)
+    for L in axes:
+        n = np.linalg.norm(L, axis=1)
+        use = n >= 1e-6                     # (near-)parallel edges: no usable axis
+        L = L / np.where(use, n, 1.0)[:, None]
+        pa = np.einsum("ck,pk->pc", ca, L)
+        pb = np.einsum("pck,pk->pc", cb, L)
+        g = np.maximum(pb.min(1) - pa.max(1), pa.min(1) - pb.max(1))
+        best = np.where(use, np.maximum(best, g), best)
+    return best
+
+
+def segment_distance(p0, p1, q0, q1) -> np.ndarray:
+    """Distance between the segments [p0, p1] and [q0, q1] (each (3,) or
+    (P, 3)): the smallest of the distances of each end point to the other
+    segment and, when the segments' lines meet the interior of both, the
+    distance of the lines' closest points."""
+    p0, p1, q0, q1 = (np.atleast_2d(np.asarray(v, np.float64)) for v in (p0, p1, q0, q1))
+
+    def point_seg(x, a, b):
+        ab = b - a
+        den = np.sum(ab * ab, 1)
+        t = np.clip(np.sum((x - a) * ab, 1) / np.where(den > 0, den, 1.0), 0.0, 1.0)
+        t = np.where(den > 0, t, 0.0)
+        return np.linalg.norm(x - (a + t[:, None] * ab), axis=1)
+
+    best = np.minimum.reduce([point_seg(p0, q0, q1), point_seg(p1, q0, q1), point_seg(q0, p0, p1),
+                              point_seg(q1, p0, p1)])
+    u, v, w = p1 - p0, q1 - q0, p0 - q0
+    a, b, c = np.sum(u * u, 1), np.sum(u * v, 1), np.sum(v * v, 1)
+    dd, e = np.sum(u * w, 1), np.sum(v * w, 1)
+    den = a * c - b * b
+    ok = den > 1e-12 * a * c
+    dsafe = np.where(ok, den, 1.0)
+    s = (b * e - c * dd) / dsafe
+    t = (a * e - b * dd) / dsafe
+    ok &= (s >= 0) & (s <= 1) & (t >= 0) & (t <= 1)
+    inner = np.linalg.norm(w + s[:, None] * u - t[:, None] * v, axis=1)
+    out = np.where(ok, np.minimum(best, inner), best)
+    return out if out.size > 1 else float(out[0])
+
+
+def gap(beads_i: np.ndarray, beads_j: np.ndarray, desc: np.ndarray) -> np.ndarray:
+    """Lower bound (P,) on the closest bead-centre distance of each pair
+    configuration desc (P, 7) = (d, q) (body j at d with orientation q in
+    body i's frame)."""
+    hi, ki, Ri, Hi = shells(beads_i)
+    hj, kj, Rj, Hj = shells(beads_j)
+    desc = np.atleast_2d(np.asarray(desc, np.float64))
+    d = desc[:, :3]
+    q = desc[:, 3:] / np.linalg.norm(desc[:, 3:], axis=1, keepdims=True)
+    R = np.stack([frames.qrotate(q, np.broadcast_to(e, (len(q), 3))) for e in np.eye(3)], axis=2)
+    gb = box_gap(hi, hj, d, R)
+    ei = np.broadcast_to(np.eye(3)[ki], d.shape)
+    ej = R[:, :, kj]
+    gc = np.atleast_1d(segment_distance(-Hi * ei, Hi * ei, d - Hj * ej, d + Hj * ej)) - Ri - Rj
+    return np.maximum(gb, gc)

@@ -29,7 +29,7 @@ SIGNATURES = {
     "rb_ctx_set_hphc": (C.c_int, [P, C.c_double, C.c_double, C.c_double, C.c_double]),
     "rb_pairlist_workspace_bytes": (SZ, [I32, DP, F64]),
     "rb_pairlist_build": (C.c_int, [I32, P, DP, F64, P, P, I32, P, P, C.c_int, P, SZ, P]),
-    "rb_pair_descriptors": (C.c_int, [I32, P, P, DP, P, P, I32, F32, F32, P, P, P, P, P]),
+    "rb_pair_descriptors": (C.c_int, [I32, P, P, DP, P, P, I32, F32, F32, P, P, P, P, P, P, F32, F32, P]),
     "rb_bead_pair_eval": (C.c_int, [P, I64, P, I32, I32, P, P, P]),
     "rb_bead_pair_forces": (C.c_int, [P, I32, P, P, P, DP, P, P, P, P, I32, P, P, P]),
     "rb_bead_pair_forces_screened": (C.c_int, [P, I32, P, P, P, DP, P, P, P, I32, F64, P, P, P, P, P, P, P]),
@@ -42,6 +42,8 @@ SIGNATURES = {
     "rb_nn_pair_forces": (C.c_int, [P, FP, C.c_int, I32, P, P, P, P, I32, P, P, I32, F32, F32, P, P,
                                     P]),
     "rb_cube_sym_descriptors": (C.c_int, [I64, P, I64, P, P, I64, P, P, P]),
+    "rb_cyl_sym_descriptors": (C.c_int, [I64, P, I64, P, P, I64, P, P, P]),
+    "rb_nn_pair_forces_cyl": (C.c_int, [P, FP, C.c_int, I32, P, P, P, P, I32, P, P, I32, F32, F32, P, P, P]),
     "rb_nn_pair_grad_sym": (C.c_int, [P, FP, C.c_int, I64, P, P, P, P, P, P, P, P]),
     "rb_nn_pair_forces_sym": (C.c_int, [P, FP, C.c_int, I32, P, P, P, P, I32, P, P, P, P, I32, F32, F32, P, P,
                                         P]),

@@ -119,10 +119,15 @@ def rb_pairlist_build(x, box, r_list, pair_i, pair_j, x_ref, flags, mode, ws):
           "rb_pairlist_build")
 
 
-def rb_pair_descriptors(x, q, box, pair_i, pair_j, d_min, desc, idx_nn, idx_bead, flags, d_max=0.0):
+def rb_pair_descriptors(x, q, box, pair_i, pair_j, d_min, desc, idx_nn, idx_bead, flags, d_max=0.0, ctx=None,
+                        types=None, gap_min=0.0, gap_max=0.0):
+    """ctx (Ctx) and types (n int32) switch on the routing by the shells'
+    lower bound on the closest bead distance (gap_min, gap_max)."""
     n = x.shape[1]
     maxp = pair_i.numel()
     _, bp = _box(box)
+    if (ctx is None) != (types is None):
+        raise ValueError("ctx and types go together")
     check(lib().rb_pair_descriptors(n, _ptr(x, torch.float64, (3, n), "x"),
                                     _ptr(q, torch.float64, (4, n), "q"), bp,
                                     _ptr(pair_i, torch.int32, name="pair_i"),
@@ -130,7 +135,10 @@ def rb_pair_descriptors(x, q, box, pair_i, pair_j, d_min, desc, idx_nn, idx_bead
                                     _ptr(desc, torch.float32, (7, maxp), "desc"),
                                     _ptr(idx_nn, torch.int32, (maxp,), "idx_nn"),
                                     _ptr(idx_bead, torch.int32, (maxp,), "idx_bead"),
-                                    _ptr(flags, torch.int32, (RB_NFLAGS,), "flags"), _stream()),
+                                    _ptr(flags, torch.int32, (RB_NFLAGS,), "flags"),
+                                    None if ctx is None else ctx.handle,
+                                    _ptr(types, torch.int32, (n,), "types", optional=True), float(gap_min),
+                                    float(gap_max), _stream()),
           "rb_pair_descriptors")
 
 
@@ -253,20 +261,46 @@ def rb_nn_pair_forces(params, norm, precision, q, pair_i, pair_j, desc, idx, cou
           "rb_nn_pair_forces")
 
 
-def rb_cube_sym_descriptors(desc, sym, jac, idx=None, count_dev=None, max_count=None):
-    """Symmetry-reduced cube-pair descriptors of desc's pairs (all of them,
-    or idx[0 .. *count_dev) compacted to rows 0 .. count with row stride
-    max_count)."""
+def _sym_descriptors(fn, name, desc, sym, jac, idx, count_dev, max_count):
     stride = desc.shape[1]
     m = int(max_count if count_dev is not None else stride)
     if sym.shape != (7, m) or jac.shape != (49, m):
         raise ValueError(f"sym must be (7, {m}) and jac (49, {m})")
-    check(lib().rb_cube_sym_descriptors(stride if count_dev is None else 0, _ptr(desc, torch.float32, name="desc"),
-                                        stride, _ptr(idx, torch.int32, name="idx", optional=True),
-                                        _ptr(count_dev, torch.int32, name="count_dev", optional=True), m,
-                                        _ptr(sym, torch.float32, (7, m), "sym"),
-                                        _ptr(jac, torch.float32, (49, m), "jac"), _stream()),
-          "rb_cube_sym_descriptors")
+    check(fn(stride if count_dev is None else 0, _ptr(desc, torch.float32, name="desc"), stride,
+             _ptr(idx, torch.int32, name="idx", optional=True),
+             _ptr(count_dev, torch.int32, name="count_dev", optional=True), m,
+             _ptr(sym, torch.float32, (7, m), "sym"), _ptr(jac, torch.float32, (49, m), "jac"), _stream()), name)
+
+
+def rb_cube_sym_descriptors(desc, sym, jac, idx=None, count_dev=None, max_count=None):
+    """Symmetry-reduced cube-pair descriptors of desc's pairs (all of them,
+    or idx[0 .. *count_dev) compacted to rows 0 .. count with row stride
+    max_count)."""
+    _sym_descriptors(lib().rb_cube_sym_descriptors, "rb_cube_sym_descriptors", desc, sym, jac, idx, count_dev,
+                     max_count)
+
+
+def rb_cyl_sym_descriptors(desc, sym, jac, idx=None, count_dev=None, max_count=None):
+    """Four-number cylinder-pair descriptors of desc's pairs, laid out as
+    rb_cube_sym_descriptors."""
+    _sym_descriptors(lib().rb_cyl_sym_descriptors, "rb_cyl_sym_descriptors", desc, sym, jac, idx, count_dev,
+                     max_count)
+
+
+def rb_nn_pair_forces_cyl(params, norm, precision, q, pair_i, pair_j, desc, idx, count_dev, max_count,
+                          sw_lo, sw_hi, acc, flags):
+    n = q.shape[1]
+    _, npn = _norm(norm)
+    check(lib().rb_nn_pair_forces_cyl(_ptr(params, torch.float32, (RB_MLP_NPARAMS,), "params"), npn, precision, n,
+                                      _ptr(q, torch.float64, (4, n), "q"),
+                                      _ptr(pair_i, torch.int32, name="pair_i"),
+                                      _ptr(pair_j, torch.int32, name="pair_j"),
+                                      _ptr(desc, torch.float32, name="desc"), desc.shape[1],
+                                      _ptr(idx, torch.int32, name="idx", optional=True),
+                                      _ptr(count_dev, torch.int32, name="count_dev"), int(max_count),
+                                      float(sw_lo), float(sw_hi), _ptr(acc, torch.int64, (acc_len(n),), "acc"),
+                                      _ptr(flags, torch.int32, (RB_NFLAGS,), "flags"), _stream()),
+          "rb_nn_pair_forces_cyl")
 
 
 def rb_nn_pair_grad_sym(params, norm, precision: int, desc, sym, jac, gE=None, energy=None, dE_ddesc=None,

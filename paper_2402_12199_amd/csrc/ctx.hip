@@ -118,6 +118,29 @@ extern "C" int rb_ctx_create(rb_ctx **out, int32_t n_types, const int32_t *n_bea
         c->dev.t.hx[t] = h[0];
         c->dev.t.hy[t] = h[1];
         c->dev.t.hz[t] = h[2];
+        // capsule along the axis of the largest half extent: radius = largest
+        // distance of a bead from the axis, half-length = smallest that keeps
+        // every bead inside (rounded outward in FP32)
+        const int k = h[2] >= h[1] && h[2] >= h[0] ? 2 : (h[1] >= h[0] ? 1 : 0);
+        const float *bt = beads + 3 * (o - n_beads[t]);
+        double R2 = 0.0;
+        for (int m = 0; m < n_beads[t]; ++m) {
+            double r2 = 0.0;
+            for (int a = 0; a < 3; ++a)
+                if (a != k) r2 += (double)bt[3 * m + a] * bt[3 * m + a];
+            if (r2 > R2) R2 = r2;
+        }
+        double H = 0.0;
+        for (int m = 0; m < n_beads[t]; ++m) {
+            double r2 = 0.0;
+            for (int a = 0; a < 3; ++a)
+                if (a != k) r2 += (double)bt[3 * m + a] * bt[3 * m + a];
+            const double hm = fabs((double)bt[3 * m + k]) - sqrt(fmax(R2 - r2, 0.0));
+            if (hm > H) H = hm;
+        }
+        c->dev.t.cax[t] = k;
+        c->dev.t.cR[t] = nextafterf((float)sqrt(R2), 1e30f);
+        c->dev.t.cH[t] = H > 0.0 ? nextafterf((float)H, 1e30f) : 0.f;
     }
     c->dev.t.n_types = n_types;
     int rc_ = RB_OK;

@@ -3,11 +3,15 @@
 // Paper section 2: the configuration of a pair is fixed by the position and
 // the orientation of body j in the frame of body i.  Here that is
 // d = R_i^T minimg(x_j - x_i) and q = q_i^* q_j (R(q) = R_i^T R_j), computed
-// in FP64 from the state and stored in FP32 (7 x max_pairs, SoA).  Pairs with
-// |d| < d_min lie outside the network's training domain and are routed to
-// the bead sum; pairs with d_min <= |d| < d_max go to the network; pairs
-// beyond d_max (zero switched network energy) go to neither.
+// in FP64 from the state and stored in FP32 (7 x max_pairs, SoA).  Pairs
+// outside the network's training domain go to the bead sum: |d| < d_min,
+// and, with shells given, pairs whose lower bound on the closest bead
+// distance is below gap_min.  Pairs with d_min <= |d| < d_max and a bound of
+// at least gap_min (and below gap_max) go to the network; pairs beyond
+// d_max (zero switched network energy) or with a bound of gap_max or more
+// (no bead pair within gap_max) go to neither.
 #include "rb_common.hpp"
+#include "shells.hpp"
 
 namespace rb {
 
@@ -37,7 +41,9 @@ __global__ __launch_bounds__(256) void k_descriptors(int32_t n, const double *__
                                                      const int32_t *__restrict__ pi, const int32_t *__restrict__ pj,
                                                      int32_t maxp, float dmin2, float dmax2, float *__restrict__ desc,
                                                      int32_t *__restrict__ idx_nn, int32_t *__restrict__ idx_bead,
-                                                     int32_t *__restrict__ flags) {
+                                                     int32_t *__restrict__ flags, Templates T,
+                                                     const int32_t *__restrict__ type, double gap_min,
+                                                     double gap_max) {
     // the first round's pair indices are requested together with the count
     // (any slot below the capacity may be read; only live ones are used)
     const int p0 = blockIdx.x * blockDim.x + threadIdx.x;
@@ -78,8 +84,18 @@ __global__ __launch_bounds__(256) void k_descriptors(int32_t n, const double *__
             desc[5 * maxp + p] = (float)ry;
             desc[6 * maxp + p] = (float)rz;
             const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-            to_nn = r2 >= (double)dmin2 && r2 < (double)dmax2;
-            to_bead = r2 < (double)dmin2;
+            const bool in_range = r2 < (double)dmax2;
+            bool near = r2 < (double)dmin2, far = false;
+            if (type && in_range && !near) {
+                double Rr[9];
+                quat_to_rot<double>(rw, rx, ry, rz, Rr);
+                const double G = shell_gap(T, type[i], type[j], d, Rr);
+                near = G < gap_min;
+                far = G >= gap_max;
+            }
+            to_nn = in_range && !near && !far;
+            to_bead = in_range && near;
+            if (!type) to_bead = near;    // no shells: every pair below d_min, as before
         }
         wave_append(live && to_nn, p, idx_nn, flags + RB_FLAG_NNN);
         wave_append(live && to_bead, p, idx_bead, flags + RB_FLAG_NBEAD);
@@ -93,17 +109,23 @@ using namespace rb;
 extern "C" int rb_pair_descriptors(int32_t n, const double *x, const double *q, const double *box,
                                    const int32_t *pair_i, const int32_t *pair_j, int32_t max_pairs, float d_min,
                                    float d_max, float *desc, int32_t *idx_nn, int32_t *idx_bead, int32_t *flags,
+                                   const rb_ctx *ctx, const int32_t *type, float gap_min, float gap_max,
                                    void *stream) {
     RB_REQUIRE(x && q && box && pair_i && pair_j && desc && idx_nn && idx_bead && flags,
                "rb_pair_descriptors: null argument");
+    RB_REQUIRE(!ctx == !type, "rb_pair_descriptors: ctx and type go together");
     RB_REQUIRE(n > 0 && max_pairs > 0, "rb_pair_descriptors: sizes must be > 0");
     RB_REQUIRE(box[0] > 0 && box[1] > 0 && box[2] > 0, "rb_pair_descriptors: box must be > 0");
     hipStream_t st = (hipStream_t)stream;
     k_route_reset<<<1, 1, 0, st>>>(flags);
     const float dm2 = d_min > 0 ? d_min * d_min : 0.f;
     const float dx2 = d_max > 0 ? d_max * d_max : 3.0e38f;
+    Templates T = {};
+    if (ctx) T = ctx->dev.t;
+    const double gmax = gap_max > 0.f ? (double)gap_max : 1e300;
     k_descriptors<<<grid_for(max_pairs, 256, 4096), 256, 0, st>>>(n, x, q, box[0], box[1], box[2], pair_i, pair_j,
-                                                                  max_pairs, dm2, dx2, desc, idx_nn, idx_bead, flags);
+                                                                  max_pairs, dm2, dx2, desc, idx_nn, idx_bead, flags,
+                                                                  T, type, (double)gap_min, gmax);
     RB_LAUNCH_CHECK("rb_pair_descriptors");
     return RB_OK;
 }

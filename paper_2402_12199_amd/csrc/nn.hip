@@ -13,6 +13,7 @@
 // FP32 path: the same tiling on v_mfma_f32_16x16x4_f32, weights read from
 // global memory (they stay in the caches), activations and derivatives in
 // FP32.
+#include "cyl_form.hpp"
 #include "nn_tile.hpp"
 
 namespace rb {
@@ -44,21 +45,58 @@ struct NNArgs {
     // desc then holds the pairs' (d, q) for the forces.  Null: plain (d, q).
     const float *sym;
     const float *jac;
+    // cylinder pairs: the network sees the four-number form of desc's
+    // (d, q), computed here together with its Jacobian (no sym/jac arrays)
+    int cyl;
 };
+
+// Whether the network's input differs from the pair's (d, q).
+__device__ inline bool reduced_input(const NNArgs &a) { return a.sym || a.cyl; }
+
+// |d| from the network input u of a pair: the cube form's first three
+// numbers are a signed permutation of d, the cylinder form starts with
+// (d_x^2 + d_y^2, d_z^2).
+__device__ inline float centre_distance(const NNArgs &a, const float u[kIn]) {
+    return a.cyl ? sqrtf(u[0] + u[1]) : sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+}
 
 // The network's input of launch row `row` (pair pid).
 __device__ inline void net_input(const NNArgs &a, int64_t row, int64_t pid, bool live, float u[kIn]) {
+    if (a.cyl && live) {
+        double ud[kIn], s[kIn];
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) ud[k] = a.desc[k * a.stride + pid];
+        cyl_features(ud, s);
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) u[k] = (float)s[k];
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < kIn; ++k)
         u[k] = !live ? (k == 3 ? 1.f : 0.f) : (a.sym ? a.sym[k * a.P + row] : a.desc[k * a.stride + pid]);
 }
 
-// dE/ds -> dE/du through the descriptor's Jacobian (symmetry-reduced form).
-__device__ inline void sym_chain(const NNArgs &a, int64_t row, float gu[kIn]) {
-    if (!a.jac) return;
+// dE/ds -> dE/du through the descriptor's Jacobian (symmetry-reduced and
+// cylinder forms).
+__device__ inline void sym_chain(const NNArgs &a, int64_t row, int64_t pid, float gu[kIn]) {
+    if (!a.jac && !a.cyl) return;
     float gs[kIn];
 #pragma unroll
     for (int r = 0; r < kIn; ++r) gs[r] = gu[r];
+    if (a.cyl) {
+        double ud[kIn], J[kIn][kIn];
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) ud[k] = a.desc[k * a.stride + pid];
+        cyl_jacobian(ud, J);
+#pragma unroll
+        for (int m = 0; m < kIn; ++m) {
+            float v = 0.f;
+#pragma unroll
+            for (int r = 0; r < kIn; ++r) v = fmaf((float)J[r][m], gs[r], v);
+            gu[m] = v;
+        }
+        return;
+    }
 #pragma unroll
     for (int m = 0; m < kIn; ++m) {
         float v = 0.f;
@@ -208,7 +246,7 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
         if (MODE == kGrad && a.gE) seed = live ? a.gE[pid] : 0.f;
         if (MODE == kForces) {
             float dsdr;
-            seed = smooth_switch(sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]), a.sw_lo, a.sw_hi, dsdr);
+            seed = smooth_switch(centre_distance(a, u), a.sw_lo, a.sw_hi, dsdr);
         }
         EpiIn ein;
         if (MODE == kForces) ein = load_epi(a, pid, live && g == 0);
@@ -218,7 +256,7 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
             E = tile_bf16<MODE != kEval>(L, a.nm, u, seed, gu);
         else
             E = tile_fp32<MODE != kEval>(L, L, a.params, a.nm, u, seed, gu);
-        if (MODE != kEval && live && g == 0) sym_chain(a, row, gu);
+        if (MODE != kEval && live && g == 0) sym_chain(a, row, pid, gu);
         if (MODE == kForces) {
             // every lane takes part in the shuffles below; the results of
             // the lanes of groups 1..3 and of dead rows are discarded
@@ -235,7 +273,7 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
                 for (int k = 0; k < kIn; ++k) a.dEdu[k * a.P + pid] = gu[k];
             if (a.ft) {
                 float ft[9], ud[kIn];
-                if (a.sym)
+                if (reduced_input(a))
 #pragma unroll
                     for (int k = 0; k < kIn; ++k) ud[k] = a.desc[k * a.stride + pid];
                 else
@@ -287,7 +325,7 @@ __device__ inline TileIn tile_in(const NNArgs &a, int64_t row, int64_t count, bo
     if (MODE == kGrad && a.gE) t.seed = t.live ? a.gE[t.pid] : 0.f;
     if (MODE == kForces) {
         float dsdr;
-        t.seed = smooth_switch(sqrtf(t.u[0] * t.u[0] + t.u[1] * t.u[1] + t.u[2] * t.u[2]), a.sw_lo, a.sw_hi, dsdr);
+        t.seed = smooth_switch(centre_distance(a, t.u), a.sw_lo, a.sw_hi, dsdr);
         t.ein = load_epi(a, t.pid, t.live && epi);
     }
     return t;
@@ -304,7 +342,7 @@ __device__ inline void store_grad(const NNArgs &a, const TileIn &t, const float 
     if (a.ft) {
         float ft[9], ud[kIn];
 #pragma unroll
-        for (int k = 0; k < kIn; ++k) ud[k] = a.sym ? a.desc[k * a.stride + pid] : t.u[k];
+        for (int k = 0; k < kIn; ++k) ud[k] = reduced_input(a) ? a.desc[k * a.stride + pid] : t.u[k];
         pair_ft_from_grad(ud, gu, ft);
 #pragma unroll
         for (int k = 0; k < 9; ++k) a.ft[k * a.P + pid] = ft[k];
@@ -328,7 +366,7 @@ __device__ inline void put_epi(const NNArgs &a, EpiLds &e, const EpiIn &in, cons
 #pragma unroll
     for (int c = 0; c < 4; ++c) e.q[c][n] = in.q[c];
 #pragma unroll
-    for (int k = 0; k < kIn; ++k) e.d[k][n] = a.sym && live ? a.desc[k * a.stride + pid] : u[k];
+    for (int k = 0; k < kIn; ++k) e.d[k][n] = reduced_input(a) && live ? a.desc[k * a.stride + pid] : u[k];
 }
 
 // Forces epilogue of the four-wave form: the group's 16 pairs are shared
@@ -441,10 +479,10 @@ __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
         const float E = tile_bf16_wide<true>(L, X[grp], a.nm, t.u, t.seed, gu, v);
         // the group's results are the same in its four waves
         if (MODE == kForces) {
-            if (a.jac) {
+            if (a.jac || a.cyl) {
                 // dE/du = J^T dE/ds once per pair, shared through LDS
                 if (v == 0 && g == 0 && t.live) {
-                    sym_chain(a, t.row, gu);
+                    sym_chain(a, t.row, t.pid, gu);
 #pragma unroll
                     for (int k = 0; k < kIn; ++k) X[grp].red[0][1 + k][n] = gu[k];
                 }
@@ -454,7 +492,7 @@ __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
             }
             forces_epilogue_wide(a, EL[grp], gu, E, t.live, v, g, n, wacc[wave], bad, ovf);
         } else if (v == 0 && t.live && g == 0) {
-            sym_chain(a, t.row, gu);
+            sym_chain(a, t.row, t.pid, gu);
             store_grad(a, t, gu, E);
         }
         base += (int64_t)gridDim.x * kWideGroups;
@@ -636,5 +674,35 @@ extern "C" int rb_nn_pair_forces_sym(const float *params, const float *norm, int
     a.flags = flags;
     a.sym = sym;
     a.jac = jac;
+    return launch<kForces>(a, precision, max_count, (hipStream_t)stream);
+}
+
+extern "C" int rb_nn_pair_forces_cyl(const float *params, const float *norm, int precision, int32_t n,
+                                     const double *q, const int32_t *pair_i, const int32_t *pair_j,
+                                     const float *desc, int32_t desc_stride, const int32_t *idx,
+                                     const int32_t *count_dev, int32_t max_count, float sw_lo, float sw_hi,
+                                     int64_t *acc, int32_t *flags, void *stream) {
+    RB_REQUIRE(params && norm && q && pair_i && pair_j && desc && count_dev && acc && flags,
+               "rb_nn_pair_forces_cyl: null argument");
+    RB_REQUIRE(precision == RB_PREC_BF16 || precision == RB_PREC_FP32, "rb_nn_pair_forces_cyl: bad precision");
+    RB_REQUIRE(n > 0 && max_count >= 0 && desc_stride >= max_count, "rb_nn_pair_forces_cyl: bad sizes");
+    if (max_count == 0) return RB_OK;
+    NNArgs a = {};
+    a.params = params;
+    a.nm = norm_from_host(norm);
+    a.P = max_count;
+    a.desc = desc;
+    a.stride = desc_stride;
+    a.idx = idx;
+    a.count_dev = count_dev;
+    a.q = q;
+    a.n = n;
+    a.pi = pair_i;
+    a.pj = pair_j;
+    a.sw_lo = sw_lo;
+    a.sw_hi = sw_hi;
+    a.acc = acc;
+    a.flags = flags;
+    a.cyl = 1;
     return launch<kForces>(a, precision, max_count, (hipStream_t)stream);
 }

@@ -36,6 +36,10 @@ struct Templates {
     int n[kMaxTypes];
     int off[kMaxTypes];
     float hx[kMaxTypes], hy[kMaxTypes], hz[kMaxTypes];   // half extents of the bead-centre box
+    // capsule around the bead centres along body axis cax: radius cR, the
+    // segment from -cH to +cH on that axis
+    int cax[kMaxTypes];
+    float cR[kMaxTypes], cH[kMaxTypes];
     int n_types;
 };
 

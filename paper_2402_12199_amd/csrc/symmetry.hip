@@ -22,6 +22,7 @@
 // their Jacobian rows follow the branch the pair takes without a separate
 // derivation.
 #include "rb_common.hpp"
+#include "cyl_form.hpp"
 
 namespace rb {
 
@@ -217,9 +218,52 @@ __global__ __launch_bounds__(256) void k_cube_sym(const float *__restrict__ desc
     }
 }
 
+// Cylinder pairs: k-th listed pair's four-number form and its Jacobian,
+// same layout as k_cube_sym.
+__global__ __launch_bounds__(256) void k_cyl_sym(const float *__restrict__ desc, int64_t stride,
+                                                 const int32_t *__restrict__ idx, const int32_t *__restrict__ count_dev,
+                                                 int64_t n_pairs, int64_t max_count, float *__restrict__ sym,
+                                                 float *__restrict__ jac) {
+    int64_t count = n_pairs;
+    if (count_dev) {
+        const int64_t c = *count_dev;
+        count = c < max_count ? c : max_count;
+    }
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t pid = idx ? idx[k] : k;
+        double u[7];
+#pragma unroll
+        for (int m = 0; m < 7; ++m) u[m] = desc[m * stride + pid];
+        double s[7], J[7][7];
+        cyl_features(u, s);
+        cyl_jacobian(u, J);
+#pragma unroll
+        for (int r = 0; r < 7; ++r) sym[r * max_count + k] = (float)s[r];
+#pragma unroll
+        for (int r = 0; r < 7; ++r)
+#pragma unroll
+            for (int m = 0; m < 7; ++m) jac[(r * 7 + m) * max_count + k] = (float)J[r][m];
+    }
+}
+
 }  // namespace rb
 
 using namespace rb;
+
+extern "C" int rb_cyl_sym_descriptors(int64_t n_pairs, const float *desc, int64_t stride, const int32_t *idx,
+                                      const int32_t *count_dev, int64_t max_count, float *sym, float *jac,
+                                      void *stream) {
+    RB_REQUIRE(n_pairs >= 0 && max_count >= 0 && stride >= 0, "rb_cyl_sym_descriptors: negative size");
+    if ((count_dev ? max_count : n_pairs) == 0) return RB_OK;
+    RB_REQUIRE(desc && sym && jac, "rb_cyl_sym_descriptors: null argument");
+    RB_REQUIRE(count_dev || n_pairs <= max_count, "rb_cyl_sym_descriptors: n_pairs > max_count");
+    const int64_t work = count_dev ? max_count : n_pairs;
+    k_cyl_sym<<<grid_for(work, 256, 4096), 256, 0, (hipStream_t)stream>>>(desc, stride, idx, count_dev, n_pairs,
+                                                                         max_count, sym, jac);
+    RB_LAUNCH_CHECK("rb_cyl_sym_descriptors");
+    return RB_OK;
+}
 
 extern "C" int rb_cube_sym_descriptors(int64_t n_pairs, const float *desc, int64_t stride, const int32_t *idx,
                                        const int32_t *count_dev, int64_t max_count, float *sym, float *jac,

@@ -35,6 +35,16 @@ class NNModel:
     sw_lo: float = 0.0             # energy switch (sw_hi <= sw_lo: off)
     sw_hi: float = 0.0
     sym: bool = False              # network takes the symmetry-reduced cube-pair descriptor
+    form: str = "dq"               # network input: "dq" (d, q), "cube" (= sym) or "cyl" (four-number form)
+    gap_min: float | None = None   # shells' bound on the closest bead distance below which the bead sum takes over
+    gap_max: float | None = None   # bound at or above which a pair is skipped (no bead pair within it)
+
+    def __post_init__(self):
+        if self.sym:
+            self.form = "cube"
+        self.sym = self.form == "cube"
+        if self.form not in ("dq", "cube", "cyl"):
+            raise ValueError(f"unknown network input form {self.form}")
 
 
 class RigidSystem:
@@ -127,14 +137,26 @@ class RigidSystem:
             self.sym = torch.zeros((7, self.max_pairs), dtype=torch.float32, device=self.dev)
             self.jac = torch.zeros((49, self.max_pairs), dtype=torch.float32, device=self.dev)
 
+    def route(self, d_min, d_max, gap_min=None, gap_max=None):
+        """Descriptors of the listed pairs and their routing (network, bead
+        sum, neither); with gap_min the shells' bound on the closest bead
+        distance routes as well."""
+        shells = gap_min is not None
+        abi.rb_pair_descriptors(self.x, self.q, self.box, self.pair_i, self.pair_j, d_min, self.desc, self.idx_nn,
+                                self.idx_bead, self.flags, d_max=d_max, ctx=self.ctx if shells else None,
+                                types=self.types if shells else None, gap_min=gap_min if shells else 0.0,
+                                gap_max=gap_max if shells and gap_max is not None else 0.0)
+
     def nn_forces(self):
         """Descriptors, routing, network forces of the routed pairs and the
         bead sum of the fallback pairs, all into the accumulator."""
         m = self.nn
-        abi.rb_pair_descriptors(self.x, self.q, self.box, self.pair_i, self.pair_j, m.d_min, self.desc,
-                                self.idx_nn, self.idx_bead, self.flags,
-                                d_max=m.sw_hi if m.sw_hi > m.sw_lo else 0.0)
-        if m.sym:
+        self.route(m.d_min, m.sw_hi if m.sw_hi > m.sw_lo else 0.0, m.gap_min, m.gap_max)
+        if m.form == "cyl":
+            abi.rb_nn_pair_forces_cyl(m.params, m.norm, m.precision, self.q, self.pair_i, self.pair_j, self.desc,
+                                      self.idx_nn, self.flags[abi.RB_FLAG_NNN:], self.max_pairs, m.sw_lo, m.sw_hi,
+                                      self.acc, self.flags)
+        elif m.form == "cube":
             abi.rb_cube_sym_descriptors(self.desc, self.sym, self.jac, self.idx_nn, self.flags[abi.RB_FLAG_NNN:],
                                         self.max_pairs)
             abi.rb_nn_pair_forces_sym(m.params, m.norm, m.precision, self.q, self.pair_i, self.pair_j, self.desc,
@@ -258,15 +280,16 @@ class RigidSystem:
         torch.cuda.current_stream().wait_stream(side)
         return g
 
-    def pair_configurations(self, d_min: float, d_max: float) -> torch.Tensor:
-        """Descriptors (7, m) of the listed pairs with d_min <= |d| < d_max
-        (training data drawn from the dynamics; uses the routing buffers)."""
+    def pair_configurations(self, d_min: float, d_max: float, gap_min=None, gap_max=None) -> torch.Tensor:
+        """Descriptors (7, m) of the listed pairs the router sends to the
+        network: d_min <= |d| < d_max and, with gap_min, a shells' bound on
+        the closest bead distance in [gap_min, gap_max) (training data drawn
+        from the dynamics; uses the routing buffers)."""
         if self.desc is None:
             self.desc = torch.zeros((7, self.max_pairs), dtype=torch.float32, device=self.dev)
             self.idx_nn = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
             self.idx_bead = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
-        abi.rb_pair_descriptors(self.x, self.q, self.box, self.pair_i, self.pair_j, d_min, self.desc, self.idx_nn,
-                                self.idx_bead, self.flags, d_max=d_max)
+        self.route(d_min, d_max, gap_min, gap_max)
         m = int(self.flags[abi.RB_FLAG_NNN].item())
         idx = torch.sort(self.idx_nn[:m].long()).values   # list order, independent of append order
         return self.desc[:, idx]

@@ -34,22 +34,35 @@ def make_norm_sym(d_cut: float, e_shift: float = 0.0, e_scale: float = 1.0, d_ga
     return np.concatenate([shift, scale, [e_shift, e_scale]]).astype(np.float32)
 
 
-def sym_descriptors(desc: torch.Tensor, chunk: int = 1 << 18, with_jac: bool = True):
+def make_norm_features(s: np.ndarray, e_shift: float = 0.0, e_scale: float = 1.0) -> np.ndarray:
+    """Normalisation of a reduced descriptor from its training values s
+    (P, 7): each used input shifted by its mean and scaled to unit spread;
+    inputs that are identically zero stay zero."""
+    s = np.asarray(s, np.float64)
+    mean, std = s.mean(0), s.std(0)
+    used = std > 0
+    shift = np.where(used, mean, 0.0)
+    scale = np.where(used, 1.0 / np.where(used, std, 1.0), 0.0)
+    return np.concatenate([shift, scale, [e_shift, e_scale]]).astype(np.float32)
+
+
+def sym_descriptors(desc: torch.Tensor, chunk: int = 1 << 18, with_jac: bool = True, form: str = "cube"):
     """(sym (7, P), jac (49, P) or None) of pair descriptors desc (7, P) on
-    the device (rb_cube_sym_descriptors), in chunks when the Jacobian is
-    dropped."""
+    the device (rb_cube_sym_descriptors, or rb_cyl_sym_descriptors for
+    form="cyl"), in chunks when the Jacobian is dropped."""
+    fn = {"cube": abi.rb_cube_sym_descriptors, "cyl": abi.rb_cyl_sym_descriptors}[form]
     P = desc.shape[1]
     sym = torch.empty((7, P), dtype=torch.float32, device=desc.device)
     if with_jac:
         jac = torch.empty((49, P), dtype=torch.float32, device=desc.device)
-        abi.rb_cube_sym_descriptors(desc, sym, jac)
+        fn(desc, sym, jac)
         return sym, jac
     for s0 in range(0, P, chunk):
         d = desc[:, s0:s0 + chunk].contiguous()
         m = d.shape[1]
         sy = torch.empty((7, m), dtype=torch.float32, device=desc.device)
         jc = torch.empty((49, m), dtype=torch.float32, device=desc.device)
-        abi.rb_cube_sym_descriptors(d, sy, jc)
+        fn(d, sy, jc)
         sym[:, s0:s0 + m] = sy
     return sym, None
 

@@ -27,7 +27,7 @@ import numpy as np
 import torch
 
 from . import abi
-from .nn import Trainer, label_pairs, make_norm, make_norm_sym, sym_descriptors
+from .nn import Trainer, label_pairs, make_norm, make_norm_features, make_norm_sym, sym_descriptors
 
 
 def make_dataset(ctx: abi.Ctx, n: int, seed: int, d_lo: float, d_hi: float, r_rej: float = 0.8,
@@ -57,9 +57,12 @@ def make_dataset(ctx: abi.Ctx, n: int, seed: int, d_lo: float, d_hi: float, r_re
 
 
 def evaluate(params, norm, precision, desc: np.ndarray, lab: np.ndarray, chunk: int = 1 << 18,
-             sym: bool = False) -> dict:
+             sym: bool = False, form: str | None = None) -> dict:
     """Held-out errors of the network against bead labels (body i frame);
-    sym: the network takes the symmetry-reduced cube-pair descriptor."""
+    form: the network's input, "dq" (the pair descriptor), "cube" (the
+    symmetry-reduced cube-pair descriptor; sym=True) or "cyl" (the
+    four-number cylinder-pair form)."""
+    form = form or ("cube" if sym else "dq")
     P = len(desc)
     E = np.empty(P, np.float32)
     ft = np.empty((P, 9), np.float32)
@@ -67,8 +70,8 @@ def evaluate(params, norm, precision, desc: np.ndarray, lab: np.ndarray, chunk: 
         d = torch.tensor(np.ascontiguousarray(desc[s:s + chunk].T), device="cuda")
         e = torch.empty(d.shape[1], device="cuda")
         f = torch.empty((9, d.shape[1]), device="cuda")
-        if sym:
-            sy, jc = sym_descriptors(d)
+        if form != "dq":
+            sy, jc = sym_descriptors(d, form=form)
             abi.rb_nn_pair_grad_sym(params, norm, precision, d, sy, jc, None, e, None, f)
         else:
             abi.rb_nn_pair_grad(params, norm, precision, d, None, e, None, f)
@@ -98,7 +101,7 @@ def label_set(ctx: abi.Ctx, desc: np.ndarray, r_rej: float = 0.8, type_i: int = 
 
 def fit(desc: np.ndarray, lab: np.ndarray, tdesc: np.ndarray, tlab: np.ndarray, d_cut: float, epochs: int,
         seed: int, batch: int = 8192, lr: float = 1e-3, precision: int = abi.RB_PREC_BF16, init_seed: int = 1003,
-        log=None, name: str = "", fm: dict | None = None, sym: bool = False) -> dict:
+        log=None, name: str = "", fm: dict | None = None, sym: bool = False, form: str | None = None) -> dict:
     """Train a fresh network (Xavier init) on energies (and, with fm =
     dict(lam_f, lam_t[, fd_step]) or dict(weight[, fd_step]), on the bead
     forces and torques too; `weight` sets lam_f, lam_t to weight over the
@@ -106,13 +109,18 @@ def fit(desc: np.ndarray, lab: np.ndarray, tdesc: np.ndarray, tlab: np.ndarray, 
     after.  sym: train on the symmetry-reduced cube-pair descriptor
     (supplementary section 1; energy loss only)."""
     from synth import sampling
-    if sym and fm is not None:
+    form = form or ("cube" if sym else "dq")
+    if form != "dq" and fm is not None:
         raise ValueError("force matching takes the (d, q) descriptor")
     e = lab[:, 0].astype(np.float64)
-    norm = (make_norm_sym if sym else make_norm)(d_cut, float(e.mean()), float(e.std()))
     d_dev = torch.tensor(np.ascontiguousarray(desc.T), device="cuda")
-    if sym:
-        d_dev = sym_descriptors(d_dev, with_jac=False)[0]
+    if form == "cyl":
+        d_dev = sym_descriptors(d_dev, with_jac=False, form="cyl")[0]
+        norm = make_norm_features(d_dev.cpu().numpy().T, float(e.mean()), float(e.std()))
+    else:
+        norm = (make_norm_sym if form == "cube" else make_norm)(d_cut, float(e.mean()), float(e.std()))
+        if form == "cube":
+            d_dev = sym_descriptors(d_dev, with_jac=False)[0]
     y_dev = torch.tensor(lab[:, 0].copy(), device="cuda")
     ft_dev = None
     if fm is not None:   # F_j and tau_j columns of the bead labels
@@ -123,7 +131,7 @@ def fit(desc: np.ndarray, lab: np.ndarray, tdesc: np.ndarray, tlab: np.ndarray, 
         ft_dev = torch.tensor(np.ascontiguousarray(ft.T.astype(np.float32)), device="cuda")
     tr = Trainer(sampling.xavier_params(init_seed), norm, precision=precision, batch=batch, lr=lr, fm=fm)
     g = sampling.rng(seed + 7)
-    before = evaluate(tr.params, norm, precision, tdesc, tlab, sym=sym)
+    before = evaluate(tr.params, norm, precision, tdesc, tlab, form=form)
     hist = []
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -134,8 +142,9 @@ def fit(desc: np.ndarray, lab: np.ndarray, tdesc: np.ndarray, tlab: np.ndarray, 
                 (f" matching {tr.fm_loss:.4f}" if fm is not None else ""))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
-    after = evaluate(tr.params, norm, precision, tdesc, tlab, sym=sym)
-    return dict(shape=name, params=tr.params, norm=norm, precision=precision, d_cut=d_cut, epochs=epochs, fm=fm, sym=sym,
+    after = evaluate(tr.params, norm, precision, tdesc, tlab, form=form)
+    return dict(shape=name, params=tr.params, norm=norm, precision=precision, d_cut=d_cut, epochs=epochs, fm=fm,
+                sym=form == "cube", form=form,
                 steps=tr.t, batch=batch, n_train=int(len(desc)), n_test=int(len(tdesc)), train_s=t_train,
                 samples_per_s=tr.t * batch / max(t_train, 1e-9), loss_history=hist, untrained=before,
                 trained=after)
@@ -158,16 +167,19 @@ def train_surrogate(body, n_train: int, n_test: int, epochs: int, seed: int = 10
     return r
 
 
-def md_pair_samples(sysm, dt: float, n: int, every: int, d_min: float, d_max: float, path: str = "bead"):
+def md_pair_samples(sysm, dt: float, n: int, every: int, d_min: float, d_max: float, path: str = "bead",
+                    gap_min=None, gap_max=None):
     """Pair configurations visited by the dynamics: every `every` steps, the
-    descriptors of all listed pairs with d_min <= |d| < d_max, until n are
-    collected (the system must have current forces)."""
+    descriptors of all listed pairs the router sends to the network
+    (d_min <= |d| < d_max; with gap_min, a shells' bound on the closest bead
+    distance in [gap_min, gap_max)), until n are collected (the system must
+    have current forces)."""
     out, have, steps = [], 0, 0
     while have < n:
         for _ in range(every):
             sysm.step(dt, path)
         steps += every
-        d = sysm.pair_configurations(d_min, d_max).cpu().numpy().T
+        d = sysm.pair_configurations(d_min, d_max, gap_min, gap_max).cpu().numpy().T
         out.append(d)
         have += len(d)
     sysm.check_capacity()
@@ -175,19 +187,22 @@ def md_pair_samples(sysm, dt: float, n: int, every: int, d_min: float, d_max: fl
 
 
 def train_surrogate_md(cfg, st, n_train: int, n_test: int, epochs: int, every: int = 10, seed: int = 1006,
-                       r_rej: float = 0.8, log=None, **kw) -> dict:
+                       r_rej: float = 0.8, log=None, gap_min=None, gap_max=None, **kw) -> dict:
     """Surrogate trained on configurations drawn from the bead-path dynamics
     of a workload (paper section 2: training pairs come from composite-body
     simulations).  The held-out set comes from the later part of the same
-    trajectory, after the training snapshots."""
+    trajectory, after the training snapshots.  With gap_min the pairs are
+    those the shells' routing gives the network (see rb_pair_descriptors)."""
     from .md import RigidSystem
     t0 = time.perf_counter()
     b = cfg.body
     sysm = RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"], cfg.box,
                        cfg.r_list, cfg.skin, hphc=cfg.hphc, margin=cfg.bead_margin)
     sysm.init_forces("bead")
-    desc, s_train = md_pair_samples(sysm, cfg.dt, n_train, every, cfg.d_min, cfg.d_cut)
-    tdesc, s_test = md_pair_samples(sysm, cfg.dt, n_test, max(1, every // 2), cfg.d_min, cfg.d_cut)
+    desc, s_train = md_pair_samples(sysm, cfg.dt, n_train, every, cfg.d_min, cfg.d_cut, gap_min=gap_min,
+                                    gap_max=gap_max)
+    tdesc, s_test = md_pair_samples(sysm, cfg.dt, n_test, max(1, every // 2), cfg.d_min, cfg.d_cut, gap_min=gap_min,
+                                    gap_max=gap_max)
     desc, lab = label_set(sysm.ctx, desc, r_rej)
     tdesc, tlab = label_set(sysm.ctx, tdesc, r_rej)
     t_label = time.perf_counter() - t0

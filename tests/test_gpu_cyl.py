@@ -1,0 +1,272 @@
+"""GPU parity of the cylinder-pair four-number descriptor (supplementary
+section 2), of the network gradient and the dynamics forces through it, and
+of the routing by the shells' lower bound on the closest bead distance,
+against the oracle."""
+import numpy as np
+import pytest
+
+from oracle import beads as obeads
+from oracle import cylinder as ocyl
+from oracle import domain as odom
+from oracle import frames as oframes
+from oracle import mlp as omlp
+from synth import configs, sampling
+from tests.tolerances import assert_close
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RTOL = {0: (2e-2, 2e-2), 1: (1e-5, 1e-4)}
+
+
+@pytest.fixture(scope="module")
+def abi():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2402_12199_amd import abi as _abi
+    return _abi
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a), device="cuda")
+
+
+def _net(params, prec):
+    return omlp.bf16_network(params) if prec == 0 else params.astype(np.float64)
+
+
+def _configs(n, seed):
+    u = sampling.pair_batch(sampling.rng(seed), n, 1.0, 11.2)
+    # the frame choice's special places: on body 1's axis, in its mid plane
+    u[:8, 0:2] *= 1e-9
+    u[8:16, 2] = 0.0
+    u[16:24, :2] = 0.0
+    u[16:24, 2] = 0.0
+    return u.astype(np.float32)
+
+
+def test_descriptor_and_jacobian_match_oracle(abi):
+    n = 3000
+    u = _configs(n, 31)
+    sym = torch.full((7, n), float("nan"), device="cuda")
+    jac = torch.full((49, n), float("nan"), device="cuda")
+    abi.rb_cyl_sym_descriptors(_dev(u.T), sym, jac)
+    ud = u.astype(np.float64)
+    s_ref = ocyl.cyl_descriptor(ud)
+    J_ref = ocyl.cyl_descriptor_jacobian(ud)
+    got = sym.cpu().numpy().T
+    for r in range(7):
+        assert_close(got[:, r], s_ref[:, r], 1e-5, f"s[{r}]")
+    J = jac.cpu().numpy().T.reshape(n, 7, 7)
+    for r in range(5):
+        assert_close(J[:, r, :], J_ref[:, r, :], 1e-5, f"J[{r}]")
+    assert not J[:, 5:, :].any()
+    # compacted form: rows idx[0 .. count) with row stride max_count
+    g = sampling.rng(32)
+    idx = g.permutation(n)[:500].astype(np.int32)
+    m = 600
+    sym2 = torch.zeros((7, m), device="cuda")
+    jac2 = torch.zeros((49, m), device="cuda")
+    cnt = torch.tensor([450], dtype=torch.int32, device="cuda")
+    abi.rb_cyl_sym_descriptors(_dev(u.T), sym2, jac2, _dev(idx), cnt, m)
+    np.testing.assert_array_equal(sym2.cpu().numpy()[:, :450], sym.cpu().numpy()[:, idx[:450]])
+    np.testing.assert_array_equal(jac2.cpu().numpy()[:, :450], jac.cpu().numpy()[:, idx[:450]])
+    assert not sym2[:, 450:].any()
+
+
+def _params(seed):
+    params = sampling.xavier_params(seed).astype(np.float32)
+    g = sampling.rng(seed + 1)
+    layers = omlp.unpack(params.astype(np.float64))
+    return omlp.pack([(W, g.normal(size=b.shape) * 0.1) for W, b in layers]).astype(np.float32)
+
+
+def _norm():
+    return omlp.Norm(in_shift=np.array([30.0, 30.0, 0.3, 20.0, 0.0, 0.0, 0.0]),
+                     in_scale=np.array([0.03, 0.03, 3.0, 0.04, 0.05, 0.0, 0.0]), out_shift=-0.5, out_scale=3.0)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_network_gradient_through_the_descriptor_matches_oracle(abi, prec):
+    n = 2049
+    u = _configs(n, 33)
+    params, norm = _params(3), _norm()
+    sym = torch.zeros((7, n), device="cuda")
+    jac = torch.zeros((49, n), device="cuda")
+    d = _dev(u.T)
+    abi.rb_cyl_sym_descriptors(d, sym, jac)
+    E = torch.zeros(n, device="cuda")
+    g = torch.zeros((7, n), device="cuda")
+    ft = torch.zeros((9, n), device="cuda")
+    abi.rb_nn_pair_grad_sym(_dev(params), norm.as_array(), prec, d, sym, jac, None, E, g, ft)
+    ud = u.astype(np.float64)
+    s = ocyl.cyl_descriptor(ud)
+    Er, gs = omlp.input_grad(_net(params, prec), s, norm)
+    gu = np.einsum("pr,prm->pm", gs, ocyl.cyl_descriptor_jacobian(ud))
+    ftr = oframes.forces_from_grad(ud, gu)
+    etol, gtol = RTOL[prec]
+    assert_close(E.cpu().numpy(), Er, etol, "E")
+    assert_close(g.cpu().numpy().T, gu, gtol, "dE/du")
+    got = ft.cpu().numpy().T
+    for k, name in ((0, "F_j"), (3, "tau_i"), (6, "tau_j")):
+        assert_close(got[:, k:k + 3], ftr[:, k:k + 3], gtol, name)
+    # no torque about either cylinder's own axis
+    aj = oframes.qrotate(ud[:, 3:] / np.linalg.norm(ud[:, 3:], axis=1, keepdims=True),
+                         np.broadcast_to([0.0, 0, 1], (n, 3)))
+    assert np.abs(got[:, 5]).max() <= 1e-4 * np.abs(got[:, 3:6]).max()
+    assert np.abs(np.sum(got[:, 6:9] * aj, 1)).max() <= 1e-4 * np.abs(got[:, 6:9]).max()
+
+
+def _oracle_routes(cfg, st, pairs, gap_min, gap_max, amb=1e-5):
+    """Oracle routing of the listed pairs (network / bead / neither) by the
+    shells' bound, and the pairs within amb of a threshold (either route is
+    valid for them)."""
+    x, q = st["x"], st["q"]
+    u = oframes.descriptors(x[pairs[:, 0]], q[pairs[:, 0]], x[pairs[:, 1]], q[pairs[:, 1]], cfg.box)
+    r = np.linalg.norm(u[:, :3], axis=1)
+    inr = r < cfg.d_cut
+    G = np.full(len(u), np.inf)
+    G[inr] = odom.gap(cfg.body.beads, cfg.body.beads, u[inr])
+    bead = inr & ((r < cfg.d_min) | (G < gap_min))
+    net = inr & ~bead & (G < gap_max)
+    ambiguous = inr & ((np.abs(G - gap_min) < amb) | (np.abs(G - gap_max) < amb) | (np.abs(r - cfg.d_cut) < amb))
+    return u, r, G, net, bead, ambiguous
+
+
+def test_shell_routing_matches_oracle_and_keeps_the_network_in_its_domain(abi, cyl_workload):
+    # On the 32768-cylinder system at t = 0: the GPU routes every pair as the
+    # oracle's bound does (pairs within 1e-5 of a threshold may go either
+    # way), every network pair has its closest bead pair at least gap_min
+    # apart (checked on a sample with the oracle's bead sum), and every
+    # skipped pair inside d_cut has no bead pair within gap_max
+    from paper_2402_12199_amd.md import RigidSystem
+    cfg, st, pairs = cyl_workload
+    gap_min, gap_max = 0.8, 2.5
+    b = cfg.body
+    sysm = RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"], cfg.box,
+                       cfg.r_list, cfg.skin)
+    sysm.desc = torch.zeros((7, sysm.max_pairs), dtype=torch.float32, device="cuda")
+    sysm.idx_nn = torch.zeros(sysm.max_pairs, dtype=torch.int32, device="cuda")
+    sysm.idx_bead = torch.zeros(sysm.max_pairs, dtype=torch.int32, device="cuda")
+    sysm.build_pairs(always=True)
+    sysm.route(cfg.d_min, cfg.d_cut, gap_min, gap_max)
+    f = sysm.check_capacity()
+    got_pairs = sysm.pairs_host()
+    key = got_pairs[:, 0].astype(np.int64) * cfg.n_bodies + got_pairs[:, 1]
+    order = np.argsort(key)
+    ref_key = pairs[:, 0].astype(np.int64) * cfg.n_bodies + pairs[:, 1]
+    np.testing.assert_array_equal(key[order], np.sort(ref_key))
+    lp = got_pairs[order]                      # list pairs in the oracle's order
+    u, r, G, net, bead, amb = _oracle_routes(cfg, st, lp, gap_min, gap_max)
+    nn_ids = np.zeros(len(key), bool)
+    nn_ids[sysm.idx_nn[:f[abi.RB_FLAG_NNN]].cpu().numpy()] = True
+    bd_ids = np.zeros(len(key), bool)
+    bd_ids[sysm.idx_bead[:f[abi.RB_FLAG_NBEAD]].cpu().numpy()] = True
+    gnet, gbead = nn_ids[order], bd_ids[order]
+    ok = ~amb
+    np.testing.assert_array_equal(gnet[ok], net[ok])
+    np.testing.assert_array_equal(gbead[ok], bead[ok])
+    assert not (gnet & gbead).any()
+    assert net.sum() > 10000 and bead.sum() > 0 and (r < cfg.d_cut).sum() > 2 * net.sum()
+    g = sampling.rng(34)
+    for sel, lo in ((np.nonzero(gnet)[0], gap_min), (np.nonzero((r < cfg.d_cut) & ~gnet & ~gbead)[0], gap_max)):
+        pick = g.choice(sel, min(1500, len(sel)), replace=False)
+        rmin = obeads.bead_pair_desc(b.beads, b.beads, u[pick], rc=1e3)[:, 10]
+        assert (rmin >= lo - 1e-9).all()
+
+
+def test_pair_with_overlapping_bead_boxes_goes_to_the_bead_sum(abi):
+    # Body j turned so that its axis lies along x, centre 1.5 + 0.6 + 4.05
+    # from body i's axis: its end cap sits 0.6 sigma from body i's side (the
+    # closest bead pair is 0.75 apart, inside the training data's rejected
+    # range) while the centres are 6.15 apart, beyond d_min = 4.  The
+    # shells' bound (0.6) is below gap_min, so the pair must go to the bead
+    # sum.  Side by side and parallel at 4.5 (bound 1.5) it goes to the
+    # network; parallel at 6.15 (bound 3.15 >= gap_max) to neither.
+    from paper_2402_12199_amd.md import RigidSystem
+    cyl = configs.cyl134()
+    turn = [np.cos(np.pi / 4), 0.0, -np.sin(np.pi / 4), 0.0]          # body axis e_z -> -e_x
+    ident = [1.0, 0.0, 0.0, 0.0]
+    zero = np.zeros((2, 3))
+    for dx, qj, want in ((6.15, turn, "bead"), (4.5, ident, "nn"), (6.15, ident, "none")):
+        x = np.array([[20.0, 20.0, 20.0], [20.0 + dx, 20.0, 20.0]])
+        qq = np.array([ident, qj])
+        sysm = RigidSystem([cyl.beads], [cyl.mass], [cyl.inertia], np.zeros(2, np.int32), x, qq, zero, zero, 60.0,
+                           2 * cyl.r_max + 3.5, 1.0)
+        sysm.desc = torch.zeros((7, sysm.max_pairs), dtype=torch.float32, device="cuda")
+        sysm.idx_nn = torch.zeros(sysm.max_pairs, dtype=torch.int32, device="cuda")
+        sysm.idx_bead = torch.zeros(sysm.max_pairs, dtype=torch.int32, device="cuda")
+        sysm.build_pairs(always=True)
+        sysm.route(4.0, 2 * cyl.r_max + 2.5, 0.8, 2.5)
+        f = sysm.flags_host()
+        assert f[abi.RB_FLAG_NPAIRS] == 1
+        u = oframes.descriptors(x[:1], qq[:1], x[1:], qq[1:])
+        G = odom.gap(cyl.beads, cyl.beads, u)[0]
+        rmin = obeads.bead_pair_desc(cyl.beads, cyl.beads, u, rc=1e3)[0, 10]
+        assert G <= rmin
+        got = "bead" if f[abi.RB_FLAG_NBEAD] else ("nn" if f[abi.RB_FLAG_NNN] else "none")
+        assert got == want, (dx, G, rmin, got)
+        if want == "bead":
+            assert abs(G - 0.6) < 1e-9 and rmin < 0.8
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_cylinder_dynamics_forces_match_oracle(abi, cyl_workload, prec):
+    # rb_nn_pair_forces_cyl on the 32768-cylinder system at t = 0 with the
+    # shells' routing: the network (features and Jacobian formed inside the
+    # kernel, switched energy) for the routed pairs, the bead sum for the
+    # fallback pairs, against the oracle doing the same
+    from paper_2402_12199_amd.md import NNModel, RigidSystem
+    cfg, st, pairs = cyl_workload
+    gap_min, gap_max = 0.8, 2.5
+    sw_lo, sw_hi = cfg.d_cut - 1.0, cfg.d_cut
+    params, norm = _params(5), _norm()
+    b = cfg.body
+    sysm = RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"], cfg.box,
+                       cfg.r_list, cfg.skin)
+    sysm.set_nn(NNModel(params=_dev(params), norm=norm.as_array(), precision=prec, d_min=cfg.d_min, sw_lo=sw_lo,
+                        sw_hi=sw_hi, form="cyl", gap_min=gap_min, gap_max=gap_max))
+    sysm.build_pairs(always=True)
+    sysm.compute_forces("nn")
+    f = sysm.check_capacity()
+    lp = sysm.pairs_host()
+    u, r, G, net, bead, amb = _oracle_routes(cfg, st, lp, gap_min, gap_max)
+    nn_ids = np.zeros(len(lp), bool)
+    nn_ids[sysm.idx_nn[:f[abi.RB_FLAG_NNN]].cpu().numpy()] = True
+    bd_ids = np.zeros(len(lp), bool)
+    bd_ids[sysm.idx_bead[:f[abi.RB_FLAG_NBEAD]].cpu().numpy()] = True
+    assert (nn_ids[~amb] == net[~amb]).all() and (bd_ids[~amb] == bead[~amb]).all()
+    # ambiguous pairs follow the GPU's route (both are valid)
+    net, bead = nn_ids, bd_ids
+    x, q = st["x"], st["q"]
+    n = cfg.n_bodies
+    F = np.zeros((n, 3))
+    T = np.zeros((n, 3))
+    un = u[net].astype(np.float32).astype(np.float64)
+    rn = np.linalg.norm(un[:, :3], axis=1)
+    s = ocyl.cyl_descriptor(un)
+    Ep, gs = omlp.input_grad(_net(params, prec), s, norm)
+    gu = np.einsum("pr,prm->pm", gs, ocyl.cyl_descriptor_jacobian(un))
+    t = np.clip((rn - sw_lo) / (sw_hi - sw_lo), 0, 1)
+    S = 1 - t * t * (3 - 2 * t)
+    dS = np.where((rn > sw_lo) & (rn < sw_hi), -6 * t * (1 - t) / (sw_hi - sw_lo), 0.0)
+    gu = gu * S[:, None]
+    gu[:, :3] += (Ep * dS / rn)[:, None] * un[:, :3]
+    pn = lp[net]
+    ft = oframes.to_lab(q[pn[:, 0]], oframes.forces_from_grad(un, gu))
+    E = float(np.sum(S * Ep))
+    np.add.at(F, pn[:, 0], -ft[:, :3])
+    np.add.at(F, pn[:, 1], ft[:, :3])
+    np.add.at(T, pn[:, 0], ft[:, 3:6])
+    np.add.at(T, pn[:, 1], ft[:, 6:])
+    for i, j in lp[bead]:
+        o = obeads.bead_pair(b.beads, b.beads, x[i], q[i], x[j], q[j], box=cfg.box)
+        E += o["E"]
+        F[i] += o["Fi"]
+        F[j] += o["Fj"]
+        T[i] += o["taui"]
+        T[j] += o["tauj"]
+    etol, gtol = RTOL[prec]
+    assert sysm.energy() == pytest.approx(E, rel=max(etol, 1e-5))
+    assert_close(sysm.force.cpu().numpy().T, F, max(gtol, 1e-4), "force")
+    assert_close(sysm.torque.cpu().numpy().T, T, max(gtol, 1e-4), "torque")

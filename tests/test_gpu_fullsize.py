@@ -10,7 +10,7 @@ import pytest
 from oracle import beads as obeads
 from oracle import frames as oframes
 from oracle import mlp as omlp
-from synth import configs, sampling, state
+from synth import sampling
 from tests.tolerances import assert_close
 
 torch = pytest.importorskip("torch")
@@ -31,13 +31,8 @@ def abi():
 
 
 @pytest.fixture(scope="module")
-def cyl():
-    """The 32768-cylinder workload at t = 0 and its brute-force pair list."""
-    cfg = configs.config5()
-    print(f"[fullsize] generating {cfg.name}", flush=True)
-    st = state.initial_state(cfg)
-    pairs = obeads.pairs_within(st["x"], cfg.box, cfg.r_list)
-    return cfg, st, pairs
+def cyl(cyl_workload):
+    return cyl_workload
 
 
 def _net(params, prec):

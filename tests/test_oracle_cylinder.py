@@ -1,0 +1,218 @@
+"""Pins of the oracle's cylinder-pair descriptor (supplementary section 2)
+and of its shape-based lower bound on the closest bead distance: closed
+forms of special configurations, the symmetries the descriptor must respect,
+the round trip through the supplement's four numbers, the Jacobian against
+a derivation by hand, forces and torques through the chain rule against
+full-chain central differences, and the bound against brute force."""
+import numpy as np
+from scipy.spatial.transform import Rotation
+
+from oracle import beads as obeads
+from oracle import cylinder as ocyl
+from oracle import domain as odom
+from oracle import frames
+from synth import configs, sampling
+
+
+def _q_of_matrix(M):
+    x, y, z, w = Rotation.from_matrix(M).as_quat()
+    return np.array([w, x, y, z])
+
+
+def _qz(a):
+    return np.array([np.cos(a / 2), 0.0, 0.0, np.sin(a / 2)])
+
+
+def _qx(a):
+    return np.array([np.cos(a / 2), np.sin(a / 2), 0.0, 0.0])
+
+
+def _random(n, seed, lo=3.0, hi=11.0):
+    return sampling.pair_batch(sampling.rng(seed), n, lo, hi)
+
+
+def test_special_configurations():
+    rho, L, z, th = 4.2, 9.3, 1.7, 0.6
+    ident = [1.0, 0.0, 0.0, 0.0]
+    ry = _q_of_matrix(Rotation.from_rotvec([0, np.pi / 2, 0]).as_matrix())   # e_z -> e_x
+    rth = _q_of_matrix(Rotation.from_rotvec([0, th, 0]).as_matrix())          # e_z -> (sin th, 0, cos th)
+    cases = [
+        ([rho * np.cos(0.7), rho * np.sin(0.7), 0.0, *ident], [rho * rho, 0, 1, 0, 0]),   # side by side
+        ([0.0, 0.0, -L, *ident], [0, L * L, 1, 0, 0]),                                   # end to end
+        ([rho, 0.0, 0.0, *ry], [rho * rho, 0, 0, rho * rho, 0]),                         # T shape
+        ([rho, 0.0, z, *rth], [rho * rho, z * z, np.cos(th) ** 2, (rho * np.sin(th)) ** 2,
+                               rho * np.sin(th) * np.cos(th) * z]),
+    ]
+    for u, want in cases:
+        s = ocyl.cyl_descriptor(np.array([u]))[0]
+        np.testing.assert_allclose(s, want + [0, 0], rtol=1e-12, atol=1e-12)
+
+
+def test_symmetries_leave_the_descriptor_unchanged():
+    # turns of either cylinder about its own axis, either cylinder turned end
+    # over end, and the mirror y -> -y of body 1's frame
+    u = _random(64, 3)
+    s0 = ocyl.cyl_descriptor(u)
+    g = sampling.rng(4)
+    for _ in range(6):
+        a, b = g.uniform(-np.pi, np.pi, 2)
+        v = u.copy()
+        v[:, :3] = frames.qrotate(np.broadcast_to(frames.qconj(_qz(a)), (len(u), 4)), u[:, :3])
+        v[:, 3:] = frames.qmul(frames.qmul(np.broadcast_to(frames.qconj(_qz(a)), (len(u), 4)), u[:, 3:]),
+                               np.broadcast_to(_qz(b), (len(u), 4)))
+        np.testing.assert_allclose(ocyl.cyl_descriptor(v), s0, rtol=1e-10, atol=1e-10)
+    flip_j = u.copy()
+    flip_j[:, 3:] = frames.qmul(u[:, 3:], np.broadcast_to(_qx(np.pi), (len(u), 4)))
+    np.testing.assert_allclose(ocyl.cyl_descriptor(flip_j), s0, rtol=1e-10, atol=1e-10)
+    flip_i = u.copy()
+    c = np.broadcast_to(frames.qconj(_qx(np.pi)), (len(u), 4))
+    flip_i[:, :3] = frames.qrotate(c, u[:, :3])
+    flip_i[:, 3:] = frames.qmul(c, u[:, 3:])
+    np.testing.assert_allclose(ocyl.cyl_descriptor(flip_i), s0, rtol=1e-10, atol=1e-10)
+    M = np.diag([1.0, -1.0, 1.0])
+    mir = u.copy()
+    mir[:, :3] = u[:, :3] @ M
+    for n in range(len(u)):
+        R = Rotation.from_quat(np.r_[u[n, 4:], u[n, 3]]).as_matrix()
+        mir[n, 3:] = _q_of_matrix(M @ R @ M)
+    np.testing.assert_allclose(ocyl.cyl_descriptor(mir), s0, rtol=1e-10, atol=1e-10)
+
+
+def test_geometric_invariants():
+    u = _random(200, 5)
+    s = ocyl.cyl_descriptor(u)
+    a = frames.qrotate(u[:, 3:], np.broadcast_to([0.0, 0.0, 1.0], (len(u), 3)))
+    np.testing.assert_allclose(s[:, 0] + s[:, 1], np.sum(u[:, :3] ** 2, 1), rtol=1e-12)
+    np.testing.assert_allclose(s[:, 2], a[:, 2] ** 2, rtol=1e-12, atol=1e-15)        # cos^2 of the axes' angle
+    np.testing.assert_allclose(s[:, 3], (u[:, 0] * a[:, 0] + u[:, 1] * a[:, 1]) ** 2, rtol=1e-10, atol=1e-12)
+    assert (s[:, 5:] == 0).all()
+
+
+def test_round_trip_through_the_four_numbers():
+    g = sampling.rng(6)
+    num = np.stack([g.uniform(0.1, 9, 50), g.uniform(0.1, 9, 50), g.uniform(0.05, np.pi - 0.05, 50),
+                    g.uniform(-3.1, 3.1, 50)], axis=1)
+    u = ocyl.cyl_configuration(num)
+    np.testing.assert_allclose(ocyl.cyl_numbers(u), num, rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(ocyl.cyl_descriptor(u), ocyl.descriptor_of_numbers(num), rtol=1e-10, atol=1e-10)
+
+
+def test_jacobian_matches_a_derivation_by_hand():
+    # s written out in (d, q) with A = q e_z q^* = (2(xz + wy), 2(yz - wx),
+    # w^2 - x^2 - y^2 + z^2) and t = d_x A_x + d_y A_y
+    u = _random(40, 7)
+    J = ocyl.cyl_descriptor_jacobian(u)
+    for n, (dx, dy, dz, w, x, y, z) in enumerate(u):
+        A = np.array([2 * (x * z + w * y), 2 * (y * z - w * x), w * w - x * x - y * y + z * z])
+        dA = np.array([[2 * y, 2 * z, 2 * w, 2 * x], [-2 * x, -2 * w, 2 * z, 2 * y], [2 * w, -2 * x, -2 * y, 2 * z]])
+        t = dx * A[0] + dy * A[1]
+        dt = np.r_[A[0], A[1], 0.0, dx * dA[0] + dy * dA[1]]
+        dAz = np.r_[0.0, 0.0, 0.0, dA[2]]
+        ref = np.zeros((7, 7))
+        ref[0, :2] = (2 * dx, 2 * dy)
+        ref[1, 2] = 2 * dz
+        ref[2] = 2 * A[2] * dAz
+        ref[3] = 2 * t * dt
+        ref[4] = A[2] * dz * dt + t * dz * dAz + np.r_[0, 0, t * A[2], 0, 0, 0, 0]
+        np.testing.assert_allclose(J[n], ref, rtol=1e-6, atol=1e-6 * np.abs(ref).max())
+
+
+def _energy_of_s(s):
+    # a smooth test energy written in the descriptor
+    return (0.3 * s[:, 0] - 0.2 * s[:, 1] + 1.5 * s[:, 2] + 0.05 * s[:, 3] - 0.4 * s[:, 4]
+            + 0.01 * s[:, 0] * s[:, 2] + 0.002 * s[:, 4] ** 2 + 0.1 * np.sin(s[:, 1] / 7.0))
+
+
+def _grad_of_s(s):
+    g = np.zeros_like(s)
+    g[:, 0] = 0.3 + 0.01 * s[:, 2]
+    g[:, 1] = -0.2 + 0.1 / 7.0 * np.cos(s[:, 1] / 7.0)
+    g[:, 2] = 1.5 + 0.01 * s[:, 0]
+    g[:, 3] = 0.05
+    g[:, 4] = -0.4 + 0.004 * s[:, 4]
+    return g
+
+
+def test_forces_and_torques_through_the_chain_rule_match_full_chain_differences():
+    # E(x_i, q_i, x_j, q_j) = E(s(d, q)): forces and torques from
+    # J^T dE/ds and the closed form against central differences of the
+    # lab-frame energy under translations and rotations of each body; the
+    # torque of each cylinder about its own axis vanishes
+    g = sampling.rng(8)
+    n = 12
+    xi, xj = g.normal(size=(n, 3)) * 3, g.normal(size=(n, 3)) * 3
+    qi, qj = g.normal(size=(n, 4)), g.normal(size=(n, 4))
+    qi /= np.linalg.norm(qi, axis=1, keepdims=True)
+    qj /= np.linalg.norm(qj, axis=1, keepdims=True)
+    u = frames.descriptors(xi, qi, xj, qj)
+    s = ocyl.cyl_descriptor(u)
+    J = ocyl.cyl_descriptor_jacobian(u)
+    gu = np.einsum("pr,prm->pm", _grad_of_s(s), J)
+    ft = frames.to_lab(qi, frames.forces_from_grad(u, gu))
+
+    def E(xi_, qi_, xj_, qj_):
+        return _energy_of_s(ocyl.cyl_descriptor(frames.descriptors(xi_, qi_, xj_, qj_)))
+
+    h = 1e-5
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        Fj = -(E(xi, qi, xj + e, qj) - E(xi, qi, xj - e, qj)) / (2 * h)
+        Fi = -(E(xi + e, qi, xj, qj) - E(xi - e, qi, xj, qj)) / (2 * h)
+        rot = lambda q, sgn: frames.qmul(np.broadcast_to(frames.qexp(sgn * e), q.shape), q)
+        tj = -(E(xi, qi, xj, rot(qj, 1)) - E(xi, qi, xj, rot(qj, -1))) / (2 * h)
+        ti = -(E(xi, rot(qi, 1), xj, qj) - E(xi, rot(qi, -1), xj, qj)) / (2 * h)
+        np.testing.assert_allclose(ft[:, k], Fj, rtol=1e-6, atol=1e-7)
+        np.testing.assert_allclose(-ft[:, k], Fi, rtol=1e-6, atol=1e-7)
+        np.testing.assert_allclose(ft[:, 3 + k], ti, rtol=1e-6, atol=1e-7)
+        np.testing.assert_allclose(ft[:, 6 + k], tj, rtol=1e-6, atol=1e-7)
+    ai = frames.qrotate(qi, np.broadcast_to([0.0, 0, 1], (n, 3)))
+    aj = frames.qrotate(qj, np.broadcast_to([0.0, 0, 1], (n, 3)))
+    assert np.abs(np.sum(ft[:, 3:6] * ai, 1)).max() < 1e-9 * np.abs(ft[:, 3:6]).max()
+    assert np.abs(np.sum(ft[:, 6:9] * aj, 1)).max() < 1e-9 * np.abs(ft[:, 6:9]).max()
+
+
+def test_shells_of_the_workload_bodies():
+    cyl = configs.cyl134()
+    h, k, R, H = odom.shells(cyl.beads)
+    np.testing.assert_allclose(h, [1.5, 1.5, 4.05], atol=1e-12)
+    assert k == 2 and abs(R - 1.5) < 1e-12 and abs(H - 4.05) < 1e-12
+    cube = configs.cube6()
+    h, k, R, H = odom.shells(cube.beads)
+    np.testing.assert_allclose(h, [2.5, 2.5, 2.5])
+    assert abs(R - 2.5 * np.sqrt(2)) < 1e-12 and abs(H - 2.5) < 1e-12
+
+
+def test_segment_distance_against_dense_sampling():
+    g = sampling.rng(9)
+    t = np.linspace(0, 1, 801)
+    for _ in range(30):
+        p0, p1, q0, q1 = g.normal(size=(4, 3)) * 2
+        if g.random() < 0.3:
+            q1 = q0 + (p1 - p0) * g.uniform(0.2, 2)            # parallel segments
+        P = p0 + t[:, None] * (p1 - p0)
+        Q = q0 + t[:, None] * (q1 - q0)
+        brute = np.sqrt(((P[:, None, :] - Q[None, :, :]) ** 2).sum(-1)).min()
+        d = odom.segment_distance(p0, p1, q0, q1)
+        assert d <= brute + 1e-12
+        assert brute - d <= 0.02 * max(np.linalg.norm(p1 - p0), np.linalg.norm(q1 - q0))
+
+
+def test_gap_bounds_the_closest_bead_distance_and_is_tight_where_expected():
+    for body in (configs.cyl134(), configs.cube6()):
+        u = sampling.pair_batch(sampling.rng(10), 300, 2.0 * body.r_in + 0.2, 2 * body.r_max + 2.5)
+        gp = odom.gap(body.beads, body.beads, u)
+        rmin = obeads.bead_pair_desc(body.beads, body.beads, u, rc=1e3)[:, 10]
+        assert (gp <= rmin + 1e-9).all()
+        assert (gp > 0).sum() > 50
+    cyl = configs.cyl134().beads
+    ident = np.array([1.0, 0, 0, 0])
+    # parallel, side by side with facing beads: gap = rho - 3 exactly
+    for rho in (4.0, 5.5):
+        u = np.array([[rho, 0.0, 0.0, *ident]])
+        assert abs(odom.gap(cyl, cyl, u)[0] - (rho - 3.0)) < 1e-12
+        assert abs(obeads.bead_pair_desc(cyl, cyl, u, rc=1e3)[0, 10] - (rho - 3.0)) < 1e-12
+    # coaxial end to end: gap = L - 8.1, the cap centres' distance
+    u = np.array([[0.0, 0.0, 9.3, *ident]])
+    assert abs(odom.gap(cyl, cyl, u)[0] - 1.2) < 1e-12
+    assert abs(obeads.bead_pair_desc(cyl, cyl, u, rc=1e3)[0, 10] - 1.2) < 1e-12

@@ -344,7 +344,7 @@ def hphc_part(args, torch, abi, log):
                     sw_lo=cfg.d_cut - 1.0, sw_hi=cfg.d_cut)
     # the same data with force and torque matching (weights 10 / mean squared label)
     log(f"[bench] {cfg.body.name} surrogate with force and torque matching, {args.hphc_epochs} epochs")
-    fm = dict(weight=10.0, fd_step=0.1)
+    fm = dict(weight=10.0)
     surf = train_surrogate_md(cfg, st, 1 << 20, 1 << 16, args.hphc_epochs, r_rej=0.0, log=log, fm=fm)
     model_fm = NNModel(params=surf["params"], norm=surf["norm"], precision=abi.RB_PREC_BF16, d_min=cfg.d_min,
                        sw_lo=cfg.d_cut - 1.0, sw_hi=cfg.d_cut)

@@ -438,19 +438,18 @@ int rb_nn_train_step(float *params, float *adam_m, float *adam_v, int32_t t, con
  * energies (section 2) and notes that forces fitted directly are more
  * accurate than gradients of an energy fit (supplementary section 6); this
  * step fits the energy's gradient to them.  The gradient of the matching
- * term is the parameter gradient of the directional derivative of E along
- * v = dloss/dg, taken as a central difference of step fd_step along v/|v|
- * in descriptor units: two extra rows per sample with output adjoints
- * +-|v| out_scale / (2 fd_step) (error O(fd_step^2); in the BF16 mode the
- * BF16 activations add rounding noise of about 2^-9 / fd_step relative per
- * sample).  batch: positive multiple of 32, at most 2^18.
- * ws: rb_nn_train_fm_workspace_bytes(batch). */
+ * term is exact: it is the parameter gradient of the directional derivative
+ * of E along v = dloss/dg, carried forward as tangents through every layer
+ * and differentiated in reverse through both the primal and the tangent
+ * chains (second derivative of SiLU where they meet); each sample adds a
+ * tangent row to the weight-gradient GEMMs.  batch: positive multiple of
+ * 32, at most 2^18.  ws: rb_nn_train_fm_workspace_bytes(batch). */
 size_t rb_nn_train_fm_workspace_bytes(int32_t batch);
 int rb_nn_train_step_fm(float *params, float *adam_m, float *adam_v, int32_t t, const float *norm,
                         int precision, int32_t batch, const float *desc, int64_t n_data,
                         const float *labels, const float *ft_labels, const int32_t *idx, float lam_f,
-                        float lam_t, float fd_step, float lr, float beta1, float beta2, float eps,
-                        float *loss, float *grad_out, void *ws, size_t ws_bytes, void *stream);
+                        float lam_t, float lr, float beta1, float beta2, float eps, float *loss,
+                        float *grad_out, void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

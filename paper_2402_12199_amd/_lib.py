@@ -54,7 +54,7 @@ SIGNATURES = {
                                       P]),
     "rb_nn_train_workspace_bytes": (SZ, [I32]),
     "rb_nn_train_fm_workspace_bytes": (SZ, [I32]),
-    "rb_nn_train_step_fm": (C.c_int, [P, P, P, I32, FP, C.c_int, I32, P, I64, P, P, P, F32, F32, F32, F32, F32, F32,
+    "rb_nn_train_step_fm": (C.c_int, [P, P, P, I32, FP, C.c_int, I32, P, I64, P, P, P, F32, F32, F32, F32, F32,
                                       F32, P, P, P, SZ, P]),
     "rb_nn_train_step": (C.c_int, [P, P, P, I32, FP, C.c_int, I32, P, I64, P, P, F32, F32, F32, F32,
                                    P, P, P, SZ, P]),

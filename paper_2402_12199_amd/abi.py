@@ -380,7 +380,7 @@ def rb_rigid_step_fused(ctx: Ctx, dt: float, x, P, q, L, types, acc, force, torq
 
 
 def rb_nn_train_step_fm(params, adam_m, adam_v, t: int, norm, precision: int, batch: int, desc, labels, ft_labels,
-                        idx, lam_f, lam_t, fd_step, lr, beta1, beta2, eps, loss, grad_out=None, ws=None):
+                        idx, lam_f, lam_t, lr, beta1, beta2, eps, loss, grad_out=None, ws=None):
     nd = desc.shape[1]
     _, npn = _norm(norm)
     check(lib().rb_nn_train_step_fm(_ptr(params, torch.float32, (RB_MLP_NPARAMS,), "params"),
@@ -389,8 +389,7 @@ def rb_nn_train_step_fm(params, adam_m, adam_v, t: int, norm, precision: int, ba
                                     precision, int(batch), _ptr(desc, torch.float32, (7, nd), "desc"), nd,
                                     _ptr(labels, torch.float32, (nd,), "labels"),
                                     _ptr(ft_labels, torch.float32, (6, nd), "ft_labels"),
-                                    _ptr(idx, torch.int32, name="idx"), float(lam_f), float(lam_t), float(fd_step),
-                                    float(lr), float(beta1), float(beta2), float(eps),
+                                    _ptr(idx, torch.int32, name="idx"), float(lam_f), float(lam_t), float(lr), float(beta1), float(beta2), float(eps),
                                     _ptr(loss, torch.float32, (2,), "loss"),
                                     _ptr(grad_out, torch.float32, (RB_MLP_NPARAMS,), "grad_out", optional=True),
                                     _ptr(ws, torch.uint8, name="ws"), ws.numel(), _stream()),

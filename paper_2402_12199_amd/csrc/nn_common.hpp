@@ -69,6 +69,15 @@ __device__ inline void silu(float z, float &h, float &dh) {
     dh = fmaf(h, 1.f - s, s);
 }
 
+// SiLU with its first and second derivatives: h'' = s (1 - s) (2 + z (1 - 2 s)).
+__device__ inline void silu2(float z, float &h, float &dh, float &d2h) {
+    const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * z);
+    const float s = __builtin_amdgcn_rcpf(1.f + e);
+    h = z * s;
+    dh = fmaf(h, 1.f - s, s);
+    d2h = s * (1.f - s) * fmaf(z, 1.f - 2.f * s, 2.f);
+}
+
 __device__ inline bf16x8 pack8(const float a[4], const float b[4]) {
     bf16x8 v;
     v[0] = (__bf16)a[0]; v[1] = (__bf16)a[1]; v[2] = (__bf16)a[2]; v[3] = (__bf16)a[3];
@@ -170,6 +179,14 @@ __device__ inline void l1_inputs(const float un[kIn], int g, float &x0, float &x
 
 __device__ inline f32x4 layer1_rows(const float (*w1)[8], const float *b1, float x0, float x1, int n, int g, int mt) {
     f32x4 c = *reinterpret_cast<const f32x4 *>(&b1[16 * mt + 4 * g]);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(w1[16 * mt + n][g], x0, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(w1[16 * mt + n][4 + g], x1, c, 0, 0, 0);
+    return c;
+}
+
+// The same product without the bias (tangents of layer 1's inputs).
+__device__ inline f32x4 layer1_rows_nobias(const float (*w1)[8], float x0, float x1, int n, int g, int mt) {
+    f32x4 c = f32x4{0.f, 0.f, 0.f, 0.f};
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(w1[16 * mt + n][g], x0, c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(w1[16 * mt + n][4 + g], x1, c, 0, 0, 0);
     return c;

@@ -21,8 +21,6 @@ struct Emit {
     bool live = false;
     float y = 0.f;          // normalised label of this row
     float k2 = 0.f;         // 2 / B: the loss gradient is k2 (e' - y')
-    bool fixed = false;     // row with a given output adjoint (no energy loss term)
-    float adj = 0.f;        // that adjoint
     __device__ float &h(int row) const { return H[row * B + b]; }
     __device__ float &d(int row) const { return D[row * B + b]; }
 };
@@ -106,8 +104,8 @@ __device__ inline float tile_bf16(const LdsBF16 &L, const Norm &nm, const float 
     const float E = fmaf(e, nm.oscale, nm.oshift);
     if (!GRAD) return E;
     if (EMIT) {
-        seed = em.live ? (em.fixed ? em.adj : em.k2 * (E - em.y)) : 0.f;
-        if (em.live && g == 0) em.R[em.b] = em.fixed ? 0.f : E - em.y;
+        seed = em.live ? em.k2 * (E - em.y) : 0.f;
+        if (em.live && g == 0) em.R[em.b] = E - em.y;
     }
 
     // reverse pass: delta_4 = seed * oscale * w5 (.) h4'
@@ -276,8 +274,8 @@ __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &n
     const float E = fmaf(e, nm.oscale, nm.oshift);
     if (!GRAD) return E;
     if (EMIT) {
-        seed = em.live ? (em.fixed ? em.adj : em.k2 * (E - em.y)) : 0.f;
-        if (em.live && g == 0 && v == 0) em.R[em.b] = em.fixed ? 0.f : E - em.y;
+        seed = em.live ? em.k2 * (E - em.y) : 0.f;
+        if (em.live && g == 0 && v == 0) em.R[em.b] = E - em.y;
     }
 
     // reverse pass: this wave's block of delta_4 = seed * oscale * w5 (.) h4'
@@ -440,8 +438,8 @@ __device__ inline float tile_fp32(const LdsFP32 &Lc, LdsFP32 &L, const float *__
     const float E = fmaf(e, nm.oscale, nm.oshift);
     if (!GRAD) return E;
     if (EMIT) {
-        seed = em.live ? (em.fixed ? em.adj : em.k2 * (E - em.y)) : 0.f;
-        if (em.live && g == 0) em.R[em.b] = em.fixed ? 0.f : E - em.y;
+        seed = em.live ? em.k2 * (E - em.y) : 0.f;
+        if (em.live && g == 0) em.R[em.b] = E - em.y;
     }
     const float s0 = seed * nm.oscale;
 #pragma unroll
@@ -522,5 +520,393 @@ template <>
 struct NNLds<false> {
     typedef LdsFP32 T;
 };
+
+// ------------------------------------------- force matching: exact gradient
+// The parameter gradient of v . dE/du (v = dloss/dg held fixed, g = dE/du)
+// is the parameter gradient of the directional derivative D_v E: carried
+// forward as tangents (z'_l = W_l h'_{l-1}, h'_l = s'(z_l) z'_l, h'_0 the
+// direction in normalised input units), then differentiated in reverse
+// through both chains: with output adjoints delta_5 (primal, the energy loss)
+// and alpha (tangent),
+//   zt_bar_l = s'(z_l) (.) ht_bar_l,
+//   z_bar_l  = s'(z_l) (.) h_bar_l + s''(z_l) z'_l (.) ht_bar_l,
+//   h_bar_{l-1} = W_l^T z_bar_l, ht_bar_{l-1} = W_l^T zt_bar_l,
+// and dW_l = z_bar_l h_{l-1}^T + zt_bar_l h'_{l-1}^T, db_l = z_bar_l (the
+// tangent chain has no bias).  Each sample therefore becomes two rows of the
+// weight-gradient GEMMs: the primal row (h_{l-1}, z_bar_l; its energy-loss
+// deltas included) and the tangent row (h'_{l-1}, zt_bar_l), which adds to
+// the weights but not to the biases.
+struct EmitFM {
+    float *H = nullptr, *D = nullptr, *R = nullptr;
+    int64_t Btot = 0;   // row stride: primal rows 0 .. B1, tangent rows B1 .. 2 B1
+    int64_t B1 = 0;
+    int64_t b = 0;      // this sample
+    bool live = false;
+    float y = 0.f;      // normalised label
+    float k2 = 0.f;     // 2 / B1: energy-loss seed k2 (e' - y')
+    float alpha = 0.f;  // output adjoint of the tangent chain
+    __device__ float &hp(int row) const { return H[row * Btot + b]; }
+    __device__ float &ht(int row) const { return H[row * Btot + B1 + b]; }
+    __device__ float &dp(int row) const { return D[row * Btot + b]; }
+    __device__ float &dt(int row) const { return D[row * Btot + B1 + b]; }
+};
+
+// Exchange blocks of the tangent chain (four-wave form).
+struct WideT {
+    bf16x8 a[kWideGroup][kWave];
+    bf16x8 dh[kWideGroup][kWave];
+    bf16x8 dl[kWideGroup][kWave];
+};
+
+// BF16, four waves per 16-row tile (as tile_bf16_wide); u the pair
+// descriptor, vt the tangent direction in normalised input units.  The
+// output layer is the identity in training (normalised energies).
+__device__ inline void tile_bf16_wide_fm(const LdsBF16 &L, WideX &X, WideT &XT, const Norm &nm, const float u[kIn],
+                                         const float vt[kIn], int v, const EmitFM &em) {
+    const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, n = lane & 15;
+    float un[kIn];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) un[k] = (u[k] - nm.shift[k]) * nm.scale[k];
+    if (em.live && g == 0 && v == 0)
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) {
+            em.hp(k) = un[k];
+            em.ht(k) = vt[k];
+        }
+    bf16x8 act[4], tact[4];
+    f16x8 spo[4], cpo[4];   // s'(z_l) and s''(z_l) z'_l of this wave's features
+    {
+        float h[2][4], d[2][4], th[2][4], c[2][4];
+        float x0, x1, t0, t1;
+        l1_inputs(un, g, x0, x1);
+        l1_inputs(vt, g, t0, t1);
+#pragma unroll
+        for (int mm = 0; mm < 2; ++mm) {
+            const int mt = 2 * v + mm;
+            const f32x4 z = layer1_rows(L.w1, L.b[0], x0, x1, n, g, mt);
+            const f32x4 zt = layer1_rows_nobias(L.w1, t0, t1, n, g, mt);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float dd;
+                silu2(z[r], h[mm][r], d[mm][r], dd);
+                th[mm][r] = d[mm][r] * zt[r];
+                c[mm][r] = dd * zt[r];
+                if (em.live) {
+                    em.hp(kIn + 32 * v + 16 * mm + 4 * g + r) = h[mm][r];
+                    em.ht(kIn + 32 * v + 16 * mm + 4 * g + r) = th[mm][r];
+                }
+            }
+        }
+        X.a[v][lane] = pack8(h[0], h[1]);
+        XT.a[v][lane] = pack8(th[0], th[1]);
+        spo[0] = pack8h(d[0], d[1]);
+        cpo[0] = pack8h(c[0], c[1]);
+    }
+    wide_sync();
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        act[kb] = X.a[kb][lane];
+        tact[kb] = XT.a[kb][lane];
+    }
+    wide_sync();
+    float e = 0.f;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        float h[2][4], d[2][4], th[2][4], c[2][4];
+#pragma unroll
+        for (int mm = 0; mm < 2; ++mm) {
+            const int mt = 2 * v + mm;
+            f32x4 cz = *reinterpret_cast<const f32x4 *>(&L.b[l + 1][16 * mt + 4 * g]);
+            f32x4 ct = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&L.w[l][16 * mt + n][32 * kb + 8 * g]);
+                cz = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kb], cz, 0, 0, 0);
+                ct = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, tact[kb], ct, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float dd;
+                silu2(cz[r], h[mm][r], d[mm][r], dd);
+                th[mm][r] = d[mm][r] * ct[r];
+                c[mm][r] = dd * ct[r];
+                if (em.live) {
+                    em.hp(kIn + kH * (l + 1) + 16 * mt + 4 * g + r) = h[mm][r];
+                    em.ht(kIn + kH * (l + 1) + 16 * mt + 4 * g + r) = th[mm][r];
+                }
+            }
+            if (l == 2) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) e = fmaf(L.w5[16 * mt + 4 * g + r], h[mm][r], e);
+            }
+        }
+        spo[l + 1] = pack8h(d[0], d[1]);
+        cpo[l + 1] = pack8h(c[0], c[1]);
+        if (l < 2) {
+            X.a[v][lane] = pack8(h[0], h[1]);
+            XT.a[v][lane] = pack8(th[0], th[1]);
+            wide_sync();
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                act[kb] = X.a[kb][lane];
+                tact[kb] = XT.a[kb][lane];
+            }
+            wide_sync();
+        }
+    }
+    e = group_sum(e);
+    if (g == 0) X.red[v][0][n] = e;
+    wide_sync();
+    const float E = ((X.red[0][0][n] + X.red[1][0][n]) + X.red[2][0][n]) + X.red[3][0][n] + L.b5;
+    wide_sync();
+    const float seed = em.live ? em.k2 * (E - em.y) : 0.f;
+    const float alpha = em.live ? em.alpha : 0.f;
+    if (em.live && g == 0 && v == 0) {
+        em.R[em.b] = E - em.y;
+        em.dp(4 * kH) = seed;
+        em.dt(4 * kH) = alpha;
+    }
+    bf16x8 dpk[4], dlk[4], tpk[4], tlk[4];
+    {
+        float zb[2][4], ztb[2][4];
+#pragma unroll
+        for (int mm = 0; mm < 2; ++mm)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int f = 32 * v + 16 * mm + 4 * g + r;
+                const float w5 = L.w5[f], dd = (float)spo[3][4 * mm + r], cc = (float)cpo[3][4 * mm + r];
+                ztb[mm][r] = dd * (alpha * w5);
+                zb[mm][r] = fmaf(dd, seed * w5, cc * (alpha * w5));
+                if (em.live) {
+                    em.dp(3 * kH + f) = zb[mm][r];
+                    em.dt(3 * kH + f) = ztb[mm][r];
+                }
+            }
+        bf16x8 hi, lo;
+        split8(zb[0], zb[1], hi, lo);
+        X.dh[v][lane] = hi;
+        X.dl[v][lane] = lo;
+        split8(ztb[0], ztb[1], hi, lo);
+        XT.dh[v][lane] = hi;
+        XT.dl[v][lane] = lo;
+    }
+    wide_sync();
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        dpk[kb] = X.dh[kb][lane];
+        dlk[kb] = X.dl[kb][lane];
+        tpk[kb] = XT.dh[kb][lane];
+        tlk[kb] = XT.dl[kb][lane];
+    }
+    wide_sync();
+#pragma unroll
+    for (int l = 2; l >= 0; --l) {
+        float zb[2][4], ztb[2][4];
+#pragma unroll
+        for (int mm = 0; mm < 2; ++mm) {
+            const int mt = 2 * v + mm;
+            const int col = 32 * (mt >> 1) + 8 * (n >> 2) + 4 * (mt & 1) + (n & 3);
+            f32x4 c = f32x4{0.f, 0.f, 0.f, 0.f}, ct = c;
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                bf16x8 a;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) a[i] = L.w[l][32 * kb + 16 * (i >> 2) + 4 * g + (i & 3)][col];
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, dpk[kb], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, dlk[kb], c, 0, 0, 0);
+                ct = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, tpk[kb], ct, 0, 0, 0);
+                ct = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, tlk[kb], ct, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float dd = (float)spo[l][4 * mm + r], cc = (float)cpo[l][4 * mm + r];
+                ztb[mm][r] = dd * ct[r];
+                zb[mm][r] = fmaf(dd, c[r], cc * ct[r]);
+                if (em.live) {
+                    em.dp(kH * l + 16 * mt + 4 * g + r) = zb[mm][r];
+                    em.dt(kH * l + 16 * mt + 4 * g + r) = ztb[mm][r];
+                }
+            }
+        }
+        if (l > 0) {
+            bf16x8 hi, lo;
+            split8(zb[0], zb[1], hi, lo);
+            X.dh[v][lane] = hi;
+            X.dl[v][lane] = lo;
+            split8(ztb[0], ztb[1], hi, lo);
+            XT.dh[v][lane] = hi;
+            XT.dl[v][lane] = lo;
+            wide_sync();
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                dpk[kb] = X.dh[kb][lane];
+                dlk[kb] = X.dl[kb][lane];
+                tpk[kb] = XT.dh[kb][lane];
+                tlk[kb] = XT.dl[kb][lane];
+            }
+            wide_sync();
+        }
+    }
+}
+
+// FP32, one wave per 16-row tile (as tile_fp32): weights from global memory,
+// s'(z_l) and s''(z_l) z'_l of every layer kept in LDS for the reverse pass.
+constexpr int kF32FmWaves = 2;
+struct alignas(16) LdsFP32FM {
+    float w1[kH][8];
+    float b[4][kH];
+    float w5[kH];
+    float b5;
+    float sp[kF32FmWaves][4][32][kWave];
+    float cp[kF32FmWaves][4][32][kWave];
+};
+
+__device__ inline void tile_fp32_fm(LdsFP32FM &L, const float *__restrict__ p, const Norm &nm, const float u[kIn],
+                                    const float vt[kIn], const EmitFM &em) {
+    const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, n = lane & 15;
+    const int w = threadIdx.x >> 6;
+    float un[kIn];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) un[k] = (u[k] - nm.shift[k]) * nm.scale[k];
+    if (em.live && g == 0)
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) {
+            em.hp(k) = un[k];
+            em.ht(k) = vt[k];
+        }
+    float hv[8][4], tv[8][4];
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int f = 16 * mt + 4 * g + r;
+            float z = L.b[0][f], zt = 0.f;
+#pragma unroll
+            for (int k = 0; k < kIn; ++k) {
+                z = fmaf(L.w1[f][k], un[k], z);
+                zt = fmaf(L.w1[f][k], vt[k], zt);
+            }
+            float d, dd;
+            silu2(z, hv[mt][r], d, dd);
+            tv[mt][r] = d * zt;
+            L.sp[w][0][4 * mt + r][lane] = d;
+            L.cp[w][0][4 * mt + r][lane] = dd * zt;
+            if (em.live) {
+                em.hp(kIn + f) = hv[mt][r];
+                em.ht(kIn + f) = tv[mt][r];
+            }
+        }
+    for (int l = 0; l < 3; ++l) {
+        const float *W = p + w_off(l + 2);
+        f32x4 acc[8], tac[8];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            acc[mt] = *reinterpret_cast<const f32x4 *>(&L.b[l + 1][16 * mt + 4 * g]);
+            tac[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            __asm__ volatile("" ::: "memory");
+            const float *row = W + (16 * mt + n) * kH + 4 * g;
+#pragma unroll
+            for (int m2 = 0; m2 < 8; ++m2) {
+                const float4 a = *reinterpret_cast<const float4 *>(row + 16 * m2);
+                const float av[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r], hv[m2][r], acc[mt], 0, 0, 0);
+                    tac[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r], tv[m2][r], tac[mt], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float d, dd;
+                silu2(acc[mt][r], hv[mt][r], d, dd);
+                tv[mt][r] = d * tac[mt][r];
+                L.sp[w][l + 1][4 * mt + r][lane] = d;
+                L.cp[w][l + 1][4 * mt + r][lane] = dd * tac[mt][r];
+                if (em.live) {
+                    em.hp(kIn + kH * (l + 1) + 16 * mt + 4 * g + r) = hv[mt][r];
+                    em.ht(kIn + kH * (l + 1) + 16 * mt + 4 * g + r) = tv[mt][r];
+                }
+            }
+    }
+    float e = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) e = fmaf(L.w5[16 * mt + 4 * g + r], hv[mt][r], e);
+    const float E = group_sum(e) + L.b5;
+    const float seed = em.live ? em.k2 * (E - em.y) : 0.f;
+    const float alpha = em.live ? em.alpha : 0.f;
+    if (em.live && g == 0) {
+        em.R[em.b] = E - em.y;
+        em.dp(4 * kH) = seed;
+        em.dt(4 * kH) = alpha;
+    }
+    // hv, tv now hold the primal and tangent deltas of the current layer
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int f = 16 * mt + 4 * g + r;
+            const float w5 = L.w5[f], d = L.sp[w][3][4 * mt + r][lane], c = L.cp[w][3][4 * mt + r][lane];
+            tv[mt][r] = d * (alpha * w5);
+            hv[mt][r] = fmaf(d, seed * w5, c * (alpha * w5));
+            if (em.live) {
+                em.dp(3 * kH + f) = hv[mt][r];
+                em.dt(3 * kH + f) = tv[mt][r];
+            }
+        }
+    for (int l = 2; l >= 0; --l) {
+        const float *W = p + w_off(l + 2);
+        f32x4 acc[8], tac[8];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            tac[mt] = acc[mt];
+        }
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            __asm__ volatile("" ::: "memory");
+            const float *colp = W + 16 * mt + n;
+#pragma unroll
+            for (int m2 = 0; m2 < 8; ++m2)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float a = colp[(16 * m2 + 4 * g + r) * kH];
+                    acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, hv[m2][r], acc[mt], 0, 0, 0);
+                    tac[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, tv[m2][r], tac[mt], 0, 0, 0);
+                }
+        }
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float d = L.sp[w][l][4 * mt + r][lane], c = L.cp[w][l][4 * mt + r][lane];
+                tv[mt][r] = d * tac[mt][r];
+                hv[mt][r] = fmaf(d, acc[mt][r], c * tac[mt][r]);
+                if (em.live) {
+                    em.dp(kH * l + 16 * mt + 4 * g + r) = hv[mt][r];
+                    em.dt(kH * l + 16 * mt + 4 * g + r) = tv[mt][r];
+                }
+            }
+    }
+}
+
+// Stages W1, biases and w5 for tile_fp32_fm.
+__device__ inline void stage_small_fm(LdsFP32FM &L, const float *__restrict__ p) {
+    for (int idx = threadIdx.x; idx < kH * 8; idx += blockDim.x) {
+        const int o = idx >> 3, k = idx & 7;
+        L.w1[o][k] = k < kIn ? p[OFF_W1 + o * kIn + k] : 0.f;
+    }
+    for (int idx = threadIdx.x; idx < 4 * kH; idx += blockDim.x)
+        L.b[idx / kH][idx % kH] = p[b_off(idx / kH + 1) + idx % kH];
+    for (int idx = threadIdx.x; idx < kH; idx += blockDim.x) L.w5[idx] = p[OFF_W5 + idx];
+    if (threadIdx.x == 0) L.b5 = p[OFF_B5];
+}
 
 }  // namespace rb

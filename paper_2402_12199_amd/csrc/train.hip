@@ -26,41 +26,54 @@ struct TrainArgs {
     const float *params;
     Norm nm;          // input normalisation; output mapped to identity
     float oshift, oscale;
-    int32_t B;        // rows of the step
-    int32_t B1;       // rows 0 .. B1: energy rows (descriptors through idx, labels)
+    int32_t B;        // rows of the weight-gradient GEMMs: B1, or 2 B1 with force matching
+    int32_t B1;       // samples; rows 0 .. B1 are their primal rows (the only ones in the
+                      // bias gradients and the loss), rows B1 .. 2 B1 their tangent rows
     float k2;         // 2 / B1
     const float *desc;
     int64_t nd;
     const float *labels;
     const int32_t *idx;
-    const float *desc2;   // rows B1 .. B: descriptors (7 x (B - B1))
-    const float *adj2;    // and their output adjoints
+    const float *vt;      // force matching: tangent direction per sample (7 x B1, normalised units)
+    const float *alpha;   // and the tangent chain's output adjoint (B1)
     float *H, *D, *R, *part;
 };
 
-// Row b of a step: an energy row (descriptor through idx, energy loss) or,
-// past B1, a row with a given output adjoint; rows past B are padding.
+// Sample b of a step: descriptor through idx and normalised label; samples
+// past B1 are padding.
 __device__ inline void load_row(const TrainArgs &a, int b, Emit &em, float u[kIn]) {
     em.H = a.H;
     em.D = a.D;
     em.R = a.R;
     em.B = a.B;
     em.b = b;
-    em.live = b < a.B;
+    em.live = b < a.B1;
     em.k2 = a.k2;
-    em.fixed = em.live && b >= a.B1;
-    if (em.fixed) {
-        const int64_t m = a.B - a.B1, r = b - a.B1;
+    const int64_t pid = em.live ? a.idx[b] : 0;
 #pragma unroll
-        for (int k = 0; k < kIn; ++k) u[k] = a.desc2[k * m + r];
-        em.adj = a.adj2[r];
-        em.y = 0.f;
-    } else {
-        const int64_t pid = em.live ? a.idx[b] : 0;
+    for (int k = 0; k < kIn; ++k) u[k] = em.live ? a.desc[k * a.nd + pid] : (k == 3 ? 1.f : 0.f);
+    em.y = em.live ? (a.labels[pid] - a.oshift) / a.oscale : 0.f;
+}
+
+// The same for the force-matching step: both rows of sample b and its
+// tangent direction.
+__device__ inline void load_row_fm(const TrainArgs &a, int b, EmitFM &em, float u[kIn], float vt[kIn]) {
+    em.H = a.H;
+    em.D = a.D;
+    em.R = a.R;
+    em.Btot = a.B;
+    em.B1 = a.B1;
+    em.b = b;
+    em.live = b < a.B1;
+    em.k2 = a.k2;
+    const int64_t pid = em.live ? a.idx[b] : 0;
 #pragma unroll
-        for (int k = 0; k < kIn; ++k) u[k] = em.live ? a.desc[k * a.nd + pid] : (k == 3 ? 1.f : 0.f);
-        em.y = em.live ? (a.labels[pid] - a.oshift) / a.oscale : 0.f;
+    for (int k = 0; k < kIn; ++k) {
+        u[k] = em.live ? a.desc[k * a.nd + pid] : (k == 3 ? 1.f : 0.f);
+        vt[k] = em.live ? a.vt[(int64_t)k * a.B1 + b] : 0.f;
     }
+    em.y = em.live ? (a.labels[pid] - a.oshift) / a.oscale : 0.f;
+    em.alpha = em.live ? a.alpha[b] : 0.f;
 }
 
 template <bool BF16>
@@ -74,7 +87,7 @@ __global__ __launch_bounds__(nn_threads(BF16, 1)) void k_train_fb(TrainArgs a) {
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), n = lane & 15;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int ntiles = (a.B + kTile - 1) / kTile;
+    const int ntiles = (a.B1 + kTile - 1) / kTile;
     for (int t = blockIdx.x * kWaves + w; t < ntiles; t += gridDim.x * kWaves) {
         __asm__ volatile("" ::: "memory");
         const int b = t * kTile + n;
@@ -102,7 +115,7 @@ __global__ __launch_bounds__(kTrainWideThreads) void k_train_fb_wide(TrainArgs a
     const int lane = threadIdx.x & (kWave - 1), n = lane & 15;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int grp = wave / kWideGroup, v = wave % kWideGroup;
-    const int ntiles = (a.B + kTile - 1) / kTile;
+    const int ntiles = (a.B1 + kTile - 1) / kTile;
     for (int base = blockIdx.x * kTrainGroups; base < ntiles; base += gridDim.x * kTrainGroups) {
         const int b = (base + grp) * kTile + n;
         Emit em;
@@ -110,6 +123,43 @@ __global__ __launch_bounds__(kTrainWideThreads) void k_train_fb_wide(TrainArgs a
         load_row(a, b, em, u);
         float gu[kIn];
         (void)tile_bf16_wide<true, true>(L, X[grp], a.nm, u, 0.f, gu, v, em);
+    }
+}
+
+// Force matching, BF16: one four-wave group per block (the tangent chain's
+// exchange blocks take the LDS a second group would use), tiles of 16
+// samples, each emitting its primal and tangent rows.
+__global__ __launch_bounds__(kWideGroup * kWave) void k_train_fb_fm_wide(TrainArgs a) {
+    __shared__ LdsBF16 L;
+    __shared__ WideX X;
+    __shared__ WideT XT;
+    stage_bf16<kWideGroup * kWave>(L, a.params);
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), n = lane & 15;
+    const int v = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ntiles = (a.B1 + kTile - 1) / kTile;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        EmitFM em;
+        float u[kIn], vt[kIn];
+        load_row_fm(a, t * kTile + n, em, u, vt);
+        tile_bf16_wide_fm(L, X, XT, a.nm, u, vt, v, em);
+    }
+}
+
+// Force matching, FP32: one wave per tile of 16 samples.
+__global__ __launch_bounds__(kF32FmWaves * kWave) void k_train_fb_fm_fp32(TrainArgs a) {
+    __shared__ LdsFP32FM L;
+    stage_small_fm(L, a.params);
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), n = lane & 15;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ntiles = (a.B1 + kTile - 1) / kTile;
+    for (int t = blockIdx.x * kF32FmWaves + w; t < ntiles; t += gridDim.x * kF32FmWaves) {
+        __asm__ volatile("" ::: "memory");
+        EmitFM em;
+        float u[kIn], vt[kIn];
+        load_row_fm(a, t * kTile + n, em, u, vt);
+        tile_fp32_fm(L, a.params, a.nm, u, vt, em);
     }
 }
 
@@ -141,7 +191,7 @@ __device__ void wgrad_edge(const TrainArgs &a, int r0, int nr, float *part, floa
 #pragma unroll
                 for (int k = 0; k < kIn; ++k) s[k] = fmaf(dv[q], E[k][b], s[k]);
             }
-            s[kIn] += dv[q];
+            if (r0 + b < a.B1) s[kIn] += dv[q];    // primal rows only: the tangent chain has no bias
         }
 #pragma unroll
         for (int k = 0; k <= kIn; ++k) s[k] = wave_sum(s[k]);
@@ -166,7 +216,7 @@ __device__ void wgrad_edge(const TrainArgs &a, int r0, int nr, float *part, floa
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
             const int b = lane + kWave * q;
-            if (b < nr) {
+            if (b < nr && r0 + b < a.B1) {
                 s5 += E[kIn][b];
                 const float r = a.R[r0 + b];
                 l = fmaf(r, r, l);
@@ -193,7 +243,8 @@ __device__ void wgrad_edge(const TrainArgs &a, int r0, int nr, float *part, floa
 // outside ma x nb.
 __device__ __attribute__((always_inline)) inline void wgrad_gemm_bf16(const float *Ar, int ma, const float *Br, int nb,
                                                                     int64_t B, int r0, int r1,
-                                                                    float *dW, int ldw, float *db, bf16x8 *S) {
+                                                                    float *dW, int ldw, float *db, int bias_end,
+                                                                    bf16x8 *S) {
     const int t = threadIdx.x, f = t >> 2, p = t & 3;
     const bool va = f < ma, vb = f < nb;
     const float *arow = Ar + (int64_t)(va ? f : 0) * B + 8 * p;
@@ -226,10 +277,12 @@ __device__ __attribute__((always_inline)) inline void wgrad_gemm_bf16(const floa
         {
             const float av0[4] = {a0.x, a0.y, a0.z, a0.w}, av1[4] = {a1.x, a1.y, a1.z, a1.w};
             const float bv0[4] = {b0.x, b0.y, b0.z, b0.w}, bv1[4] = {b1.x, b1.y, b1.z, b1.w};
+            if (k0 < bias_end) {   // 32-row steps lie wholly before or after it (multiples of 32)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) dsum += av0[r];
+                for (int r = 0; r < 4; ++r) dsum += av0[r];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) dsum += av1[r];
+                for (int r = 0; r < 4; ++r) dsum += av1[r];
+            }
             bf16x8 hi, lo;
             split8(av0, av1, hi, lo);
             Sb[slot] = hi;
@@ -296,9 +349,9 @@ __device__ void wgrad_block_bf16(const TrainArgs &a, int y, int r0, int r1, floa
     if (y < 3) {
         const int layer = y + 2;
         wgrad_gemm_bf16(a.D + (int64_t)kH * (layer - 1) * B, kH, a.H + (int64_t)(kIn + kH * (layer - 2)) * B, kH, B,
-                        r0, r1, part + w_off(layer), kH, part + b_off(layer), S);
+                        r0, r1, part + w_off(layer), kH, part + b_off(layer), a.B1, S);
     } else if (y == 3) {
-        wgrad_gemm_bf16(a.D, kH, a.H, kIn, B, r0, r1, part + OFF_W1, kIn, part + OFF_B1, S);
+        wgrad_gemm_bf16(a.D, kH, a.H, kIn, B, r0, r1, part + OFF_W1, kIn, part + OFF_B1, a.B1, S);
     } else {
         if (threadIdx.x < kWave) {
             const int lane = threadIdx.x;
@@ -306,7 +359,7 @@ __device__ void wgrad_block_bf16(const TrainArgs &a, int y, int r0, int r1, floa
 #pragma unroll
             for (int q = 0; q < kChunk / kWave; ++q) {
                 const int b = r0 + lane + kWave * q;
-                rv[q] = b < r1 ? a.R[b] : 0.f;
+                rv[q] = b < r1 && b < a.B1 ? a.R[b] : 0.f;
             }
 #pragma unroll
             for (int q = 0; q < kChunk / kWave; ++q) l = fmaf(rv[q], rv[q], l);
@@ -314,7 +367,7 @@ __device__ void wgrad_block_bf16(const TrainArgs &a, int y, int r0, int r1, floa
             if (lane == 0) part[NPARAMS] = l;
         }
         wgrad_gemm_bf16(a.D + (int64_t)(4 * kH) * B, 1, a.H + (int64_t)(kIn + 3 * kH) * B, kH, B, r0, r1,
-                        part + OFF_W5, kH, part + OFF_B5, S);
+                        part + OFF_W5, kH, part + OFF_B5, a.B1, S);
     }
 }
 
@@ -332,7 +385,7 @@ __device__ void wgrad_layer_fp32(const TrainArgs &a, int layer, int r0, int r1, 
     float dsum = 0.f;
     for (int k0 = r0; k0 < r1; k0 += 4) {
         const float A = Dl[(int64_t)(16 * mt + n) * B + k0 + g];
-        dsum += A;
+        if (k0 + g < a.B1) dsum += A;
 #pragma unroll
         for (int nt = 0; nt < 8; ++nt)
             acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A, Hl[(int64_t)(16 * nt + n) * B + k0 + g], acc[nt], 0, 0,
@@ -418,12 +471,10 @@ __global__ void k_adam(float *__restrict__ p, float *__restrict__ m, float *__re
 // network's input gradient g = dE/du (pair descriptors u = (d, q), q =
 // (w, v)).  Its parameter gradient is sum_b v_b . dg_b/dtheta with
 // v_b = dL/dg_b (linear in the errors), i.e. the parameter gradient of the
-// directional derivative of E along v_b.  That directional derivative is
-// taken as a central difference, (E(u + eps vh) - E(u - eps vh)) / (2 eps)
-// along vh = v / |v|: two extra rows per sample whose output adjoints are
-// +-|v| oscale / (2 eps), which the ordinary reverse pass and weight-
-// gradient GEMMs then handle like any other row.  The difference is exact
-// to O(eps^2) in the third derivatives of E.
+// directional derivative of E along v_b, which the tangent rows of the
+// training kernels carry exactly (tile_bf16_wide_fm, tile_fp32_fm): the
+// direction in normalised input units is (v_b / |v_b|) (.) in_scale and the
+// tangent chain's output adjoint out_scale |v_b| (E = out_scale e' + ...).
 
 constexpr int kFmThreads = 256;
 
@@ -436,14 +487,14 @@ __global__ void k_fm_gather(int32_t B1, const float *__restrict__ desc, int64_t 
     for (int k = 0; k < kIn; ++k) descb[(int64_t)k * B1 + b] = desc[k * nd + pid];
 }
 
-// Per sample: the force and torque errors, the loss term, v = dL/dg and the
-// two difference rows with their adjoints; per-block loss partials.
+// Per sample: the force and torque errors, the loss term, v = dL/dg, the
+// tangent direction and its output adjoint; per-block loss partials.
 __global__ __launch_bounds__(kFmThreads) void k_fm_rows(int32_t B1, const float *__restrict__ descb,
                                                         const float *__restrict__ gb,
                                                         const float *__restrict__ ft_labels, int64_t nd,
                                                         const int32_t *__restrict__ idx, float lam_f, float lam_t,
-                                                        float step, float oscale, float *__restrict__ desc2,
-                                                        float *__restrict__ adj2, float *__restrict__ fmpart) {
+                                                        Norm nm, float *__restrict__ vt, float *__restrict__ alpha,
+                                                        float *__restrict__ fmpart) {
     __shared__ float red[kFmThreads / kWave];
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     float lsum = 0.f;
@@ -484,15 +535,9 @@ __global__ __launch_bounds__(kFmThreads) void k_fm_rows(int32_t B1, const float 
 #pragma unroll
         for (int k = 0; k < kIn; ++k) nv2 += v[k] * v[k];
         const float nv = sqrtf(nv2), inv = nv > 0.f ? 1.f / nv : 0.f;
-        const int64_t m = 2 * (int64_t)B1;
 #pragma unroll
-        for (int k = 0; k < kIn; ++k) {
-            desc2[k * m + b] = u[k] + step * v[k] * inv;
-            desc2[k * m + B1 + b] = u[k] - step * v[k] * inv;
-        }
-        const float s = oscale * nv / (2.f * step);
-        adj2[b] = s;
-        adj2[B1 + b] = -s;
+        for (int k = 0; k < kIn; ++k) vt[(int64_t)k * B1 + b] = v[k] * inv * nm.scale[k];
+        alpha[b] = nm.oscale * nv;
     }
     lsum = wave_sum(lsum);
     if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = lsum;
@@ -530,14 +575,20 @@ static int device_cus_train() {
     return cus;
 }
 
-// Forward/reverse, weight gradients and Adam over the rows of `a` (energy
-// rows first); fmpart (nfm partials) adds the matching loss to loss[1].
+// Forward/reverse, weight gradients and Adam over the rows of `a` (a.B1
+// samples; with a.vt set, each sample's primal and tangent rows, and fmpart
+// (nfm partials) adds the matching loss to loss[1]).
 static void train_launch(TrainArgs &a, int precision, float *params, float *adam_m, float *adam_v, int32_t t,
                          float lr, float beta1, float beta2, float eps, float *loss, float *grad_out,
                          const float *fmpart, int nfm, hipStream_t st) {
-    const int ntiles = (a.B + kTile - 1) / kTile;
+    const int ntiles = (a.B1 + kTile - 1) / kTile;
     const int cus = device_cus_train();
-    if (precision == RB_PREC_BF16) {
+    if (a.vt) {
+        if (precision == RB_PREC_BF16)
+            k_train_fb_fm_wide<<<grid_for(ntiles, 1, cus), kWideGroup * kWave, 0, st>>>(a);
+        else
+            k_train_fb_fm_fp32<<<grid_for(ntiles, kF32FmWaves, cus), kF32FmWaves * kWave, 0, st>>>(a);
+    } else if (precision == RB_PREC_BF16) {
         k_train_fb_wide<<<grid_for(ntiles, kTrainGroups, cus), kTrainWideThreads, 0, st>>>(a);
     } else {
         constexpr int wv = nn_threads(false, 1) / kWave;
@@ -572,8 +623,8 @@ static TrainArgs train_args(float *params, const float *norm, const float *desc,
     a.nd = n_data;
     a.labels = labels;
     a.idx = idx;
-    a.desc2 = nullptr;
-    a.adj2 = nullptr;
+    a.vt = nullptr;
+    a.alpha = nullptr;
     a.H = reinterpret_cast<float *>(w + Lw.H);
     a.D = reinterpret_cast<float *>(w + Lw.D);
     a.R = reinterpret_cast<float *>(w + Lw.R);
@@ -581,22 +632,22 @@ static TrainArgs train_args(float *params, const float *norm, const float *desc,
     return a;
 }
 
-// Workspace of the matching step: the training rows (3 per sample), then the
-// gathered descriptors, their input gradients, the difference rows, their
-// adjoints and the loss partials.
+// Workspace of the matching step: the training rows (2 per sample), then the
+// gathered descriptors, their input gradients, the tangent directions, their
+// output adjoints and the loss partials.
 struct FmLayout {
     TrainLayout tr;
-    size_t descb, gb, desc2, adj2, fmpart, total;
+    size_t descb, gb, vt, alpha, fmpart, total;
 };
 
 static FmLayout fm_layout(int32_t batch) {
     FmLayout f;
-    f.tr = train_layout(3 * batch);
+    f.tr = train_layout(2 * batch);
     size_t o = f.tr.total;
     f.descb = o; o += al(sizeof(float) * (size_t)kIn * batch);
     f.gb = o; o += al(sizeof(float) * (size_t)kIn * batch);
-    f.desc2 = o; o += al(sizeof(float) * (size_t)kIn * 2 * batch);
-    f.adj2 = o; o += al(sizeof(float) * (size_t)2 * batch);
+    f.vt = o; o += al(sizeof(float) * (size_t)kIn * batch);
+    f.alpha = o; o += al(sizeof(float) * (size_t)batch);
     f.fmpart = o; o += al(sizeof(float) * (size_t)((batch + kFmThreads - 1) / kFmThreads));
     f.total = o;
     return f;
@@ -638,31 +689,31 @@ extern "C" int rb_nn_train_step(float *params, float *adam_m, float *adam_v, int
 extern "C" int rb_nn_train_step_fm(float *params, float *adam_m, float *adam_v, int32_t t, const float *norm,
                                    int precision, int32_t batch, const float *desc, int64_t n_data,
                                    const float *labels, const float *ft_labels, const int32_t *idx, float lam_f,
-                                   float lam_t, float fd_step, float lr, float beta1, float beta2, float eps,
-                                   float *loss, float *grad_out, void *ws, size_t ws_bytes, void *stream) {
+                                   float lam_t, float lr, float beta1, float beta2, float eps, float *loss,
+                                   float *grad_out, void *ws, size_t ws_bytes, void *stream) {
     RB_REQUIRE(params && adam_m && adam_v && norm && desc && labels && ft_labels && idx && loss && ws,
                "rb_nn_train_step_fm: null argument");
     RB_REQUIRE(precision == RB_PREC_BF16 || precision == RB_PREC_FP32, "rb_nn_train_step_fm: bad precision");
     RB_REQUIRE(batch > 0 && batch % 32 == 0 && batch <= (1 << 18),
                "rb_nn_train_step_fm: batch must be a positive multiple of 32, at most 2^18");
     RB_REQUIRE(n_data > 0 && t >= 1, "rb_nn_train_step_fm: n_data > 0 and t >= 1 required");
-    RB_REQUIRE(lam_f >= 0.f && lam_t >= 0.f && fd_step > 0.f, "rb_nn_train_step_fm: lam >= 0 and fd_step > 0");
+    RB_REQUIRE(lam_f >= 0.f && lam_t >= 0.f, "rb_nn_train_step_fm: lam >= 0 required");
     const FmLayout F = fm_layout(batch);
     RB_REQUIRE(ws_bytes >= F.total, "rb_nn_train_step_fm: workspace too small (%zu < %zu)", ws_bytes, F.total);
     char *w = static_cast<char *>(ws);
     hipStream_t st = (hipStream_t)stream;
     float *descb = reinterpret_cast<float *>(w + F.descb), *gb = reinterpret_cast<float *>(w + F.gb);
-    float *desc2 = reinterpret_cast<float *>(w + F.desc2), *adj2 = reinterpret_cast<float *>(w + F.adj2);
+    float *vt = reinterpret_cast<float *>(w + F.vt), *alpha = reinterpret_cast<float *>(w + F.alpha);
     float *fmpart = reinterpret_cast<float *>(w + F.fmpart);
     const int nblk = (batch + kFmThreads - 1) / kFmThreads;
     k_fm_gather<<<nblk, kFmThreads, 0, st>>>(batch, desc, n_data, idx, descb);
     const int rc = rb_nn_pair_grad(params, norm, precision, batch, descb, nullptr, nullptr, gb, nullptr, stream);
     if (rc != RB_OK) return rc;
-    k_fm_rows<<<nblk, kFmThreads, 0, st>>>(batch, descb, gb, ft_labels, n_data, idx, lam_f, lam_t, fd_step, norm[15],
-                                           desc2, adj2, fmpart);
-    TrainArgs a = train_args(params, norm, desc, n_data, labels, idx, 3 * batch, batch, w, F.tr);
-    a.desc2 = desc2;
-    a.adj2 = adj2;
+    k_fm_rows<<<nblk, kFmThreads, 0, st>>>(batch, descb, gb, ft_labels, n_data, idx, lam_f, lam_t,
+                                           norm_from_host(norm), vt, alpha, fmpart);
+    TrainArgs a = train_args(params, norm, desc, n_data, labels, idx, 2 * batch, batch, w, F.tr);
+    a.vt = vt;
+    a.alpha = alpha;
     train_launch(a, precision, params, adam_m, adam_v, t, lr, beta1, beta2, eps, loss, grad_out, fmpart, nblk, st);
     RB_LAUNCH_CHECK("rb_nn_train_step_fm");
     return RB_OK;

@@ -116,7 +116,7 @@ class Trainer:
 
     def __init__(self, params: np.ndarray, norm: np.ndarray, precision=abi.RB_PREC_BF16, batch=8192, lr=1e-3,
                  beta1=0.9, beta2=0.999, eps=1e-8, device="cuda", fm: dict | None = None):
-        """fm: dict(lam_f, lam_t, fd_step) adds force and torque matching
+        """fm: dict(lam_f, lam_t) adds force and torque matching
         (rb_nn_train_step_fm); the data then need (6, n) F_j, tau_j labels."""
         self.dev = torch.device(device)
         self.params = torch.tensor(np.asarray(params, np.float32), device=self.dev)
@@ -142,9 +142,8 @@ class Trainer:
                                  labels, idx, self.lr, self.beta1, self.beta2, self.eps, loss[:1], grad_out, self.ws)
         else:
             abi.rb_nn_train_step_fm(self.params, self.m, self.v, self.t, self.norm, self.precision, idx.numel(),
-                                    desc, labels, ft, idx, self.fm["lam_f"], self.fm["lam_t"],
-                                    self.fm.get("fd_step", 0.1), self.lr, self.beta1, self.beta2, self.eps, loss,
-                                    grad_out, self.ws)
+                                    desc, labels, ft, idx, self.fm["lam_f"], self.fm["lam_t"], self.lr, self.beta1,
+                                    self.beta2, self.eps, loss, grad_out, self.ws)
 
     def epoch(self, desc, labels, g: np.random.Generator, ft=None):
         """One pass over the data in a random order; returns the mean energy

@@ -103,7 +103,7 @@ def fit(desc: np.ndarray, lab: np.ndarray, tdesc: np.ndarray, tlab: np.ndarray, 
         seed: int, batch: int = 8192, lr: float = 1e-3, precision: int = abi.RB_PREC_BF16, init_seed: int = 1003,
         log=None, name: str = "", fm: dict | None = None, sym: bool = False, form: str | None = None) -> dict:
     """Train a fresh network (Xavier init) on energies (and, with fm =
-    dict(lam_f, lam_t[, fd_step]) or dict(weight[, fd_step]), on the bead
+    dict(lam_f, lam_t) or dict(weight), on the bead
     forces and torques too; `weight` sets lam_f, lam_t to weight over the
     mean squared label), return it with the held-out errors before and
     after.  sym: train on the symmetry-reduced cube-pair descriptor
@@ -187,27 +187,58 @@ def md_pair_samples(sysm, dt: float, n: int, every: int, d_min: float, d_max: fl
 
 
 def train_surrogate_md(cfg, st, n_train: int, n_test: int, epochs: int, every: int = 10, seed: int = 1006,
-                       r_rej: float = 0.8, log=None, gap_min=None, gap_max=None, **kw) -> dict:
+                       r_rej: float = 0.8, log=None, gap_min=None, gap_max=None, kTs=None, **kw) -> dict:
     """Surrogate trained on configurations drawn from the bead-path dynamics
     of a workload (paper section 2: training pairs come from composite-body
     simulations).  The held-out set comes from the later part of the same
     trajectory, after the training snapshots.  With gap_min the pairs are
-    those the shells' routing gives the network (see rb_pair_descriptors)."""
+    those the shells' routing gives the network (see rb_pair_descriptors).
+    kTs: temperatures of constant-temperature (Nose-Hoover) bead runs that
+    share the training set equally, as the paper samples over a range of
+    temperatures so that touching and slightly overlapping pairs are covered
+    (section 2); the held-out set then comes from the later part of the run
+    at kTs[0] (the workload's own temperature, normally).  None: the
+    workload's constant-energy run alone."""
     from .md import RigidSystem
     t0 = time.perf_counter()
     b = cfg.body
-    sysm = RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"], cfg.box,
-                       cfg.r_list, cfg.skin, hphc=cfg.hphc, margin=cfg.bead_margin)
-    sysm.init_forces("bead")
-    desc, s_train = md_pair_samples(sysm, cfg.dt, n_train, every, cfg.d_min, cfg.d_cut, gap_min=gap_min,
-                                    gap_max=gap_max)
-    tdesc, s_test = md_pair_samples(sysm, cfg.dt, n_test, max(1, every // 2), cfg.d_min, cfg.d_cut, gap_min=gap_min,
-                                    gap_max=gap_max)
+
+    def system(kT):
+        nvt = None if kT is None else dict(kT=kT, tau=0.5)
+        P, L = st["P"], st["L"]
+        if kT is not None:      # momenta drawn at cfg.kT, rescaled to kT
+            P, L = P * np.sqrt(kT / cfg.kT), L * np.sqrt(kT / cfg.kT)
+        s = RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], P, L, cfg.box, cfg.r_list,
+                        cfg.skin, hphc=cfg.hphc, margin=cfg.bead_margin if kT is None else None, nvt=nvt)
+        s.init_forces("bead")
+        return s
+
+    route = dict(gap_min=gap_min, gap_max=gap_max)
+    if kTs is None:
+        sysm = system(None)
+        desc, s_train = md_pair_samples(sysm, cfg.dt, n_train, every, cfg.d_min, cfg.d_cut, **route)
+        tdesc, s_test = md_pair_samples(sysm, cfg.dt, n_test, max(1, every // 2), cfg.d_min, cfg.d_cut, **route)
+    else:
+        parts, s_train, first = [], 0, None
+        for k, kT in enumerate(kTs):
+            m = n_train // len(kTs) + (n_train % len(kTs) if k == 0 else 0)
+            sk = system(kT)
+            first = first or sk
+            d, s_k = md_pair_samples(sk, cfg.dt, m, every, cfg.d_min, cfg.d_cut, **route)
+            parts.append(d)
+            s_train += s_k
+            if log:
+                log(f"[surrogate {b.name}] {len(d)} pairs from a bead run at kT={kT} ({s_k} steps)")
+        desc = np.concatenate(parts)
+        # held out: the later part of the first temperature's run
+        sysm = first
+        tdesc, s_test = md_pair_samples(sysm, cfg.dt, n_test, max(1, every // 2), cfg.d_min, cfg.d_cut, **route)
     desc, lab = label_set(sysm.ctx, desc, r_rej)
     tdesc, tlab = label_set(sysm.ctx, tdesc, r_rej)
     t_label = time.perf_counter() - t0
     r = fit(desc, lab, tdesc, tlab, cfg.d_cut, epochs, seed, log=log, name=b.name, **kw)
-    r.update(sampling=f"bead MD of {cfg.name}: {s_train} steps, every {every} (train), then {s_test} steps "
+    where = "" if kTs is None else f" at kT = {', '.join(str(v) for v in kTs)} (constant temperature)"
+    r.update(sampling=f"bead MD of {cfg.name}{where}: {s_train} steps, every {every} (train), then {s_test} steps "
                       f"(held out)", d_min=cfg.d_min, label_s=t_label)
     return r
 

@@ -203,3 +203,12 @@ def test_training_step_batch_8192_matches_oracle(abi, prec):
     pref, mref, _ = omlp.adam_step(params.astype(np.float64), 0.0, 0.0, 1, gg.astype(np.float64))
     np.testing.assert_allclose(p.cpu().numpy(), pref, rtol=1e-6, atol=1e-9)
     np.testing.assert_allclose(m.cpu().numpy(), mref, rtol=1e-6, atol=1e-12)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_force_matching_step_batch_8192_matches_oracle(abi, prec):
+    # the workload's batch with force/torque matching: 8192 primal and 8192
+    # tangent rows through the four-wave kernel's persistent loop and 64
+    # weight-gradient chunks (biases from the first 32 only)
+    from tests.test_gpu_train import fm_step_vs_oracle
+    fm_step_vs_oracle(abi, prec, 8192, 12000)

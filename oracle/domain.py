@@ -15,14 +15,19 @@ Shells, in the body frame (centre of mass at the origin):
 * a capsule along the body axis k with the largest h_k: the points within
   R of the segment from -H e_k to +H e_k, with R the largest distance of a
   bead from that axis and H the smallest half-length that keeps every bead
-  inside.
+  inside;
+* the solid cylinder around the same axis with radius R and half-height h_k.
 
 For convex sets, the gap between the projections onto any unit axis is a
 lower bound on their distance (separating-axis theorem); for the boxes the
 15 candidate axes of two boxes are tried (each box's face normals and the
 cross products of their edges).  The capsule distance is the distance of the
-two segments minus both radii.  gap = max(box gap, capsule gap) bounds the
-closest bead-centre distance from below.
+two segments minus both radii.  For the cylinders, the projected gap along
+trial directions: starting from the direction between the capsules' closest
+points, and again from the direction between the centres, each next
+direction is that of the difference of the two support points along the
+current one (six directions from each start).  gap = the largest of these
+bounds the closest bead-centre distance from below.
 """
 from __future__ import annotations
 
@@ -103,6 +108,45 @@ def segment_distance(p0, p1, q0, q1) -> np.ndarray:
     return out if out.size > 1 else float(out[0])
 
 
+def cylinder_support(c, a, H, R, n):
+    """Support points (P, 3) of solid cylinders (centres c, unit axes a,
+    half-height H, radius R) in the unit directions n: the cap centre on the
+    side n faces plus R along n's component perpendicular to the axis."""
+    na = np.sum(n * a, 1, keepdims=True)
+    perp = n - na * a
+    pn = np.linalg.norm(perp, axis=1, keepdims=True)
+    radial = np.where(pn > 1e-12, R * perp / np.where(pn > 1e-12, pn, 1.0), 0.0)
+    return c + np.where(na >= 0, H, -H) * a + radial
+
+
+def cylinder_gap(ca, aa, Ha, Ra, cb, ab, Hb, Rb, n0, iters=6):
+    """Largest projected gap between cylinders A and B over the trial
+    directions of the support-point iteration started from n0 (P, 3)."""
+    n = n0 / np.linalg.norm(n0, axis=1, keepdims=True)
+    best = np.full(len(n), -np.inf)
+    for _ in range(iters):
+        diff = cylinder_support(cb, ab, Hb, Rb, -n) - cylinder_support(ca, aa, Ha, Ra, n)
+        best = np.maximum(best, np.sum(n * diff, 1))
+        dn = np.linalg.norm(diff, axis=1, keepdims=True)
+        n = np.where(dn > 1e-12, diff / np.where(dn > 1e-12, dn, 1.0), n)
+    return best
+
+
+def _closest_direction(p0, p1, q0, q1):
+    """Unit vectors from the closest point of [p0, p1] to that of [q0, q1]
+    (dense parameter search around the exact distance is not needed: the
+    direction only seeds the cylinder iteration)."""
+    u, v, w = p1 - p0, q1 - q0, p0 - q0
+    a, b, c = np.sum(u * u, 1), np.sum(u * v, 1), np.sum(v * v, 1)
+    dd, e = np.sum(u * w, 1), np.sum(v * w, 1)
+    den = a * c - b * b
+    s = np.where(den > 1e-12 * a * c, np.clip((b * e - c * dd) / np.where(den > 0, den, 1.0), 0, 1), 0.5)
+    t = np.clip((b * s + e) / np.where(c > 0, c, 1.0), 0, 1)
+    s = np.clip((b * t - dd) / np.where(a > 0, a, 1.0), 0, 1)
+    diff = (q0 + t[:, None] * v) - (p0 + s[:, None] * u)
+    return diff
+
+
 def gap(beads_i: np.ndarray, beads_j: np.ndarray, desc: np.ndarray) -> np.ndarray:
     """Lower bound (P,) on the closest bead-centre distance of each pair
     configuration desc (P, 7) = (d, q) (body j at d with orientation q in
@@ -117,4 +161,11 @@ def gap(beads_i: np.ndarray, beads_j: np.ndarray, desc: np.ndarray) -> np.ndarra
     ei = np.broadcast_to(np.eye(3)[ki], d.shape)
     ej = R[:, :, kj]
     gc = np.atleast_1d(segment_distance(-Hi * ei, Hi * ei, d - Hj * ej, d + Hj * ej)) - Ri - Rj
-    return np.maximum(gb, gc)
+    G = np.maximum(gb, gc)
+    zero = np.zeros_like(d)
+    for n0 in (_closest_direction(-Hi * ei, Hi * ei, d - Hj * ej, d + Hj * ej), d):
+        ok = np.linalg.norm(n0, axis=1) > 1e-9
+        n0 = np.where(ok[:, None], n0, 1.0)
+        gcyl = cylinder_gap(zero, ei, hi[ki], Ri, d, ej, hj[kj], Rj, n0)
+        G = np.where(ok, np.maximum(G, gcyl), G)
+    return G

@@ -1,15 +1,17 @@
-// Lower bound on the closest bead-centre distance of a body pair from two
-// convex shells around each body's bead centres: the bead-centre box and a
-// capsule along the body's longest axis (both in the context's templates).
+// Lower bound on the closest bead-centre distance of a body pair from convex
+// shells around each body's bead centres: the bead-centre box, a capsule
+// along the body's longest axis and the solid cylinder around that axis with
+// the capsule's radius and the box's extent (all in the context's templates).
 //
 // The separation of two convex sets along any unit axis bounds their
 // distance from below (separating-axis theorem): for the boxes, the 15
 // candidate axes (each box's face normals and the cross products of their
 // edge directions, normalised; near-parallel edge pairs give no axis).  For
-// the capsules, the distance of their segments minus both radii.  The bound
-// is the larger of the two.  A pair whose bound reaches rc has no bead pair
-// within rc; a pair whose bound reaches the network's training minimum lies
-// inside the network's domain.
+// the capsules, the distance of their segments minus both radii.  For the
+// cylinders, the projected gap along a few directions found by a support-
+// point iteration.  The bound is the largest of these.  A pair whose bound
+// reaches rc has no bead pair within rc; a pair whose bound reaches the
+// network's training minimum lies inside the network's domain.
 #pragma once
 
 #include "rb_common.hpp"
@@ -21,7 +23,7 @@ namespace rb {
 // distance (a convex quadratic in s, t), s clamped, t optimal for it, and
 // s re-optimised when t had to be clamped.
 __device__ inline double segment_distance(const double c1[3], const double e1[3], double H1, const double c2[3],
-                                          const double e2[3], double H2) {
+                                          const double e2[3], double H2, double diff[3]) {
     double w[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) w[a] = c1[a] - c2[a];
@@ -38,10 +40,43 @@ __device__ inline double segment_distance(const double c1[3], const double e1[3]
     double r2 = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double v = w[a] + s * e1[a] - t * e2[a];
-        r2 += v * v;
+        diff[a] = -(w[a] + s * e1[a] - t * e2[a]);   // closest point on 2 minus closest point on 1
+        r2 += diff[a] * diff[a];
     }
     return sqrt(r2);
+}
+
+// Support point of the solid cylinder (centre c, unit axis a, half-height H,
+// radius R) in the unit direction n: the point of the cylinder farthest along
+// n (on the rim of the cap facing n; at the cap's centre when n is along the
+// axis).
+__device__ inline void cyl_support(const double c[3], const double a[3], double H, double R, const double n[3],
+                                   double s[3]) {
+    const double na = n[0] * a[0] + n[1] * a[1] + n[2] * a[2];
+    double p[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) p[k] = n[k] - na * a[k];
+    const double pn = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    const double rs = pn > 1e-12 ? R / pn : 0.0;
+    const double hs = na >= 0.0 ? H : -H;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s[k] = c[k] + hs * a[k] + rs * p[k];
+}
+
+// Gap between the projections of cylinders A and B onto the unit direction n
+// (a lower bound on their distance for every n), and the difference of the
+// two support points (B's nearest to A along n minus A's farthest toward B),
+// whose direction is the next trial direction: for the direction between the
+// cylinders' closest points the gap equals their distance.
+__device__ inline double cyl_gap_along(const double ca[3], const double aa[3], double Ha, double Ra,
+                                       const double cb[3], const double ab[3], double Hb, double Rb, const double n[3],
+                                       double diff[3]) {
+    double sa[3], sb[3], m[3] = {-n[0], -n[1], -n[2]};
+    cyl_support(ca, aa, Ha, Ra, n, sa);
+    cyl_support(cb, ab, Hb, Rb, m, sb);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) diff[k] = sb[k] - sa[k];
+    return n[0] * diff[0] + n[1] * diff[1] + n[2] * diff[2];
 }
 
 // Bound for body j (type tj) at d with rotation R (row major, body j's axes
@@ -79,8 +114,37 @@ __device__ inline double shell_gap(const Templates &T, int ti, int tj, const dou
     const double c1[3] = {0.0, 0.0, 0.0};
     const double e1[3] = {ki == 0 ? 1.0 : 0.0, ki == 1 ? 1.0 : 0.0, ki == 2 ? 1.0 : 0.0};
     const double e2[3] = {R[kj], R[3 + kj], R[6 + kj]};
-    const double sd = segment_distance(c1, e1, T.cH[ti], d, e2, T.cH[tj]);
-    return fmax(G, sd - (double)T.cR[ti] - (double)T.cR[tj]);
+    double cp[3];
+    const double sd = segment_distance(c1, e1, T.cH[ti], d, e2, T.cH[tj], cp);
+    G = fmax(G, sd - (double)T.cR[ti] - (double)T.cR[tj]);
+    // Cylinders around the same axes (radius that of the capsule, half-height
+    // the box's extent along the axis), which hold every bead centre: trial
+    // directions from the capsules' closest points and from the centres,
+    // each refined by moving to the direction between the current support
+    // points, the largest projected gap kept.
+    const double Ha = ki == 0 ? a[0] : (ki == 1 ? a[1] : a[2]);
+    const double Hb = kj == 0 ? b[0] : (kj == 1 ? b[1] : b[2]);
+    const double Ra = T.cR[ti], Rb = T.cR[tj];
+    const double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double cpn = sqrt(cp[0] * cp[0] + cp[1] * cp[1] + cp[2] * cp[2]);
+#pragma unroll
+    for (int start = 0; start < 2; ++start) {
+        double n[3];
+        const bool use_cp = start == 0 && cpn > 1e-9;
+        const double inv = use_cp ? 1.0 / cpn : (dn > 0.0 ? 1.0 / dn : 0.0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) n[k] = (use_cp ? cp[k] : d[k]) * inv;
+        if (!use_cp && dn == 0.0) break;
+        for (int it = 0; it < 6; ++it) {
+            double diff[3];
+            G = fmax(G, cyl_gap_along(c1, e1, Ha, Ra, d, e2, Hb, Rb, n, diff));
+            const double dd = sqrt(diff[0] * diff[0] + diff[1] * diff[1] + diff[2] * diff[2]);
+            if (!(dd > 1e-12)) break;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) n[k] = diff[k] / dd;
+        }
+    }
+    return G;
 }
 
 }  // namespace rb

@@ -101,12 +101,15 @@ def label_set(ctx: abi.Ctx, desc: np.ndarray, r_rej: float = 0.8, type_i: int = 
 
 def fit(desc: np.ndarray, lab: np.ndarray, tdesc: np.ndarray, tlab: np.ndarray, d_cut: float, epochs: int,
         seed: int, batch: int = 8192, lr: float = 1e-3, precision: int = abi.RB_PREC_BF16, init_seed: int = 1003,
-        log=None, name: str = "", fm: dict | None = None, sym: bool = False, form: str | None = None) -> dict:
+        log=None, name: str = "", fm: dict | None = None, sym: bool = False, form: str | None = None,
+        lr_end: float | None = None) -> dict:
     """Train a fresh network (Xavier init) on energies (and, with fm =
     dict(lam_f, lam_t) or dict(weight), on the bead
     forces and torques too; `weight` sets lam_f, lam_t to weight over the
     mean squared label), return it with the held-out errors before and
-    after.  sym: train on the symmetry-reduced cube-pair descriptor
+    after.  lr_end: the learning rate decays from lr to lr_end over the
+    epochs (half a cosine period); None keeps lr.  sym: train on the
+    symmetry-reduced cube-pair descriptor
     (supplementary section 1; energy loss only)."""
     from synth import sampling
     form = form or ("cube" if sym else "dq")
@@ -136,6 +139,8 @@ def fit(desc: np.ndarray, lab: np.ndarray, tdesc: np.ndarray, tlab: np.ndarray, 
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for ep in range(epochs):
+        if lr_end is not None:      # cosine decay from lr to lr_end over the epochs
+            tr.lr = lr_end + 0.5 * (lr - lr_end) * (1.0 + np.cos(np.pi * ep / max(epochs - 1, 1)))
         hist.append(tr.epoch(d_dev, y_dev, g, ft_dev))
         if log and (ep % max(1, epochs // 10) == 0 or ep == epochs - 1):
             log(f"[surrogate {name}] epoch {ep + 1}/{epochs} loss {hist[-1]:.4f}" +

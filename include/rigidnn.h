@@ -178,9 +178,11 @@ int rb_pair_descriptors(int32_t n, const double *x, const double *q, const doubl
                         const int32_t *type, float gap_min, float gap_max, void *stream);
 
 /* ---- bead double sum (paper section 2, first equation) -------------------
- * Every bead pair closer than rc contributes; bead pairs are skipped only
- * when a bead lies farther than rc from the other body's bead box, which
- * cannot hold a partner within rc.
+ * Every bead pair closer than rc contributes; a body pair is skipped only
+ * when the shells' lower bound on its closest bead distance (as in
+ * rb_pair_descriptors) reaches rc, and a bead only when it lies farther than
+ * rc from the other body's bead box, which cannot hold a partner within
+ * rc.
  * Per-pair form, for labelling and checks: body i of type type_i at the
  * origin with identity orientation, body j of type type_j at desc's d with
  * orientation q/|q|.  out: 11 x n_pairs FP32 = E, F_j[3], tau_i[3], tau_j[3]
@@ -192,8 +194,9 @@ int rb_bead_pair_eval(const rb_ctx *ctx, int64_t n_pairs, const float *desc, int
 
 /* Screen for the per-body form: of the pairs idx[0 .. *count_dev) of the
  * list (idx == NULL: 0 .. *count_dev, capped at max_count), keeps those whose
- * bead boxes can be within rc (separating-axis test between body j's bead
- * box and body i's grown by rc, the same test rb_bead_pair_forces applies);
+ * lower bound on the closest bead-centre distance is below rc (the shells'
+ * bound of rb_pair_descriptors: bead-centre boxes, and for cylinder-like
+ * types capsules and cylinders; the same test rb_bead_pair_forces applies);
  * every other pair has exactly zero bead energy, force and torque.  Writes
  * the kept pair ids to idx_out (capacity max_count, order not specified) and
  * their number to *count_out, to be passed to rb_bead_pair_forces.  tmp: two
@@ -221,8 +224,8 @@ int rb_bead_pair_forces(const rb_ctx *ctx, int32_t n, const double *x, const dou
  * but a launch visits only the listed pairs of a screened list unless
  * flags[RESCREEN] is set.  A launch with flags[RESCREEN] set evaluates the
  * whole list and rebuilds the screened list: screen_list (capacity
- * max_count) receives the pairs whose bead boxes come within rc + margin
- * (separating-axis test, as in rb_bead_screen with rc widened by margin),
+ * max_count) receives the pairs whose shells' bound is below rc + margin
+ * (as in rb_bead_screen with rc widened by margin),
  * flags[NSCREEN] their number; x, q are copied to x_sref (3 x n) and q_sref
  * (4 x n); flags[RESCREEN] is cleared and flags[NRESCREENS] incremented.
  * A listed pair outside the screened list has no bead pair within rc while

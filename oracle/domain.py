@@ -17,6 +17,9 @@ Shells, in the body frame (centre of mass at the origin):
   bead from that axis and H the smallest half-length that keeps every bead
   inside;
 * the solid cylinder around the same axis with radius R and half-height h_k.
+The round shells (capsule, cylinder) are formed only for bodies whose
+cylinder is narrower than their box (pi R^2 < 4 h_a h_b across the axis):
+cylinders, not cubes.
 
 For convex sets, the gap between the projections onto any unit axis is a
 lower bound on their distance (separating-axis theorem); for the boxes the
@@ -147,6 +150,13 @@ def _closest_direction(p0, p1, q0, q1):
     return diff
 
 
+def _round(h, k, R) -> bool:
+    """Whether the round shells (capsule, cylinder) are formed for a body:
+    its cylinder's cross-section pi R^2 is smaller than its box's across the
+    axis (cylinders yes, cubes no)."""
+    return np.pi * R * R < 4.0 * h[(k + 1) % 3] * h[(k + 2) % 3]
+
+
 def gap(beads_i: np.ndarray, beads_j: np.ndarray, desc: np.ndarray) -> np.ndarray:
     """Lower bound (P,) on the closest bead-centre distance of each pair
     configuration desc (P, 7) = (d, q) (body j at d with orientation q in
@@ -160,6 +170,8 @@ def gap(beads_i: np.ndarray, beads_j: np.ndarray, desc: np.ndarray) -> np.ndarra
     gb = box_gap(hi, hj, d, R)
     ei = np.broadcast_to(np.eye(3)[ki], d.shape)
     ej = R[:, :, kj]
+    if not (_round(hi, ki, Ri) and _round(hj, kj, Rj)):
+        return gb
     gc = np.atleast_1d(segment_distance(-Hi * ei, Hi * ei, d - Hj * ej, d + Hj * ej)) - Ri - Rj
     G = np.maximum(gb, gc)
     zero = np.zeros_like(d)

@@ -25,6 +25,7 @@
 //     pair identities (central bead forces): F_j = -F_i and
 //     tau_j = d x F_i - tau_i.
 #include "rb_common.hpp"
+#include "shells.hpp"
 
 namespace rb {
 
@@ -402,9 +403,9 @@ __device__ inline void pair_geometry(int32_t n, const double *__restrict__ x, co
     quat_to_rot<double>(qr[0], qr[1], qr[2], qr[3], R);
 }
 
-// Screen: one thread per listed pair; keeps the pairs whose bead boxes pass
-// the separating-axis test (the others have exactly zero bead energy, force
-// and torque) and appends them to idx_out with one atomic per wave.  tmp[0]
+// Screen: one thread per listed pair; keeps the pairs whose shells' bound on
+// the closest bead distance is below rc (the others have exactly zero bead
+// energy, force and torque) and appends them to idx_out with one atomic per wave.  tmp[0]
 // (append counter) and tmp[1] (finishing ticket) are zero on entry and left
 // zero; the last workgroup publishes the count.  The screened-out pairs are
 // counted as evaluated (their contribution is known to be zero).
@@ -436,7 +437,7 @@ __global__ __launch_bounds__(256) void k_bead_screen(Templates T, float rcm, int
             const int i = pi[pid], j = pj[pid];
             double dl[3], d[3], R[9];
             pair_geometry(n, x, q, box, i, j, dl, d, R);
-            keep = may_interact(T, type[i], type[j], d, R, rcm);
+            keep = shell_route(T, type[i], type[j], d, R, 0.f, rcm) != kRouteSkip;
         }
         const unsigned long long m = __ballot(keep);
         if (m) {
@@ -639,8 +640,11 @@ __global__ __launch_bounds__(kMdWaves * kWave) __attribute__((amdgpu_waves_per_e
             double R[9], Ri[9];
             pair_frame(n, x, q, box, i, j, dl, d, qr, qa, Ri);
             quat_to_rot<double>(qr[0], qr[1], qr[2], qr[3], R);
-            hit = may_interact(T, ti, tj, d, R, rcm);
-            if (SCREENED && full) wide = hit || may_interact(T, ti, tj, d, R, S.rcm_wide);
+            // the shells' bound on the closest bead distance (box, and for
+            // cylinder-like types capsule and cylinder) decides which pairs
+            // can have a bead pair within rc
+            hit = shell_route(T, ti, tj, d, R, 0.f, rcm) != kRouteSkip;
+            if (SCREENED && full) wide = hit || shell_route(T, ti, tj, d, R, 0.f, S.rcm_wide) != kRouteSkip;
         }
         if (SCREENED && full) {
             list_append(hit, pid, S.tmp, S.list, max_count, false, lane);

@@ -141,6 +141,7 @@ extern "C" int rb_ctx_create(rb_ctx **out, int32_t n_types, const int32_t *n_bea
         c->dev.t.cax[t] = k;
         c->dev.t.cR[t] = nextafterf((float)sqrt(R2), 1e30f);
         c->dev.t.cH[t] = H > 0.0 ? nextafterf((float)H, 1e30f) : 0.f;
+        c->dev.t.round[t] = 3.14159265358979 * R2 < 4.0 * (double)h[(k + 1) % 3] * (double)h[(k + 2) % 3];
     }
     c->dev.t.n_types = n_types;
     int rc_ = RB_OK;

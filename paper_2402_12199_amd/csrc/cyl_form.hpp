@@ -13,53 +13,57 @@
 // axis, homogeneous in q) and t = d_x A_x + d_y A_y,
 //   s = (d_x^2 + d_y^2, d_z^2, A_z^2, t^2, t A_z d_z, 0, 0),
 // smooth where the frame choice is not (p_r = 0, p_z = 0).  The Jacobian is
-// written out from these polynomials.
+// written out from these polynomials.  Templated on the arithmetic type: the
+// network kernels take FP32 (their inputs are FP32), the descriptor kernel
+// FP64.
 #pragma once
 
 #include "rb_common.hpp"
 
 namespace rb {
 
-__device__ inline void cyl_features(const double u[7], double s[7]) {
-    const double dx = u[0], dy = u[1], dz = u[2], w = u[3], x = u[4], y = u[5], z = u[6];
-    const double Ax = 2.0 * (x * z + w * y), Ay = 2.0 * (y * z - w * x), Az = w * w - x * x - y * y + z * z;
-    const double t = dx * Ax + dy * Ay;
+template <typename Real>
+__device__ inline void cyl_features(const Real u[7], Real s[7]) {
+    const Real dx = u[0], dy = u[1], dz = u[2], w = u[3], x = u[4], y = u[5], z = u[6];
+    const Real Ax = 2 * (x * z + w * y), Ay = 2 * (y * z - w * x), Az = w * w - x * x - y * y + z * z;
+    const Real t = dx * Ax + dy * Ay;
     s[0] = dx * dx + dy * dy;
     s[1] = dz * dz;
     s[2] = Az * Az;
     s[3] = t * t;
     s[4] = t * Az * dz;
-    s[5] = 0.0;
-    s[6] = 0.0;
+    s[5] = 0;
+    s[6] = 0;
 }
 
 // J[r][m] = d s_r / d u_m (rows 5, 6 are zero).
-__device__ inline void cyl_jacobian(const double u[7], double J[7][7]) {
-    const double dx = u[0], dy = u[1], dz = u[2], w = u[3], x = u[4], y = u[5], z = u[6];
-    const double Ax = 2.0 * (x * z + w * y), Ay = 2.0 * (y * z - w * x), Az = w * w - x * x - y * y + z * z;
-    const double t = dx * Ax + dy * Ay;
+template <typename Real>
+__device__ inline void cyl_jacobian(const Real u[7], Real J[7][7]) {
+    const Real dx = u[0], dy = u[1], dz = u[2], w = u[3], x = u[4], y = u[5], z = u[6];
+    const Real Ax = 2 * (x * z + w * y), Ay = 2 * (y * z - w * x), Az = w * w - x * x - y * y + z * z;
+    const Real t = dx * Ax + dy * Ay;
     // d A / d (w, x, y, z)
-    const double dAx[4] = {2.0 * y, 2.0 * z, 2.0 * w, 2.0 * x};
-    const double dAy[4] = {-2.0 * x, -2.0 * w, 2.0 * z, 2.0 * y};
-    const double dAz[4] = {2.0 * w, -2.0 * x, -2.0 * y, 2.0 * z};
-    double dt[7];
+    const Real dAx[4] = {2 * y, 2 * z, 2 * w, 2 * x};
+    const Real dAy[4] = {-2 * x, -2 * w, 2 * z, 2 * y};
+    const Real dAz[4] = {2 * w, -2 * x, -2 * y, 2 * z};
+    Real dt[7];
     dt[0] = Ax;
     dt[1] = Ay;
-    dt[2] = 0.0;
+    dt[2] = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) dt[3 + k] = dx * dAx[k] + dy * dAy[k];
 #pragma unroll
     for (int r = 0; r < 7; ++r)
 #pragma unroll
-        for (int m = 0; m < 7; ++m) J[r][m] = 0.0;
-    J[0][0] = 2.0 * dx;
-    J[0][1] = 2.0 * dy;
-    J[1][2] = 2.0 * dz;
+        for (int m = 0; m < 7; ++m) J[r][m] = 0;
+    J[0][0] = 2 * dx;
+    J[0][1] = 2 * dy;
+    J[1][2] = 2 * dz;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) J[2][3 + k] = 2.0 * Az * dAz[k];
+    for (int k = 0; k < 4; ++k) J[2][3 + k] = 2 * Az * dAz[k];
 #pragma unroll
     for (int m = 0; m < 7; ++m) {
-        J[3][m] = 2.0 * t * dt[m];
+        J[3][m] = 2 * t * dt[m];
         J[4][m] = Az * dz * dt[m];
     }
     J[4][2] += t * Az;

@@ -20,30 +20,50 @@ __global__ void k_route_reset(int32_t *flags) {
     flags[RB_FLAG_NBEAD] = 0;
 }
 
-// Appends this lane's pair to one of two lists with one atomic per wave and
-// list (ballot + popcount of the lanes below).
-__device__ inline void wave_append(bool take, int value, int32_t *list, int32_t *counter) {
-    const unsigned long long m = __ballot(take);
-    if (m == 0) return;
-    const int lane = threadIdx.x & (kWave - 1);
-    int base = 0;
-    const int leader = __ffsll((long long)m) - 1;
-    if (lane == leader) base = atomicAdd(counter, __popcll(m));
-    base = __shfl(base, leader, kWave);
-    if (take) {
-        const unsigned long long below = m & ((1ull << lane) - 1ull);
-        list[base + __popcll(below)] = value;
+constexpr int kDescThreads = 1024;
+constexpr int kDescWaves = kDescThreads / kWave;
+
+// Appends the block's lanes with take0 / take1 to two lists with one atomic
+// per list and block (many waves adding to one counter serialise on it):
+// ballots give each wave's count and each lane's rank in its wave, the
+// wave counts are scanned in LDS, one thread per list reserves the block's
+// range.  Every thread of the block calls it.
+__device__ inline void block_append2(bool take0, bool take1, int value, int32_t *list0, int32_t *counter0,
+                                     int32_t *list1, int32_t *counter1) {
+    __shared__ int wcount[2][kDescWaves];
+    __shared__ int base[2];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+    const unsigned long long m0 = __ballot(take0), m1 = __ballot(take1);
+    if (lane == 0) {
+        wcount[0][w] = __popcll(m0);
+        wcount[1][w] = __popcll(m1);
     }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        int tot = 0;
+        for (int k = 0; k < kDescWaves; ++k) tot += wcount[threadIdx.x][k];
+        base[threadIdx.x] = tot ? atomicAdd(threadIdx.x ? counter1 : counter0, tot) : 0;
+    }
+    __syncthreads();
+    int off0 = base[0], off1 = base[1];
+    for (int k = 0; k < w; ++k) {
+        off0 += wcount[0][k];
+        off1 += wcount[1][k];
+    }
+    const unsigned long long below = (1ull << lane) - 1ull;
+    if (take0) list0[off0 + __popcll(m0 & below)] = value;
+    if (take1) list1[off1 + __popcll(m1 & below)] = value;
+    __syncthreads();   // wcount and base are reused by the next round
 }
 
-__global__ __launch_bounds__(256) void k_descriptors(int32_t n, const double *__restrict__ x,
+__global__ __launch_bounds__(kDescThreads) void k_descriptors(int32_t n, const double *__restrict__ x,
                                                      const double *__restrict__ q, double L0, double L1, double L2,
                                                      const int32_t *__restrict__ pi, const int32_t *__restrict__ pj,
                                                      int32_t maxp, float dmin2, float dmax2, float *__restrict__ desc,
                                                      int32_t *__restrict__ idx_nn, int32_t *__restrict__ idx_bead,
                                                      int32_t *__restrict__ flags, Templates T,
-                                                     const int32_t *__restrict__ type, double gap_min,
-                                                     double gap_max) {
+                                                     const int32_t *__restrict__ type, float gap_min,
+                                                     float gap_max) {
     // the first round's pair indices are requested together with the count
     // (any slot below the capacity may be read; only live ones are used)
     const int p0 = blockIdx.x * blockDim.x + threadIdx.x;
@@ -89,16 +109,15 @@ __global__ __launch_bounds__(256) void k_descriptors(int32_t n, const double *__
             if (type && in_range && !near) {
                 double Rr[9];
                 quat_to_rot<double>(rw, rx, ry, rz, Rr);
-                const double G = shell_gap(T, type[i], type[j], d, Rr);
-                near = G < gap_min;
-                far = G >= gap_max;
+                const int route = shell_route(T, type[i], type[j], d, Rr, gap_min, gap_max);
+                near = route == kRouteBead;
+                far = route == kRouteSkip;
             }
             to_nn = in_range && !near && !far;
             to_bead = in_range && near;
             if (!type) to_bead = near;    // no shells: every pair below d_min, as before
         }
-        wave_append(live && to_nn, p, idx_nn, flags + RB_FLAG_NNN);
-        wave_append(live && to_bead, p, idx_bead, flags + RB_FLAG_NBEAD);
+        block_append2(live && to_nn, live && to_bead, p, idx_nn, flags + RB_FLAG_NNN, idx_bead, flags + RB_FLAG_NBEAD);
     }
 }
 
@@ -122,10 +141,11 @@ extern "C" int rb_pair_descriptors(int32_t n, const double *x, const double *q, 
     const float dx2 = d_max > 0 ? d_max * d_max : 3.0e38f;
     Templates T = {};
     if (ctx) T = ctx->dev.t;
-    const double gmax = gap_max > 0.f ? (double)gap_max : 1e300;
-    k_descriptors<<<grid_for(max_pairs, 256, 4096), 256, 0, st>>>(n, x, q, box[0], box[1], box[2], pair_i, pair_j,
+    const float gmax = gap_max > 0.f ? gap_max : 3.0e38f;
+    k_descriptors<<<grid_for(max_pairs, kDescThreads, 4096), kDescThreads, 0, st>>>(n, x, q, box[0], box[1], box[2],
+                                                                                  pair_i, pair_j,
                                                                   max_pairs, dm2, dx2, desc, idx_nn, idx_bead, flags,
-                                                                  T, type, (double)gap_min, gmax);
+                                                                  T, type, gap_min, gmax);
     RB_LAUNCH_CHECK("rb_pair_descriptors");
     return RB_OK;
 }

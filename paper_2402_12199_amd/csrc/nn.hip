@@ -63,12 +63,10 @@ __device__ inline float centre_distance(const NNArgs &a, const float u[kIn]) {
 // The network's input of launch row `row` (pair pid).
 __device__ inline void net_input(const NNArgs &a, int64_t row, int64_t pid, bool live, float u[kIn]) {
     if (a.cyl && live) {
-        double ud[kIn], s[kIn];
+        float ud[kIn];
 #pragma unroll
         for (int k = 0; k < kIn; ++k) ud[k] = a.desc[k * a.stride + pid];
-        cyl_features(ud, s);
-#pragma unroll
-        for (int k = 0; k < kIn; ++k) u[k] = (float)s[k];
+        cyl_features(ud, u);
         return;
     }
 #pragma unroll
@@ -84,7 +82,7 @@ __device__ inline void sym_chain(const NNArgs &a, int64_t row, int64_t pid, floa
 #pragma unroll
     for (int r = 0; r < kIn; ++r) gs[r] = gu[r];
     if (a.cyl) {
-        double ud[kIn], J[kIn][kIn];
+        float ud[kIn], J[kIn][kIn];
 #pragma unroll
         for (int k = 0; k < kIn; ++k) ud[k] = a.desc[k * a.stride + pid];
         cyl_jacobian(ud, J);
@@ -92,7 +90,7 @@ __device__ inline void sym_chain(const NNArgs &a, int64_t row, int64_t pid, floa
         for (int m = 0; m < kIn; ++m) {
             float v = 0.f;
 #pragma unroll
-            for (int r = 0; r < kIn; ++r) v = fmaf((float)J[r][m], gs[r], v);
+            for (int r = 0; r < kIn; ++r) v = fmaf(J[r][m], gs[r], v);
             gu[m] = v;
         }
         return;

@@ -40,6 +40,10 @@ struct Templates {
     // segment from -cH to +cH on that axis
     int cax[kMaxTypes];
     float cR[kMaxTypes], cH[kMaxTypes];
+    // whether the capsule and cylinder bounds are worth forming for a type:
+    // the cylinder's cross-section pi cR^2 is smaller than the box's across
+    // the axis (true for cylinders, false for cubes)
+    int round[kMaxTypes];
     int n_types;
 };
 

@@ -211,4 +211,4 @@ def test_force_matching_step_batch_8192_matches_oracle(abi, prec):
     # tangent rows through the four-wave kernel's persistent loop and 64
     # weight-gradient chunks (biases from the first 32 only)
     from tests.test_gpu_train import fm_step_vs_oracle
-    fm_step_vs_oracle(abi, prec, 8192, 12000)
+    fm_step_vs_oracle(abi, prec, 8192, 12000, lam=30.0)

@@ -67,9 +67,10 @@ def test_gradient_and_adam_match_oracle(abi, prec, batch):
     np.testing.assert_allclose(m.cpu().numpy(), mref, rtol=1e-6, atol=1e-12)
 
 
-def fm_step_vs_oracle(abi, prec, batch, n_data, seed=5):
+def fm_step_vs_oracle(abi, prec, batch, n_data, seed=5, lam=3.0):
     """One force/torque-matching step on the GPU against the oracle's exact
-    loss and gradient (tangents forward, reverse through both chains)."""
+    loss and gradient (tangents forward, reverse through both chains); lam
+    weights both matching terms."""
     params, desc, labels, norm = _problem(n_data, seed)
     ft = (sampling.rng(21).normal(size=(len(labels), 6)) * 0.5).astype(np.float32)
     idx = sampling.rng(11).choice(len(labels), batch, replace=False).astype(np.int32)
@@ -81,10 +82,10 @@ def fm_step_vs_oracle(abi, prec, batch, n_data, seed=5):
     ws = torch.zeros(abi.rb_nn_train_fm_workspace_bytes(batch), dtype=torch.uint8, device=dev)
     abi.rb_nn_train_step_fm(p, m, v, 1, norm.as_array(), prec, batch, torch.tensor(np.ascontiguousarray(desc.T),
                             device=dev), torch.tensor(labels, device=dev), torch.tensor(np.ascontiguousarray(ft.T),
-                            device=dev), torch.tensor(idx, device=dev), 3.0, 3.0, 1e-3, 0.9, 0.999, 1e-8, loss,
+                            device=dev), torch.tensor(idx, device=dev), lam, lam, 1e-3, 0.9, 0.999, 1e-8, loss,
                             grad, ws)
     u, y, f = desc[idx].astype(np.float64), labels[idx].astype(np.float64), ft[idx].astype(np.float64)
-    el, fl, gref = omlp.fm_loss_and_grad(_net(params, prec), u, y, f, 3.0, 3.0, norm)
+    el, fl, gref = omlp.fm_loss_and_grad(_net(params, prec), u, y, f, lam, lam, norm)
     _, g_energy = omlp.loss_and_grad(_net(params, prec), u, y, norm)
     assert np.linalg.norm(gref - g_energy) > 0.2 * np.linalg.norm(g_energy)   # the matching term matters
     tol = 2e-2 if prec == 0 else 1e-4

@@ -95,6 +95,31 @@ struct alignas(16) LdsBF16 {
     float b5;
 };
 
+// Reverse-pass operand of W^T (the A fragment of v_mfma_f32_16x16x32_bf16 for
+// lane (n, g), n = lane % 16, g = lane / 16): slot i holds W[32 kb +
+// 16 (i / 4) + 4 g + (i % 4)][input feature 16 mt + n] of layer l's LDS image.
+// Read with two transposing LDS loads (ds_read_b64_tr_b16, gfx950): within
+// each 16-lane group, lane n receives as its value k element n % 4 of the
+// 8 bytes that lane 4 k + n / 4 of the group addresses.  Lane j therefore
+// addresses row 32 kb + 4 g + j / 4 (+ 16 for slots 4..7) at the column of
+// input features 16 mt + 4 (j % 4) .. + 3, which the staging's column
+// permutation keeps consecutive (columns 32 (mt / 2) + 8 (j % 4) +
+// 4 (mt % 2) .. + 3).  The values are those of eight 2-byte column reads.
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+
+__device__ inline bf16x8 wt_frag(const LdsBF16 &L, int l, int kb, int mt, int lane) {
+    const int j = lane & 15, g = lane >> 4;
+    const int row = 32 * kb + 4 * g + (j >> 2);
+    const int col = 32 * (mt >> 1) + 8 * (j & 3) + 4 * (mt & 1);
+    const s16x4 a = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(const_cast<__bf16 *>(&L.w[l][row][col])));
+    const s16x4 b =
+        __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(const_cast<__bf16 *>(&L.w[l][row + 16][col])));
+    typedef short s16x8 __attribute__((ext_vector_type(8)));
+    const s16x8 v = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+    return __builtin_bit_cast(bf16x8, v);
+}
+
 // NT = threads of the block.  The loops have compile-time trip counts so
 // that a batch of global loads is in flight before the first LDS store (a
 // block that evaluates a single tile spends most of its time here).

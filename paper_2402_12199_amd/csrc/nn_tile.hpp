@@ -141,9 +141,7 @@ __device__ inline float tile_bf16(const LdsBF16 &L, const Norm &nm, const float 
             f32x4 c = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kb = 0; kb < 4; ++kb) {
-                bf16x8 a;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) a[i] = L.w[l][32 * kb + 16 * (i >> 2) + 4 * g + (i & 3)][col];
+                const bf16x8 a = wt_frag(L, l, kb, mt, lane);
                 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, dpk[kb], c, 0, 0, 0);
                 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, dlk[kb], c, 0, 0, 0);
             }
@@ -319,9 +317,7 @@ __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &n
             f32x4 c = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kb = 0; kb < 4; ++kb) {
-                bf16x8 a;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) a[i] = L.w[l][32 * kb + 16 * (i >> 2) + 4 * g + (i & 3)][col];
+                const bf16x8 a = wt_frag(L, l, kb, mt, lane);
                 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, dpk[kb], c, 0, 0, 0);
                 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, dlk[kb], c, 0, 0, 0);
             }
@@ -709,9 +705,7 @@ __device__ inline void tile_bf16_wide_fm(const LdsBF16 &L, WideX &X, WideT &XT, 
             f32x4 c = f32x4{0.f, 0.f, 0.f, 0.f}, ct = c;
 #pragma unroll
             for (int kb = 0; kb < 4; ++kb) {
-                bf16x8 a;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) a[i] = L.w[l][32 * kb + 16 * (i >> 2) + 4 * g + (i & 3)][col];
+                const bf16x8 a = wt_frag(L, l, kb, mt, lane);
                 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, dpk[kb], c, 0, 0, 0);
                 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, dlk[kb], c, 0, 0, 0);
                 ct = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, tpk[kb], ct, 0, 0, 0);

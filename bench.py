@@ -1,27 +1,40 @@
 """Benchmark of the rigid-body pair path on one MI355X.
 
-Workload of the headline number: 4096 cube shells of 152 beads (6x6x6
-surface lattice) at volume fraction 0.20, kT = 1, NVE velocity Verlet at
-dt = 0.005, cell-list pair list with skin 1.0.  A step is one MD step of the
-plain bead path: half kick + drift + free rotation, conditional list
-rebuild, the FP32 bead double sum over every listed pair with per-body
-accumulation, the second half kick.  value = rigid-pair F+tau evaluations
-per second over the timed steps.
+Workload of the headline: 32768 cylinders (8 rings of 12 beads, radius 1.5,
+ring spacing 0.9, two end-cap discs of 19 beads: 134 beads) at volume
+fraction 0.15, Lennard-Jones beads (rc = 2.5), NVE velocity Verlet at
+kT = 1, dt = 0.005, cell-list pair list with skin 1.0.  A step is one MD
+step: half kick + drift + free rotation, conditional list rebuild, the pair
+forces and torques, the second half kick (the kinetic energy is reduced once
+per graph of 10 steps).  Two paths from the same start:
 
-Also reported (same run): a cube-6 surrogate trained on bead-labelled
-pairs (held-out errors), the network path on the same system with it (BF16
-MLP with bead fallback below d_min), the network kernels on 2^20 random
-cylinder pairs (forward, forward + input gradient; BF16 and FP32), the
-per-kernel roofline of the bead kernel, cylinder surrogates with the
-bead-vs-network dynamics of 32768 cylinders, the same comparison on cube
-shells with the paper's half-power half-cosine bead potential, and the FP64
-oracle on the host as a CPU baseline.  Inputs are synthetic and seeded.
+  bead    the FP32 bead double sum over the listed pairs (two-level list),
+  nn      the BF16 network surrogate on the cylinder four-number descriptor
+          for the pairs whose shells' bound on the closest bead distance lies
+          in [1.0, 2.5), the bead sum for the pairs below 1.0, nothing for
+          the pairs at or above 2.5 (no bead pair within the cutoff).
+
+The surrogate is trained here, on the GPU, by the library's own training
+step, on pairs visited by bead-path runs of the same system at
+kT = 1, 2, 4 (energy loss, Adam, batch 8192, cosine decay); its held-out
+errors are reported.  value = the network path's rigid-pair F+tau
+evaluations per second: pairs whose centre distance is below the interaction
+range 2 r_max + rc (the same count for both paths; measured at the start and
+end of the timed steps) x steps per second.
+
+Also reported: the bead path's rate and the ratio of the two, the roofline
+of the network path's dominant kernel (network forces, timed with HIP events
+on its stream), the other kernels of both paths, the network kernels on 2^20
+random pairs, the training step at batch 8192, the bead-vs-network dynamics
+over 2008 steps (energy drift, g(r), P2, MSD, MSR), and the FP64 oracle on
+the host as the CPU baseline.  Inputs are synthetic and seeded.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -37,118 +50,111 @@ FP32_VECTOR_PEAK = 78.6e12     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz,
 BF16_MFMA_PEAK = 2.5e15        # dense
 FP32_MFMA_PEAK = 157.3e12
 HBM_PEAK = 8.0e12
-FLOP_PER_TEST = 8              # 3 sub + 1 mul + 2 fma
+FLOP_PER_TEST = 8              # bead-bead distance test: 3 sub + 1 mul + 2 fma
+NN_FLOP_PER_ROW = 100352       # 2 x (7 x 128 + 3 x 128 x 128 + 128) multiply-adds
+GRAPH_STEPS = 10               # MD steps recorded per HIP graph
 
-# HBM bytes per launch of the bead kernel on this workload, from two rocprofv3
-# counter runs (FETCH_SIZE, WRITE_SIZE; profiles/k_bead_md_cubes4096_hbm_traffic.txt),
-# each scaled by what the counter reads for a copy kernel of known size.  Valid
-# only for the kernel sources they were taken on (hash below); otherwise null.
-BEAD_TRAFFIC_BYTES = 4.89e6
-BEAD_TRAFFIC_SOURCES = ("paper_2402_12199_amd/csrc/bead.hip", "paper_2402_12199_amd/csrc/rb_common.hpp")
-BEAD_TRAFFIC_HASH = "4365cb67d1289c21"
+# Gap window of the network path (shells' lower bound on the closest bead
+# distance, sigma units) and that of the pairs its training data is drawn from.
+GAP_MIN, GAP_MAX, SAMPLE_GAP_MIN = 1.0, 2.5, 0.8
+
+# HBM bytes per launch of the network-forces kernel on the headline workload,
+# from two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE), each scaled by
+# what the counter reads for a copy kernel of known size.  Valid only for the
+# kernel sources they were taken on (hash below); otherwise reported as null.
+NN_TRAFFIC_BYTES = None
+NN_TRAFFIC_SOURCES = ("paper_2402_12199_amd/csrc/nn.hip", "paper_2402_12199_amd/csrc/nn_tile.hpp",
+                      "paper_2402_12199_amd/csrc/nn_common.hpp", "paper_2402_12199_amd/csrc/cyl_form.hpp",
+                      "paper_2402_12199_amd/csrc/rb_common.hpp")
+NN_TRAFFIC_HASH = None
 
 
-def bead_traffic():
-    import hashlib
+def sources_hash(files):
     h = hashlib.sha256()
-    for f in BEAD_TRAFFIC_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return BEAD_TRAFFIC_BYTES if h.hexdigest()[:16] == BEAD_TRAFFIC_HASH else None
+    return h.hexdigest()[:16]
+
+
+def nn_traffic():
+    if NN_TRAFFIC_BYTES is None or sources_hash(NN_TRAFFIC_SOURCES) != NN_TRAFFIC_HASH:
+        return None
+    return NN_TRAFFIC_BYTES
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_system(cfg, st, torch):
+def make_system(cfg, st, path, model=None):
     from paper_2402_12199_amd.md import RigidSystem
     b = cfg.body
-    return RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"], cfg.box,
-                       cfg.r_list, cfg.skin, hphc=cfg.hphc, margin=cfg.bead_margin)
+    s = RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"], cfg.box,
+                    cfg.r_list, cfg.skin, hphc=cfg.hphc, margin=cfg.bead_margin if path == "bead" else None)
+    if model is not None:
+        s.set_nn(model)
+    return s
 
 
-GRAPH_STEPS = 10   # MD steps recorded per HIP graph
+def count_within(sysm, r, torch, abi):
+    """Listed pairs whose minimum-image centre distance is below r (counted
+    on the device from the list and the positions)."""
+    m = int(sysm.flags[abi.RB_FLAG_NPAIRS].item())
+    i = sysm.pair_i[:m].long()
+    j = sysm.pair_j[:m].long()
+    d = sysm.x[:, j] - sysm.x[:, i]
+    box = torch.as_tensor(np.broadcast_to(np.asarray(sysm.box, np.float64), (3,)).copy(), device=d.device)[:, None]
+    d = d - box * torch.round(d / box)
+    return int(((d * d).sum(0) < r * r).sum().item())
 
 
-def run_md(sysm, steps, warmup, dt, path, torch, abi):
-    """Warm up eagerly, record GRAPH_STEPS steps into a HIP graph, and time
-    `steps` steps as graph replays (steps is rounded up to a multiple of
-    GRAPH_STEPS).  Returns timing and device counters."""
+def run_md(sysm, steps, warmup, dt, path, d_cut, torch, abi):
+    """Warm up eagerly, record GRAPH_STEPS fused steps into a HIP graph (and
+    the remainder of `steps` into a second one), and time exactly `steps`
+    steps as graph replays between a synchronisation on each side."""
     for _ in range(warmup):
         sysm.step(dt, path)
     torch.cuda.synchronize()
     sysm.check_capacity()
-    # fused stepping: each step is pair list (skipped unless flagged), forces
-    # into the accumulator, and one integrator launch that ends this step and
-    # starts the next
     sysm.begin_fused(dt)
     g = sysm.capture(dt, path, GRAPH_STEPS, fused=True)
+    rem = steps % GRAPH_STEPS
+    g_rem = sysm.capture(dt, path, rem, fused=True) if rem else None
     g.replay()                      # one untimed replay
     torch.cuda.synchronize()
     f0 = sysm.check_capacity()
+    within0 = count_within(sysm, d_cut, torch, abi)
     st = torch.cuda.current_stream()
-    reps = (steps + GRAPH_STEPS - 1) // GRAPH_STEPS
     e_start = torch.cuda.Event(enable_timing=True)
     e_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e_start.record(st)
-    for _ in range(reps):
+    for _ in range(steps // GRAPH_STEPS):
         g.replay()
+    if g_rem is not None:
+        g_rem.replay()
     e_end.record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     f1 = sysm.check_capacity()
+    within1 = count_within(sysm, d_cut, torch, abi)
     gpu_ms = e_start.elapsed_time(e_end)
-    neval = (int(f1[abi.RB_FLAG_NEVAL]) - int(f0[abi.RB_FLAG_NEVAL])) % (1 << 32)
     sysm.end_fused(dt, path)
-    # eager steps, timed separately (host launch overhead included)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(GRAPH_STEPS * 5):
-        sysm.step(dt, path)
-    torch.cuda.synchronize()
-    eager_ms = 1e3 * (time.perf_counter() - t1) / (GRAPH_STEPS * 5)
-    return dict(wall_s=wall, steps=reps * GRAPH_STEPS, gpu_ms=gpu_ms, pairs_evaluated=neval,
+    sysm.check_capacity()
+    return dict(wall_s=wall, steps=steps, gpu_ms=gpu_ms, pairs_within=[within0, within1],
+                pairs_within_mean=0.5 * (within0 + within1),
+                listed_pairs_evaluated=(int(f1[abi.RB_FLAG_NEVAL]) - int(f0[abi.RB_FLAG_NEVAL])) % (1 << 32),
                 rebuilds=int(f1[abi.RB_FLAG_NREBUILDS] - f0[abi.RB_FLAG_NREBUILDS]),
-                n_pairs=int(f1[abi.RB_FLAG_NPAIRS]), n_nn=int(f1[abi.RB_FLAG_NNN]),
-                n_bead=int(f1[abi.RB_FLAG_NBEAD]), eager_ms_per_step=eager_ms)
-
-
-def ntests(flags_np, abi):
-    return int(flags_np[abi.RB_FLAG_NTESTS:abi.RB_FLAG_NTESTS + 2].view(np.int64)[0])
-
-
-def bead_kernel_time(sysm, reps, torch, abi):
-    """Mean duration of the bead-sum kernel alone on the current list (HIP
-    events on the launch stream around `reps` back-to-back launches), and the
-    bead-bead distance tests it performs per launch (after culling)."""
-    st = torch.cuda.current_stream()
-    abi.rb_accum_zero(sysm.n, sysm.acc)
-
-    def launch():
-        abi.rb_bead_pair_forces(sysm.ctx, sysm.x, sysm.q, sysm.types, sysm.box, sysm.pair_i, sysm.pair_j, None,
-                                sysm.flags[abi.RB_FLAG_NPAIRS:], sysm.max_pairs, sysm.acc, sysm.flags)
-    launch()
-    torch.cuda.synchronize()
-    t0 = ntests(sysm.flags_host(), abi)
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record(st)
-    for _ in range(reps):
-        launch()
-    b.record(st)
-    torch.cuda.synchronize()
-    tests = (ntests(sysm.flags_host(), abi) - t0) / reps
-    abi.rb_accum_zero(sysm.n, sysm.acc)
-    return a.elapsed_time(b) / reps, tests
+                n_listed=int(f1[abi.RB_FLAG_NPAIRS]), n_nn=int(f1[abi.RB_FLAG_NNN]), n_bead=int(f1[abi.RB_FLAG_NBEAD]))
 
 
 def time_launches(fn, reps, torch):
-    """Mean device duration of `fn` (one or more kernel launches on the
-    current stream): `reps` calls recorded once into a HIP graph, the graph
-    replayed between HIP events (so host launch overhead does not count)."""
+    """Mean device duration of `fn` (kernel launches on the current stream):
+    `reps` calls recorded once into a HIP graph, the graph replayed on the
+    current stream between HIP events recorded on that stream."""
     fn()
     torch.cuda.synchronize()
     side = torch.cuda.Stream()
@@ -172,89 +178,111 @@ def time_launches(fn, reps, torch):
 
 def roof(ms, work, peak, unit, bound, what):
     rate = work / (ms * 1e-3)
-    return {"ms": ms, "bound": bound, "achieved": rate / (1e9 if unit == "GB/s" else 1e12), "unit": unit,
-            "peak": peak / (1e9 if unit == "GB/s" else 1e12), "frac": rate / peak, "algorithmic_work": what}
+    scale = 1e9 if unit == "GB/s" else 1e12
+    return {"ms": ms, "bound": bound, "achieved": rate / scale, "unit": unit, "peak": peak / scale,
+            "frac": rate / peak, "algorithmic_work": what}
 
 
-def kernel_table(sysm, cfg, torch, abi):
-    """Roofline of the hot-path kernels other than the bead sum, each timed
-    alone on the cube system's current state (after the timed run)."""
-    from paper_2402_12199_amd.nn import Trainer, make_norm
-    from synth import sampling
-    n, out = sysm.n, {}
+def ntests(sysm, abi):
     f = sysm.flags_host()
-    npairs = int(f[abi.RB_FLAG_NPAIRS])
-    ms = time_launches(lambda: sysm.build_pairs(always=True), 10, torch)
+    return int(f[abi.RB_FLAG_NTESTS:abi.RB_FLAG_NTESTS + 2].view(np.int64)[0])
+
+
+def nn_forces_launch(sysm, abi):
+    m = sysm.nn
+    return lambda: abi.rb_nn_pair_forces_cyl(m.params, m.norm, m.precision, sysm.q, sysm.pair_i, sysm.pair_j,
+                                             sysm.desc, sysm.idx_nn, sysm.flags[abi.RB_FLAG_NNN:], sysm.max_pairs,
+                                             m.sw_lo, m.sw_hi, sysm.acc, sysm.flags)
+
+
+def nn_forces_roofline(sysm, torch, abi, reps=20):
+    """The network path's dominant kernel alone on the current routing: mean
+    duration over `reps` launches, FLOP per launch = 2 x 100352 per network
+    pair (forward and input-gradient pass)."""
+    launch = nn_forces_launch(sysm, abi)
+    ms = time_launches(launch, reps, torch)
+    abi.rb_accum_zero(sysm.n, sysm.acc)
+    nnn = int(sysm.flags_host()[abi.RB_FLAG_NNN])
+    flop = 2.0 * NN_FLOP_PER_ROW * nnn
+    r = roof(ms, flop, BF16_MFMA_PEAK, "TFLOP/s", "mfma",
+             f"2 x {NN_FLOP_PER_ROW} FLOP per network pair (forward + input-gradient pass) x {nnn} pairs "
+             f"per launch")
+    r["pairs_per_launch"] = nnn
+    return r
+
+
+def path_kernels(sysn, sysb, cfg, torch, abi):
+    """The per-step kernels of both paths, each timed alone on the current
+    state of its system (after the timed steps)."""
+    out = {}
+    n = sysn.n
+    npairs = int(sysn.flags_host()[abi.RB_FLAG_NPAIRS])
+    ms = time_launches(lambda: sysn.build_pairs(always=True), 10, torch)
     out["pair_list_rebuild"] = roof(ms, 32.0 * n + 8.0 * npairs, HBM_PEAK, "GB/s", "hbm",
                                     f"32 B per body + 8 B per listed pair ({n} bodies, {npairs} pairs)")
-    # the builder in its bandwidth regime: 2^22 point bodies at the same
-    # number density, uniform positions (multi-kernel path, list sorted by i)
-    from paper_2402_12199_amd.md import RigidSystem
-    nb = 1 << 22
-    boxb = float(sysm.box[0]) * (nb / n) ** (1.0 / 3.0)
-    gb = sampling.rng(31)
-    zero = np.zeros((nb, 3))
-    big = RigidSystem([np.zeros((1, 3))], [1.0], [[1.0, 1.0, 1.0]], np.zeros(nb, np.int32), gb.random((nb, 3)) * boxb,
-                      np.tile([1.0, 0, 0, 0], (nb, 1)), zero, zero, boxb, sysm.r_list, 0.0)
-    msb = time_launches(lambda: big.build_pairs(always=True), 5, torch)
-    npb = int(big.check_capacity()[abi.RB_FLAG_NPAIRS])
-    out["pair_list_rebuild_4M"] = roof(msb, 32.0 * nb + 8.0 * npb, HBM_PEAK, "GB/s", "hbm",
-                                       f"32 B per body + 8 B per listed pair ({nb} bodies at the cube system's "
-                                       f"number density, {npb} pairs)")
-    del big
-    torch.cuda.empty_cache()
-    ms = time_launches(lambda: abi.rb_accum_finalize(n, sysm.acc, sysm.force, sysm.torque, sysm.ev, sysm.flags), 20,
+    m = sysn.nn
+    ms = time_launches(lambda: sysn.route(m.d_min, m.sw_hi, m.gap_min, m.gap_max), 20, torch)
+    f = sysn.flags_host()
+    nnn, nbead = int(f[abi.RB_FLAG_NNN]), int(f[abi.RB_FLAG_NBEAD])
+    out["pair_descriptors_routing"] = roof(ms, 128.0 * npairs + 32.0 * (nnn + nbead), HBM_PEAK, "GB/s", "hbm",
+                                           f"128 B read per listed pair (FP64 state of both bodies, indices, "
+                                           f"types) + 32 B written per routed pair ({npairs} listed, {nnn} "
+                                           f"network, {nbead} bead)")
+    out["pair_descriptors_routing"]["note"] = "bound by the shells' arithmetic, not by HBM"
+    t0 = ntests(sysn, abi)
+    ms = time_launches(lambda: abi.rb_bead_pair_forces(sysn.ctx, sysn.x, sysn.q, sysn.types, sysn.box, sysn.pair_i,
+                                                       sysn.pair_j, sysn.idx_bead, sysn.flags[abi.RB_FLAG_NBEAD:],
+                                                       sysn.max_pairs, sysn.acc, sysn.flags), 10, torch)
+    tests = (ntests(sysn, abi) - t0) / 21            # one eager call + two replays of 10
+    abi.rb_accum_zero(n, sysn.acc)
+    out["bead_fallback"] = roof(ms, tests * FLOP_PER_TEST, FP32_VECTOR_PEAK, "TFLOP/s", "alu",
+                                f"{tests:.0f} bead-bead tests x {FLOP_PER_TEST} FLOP per launch ({nbead} pairs)")
+    t0 = ntests(sysb, abi)
+    ms = time_launches(sysb.bead_forces, 10, torch)
+    tests = (ntests(sysb, abi) - t0) / 21
+    abi.rb_accum_zero(sysb.n, sysb.acc)
+    out["bead_path_forces"] = roof(ms, tests * FLOP_PER_TEST, FP32_VECTOR_PEAK, "TFLOP/s", "alu",
+                                   f"{tests:.0f} bead-bead tests x {FLOP_PER_TEST} FLOP per launch (the tests "
+                                   f"left after culling; two-level list)")
+    ms = time_launches(lambda: abi.rb_accum_finalize(n, sysn.acc, sysn.force, sysn.torque, sysn.ev, sysn.flags), 20,
                        torch)
     out["accum_finalize"] = roof(ms, 120.0 * n, HBM_PEAK, "GB/s", "hbm",
                                  "120 B per body (6 int64 read and cleared, 6 FP32 written)")
-    st = {k: v.clone() for k, v in (("x", sysm.x), ("P", sysm.P), ("q", sysm.q), ("L", sysm.L))}
-    ms = time_launches(lambda: abi.rb_rigid_step_fused(sysm.ctx, cfg.dt, sysm.x, sysm.P, sysm.q, sysm.L, sysm.types,
-                                                       sysm.acc, sysm.force, sysm.torque, sysm.ev, sysm.x_ref,
-                                                       sysm.half_skin, None, sysm.flags, sysm.ws_rig), 20, torch)
-    for k, v in st.items():
-        getattr(sysm, k).copy_(v)
+    saved = {k: getattr(sysn, k).clone() for k in ("x", "P", "q", "L")}
+    ms = time_launches(lambda: abi.rb_rigid_step_fused(sysn.ctx, cfg.dt, sysn.x, sysn.P, sysn.q, sysn.L, sysn.types,
+                                                       sysn.acc, sysn.force, sysn.torque, sysn.ev, sysn.x_ref,
+                                                       sysn.half_skin, None, sysn.flags, sysn.ws_rig), 20, torch)
+    for k, v in saved.items():
+        getattr(sysn, k).copy_(v)
     out["rigid_step_fused"] = roof(ms, 248.0 * n, HBM_PEAK, "GB/s", "hbm",
                                    "248 B per body (FP64 state read and written, accumulator, forces)")
-    desc = sysm.pair_configurations(cfg.d_min, cfg.d_cut)      # allocates the routing buffers
-    ms = time_launches(lambda: abi.rb_pair_descriptors(sysm.x, sysm.q, sysm.box, sysm.pair_i, sysm.pair_j, cfg.d_min,
-                                                       sysm.desc, sysm.idx_nn, sysm.idx_bead, sysm.flags,
-                                                       d_max=cfg.d_cut), 20, torch)
-    out["pair_descriptors"] = roof(ms, 100.0 * npairs, HBM_PEAK, "GB/s", "hbm",
-                                   f"100 B per listed pair ({npairs}): two bodies' FP64 state, 7 FP32 out")
-    nnn = desc.shape[1]
-    params = torch.tensor(sampling.xavier_params(5).astype(np.float32), device="cuda")
-    norm = make_norm(cfg.d_cut)
-    ms = time_launches(lambda: abi.rb_nn_pair_forces(params, norm, abi.RB_PREC_BF16, sysm.q, sysm.pair_i, sysm.pair_j,
-                                                     sysm.desc, sysm.idx_nn, sysm.flags[abi.RB_FLAG_NNN:],
-                                                     sysm.max_pairs, cfg.d_cut - 1.0, cfg.d_cut, sysm.acc,
-                                                     sysm.flags), 20, torch)
-    abi.rb_accum_zero(n, sysm.acc)
-    out["nn_pair_forces_md"] = roof(ms, 2 * 100352.0 * nnn, BF16_MFMA_PEAK, "TFLOP/s", "mfma",
-                                    f"2 x 100352 FLOP per network pair ({nnn} pairs of the list)")
-    tr = Trainer(sampling.xavier_params(6), norm, batch=8192)
-    g = sampling.rng(9)
-    dd = torch.tensor(np.ascontiguousarray(sampling.pair_batch(g, 1 << 16, cfg.d_min, cfg.d_cut)
-                                           .astype(np.float32).T), device="cuda")
-    yy = torch.tensor(g.standard_normal(1 << 16).astype(np.float32), device="cuda")
-    idx = torch.arange(8192, dtype=torch.int32, device="cuda")
-    ms = time_launches(lambda: tr.step(dd, yy, idx), 20, torch)
-    out["nn_train_step_8192"] = roof(ms, 3.0e5 * 8192, BF16_MFMA_PEAK, "TFLOP/s", "mfma",
-                                     "3.0e5 FLOP per sample (forward, input-to-weight reverse pass, weight "
-                                     "gradients), batch 8192")
-    lab = torch.empty((11, 1 << 16), dtype=torch.float32, device="cuda")
-    t0 = ntests(sysm.flags_host(), abi)
-    ms = time_launches(lambda: abi.rb_bead_pair_eval(sysm.ctx, dd, 0, 0, lab, sysm.flags), 5, torch)
-    tests = (ntests(sysm.flags_host(), abi) - t0) / 11          # 1 eager call + 2 replays of 5
-    out["bead_pair_eval_labels"] = roof(ms, tests * FLOP_PER_TEST, FP32_VECTOR_PEAK, "TFLOP/s", "alu",
-                                        f"{tests:.0f} culled bead tests x {FLOP_PER_TEST} FLOP per launch "
-                                        f"(2^16 cube-6 configurations)")
     return out
 
 
+def builder_4m(box_per_body, r_list, torch, abi):
+    """The pair builder in its bandwidth regime: 2^22 point bodies at the
+    headline system's number density, uniform positions."""
+    from paper_2402_12199_amd.md import RigidSystem
+    from synth import sampling
+    nb = 1 << 22
+    boxb = box_per_body * nb ** (1.0 / 3.0)
+    zero = np.zeros((nb, 3))
+    big = RigidSystem([np.zeros((1, 3))], [1.0], [[1.0, 1.0, 1.0]], np.zeros(nb, np.int32),
+                      sampling.rng(31).random((nb, 3)) * boxb, np.tile([1.0, 0, 0, 0], (nb, 1)), zero, zero, boxb,
+                      r_list, 0.0)
+    ms = time_launches(lambda: big.build_pairs(always=True), 5, torch)
+    npb = int(big.check_capacity()[abi.RB_FLAG_NPAIRS])
+    del big
+    torch.cuda.empty_cache()
+    return roof(ms, 32.0 * nb + 8.0 * npb, HBM_PEAK, "GB/s", "hbm",
+                f"32 B per body + 8 B per listed pair ({nb} bodies, {npb} pairs)")
+
+
 def nn_kernels(torch, abi):
-    """Network kernels on 2^20 random cylinder pair configurations."""
-    from synth import configs, sampling
+    """Network kernels on 2^20 random cylinder pair configurations (forward,
+    forward + input gradient; BF16 and FP32)."""
     from paper_2402_12199_amd.nn import make_norm
+    from synth import configs, sampling
     cfg = configs.config3()
     desc = sampling.pair_batch(sampling.rng(cfg.seed), cfg.n_pairs, cfg.d_lo, cfg.d_cut).astype(np.float32)
     d = torch.tensor(np.ascontiguousarray(desc.T), device="cuda")
@@ -263,7 +291,6 @@ def nn_kernels(torch, abi):
     P = cfg.n_pairs
     E = torch.empty(P, dtype=torch.float32, device="cuda")
     ft = torch.empty((9, P), dtype=torch.float32, device="cuda")
-    st = torch.cuda.current_stream()
     out = {}
     for prec, name in ((abi.RB_PREC_BF16, "bf16"), (abi.RB_PREC_FP32, "fp32")):
         for kind in ("fwd", "fwd_grad"):
@@ -272,112 +299,59 @@ def nn_kernels(torch, abi):
                     abi.rb_nn_pair_eval(params, norm, prec, d, E)
                 else:
                     abi.rb_nn_pair_grad(params, norm, prec, d, None, E, None, ft)
-            for _ in range(3):
-                call()
-            reps = 10
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record(st)
-            for _ in range(reps):
-                call()
-            b.record(st)
-            torch.cuda.synchronize()
-            ms = a.elapsed_time(b) / reps
-            flop = (100352 if kind == "fwd" else 2 * 100352) * P
+            ms = time_launches(call, 5, torch)
+            flop = (1 if kind == "fwd" else 2) * NN_FLOP_PER_ROW * P
             peak = BF16_MFMA_PEAK if prec == abi.RB_PREC_BF16 else FP32_MFMA_PEAK
             out[f"{name}_{kind}"] = dict(ms=ms, pairs_per_s=P / (ms * 1e-3), tflops=flop / (ms * 1e-3) / 1e12,
                                          mfma_frac=flop / (ms * 1e-3) / peak)
     return out
 
 
-def learned_part(args, torch, abi, log):
-    """Cylinder surrogate trained on uniformly drawn pair configurations
-    labelled by the bead kernel (2^21, held out 2^16 from another seed), then
-    2008 NVE steps of 32768 cylinders with the bead path and with the
-    network path (bead fallback below d_min) from the same start."""
-    from paper_2402_12199_amd.compare import compare
-    from paper_2402_12199_amd.md import NNModel
-    from paper_2402_12199_amd.surrogate import train_surrogate, train_surrogate_md
-    from synth import configs, state
-    c5 = configs.config5()
-    log(f"[bench] cylinder surrogate: 2^21 uniform pairs, {args.cyl_epochs} epochs")
-    cyl = train_surrogate(c5.body, 1 << 21, 1 << 16, args.cyl_epochs, log=log)
-    out = {"surrogate": {k: cyl[k] for k in ("shape", "sampling", "epochs", "steps", "batch", "n_train", "n_test",
-                                             "reject_rate", "label_s", "train_s", "samples_per_s", "d_min",
-                                             "d_cut")},
-           "held_out": cyl["trained"], "held_out_untrained": cyl["untrained"],
-           "label_pairs_per_s_with_host_copies": cyl["label_kernel_pairs_per_s"]}
-    log(f"[bench] generating {c5.name}")
-    st5 = state.initial_state(c5)
-    # a second surrogate trained on the pairs the bead dynamics of this
-    # workload visits (the paper's data source), held out from later steps
-    log(f"[bench] cylinder surrogate on bead-MD pairs of {c5.name}")
-    cmd = train_surrogate_md(c5, st5, 1 << 21, 1 << 16, args.cyl_epochs, log=log)
-    out["surrogate_md"] = {k: cmd[k] for k in ("sampling", "epochs", "n_train", "n_test", "train_s")}
-    out["held_out_md"] = cmd["trained"]
-
-    def model(r):
-        return NNModel(params=r["params"], norm=r["norm"], precision=abi.RB_PREC_BF16, d_min=c5.d_min,
-                       sw_lo=c5.d_cut - 1.0, sw_hi=c5.d_cut)
-    out["dynamics"] = compare(c5, st5, {"nn_uniform": model(cyl), "nn_md": model(cmd)}, chunks=8, replays=25,
-                              log=log)
-    out["workload"] = f"{c5.name}: {c5.n_bodies} cylinders ({c5.body.n} beads), NVE kT={c5.kT} dt={c5.dt}"
-    return out
-
-
-def hphc_part(args, torch, abi, log):
-    """The paper's half-power half-cosine bead potential on 4096 cube shells
-    (volume fraction 0.16, NVE kT=1): a surrogate trained on the pairs the
-    bead dynamics visits, then 2008 steps of the bead path and of the network
-    path from the same start, compared through g(r), P2, MSD, MSR and energy;
-    the same again at constant temperature (Nose-Hoover)."""
-    from paper_2402_12199_amd.compare import compare
-    from paper_2402_12199_amd.md import NNModel
-    from paper_2402_12199_amd.surrogate import train_surrogate_md
-    from synth import configs, state
-    cfg = configs.config_hphc()
-    log(f"[bench] generating {cfg.name}")
-    st = state.initial_state(cfg)
-    log(f"[bench] {cfg.body.name} half-power half-cosine surrogate on bead-MD pairs, {args.hphc_epochs} epochs")
-    sur = train_surrogate_md(cfg, st, 1 << 20, 1 << 16, args.hphc_epochs, r_rej=0.0, log=log)
-    model = NNModel(params=sur["params"], norm=sur["norm"], precision=abi.RB_PREC_BF16, d_min=cfg.d_min,
-                    sw_lo=cfg.d_cut - 1.0, sw_hi=cfg.d_cut)
-    # the same data with force and torque matching (weights 10 / mean squared label)
-    log(f"[bench] {cfg.body.name} surrogate with force and torque matching, {args.hphc_epochs} epochs")
-    fm = dict(weight=10.0)
-    surf = train_surrogate_md(cfg, st, 1 << 20, 1 << 16, args.hphc_epochs, r_rej=0.0, log=log, fm=fm)
-    model_fm = NNModel(params=surf["params"], norm=surf["norm"], precision=abi.RB_PREC_BF16, d_min=cfg.d_min,
-                       sw_lo=cfg.d_cut - 1.0, sw_hi=cfg.d_cut)
-    out = {"workload": f"{cfg.name}: {cfg.n_bodies} cube shells ({cfg.body.n} beads), half-power half-cosine "
-                       f"A={cfg.hphc['A']} b={cfg.hphc['b']} c={cfg.hphc['c']} p={cfg.hphc['p']}, "
-                       f"NVE kT={cfg.kT} dt={cfg.dt}",
-           "surrogate": {k: sur[k] for k in ("sampling", "epochs", "n_train", "n_test", "train_s", "samples_per_s")},
-           "held_out": sur["trained"], "held_out_untrained": sur["untrained"],
-           "force_matching": {"weights": fm, "lam_f": surf["fm"]["lam_f"], "lam_t": surf["fm"]["lam_t"],
-                              "train_s": surf["train_s"], "samples_per_s": surf["samples_per_s"],
-                              "held_out": surf["trained"]}}
-    # the paper's symmetry-reduced cube-pair descriptor (supplementary section 1)
-    log(f"[bench] {cfg.body.name} surrogate on the symmetry-reduced descriptor, {args.hphc_epochs} epochs")
-    surs = train_surrogate_md(cfg, st, 1 << 20, 1 << 16, args.hphc_epochs, r_rej=0.0, log=log, sym=True)
-    model_sym = NNModel(params=surs["params"], norm=surs["norm"], precision=abi.RB_PREC_BF16, d_min=cfg.d_min,
-                        sw_lo=cfg.d_cut - 1.0, sw_hi=cfg.d_cut, sym=True)
-    out["symmetry_reduced"] = {"descriptor": "(p_x, p_y, p_z, w_y, w_z, cos 4 a3, sin 4 a3)", "train_s": surs["train_s"],
-                               "held_out": surs["trained"]}
-    models = {"nn_md": model, "nn_md_fm": model_fm, "nn_md_sym": model_sym}
-    out["dynamics"] = compare(cfg, st, models, chunks=8, replays=25, log=log)
-    # the paper's ensemble: Nose-Hoover NVT at the same temperature
-    nvt = dict(kT=cfg.kT, tau=0.5)
-    out["dynamics_nvt"] = compare(cfg, st, models, chunks=8, replays=25, log=log, nvt=nvt)
-    out["dynamics_nvt"]["thermostat"] = dict(nvt, scheme="Nose-Hoover, one thermostat on all momenta, "
-                                                       "g = 6 n - 3, Q = g kT tau^2")
+def train_kernels(body, d_min, d_cut, torch, abi):
+    """One training step at batch 8192 (energy loss; energy + force/torque
+    matching), and the bead labelling of 2^16 cylinder pairs."""
+    from paper_2402_12199_amd.nn import Trainer, make_norm
+    from synth import sampling
+    g = sampling.rng(9)
+    n = 1 << 16
+    desc = sampling.pair_batch(g, n, d_min, d_cut).astype(np.float32)
+    dd = torch.tensor(np.ascontiguousarray(desc.T), device="cuda")
+    yy = torch.tensor(g.standard_normal(n).astype(np.float32), device="cuda")
+    ft = torch.tensor(g.standard_normal((6, n)).astype(np.float32), device="cuda")
+    idx = torch.arange(8192, dtype=torch.int32, device="cuda")
+    norm = make_norm(d_cut)
+    out = {}
+    tr = Trainer(sampling.xavier_params(6), norm, batch=8192)
+    ms = time_launches(lambda: tr.step(dd, yy, idx), 20, torch)
+    out["train_step_8192"] = roof(ms, 3.0 * NN_FLOP_PER_ROW * 8192, BF16_MFMA_PEAK, "TFLOP/s", "mfma",
+                                  "3 x 100352 FLOP per sample (forward, reverse pass, weight gradients), "
+                                  "batch 8192")
+    trf = Trainer(sampling.xavier_params(6), norm, batch=8192, fm=dict(lam_f=1e-3, lam_t=1e-3))
+    ms = time_launches(lambda: trf.step(dd, yy, idx, ft=ft), 20, torch)
+    out["train_step_fm_8192"] = roof(ms, 9.0 * NN_FLOP_PER_ROW * 8192, BF16_MFMA_PEAK, "TFLOP/s", "mfma",
+                                     "9 x 100352 FLOP per sample (forward and tangent rows, their reverse "
+                                     "passes, weight gradients over both), batch 8192")
+    ctx = abi.Ctx([body.beads], [body.mass], [body.inertia])
+    flags = torch.zeros(abi.RB_NFLAGS, dtype=torch.int32, device="cuda")
+    lab = torch.empty((11, n), dtype=torch.float32, device="cuda")
+    ms = time_launches(lambda: abi.rb_bead_pair_eval(ctx, dd, 0, 0, lab, flags), 5, torch)
+    f = flags.cpu().numpy()
+    tests = int(f[abi.RB_FLAG_NTESTS:abi.RB_FLAG_NTESTS + 2].view(np.int64)[0]) / 11
+    out["bead_labels_2^16"] = roof(ms, tests * FLOP_PER_TEST, FP32_VECTOR_PEAK, "TFLOP/s", "alu",
+                                   f"{tests:.0f} culled bead tests x {FLOP_PER_TEST} FLOP per launch "
+                                   f"(2^16 uniformly drawn cylinder pairs)")
+    out["bead_labels_2^16"]["pairs_per_s"] = n / (ms * 1e-3)
     return out
 
 
 def cpu_baseline(cfg, st, target_s=12.0):
-    """The FP64 oracle (plain C, OpenMP over pairs) doing the same MD steps on
-    the host: full force evaluation + integration per step."""
+    """The FP64 oracle on the host: NVE steps of the headline system (full
+    force evaluation + integration per step), the oracle network's forward
+    and input gradient on 2^16 rows, the oracle bead sum on 2^14 cylinder
+    pairs."""
     from oracle import beads as ob
-    n = cfg.n_bodies
+    from oracle import mlp as om
+    from synth import sampling
     x = np.ascontiguousarray(st["x"].copy())
     P = np.ascontiguousarray(st["P"].copy())
     q = np.ascontiguousarray(st["q"].copy())
@@ -385,177 +359,241 @@ def cpu_baseline(cfg, st, target_s=12.0):
     b = cfg.body
     t0 = time.perf_counter()
     r = ob.bead_system(x, q, st["types"], [b.beads], cfg.box)
-    t1 = time.perf_counter()
-    per_eval = t1 - t0
-    steps = max(1, int(target_s / max(per_eval, 1e-3)))
+    per_eval = time.perf_counter() - t0
+    steps = max(1, int(target_s / max(per_eval, 1e-3)) - 1)
     t0 = time.perf_counter()
     ob.nve(x, P, q, L, st["types"], [b.beads], [b.mass], [b.inertia], cfg.box, steps, cfg.dt)
     wall = time.perf_counter() - t0
-    pairs = r["n_pairs"] * (steps + 1)
-    return dict(value=pairs / wall, unit="rigid-pair F+tau evals/s", cores=ob.num_threads(), kind="oracle",
-                sample=f"{steps} NVE steps (+1 initial force evaluation) of the same 4096-cube system, "
-                       f"{r['n_pairs']} pairs per evaluation, FP64 C oracle, wall {wall:.1f} s",
-                md_steps_per_s=(steps + 1) / wall)
+    evals = steps + 1
+    out = dict(value=r["n_pairs"] * evals / wall, unit="rigid-pair F+tau evals/s", cores=ob.num_threads(),
+               kind="oracle",
+               sample=f"{steps} NVE steps (+1 initial force evaluation) of the same {cfg.n_bodies}-cylinder system "
+                      f"from the same start, {r['n_pairs']} pairs within 2 r_max + rc per evaluation, FP64 C "
+                      f"oracle (all-pairs search, OpenMP over pairs), wall {wall:.1f} s",
+               md_steps_per_s=evals / wall)
+    params = sampling.xavier_params(5)
+    d = sampling.pair_batch(sampling.rng(3), 1 << 16, cfg.d_min, cfg.d_cut)
+    norm = om.Norm(in_scale=np.array([1 / cfg.d_cut] * 3 + [1.0] * 4))
+    t0 = time.perf_counter()
+    om.input_grad(params, d, norm)
+    t_mlp = time.perf_counter() - t0
+    out["mlp_fwd_grad"] = dict(rows=1 << 16, s=t_mlp, pairs_per_s=(1 << 16) / t_mlp,
+                               kind="oracle (numpy FP64 forward + input gradient)")
+    t0 = time.perf_counter()
+    ob.bead_pair_desc(b.beads, b.beads, d[:1 << 14])
+    t_bead = time.perf_counter() - t0
+    out["bead_pairs"] = dict(pairs=1 << 14, s=t_bead, pairs_per_s=(1 << 14) / t_bead,
+                             kind="oracle (C FP64 bead double sum, uniformly drawn cylinder pairs)")
+    return out
+
+
+def kernels_only(args, torch, abi):
+    """The dominant kernels of both paths on the headline system at its start
+    (network with Xavier weights: routing and cost do not depend on the
+    weights), for counter runs."""
+    from paper_2402_12199_amd.md import NNModel
+    from paper_2402_12199_amd.nn import make_norm_features, sym_descriptors
+    from synth import configs, sampling, state
+    c5 = configs.config5()
+    st = state.initial_state(c5)
+    sysb = make_system(c5, st, "bead")
+    sysb.init_forces("bead")
+    sysn = make_system(c5, st, "nn")
+    desc = sysn.pair_configurations(c5.d_min, c5.d_cut, GAP_MIN, GAP_MAX)
+    s = sym_descriptors(desc.contiguous(), with_jac=False, form="cyl")[0].cpu().numpy().T
+    model = NNModel(params=torch.tensor(sampling.xavier_params(7).astype(np.float32), device="cuda"),
+                    norm=make_norm_features(s), d_min=c5.d_min, sw_lo=c5.d_cut - 1.0, sw_hi=c5.d_cut, form="cyl",
+                    gap_min=GAP_MIN, gap_max=GAP_MAX)
+    sysn.set_nn(model)
+    sysn.init_forces("nn")
+    torch.cuda.synchronize()
+    r = {"nn_forces": nn_forces_roofline(sysn, torch, abi, reps=args.steps)}
+    ms = time_launches(sysb.bead_forces, args.steps, torch)
+    r["bead_path_forces_ms"] = ms
+    print(json.dumps(r), flush=True)
+
+
+def cubes_part(args, torch, abi):
+    """The bead path on 4096 cube shells (152 beads, volume fraction 0.20)."""
+    from synth import configs, state
+    cfg = configs.config2()
+    st = state.initial_state(cfg)
+    sysm = make_system(cfg, st, "bead")
+    sysm.init_forces("bead")
+    r = run_md(sysm, args.steps, args.warmup, cfg.dt, "bead", cfg.d_cut, torch, abi)
+    return {"workload": f"{cfg.name}: {cfg.n_bodies} cube shells ({cfg.body.n} beads), LJ, NVE kT={cfg.kT} "
+                        f"dt={cfg.dt}, bead path",
+            "pair_evals_per_s": r["pairs_within_mean"] * r["steps"] / r["wall_s"],
+            "md_steps_per_s": r["steps"] / r["wall_s"], "pairs_within": r["pairs_within"],
+            "listed_pairs": r["n_listed"]}
+
+
+def hphc_part(args, torch, abi):
+    """The paper's half-power half-cosine bead potential on 4096 cube shells
+    (volume fraction 0.16, kT=1): surrogates trained on the pairs the bead
+    dynamics visits (energy; energy with force and torque matching; the
+    symmetry-reduced cube-pair descriptor), then 2008 steps of the bead path
+    and of each network path from the same start, at constant energy and at
+    constant temperature (Nose-Hoover)."""
+    from paper_2402_12199_amd.compare import compare
+    from paper_2402_12199_amd.md import NNModel
+    from paper_2402_12199_amd.surrogate import train_surrogate_md
+    from synth import configs, state
+    cfg = configs.config_hphc()
+    st = state.initial_state(cfg)
+    kw = dict(precision=abi.RB_PREC_BF16, d_min=cfg.d_min, sw_lo=cfg.d_cut - 1.0, sw_hi=cfg.d_cut)
+    ep = args.hphc_epochs
+    sur = train_surrogate_md(cfg, st, 1 << 20, 1 << 16, ep, r_rej=0.0, log=log)
+    fm = dict(weight=10.0)
+    surf = train_surrogate_md(cfg, st, 1 << 20, 1 << 16, ep, r_rej=0.0, log=log, fm=fm)
+    surs = train_surrogate_md(cfg, st, 1 << 20, 1 << 16, ep, r_rej=0.0, log=log, sym=True)
+    models = {"nn_md": NNModel(params=sur["params"], norm=sur["norm"], **kw),
+              "nn_md_fm": NNModel(params=surf["params"], norm=surf["norm"], **kw),
+              "nn_md_sym": NNModel(params=surs["params"], norm=surs["norm"], sym=True, **kw)}
+    out = {"workload": f"{cfg.name}: {cfg.n_bodies} cube shells ({cfg.body.n} beads), half-power half-cosine "
+                       f"A={cfg.hphc['A']} b={cfg.hphc['b']} c={cfg.hphc['c']} p={cfg.hphc['p']}, "
+                       f"kT={cfg.kT} dt={cfg.dt}",
+           "held_out": {"energy": sur["trained"], "force_matching": surf["trained"], "symmetry_reduced":
+                        surs["trained"]}}
+    out["dynamics"] = compare(cfg, st, models, chunks=8, replays=25, log=log)
+    out["dynamics_nvt"] = compare(cfg, st, models, chunks=8, replays=25, log=log, nvt=dict(kT=cfg.kT, tau=0.5))
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=600, help="surrogate training epochs (2^21 pairs each)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-nn", action="store_true", help="skip the network measurements")
-    ap.add_argument("--no-learned", action="store_true",
-                    help="skip the cylinder and half-power half-cosine surrogates and their network-vs-bead "
-                         "dynamics")
-    ap.add_argument("--cyl-epochs", type=int, default=100, help="cylinder surrogate epochs (2^21 pairs each)")
-    ap.add_argument("--hphc-epochs", type=int, default=300,
-                    help="half-power half-cosine cube surrogate epochs (2^20 pairs each)")
-    ap.add_argument("--nn-steps", type=int, default=100,
-                    help="timed steps of the network path (its trajectory stays sound for a limited time)")
-    ap.add_argument("--nn-epochs", type=int, default=100, help="surrogate training epochs (2^20 pairs each)")
+    ap.add_argument("--no-dynamics", action="store_true", help="skip the 2008-step bead-vs-network comparison")
+    ap.add_argument("--no-kernels", action="store_true", help="skip the per-kernel table")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only launch the dominant kernels of both paths on the headline system (counter runs)")
+    ap.add_argument("--extras", action="store_true",
+                    help="also the bead path on 4096 cubes and the half-power half-cosine cube surrogates")
+    ap.add_argument("--hphc-epochs", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (the path is single-GPU; --gpus {args.gpus} is not supported)",
+        print(f"bench.py measures one GPU: the path is single-GPU (--gpus {args.gpus} is not supported)",
               file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        print("--steps must be at least 1 and --warmup at least 0", file=sys.stderr)
         sys.exit(2)
 
     import torch
     from paper_2402_12199_amd import abi
     from paper_2402_12199_amd.md import NNModel
-    from synth import configs, sampling, state
+    from paper_2402_12199_amd.surrogate import train_surrogate_md
+    from synth import configs, state
 
-    cfg = configs.config2()
-    log(f"[bench] generating {cfg.name}")
-    st = state.initial_state(cfg)
-    sysm = make_system(cfg, st, torch)
-    sysm.init_forces("bead")
-    # one eager step first: its integrator pass yields the kinetic energy, so
-    # the total energy is known at the start of the measured trajectory
-    sysm.step(cfg.dt, "bead")
-    e_start = sysm.energy() + float(sysm.kinetic_host().sum())
-    torch.cuda.synchronize()
-    log(f"[bench] bead path: {args.warmup} warmup + {args.steps} timed steps")
-    bead = run_md(sysm, args.steps, args.warmup, cfg.dt, "bead", torch, abi)
-    kin = sysm.kinetic_host()
-    e_tot = sysm.energy() + float(kin.sum())
-    kern_ms, tests_done = bead_kernel_time(sysm, 20, torch, abi)
-    npairs_now = int(sysm.flags_host()[abi.RB_FLAG_NPAIRS])
-    tests_brute = npairs_now * cfg.body.n * cfg.body.n
-    achieved = tests_done * FLOP_PER_TEST / (kern_ms * 1e-3)
-    nsteps = bead["steps"]
-    steps_per_s = nsteps / bead["wall_s"]
-    value = bead["pairs_evaluated"] / bead["wall_s"]
+    if args.kernels_only:
+        kernels_only(args, torch, abi)
+        return
 
+    c5 = configs.config5()
+    log(f"[bench] generating {c5.name}")
+    st = state.initial_state(c5)
+
+    log(f"[bench] surrogate: bead-MD pairs of {c5.name} at kT = 1, 2, 4, {args.epochs} epochs")
+    t0 = time.perf_counter()
+    sur = train_surrogate_md(c5, st, 1 << 21, 1 << 16, args.epochs, every=25, gap_min=SAMPLE_GAP_MIN,
+                             gap_max=GAP_MAX, form="cyl", kTs=[1.0, 2.0, 4.0], lr_end=1e-5, log=log)
+    t_sur = time.perf_counter() - t0
+    model = NNModel(params=sur["params"], norm=sur["norm"], precision=abi.RB_PREC_BF16, d_min=c5.d_min,
+                    sw_lo=c5.d_cut - 1.0, sw_hi=c5.d_cut, form="cyl", gap_min=GAP_MIN, gap_max=GAP_MAX)
+    surrogate = {k: sur[k] for k in ("sampling", "epochs", "steps", "batch", "n_train", "n_test", "label_s",
+                                     "train_s", "samples_per_s")}
+    surrogate.update(form="cylinder four-number descriptor", total_s=t_sur, held_out=sur["trained"],
+                     held_out_untrained=sur["untrained"], loss_first_last=[sur["loss_history"][0],
+                                                                           sur["loss_history"][-1]])
+
+    legs = {}
+    systems = {}
+    for path in ("bead", "nn"):
+        sysm = make_system(c5, st, path, model if path == "nn" else None)
+        sysm.init_forces(path)
+        torch.cuda.synchronize()
+        ke0 = float((st["P"] ** 2).sum() / (2 * c5.body.mass) + (st["L"] ** 2 / (2 * c5.body.inertia)).sum())
+        e0 = sysm.energy() + ke0
+        log(f"[bench] {path} path: {args.warmup} warmup + {args.steps} timed steps")
+        r = run_md(sysm, args.steps, args.warmup, c5.dt, path, c5.d_cut, torch, abi)
+        e1 = sysm.energy() + float(sysm.kinetic_host().sum())
+        r.update(md_steps_per_s=r["steps"] / r["wall_s"], ms_per_step=1e3 * r["wall_s"] / r["steps"],
+                 gpu_ms_per_step=r["gpu_ms"] / r["steps"],
+                 pair_evals_per_s=r["pairs_within_mean"] * r["steps"] / r["wall_s"],
+                 total_energy_start_end=[e0, e1],
+                 energy_change_per_body=(e1 - e0) / c5.n_bodies,
+                 steps_in_energy_change=1 + args.warmup + GRAPH_STEPS + args.steps)
+        legs[path] = r
+        systems[path] = sysm
+    nn, bead = legs["nn"], legs["bead"]
+    nn["pairs_skipped_by_bound"] = nn["n_listed"] - nn["n_nn"] - nn["n_bead"]
+
+    log("[bench] dominant kernel of the network path")
+    rl = nn_forces_roofline(systems["nn"], torch, abi)
+    roofline = {"kernel": "k_nn_wide (rb_nn_pair_forces_cyl)", "bound": "mfma", "achieved": rl["achieved"],
+                "peak": rl["peak"], "unit": "TFLOP/s", "frac": rl["frac"], "traffic": nn_traffic(),
+                "traffic_unit": "bytes per launch", "kernel_ms": rl["ms"], "algorithmic_work": rl["algorithmic_work"]}
+
+    value = nn["pair_evals_per_s"]
     result = {
-        "metric": "rigid-pair F+tau evals/sec (bead sum FP32, MD step on 4096 cubes); MD steps/sec; "
-                  "NN(BF16) vs bead-sum(FP32), 1 GPU",
+        "metric": "rigid-pair F+tau evals/sec and MD steps/sec, NN(BF16) vs bead-sum(FP32), 1 GPU",
         "value": value,
         "unit": "rigid-pair F+tau evals/s",
         "n_gpus": 1,
-        "steps": nsteps,
+        "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * bead["wall_s"] / nsteps,
+        "ms_per_step": nn["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic (seeded random placement, orientations, Maxwell-Boltzmann momenta)",
-        "config": {"workload": "cubes4096_phi0.20: 4096 cube shells (152 beads), LJ rc=2.5, NVE dt=0.005, "
-                               "kT=1, bead path",
-                   "n_bodies": cfg.n_bodies, "beads_per_body": cfg.body.n, "box": cfg.box,
-                   "pairs_per_step": npairs_now},
-        "md_steps_per_s": steps_per_s,
-        "bead_path": {"pairs_evaluated": bead["pairs_evaluated"], "rebuilds": bead["rebuilds"],
-                      "gpu_ms_per_step": bead["gpu_ms"] / nsteps, "graph_steps": GRAPH_STEPS,
-                      "eager_ms_per_step": bead["eager_ms_per_step"],
-                      "total_energy_start": e_start, "total_energy_end": e_tot,
-                      "energy_drift_per_body": (e_tot - e_start) / sysm.n,
-                      # the first eager step, the warm-up, one untimed graph replay, the
-                      # timed steps and the eager steps timed after them
-                      "drift_over_steps": 1 + args.warmup + GRAPH_STEPS + nsteps + 5 * GRAPH_STEPS},
-        "roofline": {"kernel": "k_bead_md (rb_bead_pair_forces)", "bound": "alu", "achieved": achieved / 1e12,
-                     "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK,
-                     "traffic": bead_traffic(), "traffic_unit": "bytes per launch", "kernel_ms": kern_ms,
-                     "algorithmic_work": f"{tests_done:.0f} bead-bead distance tests x {FLOP_PER_TEST} FLOP per "
-                                         f"launch (the tests that survive exact box culling; the brute-force "
-                                         f"double sum would do {npairs_now} pairs x {cfg.body.n}^2 = "
-                                         f"{tests_brute} tests)",
-                     "brute_force_equivalent_tflops": tests_brute * FLOP_PER_TEST / (kern_ms * 1e-3) / 1e12},
+        "dtype": "bf16",
+        "data": "synthetic (seeded random placement and orientations, Maxwell-Boltzmann momenta; surrogate "
+                "trained in this run on pairs of seeded bead-path runs)",
+        "config": {"workload": f"{c5.name}: {c5.n_bodies} cylinders ({c5.body.n} beads), LJ rc={c5.rc}, NVE "
+                               f"kT={c5.kT} dt={c5.dt}, network path (BF16 surrogate on the cylinder "
+                               f"four-number descriptor, bead sum below a shells' bound of {GAP_MIN})",
+                   "n_bodies": c5.n_bodies, "beads_per_body": c5.body.n, "box": c5.box,
+                   "pair_range": c5.d_cut, "pairs_within_range": nn["pairs_within"]},
+        "md_steps_per_s": nn["md_steps_per_s"],
+        "nn_path": nn,
+        "bead_path": bead,
+        "nn_vs_bead": {"md_steps_per_s": nn["md_steps_per_s"] / bead["md_steps_per_s"],
+                       "pair_evals_per_s": nn["pair_evals_per_s"] / bead["pair_evals_per_s"]},
+        "surrogate": surrogate,
+        "roofline": roofline,
     }
 
-    log("[bench] per-kernel rooflines")
-    result["kernels"] = kernel_table(sysm, cfg, torch, abi)
-
-    if not args.no_nn:
-        # network path on the same system, with a cube-6 surrogate trained
-        # here on pairs visited by the bead dynamics from the same start,
-        # labelled by the bead kernel (its held-out errors are reported)
-        from paper_2402_12199_amd.surrogate import train_surrogate_md
-        log(f"[bench] training a {cfg.body.name} surrogate ({args.nn_epochs} epochs)")
-        sur = train_surrogate_md(cfg, st, 1 << 20, 1 << 16, args.nn_epochs, log=log)
-        log(f"[bench] surrogate: label {sur['label_s']:.1f} s, train {sur['train_s']:.1f} s, "
-            f"held-out E rmse {sur['trained']['rmse_E']:.3f} (std {sur['trained']['std_E']:.3f})")
-        summary = {k: sur[k] for k in ("shape", "sampling", "epochs", "steps", "batch", "n_train", "n_test",
-                                       "label_s", "train_s", "samples_per_s", "d_min", "d_cut")}
-        summary["held_out"] = sur["trained"]
-        summary["loss_first_last"] = [sur["loss_history"][0], sur["loss_history"][-1]]
-        log("[bench] network path on the same system")
-        st2 = state.initial_state(cfg)
-        sysn = make_system(cfg, st2, torch)
-        sysn.set_nn(NNModel(params=sur["params"], norm=sur["norm"], precision=abi.RB_PREC_BF16,
-                            d_min=cfg.d_min, sw_lo=cfg.d_cut - 1.0, sw_hi=cfg.d_cut))
-        sysn.init_forces("nn")
-        ke0 = float((st2["P"] ** 2).sum() / (2 * cfg.body.mass) + (st2["L"] ** 2 / (2 * cfg.body.inertia)).sum())
-        e_nn0 = sysn.energy() + ke0
-        nn_steps = min(args.steps, args.nn_steps)
-        nn_warm = min(args.warmup, 20)
-        try:
-            nnr = run_md(sysn, nn_steps, nn_warm, cfg.dt, "nn", torch, abi)
-        except RuntimeError as e:       # a surrogate that lets bodies overlap
-            result["nn_path"] = {"error": str(e), "surrogate": summary}
-        else:
-            kin_n = sysn.kinetic_host()
-            e_end = sysn.energy() + float(kin_n.sum())
-            # how long the surrogate trajectory stays sound: continue eagerly
-            # to the bead run's length, checking the routing and the finite flag
-            done = nn_warm + nnr["steps"] + GRAPH_STEPS * 6
-            horizon, first_fallback = None, None
-            while done < args.warmup + args.steps:
-                for _ in range(50):
-                    sysn.step(cfg.dt, "nn")
-                done += 50
-                f = sysn.flags_host()
-                if first_fallback is None and f[abi.RB_FLAG_NBEAD] > 0:
-                    first_fallback = done
-                if f[abi.RB_FLAG_NONFINITE]:
-                    horizon = done
-                    break
-            result["nn_path"] = {
-                "pairs_per_s": nnr["pairs_evaluated"] / nnr["wall_s"],
-                "md_steps_per_s": nnr["steps"] / nnr["wall_s"],
-                "ms_per_step": 1e3 * nnr["wall_s"] / nnr["steps"],
-                "timed_steps": nnr["steps"], "warmup": nn_warm,
-                "eager_ms_per_step": nnr["eager_ms_per_step"],
-                "pairs_nn": nnr["n_nn"], "pairs_bead_fallback": nnr["n_bead"],
-                "speedup_steps_vs_bead": (nnr["steps"] / nnr["wall_s"]) / steps_per_s,
-                "speedup_pairs_vs_bead": (nnr["pairs_evaluated"] / nnr["wall_s"]) / value,
-                "total_energy_start_end_of_timed": [e_nn0, e_end],
-                "first_bead_fallback_step": first_fallback,
-                "nonfinite_at_step": horizon,
-                "steps_checked": done,
-                "surrogate": summary,
-            }
+    if not args.no_kernels:
+        log("[bench] per-kernel table")
+        kt = path_kernels(systems["nn"], systems["bead"], c5, torch, abi)
+        kt["nn_pair_forces"] = rl
+        box_per_body = float(c5.box) / c5.n_bodies ** (1.0 / 3.0)
+        for k in list(systems):
+            del systems[k]
+        torch.cuda.empty_cache()
+        kt["pair_list_rebuild_4M"] = builder_4m(box_per_body, c5.r_list, torch, abi)
+        kt.update(train_kernels(c5.body, c5.d_min, c5.d_cut, torch, abi))
+        result["kernels"] = kt
         log("[bench] network kernels on 2^20 pairs")
         result["nn_kernels_2^20"] = nn_kernels(torch, abi)
+    systems.clear()
 
-    if not args.no_learned:
-        result["cylinders"] = learned_part(args, torch, abi, log)
-        result["hphc_cubes"] = hphc_part(args, torch, abi, log)
+    if not args.no_dynamics:
+        from paper_2402_12199_amd.compare import compare
+        log("[bench] bead vs network dynamics, 2008 steps each")
+        result["dynamics"] = compare(c5, st, {"nn": model}, chunks=8, replays=25, log=log)
+
+    if args.extras:
+        result["cubes4096"] = cubes_part(args, torch, abi)
+        result["hphc_cubes"] = hphc_part(args, torch, abi)
 
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
-        result["cpu_baseline"] = cpu_baseline(cfg, st)
+        result["cpu_baseline"] = cpu_baseline(c5, st)
     print(json.dumps(result), flush=True)
 
 

@@ -136,8 +136,6 @@ __device__ inline float tile_bf16(const LdsBF16 &L, const Norm &nm, const float 
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt) {
             __asm__ volatile("" ::: "memory");
-            // input feature 16 mt + n lives in LDS column col
-            const int col = 32 * (mt >> 1) + 8 * (n >> 2) + 4 * (mt & 1) + (n & 3);
             f32x4 c = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kb = 0; kb < 4; ++kb) {
@@ -312,8 +310,6 @@ __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &n
 #pragma unroll
         for (int mm = 0; mm < 2; ++mm) {
             const int mt = 2 * v + mm;
-            // input feature 16 mt + n lives in LDS column col
-            const int col = 32 * (mt >> 1) + 8 * (n >> 2) + 4 * (mt & 1) + (n & 3);
             f32x4 c = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kb = 0; kb < 4; ++kb) {
@@ -701,7 +697,6 @@ __device__ inline void tile_bf16_wide_fm(const LdsBF16 &L, WideX &X, WideT &XT, 
 #pragma unroll
         for (int mm = 0; mm < 2; ++mm) {
             const int mt = 2 * v + mm;
-            const int col = 32 * (mt >> 1) + 8 * (n >> 2) + 4 * (mt & 1) + (n & 3);
             f32x4 c = f32x4{0.f, 0.f, 0.f, 0.f}, ct = c;
 #pragma unroll
             for (int kb = 0; kb < 4; ++kb) {

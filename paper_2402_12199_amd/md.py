@@ -259,22 +259,24 @@ class RigidSystem:
                           None, 0.0, self.kinetic, None, self.ws_rig)
 
     # ------------------------------------------------------------ graphs
-    def capture(self, dt, path="bead", steps=1, fused=False):
+    def capture(self, dt, path="bead", steps=1, fused=False, kinetic_last=True):
         """Record `steps` MD steps into a HIP graph (torch.cuda.CUDAGraph).
 
         Every step only enqueues kernels whose sizes are fixed at capture and
         whose data-dependent extents (pair counts, rebuild flag) are read on
         the device, so replaying the graph performs the same work as calling
-        `step` that many times.  Capturing does not execute the steps.
+        `step` that many times.  Capturing does not execute the steps.  With
+        fused steps the kinetic energy is reduced in the graph's last step
+        (kinetic_last), so a replay leaves the energy of its end state.
         """
         # one eager call first so lazily cached host values exist before capture
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=side):
-            for _ in range(steps):
+            for k in range(steps):
                 if fused:
-                    self.fused_step(dt, path)
+                    self.fused_step(dt, path, kinetic=kinetic_last and k == steps - 1)
                 else:
                     self.step(dt, path)
         torch.cuda.current_stream().wait_stream(side)

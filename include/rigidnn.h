@@ -410,6 +410,24 @@ int rb_rigid_step_fused(const rb_ctx *ctx, int32_t n, double dt, double *x, doub
                         const double *x_sref, const double *q_sref, double half_margin,
                         double *kinetic, int32_t *flags, void *ws, size_t ws_bytes, void *stream);
 
+/* Allocation-free variant of rb_rigid_step_fused, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same arguments without ws, the same
+ * kernel and results bit for bit.  The kinetic partial sums and the
+ * completion ticket live in a file-scope device array of the library
+ * (262 656 bytes per device, held until the process ends); the call
+ * allocates nothing, clears the ticket with a small kernel before the step
+ * and needs n <= rb_rigid_step_fused_noalloc_max_bodies() (4 194 304),
+ * else RB_ERR_INVALID_ARG.  Every call on one device shares that device's
+ * array: calls that overlap on one device (different streams or host
+ * threads without ordering) race and give wrong kinetic energies. */
+size_t rb_rigid_step_fused_noalloc_max_bodies(void);
+int rb_rigid_step_fused_noalloc(const rb_ctx *ctx, int32_t n, double dt, double *x, double *P, double *q,
+                                double *L, const int32_t *type, int64_t *acc, float *force, float *torque,
+                                double *energy_virial, const double *x_ref, double half_skin,
+                                const double *x_sref, const double *q_sref, double half_margin,
+                                double *kinetic, int32_t *flags, void *stream);
+
 /* ---- training step (energy loss, Adam) ------------------------------------
  * Paper section 2: the network g_NN_U is fitted by regression to pair
  * energies that the bead method computes for sampled pair configurations

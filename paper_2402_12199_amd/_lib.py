@@ -52,6 +52,9 @@ SIGNATURES = {
                                 P]),
     "rb_rigid_step_fused": (C.c_int, [P, I32, F64, P, P, P, P, P, P, P, P, P, P, F64, P, P, F64, P, P, P, SZ,
                                       P]),
+    "rb_rigid_step_fused_noalloc": (C.c_int, [P, I32, F64, P, P, P, P, P, P, P, P, P, P, F64, P, P, F64, P, P,
+                                              P]),
+    "rb_rigid_step_fused_noalloc_max_bodies": (SZ, []),
     "rb_nn_train_workspace_bytes": (SZ, [I32]),
     "rb_nn_train_fm_workspace_bytes": (SZ, [I32]),
     "rb_nn_train_step_fm": (C.c_int, [P, P, P, I32, FP, C.c_int, I32, P, I64, P, P, P, F32, F32, F32, F32, F32,

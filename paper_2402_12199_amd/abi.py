@@ -20,7 +20,7 @@ RB_FLAG_REBUILD, RB_FLAG_NPAIRS, RB_FLAG_OVERFLOW, RB_FLAG_NREBUILDS = 0, 1, 2, 
 RB_FLAG_NBEAD, RB_FLAG_NNN, RB_FLAG_NONFINITE, RB_FLAG_NEVAL, RB_FLAG_NTESTS, RB_NFLAGS = 4, 5, 6, 7, 8, 16
 RB_FLAG_NSCREEN, RB_FLAG_RESCREEN, RB_FLAG_NRESCREENS = 10, 11, 12
 RB_FLAG_FIXOVF, RB_FLAG_QDRIFT = 13, 14
-RB_OK, RB_ERR_CAPACITY, RB_ERR_NONFINITE = 0, -2, -5
+RB_OK, RB_ERR_INVALID_ARG, RB_ERR_CAPACITY, RB_ERR_HIP, RB_ERR_UNSUPPORTED, RB_ERR_NONFINITE = 0, -1, -2, -3, -4, -5
 RB_PREC_BF16, RB_PREC_FP32 = 0, 1
 RB_BUILD_ALWAYS, RB_BUILD_IF_FLAGGED = 0, 1
 RB_MLP_NPARAMS = 50689
@@ -377,6 +377,33 @@ def rb_rigid_step_fused(ctx: Ctx, dt: float, x, P, q, L, types, acc, force, torq
                                     _ptr(flags, torch.int32, (RB_NFLAGS,), "flags"),
                                     _ptr(ws, torch.uint8, name="ws"), ws.numel(), _stream()),
           "rb_rigid_step_fused")
+
+
+def rb_rigid_step_fused_noalloc(ctx: Ctx, dt: float, x, P, q, L, types, acc, force, torque, energy_virial, x_ref,
+                                half_skin, kinetic, flags, x_sref=None, q_sref=None, half_margin=0.0):
+    n = P.shape[1]
+    check(lib().rb_rigid_step_fused_noalloc(ctx.handle, n, float(dt), _ptr(x, torch.float64, (3, n), "x"),
+                                            _ptr(P, torch.float64, (3, n), "P"),
+                                            _ptr(q, torch.float64, (4, n), "q"),
+                                            _ptr(L, torch.float64, (3, n), "L"),
+                                            _ptr(types, torch.int32, (n,), "type"),
+                                            _ptr(acc, torch.int64, (acc_len(n),), "acc"),
+                                            _ptr(force, torch.float32, (3, n), "force"),
+                                            _ptr(torque, torch.float32, (3, n), "torque"),
+                                            _ptr(energy_virial, torch.float64, (10,), "energy_virial",
+                                                 optional=True),
+                                            _ptr(x_ref, torch.float64, (3, n), "x_ref", optional=True),
+                                            float(half_skin),
+                                            _ptr(x_sref, torch.float64, (3, n), "x_sref", optional=True),
+                                            _ptr(q_sref, torch.float64, (4, n), "q_sref", optional=True),
+                                            float(half_margin),
+                                            _ptr(kinetic, torch.float64, (2,), "kinetic", optional=True),
+                                            _ptr(flags, torch.int32, (RB_NFLAGS,), "flags"), _stream()),
+          "rb_rigid_step_fused_noalloc")
+
+
+def rb_rigid_step_fused_noalloc_max_bodies() -> int:
+    return int(lib().rb_rigid_step_fused_noalloc_max_bodies())
 
 
 def rb_nn_train_step_fm(params, adam_m, adam_v, t: int, norm, precision: int, batch: int, desc, labels, ft_labels,

@@ -31,6 +31,8 @@
 #pragma clang fp contract(on)
 #include "rb_common.hpp"
 
+#include <mutex>
+
 namespace rb {
 
 constexpr int kIntThreads = 256;
@@ -374,6 +376,21 @@ __global__ __launch_bounds__(kIntThreads) void k_fused(int32_t n, double dt, dou
 
 static size_t nblocks(int32_t n) { return (size_t)((n + kIntThreads - 1) / kIntThreads); }
 
+// Allocation-free form of the fused step: the per-block kinetic partial sums
+// and the completion ticket live in this file-scope array (one copy per
+// device, held until the process ends) instead of a caller workspace.
+constexpr int32_t kNoAllocMaxBodies = 1 << 22;
+constexpr size_t kNoAllocPartialBytes =
+    ((sizeof(double) * 2 * (((size_t)kNoAllocMaxBodies + kIntThreads - 1) / kIntThreads + 1) + 255) & ~(size_t)255);
+constexpr size_t kNoAllocScratchBytes = kNoAllocPartialBytes + 256;   // partial sums, then the ticket
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+// Clears the completion ticket (a kernel, so that the call can be captured
+// in a graph).
+__global__ void k_clear_ticket(unsigned *ticket) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *ticket = 0u;
+}
+
 }  // namespace rb
 
 using namespace rb;
@@ -443,5 +460,63 @@ extern "C" int rb_rigid_step_fused(const rb_ctx *ctx, int32_t n, double dt, doub
         n, dt, x, P, q, L, type, ctx->dev.mass, ctx->dev.inertia, acc, force, torque, energy_virial,
         make_watch(ctx, x_ref, half_skin, x_sref, q_sref, half_margin), flags, partial, ticket, kinetic);
     RB_LAUNCH_CHECK("rb_rigid_step_fused");
+    return RB_OK;
+}
+
+// Device address of `scratch` on each device, taken once per device with that
+// device current (each device holds its own copy of the array).
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(unsigned char **out) {
+    int dev = -1;
+    const int rc = rb::hip_check(hipGetDevice(&dev), "rb_rigid_step_fused_noalloc: hipGetDevice");
+    if (rc != RB_OK) return rc;
+    if (dev < 0 || dev >= kMaxDevices) {
+        rb::set_error("rb_rigid_step_fused_noalloc: device %d beyond the %d devices supported", dev, kMaxDevices);
+        return RB_ERR_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const int rs = rb::hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)),
+                                     "rb_rigid_step_fused_noalloc: hipGetSymbolAddress");
+        if (rs != RB_OK) return rs;
+        if (!p) {
+            rb::set_error("rb_rigid_step_fused_noalloc: hipGetSymbolAddress returned a null address");
+            return RB_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return RB_OK;
+}
+}  // namespace
+
+extern "C" size_t rb_rigid_step_fused_noalloc_max_bodies(void) { return (size_t)kNoAllocMaxBodies; }
+
+extern "C" int rb_rigid_step_fused_noalloc(const rb_ctx *ctx, int32_t n, double dt, double *x, double *P, double *q,
+                                           double *L, const int32_t *type, int64_t *acc, float *force,
+                                           float *torque, double *energy_virial, const double *x_ref,
+                                           double half_skin, const double *x_sref, const double *q_sref,
+                                           double half_margin, double *kinetic, int32_t *flags, void *stream) {
+    RB_REQUIRE(ctx && x && P && q && L && type && acc && force && torque && flags,
+               "rb_rigid_step_fused_noalloc: null argument");
+    RB_REQUIRE(n > 0, "rb_rigid_step_fused_noalloc: n must be > 0");
+    RB_REQUIRE(n <= kNoAllocMaxBodies, "rb_rigid_step_fused_noalloc: n exceeds the scratch limit of 4194304 bodies");
+    RB_REQUIRE(!x_sref || q_sref, "rb_rigid_step_fused_noalloc: x_sref needs q_sref");
+    unsigned char *base = nullptr;
+    const int rc = scratch_address(&base);
+    if (rc != RB_OK) return rc;
+    double *partial = reinterpret_cast<double *>(base);
+    unsigned *ticket = reinterpret_cast<unsigned *>(base + kNoAllocPartialBytes);
+    hipStream_t st = (hipStream_t)stream;
+    k_clear_ticket<<<1, 64, 0, st>>>(ticket);
+    k_fused<<<(int)nblocks(n) + 1, kIntThreads, 0, st>>>(
+        n, dt, x, P, q, L, type, ctx->dev.mass, ctx->dev.inertia, acc, force, torque, energy_virial,
+        make_watch(ctx, x_ref, half_skin, x_sref, q_sref, half_margin), flags, partial, ticket, kinetic);
+    RB_LAUNCH_CHECK("rb_rigid_step_fused_noalloc");
     return RB_OK;
 }

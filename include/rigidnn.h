@@ -78,7 +78,10 @@ extern "C" {
                                 norm had drifted from 1 by more than 1e-10
                                 (|q|^2 - 1) before the integrator's
                                 renormalisation; also counts non-finite q      */
-#define RB_NFLAGS 16
+#define RB_FLAG_ROUTE_WORK 16 /* words 16..18: working counters of
+                                rb_pair_descriptors (network, bead, blocks
+                                done); zero between calls                      */
+#define RB_NFLAGS 20
 
 #define RB_PREC_BF16 0       /* 128x128 layers on BF16 MFMA, FP32 accumulate     */
 #define RB_PREC_FP32 1       /* every layer in FP32                              */
@@ -170,7 +173,9 @@ int rb_pairlist_build(int32_t n, const double *x, const double *box, double r_li
  * bead pair within gap_max, so zero bead energy when gap_max >= rc) to
  * neither, the rest to the network.  Routed pair indices go to idx_nn /
  * idx_bead (capacity max_pairs each, order not specified) with counts in
- * flags[NNN] / flags[NBEAD].  x: 3 x n, q: 4 x n. */
+ * flags[NNN] / flags[NBEAD], written by the launch's last block (words
+ * flags[RB_FLAG_ROUTE_WORK ..+2] count during the launch and are left
+ * zero).  x: 3 x n, q: 4 x n. */
 int rb_pair_descriptors(int32_t n, const double *x, const double *q, const double *box,
                         const int32_t *pair_i, const int32_t *pair_j, int32_t max_pairs,
                         float d_min, float d_max, float *desc, int32_t *idx_nn,

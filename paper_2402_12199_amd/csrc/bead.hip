@@ -764,17 +764,6 @@ static size_t device_max_lds() {
     return cached;
 }
 
-static int device_cus_bead() {
-    static int cached = 0;
-    if (cached > 0) return cached;
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-        cus = 256;
-    cached = cus;
-    return cus;
-}
-
 }  // namespace rb
 
 using namespace rb;
@@ -791,7 +780,7 @@ extern "C" int rb_bead_pair_eval(const rb_ctx *ctx, int64_t n_pairs, const float
     RB_REQUIRE(lds <= 65536, "rb_bead_pair_eval: templates need %zu bytes of LDS (max 65536)", lds);
     static int c_lds = -1, c_nb = 0;
     const int nb = blocks_per_cu(k_bead_desc<kPotLJ>, 256, lds, &c_lds, &c_nb);
-    const int grid = grid_for(n_pairs, kBeadWaves, nb * device_cus_bead());
+    const int grid = grid_for(n_pairs, kBeadWaves, nb * device_cu_count());
     if (ctx->dev.lj.kind == kPotHPHC)
         k_bead_desc<kPotHPHC><<<grid, 256, lds, (hipStream_t)stream>>>(ctx->dev.t, ctx->dev.lj, type_i, type_j,
                                                                       n_pairs, desc, out, flags, stride);
@@ -824,7 +813,7 @@ static int launch_bead_md(const rb_ctx *ctx, int32_t n, const double *x, const d
     auto kern = hphc ? k_bead_md<kPotHPHC, SCREENED> : k_bead_md<kPotLJ, SCREENED>;
     static int c_lds[2] = {-1, -1}, c_nb[2] = {0, 0};
     const int nb = blocks_per_cu(kern, kMdWaves * kWave, lds, &c_lds[hphc], &c_nb[hphc]);
-    const int grid = grid_for(max_count, kMdWaves, nb * device_cus_bead());
+    const int grid = grid_for(max_count, kMdWaves, nb * device_cu_count());
     kern<<<grid, kMdWaves * kWave, lds, (hipStream_t)stream>>>(ctx->dev.t, ctx->dev.lj, n, x, q, type, b, pair_i,
                                                               pair_j, idx, count_dev, max_count, acc, flags, stride,
                                                               S);
@@ -884,7 +873,7 @@ extern "C" int rb_bead_screen(const rb_ctx *ctx, int32_t n, const double *x, con
         b.inv[a] = 1.0 / box[a];
     }
     const float rcm = sqrtf(ctx->dev.lj.rc2) + kCullMargin;
-    k_bead_screen<<<grid_for(max_count, 256, 4 * device_cus_bead()), 256, 0, (hipStream_t)stream>>>(
+    k_bead_screen<<<grid_for(max_count, 256, 4 * device_cu_count()), 256, 0, (hipStream_t)stream>>>(
         ctx->dev.t, rcm, n, x, q, type, b, pair_i, pair_j, idx, count_dev, max_count, idx_out, count_out, tmp, flags);
     RB_LAUNCH_CHECK("rb_bead_screen");
     return RB_OK;

@@ -15,11 +15,6 @@
 
 namespace rb {
 
-__global__ void k_route_reset(int32_t *flags) {
-    flags[RB_FLAG_NNN] = 0;
-    flags[RB_FLAG_NBEAD] = 0;
-}
-
 constexpr int kDescThreads = 1024;
 constexpr int kDescWaves = kDescThreads / kWave;
 
@@ -65,7 +60,9 @@ __global__ __launch_bounds__(kDescThreads) void k_descriptors(int32_t n, const d
                                                      const int32_t *__restrict__ type, float gap_min,
                                                      float gap_max) {
     // the first round's pair indices are requested together with the count
-    // (any slot below the capacity may be read; only live ones are used)
+    // (any slot below the capacity may be read; only live ones are used).
+    // Appends go through working counters; the last block to finish
+    // publishes the counts and clears them for the next call.
     const int p0 = blockIdx.x * blockDim.x + threadIdx.x;
     int i0 = 0, j0 = 0;
     if (p0 < maxp) {
@@ -74,6 +71,7 @@ __global__ __launch_bounds__(kDescThreads) void k_descriptors(int32_t n, const d
     }
     int count = flags[RB_FLAG_NPAIRS];
     if (count > maxp) count = maxp;
+    int32_t *work = flags + RB_FLAG_ROUTE_WORK;
     const double Ls[3] = {L0, L1, L2};
     for (int base = blockIdx.x * blockDim.x; base < count; base += gridDim.x * blockDim.x) {
         const int p = base + threadIdx.x;
@@ -117,7 +115,21 @@ __global__ __launch_bounds__(kDescThreads) void k_descriptors(int32_t n, const d
             to_bead = in_range && near;
             if (!type) to_bead = near;    // no shells: every pair below d_min, as before
         }
-        block_append2(live && to_nn, live && to_bead, p, idx_nn, flags + RB_FLAG_NNN, idx_bead, flags + RB_FLAG_NBEAD);
+        block_append2(live && to_nn, live && to_bead, p, idx_nn, work, idx_bead, work + 1);
+    }
+    // No fence is needed: the block's counter atomics have returned (block
+    // append waits for them) before its ticket is taken, and the last block
+    // reads the counters with device-scope atomic loads.  The published counts
+    // reach the consumers through the kernel boundary.
+    __shared__ bool last;
+    if (threadIdx.x == 0) last = atomicAdd(work + 2, 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        flags[RB_FLAG_NNN] = __hip_atomic_load(work, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        flags[RB_FLAG_NBEAD] = __hip_atomic_load(work + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        work[0] = 0;
+        work[1] = 0;
+        work[2] = 0;
     }
 }
 
@@ -136,7 +148,6 @@ extern "C" int rb_pair_descriptors(int32_t n, const double *x, const double *q, 
     RB_REQUIRE(n > 0 && max_pairs > 0, "rb_pair_descriptors: sizes must be > 0");
     RB_REQUIRE(box[0] > 0 && box[1] > 0 && box[2] > 0, "rb_pair_descriptors: box must be > 0");
     hipStream_t st = (hipStream_t)stream;
-    k_route_reset<<<1, 1, 0, st>>>(flags);
     const float dm2 = d_min > 0 ? d_min * d_min : 0.f;
     const float dx2 = d_max > 0 ? d_max * d_max : 3.0e38f;
     Templates T = {};

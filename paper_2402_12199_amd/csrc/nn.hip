@@ -444,12 +444,111 @@ __device__ inline void forces_epilogue_wide(const NNArgs &a, const EpiLds &e, co
     }
 }
 
-template <int MODE>
+// Inputs of the next tile fetched while the current one is computed (forces
+// mode, (d, q) and cylinder inputs): one wave of each group runs a
+// three-level chain -- the routed pair index at the tile's start; after
+// layer 1 the pair's (d, q) and its two bodies, straight from global memory
+// into the group's second epilogue buffer in LDS (global_load_lds: lane l's
+// dword lands at the uniform LDS base + 4 l); after the forward pass body
+// i's FP64 orientation the same way, 32 lanes a component (lane l: half
+// l % 2 of pair l / 2).  The wave waits for all of it before the next
+// tile's first barrier.
+using lds_ptr = __attribute__((address_space(3))) void *;
+using gbl_ptr = const __attribute__((address_space(1))) void *;
+
+__device__ inline void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0f70); }   // vmcnt(0)
+
+struct NextTile {
+    const NNArgs *a;
+    EpiLds *e;
+    int64_t row0, count;   // first row of the next tile, rows in the launch
+    bool active;           // this wave fetches and there is a next tile
+    int lane;
+    int32_t pid;           // level 1: routed pair index (lanes 0..15)
+
+    __device__ bool live_row(int r) const { return row0 + r < count; }
+
+    __device__ void start() {
+        pid = 0;
+        if (active && lane < kTile && live_row(lane)) pid = a->idx ? a->idx[row0 + lane] : (int32_t)(row0 + lane);
+    }
+
+    // Every wave waits at each stage (only the fetching wave has loads in
+    // flight), so that no wave reaches code past a stage with a fetch the
+    // compiler cannot prove complete.
+    __device__ void operator()(int stage) const {
+        wait_vmem();
+        if (!active) return;
+        if (stage == 1) {
+            if (lane < kTile && live_row(lane)) {
+#pragma unroll
+                for (int k = 0; k < kIn; ++k)
+                    __builtin_amdgcn_global_load_lds((gbl_ptr)(a->desc + k * a->stride + pid), (lds_ptr)&e->d[k][0], 4,
+                                                     0, 0);
+                __builtin_amdgcn_global_load_lds((gbl_ptr)(a->pi + pid), (lds_ptr)&e->i[0], 4, 0, 0);
+                __builtin_amdgcn_global_load_lds((gbl_ptr)(a->pj + pid), (lds_ptr)&e->j[0], 4, 0, 0);
+            }
+        } else if (stage == 2) {
+            const int r = lane >> 1;
+            if (lane < 2 * kTile && live_row(r)) {
+                const int bi = e->i[r];
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    __builtin_amdgcn_global_load_lds(
+                        (gbl_ptr)(reinterpret_cast<const uint32_t *>(a->q + (int64_t)c * a->n + bi) + (lane & 1)),
+                        (lds_ptr)&e->q[c][0], 4, 0, 0);
+            }
+        }
+    }
+};
+
+// A tile's network input read back from the epilogue buffer the previous
+// tile filled.
+__device__ inline TileIn tile_from_lds(const NNArgs &a, const EpiLds &e, int64_t row, int64_t count, int n) {
+    TileIn t;
+    t.row = row;
+    t.live = row < count;
+    t.pid = 0;
+    float ud[kIn];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) ud[k] = t.live ? e.d[k][n] : (k == 3 ? 1.f : 0.f);
+    if (a.cyl)
+        cyl_features(ud, t.u);
+    else
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) t.u[k] = ud[k];
+    float dsdr;
+    t.seed = smooth_switch(centre_distance(a, t.u), a.sw_lo, a.sw_hi, dsdr);
+    return t;
+}
+
+// dE/ds -> dE/du of the cylinder form from the pair's (d, q) held in LDS.
+__device__ inline void cyl_chain_lds(const EpiLds &e, int n, float gu[kIn]) {
+    float ud[kIn], J[kIn][kIn], gs[kIn];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) {
+        ud[k] = e.d[k][n];
+        gs[k] = gu[k];
+    }
+    cyl_jacobian(ud, J);
+#pragma unroll
+    for (int m = 0; m < kIn; ++m) {
+        float v = 0.f;
+#pragma unroll
+        for (int r = 0; r < kIn; ++r) v = fmaf(J[r][m], gs[r], v);
+        gu[m] = v;
+    }
+}
+
+// PRE (forces with (d, q) or cylinder inputs): the next tile's inputs are
+// fetched during the current one into the group's other epilogue buffer.
+template <int MODE, bool PRE = false>
 __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
+    static_assert(!PRE || MODE == kForces, "prefetching is a forces-mode form");
     __shared__ LdsBF16 L;
     __shared__ WideX X[kWideGroups];
     __shared__ long long wacc[kWideGroups * kWideGroup][10];
-    __shared__ EpiLds EL[MODE == kForces ? kWideGroups : 1];
+    __shared__ EpiLds EL[MODE == kForces ? kWideGroups : 1][PRE ? 2 : 1];
     int64_t count = a.P;
     if (MODE == kForces) {
         const int64_t c = *a.count_dev;
@@ -469,18 +568,33 @@ __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
     TileIn t = tile_in<MODE>(a, (base + grp) * kTile + n, count, g == 0 && v == 0);
     stage_bf16<kWideThreads>(L, a.params);
     if (MODE == kForces && lane < 10) wacc[wave][lane] = 0;
+    if (PRE && v == 0 && g == 0) put_epi(a, EL[grp][0], t.ein, t.u, t.pid, t.live, n);
     bool bad = false, ovf = false;
-    for (;;) {
-        if (MODE == kForces && v == 0 && g == 0) put_epi(a, EL[grp], t.ein, t.u, t.pid, t.live, n);
+    for (int it = 0;; ++it) {
+        EpiLds &ecur = EL[MODE == kForces ? grp : 0][PRE ? (it & 1) : 0];
+        if (MODE == kForces && !PRE && v == 0 && g == 0) put_epi(a, ecur, t.ein, t.u, t.pid, t.live, n);
         __syncthreads();
+        if (PRE && it > 0) t = tile_from_lds(a, ecur, (base + grp) * kTile + n, count, n);
+        const int64_t nbase = base + (int64_t)gridDim.x * kWideGroups;
+        NextTile nx;
+        nx.a = &a;
+        nx.e = &EL[MODE == kForces ? grp : 0][PRE ? ((it + 1) & 1) : 0];
+        nx.row0 = (nbase + grp) * kTile;
+        nx.count = count;
+        nx.active = PRE && v == 1 && nbase < ntiles;
+        nx.lane = lane;
+        nx.start();
         float gu[kIn];
-        const float E = tile_bf16_wide<true>(L, X[grp], a.nm, t.u, t.seed, gu, v);
+        const float E = tile_bf16_wide<true, false, NextTile>(L, X[grp], a.nm, t.u, t.seed, gu, v, Emit{}, nx);
         // the group's results are the same in its four waves
         if (MODE == kForces) {
             if (a.jac || a.cyl) {
                 // dE/du = J^T dE/ds once per pair, shared through LDS
                 if (v == 0 && g == 0 && t.live) {
-                    sym_chain(a, t.row, t.pid, gu);
+                    if (PRE && a.cyl)
+                        cyl_chain_lds(ecur, n, gu);
+                    else
+                        sym_chain(a, t.row, t.pid, gu);
 #pragma unroll
                     for (int k = 0; k < kIn; ++k) X[grp].red[0][1 + k][n] = gu[k];
                 }
@@ -488,16 +602,21 @@ __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
 #pragma unroll
                 for (int k = 0; k < kIn; ++k) gu[k] = X[grp].red[0][1 + k][n];
             }
-            forces_epilogue_wide(a, EL[grp], gu, E, t.live, v, g, n, wacc[wave], bad, ovf);
+            forces_epilogue_wide(a, ecur, gu, E, t.live, v, g, n, wacc[wave], bad, ovf);
         } else if (v == 0 && t.live && g == 0) {
             sym_chain(a, t.row, t.pid, gu);
             store_grad(a, t, gu, E);
         }
-        base += (int64_t)gridDim.x * kWideGroups;
+        // the fetching wave's loads into LDS have landed before the next
+        // tile's first barrier
+        if (nx.active) wait_vmem();
+        base = nbase;
         if (base >= ntiles) break;
-        t = tile_in<MODE>(a, (base + grp) * kTile + n, count, g == 0 && v == 0);
-        // the previous tile's epilogue has read its inputs from LDS
-        __syncthreads();
+        if (!PRE) {
+            t = tile_in<MODE>(a, (base + grp) * kTile + n, count, g == 0 && v == 0);
+            // the previous tile's epilogue has read its inputs from LDS
+            __syncthreads();
+        }
     }
     if (MODE == kForces) {
         long long part[11];
@@ -518,26 +637,16 @@ __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
 // usually far fewer.
 constexpr int64_t kWideMaxTiles = 16384;
 
-// Compute units of the current device (one persistent block per CU: the
-// BF16 weight image fills most of a CU's LDS).
-static int device_cus() {
-    static int cached = 0;
-    if (cached > 0) return cached;
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-        cus = 256;
-    cached = cus;
-    return cus;
-}
-
 template <int MODE>
 static int launch(const NNArgs &a, int precision, int64_t rows, hipStream_t st) {
     const int64_t tiles = (rows + kTile - 1) / kTile;
-    const int cus = device_cus();
+    const int cus = device_cu_count();
     if constexpr (MODE != kEval) {
         if (precision == RB_PREC_BF16 && (MODE == kForces || tiles <= kWideMaxTiles)) {
-            k_nn_wide<MODE><<<grid_for(tiles, kWideGroups, cus), kWideThreads, 0, st>>>(a);
+            if (MODE == kForces && !a.sym)
+                k_nn_wide<kForces, true><<<grid_for(tiles, kWideGroups, cus), kWideThreads, 0, st>>>(a);
+            else
+                k_nn_wide<MODE><<<grid_for(tiles, kWideGroups, cus), kWideThreads, 0, st>>>(a);
             return hip_check(hipGetLastError(), "network kernel launch");
         }
     }

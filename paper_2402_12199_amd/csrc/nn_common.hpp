@@ -30,7 +30,6 @@ constexpr int kIn = 7;
 constexpr int kNnWaves = 8;
 constexpr int kNnThreads = kNnWaves * kWave;
 constexpr int kTile = 16;
-constexpr int kRow = kH + 8;   // padded LDS row of bf16 weights
 
 constexpr int OFF_W1 = 0, OFF_B1 = 896, OFF_W2 = 1024, OFF_B2 = 17408, OFF_W3 = 17536, OFF_B3 = 33920,
               OFF_W4 = 34048, OFF_B4 = 50432, OFF_W5 = 50560, OFF_B5 = 50688, NPARAMS = 50689;
@@ -87,8 +86,19 @@ __device__ inline bf16x8 pack8(const float a[4], const float b[4]) {
 
 // LDS image of the weights used by the BF16 kernels, 16-byte aligned so that
 // 16-byte weight fragments and bias vectors load as single ds_read_b128.
+// Rows of the BF16 weight image are 256 bytes (16 chunks of 8 BF16) with no
+// padding; chunk c of row r is stored at chunk c ^ wswz(r).  Over any 16
+// consecutive rows wswz is a permutation of 0..15, so the forward pass's
+// 16-byte fragment reads (16 lanes, 16 consecutive rows, one chunk) hit 16
+// different bank groups; the reverse pass's transposing reads (per 32 lanes:
+// 8 rows 4 g + j / 4 of one 32-row block, 4 chunks) spread over all 16 bank
+// groups twice, the least for reads that all take the same half of a chunk
+// (a plain 68-dword stride gives four-way conflicts there).
+__device__ inline int wswz(int r) { return ((r >> 2) & 3) | ((r & 3) << 2); }
+__device__ inline int wcol(int r, int c) { return (((c >> 3) ^ wswz(r)) << 3) | (c & 7); }
+
 struct alignas(16) LdsBF16 {
-    __bf16 w[3][kH][kRow];   // W2..W4, columns permuted per 32-block
+    __bf16 w[3][kH][kH];     // W2..W4, columns permuted per 32-block, 16-byte chunks swizzled (wcol)
     float w1[kH][8];          // W1 (7 columns, padded)
     float b[4][kH];           // b1..b4
     float w5[kH];
@@ -112,9 +122,9 @@ __device__ inline bf16x8 wt_frag(const LdsBF16 &L, int l, int kb, int mt, int la
     const int j = lane & 15, g = lane >> 4;
     const int row = 32 * kb + 4 * g + (j >> 2);
     const int col = 32 * (mt >> 1) + 8 * (j & 3) + 4 * (mt & 1);
-    const s16x4 a = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(const_cast<__bf16 *>(&L.w[l][row][col])));
+    const s16x4 a = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(const_cast<__bf16 *>(&L.w[l][row][wcol(row, col)])));
     const s16x4 b =
-        __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(const_cast<__bf16 *>(&L.w[l][row + 16][col])));
+        __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(const_cast<__bf16 *>(&L.w[l][row + 16][wcol(row + 16, col)])));
     typedef short s16x8 __attribute__((ext_vector_type(8)));
     const s16x8 v = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
     return __builtin_bit_cast(bf16x8, v);
@@ -149,7 +159,7 @@ __device__ inline void stage_bf16(LdsBF16 &L, const float *__restrict__ p) {
             const int l = idx / (kH * 16), o = (idx / 16) % kH, u = idx % 16, cb = u >> 2, g = u & 3;
             const float av[4] = {va[k].x, va[k].y, va[k].z, va[k].w};
             const float bv[4] = {vb[k].x, vb[k].y, vb[k].z, vb[k].w};
-            *reinterpret_cast<bf16x8 *>(&L.w[l][o][32 * cb + 8 * g]) = pack8(av, bv);
+            *reinterpret_cast<bf16x8 *>(&L.w[l][o][wcol(o, 32 * cb + 8 * g)]) = pack8(av, bv);
         }
     }
 #pragma unroll

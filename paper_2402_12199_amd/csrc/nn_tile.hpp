@@ -74,7 +74,7 @@ __device__ inline float tile_bf16(const LdsBF16 &L, const Norm &nm, const float 
             f32x4 c = *reinterpret_cast<const f32x4 *>(&L.b[l + 1][16 * mt + 4 * g]);
 #pragma unroll
             for (int kb = 0; kb < 4; ++kb) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&L.w[l][16 * mt + n][32 * kb + 8 * g]);
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&L.w[l][16 * mt + n][wcol(16 * mt + n, 32 * kb + 8 * g)]);
                 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kb], c, 0, 0, 0);
             }
             float h[4], d[4];
@@ -196,11 +196,28 @@ struct WideX {
     float red[kWideGroup][8][16];    // per-row partial sums (energy, dX/du)
 };
 
-__device__ inline void wide_sync() { __syncthreads(); }
+// Barrier of the four-wave tiles: their waves exchange data through LDS only,
+// so the barrier waits for the wave's LDS operations and not for its global
+// memory operations (which a full __syncthreads also waits for, e.g. loads
+// a caller has in flight across the tile); the compiler fences keep LDS
+// accesses on their side of it.
+__device__ inline void wide_sync() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 
-template <bool GRAD, bool EMIT = false>
+// Work a caller interleaves with a tile (e.g. fetching the next tile's
+// inputs): hook(1) runs after layer 1's exchange, hook(2) after the energy,
+// before the reverse pass.
+struct NoHook {
+    __device__ void operator()(int) const {}
+};
+
+template <bool GRAD, bool EMIT = false, class Hook = NoHook>
 __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &nm, const float u[kIn], float seed,
-                                       float gu[kIn], int v, const Emit &em = Emit{}) {
+                                       float gu[kIn], int v, const Emit &em = Emit{}, const Hook &hook = Hook{}) {
     const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, n = lane & 15;
     float un[kIn];
 #pragma unroll
@@ -230,19 +247,28 @@ __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &n
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) act[kb] = X.a[kb][lane];
     wide_sync();
+    hook(1);
     float e = 0.f;
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
         float h[2][4], d[2][4];
+        // the wave's two output blocks as two interleaved MFMA chains (each
+        // accumulates over kb in order, as a single chain would)
+        f32x4 c2[2];
+#pragma unroll
+        for (int mm = 0; mm < 2; ++mm) c2[mm] = *reinterpret_cast<const f32x4 *>(&L.b[l + 1][16 * (2 * v + mm) + 4 * g]);
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int mm = 0; mm < 2; ++mm) {
+                const bf16x8 a =
+                    *reinterpret_cast<const bf16x8 *>(&L.w[l][16 * (2 * v + mm) + n][wcol(16 * (2 * v + mm) + n, 32 * kb + 8 * g)]);
+                c2[mm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kb], c2[mm], 0, 0, 0);
+            }
 #pragma unroll
         for (int mm = 0; mm < 2; ++mm) {
             const int mt = 2 * v + mm;
-            f32x4 c = *reinterpret_cast<const f32x4 *>(&L.b[l + 1][16 * mt + 4 * g]);
-#pragma unroll
-            for (int kb = 0; kb < 4; ++kb) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&L.w[l][16 * mt + n][32 * kb + 8 * g]);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kb], c, 0, 0, 0);
-            }
+            const f32x4 c = c2[mm];
 #pragma unroll
             for (int r = 0; r < 4; ++r) silu(c[r], h[mm][r], d[mm][r]);
             if (EMIT && em.live)
@@ -267,6 +293,7 @@ __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &n
     wide_sync();
     e = ((X.red[0][0][n] + X.red[1][0][n]) + X.red[2][0][n]) + X.red[3][0][n] + L.b5;
     wide_sync();
+    hook(2);
     const float E = fmaf(e, nm.oscale, nm.oshift);
     if (!GRAD) return E;
     if (EMIT) {
@@ -307,16 +334,23 @@ __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &n
 #pragma unroll
     for (int l = 2; l >= 0; --l) {
         float d[2][4];
+        // two interleaved chains, one per output block of the wave (each in
+        // the order of a single chain: kb ascending, head then remainder)
+        f32x4 c2[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+            bf16x8 a2[2];
+#pragma unroll
+            for (int mm = 0; mm < 2; ++mm) a2[mm] = wt_frag(L, l, kb, 2 * v + mm, lane);
+#pragma unroll
+            for (int mm = 0; mm < 2; ++mm) c2[mm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[mm], dpk[kb], c2[mm], 0, 0, 0);
+#pragma unroll
+            for (int mm = 0; mm < 2; ++mm) c2[mm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[mm], dlk[kb], c2[mm], 0, 0, 0);
+        }
 #pragma unroll
         for (int mm = 0; mm < 2; ++mm) {
             const int mt = 2 * v + mm;
-            f32x4 c = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int kb = 0; kb < 4; ++kb) {
-                const bf16x8 a = wt_frag(L, l, kb, mt, lane);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, dpk[kb], c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, dlk[kb], c, 0, 0, 0);
-            }
+            const f32x4 c = c2[mm];
 #pragma unroll
             for (int r = 0; r < 4; ++r) d[mm][r] = c[r] * (float)spo[l][4 * mm + r];
             if (EMIT && em.live)
@@ -612,7 +646,7 @@ __device__ inline void tile_bf16_wide_fm(const LdsBF16 &L, WideX &X, WideT &XT, 
             f32x4 ct = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kb = 0; kb < 4; ++kb) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&L.w[l][16 * mt + n][32 * kb + 8 * g]);
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&L.w[l][16 * mt + n][wcol(16 * mt + n, 32 * kb + 8 * g)]);
                 cz = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kb], cz, 0, 0, 0);
                 ct = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, tact[kb], ct, 0, 0, 0);
             }

@@ -567,13 +567,6 @@ static TrainLayout train_layout(int32_t B) {
     return t;
 }
 
-static int device_cus_train() {
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-        cus = 256;
-    return cus;
-}
 
 // Forward/reverse, weight gradients and Adam over the rows of `a` (a.B1
 // samples; with a.vt set, each sample's primal and tangent rows, and fmpart
@@ -582,7 +575,7 @@ static void train_launch(TrainArgs &a, int precision, float *params, float *adam
                          float lr, float beta1, float beta2, float eps, float *loss, float *grad_out,
                          const float *fmpart, int nfm, hipStream_t st) {
     const int ntiles = (a.B1 + kTile - 1) / kTile;
-    const int cus = device_cus_train();
+    const int cus = device_cu_count();
     if (a.vt) {
         if (precision == RB_PREC_BF16)
             k_train_fb_fm_wide<<<grid_for(ntiles, 1, cus), kWideGroup * kWave, 0, st>>>(a);

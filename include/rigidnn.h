@@ -81,6 +81,8 @@ extern "C" {
 #define RB_FLAG_ROUTE_WORK 16 /* words 16..18: working counters of
                                 rb_pair_descriptors (network, bead, blocks
                                 done); zero between calls                      */
+#define RB_FLAG_WAIT_TIMEOUT 19 /* 1: a kernel's internal wait between waves
+                                gave up (an internal error: results invalid)   */
 #define RB_NFLAGS 20
 
 #define RB_PREC_BF16 0       /* 128x128 layers on BF16 MFMA, FP32 accumulate     */
@@ -130,7 +132,8 @@ const char *rb_last_error(void);
  * (flags_host, RB_NFLAGS int32): RB_ERR_CAPACITY when the last pair-list
  * build overflowed its capacity, RB_ERR_NONFINITE when a non-finite pair
  * force or energy (RB_FLAG_NONFINITE), a fixed-point accumulator overflow
- * (RB_FLAG_FIXOVF) or a quaternion norm drift (RB_FLAG_QDRIFT) was
+ * (RB_FLAG_FIXOVF), a quaternion norm drift (RB_FLAG_QDRIFT) or an
+ * internal wait that gave up (RB_FLAG_WAIT_TIMEOUT) was
  * reported, RB_OK otherwise; rb_last_error() names the condition.  Touches
  * no device state. */
 int rb_flags_check(const int32_t *flags_host);

@@ -76,6 +76,10 @@ extern "C" int rb_flags_check(const int32_t *f) {
         set_error("fixed-point accumulator overflow (a term of 2^28 or a total of 2^30 in magnitude)");
         return RB_ERR_NONFINITE;
     }
+    if (f[RB_FLAG_WAIT_TIMEOUT]) {
+        set_error("an internal wait between the waves of a kernel timed out");
+        return RB_ERR_NONFINITE;
+    }
     if (f[RB_FLAG_QDRIFT]) {
         set_error("quaternion norm drift beyond 1e-10 in %d body updates", f[RB_FLAG_QDRIFT]);
         return RB_ERR_NONFINITE;

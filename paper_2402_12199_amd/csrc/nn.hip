@@ -433,15 +433,13 @@ __device__ inline void forces_epilogue_wide(const NNArgs &a, const EpiLds &e, co
         }
     }
     if (v != 0) return;
+    // each lane adds its terms into the wave's LDS sums (integer adds: the
+    // totals do not depend on their order)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-        long long s = ev[b];
-        s += __shfl_xor(s, 1, kWave);
-        s += __shfl_xor(s, 2, kWave);
-        s += __shfl_xor(s, 4, kWave);
-        s += __shfl_xor(s, 8, kWave);
-        if (n == 0 && (g > 0 || b == 0)) wsum[g == 0 ? 0 : 1 + 3 * (g - 1) + b] += s;
-    }
+    for (int b = 0; b < 3; ++b)
+        if ((g > 0 || b == 0) && ev[b] != 0)
+            atomicAdd(reinterpret_cast<unsigned long long *>(&wsum[g == 0 ? 0 : 1 + 3 * (g - 1) + b]),
+                      (unsigned long long)ev[b]);
 }
 
 // Inputs of the next tile fetched while the current one is computed (forces
@@ -549,6 +547,10 @@ __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
     __shared__ WideX X[kWideGroups];
     __shared__ long long wacc[kWideGroups * kWideGroup][10];
     __shared__ EpiLds EL[MODE == kForces ? kWideGroups : 1][PRE ? 2 : 1];
+    // PRE: the tile groups synchronise on their own (GroupSync) after the
+    // first tile's block-wide barrier
+    __shared__ __attribute__((aligned(16))) int gword[kWideGroups][kWideGroup];
+    __shared__ int gtimeout;
     int64_t count = a.P;
     if (MODE == kForces) {
         const int64_t c = *a.count_dev;
@@ -569,11 +571,18 @@ __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
     stage_bf16<kWideThreads>(L, a.params);
     if (MODE == kForces && lane < 10) wacc[wave][lane] = 0;
     if (PRE && v == 0 && g == 0) put_epi(a, EL[grp][0], t.ein, t.u, t.pid, t.live, n);
+    if (PRE && threadIdx.x < kWideGroups * kWideGroup) gword[threadIdx.x / kWideGroup][threadIdx.x % kWideGroup] = 0;
+    if (PRE && threadIdx.x == 0) gtimeout = 0;
+    int gen = 0;
+    const GroupSync gsync{(lds_int *)&gword[grp][0], v, &gen, (lds_int *)&gtimeout};
     bool bad = false, ovf = false;
     for (int it = 0;; ++it) {
         EpiLds &ecur = EL[MODE == kForces ? grp : 0][PRE ? (it & 1) : 0];
         if (MODE == kForces && !PRE && v == 0 && g == 0) put_epi(a, ecur, t.ein, t.u, t.pid, t.live, n);
-        __syncthreads();
+        if (!PRE || it == 0)
+            __syncthreads();
+        else
+            gsync();
         if (PRE && it > 0) t = tile_from_lds(a, ecur, (base + grp) * kTile + n, count, n);
         const int64_t nbase = base + (int64_t)gridDim.x * kWideGroups;
         NextTile nx;
@@ -585,16 +594,21 @@ __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
         nx.lane = lane;
         nx.start();
         float gu[kIn];
-        const float E = tile_bf16_wide<true, false, NextTile>(L, X[grp], a.nm, t.u, t.seed, gu, v, Emit{}, nx);
+        float E;
+        if constexpr (PRE)
+            E = tile_bf16_wide<true, false, NextTile, GroupSync>(L, X[grp], a.nm, t.u, t.seed, gu, v, Emit{}, nx, gsync);
+        else
+            E = tile_bf16_wide<true, false, NextTile>(L, X[grp], a.nm, t.u, t.seed, gu, v, Emit{}, nx);
         // the group's results are the same in its four waves
         if (MODE == kForces) {
-            if (a.jac || a.cyl) {
+            if (PRE && a.cyl) {
+                // dE/du = J^T dE/ds in every lane from the pair's (d, q) in
+                // LDS (the same arithmetic in each, so the group's lanes agree)
+                if (t.live) cyl_chain_lds(ecur, n, gu);
+            } else if (a.jac || a.cyl) {
                 // dE/du = J^T dE/ds once per pair, shared through LDS
                 if (v == 0 && g == 0 && t.live) {
-                    if (PRE && a.cyl)
-                        cyl_chain_lds(ecur, n, gu);
-                    else
-                        sym_chain(a, t.row, t.pid, gu);
+                    sym_chain(a, t.row, t.pid, gu);
 #pragma unroll
                     for (int k = 0; k < kIn; ++k) X[grp].red[0][1 + k][n] = gu[k];
                 }
@@ -626,6 +640,7 @@ __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
         block_flush_globals<kWideGroups * kWideGroup>(part, a.acc + 6 * (int64_t)a.n, nullptr);
         if (__any(bad) && lane == 0) atomicOr(a.flags + RB_FLAG_NONFINITE, 1);
         report_fixovf(ovf, a.flags);
+        if (PRE && threadIdx.x == 0 && gtimeout) atomicOr(a.flags + RB_FLAG_WAIT_TIMEOUT, 1);
     }
 }
 

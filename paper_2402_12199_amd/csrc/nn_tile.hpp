@@ -215,9 +215,50 @@ struct NoHook {
     __device__ void operator()(int) const {}
 };
 
-template <bool GRAD, bool EMIT = false, class Hook = NoHook>
+// Synchronisation of a tile's four waves: the whole block (BlockSync), or the
+// group alone (GroupSync): each wave of the group writes the number of
+// barriers it has reached into its own LDS word (after its own LDS
+// operations are done) and waits until all four words have reached it; the
+// waits of one group then do not hold the block's other groups.  The wait is
+// bounded: past kGroupSyncSpins polls it records a timeout (an internal
+// error the caller reports) and goes on, so a kernel always ends.
+struct BlockSync {
+    __device__ void operator()() const { wide_sync(); }
+};
+
+constexpr int kGroupSyncSpins = 1 << 16;
+
+typedef __attribute__((address_space(3))) int lds_int;
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) volatile i32x4 lds_vi32x4;
+
+struct GroupSync {
+    lds_int *word;      // the group's four LDS words (16-byte aligned), zero at the first barrier
+    int v;              // this wave's index in the group
+    int *gen;           // barriers this wave has passed (a register of the caller)
+    lds_int *timeout;   // LDS word set on a timeout
+    __device__ void operator()() const {
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): this wave's LDS writes are done
+        const int target = ++*gen;
+        if ((threadIdx.x & (kWave - 1)) == 0) *(volatile lds_int *)(word + v) = target;
+        for (int spin = 0;; ++spin) {
+            const i32x4 w = *(lds_vi32x4 *)word;
+            if (w[0] >= target && w[1] >= target && w[2] >= target && w[3] >= target) break;
+            if (spin >= kGroupSyncSpins) {
+                *timeout = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    }
+};
+
+template <bool GRAD, bool EMIT = false, class Hook = NoHook, class Sync = BlockSync>
 __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &nm, const float u[kIn], float seed,
-                                       float gu[kIn], int v, const Emit &em = Emit{}, const Hook &hook = Hook{}) {
+                                       float gu[kIn], int v, const Emit &em = Emit{}, const Hook &hook = Hook{},
+                                       const Sync &sync = Sync{}) {
     const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, n = lane & 15;
     float un[kIn];
 #pragma unroll
@@ -243,10 +284,10 @@ __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &n
         X.a[v][lane] = pack8(h[0], h[1]);
         if (GRAD) spo[0] = pack8h(d[0], d[1]);
     }
-    wide_sync();
+    sync();
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) act[kb] = X.a[kb][lane];
-    wide_sync();
+    sync();
     hook(1);
     float e = 0.f;
 #pragma unroll
@@ -282,17 +323,17 @@ __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &n
         if (GRAD) spo[l + 1] = pack8h(d[0], d[1]);
         if (l < 2) {
             X.a[v][lane] = pack8(h[0], h[1]);
-            wide_sync();
+            sync();
 #pragma unroll
             for (int kb = 0; kb < 4; ++kb) act[kb] = X.a[kb][lane];
-            wide_sync();
+            sync();
         }
     }
     e = group_sum(e);
     if (g == 0) X.red[v][0][n] = e;
-    wide_sync();
+    sync();
     e = ((X.red[0][0][n] + X.red[1][0][n]) + X.red[2][0][n]) + X.red[3][0][n] + L.b5;
-    wide_sync();
+    sync();
     hook(2);
     const float E = fmaf(e, nm.oscale, nm.oshift);
     if (!GRAD) return E;
@@ -321,13 +362,13 @@ __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &n
         X.dh[v][lane] = hi;
         X.dl[v][lane] = lo;
     }
-    wide_sync();
+    sync();
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) {
         dpk[kb] = X.dh[kb][lane];
         dlk[kb] = X.dl[kb][lane];
     }
-    wide_sync();
+    sync();
     float gk[kIn];
 #pragma unroll
     for (int k = 0; k < kIn; ++k) gk[k] = 0.f;
@@ -370,13 +411,13 @@ __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &n
             split8(d[0], d[1], hi, lo);
             X.dh[v][lane] = hi;
             X.dl[v][lane] = lo;
-            wide_sync();
+            sync();
 #pragma unroll
             for (int kb = 0; kb < 4; ++kb) {
                 dpk[kb] = X.dh[kb][lane];
                 dlk[kb] = X.dl[kb][lane];
             }
-            wide_sync();
+            sync();
         }
     }
 #pragma unroll
@@ -384,11 +425,11 @@ __device__ inline float tile_bf16_wide(const LdsBF16 &L, WideX &X, const Norm &n
         const float s = group_sum(gk[k]);
         if (g == 0) X.red[v][1 + k][n] = s;
     }
-    wide_sync();
+    sync();
 #pragma unroll
     for (int k = 0; k < kIn; ++k)
         gu[k] = (((X.red[0][1 + k][n] + X.red[1][1 + k][n]) + X.red[2][1 + k][n]) + X.red[3][1 + k][n]) * nm.scale[k];
-    wide_sync();
+    sync();
     return E;
 }
 

@@ -72,6 +72,16 @@ __global__ __launch_bounds__(kDescThreads) void k_descriptors(int32_t n, const d
     int count = flags[RB_FLAG_NPAIRS];
     if (count > maxp) count = maxp;
     int32_t *work = flags + RB_FLAG_ROUTE_WORK;
+    // the grid is sized for the capacity: only the blocks with pairs take part
+    // (and take the completion ticket); with no pairs block 0 publishes zeros
+    const int nactive = min((int)gridDim.x, (count + (int)blockDim.x - 1) / (int)blockDim.x);
+    if ((int)blockIdx.x >= nactive) {
+        if (nactive == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+            flags[RB_FLAG_NNN] = 0;
+            flags[RB_FLAG_NBEAD] = 0;
+        }
+        return;
+    }
     const double Ls[3] = {L0, L1, L2};
     for (int base = blockIdx.x * blockDim.x; base < count; base += gridDim.x * blockDim.x) {
         const int p = base + threadIdx.x;
@@ -122,7 +132,7 @@ __global__ __launch_bounds__(kDescThreads) void k_descriptors(int32_t n, const d
     // reads the counters with device-scope atomic loads.  The published counts
     // reach the consumers through the kernel boundary.
     __shared__ bool last;
-    if (threadIdx.x == 0) last = atomicAdd(work + 2, 1) == (int)gridDim.x - 1;
+    if (threadIdx.x == 0) last = atomicAdd(work + 2, 1) == nactive - 1;
     __syncthreads();
     if (last && threadIdx.x == 0) {
         flags[RB_FLAG_NNN] = __hip_atomic_load(work, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -153,7 +163,7 @@ extern "C" int rb_pair_descriptors(int32_t n, const double *x, const double *q, 
     Templates T = {};
     if (ctx) T = ctx->dev.t;
     const float gmax = gap_max > 0.f ? gap_max : 3.0e38f;
-    k_descriptors<<<grid_for(max_pairs, kDescThreads, 4096), kDescThreads, 0, st>>>(n, x, q, box[0], box[1], box[2],
+    k_descriptors<<<grid_for(max_pairs, kDescThreads, 2 * device_cu_count()), kDescThreads, 0, st>>>(n, x, q, box[0], box[1], box[2],
                                                                                   pair_i, pair_j,
                                                                   max_pairs, dm2, dx2, desc, idx_nn, idx_bead, flags,
                                                                   T, type, gap_min, gmax);

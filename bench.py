@@ -60,15 +60,15 @@ GAP_MIN, GAP_MAX, SAMPLE_GAP_MIN = 1.0, 2.5, 0.8
 
 # HBM bytes per launch of the network-forces kernel on the headline workload
 # at its start (31.3k network pairs), from two rocprofv3 counter runs
-# (FETCH_SIZE 7423.94 KiB x 2.000, WRITE_SIZE 16351.16 KiB x 1.000; the
+# (FETCH_SIZE 6754.25 KiB x 2.000, WRITE_SIZE 11744.47 KiB x 1.000; the
 # factors are what the counters read for a 256 MiB copy), see
 # profiles/k_nn_wide_cyl32768_hbm_traffic.txt.  Valid only for the kernel
 # sources they were taken on (hash below); otherwise reported as null.
-NN_TRAFFIC_BYTES = 31947817
+NN_TRAFFIC_BYTES = 25859041
 NN_TRAFFIC_SOURCES = ("paper_2402_12199_amd/csrc/nn.hip", "paper_2402_12199_amd/csrc/nn_tile.hpp",
                       "paper_2402_12199_amd/csrc/nn_common.hpp", "paper_2402_12199_amd/csrc/cyl_form.hpp",
                       "paper_2402_12199_amd/csrc/rb_common.hpp")
-NN_TRAFFIC_HASH = "9ff453285cf5f0ef"
+NN_TRAFFIC_HASH = "dedc6344d24d5d50"
 
 
 def sources_hash(files):

@@ -83,7 +83,10 @@ extern "C" {
                                 done); zero between calls                      */
 #define RB_FLAG_WAIT_TIMEOUT 19 /* 1: a kernel's internal wait between waves
                                 gave up (an internal error: results invalid)   */
-#define RB_NFLAGS 20
+#define RB_FLAG_FB_WORK 20   /* words 20..21: working counters of the bead-sum
+                                phase of rb_nn_pair_forces_routed (pair counter,
+                                finishing ticket); zero between calls           */
+#define RB_NFLAGS 24
 
 #define RB_PREC_BF16 0       /* 128x128 layers on BF16 MFMA, FP32 accumulate     */
 #define RB_PREC_FP32 1       /* every layer in FP32                              */
@@ -435,6 +438,29 @@ int rb_rigid_step_fused_noalloc(const rb_ctx *ctx, int32_t n, double dt, double 
                                 double *energy_virial, const double *x_ref, double half_skin,
                                 const double *x_sref, const double *q_sref, double half_margin,
                                 double *kinetic, int32_t *flags, void *stream);
+
+/* Forces of a routed list in one call: the network forces of the pairs
+ * idx_nn[0 .. *nn_count) as rb_nn_pair_forces (form 0: (d, q) input) or
+ * rb_nn_pair_forces_cyl (form 1: cylinder four-number form), and the bead
+ * double sums of the pairs idx_bead[0 .. *bead_count) as rb_bead_pair_forces
+ * (paper section 2: the bead sum takes the pairs outside the network's
+ * domain), into the same accumulator and flags (flags[NEVAL] counts both).
+ * With BF16 precision and templates whose staging fits the LDS of the
+ * network kernel's weight image (36 x max_beads + total_beads float4 within
+ * 104 976 bytes: up to 176 beads for a single type) one launch does both:
+ * after its network tiles each block of the persistent grid claims
+ * fallback pairs, one per wave and round, from a counter in flags (words
+ * RB_FLAG_FB_WORK..+1, zero between calls, left zero); otherwise the two
+ * kernels run one after the other.  The per-pair arithmetic is that of
+ * the two calls it replaces, and so are the fixed-point sums.  ctx:
+ * templates and bead potential; x (3 x n), q (4 x n), type (n), box[3] as
+ * for the bead sums. */
+int rb_nn_pair_forces_routed(const rb_ctx *ctx, const float *params, const float *norm, int precision, int form,
+                             int32_t n, const double *x, const double *q, const int32_t *type, const double *box,
+                             const int32_t *pair_i, const int32_t *pair_j, const float *desc, int32_t desc_stride,
+                             const int32_t *idx_nn, const int32_t *nn_count_dev, const int32_t *idx_bead,
+                             const int32_t *bead_count_dev, int32_t max_count, float sw_lo, float sw_hi,
+                             int64_t *acc, int32_t *flags, void *stream);
 
 /* ---- training step (energy loss, Adam) ------------------------------------
  * Paper section 2: the network g_NN_U is fitted by regression to pair

@@ -44,6 +44,8 @@ SIGNATURES = {
     "rb_cube_sym_descriptors": (C.c_int, [I64, P, I64, P, P, I64, P, P, P]),
     "rb_cyl_sym_descriptors": (C.c_int, [I64, P, I64, P, P, I64, P, P, P]),
     "rb_nn_pair_forces_cyl": (C.c_int, [P, FP, C.c_int, I32, P, P, P, P, I32, P, P, I32, F32, F32, P, P, P]),
+    "rb_nn_pair_forces_routed": (C.c_int, [P, P, FP, C.c_int, C.c_int, I32, P, P, P, P, P, P, P, I32, P, P, P, P,
+                                           I32, F32, F32, P, P, P]),
     "rb_nn_pair_grad_sym": (C.c_int, [P, FP, C.c_int, I64, P, P, P, P, P, P, P, P]),
     "rb_nn_pair_forces_sym": (C.c_int, [P, FP, C.c_int, I32, P, P, P, P, I32, P, P, P, P, I32, F32, F32, P, P,
                                         P]),

@@ -17,9 +17,9 @@ import torch
 from ._lib import check, lib
 
 RB_FLAG_REBUILD, RB_FLAG_NPAIRS, RB_FLAG_OVERFLOW, RB_FLAG_NREBUILDS = 0, 1, 2, 3
-RB_FLAG_NBEAD, RB_FLAG_NNN, RB_FLAG_NONFINITE, RB_FLAG_NEVAL, RB_FLAG_NTESTS, RB_NFLAGS = 4, 5, 6, 7, 8, 20
+RB_FLAG_NBEAD, RB_FLAG_NNN, RB_FLAG_NONFINITE, RB_FLAG_NEVAL, RB_FLAG_NTESTS, RB_NFLAGS = 4, 5, 6, 7, 8, 24
 RB_FLAG_NSCREEN, RB_FLAG_RESCREEN, RB_FLAG_NRESCREENS = 10, 11, 12
-RB_FLAG_FIXOVF, RB_FLAG_QDRIFT, RB_FLAG_WAIT_TIMEOUT = 13, 14, 19
+RB_FLAG_FIXOVF, RB_FLAG_QDRIFT, RB_FLAG_WAIT_TIMEOUT, RB_FLAG_FB_WORK = 13, 14, 19, 20
 RB_OK, RB_ERR_INVALID_ARG, RB_ERR_CAPACITY, RB_ERR_HIP, RB_ERR_UNSUPPORTED, RB_ERR_NONFINITE = 0, -1, -2, -3, -4, -5
 RB_PREC_BF16, RB_PREC_FP32 = 0, 1
 RB_BUILD_ALWAYS, RB_BUILD_IF_FLAGGED = 0, 1
@@ -301,6 +301,27 @@ def rb_nn_pair_forces_cyl(params, norm, precision, q, pair_i, pair_j, desc, idx,
                                       float(sw_lo), float(sw_hi), _ptr(acc, torch.int64, (acc_len(n),), "acc"),
                                       _ptr(flags, torch.int32, (RB_NFLAGS,), "flags"), _stream()),
           "rb_nn_pair_forces_cyl")
+
+
+def rb_nn_pair_forces_routed(ctx: Ctx, params, norm, precision, form: int, x, q, types, box, pair_i, pair_j, desc,
+                             idx_nn, nn_count_dev, idx_bead, bead_count_dev, max_count, sw_lo, sw_hi, acc, flags):
+    n = q.shape[1]
+    _, npn = _norm(norm)
+    boxa, bp = _box(box)
+    check(lib().rb_nn_pair_forces_routed(ctx.handle, _ptr(params, torch.float32, (RB_MLP_NPARAMS,), "params"), npn,
+                                         precision, int(form), n, _ptr(x, torch.float64, (3, n), "x"),
+                                         _ptr(q, torch.float64, (4, n), "q"), _ptr(types, torch.int32, (n,), "type"),
+                                         bp,
+                                         _ptr(pair_i, torch.int32, name="pair_i"),
+                                         _ptr(pair_j, torch.int32, name="pair_j"),
+                                         _ptr(desc, torch.float32, name="desc"), desc.shape[1],
+                                         _ptr(idx_nn, torch.int32, name="idx_nn"),
+                                         _ptr(nn_count_dev, torch.int32, name="nn_count_dev"),
+                                         _ptr(idx_bead, torch.int32, name="idx_bead"),
+                                         _ptr(bead_count_dev, torch.int32, name="bead_count_dev"), int(max_count),
+                                         float(sw_lo), float(sw_hi), _ptr(acc, torch.int64, (acc_len(n),), "acc"),
+                                         _ptr(flags, torch.int32, (RB_NFLAGS,), "flags"), _stream()),
+          "rb_nn_pair_forces_routed")
 
 
 def rb_nn_pair_grad_sym(params, norm, precision: int, desc, sym, jac, gE=None, energy=None, dE_ddesc=None,

@@ -13,6 +13,7 @@
 // FP32 path: the same tiling on v_mfma_f32_16x16x4_f32, weights read from
 // global memory (they stay in the caches), activations and derivatives in
 // FP32.
+#include "bead_pair.hpp"
 #include "cyl_form.hpp"
 #include "nn_tile.hpp"
 
@@ -48,6 +49,17 @@ struct NNArgs {
     // cylinder pairs: the network sees the four-number form of desc's
     // (d, q), computed here together with its Jacobian (no sym/jac arrays)
     int cyl;
+    // forces mode with the bead-sum fallback in the same launch: after its
+    // network tiles each wave takes pairs idx_bead[0 .. *bead_count) one at a
+    // time and adds their bead double sums (null idx_bead: no fallback)
+    const int32_t *idx_bead;
+    const int32_t *bead_count;
+    const double *x;
+    const int32_t *type;
+    Box box;
+    Templates T;
+    LJ lj;
+    int bead_stride;    // float4 per wave staging array
 };
 
 // Whether the network's input differs from the pair's (d, q).
@@ -540,9 +552,19 @@ __device__ inline void cyl_chain_lds(const EpiLds &e, int n, float gu[kIn]) {
 
 // PRE (forces with (d, q) or cylinder inputs): the next tile's inputs are
 // fetched during the current one into the group's other epilogue buffer.
-template <int MODE, bool PRE = false>
+// FB (PRE only; 1: Lennard-Jones, 2: half-power half-cosine beads): the
+// launch also adds the bead double sums of the fallback pairs.  Every block
+// of the grid takes part: after the block's network tiles (if any) the
+// weight image's LDS holds the bead templates and the waves' staging arrays,
+// and the block claims the fallback pairs a round of one pair per wave at a
+// time from a counter in flags (RB_FLAG_FB_WORK; FB_WORK + 1 is the
+// finishing ticket; both zero between launches), so that blocks with fewer
+// network tiles take more pairs.  One claim per block and round keeps the
+// counter's atomics few (one per wave serialised the grid on that address).
+template <int MODE, bool PRE = false, int FB = 0>
 __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
     static_assert(!PRE || MODE == kForces, "prefetching is a forces-mode form");
+    static_assert(FB == 0 || PRE, "the bead fallback runs in the prefetching forces form");
     __shared__ LdsBF16 L;
     __shared__ WideX X[kWideGroups];
     __shared__ long long wacc[kWideGroups * kWideGroup][10];
@@ -552,92 +574,146 @@ __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
     __shared__ __attribute__((aligned(16))) int gword[kWideGroups][kWideGroup];
     __shared__ int gtimeout;
     int64_t count = a.P;
+    int nbead = 0;
     if (MODE == kForces) {
         const int64_t c = *a.count_dev;
         count = c < a.P ? c : a.P;
-        if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.flags + RB_FLAG_NEVAL, (int)count);
+        if (FB) {
+            nbead = *a.bead_count;
+            if (nbead > a.P) nbead = (int)a.P;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.flags + RB_FLAG_NEVAL, (int)count + nbead);
     }
     const int64_t ntiles = (count + kTile - 1) / kTile;
-    // the grid is sized for the capacity; blocks without a tile leave before
-    // staging the weights
-    if ((int64_t)blockIdx.x * kWideGroups >= ntiles) return;
+    // the grid is sized for the capacity; without a fallback, blocks without
+    // a tile leave before staging the weights
+    const bool net = (int64_t)blockIdx.x * kWideGroups < ntiles;
+    if (!FB && !net) return;
     const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, n = lane & 15;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int grp = wave / kWideGroup, v = wave % kWideGroup;
-    // the first tile's inputs are requested before the weights are staged,
-    // so that their latency overlaps the staging
-    int64_t base = (int64_t)blockIdx.x * kWideGroups;
-    TileIn t = tile_in<MODE>(a, (base + grp) * kTile + n, count, g == 0 && v == 0);
-    stage_bf16<kWideThreads>(L, a.params);
     if (MODE == kForces && lane < 10) wacc[wave][lane] = 0;
-    if (PRE && v == 0 && g == 0) put_epi(a, EL[grp][0], t.ein, t.u, t.pid, t.live, n);
-    if (PRE && threadIdx.x < kWideGroups * kWideGroup) gword[threadIdx.x / kWideGroup][threadIdx.x % kWideGroup] = 0;
     if (PRE && threadIdx.x == 0) gtimeout = 0;
-    int gen = 0;
-    const GroupSync gsync{(lds_int *)&gword[grp][0], v, &gen, (lds_int *)&gtimeout};
     bool bad = false, ovf = false;
-    for (int it = 0;; ++it) {
-        EpiLds &ecur = EL[MODE == kForces ? grp : 0][PRE ? (it & 1) : 0];
-        if (MODE == kForces && !PRE && v == 0 && g == 0) put_epi(a, ecur, t.ein, t.u, t.pid, t.live, n);
-        if (!PRE || it == 0)
-            __syncthreads();
-        else
-            gsync();
-        if (PRE && it > 0) t = tile_from_lds(a, ecur, (base + grp) * kTile + n, count, n);
-        const int64_t nbase = base + (int64_t)gridDim.x * kWideGroups;
-        NextTile nx;
-        nx.a = &a;
-        nx.e = &EL[MODE == kForces ? grp : 0][PRE ? ((it + 1) & 1) : 0];
-        nx.row0 = (nbase + grp) * kTile;
-        nx.count = count;
-        nx.active = PRE && v == 1 && nbase < ntiles;
-        nx.lane = lane;
-        nx.start();
-        float gu[kIn];
-        float E;
-        if constexpr (PRE)
-            E = tile_bf16_wide<true, false, NextTile, GroupSync>(L, X[grp], a.nm, t.u, t.seed, gu, v, Emit{}, nx, gsync);
-        else
-            E = tile_bf16_wide<true, false, NextTile>(L, X[grp], a.nm, t.u, t.seed, gu, v, Emit{}, nx);
-        // the group's results are the same in its four waves
-        if (MODE == kForces) {
-            if (PRE && a.cyl) {
-                // dE/du = J^T dE/ds in every lane from the pair's (d, q) in
-                // LDS (the same arithmetic in each, so the group's lanes agree)
-                if (t.live) cyl_chain_lds(ecur, n, gu);
-            } else if (a.jac || a.cyl) {
-                // dE/du = J^T dE/ds once per pair, shared through LDS
-                if (v == 0 && g == 0 && t.live) {
-                    sym_chain(a, t.row, t.pid, gu);
-#pragma unroll
-                    for (int k = 0; k < kIn; ++k) X[grp].red[0][1 + k][n] = gu[k];
-                }
+    if (net) {
+        // the first tile's inputs are requested before the weights are
+        // staged, so that their latency overlaps the staging
+        int64_t base = (int64_t)blockIdx.x * kWideGroups;
+        TileIn t = tile_in<MODE>(a, (base + grp) * kTile + n, count, g == 0 && v == 0);
+        stage_bf16<kWideThreads>(L, a.params);
+        if (PRE && v == 0 && g == 0) put_epi(a, EL[grp][0], t.ein, t.u, t.pid, t.live, n);
+        if (PRE && threadIdx.x < kWideGroups * kWideGroup)
+            gword[threadIdx.x / kWideGroup][threadIdx.x % kWideGroup] = 0;
+        int gen = 0;
+        const GroupSync gsync{(lds_int *)&gword[grp][0], v, &gen, (lds_int *)&gtimeout};
+        for (int it = 0;; ++it) {
+            EpiLds &ecur = EL[MODE == kForces ? grp : 0][PRE ? (it & 1) : 0];
+            if (MODE == kForces && !PRE && v == 0 && g == 0) put_epi(a, ecur, t.ein, t.u, t.pid, t.live, n);
+            if (!PRE || it == 0)
                 __syncthreads();
+            else
+                gsync();
+            if (PRE && it > 0) t = tile_from_lds(a, ecur, (base + grp) * kTile + n, count, n);
+            const int64_t nbase = base + (int64_t)gridDim.x * kWideGroups;
+            NextTile nx;
+            nx.a = &a;
+            nx.e = &EL[MODE == kForces ? grp : 0][PRE ? ((it + 1) & 1) : 0];
+            nx.row0 = (nbase + grp) * kTile;
+            nx.count = count;
+            nx.active = PRE && v == 1 && nbase < ntiles;
+            nx.lane = lane;
+            nx.start();
+            float gu[kIn];
+            float E;
+            if constexpr (PRE)
+                E = tile_bf16_wide<true, false, NextTile, GroupSync>(L, X[grp], a.nm, t.u, t.seed, gu, v, Emit{}, nx,
+                                                                     gsync);
+            else
+                E = tile_bf16_wide<true, false, NextTile>(L, X[grp], a.nm, t.u, t.seed, gu, v, Emit{}, nx);
+            // the group's results are the same in its four waves
+            if (MODE == kForces) {
+                if (PRE && a.cyl) {
+                    // dE/du = J^T dE/ds in every lane from the pair's (d, q) in
+                    // LDS (the same arithmetic in each, so the group's lanes agree)
+                    if (t.live) cyl_chain_lds(ecur, n, gu);
+                } else if (a.jac || a.cyl) {
+                    // dE/du = J^T dE/ds once per pair, shared through LDS
+                    if (v == 0 && g == 0 && t.live) {
+                        sym_chain(a, t.row, t.pid, gu);
 #pragma unroll
-                for (int k = 0; k < kIn; ++k) gu[k] = X[grp].red[0][1 + k][n];
+                        for (int k = 0; k < kIn; ++k) X[grp].red[0][1 + k][n] = gu[k];
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int k = 0; k < kIn; ++k) gu[k] = X[grp].red[0][1 + k][n];
+                }
+                forces_epilogue_wide(a, ecur, gu, E, t.live, v, g, n, wacc[wave], bad, ovf);
+            } else if (v == 0 && t.live && g == 0) {
+                sym_chain(a, t.row, t.pid, gu);
+                store_grad(a, t, gu, E);
             }
-            forces_epilogue_wide(a, ecur, gu, E, t.live, v, g, n, wacc[wave], bad, ovf);
-        } else if (v == 0 && t.live && g == 0) {
-            sym_chain(a, t.row, t.pid, gu);
-            store_grad(a, t, gu, E);
+            // the fetching wave's loads into LDS have landed before the next
+            // tile's first barrier
+            if (nx.active) wait_vmem();
+            base = nbase;
+            if (base >= ntiles) break;
+            if (!PRE) {
+                t = tile_in<MODE>(a, (base + grp) * kTile + n, count, g == 0 && v == 0);
+                // the previous tile's epilogue has read its inputs from LDS
+                __syncthreads();
+            }
         }
-        // the fetching wave's loads into LDS have landed before the next
-        // tile's first barrier
-        if (nx.active) wait_vmem();
-        base = nbase;
-        if (base >= ntiles) break;
-        if (!PRE) {
-            t = tile_in<MODE>(a, (base + grp) * kTile + n, count, g == 0 && v == 0);
-            // the previous tile's epilogue has read its inputs from LDS
+    }
+    long long ntests = 0;
+    if constexpr (FB != 0) {
+        constexpr int POT = FB == 1 ? kPotLJ : kPotHPHC;
+        constexpr int kWaves = kWideThreads / kWave;
+        __syncthreads();   // every group of the block is done with the weight image
+        float4 *bl = reinterpret_cast<float4 *>(&L);
+        float4 *tb = bl + (size_t)kWaves * 3 * a.bead_stride;
+        for (int k = threadIdx.x; k < a.T.total; k += blockDim.x) tb[k] = a.T.beads[k];
+        __syncthreads();
+        WaveLds WL = wave_lds(bl, wave, a.bead_stride);
+        const float rcm = sqrtf(a.lj.rc2) + kCullMargin, cut2 = rcm * rcm;
+        // rounds of one pair per wave: thread 0 claims the block's next
+        // kWaves pairs from the counter while the current ones are summed
+        __shared__ int fb_base[2];
+        int32_t *work = a.flags + RB_FLAG_FB_WORK;
+        if (threadIdx.x == 0) fb_base[0] = atomicAdd(work, kWaves);
+        __syncthreads();
+        for (int r = 0;; ++r) {
+            const int base = fb_base[r & 1];
+            if (base >= nbead) break;
+            int next = 0;
+            if (threadIdx.x == 0) next = atomicAdd(work, kWaves);
+            const int k = base + wave;
+            if (k < nbead) {
+                const int pid = a.idx_bead[k];
+                const int i = a.pi[pid], j = a.pj[pid];
+                const int ti = a.type[i], tj = a.type[j];
+                double dl[3], d[3], qr[4], qa[4], Ri[9], R[9];
+                pair_frame(a.n, a.x, a.q, a.box, i, j, dl, d, qr, qa, Ri);
+                quat_to_rot<double>(qr[0], qr[1], qr[2], qr[3], R);
+                md_pair<POT>(a.T, a.lj, tb, WL, lane, cut2, a.n, i, j, ti, tj, dl, d, R, Ri, a.acc, wacc[wave],
+                             ntests, bad, ovf);
+            }
+            // the slot written here was last read before the previous barrier
+            if (threadIdx.x == 0) fb_base[(r + 1) & 1] = next;
             __syncthreads();
+        }
+        // every claim of every block has returned before its ticket; the last
+        // block clears the counter and the ticket for the next launch
+        if (threadIdx.x == 0 && atomicAdd(work + 1, 1) == (int)gridDim.x - 1) {
+            work[0] = 0;
+            work[1] = 0;
         }
     }
     if (MODE == kForces) {
         long long part[11];
 #pragma unroll
         for (int k = 0; k < 10; ++k) part[k] = wacc[wave][k];
-        part[10] = 0;
-        block_flush_globals<kWideGroups * kWideGroup>(part, a.acc + 6 * (int64_t)a.n, nullptr);
+        part[10] = ntests;
+        block_flush_globals<kWideGroups * kWideGroup>(part, a.acc + 6 * (int64_t)a.n, FB ? a.flags : nullptr);
         if (__any(bad) && lane == 0) atomicOr(a.flags + RB_FLAG_NONFINITE, 1);
         report_fixovf(ovf, a.flags);
         if (PRE && threadIdx.x == 0 && gtimeout) atomicOr(a.flags + RB_FLAG_WAIT_TIMEOUT, 1);
@@ -743,6 +819,67 @@ extern "C" int rb_nn_pair_forces(const float *params, const float *norm, int pre
     a.acc = acc;
     a.flags = flags;
     return launch<kForces>(a, precision, max_count, (hipStream_t)stream);
+}
+
+extern "C" int rb_nn_pair_forces_routed(const rb_ctx *ctx, const float *params, const float *norm, int precision,
+                                        int form, int32_t n, const double *x, const double *q, const int32_t *type,
+                                        const double *box, const int32_t *pair_i, const int32_t *pair_j,
+                                        const float *desc, int32_t desc_stride, const int32_t *idx_nn,
+                                        const int32_t *nn_count_dev, const int32_t *idx_bead,
+                                        const int32_t *bead_count_dev, int32_t max_count, float sw_lo, float sw_hi,
+                                        int64_t *acc, int32_t *flags, void *stream) {
+    RB_REQUIRE(ctx && params && norm && x && q && type && box && pair_i && pair_j && desc && nn_count_dev &&
+                   idx_bead && bead_count_dev && acc && flags,
+               "rb_nn_pair_forces_routed: null argument");
+    RB_REQUIRE(precision == RB_PREC_BF16 || precision == RB_PREC_FP32, "rb_nn_pair_forces_routed: bad precision");
+    RB_REQUIRE(form == 0 || form == 1, "rb_nn_pair_forces_routed: form must be 0 ((d, q)) or 1 (cylinder)");
+    RB_REQUIRE(n > 0 && max_count >= 0 && desc_stride >= max_count, "rb_nn_pair_forces_routed: bad sizes");
+    RB_REQUIRE(box[0] > 0 && box[1] > 0 && box[2] > 0, "rb_nn_pair_forces_routed: box must be > 0");
+    if (max_count == 0) return RB_OK;
+    hipStream_t st = (hipStream_t)stream;
+    NNArgs a = {};
+    a.params = params;
+    a.nm = norm_from_host(norm);
+    a.P = max_count;
+    a.desc = desc;
+    a.stride = desc_stride;
+    a.idx = idx_nn;
+    a.count_dev = nn_count_dev;
+    a.q = q;
+    a.n = n;
+    a.pi = pair_i;
+    a.pj = pair_j;
+    a.sw_lo = sw_lo;
+    a.sw_hi = sw_hi;
+    a.acc = acc;
+    a.flags = flags;
+    a.cyl = form;
+    const int stride = (ctx->max_beads + 3) & ~3;
+    const size_t need = sizeof(float4) * (3 * (size_t)stride * (kWideThreads / kWave) + (size_t)ctx->total_beads);
+    if (precision != RB_PREC_BF16 || need > sizeof(LdsBF16)) {
+        const int rc = launch<kForces>(a, precision, max_count, st);
+        if (rc != RB_OK) return rc;
+        return rb_bead_pair_forces(ctx, n, x, q, type, box, pair_i, pair_j, idx_bead, bead_count_dev, max_count, acc,
+                                   flags, stream);
+    }
+    a.idx_bead = idx_bead;
+    a.bead_count = bead_count_dev;
+    a.x = x;
+    a.type = type;
+    for (int k = 0; k < 3; ++k) {
+        a.box.L[k] = box[k];
+        a.box.inv[k] = 1.0 / box[k];
+    }
+    a.T = ctx->dev.t;
+    a.lj = ctx->dev.lj;
+    a.bead_stride = stride;
+    const int64_t tiles = ((int64_t)max_count + kTile - 1) / kTile;
+    const int grid = grid_for(tiles, kWideGroups, device_cu_count());
+    if (ctx->dev.lj.kind == kPotHPHC)
+        k_nn_wide<kForces, true, 2><<<grid, kWideThreads, 0, st>>>(a);
+    else
+        k_nn_wide<kForces, true, 1><<<grid, kWideThreads, 0, st>>>(a);
+    return hip_check(hipGetLastError(), "rb_nn_pair_forces_routed launch");
 }
 
 extern "C" int rb_nn_pair_grad_sym(const float *params, const float *norm, int precision, int64_t n_pairs,

@@ -152,20 +152,20 @@ class RigidSystem:
         bead sum of the fallback pairs, all into the accumulator."""
         m = self.nn
         self.route(m.d_min, m.sw_hi if m.sw_hi > m.sw_lo else 0.0, m.gap_min, m.gap_max)
-        if m.form == "cyl":
-            abi.rb_nn_pair_forces_cyl(m.params, m.norm, m.precision, self.q, self.pair_i, self.pair_j, self.desc,
-                                      self.idx_nn, self.flags[abi.RB_FLAG_NNN:], self.max_pairs, m.sw_lo, m.sw_hi,
-                                      self.acc, self.flags)
-        elif m.form == "cube":
+        if m.form in ("cyl", "dq"):
+            # network pairs and bead-sum pairs in one call (one launch in BF16)
+            abi.rb_nn_pair_forces_routed(self.ctx, m.params, m.norm, m.precision, 1 if m.form == "cyl" else 0, self.x,
+                                         self.q, self.types, self.box, self.pair_i, self.pair_j, self.desc,
+                                         self.idx_nn, self.flags[abi.RB_FLAG_NNN:], self.idx_bead,
+                                         self.flags[abi.RB_FLAG_NBEAD:], self.max_pairs, m.sw_lo, m.sw_hi, self.acc,
+                                         self.flags)
+            return
+        if m.form == "cube":
             abi.rb_cube_sym_descriptors(self.desc, self.sym, self.jac, self.idx_nn, self.flags[abi.RB_FLAG_NNN:],
                                         self.max_pairs)
             abi.rb_nn_pair_forces_sym(m.params, m.norm, m.precision, self.q, self.pair_i, self.pair_j, self.desc,
                                       self.sym, self.jac, self.idx_nn, self.flags[abi.RB_FLAG_NNN:], self.max_pairs,
                                       m.sw_lo, m.sw_hi, self.acc, self.flags)
-        else:
-            abi.rb_nn_pair_forces(m.params, m.norm, m.precision, self.q, self.pair_i, self.pair_j, self.desc,
-                                  self.idx_nn, self.flags[abi.RB_FLAG_NNN:], self.max_pairs, m.sw_lo, m.sw_hi,
-                                  self.acc, self.flags)
         abi.rb_bead_pair_forces(self.ctx, self.x, self.q, self.types, self.box, self.pair_i, self.pair_j,
                                 self.idx_bead, self.flags[abi.RB_FLAG_NBEAD:], self.max_pairs, self.acc, self.flags)
 

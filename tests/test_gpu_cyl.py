@@ -279,3 +279,57 @@ def test_cylinder_dynamics_forces_match_oracle(abi, cyl_workload, prec):
     assert sysm.energy() == pytest.approx(E, rel=max(etol, 1e-5))
     assert_close(sysm.force.cpu().numpy().T, F, max(gtol, 1e-4), "force")
     assert_close(sysm.torque.cpu().numpy().T, T, max(gtol, 1e-4), "torque")
+
+
+@pytest.mark.parametrize("case", ["both", "no_network_pairs", "no_bead_pairs"])
+def test_routed_forces_in_one_launch_equal_the_two_calls(abi, cyl_workload, case):
+    # rb_nn_pair_forces_routed (BF16: the network tiles, then the bead sums of
+    # the fallback pairs in the same launch) against rb_nn_pair_forces_cyl
+    # followed by rb_bead_pair_forces on the same routing, with empty lists
+    # as edge cases: the same per-pair arithmetic, so the same fixed-point
+    # sums, forces, torques, energy and virial
+    from paper_2402_12199_amd.md import NNModel, RigidSystem
+    cfg, st, pairs = cyl_workload
+    b = cfg.body
+    params, norm = _params(5), _norm()
+    sysm = RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"], cfg.box,
+                       cfg.r_list, cfg.skin)
+    m = NNModel(params=_dev(params), norm=norm.as_array(), precision=abi.RB_PREC_BF16, d_min=cfg.d_min,
+                sw_lo=cfg.d_cut - 1.0, sw_hi=cfg.d_cut, form="cyl", gap_min=1.0, gap_max=2.5)
+    sysm.set_nn(m)
+    sysm.build_pairs(always=True)
+    sysm.route(m.d_min, m.sw_hi, m.gap_min, m.gap_max)
+    f = sysm.check_capacity()
+    assert f[abi.RB_FLAG_NNN] > 12288 and f[abi.RB_FLAG_NBEAD] > 500   # several network rounds, a real fallback
+    zero = torch.zeros(1, dtype=torch.int32, device="cuda")
+    nn_cnt = zero if case == "no_network_pairs" else sysm.flags[abi.RB_FLAG_NNN:]
+    bd_cnt = zero if case == "no_bead_pairs" else sysm.flags[abi.RB_FLAG_NBEAD:]
+    results = []
+    for one_launch in (False, True):
+        flags = sysm.flags.clone()
+        abi.rb_accum_zero(sysm.n, sysm.acc)
+        if one_launch:
+            abi.rb_nn_pair_forces_routed(sysm.ctx, m.params, m.norm, m.precision, 1, sysm.x, sysm.q, sysm.types,
+                                         sysm.box, sysm.pair_i, sysm.pair_j, sysm.desc, sysm.idx_nn, nn_cnt,
+                                         sysm.idx_bead, bd_cnt, sysm.max_pairs, m.sw_lo, m.sw_hi, sysm.acc, flags)
+        else:
+            abi.rb_nn_pair_forces_cyl(m.params, m.norm, m.precision, sysm.q, sysm.pair_i, sysm.pair_j, sysm.desc,
+                                      sysm.idx_nn, nn_cnt, sysm.max_pairs, m.sw_lo, m.sw_hi, sysm.acc, flags)
+            abi.rb_bead_pair_forces(sysm.ctx, sysm.x, sysm.q, sysm.types, sysm.box, sysm.pair_i, sysm.pair_j,
+                                    sysm.idx_bead, bd_cnt, sysm.max_pairs, sysm.acc, flags)
+        force = torch.zeros_like(sysm.force)
+        torque = torch.zeros_like(sysm.torque)
+        ev = torch.zeros_like(sysm.ev)
+        abi.rb_accum_finalize(sysm.n, sysm.acc, force, torque, ev, flags)
+        torch.cuda.synchronize()
+        fh = flags.cpu().numpy()
+        assert abi.rb_flags_check(fh)[0] == abi.RB_OK
+        assert (fh[abi.RB_FLAG_FB_WORK:abi.RB_FLAG_FB_WORK + 2] == 0).all()   # working words left zero
+        results.append((force.cpu().numpy(), torque.cpu().numpy(), ev.cpu().numpy(), int(fh[abi.RB_FLAG_NEVAL])))
+    (f0, t0, e0, n0), (f1, t1, e1, n1) = results
+    np.testing.assert_array_equal(f1, f0)
+    np.testing.assert_array_equal(t1, t0)
+    np.testing.assert_array_equal(e1, e0)
+    assert n1 == n0
+    if case != "both":
+        assert np.abs(f0).max() > 0

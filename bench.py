@@ -58,17 +58,17 @@ GRAPH_STEPS = 10               # MD steps recorded per HIP graph
 # distance, sigma units) and that of the pairs its training data is drawn from.
 GAP_MIN, GAP_MAX, SAMPLE_GAP_MIN = 1.0, 2.5, 0.8
 
-# HBM bytes per launch of the network-forces kernel on the headline workload
-# at its start (31.3k network pairs), from two rocprofv3 counter runs
-# (FETCH_SIZE 6754.25 KiB x 2.000, WRITE_SIZE 11744.47 KiB x 1.000; the
-# factors are what the counters read for a 256 MiB copy), see
-# profiles/k_nn_wide_cyl32768_hbm_traffic.txt.  Valid only for the kernel
-# sources they were taken on (hash below); otherwise reported as null.
-NN_TRAFFIC_BYTES = 25859041
+# HBM bytes per launch of the network path's forces kernel on the headline
+# workload at its start (31.3k network pairs, 2.5k fallback pairs), from two
+# rocprofv3 counter runs (FETCH_SIZE 8405.75 KiB x 2.000, WRITE_SIZE
+# 12726.69 KiB x 1.000; the factors are what the counters read for a 256 MiB
+# copy), see profiles/k_nn_wide_cyl32768_hbm_traffic.txt.  Valid only for the
+# kernel sources they were taken on (hash below); otherwise reported as null.
+NN_TRAFFIC_BYTES = 30247107
 NN_TRAFFIC_SOURCES = ("paper_2402_12199_amd/csrc/nn.hip", "paper_2402_12199_amd/csrc/nn_tile.hpp",
                       "paper_2402_12199_amd/csrc/nn_common.hpp", "paper_2402_12199_amd/csrc/cyl_form.hpp",
-                      "paper_2402_12199_amd/csrc/rb_common.hpp")
-NN_TRAFFIC_HASH = "dedc6344d24d5d50"
+                      "paper_2402_12199_amd/csrc/rb_common.hpp", "paper_2402_12199_amd/csrc/bead_pair.hpp")
+NN_TRAFFIC_HASH = "5dcb2f8c388d10da"
 
 
 def sources_hash(files):
@@ -191,25 +191,40 @@ def ntests(sysm, abi):
 
 
 def nn_forces_launch(sysm, abi):
+    """The network path's pair forces of one step: one launch that evaluates
+    the network pairs and then the bead sums of the fallback pairs."""
     m = sysm.nn
-    return lambda: abi.rb_nn_pair_forces_cyl(m.params, m.norm, m.precision, sysm.q, sysm.pair_i, sysm.pair_j,
-                                             sysm.desc, sysm.idx_nn, sysm.flags[abi.RB_FLAG_NNN:], sysm.max_pairs,
-                                             m.sw_lo, m.sw_hi, sysm.acc, sysm.flags)
+    return lambda: abi.rb_nn_pair_forces_routed(sysm.ctx, m.params, m.norm, m.precision, 1, sysm.x, sysm.q,
+                                                sysm.types, sysm.box, sysm.pair_i, sysm.pair_j, sysm.desc,
+                                                sysm.idx_nn, sysm.flags[abi.RB_FLAG_NNN:], sysm.idx_bead,
+                                                sysm.flags[abi.RB_FLAG_NBEAD:], sysm.max_pairs, m.sw_lo, m.sw_hi,
+                                                sysm.acc, sysm.flags)
 
 
 def nn_forces_roofline(sysm, torch, abi, reps=20):
     """The network path's dominant kernel alone on the current routing: mean
-    duration over `reps` launches, FLOP per launch = 2 x 100352 per network
-    pair (forward and input-gradient pass)."""
+    duration over `reps` launches.  achieved = the network's FLOP per launch
+    (2 x 100352 per network pair: forward and input-gradient pass) over that
+    duration, against the dense BF16 MFMA peak; the bead sums of the fallback
+    pairs in the same launch are FP32 vector work, reported beside it (tests
+    x 8 FLOP against the FP32 vector peak) and in frac_combined, the sum of
+    both parts' times at their peaks over the launch's duration."""
     launch = nn_forces_launch(sysm, abi)
+    t0 = ntests(sysm, abi)
     ms = time_launches(launch, reps, torch)
+    tests = (ntests(sysm, abi) - t0) / (reps + 1)    # one eager call + one replay of reps
     abi.rb_accum_zero(sysm.n, sysm.acc)
-    nnn = int(sysm.flags_host()[abi.RB_FLAG_NNN])
+    f = sysm.flags_host()
+    nnn, nbead = int(f[abi.RB_FLAG_NNN]), int(f[abi.RB_FLAG_NBEAD])
     flop = 2.0 * NN_FLOP_PER_ROW * nnn
     r = roof(ms, flop, BF16_MFMA_PEAK, "TFLOP/s", "mfma",
              f"2 x {NN_FLOP_PER_ROW} FLOP per network pair (forward + input-gradient pass) x {nnn} pairs "
-             f"per launch")
+             f"per launch; the same launch's bead sums of {nbead} fallback pairs are not counted here")
+    bead_flop = tests * FLOP_PER_TEST
     r["pairs_per_launch"] = nnn
+    r["fallback"] = {"pairs_per_launch": nbead, "bead_tests_per_launch": tests, "flop": bead_flop,
+                     "peak_tflops": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s"}
+    r["frac_combined"] = (flop / BF16_MFMA_PEAK + bead_flop / FP32_VECTOR_PEAK) / (ms * 1e-3)
     return r
 
 
@@ -231,6 +246,14 @@ def path_kernels(sysn, sysb, cfg, torch, abi):
                                            f"types) + 32 B written per routed pair ({npairs} listed, {nnn} "
                                            f"network, {nbead} bead)")
     out["pair_descriptors_routing"]["note"] = "bound by the shells' arithmetic, not by HBM"
+    ms = time_launches(lambda: abi.rb_nn_pair_forces_cyl(m.params, m.norm, m.precision, sysn.q, sysn.pair_i,
+                                                         sysn.pair_j, sysn.desc, sysn.idx_nn,
+                                                         sysn.flags[abi.RB_FLAG_NNN:], sysn.max_pairs, m.sw_lo,
+                                                         m.sw_hi, sysn.acc, sysn.flags), 20, torch)
+    abi.rb_accum_zero(n, sysn.acc)
+    out["network_pairs_only"] = roof(ms, 2.0 * NN_FLOP_PER_ROW * nnn, BF16_MFMA_PEAK, "TFLOP/s", "mfma",
+                                     f"2 x {NN_FLOP_PER_ROW} FLOP per network pair x {nnn} pairs per launch "
+                                     f"(the network part of the step's forces launch, alone)")
     t0 = ntests(sysn, abi)
     ms = time_launches(lambda: abi.rb_bead_pair_forces(sysn.ctx, sysn.x, sysn.q, sysn.types, sysn.box, sysn.pair_i,
                                                        sysn.pair_j, sysn.idx_bead, sysn.flags[abi.RB_FLAG_NBEAD:],
@@ -536,9 +559,11 @@ def main():
 
     log("[bench] dominant kernel of the network path")
     rl = nn_forces_roofline(systems["nn"], torch, abi)
-    roofline = {"kernel": "k_nn_wide (rb_nn_pair_forces_cyl)", "bound": "mfma", "achieved": rl["achieved"],
+    roofline = {"kernel": "k_nn_wide<2, true, 1> (rb_nn_pair_forces_routed: network pairs, then the fallback "
+                          "pairs' bead sums)", "bound": "mfma", "achieved": rl["achieved"],
                 "peak": rl["peak"], "unit": "TFLOP/s", "frac": rl["frac"], "traffic": nn_traffic(),
-                "traffic_unit": "bytes per launch", "kernel_ms": rl["ms"], "algorithmic_work": rl["algorithmic_work"]}
+                "traffic_unit": "bytes per launch", "kernel_ms": rl["ms"], "algorithmic_work": rl["algorithmic_work"],
+                "fallback": rl["fallback"], "frac_combined": rl["frac_combined"]}
 
     value = nn["pair_evals_per_s"]
     result = {

@@ -78,9 +78,10 @@ extern "C" {
                                 norm had drifted from 1 by more than 1e-10
                                 (|q|^2 - 1) before the integrator's
                                 renormalisation; also counts non-finite q      */
-#define RB_FLAG_ROUTE_WORK 16 /* words 16..18: working counters of
-                                rb_pair_descriptors (network, bead, blocks
-                                done); zero between calls                      */
+#define RB_FLAG_ROUTE_WORK 16 /* words 16..17: one 64-bit working word of
+                                rb_pair_descriptors (network count, bead count,
+                                blocks done); zero between calls; word 18 is
+                                unused                                         */
 #define RB_FLAG_WAIT_TIMEOUT 19 /* 1: a kernel's internal wait between waves
                                 gave up (an internal error: results invalid)   */
 #define RB_FLAG_FB_WORK 20   /* words 20..21: working counters of the bead-sum
@@ -180,8 +181,9 @@ int rb_pairlist_build(int32_t n, const double *x, const double *box, double r_li
  * neither, the rest to the network.  Routed pair indices go to idx_nn /
  * idx_bead (capacity max_pairs each, order not specified) with counts in
  * flags[NNN] / flags[NBEAD], written by the launch's last block (words
- * flags[RB_FLAG_ROUTE_WORK ..+2] count during the launch and are left
- * zero).  x: 3 x n, q: 4 x n. */
+ * flags[RB_FLAG_ROUTE_WORK ..+1] count during the launch and are left
+ * zero).  x: 3 x n, q: 4 x n.  RB_ERR_INVALID_ARG if max_pairs >= 2^27 or
+ * flags is not 8-byte aligned. */
 int rb_pair_descriptors(int32_t n, const double *x, const double *q, const double *box,
                         const int32_t *pair_i, const int32_t *pair_j, int32_t max_pairs,
                         float d_min, float d_max, float *desc, int32_t *idx_nn,

@@ -19,7 +19,7 @@ from ._lib import check, lib
 RB_FLAG_REBUILD, RB_FLAG_NPAIRS, RB_FLAG_OVERFLOW, RB_FLAG_NREBUILDS = 0, 1, 2, 3
 RB_FLAG_NBEAD, RB_FLAG_NNN, RB_FLAG_NONFINITE, RB_FLAG_NEVAL, RB_FLAG_NTESTS, RB_NFLAGS = 4, 5, 6, 7, 8, 24
 RB_FLAG_NSCREEN, RB_FLAG_RESCREEN, RB_FLAG_NRESCREENS = 10, 11, 12
-RB_FLAG_FIXOVF, RB_FLAG_QDRIFT, RB_FLAG_WAIT_TIMEOUT, RB_FLAG_FB_WORK = 13, 14, 19, 20
+RB_FLAG_FIXOVF, RB_FLAG_QDRIFT, RB_FLAG_ROUTE_WORK, RB_FLAG_WAIT_TIMEOUT, RB_FLAG_FB_WORK = 13, 14, 16, 19, 20
 RB_OK, RB_ERR_INVALID_ARG, RB_ERR_CAPACITY, RB_ERR_HIP, RB_ERR_UNSUPPORTED, RB_ERR_NONFINITE = 0, -1, -2, -3, -4, -5
 RB_PREC_BF16, RB_PREC_FP32 = 0, 1
 RB_BUILD_ALWAYS, RB_BUILD_IF_FLAGGED = 0, 1

@@ -18,15 +18,28 @@ namespace rb {
 constexpr int kDescThreads = 1024;
 constexpr int kDescWaves = kDescThreads / kWave;
 
+// The working word of the appends (64 bits at flags + RB_FLAG_ROUTE_WORK):
+// the network list's count in bits 0..26, the bead list's in bits 27..53 and
+// the finishing ticket (blocks done) in bits 54..63.  One atomic per block
+// then reserves both ranges and takes the ticket, and its return value holds
+// every other block's contribution.
+constexpr int kRouteCountBits = 27;
+constexpr unsigned long long kRouteCountMask = (1ull << kRouteCountBits) - 1ull;
+constexpr int kRouteTicketShift = 2 * kRouteCountBits;
+constexpr int kRouteMaxBlocks = (1 << (64 - kRouteTicketShift)) - 1;
+
 // Appends the block's lanes with take0 / take1 to two lists with one atomic
-// per list and block (many waves adding to one counter serialise on it):
-// ballots give each wave's count and each lane's rank in its wave, the
-// wave counts are scanned in LDS, one thread per list reserves the block's
-// range.  Every thread of the block calls it.
-__device__ inline void block_append2(bool take0, bool take1, int value, int32_t *list0, int32_t *counter0,
-                                     int32_t *list1, int32_t *counter1) {
+// per block (many waves adding to one counter serialise on it): ballots give
+// each wave's count and each lane's rank in its wave, the wave counts are
+// scanned in LDS, thread 0 reserves the block's ranges (and takes the ticket
+// in the block's final round).  Every thread of the block calls it.  Returns
+// true in every thread of the last block to finish, with the lists' final
+// lengths in n0, n1.
+__device__ inline bool block_append2(bool take0, bool take1, int value, int32_t *list0, int32_t *list1,
+                                     unsigned long long *work, bool final_round, int nactive, int &n0, int &n1) {
     __shared__ int wcount[2][kDescWaves];
-    __shared__ int base[2];
+    __shared__ int base[2], total[2];
+    __shared__ bool last;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
     const unsigned long long m0 = __ballot(take0), m1 = __ballot(take1);
     if (lane == 0) {
@@ -34,10 +47,20 @@ __device__ inline void block_append2(bool take0, bool take1, int value, int32_t 
         wcount[1][w] = __popcll(m1);
     }
     __syncthreads();
-    if (threadIdx.x < 2) {
-        int tot = 0;
-        for (int k = 0; k < kDescWaves; ++k) tot += wcount[threadIdx.x][k];
-        base[threadIdx.x] = tot ? atomicAdd(threadIdx.x ? counter1 : counter0, tot) : 0;
+    if (threadIdx.x == 0) {
+        int t0 = 0, t1 = 0;
+        for (int k = 0; k < kDescWaves; ++k) {
+            t0 += wcount[0][k];
+            t1 += wcount[1][k];
+        }
+        const unsigned long long add = (unsigned long long)t0 | ((unsigned long long)t1 << kRouteCountBits) |
+                                       (final_round ? 1ull << kRouteTicketShift : 0ull);
+        const unsigned long long old = add ? atomicAdd(work, add) : 0ull;
+        base[0] = (int)(old & kRouteCountMask);
+        base[1] = (int)((old >> kRouteCountBits) & kRouteCountMask);
+        total[0] = base[0] + t0;
+        total[1] = base[1] + t1;
+        last = final_round && (int)(old >> kRouteTicketShift) == nactive - 1;
     }
     __syncthreads();
     int off0 = base[0], off1 = base[1];
@@ -48,7 +71,11 @@ __device__ inline void block_append2(bool take0, bool take1, int value, int32_t 
     const unsigned long long below = (1ull << lane) - 1ull;
     if (take0) list0[off0 + __popcll(m0 & below)] = value;
     if (take1) list1[off1 + __popcll(m1 & below)] = value;
-    __syncthreads();   // wcount and base are reused by the next round
+    n0 = total[0];
+    n1 = total[1];
+    const bool is_last = last;
+    __syncthreads();   // the shared words are reused by the next round
+    return is_last;
 }
 
 __global__ __launch_bounds__(kDescThreads) void k_descriptors(int32_t n, const double *__restrict__ x,
@@ -61,8 +88,8 @@ __global__ __launch_bounds__(kDescThreads) void k_descriptors(int32_t n, const d
                                                      float gap_max) {
     // the first round's pair indices are requested together with the count
     // (any slot below the capacity may be read; only live ones are used).
-    // Appends go through working counters; the last block to finish
-    // publishes the counts and clears them for the next call.
+    // Appends go through the working word; the last block to finish
+    // publishes the counts and clears it for the next call.
     const int p0 = blockIdx.x * blockDim.x + threadIdx.x;
     int i0 = 0, j0 = 0;
     if (p0 < maxp) {
@@ -71,7 +98,7 @@ __global__ __launch_bounds__(kDescThreads) void k_descriptors(int32_t n, const d
     }
     int count = flags[RB_FLAG_NPAIRS];
     if (count > maxp) count = maxp;
-    int32_t *work = flags + RB_FLAG_ROUTE_WORK;
+    unsigned long long *work = reinterpret_cast<unsigned long long *>(flags + RB_FLAG_ROUTE_WORK);
     // the grid is sized for the capacity: only the blocks with pairs take part
     // (and take the completion ticket); with no pairs block 0 publishes zeros
     const int nactive = min((int)gridDim.x, (count + (int)blockDim.x - 1) / (int)blockDim.x);
@@ -83,7 +110,8 @@ __global__ __launch_bounds__(kDescThreads) void k_descriptors(int32_t n, const d
         return;
     }
     const double Ls[3] = {L0, L1, L2};
-    for (int base = blockIdx.x * blockDim.x; base < count; base += gridDim.x * blockDim.x) {
+    const int stride = gridDim.x * blockDim.x;
+    for (int base = blockIdx.x * blockDim.x; base < count; base += stride) {
         const int p = base + threadIdx.x;
         const bool live = p < count;
         bool to_nn = false, to_bead = false;
@@ -125,21 +153,17 @@ __global__ __launch_bounds__(kDescThreads) void k_descriptors(int32_t n, const d
             to_bead = in_range && near;
             if (!type) to_bead = near;    // no shells: every pair below d_min, as before
         }
-        block_append2(live && to_nn, live && to_bead, p, idx_nn, work, idx_bead, work + 1);
-    }
-    // No fence is needed: the block's counter atomics have returned (block
-    // append waits for them) before its ticket is taken, and the last block
-    // reads the counters with device-scope atomic loads.  The published counts
-    // reach the consumers through the kernel boundary.
-    __shared__ bool last;
-    if (threadIdx.x == 0) last = atomicAdd(work + 2, 1) == nactive - 1;
-    __syncthreads();
-    if (last && threadIdx.x == 0) {
-        flags[RB_FLAG_NNN] = __hip_atomic_load(work, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        flags[RB_FLAG_NBEAD] = __hip_atomic_load(work + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        work[0] = 0;
-        work[1] = 0;
-        work[2] = 0;
+        int nn = 0, nb = 0;
+        const bool final_round = base + stride >= count;
+        if (block_append2(live && to_nn, live && to_bead, p, idx_nn, idx_bead, work, final_round, nactive, nn, nb) &&
+            threadIdx.x == 0) {
+            // every block's atomic is in the value this one returned: the
+            // counts are final and the word can be cleared.  No fence: the
+            // counts reach their consumers through the kernel boundary.
+            flags[RB_FLAG_NNN] = nn;
+            flags[RB_FLAG_NBEAD] = nb;
+            *work = 0ull;
+        }
     }
 }
 
@@ -156,6 +180,8 @@ extern "C" int rb_pair_descriptors(int32_t n, const double *x, const double *q, 
                "rb_pair_descriptors: null argument");
     RB_REQUIRE(!ctx == !type, "rb_pair_descriptors: ctx and type go together");
     RB_REQUIRE(n > 0 && max_pairs > 0, "rb_pair_descriptors: sizes must be > 0");
+    RB_REQUIRE(max_pairs <= (int32_t)kRouteCountMask, "rb_pair_descriptors: max_pairs must be below 2^27");
+    RB_REQUIRE(((uintptr_t)flags & 7) == 0, "rb_pair_descriptors: flags must be 8-byte aligned");
     RB_REQUIRE(box[0] > 0 && box[1] > 0 && box[2] > 0, "rb_pair_descriptors: box must be > 0");
     hipStream_t st = (hipStream_t)stream;
     const float dm2 = d_min > 0 ? d_min * d_min : 0.f;
@@ -163,10 +189,9 @@ extern "C" int rb_pair_descriptors(int32_t n, const double *x, const double *q, 
     Templates T = {};
     if (ctx) T = ctx->dev.t;
     const float gmax = gap_max > 0.f ? gap_max : 3.0e38f;
-    k_descriptors<<<grid_for(max_pairs, kDescThreads, 2 * device_cu_count()), kDescThreads, 0, st>>>(n, x, q, box[0], box[1], box[2],
-                                                                                  pair_i, pair_j,
-                                                                  max_pairs, dm2, dx2, desc, idx_nn, idx_bead, flags,
-                                                                  T, type, gap_min, gmax);
+    const int grid = grid_for(max_pairs, kDescThreads, std::min(2 * device_cu_count(), kRouteMaxBlocks));
+    k_descriptors<<<grid, kDescThreads, 0, st>>>(n, x, q, box[0], box[1], box[2], pair_i, pair_j, max_pairs, dm2, dx2,
+                                                 desc, idx_nn, idx_bead, flags, T, type, gap_min, gmax);
     RB_LAUNCH_CHECK("rb_pair_descriptors");
     return RB_OK;
 }

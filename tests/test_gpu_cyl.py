@@ -185,6 +185,47 @@ def test_shell_routing_matches_oracle_and_keeps_the_network_in_its_domain(abi, c
     _check_routes(abi, cfg, st, got_pairs[order], nn_ids[order], bd_ids[order], gap_min, gap_max)
 
 
+def test_routing_over_several_rounds_per_block_matches_one_round(abi, cyl_workload):
+    # 18 copies of the 32768-cylinder pair list (~610k entries, more than the
+    # routing grid's 512 blocks of 1024 threads take in one round): the whole
+    # list and its two halves (each taken in one round) give the same
+    # descriptors and route the same entries, and the launch leaves its
+    # working word zero
+    from paper_2402_12199_amd.md import RigidSystem
+    cfg, st, pairs = cyl_workload
+    b = cfg.body
+    sysm = RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"], cfg.box,
+                       cfg.r_list, cfg.skin)
+    pi = np.tile(pairs[:, 0].astype(np.int32), 18)
+    pj = np.tile(pairs[:, 1].astype(np.int32), 18)
+    M = len(pi)
+    assert M > 512 * 1024
+
+    def route(lo, hi):
+        m = hi - lo
+        desc = torch.zeros((7, m), dtype=torch.float32, device="cuda")
+        inn = torch.zeros(m, dtype=torch.int32, device="cuda")
+        ibd = torch.zeros(m, dtype=torch.int32, device="cuda")
+        flags = torch.zeros(abi.RB_NFLAGS, dtype=torch.int32, device="cuda")
+        flags[abi.RB_FLAG_NPAIRS] = m
+        abi.rb_pair_descriptors(sysm.x, sysm.q, sysm.box, _dev(pi[lo:hi]), _dev(pj[lo:hi]), cfg.d_min, desc, inn,
+                                ibd, flags, d_max=cfg.d_cut, ctx=sysm.ctx, types=sysm.types, gap_min=0.8,
+                                gap_max=2.5)
+        f = flags.cpu().numpy()
+        assert (f[abi.RB_FLAG_ROUTE_WORK:abi.RB_FLAG_ROUTE_WORK + 2] == 0).all()
+        return (desc.cpu().numpy(), np.sort(inn[:f[abi.RB_FLAG_NNN]].cpu().numpy()) + lo,
+                np.sort(ibd[:f[abi.RB_FLAG_NBEAD]].cpu().numpy()) + lo)
+
+    dw, nw, bw = route(0, M)
+    h = M // 2
+    d1, n1, b1 = route(0, h)
+    d2, n2, b2 = route(h, M)
+    np.testing.assert_array_equal(dw, np.concatenate([d1, d2], axis=1))
+    np.testing.assert_array_equal(nw, np.concatenate([n1, n2]))
+    np.testing.assert_array_equal(bw, np.concatenate([b1, b2]))
+    assert len(nw) > 0 and len(bw) > 0 and len(np.unique(nw)) == len(nw)
+
+
 def test_pair_with_overlapping_bead_boxes_goes_to_the_bead_sum(abi):
     # Body j turned so that its axis lies along x, centre 1.5 + 0.6 + 4.05
     # from body i's axis: its end cap sits 0.6 sigma from body i's side (the

@@ -229,10 +229,6 @@ __device__ inline void wave_sum8(const float v[8], int lane, float out[8]) {
     for (int k = 0; k < 8; ++k) out[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(e), 8 * k));
 }
 
-// The ni x nj surviving tests.  Returns, reduced over the wave (valid in
-// every lane): r[0] = E, r[1..3] = F_i, r[4..6] = tau_i (body i frame, about
-// its centre), r[7] = min squared distance over the tests performed (only
-// when TRACK_MIN).
 // Energy and -(du/dr)/r of one bead pair at squared distance r2 < rc2.
 // Lennard-Jones: from 1/r^2.  Half-power half-cosine, with the attractive
 // branch read as -A (1 + cos(c (r - b))) (continuous with zero slope at b
@@ -259,17 +255,24 @@ __device__ inline void bead_pot(const LJ &lj, float r2, float &ee, float &fr) {
     }
 }
 
+// The ni x nj surviving tests.  Returns, reduced over the wave (valid in
+// every lane): r[0] = E, r[1..3] = F_i, r[4..6] = tau_i (body i frame, about
+// its centre), r[7] = min squared distance over the tests performed (only
+// when TRACK_MIN).
+// Lane mapping: body i's beads in blocks of P, P the largest power of two
+// (at most 64) not above the beads left, so that every lane of a block holds
+// a bead; the 64 / P lane groups of a block split body j's beads.  A pair
+// with 72 surviving beads on each side takes 72 + 9 iterations per lane
+// instead of 2 x 72, one with 41 x 41 takes 21 + 6 + 1 instead of 41.
 template <bool TRACK_MIN, int POT>
 __device__ inline void pair_sum(const LJ &lj, int ni, int nj, const WaveLds &L, int lane, float r[8]) {
-    int P = 1;
-    while (P < ni && P < kWave) P <<= 1;
-    const int G = kWave / P, g = lane / P, kk = lane % P;
     float e = 0.f, r2min = 3.0e38f;
     float F[3] = {0.f, 0.f, 0.f}, t[3] = {0.f, 0.f, 0.f};
-    for (int kb = 0; kb < ni; kb += P) {
-        const int k = kb + kk;
-        const bool kv = k < ni;
-        const float4 b = kv ? L.i[k] : make_float4(1.0e4f, 1.0e4f, 1.0e4f, 0.f);
+    for (int kb = 0; kb < ni;) {
+        const int left = ni - kb;
+        const int lg = left >= kWave ? 6 : 31 - __builtin_clz(left);   // log2 P
+        const int P = 1 << lg, G = kWave >> lg, g = lane >> lg, kk = lane & (P - 1);
+        const float4 b = L.i[kb + kk];
         float fx = 0.f, fy = 0.f, fz = 0.f;
 #pragma unroll 2
         for (int l = g; l < nj; l += G) {
@@ -291,6 +294,7 @@ __device__ inline void pair_sum(const LJ &lj, int ni, int nj, const WaveLds &L, 
         t[0] += b.y * fz - b.z * fy;
         t[1] += b.z * fx - b.x * fz;
         t[2] += b.x * fy - b.y * fx;
+        kb += P;
     }
     const float v8[8] = {e, F[0], F[1], F[2], t[0], t[1], t[2], 0.f};
     wave_sum8(v8, lane, r);

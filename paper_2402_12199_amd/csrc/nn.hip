@@ -311,6 +311,14 @@ __global__ __launch_bounds__(nn_threads(BF16, MODE)) void k_nn(NNArgs a) {
 // tile) so that every wave meets the same barriers.
 constexpr int kWideGroups = 3;
 constexpr int kWideThreads = kWideGroups * kWideGroup * kWave;
+// Fallback phase: LDS words of the chunks in use, a 6-bit chunk tag above
+// a 26-bit first pair index (the fused launch is taken only for lists below
+// kFbMaxPairs, so that the counter, which runs past the count by at most two
+// chunks per block, stays below 2^26).
+constexpr int kFbSlots = 4;
+constexpr int kFbBaseBits = 26;
+constexpr unsigned kFbBaseMask = (1u << kFbBaseBits) - 1u;
+constexpr int64_t kFbMaxPairs = (1 << kFbBaseBits) - (1 << 16);
 
 // Inputs of one lane's row of a tile: the network input, the backward seed
 // (the switch for dynamics, dL/dE for gradients) and, for the lanes that
@@ -556,11 +564,12 @@ __device__ inline void cyl_chain_lds(const EpiLds &e, int n, float gu[kIn]) {
 // launch also adds the bead double sums of the fallback pairs.  Every block
 // of the grid takes part: after the block's network tiles (if any) the
 // weight image's LDS holds the bead templates and the waves' staging arrays,
-// and the block claims the fallback pairs a round of one pair per wave at a
-// time from a counter in flags (RB_FLAG_FB_WORK; FB_WORK + 1 is the
-// finishing ticket; both zero between launches), so that blocks with fewer
-// network tiles take more pairs.  One claim per block and round keeps the
-// counter's atomics few (one per wave serialised the grid on that address).
+// and the block's waves take the fallback pairs one at a time from chunks
+// the block claims from a counter in flags (RB_FLAG_FB_WORK; FB_WORK + 1 is
+// the finishing ticket; both zero between launches), so that blocks with
+// fewer network tiles take more pairs and no wave waits for another's pair.
+// One global claim per chunk keeps the counter's atomics few (one per wave
+// serialised the grid on that address).
 template <int MODE, bool PRE = false, int FB = 0>
 __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
     static_assert(!PRE || MODE == kForces, "prefetching is a forces-mode form");
@@ -675,32 +684,63 @@ __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
         __syncthreads();
         WaveLds WL = wave_lds(bl, wave, a.bead_stride);
         const float rcm = sqrtf(a.lj.rc2) + kCullMargin, cut2 = rcm * rcm;
-        // rounds of one pair per wave: thread 0 claims the block's next
-        // kWaves pairs from the counter while the current ones are summed
-        __shared__ int fb_base[2];
+        // The block takes the pairs from the global counter in chunks of
+        // kWaves (one atomic per chunk); each wave takes its next slot from
+        // an LDS counter, without waiting for the block's other waves.  The
+        // wave whose slot opens a chunk fetches the chunk's first pair index
+        // and publishes it in one of kFbSlots LDS words, tagged with the
+        // chunk's number; the chunk's other waves wait for that word (a
+        // bounded wait: past kGroupSyncSpins polls it records a timeout and
+        // the wave stops).  The fetching wave waits on nothing, so the waits
+        // end.  A word is reused four chunks later, long after its readers
+        // have read it (they wait only for one atomic).
+        __shared__ int fb_next;
+        __shared__ unsigned fb_word[kFbSlots];
         int32_t *work = a.flags + RB_FLAG_FB_WORK;
-        if (threadIdx.x == 0) fb_base[0] = atomicAdd(work, kWaves);
+        if (threadIdx.x == 0) fb_next = 0;
+        if (threadIdx.x < kFbSlots) fb_word[threadIdx.x] = 0u;
         __syncthreads();
-        for (int r = 0;; ++r) {
-            const int base = fb_base[r & 1];
-            if (base >= nbead) break;
-            int next = 0;
-            if (threadIdx.x == 0) next = atomicAdd(work, kWaves);
-            const int k = base + wave;
-            if (k < nbead) {
-                const int pid = a.idx_bead[k];
-                const int i = a.pi[pid], j = a.pj[pid];
-                const int ti = a.type[i], tj = a.type[j];
-                double dl[3], d[3], qr[4], qa[4], Ri[9], R[9];
-                pair_frame(a.n, a.x, a.q, a.box, i, j, dl, d, qr, qa, Ri);
-                quat_to_rot<double>(qr[0], qr[1], qr[2], qr[3], R);
-                md_pair<POT>(a.T, a.lj, tb, WL, lane, cut2, a.n, i, j, ti, tj, dl, d, R, Ri, a.acc, wacc[wave],
-                             ntests, bad, ovf);
+        for (;;) {
+            int m = 0;
+            if (lane == 0) m = atomicAdd(&fb_next, 1);
+            m = __builtin_amdgcn_readfirstlane(m);
+            const int c = m / kWaves, o = m - c * kWaves;
+            const unsigned tag = (unsigned)((c + 1) & 63) << kFbBaseBits;
+            volatile lds_uint *slot = (volatile lds_uint *)&fb_word[c % kFbSlots];
+            int base;
+            if (o == 0) {
+                int b0 = 0;
+                if (lane == 0) {
+                    b0 = atomicAdd(work, kWaves);
+                    *slot = tag | (unsigned)b0;
+                }
+                base = __builtin_amdgcn_readfirstlane(b0);
+            } else {
+                unsigned w = 0;
+                for (int spin = 0;; ++spin) {
+                    w = __builtin_amdgcn_readfirstlane(*slot);
+                    if ((w & ~kFbBaseMask) == tag) break;
+                    if (spin >= kGroupSyncSpins) {
+                        if (lane == 0) gtimeout = 1;
+                        w = tag | (unsigned)nbead;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                base = (int)(w & kFbBaseMask);
             }
-            // the slot written here was last read before the previous barrier
-            if (threadIdx.x == 0) fb_base[(r + 1) & 1] = next;
-            __syncthreads();
+            const int k = base + o;
+            if (k >= nbead) break;
+            const int pid = a.idx_bead[k];
+            const int i = a.pi[pid], j = a.pj[pid];
+            const int ti = a.type[i], tj = a.type[j];
+            double dl[3], d[3], qr[4], qa[4], Ri[9], R[9];
+            pair_frame(a.n, a.x, a.q, a.box, i, j, dl, d, qr, qa, Ri);
+            quat_to_rot<double>(qr[0], qr[1], qr[2], qr[3], R);
+            md_pair<POT>(a.T, a.lj, tb, WL, lane, cut2, a.n, i, j, ti, tj, dl, d, R, Ri, a.acc, wacc[wave], ntests,
+                         bad, ovf);
         }
+        __syncthreads();
         // every claim of every block has returned before its ticket; the last
         // block clears the counter and the ticket for the next launch
         if (threadIdx.x == 0 && atomicAdd(work + 1, 1) == (int)gridDim.x - 1) {
@@ -856,7 +896,7 @@ extern "C" int rb_nn_pair_forces_routed(const rb_ctx *ctx, const float *params, 
     a.cyl = form;
     const int stride = (ctx->max_beads + 3) & ~3;
     const size_t need = sizeof(float4) * (3 * (size_t)stride * (kWideThreads / kWave) + (size_t)ctx->total_beads);
-    if (precision != RB_PREC_BF16 || need > sizeof(LdsBF16)) {
+    if (precision != RB_PREC_BF16 || need > sizeof(LdsBF16) || max_count >= kFbMaxPairs) {
         const int rc = launch<kForces>(a, precision, max_count, st);
         if (rc != RB_OK) return rc;
         return rb_bead_pair_forces(ctx, n, x, q, type, box, pair_i, pair_j, idx_bead, bead_count_dev, max_count, acc,

@@ -229,6 +229,7 @@ struct BlockSync {
 constexpr int kGroupSyncSpins = 1 << 16;
 
 typedef __attribute__((address_space(3))) int lds_int;
+typedef __attribute__((address_space(3))) unsigned lds_uint;
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) volatile i32x4 lds_vi32x4;
 

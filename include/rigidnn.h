@@ -148,9 +148,10 @@ int rb_flags_check(const int32_t *flags_host);
  * distance is below 2 r_max + rc, so r_list = 2 r_max + rc + skin.  Cell list
  * over a periodic orthorhombic box (host box[3]); requires box >= 2 r_list
  * per axis.  x: 3 x n FP64 positions (any periodic image).  Writes
- * pair_i/pair_j (capacity max_pairs): the exact set of pairs; the pairs of
- * one body i are contiguous and in a fixed cell order, the order of the
- * bodies' runs is not specified for n <= 65536 (sorted by i above);
+ * pair_i/pair_j (capacity max_pairs): the exact set of pairs, each once with
+ * pair_i < pair_j; for n <= 65536 the pairs of one body i are contiguous and
+ * in a fixed cell order and the order of the bodies' runs is not specified;
+ * above, the order is fixed (the same list for the same input);
  * flags[NPAIRS] = min(found, max_pairs) and
  * flags[OVERFLOW] = found if found > max_pairs (else 0).  Copies x into
  * x_ref (3 x n) for the skin test of rb_rigid_step.  With

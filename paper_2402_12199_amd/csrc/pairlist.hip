@@ -9,12 +9,19 @@
 //   exclusive scan of cell counts -> cell starts
 //   scatter body ids into cell order, then sort each cell's ids, which makes
 //   the cell contents independent of atomic arrival order
-//   per body i: count neighbours j > i in the 27 surrounding cells
-//   exclusive scan of those counts -> per-body offsets, total -> flags
-//   per body i: write its pairs at its offset, in the same cell order
-// The resulting list is sorted by i and fully deterministic.  Either way the
-// set of pairs is exact; the forces built from it do not depend on its order
-// (fixed-point accumulation).
+//   with at least 3 cells on every axis (half stencil): per position t in
+//   cell order, count the pairs with the later bodies of its own cell and
+//   the bodies of the 13 forward neighbour cells (FP32 distances from
+//   cell-relative positions, the exact FP64 test near r_list); exclusive
+//   scan of the counts; write them as (min, max) at t's offset
+//   otherwise (full stencil): per body i, count neighbours j > i in the 27
+//   surrounding cells, scan, write its pairs at its offset (sorted by i)
+// The resulting list is fully deterministic.  Either way the set of pairs is
+// exact; the forces built from it do not depend on its order (fixed-point
+// accumulation).
+#include <algorithm>
+#include <cfloat>
+
 #include "rb_common.hpp"
 
 namespace rb {
@@ -28,6 +35,13 @@ struct CellGrid {
     int ncell;
     double L[3], inv[3], cinv[3];  // cinv: cells per unit length
     double rl2;
+    // half-stencil search (every axis with at least 3 cells): cell edges in
+    // FP64 and FP32, and the band around r_list^2 inside which the FP32
+    // squared distance is not trusted to decide (the exact FP64 test is
+    // taken there)
+    double edge[3];
+    float edge_f[3];
+    float lo2, hi2;
 };
 
 __device__ inline bool skip(const int32_t *flags, int mode) {
@@ -184,6 +198,166 @@ __global__ void k_sort_cells(int ncell, int32_t n, const double *__restrict__ x,
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
     sort_cell_and_gather(start[c], start[c + 1], n, x, sorted, xs);
+}
+
+// Cell-order copy for the half-stencil search: per sorted position k the
+// position relative to its cell's origin in FP32 (xr, 3 x n SoA) and the
+// cell index (cs).  The offset of a neighbour cell's origin is then a whole
+// number of edges, the same for all of that cell's bodies.
+__global__ void k_sort_cells_rel(int ncell, int32_t n, const double *__restrict__ x, CellGrid g,
+                                 const int32_t *__restrict__ start, int32_t *__restrict__ sorted,
+                                 float *__restrict__ xr, int32_t *__restrict__ cs, const int32_t *flags, int mode) {
+    if (skip(flags, mode)) return;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const int b = start[c], e = start[c + 1];
+    for (int k = b + 1; k < e; ++k) {
+        int v = sorted[k], m = k - 1;
+        while (m >= b && sorted[m] > v) {
+            sorted[m + 1] = sorted[m];
+            --m;
+        }
+        sorted[m + 1] = v;
+    }
+    const int cc[3] = {c / (g.nc[2] * g.nc[1]), (c / g.nc[2]) % g.nc[1], c % g.nc[2]};
+    for (int k = b; k < e; ++k) {
+        const int j = sorted[k];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double v = x[a * n + j];
+            const double w = v - g.L[a] * floor(v / g.L[a]);
+            xr[a * n + k] = (float)(w - cc[a] * g.edge[a]);
+        }
+        cs[k] = c;
+    }
+}
+
+// Half-stencil search: thread t takes the t-th body in cell order and pairs
+// it with the later bodies of its own cell and all bodies of the 13 cells
+// that follow it in the (x, y, z) lexicographic order of the offsets, so
+// that each pair is examined once; it is written as (min, max).  The
+// candidates' positions are requested in batches, so that a lane has many
+// loads in flight (the search is bound by load latency).  The squared distance
+// is formed in FP32 from the cell-relative positions; inside the band
+// [lo2, hi2) around r_list^2 the FP64 minimum-image test of the full
+// pipeline decides, so the set of pairs is exactly that test's.  Counts and
+// offsets are indexed by the cell-order position.
+// The writing pass stages each wave's pairs in LDS (the wave's pairs form
+// one contiguous range of the list) and stores them with coalesced writes;
+// pairs beyond kHalfBuf per wave go straight to memory.
+constexpr int kHalfThreads = 256;
+constexpr int kHalfBuf = 512;
+constexpr int kHalfBatch = 3;
+
+template <bool EMIT>
+__global__ __launch_bounds__(kHalfThreads) void k_neigh_half(
+    int32_t n, const float *__restrict__ xr, const double *__restrict__ x, CellGrid g,
+    const int32_t *__restrict__ cs, const int32_t *__restrict__ start, const int32_t *__restrict__ sorted,
+    int32_t *__restrict__ ncount, const int32_t *__restrict__ noff, int32_t *__restrict__ pi,
+    int32_t *__restrict__ pj, int32_t cap, const int32_t *flags, int mode) {
+    if (skip(flags, mode)) return;
+    __shared__ int2 buf[EMIT ? kHalfThreads / kWave : 1][EMIT ? kHalfBuf : 1];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+    const bool live = t < n;
+    const int tc = live ? t : n - 1;
+    const int c = cs[tc], i = sorted[tc];
+    const int cz = c % g.nc[2], cy = (c / g.nc[2]) % g.nc[1], cx = c / (g.nc[2] * g.nc[1]);
+    const float xi = xr[tc], yi = xr[n + tc], zi = xr[2 * n + tc];
+    int cnt = 0;
+    int wbase = 0, wtotal = 0;
+    const int t0 = t - lane;   // the wave's first position
+    if (EMIT && t0 < n) {
+        const int t1 = t0 + kWave < n ? t0 + kWave : n;
+        wbase = noff[t0];
+        wtotal = noff[t1] - wbase;
+    }
+    int out = EMIT ? noff[tc] : 0;
+    // The 14 cells' ranges (the own cell from position t + 1 on, then the 13
+    // forward cells, offsets k = 14 .. 26 with k = 9 (dx + 1) + 3 (dy + 1) +
+    // (dz + 1)), requested together; then per cell its first kHalfBatch
+    // candidates in one batch of loads (unused slots read a valid position
+    // and are not tested), the rest of a fuller cell one by one.
+    int mb[14], me[14];
+    mb[0] = t + 1;
+    me[0] = start[c + 1];
+#pragma unroll
+    for (int q = 1; q < 14; ++q) {
+        const int kk = 13 + q;
+        int nx = cx + kk / 9 - 1, ny = cy + (kk / 3) % 3 - 1, nz = cz + kk % 3 - 1;
+        nx += nx < 0 ? g.nc[0] : (nx >= g.nc[0] ? -g.nc[0] : 0);
+        ny += ny < 0 ? g.nc[1] : (ny >= g.nc[1] ? -g.nc[1] : 0);
+        nz += nz < 0 ? g.nc[2] : (nz >= g.nc[2] ? -g.nc[2] : 0);
+        const int cn = (nx * g.nc[1] + ny) * g.nc[2] + nz;
+        mb[q] = start[cn];
+        me[q] = start[cn + 1];
+    }
+    if (!live)
+#pragma unroll
+        for (int q = 0; q < 14; ++q) me[q] = mb[q];
+    auto test = [&](int m, float px, float py, float pz, float ox, float oy, float oz) {
+        const float ddx = (px + ox) - xi, ddy = (py + oy) - yi, ddz = (pz + oz) - zi;
+        const float r2 = fmaf(ddx, ddx, fmaf(ddy, ddy, ddz * ddz));
+        bool in = r2 < g.lo2;
+        if (!in && r2 < g.hi2) {
+            const int j = sorted[m];
+            const double ex = min_image(x[j] - x[i], g.L[0], g.inv[0]);
+            const double ey = min_image(x[n + j] - x[n + i], g.L[1], g.inv[1]);
+            const double ez = min_image(x[2 * n + j] - x[2 * n + i], g.L[2], g.inv[2]);
+            in = ex * ex + ey * ey + ez * ez < g.rl2;
+        }
+        if (in) {
+            if (EMIT) {
+                const int j = sorted[m];
+                const int a = i < j ? i : j, b = i < j ? j : i;
+                const int local = out - wbase;
+                if (local < kHalfBuf)
+                    buf[w][local] = make_int2(a, b);
+                else if (out < cap) {
+                    pi[out] = a;
+                    pj[out] = b;
+                }
+                ++out;
+            } else {
+                ++cnt;
+            }
+        }
+    };
+#pragma unroll
+    for (int q = 0; q < 14; ++q) {
+        const int kk = q == 0 ? 13 : 13 + q;
+        const float ox = (float)(kk / 9 - 1) * g.edge_f[0], oy = (float)((kk / 3) % 3 - 1) * g.edge_f[1],
+                    oz = (float)(kk % 3 - 1) * g.edge_f[2];
+        float px[kHalfBatch], py[kHalfBatch], pz[kHalfBatch];
+#pragma unroll
+        for (int v = 0; v < kHalfBatch; ++v) {
+            const int mm = mb[q] + v < n ? mb[q] + v : n - 1;
+            px[v] = xr[mm];
+            py[v] = xr[n + mm];
+            pz[v] = xr[2 * n + mm];
+        }
+#pragma unroll
+        for (int v = 0; v < kHalfBatch; ++v)
+            if (mb[q] + v < me[q]) test(mb[q] + v, px[v], py[v], pz[v], ox, oy, oz);
+        for (int m = mb[q] + kHalfBatch; m < me[q]; ++m) test(m, xr[m], xr[n + m], xr[2 * n + m], ox, oy, oz);
+    }
+    if (EMIT) {
+        // the lanes' LDS writes are done before the wave reads them back
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int nb = wtotal < kHalfBuf ? wtotal : kHalfBuf;
+        for (int k = lane; k < nb; k += kWave) {
+            const int o = wbase + k;
+            if (o < cap) {
+                const int2 v = buf[w][k];
+                pi[o] = v.x;
+                pj[o] = v.y;
+            }
+        }
+    } else if (live) {
+        ncount[t] = cnt;
+    }
 }
 
 // Thread t takes the t-th body in cell order, so that neighbouring threads
@@ -437,7 +611,7 @@ __global__ __launch_bounds__(kPairThreads) void k_pl_pairs(int32_t n, const doub
 }
 
 struct PLLayout {
-    size_t cell_of, cnt, start, fill, sorted, ncount, noff, tmp, counter, xs, total;
+    size_t cell_of, cnt, start, fill, sorted, ncount, noff, tmp, counter, xs, cs, total;
 };
 
 static bool make_grid(int32_t n, const double *box, double r_list, CellGrid &g) {
@@ -451,11 +625,19 @@ static bool make_grid(int32_t n, const double *box, double r_list, CellGrid &g) 
         g.L[a] = box[a];
         g.inv[a] = 1.0 / box[a];
         g.cinv[a] = nc / box[a];
+        g.edge[a] = box[a] / nc;
+        g.edge_f[a] = (float)g.edge[a];
         ncell *= nc;
     }
     if (ncell > (int64_t)kScanTile * kScanTile) return false;
     g.ncell = (int)ncell;
     g.rl2 = r_list * r_list;
+    // FP32 distances from cell-relative positions (|component| < 2 edges)
+    // are off by a few ulps of 2 edges per component; the band is far wider
+    const double emax = std::max(g.edge[0], std::max(g.edge[1], g.edge[2]));
+    const double band = 256.0 * FLT_EPSILON * (2.0 * emax) * (2.0 * emax);
+    g.lo2 = (float)(g.rl2 - band);
+    g.hi2 = (float)(g.rl2 + band);
     (void)n;
     return true;
 }
@@ -474,7 +656,8 @@ static PLLayout layout(int32_t n, int ncell) {
     L.noff = o; o += al(sizeof(int32_t) * (n + 1));
     L.tmp = o; o += al(sizeof(int32_t) * kScanTile);
     L.counter = o; o += al(sizeof(int32_t) * 2);
-    L.xs = o; o += al(sizeof(double) * 3 * (size_t)n);
+    L.xs = o; o += al(sizeof(double) * 3 * (size_t)n);   // FP64 copy, or the FP32 relative one
+    L.cs = o; o += al(sizeof(int32_t) * n);
     L.total = o;
     return L;
 }
@@ -533,6 +716,20 @@ extern "C" int rb_pairlist_build(int32_t n, const double *x, const double *box, 
     k_bin<<<gb, 256, 0, st>>>(n, x, g, cell_of, cnt, x_ref, flags, mode);
     scan(cnt, start, g.ncell, tmp, flags, mode, -1, st);
     k_scatter<<<gb, 256, 0, st>>>(n, cell_of, start, fill, sorted, flags, mode);
+    if (g.nc[0] >= 3 && g.nc[1] >= 3 && g.nc[2] >= 3) {
+        float *xr = (float *)(w + L.xs);
+        int32_t *cs = (int32_t *)(w + L.cs);
+        k_sort_cells_rel<<<gc, 256, 0, st>>>(g.ncell, n, x, g, start, sorted, xr, cs, flags, mode);
+        const int gh = (n + kHalfThreads - 1) / kHalfThreads;
+        k_neigh_half<false><<<gh, kHalfThreads, 0, st>>>(n, xr, x, g, cs, start, sorted, ncount, nullptr, nullptr,
+                                                         nullptr, 0, flags, mode);
+        scan(ncount, noff, n, tmp, flags, mode, max_pairs, st);
+        k_neigh_half<true><<<gh, kHalfThreads, 0, st>>>(n, xr, x, g, cs, start, sorted, nullptr, noff, pair_i,
+                                                        pair_j, max_pairs, flags, mode);
+        k_finish<<<1, 1, 0, st>>>(flags, mode);
+        RB_LAUNCH_CHECK("rb_pairlist_build");
+        return RB_OK;
+    }
     k_sort_cells<<<gc, 256, 0, st>>>(g.ncell, n, x, start, sorted, xs, flags, mode);
     k_neigh<false><<<gb, 256, 0, st>>>(n, xs, g, cell_of, start, sorted, ncount, nullptr, nullptr, nullptr, 0,
                                        flags, mode);

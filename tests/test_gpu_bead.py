@@ -390,9 +390,57 @@ def test_pairlist_multi_kernel_path_matches_oracle(abi):
     got = sysm.pairs_host()
     ref = np.sort(obeads.pairs_within(x, box, r), axis=1)
     assert f[abi.RB_FLAG_NPAIRS] == len(ref)
+    assert (got[:, 0] < got[:, 1]).all()
     key = lambda a: a[:, 0].astype(np.int64) * n + a[:, 1]
     np.testing.assert_array_equal(np.sort(key(got)), np.sort(key(ref)))
-    assert np.all(np.diff(got[:, 0]) >= 0)
+    # the same input gives the same list, in the same order
+    sysm.build_pairs(always=True)
+    np.testing.assert_array_equal(sysm.pairs_host(), got)
+
+
+def test_pairlist_half_stencil_decides_near_cutoff_pairs_exactly(abi):
+    # 41^3 bodies on a lattice of spacing 1.25 r (no pair), then bodies moved
+    # so that chosen pairs sit at r (1 -+ 1e-9) and r (1 -+ 3e-5): within the
+    # FP32 band around r^2, where the exact FP64 test decides.  Pairs along
+    # each axis, across cell and periodic boundaries.  Reference: the pairs
+    # placed inside r (a moved body stays farther than r from every other
+    # body: 1.5 r along its axis, 1.27 r across), which is the oracle's
+    # brute-force set for this construction (27 s on the host, so not re-run)
+    from paper_2402_12199_amd.md import RigidSystem
+    r, m = 9.0, 41
+    s = 1.25 * r
+    box = m * s
+    idx = np.arange(m ** 3)
+    lat = np.stack([idx // (m * m), (idx // m) % m, idx % m], axis=1).astype(np.float64)
+    x = lat * s + 0.5
+    site = lambda a, b, c: (a % m) * m * m + (b % m) * m + (c % m)
+    moves, inside = [], []
+    for axis in range(3):
+        for k, (rel, at) in enumerate(((-1e-9, 3), (1e-9, 9), (-3e-5, 15), (3e-5, 21), (-1e-9, m - 1),
+                                       (1e-9, m - 1))):
+            a = [at, 5 + 6 * k, 7 + 4 * axis]
+            b = list(a)
+            b[axis] += 1
+            ia, ib = site(*a), site(*b)
+            xb = x[ia].copy()
+            xb[axis] += r * (1.0 + rel)
+            moves.append((ib, xb))
+            if rel < 0:
+                inside.append((min(ia, ib), max(ia, ib)))
+    for ib, xb in moves:
+        x[ib] = xb
+    n = len(x)
+    q = np.tile([1.0, 0, 0, 0], (n, 1))
+    zero = np.zeros((n, 3))
+    sysm = RigidSystem([np.zeros((1, 3))], [1.0], [[1.0, 1.0, 1.0]], np.zeros(n, np.int32), x, q, zero, zero, box,
+                       r, 0.0)
+    sysm.build_pairs(always=True)
+    sysm.check_capacity()
+    got = sysm.pairs_host()
+    ref = np.array(inside)
+    key = lambda a: a[:, 0].astype(np.int64) * n + a[:, 1]
+    assert len(ref) == 9
+    np.testing.assert_array_equal(np.sort(key(got)), np.sort(key(ref)))
 
 
 @pytest.mark.parametrize("path", ["bead", "nn"])

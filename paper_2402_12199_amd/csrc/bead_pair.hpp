@@ -259,20 +259,34 @@ __device__ inline void bead_pot(const LJ &lj, float r2, float &ee, float &fr) {
 // every lane): r[0] = E, r[1..3] = F_i, r[4..6] = tau_i (body i frame, about
 // its centre), r[7] = min squared distance over the tests performed (only
 // when TRACK_MIN).
-// Lane mapping: body i's beads in blocks of P, P the largest power of two
-// (at most 64) not above the beads left, so that every lane of a block holds
-// a bead; the 64 / P lane groups of a block split body j's beads.  A pair
-// with 72 surviving beads on each side takes 72 + 9 iterations per lane
-// instead of 2 x 72, one with 41 x 41 takes 21 + 6 + 1 instead of 41.
+// Lane mapping: body i's beads in blocks of P lanes, the 64 / P lane groups
+// of a block splitting body j's beads.  Two choices of blocks, the cheaper
+// in iterations per lane taken (a wave-uniform decision): one P for all, the
+// smallest power of two not below n_i (at most 64; the last block may have
+// idle lanes), or P the largest power of two not above the beads left, so
+// that every lane holds a bead (one extra iteration charged per extra
+// block).  72 x 72 beads take 72 + 9 iterations instead of 2 x 72, 41 x 41
+// take 21 + 6 + 1 instead of 41, 11 x 11 keep one block of 16 (3).
 template <bool TRACK_MIN, int POT>
 __device__ inline void pair_sum(const LJ &lj, int ni, int nj, const WaveLds &L, int lane, float r[8]) {
     float e = 0.f, r2min = 3.0e38f;
     float F[3] = {0.f, 0.f, 0.f}, t[3] = {0.f, 0.f, 0.f};
+    int lgfix = 0;
+    while ((1 << lgfix) < ni && lgfix < 6) ++lgfix;
+    const int cost_fix = ((ni + (1 << lgfix) - 1) >> lgfix) * ((nj << lgfix) + kWave - 1) / kWave;
+    int cost_pow = -1;
+    for (int left = ni; left > 0;) {
+        const int lg = left >= kWave ? 6 : 31 - __builtin_clz(left);
+        cost_pow += 1 + ((nj << lg) + kWave - 1) / kWave;
+        left -= 1 << lg;
+    }
+    const bool greedy = cost_pow < cost_fix;
     for (int kb = 0; kb < ni;) {
         const int left = ni - kb;
-        const int lg = left >= kWave ? 6 : 31 - __builtin_clz(left);   // log2 P
+        const int lg = greedy ? (left >= kWave ? 6 : 31 - __builtin_clz(left)) : lgfix;
         const int P = 1 << lg, G = kWave >> lg, g = lane >> lg, kk = lane & (P - 1);
-        const float4 b = L.i[kb + kk];
+        const bool kv = kb + kk < ni;
+        const float4 b = kv ? L.i[kb + kk] : make_float4(1.0e4f, 1.0e4f, 1.0e4f, 0.f);
         float fx = 0.f, fy = 0.f, fz = 0.f;
 #pragma unroll 2
         for (int l = g; l < nj; l += G) {

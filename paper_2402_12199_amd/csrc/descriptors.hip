@@ -86,22 +86,20 @@ __global__ __launch_bounds__(kDescThreads) void k_descriptors(int32_t n, const d
                                                      int32_t *__restrict__ flags, Templates T,
                                                      const int32_t *__restrict__ type, float gap_min,
                                                      float gap_max) {
-    // the first round's pair indices are requested together with the count
-    // (any slot below the capacity may be read; only live ones are used).
-    // Appends go through the working word; the last block to finish
-    // publishes the counts and clears it for the next call.
-    const int p0 = blockIdx.x * blockDim.x + threadIdx.x;
-    int i0 = 0, j0 = 0;
-    if (p0 < maxp) {
-        i0 = pi[p0];
-        j0 = pj[p0];
-    }
+    // Each block takes a span of the list: the count spread evenly over the
+    // grid (one block per CU) in whole waves, at most the block's threads, so
+    // that every CU has work and none more than its share; lists longer than
+    // the grid's threads take several rounds.  Appends go through the
+    // working word; the last block to finish publishes the counts and clears
+    // it for the next call.
     int count = flags[RB_FLAG_NPAIRS];
     if (count > maxp) count = maxp;
     unsigned long long *work = reinterpret_cast<unsigned long long *>(flags + RB_FLAG_ROUTE_WORK);
-    // the grid is sized for the capacity: only the blocks with pairs take part
-    // (and take the completion ticket); with no pairs block 0 publishes zeros
-    const int nactive = min((int)gridDim.x, (count + (int)blockDim.x - 1) / (int)blockDim.x);
+    int span = (count + (int)gridDim.x - 1) / (int)gridDim.x;
+    span = min((int)blockDim.x, max(kWave, (span + kWave - 1) / kWave * kWave));
+    // only the blocks with pairs take part (and take the completion ticket);
+    // with no pairs block 0 publishes zeros
+    const int nactive = min((int)gridDim.x, (count + span - 1) / span);
     if ((int)blockIdx.x >= nactive) {
         if (nactive == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
             flags[RB_FLAG_NNN] = 0;
@@ -110,13 +108,13 @@ __global__ __launch_bounds__(kDescThreads) void k_descriptors(int32_t n, const d
         return;
     }
     const double Ls[3] = {L0, L1, L2};
-    const int stride = gridDim.x * blockDim.x;
-    for (int base = blockIdx.x * blockDim.x; base < count; base += stride) {
+    const int stride = gridDim.x * span;
+    for (int base = blockIdx.x * span; base < count; base += stride) {
         const int p = base + threadIdx.x;
-        const bool live = p < count;
+        const bool live = (int)threadIdx.x < span && p < count;
         bool to_nn = false, to_bead = false;
         if (live) {
-            const int i = p == p0 ? i0 : pi[p], j = p == p0 ? j0 : pj[p];
+            const int i = pi[p], j = pj[p];
             double dl[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) dl[a] = min_image(x[a * n + j] - x[a * n + i], Ls[a], 1.0 / Ls[a]);
@@ -189,7 +187,7 @@ extern "C" int rb_pair_descriptors(int32_t n, const double *x, const double *q, 
     Templates T = {};
     if (ctx) T = ctx->dev.t;
     const float gmax = gap_max > 0.f ? gap_max : 3.0e38f;
-    const int grid = grid_for(max_pairs, kDescThreads, std::min(2 * device_cu_count(), kRouteMaxBlocks));
+    const int grid = grid_for(max_pairs, kWave, std::min(device_cu_count(), kRouteMaxBlocks));
     k_descriptors<<<grid, kDescThreads, 0, st>>>(n, x, q, box[0], box[1], box[2], pair_i, pair_j, max_pairs, dm2, dx2,
                                                  desc, idx_nn, idx_bead, flags, T, type, gap_min, gmax);
     RB_LAUNCH_CHECK("rb_pair_descriptors");

@@ -60,15 +60,15 @@ GAP_MIN, GAP_MAX, SAMPLE_GAP_MIN = 1.0, 2.5, 0.8
 
 # HBM bytes per launch of the network path's forces kernel on the headline
 # workload at its start (31.3k network pairs, 2.5k fallback pairs), from two
-# rocprofv3 counter runs (FETCH_SIZE 8406.69 KiB x 2.000, WRITE_SIZE
-# 12725.38 KiB x 1.000; the factors are what the counters read for a 256 MiB
+# rocprofv3 counter runs (FETCH_SIZE 8440.62 KiB x 2.000, WRITE_SIZE
+# 12726.69 KiB x 1.000; the factors are what the counters read for a 256 MiB
 # copy), see profiles/k_nn_wide_cyl32768_hbm_traffic.txt.  Valid only for the
 # kernel sources they were taken on (hash below); otherwise reported as null.
-NN_TRAFFIC_BYTES = 30247690
+NN_TRAFFIC_BYTES = 30318520
 NN_TRAFFIC_SOURCES = ("paper_2402_12199_amd/csrc/nn.hip", "paper_2402_12199_amd/csrc/nn_tile.hpp",
                       "paper_2402_12199_amd/csrc/nn_common.hpp", "paper_2402_12199_amd/csrc/cyl_form.hpp",
                       "paper_2402_12199_amd/csrc/rb_common.hpp", "paper_2402_12199_amd/csrc/bead_pair.hpp")
-NN_TRAFFIC_HASH = "01d4706b82fa2fb4"
+NN_TRAFFIC_HASH = "56430f09a8545ddf"
 
 
 def sources_hash(files):

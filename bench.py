@@ -12,7 +12,9 @@ per graph of 10 steps).  Two paths from the same start:
   nn      the BF16 network surrogate on the cylinder four-number descriptor
           for the pairs whose shells' bound on the closest bead distance lies
           in [1.0, 2.5), the bead sum for the pairs below 1.0, nothing for
-          the pairs at or above 2.5 (no bead pair within the cutoff).
+          the pairs at or above 2.5 (no bead pair within the cutoff); the
+          routing visits the candidates of a two-level list (same margin as
+          the bead path's), re-screened when a bead may have moved margin/2.
 
 The surrogate is trained here, on the GPU, by the library's own training
 step, on pairs visited by bead-path runs of the same system at
@@ -93,7 +95,7 @@ def make_system(cfg, st, path, model=None):
     from paper_2402_12199_amd.md import RigidSystem
     b = cfg.body
     s = RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"], cfg.box,
-                    cfg.r_list, cfg.skin, hphc=cfg.hphc, margin=cfg.bead_margin if path == "bead" else None)
+                    cfg.r_list, cfg.skin, hphc=cfg.hphc, margin=cfg.bead_margin)
     if model is not None:
         s.set_nn(model)
     return s
@@ -150,6 +152,8 @@ def run_md(sysm, steps, warmup, dt, path, d_cut, torch, abi):
                 pairs_within_mean=0.5 * (within0 + within1),
                 listed_pairs_evaluated=(int(f1[abi.RB_FLAG_NEVAL]) - int(f0[abi.RB_FLAG_NEVAL])) % (1 << 32),
                 rebuilds=int(f1[abi.RB_FLAG_NREBUILDS] - f0[abi.RB_FLAG_NREBUILDS]),
+                rescreens=int(f1[abi.RB_FLAG_NRESCREENS] - f0[abi.RB_FLAG_NRESCREENS]),
+                n_candidates=int(f1[abi.RB_FLAG_NSCREEN]),
                 n_listed=int(f1[abi.RB_FLAG_NPAIRS]), n_nn=int(f1[abi.RB_FLAG_NNN]), n_bead=int(f1[abi.RB_FLAG_NBEAD]))
 
 
@@ -238,14 +242,24 @@ def path_kernels(sysn, sysb, cfg, torch, abi):
     out["pair_list_rebuild"] = roof(ms, 32.0 * n + 8.0 * npairs, HBM_PEAK, "GB/s", "hbm",
                                     f"32 B per body + 8 B per listed pair ({n} bodies, {npairs} pairs)")
     m = sysn.nn
-    ms = time_launches(lambda: sysn.route(m.d_min, m.sw_hi, m.gap_min, m.gap_max), 20, torch)
+    ms = time_launches(lambda: sysn.route(m.d_min, m.sw_hi, m.gap_min, m.gap_max, two_level=False), 20, torch)
     f = sysn.flags_host()
     nnn, nbead = int(f[abi.RB_FLAG_NNN]), int(f[abi.RB_FLAG_NBEAD])
-    out["pair_descriptors_routing"] = roof(ms, 128.0 * npairs + 32.0 * (nnn + nbead), HBM_PEAK, "GB/s", "hbm",
-                                           f"128 B read per listed pair (FP64 state of both bodies, indices, "
-                                           f"types) + 32 B written per routed pair ({npairs} listed, {nnn} "
-                                           f"network, {nbead} bead)")
-    out["pair_descriptors_routing"]["note"] = "bound by the shells' arithmetic, not by HBM"
+    out["pair_descriptors_routing_full"] = roof(ms, 128.0 * npairs + 32.0 * (nnn + nbead), HBM_PEAK, "GB/s", "hbm",
+                                                f"128 B read per listed pair (FP64 state of both bodies, indices, "
+                                                f"types) + 32 B written per routed pair ({npairs} listed, {nnn} "
+                                                f"network, {nbead} bead)")
+    out["pair_descriptors_routing_full"]["note"] = "every listed pair (a screening step's work, less its list)"
+    ms = time_launches(lambda: sysn.route(m.d_min, m.sw_hi, m.gap_min, m.gap_max), 20, torch)
+    f = sysn.flags_host()
+    ncand = int(f[abi.RB_FLAG_NSCREEN])
+    nnn, nbead = int(f[abi.RB_FLAG_NNN]), int(f[abi.RB_FLAG_NBEAD])
+    out["pair_descriptors_routing"] = roof(ms, 132.0 * ncand + 32.0 * (nnn + nbead), HBM_PEAK, "GB/s", "hbm",
+                                           f"132 B read per candidate pair (its index, FP64 state of both "
+                                           f"bodies, indices, types) + 32 B written per routed pair ({ncand} "
+                                           f"candidates of {npairs} listed, {nnn} network, {nbead} bead)")
+    out["pair_descriptors_routing"]["note"] = ("two-level routing between screenings; bound by the shells' "
+                                               "arithmetic and the load latency, not by HBM")
     ms = time_launches(lambda: abi.rb_nn_pair_forces_cyl(m.params, m.norm, m.precision, sysn.q, sysn.pair_i,
                                                          sysn.pair_j, sysn.desc, sysn.idx_nn,
                                                          sysn.flags[abi.RB_FLAG_NNN:], sysn.max_pairs, m.sw_lo,

@@ -64,7 +64,8 @@ extern "C" {
                                 bead distance tests performed after culling    */
 #define RB_FLAG_NSCREEN 10   /* pairs kept by rb_bead_screen (when its count_out
                                 is &flags[NSCREEN]), or in the screened list of
-                                rb_bead_pair_forces_screened                    */
+                                rb_bead_pair_forces_screened or the candidate
+                                list of rb_pair_descriptors_screened            */
 #define RB_FLAG_RESCREEN 11  /* 1: the screened list must be rebuilt before use;
                                 set by every pair-list build and by the
                                 integrator's margin test                        */
@@ -80,8 +81,9 @@ extern "C" {
                                 renormalisation; also counts non-finite q      */
 #define RB_FLAG_ROUTE_WORK 16 /* words 16..17: one 64-bit working word of
                                 rb_pair_descriptors (network count, bead count,
-                                blocks done); zero between calls; word 18 is
-                                unused                                         */
+                                blocks done); word 18: candidate count of
+                                rb_pair_descriptors_screened; zero between
+                                calls                                          */
 #define RB_FLAG_WAIT_TIMEOUT 19 /* 1: a kernel's internal wait between waves
                                 gave up (an internal error: results invalid)   */
 #define RB_FLAG_FB_WORK 20   /* words 20..21: working counters of the bead-sum
@@ -190,6 +192,32 @@ int rb_pair_descriptors(int32_t n, const double *x, const double *q, const doubl
                         float d_min, float d_max, float *desc, int32_t *idx_nn,
                         int32_t *idx_bead, int32_t *flags, const rb_ctx *ctx,
                         const int32_t *type, float gap_min, float gap_max, void *stream);
+
+/* Two-level routing (the same routes, computed for fewer pairs): a call with
+ * flags[RESCREEN] set does what rb_pair_descriptors does with shells and
+ * also keeps, in cand_list (capacity max_pairs; flags[NSCREEN] their
+ * number; word flags[RB_FLAG_ROUTE_WORK + 2] counts during the call and is
+ * left zero), the listed pairs that can still be routed while no bead has
+ * moved by margin / 2: centres closer than d_max + margin, and closer than
+ * d_min + margin or with G below gap_max + margin; it copies x, q to x_sref
+ * (3 x n) and q_sref (4 x n), clears flags[RESCREEN] and increments
+ * flags[NRESCREENS].  A call with the flag clear writes desc for, and
+ * routes, the pairs of cand_list only, each exactly as a full call would.
+ * A listed pair left out has its centres at least d_max apart, or at least
+ * d_min apart and no bead pair within gap_max (zero bead energy when
+ * gap_max >= rc), until some bead has moved by margin / 2, which
+ * rb_rigid_step and rb_rigid_step_fused test (given x_sref, q_sref and
+ * half_margin = margin / 2) and report by setting flags[RESCREEN]; every
+ * pair-list build sets it too.  A full call may route such a pair to the
+ * network or the bead sum when its current bound is looser; this call then
+ * leaves it out.  Set flags[RESCREEN] before the first call.  ctx and type
+ * are required; gap_max > 0, 0 <= margin < 1e6. */
+int rb_pair_descriptors_screened(int32_t n, const double *x, const double *q, const double *box,
+                                 const int32_t *pair_i, const int32_t *pair_j, int32_t max_pairs,
+                                 float d_min, float d_max, float *desc, int32_t *idx_nn,
+                                 int32_t *idx_bead, int32_t *flags, const rb_ctx *ctx,
+                                 const int32_t *type, float gap_min, float gap_max, float margin,
+                                 int32_t *cand_list, double *x_sref, double *q_sref, void *stream);
 
 /* ---- bead double sum (paper section 2, first equation) -------------------
  * Every bead pair closer than rc contributes; a body pair is skipped only

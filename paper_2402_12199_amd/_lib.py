@@ -30,6 +30,8 @@ SIGNATURES = {
     "rb_pairlist_workspace_bytes": (SZ, [I32, DP, F64]),
     "rb_pairlist_build": (C.c_int, [I32, P, DP, F64, P, P, I32, P, P, C.c_int, P, SZ, P]),
     "rb_pair_descriptors": (C.c_int, [I32, P, P, DP, P, P, I32, F32, F32, P, P, P, P, P, P, F32, F32, P]),
+    "rb_pair_descriptors_screened": (C.c_int, [I32, P, P, DP, P, P, I32, F32, F32, P, P, P, P, P, P, F32, F32, F32,
+                                                P, P, P, P]),
     "rb_bead_pair_eval": (C.c_int, [P, I64, P, I32, I32, P, P, P]),
     "rb_bead_pair_forces": (C.c_int, [P, I32, P, P, P, DP, P, P, P, P, I32, P, P, P]),
     "rb_bead_pair_forces_screened": (C.c_int, [P, I32, P, P, P, DP, P, P, P, I32, F64, P, P, P, P, P, P, P]),

@@ -142,6 +142,29 @@ def rb_pair_descriptors(x, q, box, pair_i, pair_j, d_min, desc, idx_nn, idx_bead
           "rb_pair_descriptors")
 
 
+def rb_pair_descriptors_screened(x, q, box, pair_i, pair_j, d_min, desc, idx_nn, idx_bead, flags, d_max, ctx,
+                                 types, gap_min, gap_max, margin, cand_list, x_sref, q_sref):
+    """Two-level routing: the full routing (and a new candidate list) when
+    flags[RESCREEN] is set, the candidates only otherwise."""
+    n = x.shape[1]
+    maxp = pair_i.numel()
+    _, bp = _box(box)
+    check(lib().rb_pair_descriptors_screened(n, _ptr(x, torch.float64, (3, n), "x"),
+                                             _ptr(q, torch.float64, (4, n), "q"), bp,
+                                             _ptr(pair_i, torch.int32, name="pair_i"),
+                                             _ptr(pair_j, torch.int32, name="pair_j"), maxp, float(d_min),
+                                             float(d_max), _ptr(desc, torch.float32, (7, maxp), "desc"),
+                                             _ptr(idx_nn, torch.int32, (maxp,), "idx_nn"),
+                                             _ptr(idx_bead, torch.int32, (maxp,), "idx_bead"),
+                                             _ptr(flags, torch.int32, (RB_NFLAGS,), "flags"), ctx.handle,
+                                             _ptr(types, torch.int32, (n,), "types"), float(gap_min),
+                                             float(gap_max), float(margin),
+                                             _ptr(cand_list, torch.int32, (maxp,), "cand_list"),
+                                             _ptr(x_sref, torch.float64, (3, n), "x_sref"),
+                                             _ptr(q_sref, torch.float64, (4, n), "q_sref"), _stream()),
+          "rb_pair_descriptors_screened")
+
+
 def rb_bead_pair_eval(ctx: Ctx, desc, type_i: int, type_j: int, out, flags=None):
     P = desc.shape[1]
     check(lib().rb_bead_pair_eval(ctx.handle, P, _ptr(desc, torch.float32, (7, P), "desc"), type_i, type_j,

@@ -99,8 +99,14 @@ __device__ inline float cyl_gap_along(const float ca[3], const float aa[3], floa
 // 0.01 -- so that both decisions stay on the safe side).  The bounds are
 // formed from the cheapest up and the pair leaves as soon as one reaches
 // gap_max.
+//
+// gap_exit (>= gap_max): the bound at which the formation stops early;
+// keep (may be null) is set to whether the final bound stays below it.  The
+// route does not depend on gap_exit (the bound only grows).
 __device__ inline int shell_route(const Templates &T, int ti, int tj, const double dd[3], const double Rd[9],
-                                  float gap_min, float gap_max) {
+                                  float gap_min, float gap_max, float gap_exit = -1.f, bool *keep = nullptr) {
+    if (!(gap_exit >= gap_max)) gap_exit = gap_max;
+    if (keep) *keep = false;
     constexpr float kSafe = 2e-4f;
     const float a[3] = {T.hx[ti], T.hy[ti], T.hz[ti]};
     const float b[3] = {T.hx[tj], T.hy[tj], T.hz[tj]};
@@ -134,15 +140,18 @@ __device__ inline int shell_route(const Templates &T, int ti, int tj, const doub
             }
         }
     }
-    if (G - kSafe >= gap_max) return kRouteSkip;
-    if (!T.round[ti] || !T.round[tj]) return G - kSafe < gap_min ? kRouteBead : kRouteNet;
+    if (G - kSafe >= gap_exit) return kRouteSkip;
+    if (!T.round[ti] || !T.round[tj]) {
+        if (keep) *keep = true;
+        return G - kSafe >= gap_max ? kRouteSkip : (G - kSafe < gap_min ? kRouteBead : kRouteNet);
+    }
     const int ki = T.cax[ti], kj = T.cax[tj];
     const float c1[3] = {0.f, 0.f, 0.f};
     const float e1[3] = {ki == 0 ? 1.f : 0.f, ki == 1 ? 1.f : 0.f, ki == 2 ? 1.f : 0.f};
     const float e2[3] = {R[kj], R[3 + kj], R[6 + kj]};
     float cp[3];
     G = fmaxf(G, segment_distance(c1, e1, T.cH[ti], d, e2, T.cH[tj], cp) - T.cR[ti] - T.cR[tj]);
-    if (G - kSafe >= gap_max) return kRouteSkip;
+    if (G - kSafe >= gap_exit) return kRouteSkip;
     // Cylinders around the same axes (radius that of the capsule, half-height
     // the box's extent along the axis), which hold every bead centre: trial
     // directions from the capsules' closest points and from the centres,
@@ -163,7 +172,7 @@ __device__ inline int shell_route(const Templates &T, int ti, int tj, const doub
         for (int it = 0; it < 6; ++it) {
             float diff[3];
             G = fmaxf(G, cyl_gap_along(c1, e1, Ha, Ra, d, e2, Hb, Rb, n, diff));
-            if (G - kSafe >= gap_max) return kRouteSkip;
+            if (G - kSafe >= gap_exit) return kRouteSkip;
             const float dd2 = diff[0] * diff[0] + diff[1] * diff[1] + diff[2] * diff[2];
             if (!(dd2 > 1e-20f)) break;
             const float r = rsqrtf(dd2);
@@ -171,7 +180,8 @@ __device__ inline int shell_route(const Templates &T, int ti, int tj, const doub
             for (int k = 0; k < 3; ++k) n[k] = diff[k] * r;
         }
     }
-    return G - kSafe < gap_min ? kRouteBead : kRouteNet;
+    if (keep) *keep = true;
+    return G - kSafe >= gap_max ? kRouteSkip : (G - kSafe < gap_min ? kRouteBead : kRouteNet);
 }
 
 }  // namespace rb

@@ -53,9 +53,11 @@ class RigidSystem:
                  margin=None, nvt=None):
         """hphc: dict(A, b, c, p) selects the half-power half-cosine bead
         potential instead of Lennard-Jones (r_list must then cover its
-        cutoff b + pi / c).  margin: bead path over a two-level list whose
-        screened pairs are rebuilt when a body's beads may have moved by
-        margin / 2 (rb_bead_pair_forces_screened).  nvt: dict(kT, tau) runs
+        cutoff b + pi / c).  margin: two-level lists rebuilt when a body's
+        beads may have moved by margin / 2 -- the bead path's screened pairs
+        (rb_bead_pair_forces_screened) or the network path's routing
+        candidates (rb_pair_descriptors_screened); both use the rescreen
+        flag, so a system takes one of the two.  nvt: dict(kT, tau) runs
         the plain steps at constant temperature (Nose-Hoover, g = 6 n - 3,
         Q = g kT tau^2)."""
         if screen and margin is not None:
@@ -111,6 +113,8 @@ class RigidSystem:
         self.x_sref = self.q_sref = None
         if self.margin is not None:
             self.screen_list = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
+            self.cand_list = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
+            self._two_level = None   # "bead" or "route": the user of the rescreen flag
             self.x_sref = torch.zeros_like(self.x)
             self.q_sref = torch.zeros_like(self.q)
             self.tmp_two = torch.zeros(4, dtype=torch.int32, device=self.dev)
@@ -137,11 +141,28 @@ class RigidSystem:
             self.sym = torch.zeros((7, self.max_pairs), dtype=torch.float32, device=self.dev)
             self.jac = torch.zeros((49, self.max_pairs), dtype=torch.float32, device=self.dev)
 
-    def route(self, d_min, d_max, gap_min=None, gap_max=None):
+    def _take_two_level(self, user):
+        if self._two_level is None:
+            self._two_level = user
+        elif self._two_level != user:
+            raise RuntimeError(f"this system's two-level list serves the {self._two_level} path; "
+                               f"the {user} path needs a system of its own")
+
+    def route(self, d_min, d_max, gap_min=None, gap_max=None, two_level=True):
         """Descriptors of the listed pairs and their routing (network, bead
         sum, neither); with gap_min the shells' bound on the closest bead
-        distance routes as well."""
+        distance routes as well, and with a margin (two-level list) only the
+        candidates of the last screening are routed (two_level=False: every
+        listed pair)."""
         shells = gap_min is not None
+        if two_level and shells and self.margin is not None and gap_max is not None and gap_max > 0:
+            # two-level routing: the candidates of the last screening only
+            self._take_two_level("route")
+            abi.rb_pair_descriptors_screened(self.x, self.q, self.box, self.pair_i, self.pair_j, d_min, self.desc,
+                                             self.idx_nn, self.idx_bead, self.flags, d_max, self.ctx, self.types,
+                                             gap_min, gap_max, self.margin, self.cand_list, self.x_sref,
+                                             self.q_sref)
+            return
         abi.rb_pair_descriptors(self.x, self.q, self.box, self.pair_i, self.pair_j, d_min, self.desc, self.idx_nn,
                                 self.idx_bead, self.flags, d_max=d_max, ctx=self.ctx if shells else None,
                                 types=self.types if shells else None, gap_min=gap_min if shells else 0.0,
@@ -172,6 +193,7 @@ class RigidSystem:
     def bead_forces(self):
         """Bead sum over the whole list (or over the screened pairs)."""
         if self.margin is not None:
+            self._take_two_level("bead")
             abi.rb_bead_pair_forces_screened(self.ctx, self.x, self.q, self.types, self.box, self.pair_i,
                                              self.pair_j, self.flags[abi.RB_FLAG_NPAIRS:], self.max_pairs,
                                              self.margin, self.screen_list, self.x_sref, self.q_sref, self.tmp_two,
@@ -291,7 +313,7 @@ class RigidSystem:
             self.desc = torch.zeros((7, self.max_pairs), dtype=torch.float32, device=self.dev)
             self.idx_nn = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
             self.idx_bead = torch.zeros(self.max_pairs, dtype=torch.int32, device=self.dev)
-        self.route(d_min, d_max, gap_min, gap_max)
+        self.route(d_min, d_max, gap_min, gap_max, two_level=False)
         m = int(self.flags[abi.RB_FLAG_NNN].item())
         idx = torch.sort(self.idx_nn[:m].long()).values   # list order, independent of append order
         return self.desc[:, idx]

@@ -226,6 +226,72 @@ def test_routing_over_several_rounds_per_block_matches_one_round(abi, cyl_worklo
     assert len(nw) > 0 and len(bw) > 0 and len(np.unique(nw)) == len(nw)
 
 
+def test_two_level_routing_routes_its_candidates_as_the_full_routing(abi, cyl_workload):
+    # 32768 cylinders with the bead path's margin.  A screening call routes
+    # as the full routing does; after moves that keep every bead within
+    # margin / 2 the candidates alone are routed, each exactly as the full
+    # routing routes it, and a pair only the full routing sends somewhere has
+    # no bead pair within gap_max (the oracle's closest bead distance); a
+    # rescreen matches the full routing again
+    from paper_2402_12199_amd.md import RigidSystem
+    cfg, st, pairs = cyl_workload
+    b = cfg.body
+    gap_min, gap_max, margin = 1.0, 2.5, cfg.bead_margin
+    sysm = RigidSystem([b.beads], [b.mass], [b.inertia], st["types"], st["x"], st["q"], st["P"], st["L"], cfg.box,
+                       cfg.r_list, cfg.skin, margin=margin)
+    sysm.desc = torch.zeros((7, sysm.max_pairs), dtype=torch.float32, device="cuda")
+    sysm.idx_nn = torch.zeros(sysm.max_pairs, dtype=torch.int32, device="cuda")
+    sysm.idx_bead = torch.zeros(sysm.max_pairs, dtype=torch.int32, device="cuda")
+    sysm.build_pairs(always=True)
+
+    def routed(two_level):
+        sysm.route(cfg.d_min, cfg.d_cut, gap_min, gap_max, two_level=two_level)
+        f = sysm.flags_host()
+        nn = np.sort(sysm.idx_nn[:f[abi.RB_FLAG_NNN]].cpu().numpy())
+        bd = np.sort(sysm.idx_bead[:f[abi.RB_FLAG_NBEAD]].cpu().numpy())
+        return nn, bd, sysm.desc.clone(), f
+
+    nn2, bd2, desc2, f = routed(True)      # a screening call (the pair-list build set the flag)
+    assert f[abi.RB_FLAG_RESCREEN] == 0 and f[abi.RB_FLAG_NRESCREENS] == 1
+    ncand = int(f[abi.RB_FLAG_NSCREEN])
+    assert len(nn2) + len(bd2) < ncand < f[abi.RB_FLAG_NPAIRS]
+    assert (sysm.x_sref == sysm.x).all() and (sysm.q_sref == sysm.q).all()
+    cand = np.sort(sysm.cand_list[:ncand].cpu().numpy())
+    assert len(np.unique(cand)) == ncand
+    nn1, bd1, desc1, _ = routed(False)
+    np.testing.assert_array_equal(nn2, nn1)
+    np.testing.assert_array_equal(bd2, bd1)
+
+    # moves: |dx| <= 0.03 per axis, turns of 0.005 rad (beads move < 0.08 < margin / 2)
+    g = sampling.rng(41)
+    n = sysm.n
+    sysm.x += torch.tensor(g.uniform(-0.03, 0.03, (3, n)), device="cuda")
+    ax = g.normal(size=(n, 3))
+    ax /= np.linalg.norm(ax, axis=1, keepdims=True)
+    dq = np.concatenate([np.full((n, 1), np.cos(0.0025)), np.sin(0.0025) * ax], axis=1)
+    qn = oframes.qmul(sysm.q.cpu().numpy().T, dq)
+    sysm.q.copy_(torch.tensor((qn / np.linalg.norm(qn, axis=1, keepdims=True)).T.copy(), device="cuda"))
+    nn2, bd2, desc2, f = routed(True)
+    assert f[abi.RB_FLAG_NRESCREENS] == 1 and f[abi.RB_FLAG_NSCREEN] == ncand
+    nn1, bd1, desc1, _ = routed(False)
+    np.testing.assert_array_equal(nn2, np.intersect1d(nn1, cand))
+    np.testing.assert_array_equal(bd2, np.intersect1d(bd1, cand))
+    both = np.concatenate([nn2, bd2]).astype(np.int64)
+    assert torch.equal(desc2[:, both], desc1[:, both])
+    extra = np.setdiff1d(np.concatenate([nn1, bd1]), cand)
+    if len(extra):
+        pl = sysm.pairs_host()[extra[:500]]
+        xh, qh = sysm.x.cpu().numpy().T, sysm.q.cpu().numpy().T
+        u = oframes.descriptors(xh[pl[:, 0]], qh[pl[:, 0]], xh[pl[:, 1]], qh[pl[:, 1]], cfg.box)
+        assert (obeads.bead_pair_desc(b.beads, b.beads, u, rc=1e3)[:, 10] >= gap_max - 1e-9).all()
+
+    sysm.flags[abi.RB_FLAG_RESCREEN] = 1
+    nn2, bd2, _, f = routed(True)
+    assert f[abi.RB_FLAG_NRESCREENS] == 2
+    np.testing.assert_array_equal(nn2, nn1)
+    np.testing.assert_array_equal(bd2, bd1)
+
+
 def test_pair_with_overlapping_bead_boxes_goes_to_the_bead_sum(abi):
     # Body j turned so that its axis lies along x, centre 1.5 + 0.6 + 4.05
     # from body i's axis: its end cap sits 0.6 sigma from body i's side (the

@@ -8,7 +8,9 @@
 //   bin bodies into cells of edge >= r_list (count per cell)
 //   exclusive scan of cell counts -> cell starts
 //   scatter body ids into cell order, then sort each cell's ids, which makes
-//   the cell contents independent of atomic arrival order
+//   the cell contents independent of atomic arrival order (with at least 3
+//   cells on every axis the binning atomic gives each body's rank in its
+//   cell and the scatter moves its cell-relative position along)
 //   with at least 3 cells on every axis (half stencil): per position t in
 //   cell order, count the pairs with the later bodies of its own cell and
 //   the bodies of the 13 forward neighbour cells (FP32 distances from
@@ -200,34 +202,78 @@ __global__ void k_sort_cells(int ncell, int32_t n, const double *__restrict__ x,
     sort_cell_and_gather(start[c], start[c + 1], n, x, sorted, xs);
 }
 
-// Cell-order copy for the half-stencil search: per sorted position k the
-// position relative to its cell's origin in FP32 (xr, 3 x n SoA) and the
-// cell index (cs).  The offset of a neighbour cell's origin is then a whole
-// number of edges, the same for all of that cell's bodies.
-__global__ void k_sort_cells_rel(int ncell, int32_t n, const double *__restrict__ x, CellGrid g,
-                                 const int32_t *__restrict__ start, int32_t *__restrict__ sorted,
-                                 float *__restrict__ xr, int32_t *__restrict__ cs, const int32_t *flags, int mode) {
+// Half-stencil pipeline, first steps.  Binning takes each body's rank in its
+// cell from the cell counter's atomic, so that the scatter needs none: it
+// writes the body id and the body's position relative to its cell's origin
+// (FP32, a 16-byte record) at the body's place in cell order, reading the
+// positions in body order.  The per-cell sort then orders each cell's
+// (id, record) pairs by id (the cell contents no longer depend on the
+// atomics' order) and writes the cell-order copy the search reads: xr (3 x n
+// SoA) and the cell index cs.  The offset of a neighbour cell's origin is a
+// whole number of edges, the same for all of that cell's bodies.
+__global__ void k_bin_rank(int32_t n, const double *__restrict__ x, CellGrid g, int32_t *__restrict__ cell_of,
+                           int32_t *__restrict__ cnt, int32_t *__restrict__ rank, double *__restrict__ x_ref,
+                           const int32_t *flags, int mode) {
+    if (skip(flags, mode)) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double v = x[a * n + i];
+        if (x_ref) x_ref[a * n + i] = v;
+        c[a] = cell_coord(v, g.L[a], g.cinv[a], g.nc[a]);
+    }
+    const int id = (c[0] * g.nc[1] + c[1]) * g.nc[2] + c[2];
+    cell_of[i] = id;
+    rank[i] = atomicAdd(cnt + id, 1);
+}
+
+__global__ void k_scatter_rel(int32_t n, const double *__restrict__ x, CellGrid g,
+                              const int32_t *__restrict__ cell_of, const int32_t *__restrict__ start,
+                              const int32_t *__restrict__ rank, int32_t *__restrict__ sorted,
+                              float4 *__restrict__ rec, const int32_t *flags, int mode) {
+    if (skip(flags, mode)) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = cell_of[i];
+    const int pos = start[c] + rank[i];
+    const int cc[3] = {c / (g.nc[2] * g.nc[1]), (c / g.nc[2]) % g.nc[1], c % g.nc[2]};
+    float r[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double v = x[a * n + i];
+        const double w = v - g.L[a] * floor(v / g.L[a]);
+        r[a] = (float)(w - cc[a] * g.edge[a]);
+    }
+    sorted[pos] = i;
+    rec[pos] = make_float4(r[0], r[1], r[2], 0.f);
+}
+
+__global__ void k_sort_cells_rec(int ncell, int32_t n, const int32_t *__restrict__ start,
+                                 int32_t *__restrict__ sorted, float4 *__restrict__ rec, float *__restrict__ xr,
+                                 int32_t *__restrict__ cs, const int32_t *flags, int mode) {
     if (skip(flags, mode)) return;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
     const int b = start[c], e = start[c + 1];
     for (int k = b + 1; k < e; ++k) {
-        int v = sorted[k], m = k - 1;
+        const int v = sorted[k];
+        const float4 vr = rec[k];
+        int m = k - 1;
         while (m >= b && sorted[m] > v) {
             sorted[m + 1] = sorted[m];
+            rec[m + 1] = rec[m];
             --m;
         }
         sorted[m + 1] = v;
+        rec[m + 1] = vr;
     }
-    const int cc[3] = {c / (g.nc[2] * g.nc[1]), (c / g.nc[2]) % g.nc[1], c % g.nc[2]};
     for (int k = b; k < e; ++k) {
-        const int j = sorted[k];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const double v = x[a * n + j];
-            const double w = v - g.L[a] * floor(v / g.L[a]);
-            xr[a * n + k] = (float)(w - cc[a] * g.edge[a]);
-        }
+        const float4 r = rec[k];
+        xr[k] = r.x;
+        xr[n + k] = r.y;
+        xr[2 * n + k] = r.z;
         cs[k] = c;
     }
 }
@@ -611,7 +657,7 @@ __global__ __launch_bounds__(kPairThreads) void k_pl_pairs(int32_t n, const doub
 }
 
 struct PLLayout {
-    size_t cell_of, cnt, start, fill, sorted, ncount, noff, tmp, counter, xs, cs, total;
+    size_t cell_of, cnt, start, fill, sorted, ncount, noff, tmp, counter, xs, cs, rec, total;
 };
 
 static bool make_grid(int32_t n, const double *box, double r_list, CellGrid &g) {
@@ -658,6 +704,7 @@ static PLLayout layout(int32_t n, int ncell) {
     L.counter = o; o += al(sizeof(int32_t) * 2);
     L.xs = o; o += al(sizeof(double) * 3 * (size_t)n);   // FP64 copy, or the FP32 relative one
     L.cs = o; o += al(sizeof(int32_t) * n);
+    L.rec = o; o += al(sizeof(float4) * (size_t)n);
     L.total = o;
     return L;
 }
@@ -711,15 +758,16 @@ extern "C" int rb_pairlist_build(int32_t n, const double *x, const double *box, 
         return RB_OK;
     }
     const int gb = (n + 255) / 256, gc = (g.ncell + 255) / 256;
-    k_fill<<<gc, 256, 0, st>>>(cnt, g.ncell, 0, flags, mode);
-    k_fill<<<gc, 256, 0, st>>>(fill, g.ncell, 0, flags, mode);
-    k_bin<<<gb, 256, 0, st>>>(n, x, g, cell_of, cnt, x_ref, flags, mode);
-    scan(cnt, start, g.ncell, tmp, flags, mode, -1, st);
-    k_scatter<<<gb, 256, 0, st>>>(n, cell_of, start, fill, sorted, flags, mode);
     if (g.nc[0] >= 3 && g.nc[1] >= 3 && g.nc[2] >= 3) {
         float *xr = (float *)(w + L.xs);
         int32_t *cs = (int32_t *)(w + L.cs);
-        k_sort_cells_rel<<<gc, 256, 0, st>>>(g.ncell, n, x, g, start, sorted, xr, cs, flags, mode);
+        float4 *rec = (float4 *)(w + L.rec);
+        int32_t *rank = ncount;   // free until the count pass
+        k_fill<<<gc, 256, 0, st>>>(cnt, g.ncell, 0, flags, mode);
+        k_bin_rank<<<gb, 256, 0, st>>>(n, x, g, cell_of, cnt, rank, x_ref, flags, mode);
+        scan(cnt, start, g.ncell, tmp, flags, mode, -1, st);
+        k_scatter_rel<<<gb, 256, 0, st>>>(n, x, g, cell_of, start, rank, sorted, rec, flags, mode);
+        k_sort_cells_rec<<<gc, 256, 0, st>>>(g.ncell, n, start, sorted, rec, xr, cs, flags, mode);
         const int gh = (n + kHalfThreads - 1) / kHalfThreads;
         k_neigh_half<false><<<gh, kHalfThreads, 0, st>>>(n, xr, x, g, cs, start, sorted, ncount, nullptr, nullptr,
                                                          nullptr, 0, flags, mode);
@@ -730,6 +778,11 @@ extern "C" int rb_pairlist_build(int32_t n, const double *x, const double *box, 
         RB_LAUNCH_CHECK("rb_pairlist_build");
         return RB_OK;
     }
+    k_fill<<<gc, 256, 0, st>>>(cnt, g.ncell, 0, flags, mode);
+    k_fill<<<gc, 256, 0, st>>>(fill, g.ncell, 0, flags, mode);
+    k_bin<<<gb, 256, 0, st>>>(n, x, g, cell_of, cnt, x_ref, flags, mode);
+    scan(cnt, start, g.ncell, tmp, flags, mode, -1, st);
+    k_scatter<<<gb, 256, 0, st>>>(n, cell_of, start, fill, sorted, flags, mode);
     k_sort_cells<<<gc, 256, 0, st>>>(g.ncell, n, x, start, sorted, xs, flags, mode);
     k_neigh<false><<<gb, 256, 0, st>>>(n, xs, g, cell_of, start, sorted, ncount, nullptr, nullptr, nullptr, 0,
                                        flags, mode);

@@ -208,8 +208,8 @@ __global__ void k_sort_cells(int ncell, int32_t n, const double *__restrict__ x,
 // (FP32, a 16-byte record) at the body's place in cell order, reading the
 // positions in body order.  The per-cell sort then orders each cell's
 // (id, record) pairs by id (the cell contents no longer depend on the
-// atomics' order) and writes the cell-order copy the search reads: xr (3 x n
-// SoA) and the cell index cs.  The offset of a neighbour cell's origin is a
+// atomics' order) and completes the records the search reads (the body id
+// in the fourth word) and the cell index cs of each position.  The offset of a neighbour cell's origin is a
 // whole number of edges, the same for all of that cell's bodies.
 __global__ void k_bin_rank(int32_t n, const double *__restrict__ x, CellGrid g, int32_t *__restrict__ cell_of,
                            int32_t *__restrict__ cnt, int32_t *__restrict__ rank, double *__restrict__ x_ref,
@@ -250,9 +250,8 @@ __global__ void k_scatter_rel(int32_t n, const double *__restrict__ x, CellGrid 
     rec[pos] = make_float4(r[0], r[1], r[2], 0.f);
 }
 
-__global__ void k_sort_cells_rec(int ncell, int32_t n, const int32_t *__restrict__ start,
-                                 int32_t *__restrict__ sorted, float4 *__restrict__ rec, float *__restrict__ xr,
-                                 int32_t *__restrict__ cs, const int32_t *flags, int mode) {
+__global__ void k_sort_cells_rec(int ncell, const int32_t *__restrict__ start, int32_t *__restrict__ sorted,
+                                 float4 *__restrict__ rec, int32_t *__restrict__ cs, const int32_t *flags, int mode) {
     if (skip(flags, mode)) return;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
@@ -270,10 +269,7 @@ __global__ void k_sort_cells_rec(int ncell, int32_t n, const int32_t *__restrict
         rec[m + 1] = vr;
     }
     for (int k = b; k < e; ++k) {
-        const float4 r = rec[k];
-        xr[k] = r.x;
-        xr[n + k] = r.y;
-        xr[2 * n + k] = r.z;
+        rec[k].w = __int_as_float(sorted[k]);
         cs[k] = c;
     }
 }
@@ -297,19 +293,21 @@ constexpr int kHalfBatch = 3;
 
 template <bool EMIT>
 __global__ __launch_bounds__(kHalfThreads) void k_neigh_half(
-    int32_t n, const float *__restrict__ xr, const double *__restrict__ x, CellGrid g,
-    const int32_t *__restrict__ cs, const int32_t *__restrict__ start, const int32_t *__restrict__ sorted,
-    int32_t *__restrict__ ncount, const int32_t *__restrict__ noff, int32_t *__restrict__ pi,
-    int32_t *__restrict__ pj, int32_t cap, const int32_t *flags, int mode) {
+    int32_t n, const float4 *__restrict__ rec, const double *__restrict__ x, CellGrid g,
+    const int32_t *__restrict__ cs, const int32_t *__restrict__ start, int32_t *__restrict__ ncount,
+    const int32_t *__restrict__ noff, int32_t *__restrict__ pi, int32_t *__restrict__ pj, int32_t cap,
+    const int32_t *flags, int mode) {
     if (skip(flags, mode)) return;
     __shared__ int2 buf[EMIT ? kHalfThreads / kWave : 1][EMIT ? kHalfBuf : 1];
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
     const bool live = t < n;
     const int tc = live ? t : n - 1;
-    const int c = cs[tc], i = sorted[tc];
+    const int c = cs[tc];
+    const float4 own = rec[tc];
+    const int i = __float_as_int(own.w);
     const int cz = c % g.nc[2], cy = (c / g.nc[2]) % g.nc[1], cx = c / (g.nc[2] * g.nc[1]);
-    const float xi = xr[tc], yi = xr[n + tc], zi = xr[2 * n + tc];
+    const float xi = own.x, yi = own.y, zi = own.z;
     int cnt = 0;
     int wbase = 0, wtotal = 0;
     const int t0 = t - lane;   // the wave's first position
@@ -341,12 +339,12 @@ __global__ __launch_bounds__(kHalfThreads) void k_neigh_half(
     if (!live)
 #pragma unroll
         for (int q = 0; q < 14; ++q) me[q] = mb[q];
-    auto test = [&](int m, float px, float py, float pz, float ox, float oy, float oz) {
-        const float ddx = (px + ox) - xi, ddy = (py + oy) - yi, ddz = (pz + oz) - zi;
+    auto test = [&](const float4 p, float ox, float oy, float oz) {
+        const float ddx = (p.x + ox) - xi, ddy = (p.y + oy) - yi, ddz = (p.z + oz) - zi;
         const float r2 = fmaf(ddx, ddx, fmaf(ddy, ddy, ddz * ddz));
+        const int j = __float_as_int(p.w);
         bool in = r2 < g.lo2;
         if (!in && r2 < g.hi2) {
-            const int j = sorted[m];
             const double ex = min_image(x[j] - x[i], g.L[0], g.inv[0]);
             const double ey = min_image(x[n + j] - x[n + i], g.L[1], g.inv[1]);
             const double ez = min_image(x[2 * n + j] - x[2 * n + i], g.L[2], g.inv[2]);
@@ -354,7 +352,6 @@ __global__ __launch_bounds__(kHalfThreads) void k_neigh_half(
         }
         if (in) {
             if (EMIT) {
-                const int j = sorted[m];
                 const int a = i < j ? i : j, b = i < j ? j : i;
                 const int local = out - wbase;
                 if (local < kHalfBuf)
@@ -374,18 +371,13 @@ __global__ __launch_bounds__(kHalfThreads) void k_neigh_half(
         const int kk = q == 0 ? 13 : 13 + q;
         const float ox = (float)(kk / 9 - 1) * g.edge_f[0], oy = (float)((kk / 3) % 3 - 1) * g.edge_f[1],
                     oz = (float)(kk % 3 - 1) * g.edge_f[2];
-        float px[kHalfBatch], py[kHalfBatch], pz[kHalfBatch];
+        float4 pv[kHalfBatch];
 #pragma unroll
-        for (int v = 0; v < kHalfBatch; ++v) {
-            const int mm = mb[q] + v < n ? mb[q] + v : n - 1;
-            px[v] = xr[mm];
-            py[v] = xr[n + mm];
-            pz[v] = xr[2 * n + mm];
-        }
+        for (int v = 0; v < kHalfBatch; ++v) pv[v] = rec[mb[q] + v < n ? mb[q] + v : n - 1];
 #pragma unroll
         for (int v = 0; v < kHalfBatch; ++v)
-            if (mb[q] + v < me[q]) test(mb[q] + v, px[v], py[v], pz[v], ox, oy, oz);
-        for (int m = mb[q] + kHalfBatch; m < me[q]; ++m) test(m, xr[m], xr[n + m], xr[2 * n + m], ox, oy, oz);
+            if (mb[q] + v < me[q]) test(pv[v], ox, oy, oz);
+        for (int m = mb[q] + kHalfBatch; m < me[q]; ++m) test(rec[m], ox, oy, oz);
     }
     if (EMIT) {
         // the lanes' LDS writes are done before the wave reads them back
@@ -702,7 +694,7 @@ static PLLayout layout(int32_t n, int ncell) {
     L.noff = o; o += al(sizeof(int32_t) * (n + 1));
     L.tmp = o; o += al(sizeof(int32_t) * kScanTile);
     L.counter = o; o += al(sizeof(int32_t) * 2);
-    L.xs = o; o += al(sizeof(double) * 3 * (size_t)n);   // FP64 copy, or the FP32 relative one
+    L.xs = o; o += al(sizeof(double) * 3 * (size_t)n);   // FP64 copy (full-stencil search)
     L.cs = o; o += al(sizeof(int32_t) * n);
     L.rec = o; o += al(sizeof(float4) * (size_t)n);
     L.total = o;
@@ -759,7 +751,6 @@ extern "C" int rb_pairlist_build(int32_t n, const double *x, const double *box, 
     }
     const int gb = (n + 255) / 256, gc = (g.ncell + 255) / 256;
     if (g.nc[0] >= 3 && g.nc[1] >= 3 && g.nc[2] >= 3) {
-        float *xr = (float *)(w + L.xs);
         int32_t *cs = (int32_t *)(w + L.cs);
         float4 *rec = (float4 *)(w + L.rec);
         int32_t *rank = ncount;   // free until the count pass
@@ -767,13 +758,13 @@ extern "C" int rb_pairlist_build(int32_t n, const double *x, const double *box, 
         k_bin_rank<<<gb, 256, 0, st>>>(n, x, g, cell_of, cnt, rank, x_ref, flags, mode);
         scan(cnt, start, g.ncell, tmp, flags, mode, -1, st);
         k_scatter_rel<<<gb, 256, 0, st>>>(n, x, g, cell_of, start, rank, sorted, rec, flags, mode);
-        k_sort_cells_rec<<<gc, 256, 0, st>>>(g.ncell, n, start, sorted, rec, xr, cs, flags, mode);
+        k_sort_cells_rec<<<gc, 256, 0, st>>>(g.ncell, start, sorted, rec, cs, flags, mode);
         const int gh = (n + kHalfThreads - 1) / kHalfThreads;
-        k_neigh_half<false><<<gh, kHalfThreads, 0, st>>>(n, xr, x, g, cs, start, sorted, ncount, nullptr, nullptr,
-                                                         nullptr, 0, flags, mode);
+        k_neigh_half<false><<<gh, kHalfThreads, 0, st>>>(n, rec, x, g, cs, start, ncount, nullptr, nullptr, nullptr,
+                                                         0, flags, mode);
         scan(ncount, noff, n, tmp, flags, mode, max_pairs, st);
-        k_neigh_half<true><<<gh, kHalfThreads, 0, st>>>(n, xr, x, g, cs, start, sorted, nullptr, noff, pair_i,
-                                                        pair_j, max_pairs, flags, mode);
+        k_neigh_half<true><<<gh, kHalfThreads, 0, st>>>(n, rec, x, g, cs, start, nullptr, noff, pair_i, pair_j,
+                                                        max_pairs, flags, mode);
         k_finish<<<1, 1, 0, st>>>(flags, mode);
         RB_LAUNCH_CHECK("rb_pairlist_build");
         return RB_OK;

@@ -289,7 +289,7 @@ __global__ void k_sort_cells_rec(int ncell, const int32_t *__restrict__ start, i
 // pairs beyond kHalfBuf per wave go straight to memory.
 constexpr int kHalfThreads = 256;
 constexpr int kHalfBuf = 512;
-constexpr int kHalfBatch = 3;
+constexpr int kHalfBatch = 4;
 
 template <bool EMIT>
 __global__ __launch_bounds__(kHalfThreads) void k_neigh_half(

@@ -479,6 +479,7 @@ constexpr int kSmallThreads = 1024;
 constexpr int kPairThreads = 256;
 constexpr int kSmallBodies = 65536;
 constexpr int kSmallCells = 262144;
+constexpr int kSmallLdsCells = 16000;   // LDS counts: 64 000 bytes, with the scan's words below 64 KiB
 
 // Exclusive scan of in[0..m) into out[0..m) by one block; returns the total
 // (all threads).
@@ -519,34 +520,63 @@ __global__ __launch_bounds__(kSmallThreads) void k_pl_cells(int32_t n, const dou
                                                             int32_t *__restrict__ start, int32_t *__restrict__ fill,
                                                             int32_t *__restrict__ sorted, double *__restrict__ xs,
                                                             double *__restrict__ x_ref, int32_t *__restrict__ counter,
+                                                            int32_t *__restrict__ rank, int lds_counts,
                                                             const int32_t *__restrict__ flags, int mode) {
     if (skip(flags, mode)) return;
     const int t = threadIdx.x, T = kSmallThreads;
     if (t < 2) counter[t] = 0;   // pair count and finishing ticket of k_pl_pairs
-    for (int c = t; c < g.ncell; c += T) {
-        cnt[c] = 0;
-        fill[c] = 0;
-    }
-    __syncthreads();
-    for (int i = t; i < n; i += T) {
-        int c[3];
+    if (lds_counts) {
+        // cell counts in LDS (grids of at most kSmallLdsCells cells): the
+        // count's atomic gives each body its rank in the cell, so the scatter
+        // needs no atomics
+        extern __shared__ int lcnt[];
+        for (int c = t; c < g.ncell; c += T) lcnt[c] = 0;
+        __syncthreads();
+        for (int i = t; i < n; i += T) {
+            int c[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const double v = x[a * n + i];
-            if (x_ref) x_ref[a * n + i] = v;
-            c[a] = cell_coord(v, g.L[a], g.cinv[a], g.nc[a]);
+            for (int a = 0; a < 3; ++a) {
+                const double v = x[a * n + i];
+                if (x_ref) x_ref[a * n + i] = v;
+                c[a] = cell_coord(v, g.L[a], g.cinv[a], g.nc[a]);
+            }
+            const int id = (c[0] * g.nc[1] + c[1]) * g.nc[2] + c[2];
+            cell_of[i] = id;
+            rank[i] = atomicAdd(lcnt + id, 1);
         }
-        const int id = (c[0] * g.nc[1] + c[1]) * g.nc[2] + c[2];
-        cell_of[i] = id;
-        atomicAdd(cnt + id, 1);
-    }
-    __syncthreads();
-    const int total_cells = block_scan(cnt, start, g.ncell);
-    if (t == 0) start[g.ncell] = total_cells;
-    __syncthreads();
-    for (int i = t; i < n; i += T) {
-        const int c = cell_of[i];
-        sorted[start[c] + atomicAdd(fill + c, 1)] = i;
+        __syncthreads();
+        for (int c = t; c < g.ncell; c += T) cnt[c] = lcnt[c];
+        __syncthreads();
+        const int total_cells = block_scan(cnt, start, g.ncell);
+        if (t == 0) start[g.ncell] = total_cells;
+        __syncthreads();
+        for (int i = t; i < n; i += T) sorted[start[cell_of[i]] + rank[i]] = i;
+    } else {
+        for (int c = t; c < g.ncell; c += T) {
+            cnt[c] = 0;
+            fill[c] = 0;
+        }
+        __syncthreads();
+        for (int i = t; i < n; i += T) {
+            int c[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double v = x[a * n + i];
+                if (x_ref) x_ref[a * n + i] = v;
+                c[a] = cell_coord(v, g.L[a], g.cinv[a], g.nc[a]);
+            }
+            const int id = (c[0] * g.nc[1] + c[1]) * g.nc[2] + c[2];
+            cell_of[i] = id;
+            atomicAdd(cnt + id, 1);
+        }
+        __syncthreads();
+        const int total_cells = block_scan(cnt, start, g.ncell);
+        if (t == 0) start[g.ncell] = total_cells;
+        __syncthreads();
+        for (int i = t; i < n; i += T) {
+            const int c = cell_of[i];
+            sorted[start[c] + atomicAdd(fill + c, 1)] = i;
+        }
     }
     __syncthreads();
     for (int c = t; c < g.ncell; c += T) sort_cell_and_gather(start[c], start[c + 1], n, x, sorted, xs);
@@ -617,8 +647,9 @@ __global__ __launch_bounds__(kPairThreads) void k_pl_pairs(int32_t n, const doub
         c = (nx * g.nc[1] + ny) * g.nc[2] + nz;
         cnt = cell_pairs<false>(i, c, xi, yi, zi, n, xs, g, start, sorted, 0, pi, pj, cap);
     }
-    // offsets of the lanes within the body's run (half-wave scan), one
-    // reservation per body
+    // offsets of the lanes within the body's run (half-wave scan), then of
+    // the bodies within the block's run (one reservation per block: many
+    // reservations on one counter serialise)
     int incl = cnt;
 #pragma unroll
     for (int o = 1; o < 32; o <<= 1) {
@@ -626,19 +657,29 @@ __global__ __launch_bounds__(kPairThreads) void k_pl_pairs(int32_t n, const doub
         if (k >= o) incl += v;
     }
     const int total = __shfl(incl, 31, 32);
-    int base = 0;
-    if (k == 0 && total > 0) base = atomicAdd(counter, total);
-    base = __shfl(base, 0, 32);
-    if (active && cnt > 0)
-        (void)cell_pairs<true>(i, c, xi, yi, zi, n, xs, g, start, sorted, base + incl - cnt, pi, pj, cap);
+    __shared__ int btot[kPairThreads / 32], bbase;
+    const int hw = threadIdx.x >> 5;
+    if (k == 0) btot[hw] = total;
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
-        last = atomicAdd(counter + 1, 1) == (int)gridDim.x - 1;
+        int sum = 0;
+        for (int h = 0; h < kPairThreads / 32; ++h) {
+            const int v = btot[h];
+            btot[h] = sum;
+            sum += v;
+        }
+        bbase = sum > 0 ? atomicAdd(counter, sum) : 0;
     }
     __syncthreads();
+    const int base = bbase + btot[hw];
+    if (active && cnt > 0)
+        (void)cell_pairs<true>(i, c, xi, yi, zi, n, xs, g, start, sorted, base + incl - cnt, pi, pj, cap);
+    // No fence: the block's reservation has returned before its ticket, and
+    // the last block reads the counter with an agent-scope load; the pairs
+    // reach their consumers through the kernel boundary.
+    if (threadIdx.x == 0) last = atomicAdd(counter + 1, 1) == (int)gridDim.x - 1;
+    __syncthreads();
     if (last && threadIdx.x == 0) {
-        __threadfence();
         const int tot = __hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         flags[RB_FLAG_NPAIRS] = tot < cap ? tot : cap;
         flags[RB_FLAG_OVERFLOW] = tot > cap ? tot : 0;
@@ -741,8 +782,9 @@ extern "C" int rb_pairlist_build(int32_t n, const double *x, const double *box, 
     hipStream_t st = (hipStream_t)stream;
     if (n <= kSmallBodies && g.ncell <= kSmallCells) {
         int32_t *counter = (int32_t *)(w + L.counter);
-        k_pl_cells<<<1, kSmallThreads, 0, st>>>(n, x, g, cell_of, cnt, start, fill, sorted, xs, x_ref, counter,
-                                                flags, mode);
+        const int lds_counts = g.ncell <= kSmallLdsCells;
+        k_pl_cells<<<1, kSmallThreads, lds_counts ? sizeof(int) * g.ncell : 0, st>>>(
+            n, x, g, cell_of, cnt, start, fill, sorted, xs, x_ref, counter, ncount, lds_counts, flags, mode);
         const int bodies_per_block = 2 * kPairThreads / kWave;
         k_pl_pairs<<<(n + bodies_per_block - 1) / bodies_per_block, kPairThreads, 0, st>>>(
             n, xs, g, cell_of, start, sorted, pair_i, pair_j, max_pairs, counter, flags, mode);

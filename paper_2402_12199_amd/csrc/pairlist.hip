@@ -616,10 +616,8 @@ __global__ __launch_bounds__(kPairThreads) void k_pl_pairs(int32_t n, const doub
                                                            int32_t *__restrict__ flags, int mode) {
     if (skip(flags, mode)) return;
     __shared__ bool last;
-    const int lane = threadIdx.x & (kWave - 1), k = lane & 31;
-    // half-wave t takes the t-th body in cell order (neighbouring half-waves
-    // scan the same cells)
-    const int t = (int)(((int64_t)blockIdx.x * (kPairThreads / kWave) + (threadIdx.x >> 6)) * 2 + (lane >> 5));
+    __shared__ int btot[kPairThreads / 32], bbase;
+    const int lane = threadIdx.x & (kWave - 1), k = lane & 31, hw = threadIdx.x >> 5;
     // neighbour cells per axis: all three offsets, or every cell when the
     // axis has fewer than three
     int lo[3], m[3];
@@ -628,55 +626,62 @@ __global__ __launch_bounds__(kPairThreads) void k_pl_pairs(int32_t n, const doub
         lo[a] = g.nc[a] >= 3 ? -1 : 0;
         m[a] = g.nc[a] >= 3 ? 3 : g.nc[a];
     }
-    const bool active = t < n && k < m[0] * m[1] * m[2];
-    double xi = 0, yi = 0, zi = 0;
-    int i = 0, c = 0, cnt = 0;
-    if (active) {
-        i = sorted[t];
-        xi = xs[t];
-        yi = xs[n + t];
-        zi = xs[2 * n + t];
-        const int id = cell_of[i];
-        const int cz = id % g.nc[2], cy = (id / g.nc[2]) % g.nc[1], cx = id / (g.nc[2] * g.nc[1]);
-        int nx = cx + lo[0] + k / (m[1] * m[2]);
-        int ny = cy + lo[1] + (k / m[2]) % m[1];
-        int nz = cz + lo[2] + k % m[2];
-        nx += nx < 0 ? g.nc[0] : (nx >= g.nc[0] ? -g.nc[0] : 0);
-        ny += ny < 0 ? g.nc[1] : (ny >= g.nc[1] ? -g.nc[1] : 0);
-        nz += nz < 0 ? g.nc[2] : (nz >= g.nc[2] ? -g.nc[2] : 0);
-        c = (nx * g.nc[1] + ny) * g.nc[2] + nz;
-        cnt = cell_pairs<false>(i, c, xi, yi, zi, n, xs, g, start, sorted, 0, pi, pj, cap);
-    }
-    // offsets of the lanes within the body's run (half-wave scan), then of
-    // the bodies within the block's run (one reservation per block: many
-    // reservations on one counter serialise)
-    int incl = cnt;
-#pragma unroll
-    for (int o = 1; o < 32; o <<= 1) {
-        const int v = __shfl_up(incl, o, 32);
-        if (k >= o) incl += v;
-    }
-    const int total = __shfl(incl, 31, 32);
-    __shared__ int btot[kPairThreads / 32], bbase;
-    const int hw = threadIdx.x >> 5;
-    if (k == 0) btot[hw] = total;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int sum = 0;
-        for (int h = 0; h < kPairThreads / 32; ++h) {
-            const int v = btot[h];
-            btot[h] = sum;
-            sum += v;
+    // a persistent grid (so that a launch with no rebuild flagged costs few
+    // workgroups): each round, half-wave h of the block takes the body at
+    // cell-order position base + h (neighbouring half-waves scan the same
+    // cells)
+    constexpr int kBodies = kPairThreads / 32;
+    for (int base = blockIdx.x * kBodies; base < n; base += gridDim.x * kBodies) {
+        const int t = base + hw;
+        const bool active = t < n && k < m[0] * m[1] * m[2];
+        double xi = 0, yi = 0, zi = 0;
+        int i = 0, c = 0, cnt = 0;
+        if (active) {
+            i = sorted[t];
+            xi = xs[t];
+            yi = xs[n + t];
+            zi = xs[2 * n + t];
+            const int id = cell_of[i];
+            const int cz = id % g.nc[2], cy = (id / g.nc[2]) % g.nc[1], cx = id / (g.nc[2] * g.nc[1]);
+            int nx = cx + lo[0] + k / (m[1] * m[2]);
+            int ny = cy + lo[1] + (k / m[2]) % m[1];
+            int nz = cz + lo[2] + k % m[2];
+            nx += nx < 0 ? g.nc[0] : (nx >= g.nc[0] ? -g.nc[0] : 0);
+            ny += ny < 0 ? g.nc[1] : (ny >= g.nc[1] ? -g.nc[1] : 0);
+            nz += nz < 0 ? g.nc[2] : (nz >= g.nc[2] ? -g.nc[2] : 0);
+            c = (nx * g.nc[1] + ny) * g.nc[2] + nz;
+            cnt = cell_pairs<false>(i, c, xi, yi, zi, n, xs, g, start, sorted, 0, pi, pj, cap);
         }
-        bbase = sum > 0 ? atomicAdd(counter, sum) : 0;
+        // offsets of the lanes within the body's run (half-wave scan), then
+        // of the bodies within the block's run (one reservation per block
+        // and round: many reservations on one counter serialise)
+        int incl = cnt;
+#pragma unroll
+        for (int o = 1; o < 32; o <<= 1) {
+            const int v = __shfl_up(incl, o, 32);
+            if (k >= o) incl += v;
+        }
+        const int total = __shfl(incl, 31, 32);
+        if (k == 0) btot[hw] = total;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int sum = 0;
+            for (int h = 0; h < kBodies; ++h) {
+                const int v = btot[h];
+                btot[h] = sum;
+                sum += v;
+            }
+            bbase = sum > 0 ? atomicAdd(counter, sum) : 0;
+        }
+        __syncthreads();
+        const int off = bbase + btot[hw];
+        if (active && cnt > 0)
+            (void)cell_pairs<true>(i, c, xi, yi, zi, n, xs, g, start, sorted, off + incl - cnt, pi, pj, cap);
+        __syncthreads();   // btot and bbase are reused by the next round
     }
-    __syncthreads();
-    const int base = bbase + btot[hw];
-    if (active && cnt > 0)
-        (void)cell_pairs<true>(i, c, xi, yi, zi, n, xs, g, start, sorted, base + incl - cnt, pi, pj, cap);
-    // No fence: the block's reservation has returned before its ticket, and
-    // the last block reads the counter with an agent-scope load; the pairs
-    // reach their consumers through the kernel boundary.
+    // No fence: every reservation of the block has returned before its
+    // ticket, and the last block reads the counter with an agent-scope load;
+    // the pairs reach their consumers through the kernel boundary.
     if (threadIdx.x == 0) last = atomicAdd(counter + 1, 1) == (int)gridDim.x - 1;
     __syncthreads();
     if (last && threadIdx.x == 0) {
@@ -785,8 +790,7 @@ extern "C" int rb_pairlist_build(int32_t n, const double *x, const double *box, 
         const int lds_counts = g.ncell <= kSmallLdsCells;
         k_pl_cells<<<1, kSmallThreads, lds_counts ? sizeof(int) * g.ncell : 0, st>>>(
             n, x, g, cell_of, cnt, start, fill, sorted, xs, x_ref, counter, ncount, lds_counts, flags, mode);
-        const int bodies_per_block = 2 * kPairThreads / kWave;
-        k_pl_pairs<<<(n + bodies_per_block - 1) / bodies_per_block, kPairThreads, 0, st>>>(
+        k_pl_pairs<<<grid_for(n, kPairThreads / 32, 2 * device_cu_count()), kPairThreads, 0, st>>>(
             n, xs, g, cell_of, start, sorted, pair_i, pair_j, max_pairs, counter, flags, mode);
         RB_LAUNCH_CHECK("rb_pairlist_build");
         return RB_OK;

@@ -108,8 +108,10 @@ struct RouteScreen {
 // bead has moved margin / 2: centres closer than d_max + margin, and closer
 // than d_min + margin or with the shells' bound below gap_max + margin); a
 // launch with the flag clear routes the candidates only.  A candidate is
-// routed exactly as by a launch over the whole list.
-template <bool SCREENED>
+// routed exactly as by a launch over the whole list.  ONE: the context has a
+// single template, so the shells' sizes are the same for every pair (uniform
+// values, no type loads).
+template <bool SCREENED, bool ONE>
 __global__ __launch_bounds__(kDescThreads) void k_descriptors(int32_t n, const double *__restrict__ x,
                                                      const double *__restrict__ q, double L0, double L1, double L2,
                                                      const int32_t *__restrict__ pi, const int32_t *__restrict__ pj,
@@ -196,7 +198,8 @@ __global__ __launch_bounds__(kDescThreads) void k_descriptors(int32_t n, const d
             if (type && in_range && !near) {
                 double Rr[9];
                 quat_to_rot<double>(rw, rx, ry, rz, Rr);
-                const int route = shell_route(T, type[i], type[j], d, Rr, gap_min, gap_max, gap_exit, &keep);
+                const int route = ONE ? shell_route(T, 0, 0, d, Rr, gap_min, gap_max, gap_exit, &keep)
+                                      : shell_route(T, type[i], type[j], d, Rr, gap_min, gap_max, gap_exit, &keep);
                 near = route == kRouteBead;
                 far = route == kRouteSkip;
             }
@@ -249,14 +252,16 @@ static int route_launch(const char *who, int32_t n, const double *x, const doubl
     if (ctx) T = ctx->dev.t;
     const float gmax = gap_max > 0.f ? gap_max : 3.0e38f;
     const int grid = grid_for(max_pairs, kWave, std::min(device_cu_count(), kRouteMaxBlocks));
+    const bool one = ctx && ctx->n_types == 1;
+    const RouteScreen S0 = S ? *S : RouteScreen{};
+    auto go = [&](auto kernel) {
+        kernel<<<grid, kDescThreads, 0, st>>>(n, x, q, box[0], box[1], box[2], pair_i, pair_j, max_pairs, dm2, dx2,
+                                              desc, idx_nn, idx_bead, flags, T, type, gap_min, gmax, S0);
+    };
     if (S)
-        k_descriptors<true><<<grid, kDescThreads, 0, st>>>(n, x, q, box[0], box[1], box[2], pair_i, pair_j,
-                                                           max_pairs, dm2, dx2, desc, idx_nn, idx_bead, flags, T,
-                                                           type, gap_min, gmax, *S);
+        one ? go(k_descriptors<true, true>) : go(k_descriptors<true, false>);
     else
-        k_descriptors<false><<<grid, kDescThreads, 0, st>>>(n, x, q, box[0], box[1], box[2], pair_i, pair_j,
-                                                            max_pairs, dm2, dx2, desc, idx_nn, idx_bead, flags, T,
-                                                            type, gap_min, gmax, RouteScreen{});
+        one ? go(k_descriptors<false, true>) : go(k_descriptors<false, false>);
     RB_LAUNCH_CHECK(who);
     return RB_OK;
 }

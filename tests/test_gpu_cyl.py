@@ -185,6 +185,36 @@ def test_shell_routing_matches_oracle_and_keeps_the_network_in_its_domain(abi, c
     _check_routes(abi, cfg, st, got_pairs[order], nn_ids[order], bd_ids[order], gap_min, gap_max)
 
 
+def test_routing_with_two_identical_templates_equals_the_single_template_routing(abi, cyl_workload):
+    # The routing kernel has a form for single-template contexts (uniform
+    # shell sizes) and the general one (per-pair type lookups); the same
+    # cylinders under a context with the template given twice (types
+    # alternating) must get the same descriptors and the same routes
+    from paper_2402_12199_amd.md import RigidSystem
+    cfg, st, pairs = cyl_workload
+    b = cfg.body
+    out = []
+    for ntypes in (1, 2):
+        types = (np.arange(cfg.n_bodies) % ntypes).astype(np.int32)
+        sysm = RigidSystem([b.beads] * ntypes, [b.mass] * ntypes, [b.inertia] * ntypes, types, st["x"], st["q"],
+                           st["P"], st["L"], cfg.box, cfg.r_list, cfg.skin)
+        sysm.desc = torch.zeros((7, sysm.max_pairs), dtype=torch.float32, device="cuda")
+        sysm.idx_nn = torch.zeros(sysm.max_pairs, dtype=torch.int32, device="cuda")
+        sysm.idx_bead = torch.zeros(sysm.max_pairs, dtype=torch.int32, device="cuda")
+        sysm.build_pairs(always=True)
+        sysm.route(cfg.d_min, cfg.d_cut, 1.0, 2.5)
+        f = sysm.check_capacity()
+        p = sysm.pairs_host()
+        key = p[:, 0].astype(np.int64) * cfg.n_bodies + p[:, 1]
+        nn = np.sort(key[sysm.idx_nn[:f[abi.RB_FLAG_NNN]].cpu().numpy()])
+        bd = np.sort(key[sysm.idx_bead[:f[abi.RB_FLAG_NBEAD]].cpu().numpy()])
+        order = np.argsort(key)
+        out.append((nn, bd, sysm.desc[:, :len(key)].cpu().numpy()[:, order]))
+    assert len(out[0][0]) > 10000 and len(out[0][1]) > 500
+    for a0, a1 in zip(out[0], out[1]):
+        np.testing.assert_array_equal(a1, a0)
+
+
 def test_routing_over_several_rounds_per_block_matches_one_round(abi, cyl_workload):
     # 18 copies of the 32768-cylinder pair list (~610k entries, more than the
     # routing grid's 512 blocks of 1024 threads take in one round): the whole

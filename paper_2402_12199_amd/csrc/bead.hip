@@ -265,16 +265,21 @@ __global__ __launch_bounds__(kMdWaves * kWave) __attribute__((amdgpu_waves_per_e
                 pid = idx ? idx[p] : p;
             i = pi[pid];
             j = pj[pid];
-            ti = type[i];
-            tj = type[j];
+            // one template: uniform shell sizes, no type loads
+            const bool one = T.n_types == 1;
+            ti = one ? 0 : type[i];
+            tj = one ? 0 : type[j];
             double R[9], Ri[9];
             pair_frame(n, x, q, box, i, j, dl, d, qr, qa, Ri);
             quat_to_rot<double>(qr[0], qr[1], qr[2], qr[3], R);
             // the shells' bound on the closest bead distance (box, and for
             // cylinder-like types capsule and cylinder) decides which pairs
             // can have a bead pair within rc
-            hit = shell_route(T, ti, tj, d, R, 0.f, rcm) != kRouteSkip;
-            if (SCREENED && full) wide = hit || shell_route(T, ti, tj, d, R, 0.f, S.rcm_wide) != kRouteSkip;
+            auto route = [&](float gap_max) {
+                return one ? shell_route(T, 0, 0, d, R, 0.f, gap_max) : shell_route(T, ti, tj, d, R, 0.f, gap_max);
+            };
+            hit = route(rcm) != kRouteSkip;
+            if (SCREENED && full) wide = hit || route(S.rcm_wide) != kRouteSkip;
         }
         if (SCREENED && full) {
             list_append(hit, pid, S.tmp, S.list, max_count, false, lane);

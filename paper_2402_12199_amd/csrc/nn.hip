@@ -733,7 +733,8 @@ __global__ __launch_bounds__(kWideThreads) void k_nn_wide(NNArgs a) {
             if (k >= nbead) break;
             const int pid = a.idx_bead[k];
             const int i = a.pi[pid], j = a.pj[pid];
-            const int ti = a.type[i], tj = a.type[j];
+            const bool one = a.T.n_types == 1;   // one template: no type loads
+            const int ti = one ? 0 : a.type[i], tj = one ? 0 : a.type[j];
             double dl[3], d[3], qr[4], qa[4], Ri[9], R[9];
             pair_frame(a.n, a.x, a.q, a.box, i, j, dl, d, qr, qa, Ri);
             quat_to_rot<double>(qr[0], qr[1], qr[2], qr[3], R);

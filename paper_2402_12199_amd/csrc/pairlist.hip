@@ -1,8 +1,8 @@
 // Cell-list pair builder: half list (i < j) of body pairs whose minimum-image
 // centre distance is below r_list.
 //
-// Up to 65536 bodies: the two-launch pipeline below (k_pl_cells,
-// k_pl_pairs).  Beyond: the multi-kernel pipeline (each kernel returns at
+// Up to 65536 bodies: the one-launch pipeline below (k_pl_small).  Beyond:
+// the multi-kernel pipeline (each kernel returns at
 // once when the list is only rebuilt on request and the rebuild flag is
 // clear, so the whole sequence can sit in a captured graph):
 //   bin bodies into cells of edge >= r_list (count per cell)
@@ -464,19 +464,19 @@ __global__ void k_finish(int32_t *flags, int mode) {
     flags[RB_FLAG_RESCREEN] = 1;   // a screened list drawn from the old list is stale
 }
 
-// ----------------------------------------------------- two-launch pipeline
-// For up to kSmallBodies bodies a rebuild takes two launches, each of which
-// returns at once when no rebuild is flagged:
-//   k_pl_cells (one workgroup, barriers between phases): bin, scan the cell
-//     counts, scatter, sort each cell
-//   k_pl_pairs (many workgroups): half a wave per body, one lane per
-//     neighbour cell; the lanes count their pairs, the body reserves room
-//     for all of them with one atomic, and the lanes write them; the last
-//     workgroup to finish publishes the count and clears the rebuild flag.
+// ----------------------------------------------------- one-launch pipeline
+// For up to kSmallBodies bodies a rebuild is one launch, which returns at
+// once when no rebuild is flagged (k_pl_small):
+//   the cell phase (workgroup 0, barriers between steps): bin, scan the
+//     cell counts, scatter, sort each cell
+//   the pair phase (every workgroup, once the cell phase is done): half a
+//     wave per body, one lane per neighbour cell; the lanes count their
+//     pairs, the body reserves room for all of them with one atomic, and the
+//     lanes write them; the last workgroup to finish publishes the count and
+//     clears the rebuild flag.
 // The pairs of one body are contiguous and in cell order; the order of the
 // bodies' runs in the list follows the reservations and is not fixed.
 constexpr int kSmallThreads = 1024;
-constexpr int kPairThreads = 256;
 constexpr int kSmallBodies = 65536;
 constexpr int kSmallCells = 262144;
 constexpr int kSmallLdsCells = 16000;   // LDS counts: 64 000 bytes, with the scan's words below 64 KiB
@@ -515,16 +515,13 @@ __device__ int block_scan(const int32_t *in, int32_t *out, int m) {
 }
 
 
-__global__ __launch_bounds__(kSmallThreads) void k_pl_cells(int32_t n, const double *__restrict__ x, CellGrid g,
-                                                            int32_t *__restrict__ cell_of, int32_t *__restrict__ cnt,
-                                                            int32_t *__restrict__ start, int32_t *__restrict__ fill,
-                                                            int32_t *__restrict__ sorted, double *__restrict__ xs,
-                                                            double *__restrict__ x_ref, int32_t *__restrict__ counter,
-                                                            int32_t *__restrict__ rank, int lds_counts,
-                                                            const int32_t *__restrict__ flags, int mode) {
-    if (skip(flags, mode)) return;
+// The cell phase of a rebuild, by one workgroup.
+__device__ void pl_cells(int32_t n, const double *__restrict__ x, const CellGrid &g, int32_t *__restrict__ cell_of,
+                         int32_t *__restrict__ cnt, int32_t *__restrict__ start, int32_t *__restrict__ fill,
+                         int32_t *__restrict__ sorted, double *__restrict__ xs, double *__restrict__ x_ref,
+                         int32_t *__restrict__ counter, int32_t *__restrict__ rank, int lds_counts) {
     const int t = threadIdx.x, T = kSmallThreads;
-    if (t < 2) counter[t] = 0;   // pair count and finishing ticket of k_pl_pairs
+    if (t < 2) counter[t] = 0;   // pair count and finishing ticket of the pair phase
     if (lds_counts) {
         // cell counts in LDS (grids of at most kSmallLdsCells cells): the
         // count's atomic gives each body its rank in the cell, so the scatter
@@ -607,16 +604,14 @@ __device__ inline int cell_pairs(int i, int c, double xi, double yi, double zi, 
     return cnt;
 }
 
-__global__ __launch_bounds__(kPairThreads) void k_pl_pairs(int32_t n, const double *__restrict__ xs, CellGrid g,
-                                                           const int32_t *__restrict__ cell_of,
-                                                           const int32_t *__restrict__ start,
-                                                           const int32_t *__restrict__ sorted,
-                                                           int32_t *__restrict__ pi, int32_t *__restrict__ pj,
-                                                           int32_t cap, int32_t *__restrict__ counter,
-                                                           int32_t *__restrict__ flags, int mode) {
-    if (skip(flags, mode)) return;
+// The pair phase, by every workgroup of the grid once the cell phase is
+// visible to it.
+__device__ void pl_pairs(int32_t n, const double *__restrict__ xs, const CellGrid &g,
+                         const int32_t *__restrict__ cell_of, const int32_t *__restrict__ start,
+                         const int32_t *__restrict__ sorted, int32_t *__restrict__ pi, int32_t *__restrict__ pj,
+                         int32_t cap, int32_t *__restrict__ counter, int32_t *__restrict__ flags) {
     __shared__ bool last;
-    __shared__ int btot[kPairThreads / 32], bbase;
+    __shared__ int btot[kSmallThreads / 32], bbase;
     const int lane = threadIdx.x & (kWave - 1), k = lane & 31, hw = threadIdx.x >> 5;
     // neighbour cells per axis: all three offsets, or every cell when the
     // axis has fewer than three
@@ -630,7 +625,7 @@ __global__ __launch_bounds__(kPairThreads) void k_pl_pairs(int32_t n, const doub
     // workgroups): each round, half-wave h of the block takes the body at
     // cell-order position base + h (neighbouring half-waves scan the same
     // cells)
-    constexpr int kBodies = kPairThreads / 32;
+    constexpr int kBodies = kSmallThreads / 32;
     for (int base = blockIdx.x * kBodies; base < n; base += gridDim.x * kBodies) {
         const int t = base + hw;
         const bool active = t < n && k < m[0] * m[1] * m[2];
@@ -692,6 +687,53 @@ __global__ __launch_bounds__(kPairThreads) void k_pl_pairs(int32_t n, const doub
         flags[RB_FLAG_NREBUILDS] += 1;
         flags[RB_FLAG_RESCREEN] = 1;   // a screened list drawn from the old list is stale
     }
+}
+
+// A rebuild in one launch (and a launch that returns at once when none is
+// flagged): workgroup 0 runs the cell phase and then sets flags[REBUILD] to
+// kCellsDone (after a fence, so its writes are visible to every CU); the
+// other workgroups wait for that value, fence, and join the pair phase,
+// whose last workgroup clears the flag.  Only workgroup 0 is waited for, and
+// it is dispatched first, so the wait ends; it is bounded all the same (past
+// kCellsWaitSpins polls of ~3 us the workgroup records a timeout and goes
+// on, leaving the list invalid).  A workgroup that starts after workgroup 0
+// finished its phase sees kCellsDone, not 0, and takes part.
+constexpr int kCellsDone = 2;
+constexpr int kCellsWaitSpins = 1 << 16;
+
+__global__ __launch_bounds__(kSmallThreads) void k_pl_small(int32_t n, const double *__restrict__ x, CellGrid g,
+                                                            int32_t *__restrict__ cell_of, int32_t *__restrict__ cnt,
+                                                            int32_t *__restrict__ start, int32_t *__restrict__ fill,
+                                                            int32_t *__restrict__ sorted, double *__restrict__ xs,
+                                                            double *__restrict__ x_ref, int32_t *__restrict__ counter,
+                                                            int32_t *__restrict__ rank, int lds_counts,
+                                                            int32_t *__restrict__ pi, int32_t *__restrict__ pj,
+                                                            int32_t cap, int32_t *__restrict__ flags, int mode) {
+    if (skip(flags, mode)) return;
+    if (blockIdx.x == 0) {
+        pl_cells(n, x, g, cell_of, cnt, start, fill, sorted, xs, x_ref, counter, rank, lds_counts);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            __hip_atomic_store(flags + RB_FLAG_REBUILD, kCellsDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    } else {
+        if (threadIdx.x == 0) {
+            for (int spin = 0;; ++spin) {
+                if (__hip_atomic_load(flags + RB_FLAG_REBUILD, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                    kCellsDone)
+                    break;
+                if (spin >= kCellsWaitSpins) {
+                    atomicOr(flags + RB_FLAG_WAIT_TIMEOUT, 1);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(127);
+            }
+            __threadfence();
+        }
+        __syncthreads();
+    }
+    pl_pairs(n, xs, g, cell_of, start, sorted, pi, pj, cap, counter, flags);
 }
 
 struct PLLayout {
@@ -788,10 +830,10 @@ extern "C" int rb_pairlist_build(int32_t n, const double *x, const double *box, 
     if (n <= kSmallBodies && g.ncell <= kSmallCells) {
         int32_t *counter = (int32_t *)(w + L.counter);
         const int lds_counts = g.ncell <= kSmallLdsCells;
-        k_pl_cells<<<1, kSmallThreads, lds_counts ? sizeof(int) * g.ncell : 0, st>>>(
-            n, x, g, cell_of, cnt, start, fill, sorted, xs, x_ref, counter, ncount, lds_counts, flags, mode);
-        k_pl_pairs<<<grid_for(n, kPairThreads / 32, 2 * device_cu_count()), kPairThreads, 0, st>>>(
-            n, xs, g, cell_of, start, sorted, pair_i, pair_j, max_pairs, counter, flags, mode);
+        k_pl_small<<<grid_for(n, kSmallThreads / 32, device_cu_count()), kSmallThreads,
+                     lds_counts ? sizeof(int) * g.ncell : 0, st>>>(n, x, g, cell_of, cnt, start, fill, sorted, xs,
+                                                                   x_ref, counter, ncount, lds_counts, pair_i, pair_j,
+                                                                   max_pairs, flags, mode);
         RB_LAUNCH_CHECK("rb_pairlist_build");
         return RB_OK;
     }

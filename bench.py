@@ -62,15 +62,15 @@ GAP_MIN, GAP_MAX, SAMPLE_GAP_MIN = 1.0, 2.5, 0.8
 
 # HBM bytes per launch of the network path's forces kernel on the headline
 # workload at its start (31.3k network pairs, 2.5k fallback pairs), from two
-# rocprofv3 counter runs (FETCH_SIZE 8415.88 KiB x 2.000, WRITE_SIZE
-# 12724.62 KiB x 1.000; the factors are what the counters read for a 256 MiB
+# rocprofv3 counter runs (FETCH_SIZE 8204.81 KiB x 2.000, WRITE_SIZE
+# 12726.69 KiB x 1.000; the factors are what the counters read for a 256 MiB
 # copy), see profiles/k_nn_wide_cyl32768_hbm_traffic.txt.  Valid only for the
 # kernel sources they were taken on (hash below); otherwise reported as null.
-NN_TRAFFIC_BYTES = 30265733
+NN_TRAFFIC_BYTES = 29835581
 NN_TRAFFIC_SOURCES = ("paper_2402_12199_amd/csrc/nn.hip", "paper_2402_12199_amd/csrc/nn_tile.hpp",
                       "paper_2402_12199_amd/csrc/nn_common.hpp", "paper_2402_12199_amd/csrc/cyl_form.hpp",
                       "paper_2402_12199_amd/csrc/rb_common.hpp", "paper_2402_12199_amd/csrc/bead_pair.hpp")
-NN_TRAFFIC_HASH = "030ce455874145af"
+NN_TRAFFIC_HASH = "45f80cbe9c57f728"
 
 
 def sources_hash(files):

@@ -480,6 +480,8 @@ constexpr int kSmallThreads = 1024;
 constexpr int kSmallBodies = 65536;
 constexpr int kSmallCells = 262144;
 constexpr int kSmallLdsCells = 16000;   // LDS counts: 64 000 bytes, with the scan's words below 64 KiB
+constexpr int kCellBatch = 4;           // bodies per thread and pass in the cell phase
+constexpr int kSmallCell = 8;           // cells up to this size are sorted in registers
 
 // Exclusive scan of in[0..m) into out[0..m) by one block; returns the total
 // (all threads).
@@ -529,25 +531,48 @@ __device__ void pl_cells(int32_t n, const double *__restrict__ x, const CellGrid
         extern __shared__ int lcnt[];
         for (int c = t; c < g.ncell; c += T) lcnt[c] = 0;
         __syncthreads();
-        for (int i = t; i < n; i += T) {
-            int c[3];
+        // kCellBatch bodies per thread and pass, their loads issued together
+        for (int i0 = t; i0 < n; i0 += kCellBatch * T) {
+            double v[kCellBatch][3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const double v = x[a * n + i];
-                if (x_ref) x_ref[a * n + i] = v;
-                c[a] = cell_coord(v, g.L[a], g.cinv[a], g.nc[a]);
+            for (int u = 0; u < kCellBatch; ++u) {
+                const int i = i0 + u * T;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) v[u][a] = i < n ? x[a * n + i] : 0.0;
             }
-            const int id = (c[0] * g.nc[1] + c[1]) * g.nc[2] + c[2];
-            cell_of[i] = id;
-            rank[i] = atomicAdd(lcnt + id, 1);
+#pragma unroll
+            for (int u = 0; u < kCellBatch; ++u) {
+                const int i = i0 + u * T;
+                if (i >= n) break;
+                int c[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    if (x_ref) x_ref[a * n + i] = v[u][a];
+                    c[a] = cell_coord(v[u][a], g.L[a], g.cinv[a], g.nc[a]);
+                }
+                const int id = (c[0] * g.nc[1] + c[1]) * g.nc[2] + c[2];
+                cell_of[i] = id;
+                rank[i] = atomicAdd(lcnt + id, 1);
+            }
         }
         __syncthreads();
-        for (int c = t; c < g.ncell; c += T) cnt[c] = lcnt[c];
-        __syncthreads();
-        const int total_cells = block_scan(cnt, start, g.ncell);
+        const int total_cells = block_scan(lcnt, start, g.ncell);   // the counts straight from LDS
         if (t == 0) start[g.ncell] = total_cells;
         __syncthreads();
-        for (int i = t; i < n; i += T) sorted[start[cell_of[i]] + rank[i]] = i;
+        for (int i0 = t; i0 < n; i0 += kCellBatch * T) {
+            int c[kCellBatch], r[kCellBatch], b[kCellBatch];
+#pragma unroll
+            for (int u = 0; u < kCellBatch; ++u) {
+                const int i = i0 + u * T;
+                c[u] = i < n ? cell_of[i] : 0;
+                r[u] = i < n ? rank[i] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kCellBatch; ++u) b[u] = start[c[u]];
+#pragma unroll
+            for (int u = 0; u < kCellBatch; ++u)
+                if (i0 + u * T < n) sorted[b[u] + r[u]] = i0 + u * T;
+        }
     } else {
         for (int c = t; c < g.ncell; c += T) {
             cnt[c] = 0;
@@ -576,7 +601,40 @@ __device__ void pl_cells(int32_t n, const double *__restrict__ x, const CellGrid
         }
     }
     __syncthreads();
-    for (int c = t; c < g.ncell; c += T) sort_cell_and_gather(start[c], start[c + 1], n, x, sorted, xs);
+    // cells of up to kSmallCell bodies sorted in registers (a cell's loads
+    // in flight together); larger cells by the insertion sort in memory
+    for (int c = t; c < g.ncell; c += T) {
+        const int b = start[c], m = start[c + 1] - b;
+        if (m > kSmallCell) {
+            sort_cell_and_gather(b, b + m, n, x, sorted, xs);
+            continue;
+        }
+        int v[kSmallCell];
+#pragma unroll
+        for (int k = 0; k < kSmallCell; ++k) v[k] = k < m ? sorted[b + k] : INT32_MAX;
+        // odd-even transposition sort: kSmallCell rounds sort kSmallCell
+        // values (the padding goes to the end)
+#pragma unroll
+        for (int rd = 0; rd < kSmallCell; ++rd)
+#pragma unroll
+            for (int k = rd & 1; k + 1 < kSmallCell; k += 2) {
+                const int lo = min(v[k], v[k + 1]), hi = max(v[k], v[k + 1]);
+                v[k] = lo;
+                v[k + 1] = hi;
+            }
+        double p[kSmallCell][3];
+#pragma unroll
+        for (int k = 0; k < kSmallCell; ++k)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) p[k][a] = k < m ? x[a * n + v[k]] : 0.0;
+#pragma unroll
+        for (int k = 0; k < kSmallCell; ++k)
+            if (k < m) {
+                sorted[b + k] = v[k];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) xs[a * n + b + k] = p[k][a];
+            }
+    }
 }
 
 // Pairs (i, j > i) of body i with the bodies of one neighbour cell c; writes

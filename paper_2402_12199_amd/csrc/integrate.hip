@@ -77,16 +77,25 @@ __device__ inline void free_sub(int k, double h, double I, double q[4], double L
     L[b] = -s2 * La + c2 * Lb;
 }
 
-__device__ inline void kick(double dt, double q[4], double P[3], double L[3], const float *force,
-                            const float *torque, int n, int i) {
+// Half kick with the body's force f and lab-frame torque tq (turned into
+// the body frame of the angular momentum L).
+__device__ inline void kick_with(double dt, double q[4], double P[3], double L[3], const float f[3],
+                                 const float tq[3]) {
     double R[9];
     quat_to_rot<double>(q[0], q[1], q[2], q[3], R);
-    const double t[3] = {torque[i], torque[n + i], torque[2 * n + i]};
+    const double t[3] = {tq[0], tq[1], tq[2]};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        P[a] += 0.5 * dt * (double)force[a * n + i];
+        P[a] += 0.5 * dt * (double)f[a];
         L[a] += 0.5 * dt * (R[a] * t[0] + R[3 + a] * t[1] + R[6 + a] * t[2]);
     }
+}
+
+__device__ inline void kick(double dt, double q[4], double P[3], double L[3], const float *force,
+                            const float *torque, int n, int i) {
+    const float f[3] = {force[i], force[n + i], force[2 * n + i]};
+    const float tq[3] = {torque[i], torque[n + i], torque[2 * n + i]};
+    kick_with(dt, q, P, L, f, tq);
 }
 
 // Displacement watch of the lists built from an earlier state.  Pair list:
@@ -104,13 +113,32 @@ struct Watch {
     double rho[kMaxTypes];   // largest bead radius per type, rounded up
 };
 
-__device__ inline void watch(const Watch &wt, int32_t n, int i, int t, const double xn[3], const double qn[4],
-                             bool &rebuild, bool &rescreen) {
+// The body's reference positions and orientation of the watch (zeros for
+// the lists the watch does not follow).
+struct WatchRef {
+    double x[3], xs[3], qs[4];
+};
+
+__device__ inline WatchRef watch_ref(const Watch &wt, int32_t n, int i) {
+    WatchRef r = {};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (wt.x_ref) r.x[a] = wt.x_ref[a * n + i];
+        if (wt.x_sref) r.xs[a] = wt.x_sref[a * n + i];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+        if (wt.x_sref) r.qs[a] = wt.q_sref[a * n + i];
+    return r;
+}
+
+__device__ inline void watch_with(const Watch &wt, const WatchRef &r, int t, const double xn[3], const double qn[4],
+                                  bool &rebuild, bool &rescreen) {
     if (wt.x_ref) {
         double d2 = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const double dd = xn[a] - wt.x_ref[a * n + i];
+            const double dd = xn[a] - r.x[a];
             d2 += dd * dd;
         }
         rebuild = d2 > wt.half_skin2;
@@ -119,16 +147,21 @@ __device__ inline void watch(const Watch &wt, int32_t n, int i, int t, const dou
         double d2 = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const double dd = xn[a] - wt.x_sref[a * n + i];
+            const double dd = xn[a] - r.xs[a];
             d2 += dd * dd;
         }
-        const double sw = wt.q_sref[i], sx = wt.q_sref[n + i], sy = wt.q_sref[2 * n + i], sz = wt.q_sref[3 * n + i];
+        const double sw = r.qs[0], sx = r.qs[1], sy = r.qs[2], sz = r.qs[3];
         // vector part of q_ref^* q = sw v - w s - s x v
         const double vx = sw * qn[1] - qn[0] * sx - (sy * qn[3] - sz * qn[2]);
         const double vy = sw * qn[2] - qn[0] * sy - (sz * qn[1] - sx * qn[3]);
         const double vz = sw * qn[3] - qn[0] * sz - (sx * qn[2] - sy * qn[1]);
         rescreen = sqrt(d2) + 2.0 * wt.rho[t] * sqrt(vx * vx + vy * vy + vz * vz) > wt.half_margin;
     }
+}
+
+__device__ inline void watch(const Watch &wt, int32_t n, int i, int t, const double xn[3], const double qn[4],
+                             bool &rebuild, bool &rescreen) {
+    watch_with(wt, watch_ref(wt, n, i), t, xn, qn, rebuild, rescreen);
 }
 
 __device__ inline void raise_flags(bool rebuild, bool rescreen, int32_t *flags) {
@@ -316,26 +349,38 @@ __global__ __launch_bounds__(kIntThreads) void k_fused(int32_t n, double dt, dou
                                                        float *__restrict__ force, float *__restrict__ torque,
                                                        double *__restrict__ ev, Watch wt, int32_t *__restrict__ flags,
                                                        double *__restrict__ partial, unsigned *__restrict__ ticket,
-                                                       double *__restrict__ kinetic) {
+                                                       double *__restrict__ kinetic, int one_type) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const double s = 1.0 / RB_ACC_SCALE;
     double kt = 0, kr = 0;
     bool rebuild = false, rescreen = false, drift = false, ovf = false;
     if (i < n) {
+        // every load of the body first (accumulator, state, the watch's
+        // references; with one template no type load), then the arithmetic
+        long long fw[3], tw[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const long long fw = acc[a * (int64_t)n + i], tw = acc[(3 + a) * (int64_t)n + i];
-            ovf |= !fix_word_ok(fw) || !fix_word_ok(tw);
-            force[a * n + i] = (float)((double)fw * s);
-            torque[a * n + i] = (float)((double)tw * s);
-            acc[a * (int64_t)n + i] = 0;
-            acc[(3 + a) * (int64_t)n + i] = 0;
+            fw[a] = acc[a * (int64_t)n + i];
+            tw[a] = acc[(3 + a) * (int64_t)n + i];
         }
-        const int t = type[i];
+        const int t = one_type ? 0 : type[i];
         double qi[4] = {q[i], q[n + i], q[2 * n + i], q[3 * n + i]};
         double Pi[3] = {P[i], P[n + i], P[2 * n + i]};
         double Li[3] = {L[i], L[n + i], L[2 * n + i]};
-        kick(dt, qi, Pi, Li, force, torque, n, i);
+        const double x0[3] = {x[i], x[n + i], x[2 * n + i]};
+        const WatchRef ref = watch_ref(wt, n, i);
+        float f[3], tq[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            ovf |= !fix_word_ok(fw[a]) || !fix_word_ok(tw[a]);
+            f[a] = (float)((double)fw[a] * s);
+            tq[a] = (float)((double)tw[a] * s);
+            force[a * n + i] = f[a];
+            torque[a * n + i] = tq[a];
+            acc[a * (int64_t)n + i] = 0;
+            acc[(3 + a) * (int64_t)n + i] = 0;
+        }
+        kick_with(dt, qi, Pi, Li, f, tq);
         const double m = mass[t];
         const double I[3] = {inertia[3 * t], inertia[3 * t + 1], inertia[3 * t + 2]};
 #pragma unroll
@@ -344,12 +389,12 @@ __global__ __launch_bounds__(kIntThreads) void k_fused(int32_t n, double dt, dou
             kr += Li[a] * Li[a] / (2.0 * I[a]);
         }
         // next step: half kick, drift, free rotation
-        kick(dt, qi, Pi, Li, force, torque, n, i);
+        kick_with(dt, qi, Pi, Li, f, tq);
         const double im = 1.0 / m;
         double xn[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            xn[a] = x[a * n + i] + dt * Pi[a] * im;
+            xn[a] = x0[a] + dt * Pi[a] * im;
             x[a * n + i] = xn[a];
         }
         free_sub(2, 0.5 * dt, I[2], qi, Li);
@@ -365,7 +410,7 @@ __global__ __launch_bounds__(kIntThreads) void k_fused(int32_t n, double dt, dou
             P[a * n + i] = Pi[a];
             L[a * n + i] = Li[a];
         }
-        watch(wt, n, i, t, xn, qi, rebuild, rescreen);
+        watch_with(wt, ref, t, xn, qi, rebuild, rescreen);
     }
     raise_flags(rebuild, rescreen, flags);
     count_drift(drift, flags);
@@ -458,7 +503,8 @@ extern "C" int rb_rigid_step_fused(const rb_ctx *ctx, int32_t n, double dt, doub
     // one block more than the bodies need: it adds up the global sums
     k_fused<<<(int)nblocks(n) + 1, kIntThreads, 0, (hipStream_t)stream>>>(
         n, dt, x, P, q, L, type, ctx->dev.mass, ctx->dev.inertia, acc, force, torque, energy_virial,
-        make_watch(ctx, x_ref, half_skin, x_sref, q_sref, half_margin), flags, partial, ticket, kinetic);
+        make_watch(ctx, x_ref, half_skin, x_sref, q_sref, half_margin), flags, partial, ticket, kinetic,
+        ctx->n_types == 1);
     RB_LAUNCH_CHECK("rb_rigid_step_fused");
     return RB_OK;
 }
@@ -516,7 +562,8 @@ extern "C" int rb_rigid_step_fused_noalloc(const rb_ctx *ctx, int32_t n, double 
     k_clear_ticket<<<1, 64, 0, st>>>(ticket);
     k_fused<<<(int)nblocks(n) + 1, kIntThreads, 0, st>>>(
         n, dt, x, P, q, L, type, ctx->dev.mass, ctx->dev.inertia, acc, force, torque, energy_virial,
-        make_watch(ctx, x_ref, half_skin, x_sref, q_sref, half_margin), flags, partial, ticket, kinetic);
+        make_watch(ctx, x_ref, half_skin, x_sref, q_sref, half_margin), flags, partial, ticket, kinetic,
+        ctx->n_types == 1);
     RB_LAUNCH_CHECK("rb_rigid_step_fused_noalloc");
     return RB_OK;
 }

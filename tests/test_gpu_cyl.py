@@ -186,14 +186,18 @@ def test_shell_routing_matches_oracle_and_keeps_the_network_in_its_domain(abi, c
 
 
 def test_routing_with_two_identical_templates_equals_the_single_template_routing(abi, cyl_workload):
-    # The routing kernel has a form for single-template contexts (uniform
-    # shell sizes) and the general one (per-pair type lookups); the same
-    # cylinders under a context with the template given twice (types
-    # alternating) must get the same descriptors and the same routes
-    from paper_2402_12199_amd.md import RigidSystem
+    # The routing kernel, the bead kernel's screen and the fallback of the
+    # one-launch network forces have a form for single-template contexts
+    # (uniform shell sizes, no type loads) and the general one (per-pair
+    # type lookups); the same cylinders under a context with the template
+    # given twice (types alternating) must get the same descriptors, the
+    # same routes and, bit for bit, the same bead-path and network-path
+    # forces, torques and energy
+    from paper_2402_12199_amd.md import NNModel, RigidSystem
     cfg, st, pairs = cyl_workload
     b = cfg.body
-    out = []
+    params, norm = _params(5), _norm()
+    out, sums = [], []
     for ntypes in (1, 2):
         types = (np.arange(cfg.n_bodies) % ntypes).astype(np.int32)
         sysm = RigidSystem([b.beads] * ntypes, [b.mass] * ntypes, [b.inertia] * ntypes, types, st["x"], st["q"],
@@ -210,8 +214,19 @@ def test_routing_with_two_identical_templates_equals_the_single_template_routing
         bd = np.sort(key[sysm.idx_bead[:f[abi.RB_FLAG_NBEAD]].cpu().numpy()])
         order = np.argsort(key)
         out.append((nn, bd, sysm.desc[:, :len(key)].cpu().numpy()[:, order]))
+        res = []
+        sysm.set_nn(NNModel(params=_dev(params), norm=norm.as_array(), precision=abi.RB_PREC_BF16,
+                            d_min=cfg.d_min, sw_lo=cfg.d_cut - 1.0, sw_hi=cfg.d_cut, form="cyl", gap_min=1.0,
+                            gap_max=2.5))
+        for path in ("bead", "nn"):
+            sysm.compute_forces(path)
+            sysm.check_capacity()
+            res += [sysm.force.cpu().numpy(), sysm.torque.cpu().numpy(), sysm.ev.cpu().numpy()]
+        sums.append(res)
     assert len(out[0][0]) > 10000 and len(out[0][1]) > 500
     for a0, a1 in zip(out[0], out[1]):
+        np.testing.assert_array_equal(a1, a0)
+    for a0, a1 in zip(sums[0], sums[1]):
         np.testing.assert_array_equal(a1, a0)
 
 

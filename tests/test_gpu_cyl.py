@@ -192,7 +192,7 @@ def test_routing_with_two_identical_templates_equals_the_single_template_routing
     # type lookups); the same cylinders under a context with the template
     # given twice (types alternating) must get the same descriptors, the
     # same routes and, bit for bit, the same bead-path and network-path
-    # forces, torques and energy
+    # forces, torques and energy, and the same states after fused steps
     from paper_2402_12199_amd.md import NNModel, RigidSystem
     cfg, st, pairs = cyl_workload
     b = cfg.body
@@ -222,6 +222,13 @@ def test_routing_with_two_identical_templates_equals_the_single_template_routing
             sysm.compute_forces(path)
             sysm.check_capacity()
             res += [sysm.force.cpu().numpy(), sysm.torque.cpu().numpy(), sysm.ev.cpu().numpy()]
+        # and three fused integrator steps (per-type masses and inertias)
+        sysm.begin_fused(cfg.dt)
+        for _ in range(3):
+            sysm.fused_step(cfg.dt, "bead")
+        sysm.end_fused(cfg.dt, "bead")
+        sysm.check_capacity()
+        res += [t.cpu().numpy() for t in (sysm.x, sysm.q, sysm.P, sysm.L, sysm.kinetic)]
         sums.append(res)
     assert len(out[0][0]) > 10000 and len(out[0][1]) > 500
     for a0, a1 in zip(out[0], out[1]):

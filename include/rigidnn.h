@@ -159,6 +159,9 @@ int rb_flags_check(const int32_t *flags_host);
  * x_ref (3 x n) for the skin test of rb_rigid_step.  With
  * RB_BUILD_IF_FLAGGED the kernels do nothing unless flags[REBUILD] is set,
  * which makes the call safe to capture in a graph; the call clears it.
+ * For n <= 65536 the build is one launch whose workgroups wait for the one
+ * that bins the bodies (a bounded wait: past it flags[WAIT_TIMEOUT] is set
+ * and the list is invalid); flags[REBUILD] holds 2 while that launch runs.
  * ws: scratch of rb_pairlist_workspace_bytes(n, box, r_list) bytes. */
 size_t rb_pairlist_workspace_bytes(int32_t n, const double *box, double r_list);
 int rb_pairlist_build(int32_t n, const double *x, const double *box, double r_list,
